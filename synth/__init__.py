@@ -1,0 +1,16 @@
+"""Seeded synthetic inputs for the adaptive-multilevel BDDC solver.
+
+This package only draws inputs (coefficient fields, substructure partitions,
+level agglomerations, right-hand sides).  It holds none of the method's
+arithmetic, so both the CPU oracle and the GPU library may use it.
+"""
+
+from .configs import (  # noqa: F401
+    Problem,
+    square_partition,
+    square_agglomeration,
+    add_channels,
+    square_problem,
+    config,
+    CONFIG_NAMES,
+)

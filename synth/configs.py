@@ -1,0 +1,155 @@
+"""Seeded problem generators.
+
+The model problem is scalar diffusion  -div(k grad u) = f  on the unit square
+with zero Dirichlet data on the whole boundary, discretised on an nx x ny grid
+of square (or rectangular) elements.  Element e = j*nx + i covers
+[i/nx, (i+1)/nx] x [j/ny, (j+1)/ny].  Free node (i, j), 1 <= i <= nx-1,
+1 <= j <= ny-1, has index (j-1)*(nx-1) + (i-1).
+
+Every random draw goes through one numpy Generator(PCG64(seed)) in a fixed
+order: coefficient, channels, partition seeds, right-hand side.
+
+Workload shapes follow the numerical section of the paper (unit square,
+H/h = 16, coarsening ratio 16 between levels, about a million unknowns at
+the largest size); the paper's own experiment is elasticity on a jagged
+partition whose geometry is not available, so these seeded scalar problems
+stand in for it.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+CONSTRAINT_KINDS = ("corners", "corners_edges", "adaptive")
+
+
+@dataclass
+class Problem:
+    nx: int
+    ny: int
+    coeff: np.ndarray            # float64, nx*ny, element-wise k_e > 0
+    part: np.ndarray             # int32, nx*ny, level-1 substructure of each element
+    nsub: int
+    levels: int                  # L >= 2
+    agglom: List[np.ndarray]     # agglom[l-2][s] = level-l substructure of level-(l-1) substructure s
+    constraints: str = "corners"
+    tau: float = float("inf")
+    f: Optional[np.ndarray] = None   # float64 (nrhs, n_free) dual load vectors
+    element: str = "Q1"
+    rtol: float = 1e-8
+    name: str = ""
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_free(self) -> int:
+        return (self.nx - 1) * (self.ny - 1)
+
+
+def square_partition(nx: int, ny: int, nsx: int, nsy: int) -> np.ndarray:
+    """Element -> substructure id for an nsx x nsy grid of rectangular blocks."""
+    i = np.arange(nx)
+    j = np.arange(ny)
+    bi = (i * nsx) // nx
+    bj = (j * nsy) // ny
+    part = bj[:, None] * nsx + bi[None, :]
+    return part.reshape(-1).astype(np.int32)
+
+
+def square_agglomeration(nsx: int, nsy: int, gx: int, gy: int) -> np.ndarray:
+    """Substructure (I, J) of an nsx x nsy grid -> group of a gx x gy grid."""
+    I = np.arange(nsx)
+    J = np.arange(nsy)
+    gi = (I * gx) // nsx
+    gj = (J * gy) // nsy
+    return (gj[:, None] * gx + gi[None, :]).reshape(-1).astype(np.int32)
+
+
+def add_channels(rng: np.random.Generator, nx: int, ny: int, coeff: np.ndarray,
+                 count: int = 8, kval: float = 1e6) -> list:
+    """Straight high-coefficient channels two elements wide across the domain.
+
+    Each channel draws its orientation (0 = horizontal, 1 = vertical) and then
+    an offset t in {0, ..., n-2}; rows (or columns) t and t+1 get k = kval.
+    """
+    k2 = coeff.reshape(ny, nx)
+    drawn = []
+    for _ in range(count):
+        orient = int(rng.integers(0, 2))
+        if orient == 0:
+            t = int(rng.integers(0, ny - 1))
+            k2[t:t + 2, :] = kval
+        else:
+            t = int(rng.integers(0, nx - 1))
+            k2[:, t:t + 2] = kval
+        drawn.append((orient, t))
+    return drawn
+
+
+def _levels_agglom(nsx, nsy, levels, groups):
+    agg = []
+    if levels >= 3:
+        gx, gy = groups
+        agg.append(square_agglomeration(nsx, nsy, gx, gy))
+        cx, cy = gx, gy
+        for _ in range(levels - 3):
+            nx2, ny2 = max(1, cx // 4), max(1, cy // 4)
+            agg.append(square_agglomeration(cx, cy, nx2, ny2))
+            cx, cy = nx2, ny2
+    return agg
+
+
+def square_problem(nx: int, nsx: int, *, ny: Optional[int] = None, nsy: Optional[int] = None,
+                   levels: int = 2, groups=(1, 1), constraints: str = "corners",
+                   tau: float = float("inf"), kmode: str = "one", kmax_exp: float = 0.0,
+                   channels: int = 0, nrhs: int = 1, seed: int = 0,
+                   element: str = "Q1", name: str = "") -> Problem:
+    """A seeded problem on a square partition.
+
+    kmode: "one" (k = 1), "loguniform" (k = 10**U(0, kmax_exp) per element).
+    groups: level-2 groups per side (gx, gy), used when levels >= 3.
+    """
+    ny = nx if ny is None else ny
+    nsy = nsx if nsy is None else nsy
+    assert constraints in CONSTRAINT_KINDS
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if kmode == "one":
+        coeff = np.ones(nx * ny)
+    elif kmode == "loguniform":
+        coeff = 10.0 ** rng.uniform(0.0, kmax_exp, size=nx * ny)
+    else:
+        raise ValueError(kmode)
+    ch = add_channels(rng, nx, ny, coeff, count=channels) if channels else []
+    part = square_partition(nx, ny, nsx, nsy)
+    agg = _levels_agglom(nsx, nsy, levels, groups)
+    nfree = (nx - 1) * (ny - 1)
+    f = rng.uniform(-1.0, 1.0, size=(nrhs, nfree))
+    return Problem(nx=nx, ny=ny, coeff=coeff, part=part, nsub=nsx * nsy, levels=levels,
+                   agglom=agg, constraints=constraints, tau=tau, f=f, element=element,
+                   name=name, meta={"channels": ch, "nsx": nsx, "nsy": nsy, "groups": groups})
+
+
+CONFIG_NAMES = {
+    1: "two-level c+e, 32x32 Q1, 4x4 subs (H/h=8), k=1",
+    2: "adaptive three-level, 256x256 Q1, 16x16 subs (H/h=16), 4x4 groups, "
+       "k=10^U(0,6) + 8 channels k=1e6, tau=10",
+    3: "adaptive three-level, 1024x1024 Q1, 64x64 subs (H/h=16), 16x16 groups, k=1, tau=10",
+}
+
+
+def config(cid: int, nrhs: int = 1) -> Problem:
+    """The seeded workloads; config c uses seed 1000*c."""
+    seed = 1000 * cid
+    if cid == 1:
+        return square_problem(32, 4, levels=2, constraints="corners_edges", kmode="one",
+                              nrhs=nrhs, seed=seed, name="config1")
+    if cid == 2:
+        return square_problem(256, 16, levels=3, groups=(4, 4), constraints="adaptive",
+                              tau=10.0, kmode="loguniform", kmax_exp=6.0, channels=8,
+                              nrhs=nrhs, seed=seed, name="config2")
+    if cid == 3:
+        return square_problem(1024, 64, levels=3, groups=(4, 4), constraints="adaptive",
+                              tau=10.0, kmode="one", nrhs=nrhs, seed=seed, name="config3")
+    raise ValueError(f"unknown config {cid}")
