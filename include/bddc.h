@@ -1,0 +1,160 @@
+/*
+ * bddc.h -- C ABI of libbddc.so: adaptive-multilevel BDDC for 2D scalar
+ * diffusion on MI355X (gfx950).
+ *
+ * Method: Sousedik and Mandel, "On Adaptive-Multilevel BDDC".
+ *   - Problem statement (Section 2, eq. (problem)): find u in U with
+ *     a(u, v) = <f, v> for all v in U, U = continuous P1 or Q1 functions on
+ *     the unit square vanishing on its boundary, a(u, v) = sum over elements
+ *     of k_e * int grad u . grad v.
+ *   - Preconditioner: Algorithm "Multilevel BDDC" (Section 2.1).
+ *   - Adaptive coarse dofs: Theorem "local-est" (Section 3), Theorem
+ *     "adaptive" (Section 4) and the adaptive setup algorithm (Section 5).
+ *   - Krylov method: preconditioned conjugate gradients (Section 5),
+ *     stopping test ||r||_2 <= rtol * ||f||_2.
+ *
+ * Conventions shared by every call
+ *   - Every call returns a bddc_status; nothing throws across the ABI.
+ *   - Arguments are validated on the host before any device work; a call
+ *     that fails validation has no effect.
+ *   - Vectors r, z, f, u are DEVICE pointers to FP64 data owned by the
+ *     caller, column-major with nrhs columns of length n_free =
+ *     (nx-1)*(ny-1) and leading dimension ld >= n_free.  Free node (i, j),
+ *     1 <= i <= nx-1, 1 <= j <= ny-1, has index (j-1)*(nx-1) + (i-1).
+ *   - f is the dual (load) vector: entry j is <f, phi_j>.
+ *   - hip_stream is a hipStream_t (NULL = the null stream).  apply and solve
+ *     are enqueued on it; solve synchronises it before returning.
+ *   - A handle must not be used by two threads at once.  Calls on different
+ *     handles are independent.
+ */
+#ifndef BDDC_H
+#define BDDC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BDDC_OK = 0,
+  BDDC_EINVAL = -1,       /* bad argument (size, pointer, value out of range, k <= 0 or not finite) */
+  BDDC_ENOMEM = -2,       /* device allocation failed */
+  BDDC_ESINGULAR = -3,    /* a local or coarse factorization met a non-positive pivot */
+  BDDC_EPARTITION = -4,   /* partition or agglomeration invalid (id out of range, empty substructure) */
+  BDDC_ENOCONV = -5,      /* PCG reached maxit; u holds the last iterate */
+  BDDC_EDEVICE = -6,      /* a HIP runtime call failed */
+  BDDC_EBUSY = -7,        /* reserved for admission control */
+  BDDC_EUNSUPPORTED = -8  /* valid input outside what this build implements (sizes, precision) */
+} bddc_status;
+
+typedef enum { BDDC_Q1 = 0, BDDC_P1 = 1 } bddc_element;   /* P1: each element square split along its SW-NE diagonal */
+typedef enum { BDDC_CORNERS = 0, BDDC_CORNERS_EDGES = 1, BDDC_ADAPTIVE = 2 } bddc_constraints;
+typedef enum { BDDC_FP64 = 0, BDDC_FP32 = 1, BDDC_BF16 = 2 } bddc_precision;
+
+typedef struct bddc_ctx* bddc_handle;   /* opaque, owned by the library */
+
+#define BDDC_MAX_LEVELS 8
+
+/* Problem description; every pointer is a HOST pointer read during the call only. */
+typedef struct {
+  int32_t nx, ny;              /* elements per side of the unit square, nx, ny >= 2 */
+  int32_t element;             /* bddc_element */
+  const double* coeff;         /* nx*ny, k_e > 0 and finite; element e = j*nx + i covers [i/nx,(i+1)/nx] x [j/ny,(j+1)/ny] */
+  const int32_t* part;         /* nx*ny, level-1 substructure of each element, in [0, nsub) */
+  int32_t nsub;                /* number of level-1 substructures, >= 1; each must own an element */
+  int32_t levels;              /* L >= 2 decomposition levels; level L is the directly solved coarse problem */
+  const int32_t* const* agglom;/* levels-2 arrays: agglom[l-2][s] = level-l substructure of level-(l-1)
+                                  substructure s (l = 2..L-1); may be NULL when levels == 2 */
+  int32_t constraints;         /* bddc_constraints; corners are always coarse dofs */
+  double tau;                  /* ADAPTIVE threshold: eigenvectors with lambda > tau become coarse dofs */
+  int32_t precision;           /* bddc_precision; this build implements BDDC_FP64 */
+} bddc_problem;
+
+/* Sizes and diagnostics of a set-up preconditioner (per level l = 1..levels-1 at index l-1). */
+typedef struct {
+  int64_t n_free;                       /* unknowns of the level-1 problem */
+  int32_t levels;
+  int32_t nsub[BDDC_MAX_LEVELS];        /* substructures of level l */
+  int32_t n_dof[BDDC_MAX_LEVELS];       /* dofs of level l (level 1: n_free) */
+  int32_t n_interface[BDDC_MAX_LEVELS]; /* interface dofs of level l */
+  int32_t n_corners[BDDC_MAX_LEVELS];
+  int32_t n_edges[BDDC_MAX_LEVELS];
+  int32_t nc[BDDC_MAX_LEVELS];          /* coarse dofs of level l (= dofs of level l+1) */
+  int32_t n_adaptive[BDDC_MAX_LEVELS];  /* coarse dofs added by the eigenproblems at level l */
+  double omega[BDDC_MAX_LEVELS];        /* max over edges of the largest unselected eigenvalue (ADAPTIVE) */
+  double indicator;                     /* product of omega over levels (ADAPTIVE), else 0 */
+  double kappa;                         /* Lanczos condition estimate of the last solve (first column) */
+  int32_t last_iters;                   /* iterations of the last solve (first column) */
+  int64_t device_bytes;                 /* device memory held by the handle */
+  int64_t apply_bytes;                  /* algorithmic bytes streamed by one interface preconditioner apply */
+  int64_t matvec_bytes;                 /* algorithmic bytes streamed by one interface operator product */
+} bddc_info;
+
+/* Validate a problem and report its level-1 topology (n_free, nsub, interface,
+ * corner and edge counts) without touching the device.  Only level 1 is filled
+ * (levels beyond 1 depend on the coarse dofs chosen at set-up).
+ * Errors: BDDC_EINVAL, BDDC_EPARTITION, BDDC_EUNSUPPORTED. */
+bddc_status bddc_plan(const bddc_problem* p, bddc_info* info);
+
+/* Set up the preconditioner (Section 5, adaptive setup algorithm, then the
+ * structures of Algorithm "Multilevel BDDC" at every level).  Host inputs are
+ * copied; the caller may free them after return.  On success *out owns all
+ * device data until bddc_destroy.  On failure *out is NULL and nothing leaks.
+ * Errors: BDDC_EINVAL, BDDC_EPARTITION, BDDC_EUNSUPPORTED, BDDC_ESINGULAR,
+ * BDDC_ENOMEM, BDDC_EDEVICE. */
+bddc_status bddc_setup(const bddc_problem* p, void* hip_stream, bddc_handle* out);
+
+/* z = M^{-1} r for nrhs columns: the full-space multilevel preconditioner of
+ * Algorithm "Multilevel BDDC" (interior pre-correction, substructure
+ * correction, coarse problem by recursion, averaging, interior
+ * post-correction).  r and z are device arrays (may not alias).
+ * Errors: BDDC_EINVAL, BDDC_EDEVICE. */
+bddc_status bddc_apply(bddc_handle h, const double* r, double* z, int32_t nrhs, int64_t ld,
+                       void* hip_stream);
+
+/* Solve A u = f for nrhs columns with PCG preconditioned by M (Section 5).
+ * Level 1 is reduced to the interface (Section 5, last remark): PCG starts
+ * from the condensed iterate (interior values solve the interior problems,
+ * interface values 0), runs on the interface, and the interior values are
+ * recovered at the end.  Each column stops when ||r||_2 <= rtol ||f||_2 on
+ * the recursively updated residual, or after maxit iterations.
+ * iters[nrhs] and relres[nrhs] are HOST arrays written after the stream is
+ * synchronised (relres = final ||r|| / ||f||; 0 if f = 0).
+ * Errors: BDDC_EINVAL, BDDC_ENOCONV (u holds the last iterate), BDDC_EDEVICE. */
+bddc_status bddc_solve(bddc_handle h, const double* f, double* u, int32_t nrhs, int64_t ld,
+                       double rtol, int32_t maxit, int32_t* iters, double* relres, void* hip_stream);
+
+/* Sizes and diagnostics.  Errors: BDDC_EINVAL. */
+bddc_status bddc_query(bddc_handle h, bddc_info* info);
+
+/* Eigenvalues of the pair eigenproblem of Theorem "local-est" for edge
+ * `edge` (0-based, pairs (s,t), s < t, in increasing order) of level `level`
+ * (1-based) of an ADAPTIVE set-up.  Writes up to cap eigenvalues in
+ * decreasing order to the host array lam, their count to *n_lam, the number
+ * selected (lambda > tau) to *n_sel, the pair to pair[0..1], and the number
+ * of edge dofs to *n_edge_dofs.  Any output pointer may be NULL.
+ * Errors: BDDC_EINVAL (not adaptive, level or edge out of range). */
+bddc_status bddc_edge_eigs(bddc_handle h, int32_t level, int32_t edge, double* lam, int32_t cap,
+                           int32_t* n_lam, int32_t* n_sel, int32_t* pair, int32_t* n_edge_dofs);
+
+/* Coarse dofs installed on an edge: the level's dof ids of the edge (host
+ * array dofs, cap_dofs entries) and the constraint weights, one column per
+ * coarse dof, column-major n_edge_dofs x n_cols in the host array q with
+ * leading dimension n_edge_dofs (cap_q entries).  Columns of an ADAPTIVE
+ * set-up are orthonormal.  Errors: BDDC_EINVAL (sizes too small, out of range). */
+bddc_status bddc_edge_constraints(bddc_handle h, int32_t level, int32_t edge, int32_t* dofs,
+                                  int32_t cap_dofs, double* q, int32_t cap_q,
+                                  int32_t* n_edge_dofs, int32_t* n_cols);
+
+/* Static description of a status code (never NULL). */
+const char* bddc_status_string(bddc_status s);
+
+/* Release every resource of the handle (NULL-safe).  Synchronises the device. */
+void bddc_destroy(bddc_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BDDC_H */

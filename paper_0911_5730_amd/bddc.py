@@ -1,0 +1,243 @@
+"""ctypes binding of libbddc.so (argument marshalling only).
+
+Every step of the method runs in the library's HIP kernels; this module only
+converts Python objects into the C structures of include/bddc.h, passes device
+pointers of torch tensors through, and turns status codes into exceptions.
+It fails loudly when the library has not been built.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbddc.so")
+MAX_LEVELS = 8
+
+STATUS = {0: "BDDC_OK", -1: "BDDC_EINVAL", -2: "BDDC_ENOMEM", -3: "BDDC_ESINGULAR",
+          -4: "BDDC_EPARTITION", -5: "BDDC_ENOCONV", -6: "BDDC_EDEVICE", -7: "BDDC_EBUSY",
+          -8: "BDDC_EUNSUPPORTED"}
+ELEMENT = {"Q1": 0, "P1": 1}
+CONSTRAINTS = {"corners": 0, "corners_edges": 1, "adaptive": 2}
+PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2}
+
+
+class BddcProblemC(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("element", ctypes.c_int32),
+                ("coeff", ctypes.POINTER(ctypes.c_double)), ("part", ctypes.POINTER(ctypes.c_int32)),
+                ("nsub", ctypes.c_int32), ("levels", ctypes.c_int32),
+                ("agglom", ctypes.POINTER(ctypes.POINTER(ctypes.c_int32))),
+                ("constraints", ctypes.c_int32), ("tau", ctypes.c_double), ("precision", ctypes.c_int32)]
+
+
+class BddcInfoC(ctypes.Structure):
+    _fields_ = [("n_free", ctypes.c_int64), ("levels", ctypes.c_int32),
+                ("nsub", ctypes.c_int32 * MAX_LEVELS), ("n_dof", ctypes.c_int32 * MAX_LEVELS),
+                ("n_interface", ctypes.c_int32 * MAX_LEVELS), ("n_corners", ctypes.c_int32 * MAX_LEVELS),
+                ("n_edges", ctypes.c_int32 * MAX_LEVELS), ("nc", ctypes.c_int32 * MAX_LEVELS),
+                ("n_adaptive", ctypes.c_int32 * MAX_LEVELS), ("omega", ctypes.c_double * MAX_LEVELS),
+                ("indicator", ctypes.c_double), ("kappa", ctypes.c_double), ("last_iters", ctypes.c_int32),
+                ("device_bytes", ctypes.c_int64), ("apply_bytes", ctypes.c_int64),
+                ("matvec_bytes", ctypes.c_int64)]
+
+
+SYMBOLS = ["bddc_plan", "bddc_setup", "bddc_apply", "bddc_solve", "bddc_query", "bddc_edge_eigs",
+           "bddc_edge_constraints", "bddc_status_string", "bddc_destroy"]
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_0911_5730_amd.build`")
+    lib = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    i32, i64, dbl, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+    lib.bddc_plan.argtypes = [P(BddcProblemC), P(BddcInfoC)]
+    lib.bddc_setup.argtypes = [P(BddcProblemC), vp, P(vp)]
+    lib.bddc_apply.argtypes = [vp, vp, vp, i32, i64, vp]
+    lib.bddc_solve.argtypes = [vp, vp, vp, i32, i64, dbl, i32, P(i32), P(dbl), vp]
+    lib.bddc_query.argtypes = [vp, P(BddcInfoC)]
+    lib.bddc_edge_eigs.argtypes = [vp, i32, i32, P(dbl), i32, P(i32), P(i32), P(i32), P(i32)]
+    lib.bddc_edge_constraints.argtypes = [vp, i32, i32, P(i32), i32, P(dbl), i32, P(i32), P(i32)]
+    lib.bddc_status_string.argtypes = [i32]
+    lib.bddc_status_string.restype = ctypes.c_char_p
+    lib.bddc_destroy.argtypes = [vp]
+    lib.bddc_destroy.restype = None
+    for name in SYMBOLS[:-2]:
+        if name != "bddc_status_string":
+            getattr(lib, name).restype = i32
+    _lib = lib
+    return lib
+
+
+class BDDCError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+        super().__init__(f"{where}: {self.name}")
+
+
+def _check(st: int, where: str):
+    if st != 0:
+        raise BDDCError(st, where)
+
+
+class _Marshalled:
+    """C view of a problem; keeps the numpy buffers alive while in use."""
+
+    def __init__(self, prob, tau=None, constraints=None, precision="fp64"):
+        self.coeff = np.ascontiguousarray(prob.coeff, dtype=np.float64)
+        self.part = np.ascontiguousarray(prob.part, dtype=np.int32)
+        self.agg = [np.ascontiguousarray(a, dtype=np.int32) for a in (prob.agglom or [])]
+        n = max(1, len(self.agg))
+        self.agg_ptrs = (ctypes.POINTER(ctypes.c_int32) * n)()
+        for i, a in enumerate(self.agg):
+            self.agg_ptrs[i] = a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        kind = constraints or prob.constraints
+        t = prob.tau if tau is None else tau
+        self.c = BddcProblemC(
+            nx=prob.nx, ny=prob.ny, element=ELEMENT[prob.element],
+            coeff=self.coeff.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+            part=self.part.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+            nsub=prob.nsub, levels=prob.levels,
+            agglom=ctypes.cast(self.agg_ptrs, ctypes.POINTER(ctypes.POINTER(ctypes.c_int32)))
+            if self.agg else None,
+            constraints=CONSTRAINTS[kind], tau=float(t) if math.isfinite(t) else float("inf"),
+            precision=PRECISION[precision])
+
+
+def info_dict(ci: BddcInfoC) -> dict:
+    L = max(1, ci.levels - 1)
+    per = lambda arr: [arr[i] for i in range(L)]
+    return dict(n_free=ci.n_free, levels=ci.levels, nsub=per(ci.nsub), n_dof=per(ci.n_dof),
+                n_interface=per(ci.n_interface), n_corners=per(ci.n_corners), n_edges=per(ci.n_edges),
+                nc=per(ci.nc), n_adaptive=per(ci.n_adaptive), omega=per(ci.omega),
+                indicator=ci.indicator, kappa=ci.kappa, last_iters=ci.last_iters,
+                device_bytes=ci.device_bytes, apply_bytes=ci.apply_bytes, matvec_bytes=ci.matvec_bytes)
+
+
+def plan(prob, **kw) -> dict:
+    """Host-only validation and level-1 topology (bddc_plan)."""
+    lib = load_library()
+    m = _Marshalled(prob, **kw)
+    ci = BddcInfoC()
+    _check(lib.bddc_plan(ctypes.byref(m.c), ctypes.byref(ci)), "bddc_plan")
+    d = info_dict(ci)
+    return {k: (v[0] if isinstance(v, list) else v) for k, v in d.items()}
+
+
+def _stream_ptr(stream) -> int:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+def _vec_args(t, n_free):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError("expected a contiguous float64 CUDA tensor")
+    if t.dim() == 1:
+        if t.shape[0] != n_free:
+            raise ValueError("vector length must be n_free")
+        return 1, n_free
+    if t.dim() == 2 and t.shape[1] == n_free:
+        return t.shape[0], n_free
+    raise ValueError("expected shape (n_free,) or (nrhs, n_free)")
+
+
+class Solver:
+    """A set-up adaptive-multilevel BDDC preconditioner on the current GPU."""
+
+    def __init__(self, prob, *, tau=None, constraints=None, precision="fp64", stream=None):
+        self.lib = load_library()
+        m = _Marshalled(prob, tau=tau, constraints=constraints, precision=precision)
+        h = ctypes.c_void_p()
+        _check(self.lib.bddc_setup(ctypes.byref(m.c), ctypes.c_void_p(_stream_ptr(stream)), ctypes.byref(h)),
+               "bddc_setup")
+        self.h = h
+        self.n_free = (prob.nx - 1) * (prob.ny - 1)
+        self.levels = prob.levels
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.bddc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def info(self) -> dict:
+        ci = BddcInfoC()
+        _check(self.lib.bddc_query(self.h, ctypes.byref(ci)), "bddc_query")
+        return info_dict(ci)
+
+    def apply(self, r, z=None, stream=None):
+        import torch
+        nrhs, ld = _vec_args(r, self.n_free)
+        if z is None:
+            z = torch.empty_like(r)
+        _check(self.lib.bddc_apply(self.h, ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(z.data_ptr()),
+                                   nrhs, ld, ctypes.c_void_p(_stream_ptr(stream))), "bddc_apply")
+        return z
+
+    def solve(self, f, u=None, rtol=1e-8, maxit=1000, stream=None, allow_noconv=False):
+        import torch
+        nrhs, ld = _vec_args(f, self.n_free)
+        if u is None:
+            u = torch.empty_like(f)
+        iters = (ctypes.c_int32 * nrhs)()
+        relres = (ctypes.c_double * nrhs)()
+        st = self.lib.bddc_solve(self.h, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(u.data_ptr()), nrhs, ld,
+                                 float(rtol), int(maxit), iters, relres, ctypes.c_void_p(_stream_ptr(stream)))
+        if not (st == -5 and allow_noconv):
+            _check(st, "bddc_solve")
+        return u, list(iters), list(relres)
+
+    def edge_eigs(self, level: int, edge: int):
+        n_lam, n_sel, ned = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        pair = (ctypes.c_int32 * 2)()
+        _check(self.lib.bddc_edge_eigs(self.h, level, edge, None, 0, ctypes.byref(n_lam), ctypes.byref(n_sel),
+                                       pair, ctypes.byref(ned)), "bddc_edge_eigs")
+        lam = (ctypes.c_double * max(1, n_lam.value))()
+        _check(self.lib.bddc_edge_eigs(self.h, level, edge, lam, n_lam.value, None, None, None, None),
+               "bddc_edge_eigs")
+        return np.array(lam[:n_lam.value]), n_sel.value, (pair[0], pair[1])
+
+    def edge_constraints(self, level: int, edge: int):
+        ne, m = ctypes.c_int32(), ctypes.c_int32()
+        _check(self.lib.bddc_edge_constraints(self.h, level, edge, None, 0, None, 0, ctypes.byref(ne),
+                                              ctypes.byref(m)), "bddc_edge_constraints")
+        dofs = (ctypes.c_int32 * max(1, ne.value))()
+        q = (ctypes.c_double * max(1, ne.value * m.value))()
+        _check(self.lib.bddc_edge_constraints(self.h, level, edge, dofs, ne.value, q, ne.value * m.value, None,
+                                              None), "bddc_edge_constraints")
+        Q = np.array(q[:ne.value * m.value]).reshape(m.value, ne.value).T
+        return np.array(dofs[:ne.value]), Q
+
+
+def status_string(code: int) -> str:
+    return load_library().bddc_status_string(code).decode()
+
+
+def exported_symbols(path: str = LIB_PATH) -> Sequence[str]:
+    lib = ctypes.CDLL(path)
+    return [s for s in SYMBOLS if hasattr(lib, s)]

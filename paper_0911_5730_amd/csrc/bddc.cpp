@@ -1,0 +1,1186 @@
+// libbddc: host orchestration of adaptive-multilevel BDDC on one GPU.
+//
+// bddc_setup follows the adaptive setup algorithm of Section 5 level by level:
+// topology and coarse-dof candidates (host, integer), then on the device the
+// local matrices, stiffness-scaling weights, interior elimination, per-edge
+// eigenproblems, constrained local factors with the energy-minimal coarse
+// basis and the next level's matrices; the last level is factored directly.
+// bddc_apply runs Algorithm "Multilevel BDDC"; bddc_solve runs PCG on the
+// level-1 interface (Section 5, reduction of level 1 to the interfaces).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <memory>
+#include <numeric>
+#include <unordered_map>
+
+#include "common.hpp"
+#include "kernels.hpp"
+#include "topology.hpp"
+
+namespace bddc {
+
+namespace {
+
+constexpr size_t kLdsLimit = 64 * 1024 - 1024;   // dynamic LDS without an opt-in attribute
+
+inline uint64_t pkey(int s, int t) {
+  return (static_cast<uint64_t>(static_cast<uint32_t>(s)) << 32) | static_cast<uint32_t>(t);
+}
+
+template <class T>
+std::vector<T> prefix(const std::vector<T>& cnt) {
+  std::vector<T> p(cnt.size() + 1, 0);
+  for (size_t i = 0; i < cnt.size(); ++i) p[i + 1] = p[i] + cnt[i];
+  return p;
+}
+
+// reference element matrices (k = 1) of an hx x hy rectangle, local nodes
+// (i,j), (i+1,j), (i+1,j+1), (i,j+1)
+Khat16 element_matrix(int element, int nx, int ny) {
+  const double rho = (1.0 / ny) / (1.0 / nx);   // hy / hx
+  Khat16 k{};
+  if (element == BDDC_Q1) {
+    // (hy/hx) * int dphi/dx dphi/dx + (hx/hy) * int dphi/dy dphi/dy on the unit square
+    const double ax[16] = {2, -2, -1, 1, -2, 2, 1, -1, -1, 1, 2, -2, 1, -1, -2, 2};
+    const double ay[16] = {2, 1, -1, -2, 1, 2, -2, -1, -1, -2, 2, 1, -2, -1, 1, 2};
+    for (int i = 0; i < 16; ++i) k.v[i] = (rho * ax[i] + ay[i] / rho) / 6.0;
+  } else {
+    // two P1 triangles split along the SW-NE diagonal
+    const double a = rho, b = 1.0 / rho;
+    const double m[16] = {a + b, -a, 0, -b, -a, a + b, -b, 0, 0, -b, a + b, -a, -b, 0, -a, a + b};
+    for (int i = 0; i < 16; ++i) k.v[i] = 0.5 * m[i];
+  }
+  return k;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+struct Level {
+  int ell = 1;
+  Topology topo;
+  int nsub = 0, n = 0;
+  // layout
+  std::vector<int64_t> koff;
+  std::vector<int32_t> goff, ioff, coff;
+  int nflat_g = 0, nflat_i = 0, nflat_c = 0;
+  std::vector<int32_t> int_gid, gam_gid, gam_iid, iface_dof, sh_ptr, sh_flat;
+  std::vector<int32_t> nr_v;
+  int nImax = 0, ngmax = 0, nmax = 0, ncsmax = 0, nrmax = 0;
+  // edges and (substructure, edge) incidences
+  int nedge = 0;
+  std::vector<int32_t> edge_nsc, edge_ne, edge_fptr, edge_fdof;
+  std::vector<int32_t> inc_sub, inc_edge, inc_fptr, inc_fpos;
+  std::vector<int32_t> sub_inc_ptr, sub_inc;
+  std::vector<int64_t> inc_off, eig_woff, lamoff, qoff;
+  int nemax = 0;
+  // coarse dofs
+  std::vector<int32_t> edge_m, edge_nsel;
+  std::vector<double> lam;
+  std::vector<double> qhost;     // constraint weights, copied back for queries
+  int nc = 0;
+  std::vector<int32_t> cid, csh_ptr, csh_flat, cd_dof, cd_col, ncr;
+  std::vector<int64_t> croff, toff, psioff, acoff, cwoff;
+  double omega = 0.0;
+  int n_adaptive = 0;
+  std::vector<int32_t> agglom_of;   // level-(l+1) substructure of each substructure
+  // device
+  Arena arena_a, arena_b, arena_pcg;
+  struct {
+    int32_t *loc_ptr, *nint, *nr, *goff, *ioff, *int_gid, *gam_gid, *gam_iid, *iface_dof, *sh_ptr, *sh_flat;
+    int64_t* koff;
+    double *K, *diagK, *delta;
+    // level-1 assembly
+    int32_t *node_el, *sub_el_ptr, *el_gid, *el_loc;
+    double* coeff;
+    // level >= 2 assembly
+    int32_t *child_ptr, *child_id, *child_map_off, *child_map;
+    // incidences / edges
+    int32_t *inc_sub, *inc_edge, *inc_fptr, *inc_fpos, *sub_inc_ptr, *sub_inc;
+    int32_t *edge_s, *edge_t, *edge_nsc, *edge_ne, *edge_fdof, *edge_fptr, *edge_ptr, *edge_dof;
+    uint8_t* floating;
+    int64_t *inc_off, *eig_woff, *lamoff, *qoff;
+    double *Shat, *Sff, *eig_work, *lam, *Q;
+    int32_t *nsel, *nkept;
+    double* z;
+    // coarse
+    int32_t *edge_m, *coff, *cid, *csh_ptr, *csh_flat, *cd_dof, *cd_col, *ncr, *ncs;
+    int64_t *croff, *toff, *psioff, *acoff, *cwoff;
+    double *Cr, *T, *Psi, *Ac, *cwork, *znext;
+    // scratch
+    double *y, *t, *a, *v, *b, *rc, *uc, *qloc;
+  } d{};
+  LevelDev dev;
+};
+
+}  // namespace bddc
+
+struct bddc_ctx {
+  int nx = 0, ny = 0, L = 2, element = 0, constraints = 0, precision = 0;
+  double tau = 0;
+  int64_t n_free = 0;
+  hipStream_t stream = nullptr;
+  std::vector<std::unique_ptr<bddc::Level>> levels;
+  bddc::Arena top;        // coarsest factor, PCG state, status flag
+  double* AL = nullptr;
+  int ncL = 0;
+  int* status = nullptr;
+  // PCG on the level-1 interface
+  double *x = nullptr, *r = nullptr, *p = nullptr, *zv = nullptr, *q = nullptr, *partial = nullptr;
+  bddc::PcgScalars* sc = nullptr;
+  bddc::PcgScalars* sc_host = nullptr;   // pinned
+  int nblk = 1;
+  bddc_info info{};
+};
+
+namespace bddc {
+
+// ---------------------------------------------------------------------------
+// validation
+static void validate(const bddc_problem* p) {
+  if (!p) fail(BDDC_EINVAL, "problem is NULL");
+  if (p->nx < 2 || p->ny < 2) fail(BDDC_EINVAL, "nx and ny must be >= 2");
+  if ((int64_t)p->nx * p->ny > (int64_t)1 << 30) fail(BDDC_EUNSUPPORTED, "mesh too large");
+  if (p->element != BDDC_Q1 && p->element != BDDC_P1) fail(BDDC_EINVAL, "unknown element");
+  if (!p->coeff || !p->part) fail(BDDC_EINVAL, "coeff and part are required");
+  if (p->nsub < 1) fail(BDDC_EINVAL, "nsub must be >= 1");
+  if (p->levels < 2 || p->levels > BDDC_MAX_LEVELS) fail(BDDC_EINVAL, "levels must be in [2, 8]");
+  if (p->constraints < 0 || p->constraints > 2) fail(BDDC_EINVAL, "unknown constraint kind");
+  if (std::isnan(p->tau) || p->tau < 0) fail(BDDC_EINVAL, "tau must be >= 0");
+  if (p->precision != BDDC_FP64) {
+    if (p->precision == BDDC_FP32 || p->precision == BDDC_BF16) fail(BDDC_EUNSUPPORTED, "only FP64 is implemented");
+    fail(BDDC_EINVAL, "unknown precision");
+  }
+  const int64_t ne = (int64_t)p->nx * p->ny;
+  for (int64_t e = 0; e < ne; ++e) {
+    const double k = p->coeff[e];
+    if (!(k > 0.0) || !std::isfinite(k)) fail(BDDC_EINVAL, "coefficients must be positive and finite");
+    if (p->part[e] < 0 || p->part[e] >= p->nsub) fail(BDDC_EPARTITION, "partition id out of range");
+  }
+  std::vector<char> used(p->nsub, 0);
+  for (int64_t e = 0; e < ne; ++e) used[p->part[e]] = 1;
+  for (int s = 0; s < p->nsub; ++s)
+    if (!used[s]) fail(BDDC_EPARTITION, "substructure " + std::to_string(s) + " owns no element");
+  if (p->levels > 2) {
+    if (!p->agglom) fail(BDDC_EINVAL, "agglom is required for levels > 2");
+    int nprev = p->nsub;
+    for (int l = 0; l < p->levels - 2; ++l) {
+      const int32_t* a = p->agglom[l];
+      if (!a) fail(BDDC_EINVAL, "agglom entry is NULL");
+      int mx = -1;
+      for (int s = 0; s < nprev; ++s) {
+        if (a[s] < 0) fail(BDDC_EPARTITION, "agglomeration id out of range");
+        mx = std::max(mx, a[s]);
+      }
+      std::vector<char> u(mx + 1, 0);
+      for (int s = 0; s < nprev; ++s) u[a[s]] = 1;
+      for (int g = 0; g <= mx; ++g)
+        if (!u[g]) fail(BDDC_EPARTITION, "empty agglomerate");
+      nprev = mx + 1;
+    }
+  }
+}
+
+// level-1 element -> dof incidence (Dirichlet nodes dropped)
+struct Level1Elements {
+  std::vector<int32_t> ptr, dof, sub;
+  std::vector<uint8_t> touch;
+  std::vector<int32_t> nodes;   // 4 per element, -1 = Dirichlet
+};
+
+static Level1Elements level1_elements(const bddc_problem* p) {
+  const int nx = p->nx, ny = p->ny;
+  Level1Elements E;
+  const int ne = nx * ny;
+  E.ptr.resize(ne + 1);
+  E.dof.reserve((size_t)ne * 4);
+  E.sub.assign(p->part, p->part + ne);
+  E.touch.assign(ne, 0);
+  E.nodes.resize((size_t)ne * 4);
+  auto fid = [&](int i, int j) -> int {
+    if (i <= 0 || j <= 0 || i >= nx || j >= ny) return -1;
+    return (j - 1) * (nx - 1) + (i - 1);
+  };
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      const int e = j * nx + i;
+      const int nd[4] = {fid(i, j), fid(i + 1, j), fid(i + 1, j + 1), fid(i, j + 1)};
+      E.ptr[e] = (int32_t)E.dof.size();
+      for (int q = 0; q < 4; ++q) {
+        E.nodes[(size_t)e * 4 + q] = nd[q];
+        if (nd[q] >= 0) E.dof.push_back(nd[q]);
+        else E.touch[e] = 1;
+      }
+    }
+  E.ptr[ne] = (int32_t)E.dof.size();
+  return E;
+}
+
+// ---------------------------------------------------------------------------
+// host layout of a level after classification
+static void layout_level(Level& lv) {
+  const Topology& T = lv.topo;
+  const int nsub = lv.nsub = T.nsub;
+  lv.n = T.n;
+  lv.koff.resize(nsub);
+  std::vector<int32_t> gcnt(nsub), icnt(nsub);
+  int64_t ko = 0;
+  for (int s = 0; s < nsub; ++s) {
+    const int n = T.nloc(s);
+    lv.koff[s] = ko;
+    ko += (int64_t)n * n;
+    gcnt[s] = T.ngam(s);
+    icnt[s] = T.n_int[s];
+    lv.nImax = std::max(lv.nImax, (int)T.n_int[s]);
+    lv.ngmax = std::max(lv.ngmax, T.ngam(s));
+    lv.nmax = std::max(lv.nmax, n);
+    lv.nrmax = std::max(lv.nrmax, (int)T.n_r[s]);
+  }
+  lv.goff = prefix(gcnt);
+  lv.ioff = prefix(icnt);
+  lv.nflat_g = lv.goff[nsub];
+  lv.nflat_i = lv.ioff[nsub];
+  lv.nr_v = T.n_r;
+  // interface numbering (ascending dof)
+  std::vector<int32_t> iid(T.n, -1);
+  for (int d = 0; d < T.n; ++d)
+    if (T.nshare[d] >= 2) {
+      iid[d] = (int32_t)lv.iface_dof.size();
+      lv.iface_dof.push_back(d);
+    }
+  const int nif = (int)lv.iface_dof.size();
+  lv.int_gid.resize(lv.nflat_i);
+  lv.gam_gid.resize(lv.nflat_g);
+  lv.gam_iid.resize(lv.nflat_g);
+  std::vector<int32_t> shcnt(nif, 0);
+  for (int s = 0; s < nsub; ++s) {
+    const int b = T.loc_ptr[s], nI = T.n_int[s], ng = T.ngam(s);
+    for (int i = 0; i < nI; ++i) lv.int_gid[lv.ioff[s] + i] = T.loc_dof[b + i];
+    for (int a = 0; a < ng; ++a) {
+      const int d = T.loc_dof[b + nI + a];
+      lv.gam_gid[lv.goff[s] + a] = d;
+      lv.gam_iid[lv.goff[s] + a] = iid[d];
+      shcnt[iid[d]]++;
+    }
+  }
+  lv.sh_ptr = prefix(shcnt);
+  lv.sh_flat.resize(lv.nflat_g);
+  {
+    std::vector<int32_t> pos(lv.sh_ptr.begin(), lv.sh_ptr.end() - 1);
+    for (int s = 0; s < nsub; ++s)
+      for (int a = 0; a < T.ngam(s); ++a) {
+        const int f = lv.goff[s] + a;
+        lv.sh_flat[pos[lv.gam_iid[f]]++] = f;
+      }
+  }
+  // edges: shared corners then edge dofs
+  lv.nedge = T.nedges();
+  std::unordered_map<uint64_t, int> eid;
+  eid.reserve(lv.nedge * 2 + 1);
+  for (int e = 0; e < lv.nedge; ++e) eid[pkey(T.edge_s[e], T.edge_t[e])] = e;
+  std::vector<std::vector<int32_t>> shared(lv.nedge);
+  for (int c : T.corners)
+    for (int a = 0; a < T.nshare[c]; ++a)
+      for (int b2 = a + 1; b2 < T.nshare[c]; ++b2) {
+        auto it = eid.find(pkey(T.share[c][a], T.share[c][b2]));
+        if (it != eid.end()) shared[it->second].push_back(c);
+      }
+  lv.edge_nsc.resize(lv.nedge);
+  lv.edge_ne.resize(lv.nedge);
+  lv.edge_fptr.assign(1, 0);
+  for (int e = 0; e < lv.nedge; ++e) {
+    lv.edge_nsc[e] = (int32_t)shared[e].size();
+    lv.edge_ne[e] = T.edge_ptr[e + 1] - T.edge_ptr[e];
+    for (int c : shared[e]) lv.edge_fdof.push_back(c);
+    for (int k = T.edge_ptr[e]; k < T.edge_ptr[e + 1]; ++k) lv.edge_fdof.push_back(T.edge_dof[k]);
+    lv.edge_fptr.push_back((int32_t)lv.edge_fdof.size());
+    lv.nemax = std::max(lv.nemax, (int)lv.edge_ne[e]);
+  }
+  // incidences: 2e = s side, 2e+1 = t side
+  const int ninc = 2 * lv.nedge;
+  lv.inc_sub.resize(ninc);
+  lv.inc_edge.resize(ninc);
+  std::vector<int32_t> sic(nsub, 0);
+  for (int e = 0; e < lv.nedge; ++e) {
+    lv.inc_sub[2 * e] = T.edge_s[e];
+    lv.inc_sub[2 * e + 1] = T.edge_t[e];
+    lv.inc_edge[2 * e] = lv.inc_edge[2 * e + 1] = e;
+    sic[T.edge_s[e]]++;
+    sic[T.edge_t[e]]++;
+  }
+  lv.sub_inc_ptr = prefix(sic);
+  lv.sub_inc.resize(ninc);
+  {
+    std::vector<int32_t> pos(lv.sub_inc_ptr.begin(), lv.sub_inc_ptr.end() - 1);
+    for (int i = 0; i < ninc; ++i) lv.sub_inc[pos[lv.inc_sub[i]]++] = i;   // ascending edge per sub
+  }
+  lv.inc_fptr.assign(ninc + 1, 0);
+  for (int i = 0; i < ninc; ++i) {
+    const int e = lv.inc_edge[i];
+    lv.inc_fptr[i + 1] = lv.inc_fptr[i] + (lv.edge_fptr[e + 1] - lv.edge_fptr[e]);
+  }
+  lv.inc_fpos.resize(lv.inc_fptr[ninc]);
+  std::vector<int32_t> posin(T.n, -1);
+  for (int s = 0; s < nsub; ++s) {
+    const int b = T.loc_ptr[s] + T.n_int[s];
+    for (int a = 0; a < T.ngam(s); ++a) posin[T.loc_dof[b + a]] = a;
+    for (int k = lv.sub_inc_ptr[s]; k < lv.sub_inc_ptr[s + 1]; ++k) {
+      const int i = lv.sub_inc[k], e = lv.inc_edge[i];
+      int o = lv.inc_fptr[i];
+      for (int q = lv.edge_fptr[e]; q < lv.edge_fptr[e + 1]; ++q) {
+        const int pp = posin[lv.edge_fdof[q]];
+        if (pp < 0) fail(BDDC_EPARTITION, "internal: shared dof not on the substructure interface");
+        lv.inc_fpos[o++] = pp;
+      }
+    }
+    for (int a = 0; a < T.ngam(s); ++a) posin[T.loc_dof[b + a]] = -1;
+  }
+  lv.inc_off.resize(ninc);
+  int64_t io = 0;
+  for (int i = 0; i < ninc; ++i) {
+    const int nf = lv.inc_fptr[i + 1] - lv.inc_fptr[i];
+    lv.inc_off[i] = io;
+    io += (int64_t)nf * nf;
+  }
+  lv.inc_off.push_back(io);
+}
+
+// ---------------------------------------------------------------------------
+class Builder {
+ public:
+  Builder(bddc_ctx* h, const bddc_problem* p) : h_(h), p_(p), st_(h->stream) {}
+
+  void run() {
+    Level1Elements E = level1_elements(p_);
+    // level 1
+    auto lv = std::make_unique<Level>();
+    lv->ell = 1;
+    lv->topo = classify((int)h_->n_free, p_->nsub, E.ptr, E.dof, E.sub, E.touch);
+    layout_level(*lv);
+    check_limits(*lv);
+    top_alloc();
+    alloc_a(*lv, &E, nullptr);
+    assemble_l1(*lv, E);
+    factor_level(*lv, nullptr);
+    h_->levels.push_back(std::move(lv));
+    for (int ell = 2; ell < h_->L; ++ell) {
+      Level& prev = *h_->levels.back();
+      auto nl = std::make_unique<Level>();
+      nl->ell = ell;
+      std::vector<int32_t> eptr(prev.nsub + 1), edof, esub(prev.agglom_of.begin(), prev.agglom_of.end());
+      std::vector<uint8_t> etouch(prev.nsub);
+      for (int s = 0; s < prev.nsub; ++s) {
+        eptr[s] = (int32_t)edof.size();
+        for (int k = prev.coff[s]; k < prev.coff[s + 1]; ++k) edof.push_back(prev.cid[k]);
+        etouch[s] = prev.topo.floating[s] ? 0 : 1;
+      }
+      eptr[prev.nsub] = (int32_t)edof.size();
+      const int nsub_next = *std::max_element(esub.begin(), esub.end()) + 1;
+      nl->topo = classify(prev.nc, nsub_next, eptr, edof, esub, etouch);
+      layout_level(*nl);
+      check_limits(*nl);
+      alloc_a(*nl, nullptr, &prev);
+      assemble_coarse(*nl, prev);
+      factor_level(*nl, &prev);
+      h_->levels.push_back(std::move(nl));
+    }
+    coarsest();
+    BDDC_HIP(hipStreamSynchronize(st_));
+    int bad = 0;
+    BDDC_HIP(hipMemcpy(&bad, h_->status, sizeof(int), hipMemcpyDeviceToHost));
+    if (bad) fail(BDDC_ESINGULAR, "a local or coarse factorization met a non-positive pivot");
+  }
+
+ private:
+  bddc_ctx* h_;
+  const bddc_problem* p_;
+  hipStream_t st_;
+
+  void check_limits(const Level& lv) {
+    if (pair_schur_lds(lv.ngmax) > kLdsLimit || partial_chol_lds(lv.nmax) > kLdsLimit ||
+        pair_eig_lds(lv.nemax) > kLdsLimit)
+      fail(BDDC_EUNSUPPORTED, "substructure interface or edge too large for this build");
+  }
+
+  void top_alloc() {
+    h_->top.reset_sizing();
+    h_->status = h_->top.take<int>(1);
+    h_->top.allocate(st_);
+    h_->status = h_->top.take<int>(1);
+    BDDC_HIP(hipMemsetAsync(h_->status, 0, sizeof(int), st_));
+  }
+
+  // device allocation of everything known before the coarse dofs are chosen
+  void alloc_a(Level& lv, const Level1Elements* E, const Level* prev) {
+    const Topology& T = lv.topo;
+    const int nsub = lv.nsub;
+    const int ninc = 2 * lv.nedge;
+    const bool adaptive = h_->constraints == BDDC_ADAPTIVE;
+    // level-1 assembly maps
+    std::vector<int32_t> node_el, sub_el_ptr, el_gid, el_loc;
+    std::vector<int32_t> child_ptr, child_id, child_map_off, child_map;
+    if (E) {
+      const int ne = h_->nx * h_->ny;
+      std::vector<int32_t> cnt(nsub, 0);
+      for (int e = 0; e < ne; ++e) cnt[E->sub[e]]++;
+      sub_el_ptr = prefix(cnt);
+      el_gid.resize(ne);
+      {
+        std::vector<int32_t> pos(sub_el_ptr.begin(), sub_el_ptr.end() - 1);
+        for (int e = 0; e < ne; ++e) el_gid[pos[E->sub[e]]++] = e;
+      }
+      el_loc.assign((size_t)ne * 4, -1);
+      node_el.assign((size_t)T.loc_ptr[nsub] * 4, -1);
+      std::vector<int32_t> posin(T.n, -1);
+      for (int s = 0; s < nsub; ++s) {
+        const int b = T.loc_ptr[s];
+        for (int a = 0; a < T.nloc(s); ++a) posin[T.loc_dof[b + a]] = a;
+        for (int le = 0; le < sub_el_ptr[s + 1] - sub_el_ptr[s]; ++le) {
+          const int e = el_gid[sub_el_ptr[s] + le];
+          for (int q = 0; q < 4; ++q) {
+            const int d = E->nodes[(size_t)e * 4 + q];
+            if (d < 0) continue;
+            const int a = posin[d];
+            el_loc[(size_t)(sub_el_ptr[s] + le) * 4 + q] = a;
+            int32_t* slot = &node_el[(size_t)(b + a) * 4];
+            int k = 0;
+            while (slot[k] >= 0) ++k;
+            slot[k] = (le << 2) | q;
+          }
+        }
+        for (int a = 0; a < T.nloc(s); ++a) posin[T.loc_dof[b + a]] = -1;
+      }
+    }
+    if (prev) {
+      // children of each level-l substructure and their coarse dofs in its local numbering
+      std::vector<int32_t> cnt(nsub, 0);
+      for (int c = 0; c < prev->nsub; ++c) cnt[prev->agglom_of[c]]++;
+      child_ptr = prefix(cnt);
+      child_id.resize(prev->nsub);
+      {
+        std::vector<int32_t> pos(child_ptr.begin(), child_ptr.end() - 1);
+        for (int c = 0; c < prev->nsub; ++c) child_id[pos[prev->agglom_of[c]]++] = c;
+      }
+      std::vector<int32_t> posin(T.n, -1);
+      for (int s = 0; s < nsub; ++s) {
+        const int b = T.loc_ptr[s];
+        for (int a = 0; a < T.nloc(s); ++a) posin[T.loc_dof[b + a]] = a;
+        for (int k = child_ptr[s]; k < child_ptr[s + 1]; ++k) {
+          const int c = child_id[k];
+          child_map_off.push_back((int32_t)child_map.size());
+          for (int q = prev->coff[c]; q < prev->coff[c + 1]; ++q) child_map.push_back(posin[prev->cid[q]]);
+        }
+        for (int a = 0; a < T.nloc(s); ++a) posin[T.loc_dof[b + a]] = -1;
+      }
+    }
+    // eigen work sizes
+    lv.eig_woff.assign(lv.nedge + 1, 0);
+    lv.lamoff.assign(lv.nedge + 1, 0);
+    lv.qoff.assign(lv.nedge + 1, 0);
+    for (int e = 0; e < lv.nedge; ++e) {
+      const int ne_ = lv.edge_ne[e], nv = lv.edge_nsc[e] + 2 * ne_;
+      lv.eig_woff[e + 1] = lv.eig_woff[e] + (adaptive ? (int64_t)nv * nv + (int64_t)nv * ne_ + (int64_t)ne_ * ne_ : 0);
+      lv.lamoff[e + 1] = lv.lamoff[e] + ne_;
+      lv.qoff[e + 1] = lv.qoff[e] + (int64_t)ne_ * ne_;
+    }
+    std::vector<int32_t> edge_ptr(T.edge_ptr), edge_dof(T.edge_dof);
+    std::vector<uint8_t> floating(T.floating);
+
+    Arena& A = lv.arena_a;
+    auto& d = lv.d;
+    // the same layout runs twice: sizing (null base), then on the allocation
+    auto layout = [&](bool real) {
+      (void)real;
+      d.loc_ptr = A.take<int32_t>(nsub + 1);
+      d.nint = A.take<int32_t>(nsub);
+      d.nr = A.take<int32_t>(nsub);
+      d.goff = A.take<int32_t>(nsub + 1);
+      d.ioff = A.take<int32_t>(nsub + 1);
+      d.koff = A.take<int64_t>(nsub);
+      d.int_gid = A.take<int32_t>(lv.nflat_i);
+      d.gam_gid = A.take<int32_t>(lv.nflat_g);
+      d.gam_iid = A.take<int32_t>(lv.nflat_g);
+      d.iface_dof = A.take<int32_t>(lv.iface_dof.size());
+      d.sh_ptr = A.take<int32_t>(lv.sh_ptr.size());
+      d.sh_flat = A.take<int32_t>(lv.sh_flat.size());
+      d.K = A.take<double>((size_t)(lv.koff.empty() ? 0 : lv.koff.back() + (int64_t)T.nloc(nsub - 1) * T.nloc(nsub - 1)));
+      d.diagK = A.take<double>(lv.nflat_g);
+      d.delta = A.take<double>(lv.nflat_g);
+      d.node_el = A.take<int32_t>(node_el.size());
+      d.sub_el_ptr = A.take<int32_t>(sub_el_ptr.size());
+      d.el_gid = A.take<int32_t>(el_gid.size());
+      d.el_loc = A.take<int32_t>(el_loc.size());
+      d.coeff = A.take<double>(E ? (size_t)h_->nx * h_->ny : 0);
+      d.child_ptr = A.take<int32_t>(child_ptr.size());
+      d.child_id = A.take<int32_t>(child_id.size());
+      d.child_map_off = A.take<int32_t>(child_map_off.size());
+      d.child_map = A.take<int32_t>(child_map.size());
+      d.inc_sub = A.take<int32_t>(ninc);
+      d.inc_edge = A.take<int32_t>(ninc);
+      d.inc_fptr = A.take<int32_t>(ninc + 1);
+      d.inc_fpos = A.take<int32_t>(lv.inc_fpos.size());
+      d.sub_inc_ptr = A.take<int32_t>(nsub + 1);
+      d.sub_inc = A.take<int32_t>(ninc);
+      d.edge_s = A.take<int32_t>(lv.nedge);
+      d.edge_t = A.take<int32_t>(lv.nedge);
+      d.edge_nsc = A.take<int32_t>(lv.nedge);
+      d.edge_ne = A.take<int32_t>(lv.nedge);
+      d.edge_fdof = A.take<int32_t>(lv.edge_fdof.size());
+      d.edge_fptr = A.take<int32_t>(lv.edge_fptr.size());
+      d.edge_ptr = A.take<int32_t>(edge_ptr.size());
+      d.edge_dof = A.take<int32_t>(edge_dof.size());
+      d.floating = A.take<uint8_t>(nsub);
+      d.inc_off = A.take<int64_t>(lv.inc_off.size());
+      d.eig_woff = A.take<int64_t>(lv.eig_woff.size());
+      d.lamoff = A.take<int64_t>(lv.lamoff.size());
+      d.qoff = A.take<int64_t>(lv.qoff.size());
+      d.Shat = A.take<double>(adaptive ? (size_t)lv.inc_off.back() : 0);
+      d.Sff = A.take<double>(adaptive ? (size_t)lv.inc_off.back() : 0);
+      d.eig_work = A.take<double>((size_t)lv.eig_woff.back());
+      d.lam = A.take<double>((size_t)lv.lamoff.back());
+      d.Q = A.take<double>((size_t)lv.qoff.back());
+      d.nsel = A.take<int32_t>(lv.nedge);
+      d.nkept = A.take<int32_t>(lv.nedge);
+      d.z = A.take<double>(lv.n);
+      d.y = A.take<double>(lv.nflat_i);
+      d.t = A.take<double>(lv.nflat_g);
+      d.a = A.take<double>(lv.nflat_g);
+      d.v = A.take<double>(lv.nflat_g);
+      d.qloc = A.take<double>(lv.nflat_g);
+    };
+    A.reset_sizing();
+    layout(false);
+    A.allocate(st_);
+    layout(true);
+
+    std::vector<int32_t> nint(T.n_int), nr(T.n_r);
+    h2d(d.loc_ptr, T.loc_ptr, st_);
+    h2d(d.nint, nint, st_);
+    h2d(d.nr, nr, st_);
+    h2d(d.goff, lv.goff, st_);
+    h2d(d.ioff, lv.ioff, st_);
+    h2d(d.koff, lv.koff, st_);
+    h2d(d.int_gid, lv.int_gid, st_);
+    h2d(d.gam_gid, lv.gam_gid, st_);
+    h2d(d.gam_iid, lv.gam_iid, st_);
+    h2d(d.iface_dof, lv.iface_dof, st_);
+    h2d(d.sh_ptr, lv.sh_ptr, st_);
+    h2d(d.sh_flat, lv.sh_flat, st_);
+    h2d(d.node_el, node_el, st_);
+    h2d(d.sub_el_ptr, sub_el_ptr, st_);
+    h2d(d.el_gid, el_gid, st_);
+    h2d(d.el_loc, el_loc, st_);
+    if (E) BDDC_HIP(hipMemcpyAsync(d.coeff, p_->coeff, sizeof(double) * h_->nx * h_->ny, hipMemcpyHostToDevice, st_));
+    h2d(d.child_ptr, child_ptr, st_);
+    h2d(d.child_id, child_id, st_);
+    h2d(d.child_map_off, child_map_off, st_);
+    h2d(d.child_map, child_map, st_);
+    h2d(d.inc_sub, lv.inc_sub, st_);
+    h2d(d.inc_edge, lv.inc_edge, st_);
+    h2d(d.inc_fptr, lv.inc_fptr, st_);
+    h2d(d.inc_fpos, lv.inc_fpos, st_);
+    h2d(d.sub_inc_ptr, lv.sub_inc_ptr, st_);
+    h2d(d.sub_inc, lv.sub_inc, st_);
+    h2d(d.edge_s, T.edge_s, st_);
+    h2d(d.edge_t, T.edge_t, st_);
+    h2d(d.edge_nsc, lv.edge_nsc, st_);
+    h2d(d.edge_ne, lv.edge_ne, st_);
+    h2d(d.edge_fdof, lv.edge_fdof, st_);
+    h2d(d.edge_fptr, lv.edge_fptr, st_);
+    h2d(d.edge_ptr, edge_ptr, st_);
+    h2d(d.edge_dof, edge_dof, st_);
+    h2d(d.floating, floating, st_);
+    h2d(d.inc_off, lv.inc_off, st_);
+    h2d(d.eig_woff, lv.eig_woff, st_);
+    h2d(d.lamoff, lv.lamoff, st_);
+    h2d(d.qoff, lv.qoff, st_);
+    if (prev) {
+      // the constant's coarse values, computed on the previous level
+      BDDC_HIP(hipMemcpyAsync(d.z, prev->d.znext, sizeof(double) * lv.n, hipMemcpyDeviceToDevice, st_));
+    } else if (adaptive) {
+      std::vector<double> ones(lv.n, 1.0);
+      h2d(d.z, ones, st_);
+      BDDC_HIP(hipStreamSynchronize(st_));
+    }
+    // keep the host staging vectors alive until the copies have been consumed
+    BDDC_HIP(hipStreamSynchronize(st_));
+  }
+
+  void assemble_l1(Level& lv, const Level1Elements&) {
+    const Khat16 kh = element_matrix(p_->element, h_->nx, h_->ny);
+    launch_assemble_l1(st_, lv.nsub, lv.d.koff, lv.d.loc_ptr, lv.d.nint, lv.d.node_el, lv.d.sub_el_ptr,
+                       lv.d.el_gid, lv.d.el_loc, lv.d.coeff, kh, lv.d.K, lv.d.diagK, lv.d.goff);
+  }
+
+  void assemble_coarse(Level& lv, const Level& prev) {
+    launch_assemble_coarse(st_, lv.nsub, lv.d.koff, lv.d.loc_ptr, lv.d.nint, lv.d.child_ptr, lv.d.child_id,
+                           lv.d.child_map_off, lv.d.child_map, prev.d.Ac, prev.d.acoff, prev.d.ncs, lv.d.K,
+                           lv.d.diagK, lv.d.goff);
+  }
+
+  // weights, interior elimination, constraint selection, constrained factors
+  void factor_level(Level& lv, const Level*) {
+    auto& d = lv.d;
+    const Topology& T = lv.topo;
+    launch_weights(st_, lv.nflat_g, d.gam_iid, d.sh_ptr, d.sh_flat, d.diagK, d.delta);
+    launch_partial_chol(st_, lv.nsub, lv.nmax, d.koff, d.loc_ptr, d.nint, d.K, h_->status);
+    const int ne_tot = lv.nedge;
+    lv.edge_m.assign(ne_tot, 0);
+    lv.edge_nsel.assign(ne_tot, 0);
+    std::vector<double> qh;
+    if (h_->constraints == BDDC_ADAPTIVE && ne_tot > 0) {
+      launch_pair_schur(st_, 2 * ne_tot, lv.ngmax, d.inc_sub, d.inc_fptr, d.inc_fpos, d.koff, d.loc_ptr, d.nint,
+                        d.K, d.inc_off, d.Shat, d.Sff, h_->status);
+      launch_pair_eig(st_, ne_tot, lv.nemax, d.edge_s, d.edge_t, d.edge_nsc, d.edge_ne, d.edge_fdof, d.edge_fptr,
+                      d.inc_fptr, d.inc_fpos, d.goff, d.diagK, d.floating, d.z, d.Shat, d.Sff, d.inc_off,
+                      d.eig_work, d.eig_woff, h_->tau, d.lam, d.lamoff, d.Q, d.qoff, d.nsel, d.nkept,
+                      h_->status);
+      std::vector<int32_t> nkept(ne_tot);
+      lv.lam.resize(lv.lamoff.back());
+      BDDC_HIP(hipMemcpyAsync(nkept.data(), d.nkept, sizeof(int32_t) * ne_tot, hipMemcpyDeviceToHost, st_));
+      BDDC_HIP(hipMemcpyAsync(lv.edge_nsel.data(), d.nsel, sizeof(int32_t) * ne_tot, hipMemcpyDeviceToHost, st_));
+      BDDC_HIP(hipMemcpyAsync(lv.lam.data(), d.lam, sizeof(double) * lv.lam.size(), hipMemcpyDeviceToHost, st_));
+      BDDC_HIP(hipStreamSynchronize(st_));
+      lv.omega = 0.0;
+      for (int e = 0; e < ne_tot; ++e) {
+        lv.edge_m[e] = nkept[e];
+        lv.n_adaptive += nkept[e];
+        const int ns = lv.edge_nsel[e], nn = lv.edge_ne[e];
+        const double nxt = ns < nn ? lv.lam[lv.lamoff[e] + ns] : 0.0;
+        lv.omega = std::max(lv.omega, nxt);
+      }
+    } else if (h_->constraints == BDDC_CORNERS_EDGES && ne_tot > 0) {
+      qh.assign(lv.qoff.back(), 0.0);
+      for (int e = 0; e < ne_tot; ++e) {
+        const int nn = lv.edge_ne[e];
+        for (int p = 0; p < nn; ++p) qh[lv.qoff[e] + p] = 1.0 / nn;
+        lv.edge_m[e] = 1;
+      }
+      h2d(d.Q, qh, st_);
+    }
+    coarse_numbering(lv);
+    alloc_b(lv);
+    launch_build_cr(st_, lv.nsub, d.sub_inc_ptr, d.sub_inc, d.inc_edge, d.inc_fptr, d.inc_fpos, d.edge_nsc,
+                    d.edge_ne, d.edge_m, d.qoff, d.Q, d.nr, d.ncr, d.croff, d.Cr);
+    launch_constrained_factor(st_, lv.nsub, d.koff, d.loc_ptr, d.nint, d.nr, d.ncr, d.croff, d.Cr, d.K, d.T,
+                              d.toff, d.Psi, d.psioff, d.Ac, d.acoff, d.cwork, d.cwoff, h_->status);
+    if (h_->constraints == BDDC_ADAPTIVE && lv.ell < h_->L - 1)
+      launch_coarse_z(st_, lv.nc, d.cd_dof, d.cd_col, d.edge_ptr, d.edge_dof, d.qoff, d.Q, d.z, d.znext);
+    // keep the installed constraint weights for queries
+    lv.qhost.resize(lv.qoff.back());
+    if (!lv.qhost.empty())
+      BDDC_HIP(hipMemcpyAsync(lv.qhost.data(), d.Q, sizeof(double) * lv.qhost.size(), hipMemcpyDeviceToHost, st_));
+    BDDC_HIP(hipStreamSynchronize(st_));
+    (void)T;
+    // agglomeration towards the next level
+    if (lv.ell < h_->L - 1) {
+      const int32_t* a = p_->agglom[lv.ell - 1];
+      lv.agglom_of.assign(a, a + lv.nsub);
+    }
+    fill_dev(lv);
+  }
+
+  void coarse_numbering(Level& lv) {
+    const Topology& T = lv.topo;
+    const int nsub = lv.nsub;
+    const int ncorner = (int)T.corners.size();
+    std::vector<int32_t> corner_id(T.n, -1);
+    for (int k = 0; k < ncorner; ++k) corner_id[T.corners[k]] = k;
+    std::vector<int32_t> ebase(lv.nedge + 1, ncorner);
+    for (int e = 0; e < lv.nedge; ++e) ebase[e + 1] = ebase[e] + lv.edge_m[e];
+    lv.nc = ebase[lv.nedge];
+    lv.cd_dof.resize(lv.nc);
+    lv.cd_col.resize(lv.nc);
+    for (int k = 0; k < ncorner; ++k) { lv.cd_dof[k] = T.corners[k]; lv.cd_col[k] = -1; }
+    for (int e = 0; e < lv.nedge; ++e)
+      for (int j = 0; j < lv.edge_m[e]; ++j) { lv.cd_dof[ebase[e] + j] = e; lv.cd_col[ebase[e] + j] = j; }
+    std::vector<int32_t> cnt(nsub);
+    lv.ncr.assign(nsub, 0);
+    for (int s = 0; s < nsub; ++s) {
+      for (int k = lv.sub_inc_ptr[s]; k < lv.sub_inc_ptr[s + 1]; ++k) lv.ncr[s] += lv.edge_m[lv.inc_edge[lv.sub_inc[k]]];
+      cnt[s] = T.n_c[s] + lv.ncr[s];
+    }
+    lv.coff = prefix(cnt);
+    lv.nflat_c = lv.coff[nsub];
+    lv.cid.resize(lv.nflat_c);
+    std::vector<int32_t> ccnt(lv.nc, 0);
+    for (int s = 0; s < nsub; ++s) {
+      int o = lv.coff[s];
+      const int b = T.loc_ptr[s] + T.n_int[s] + T.n_r[s];
+      for (int k = 0; k < T.n_c[s]; ++k) lv.cid[o++] = corner_id[T.loc_dof[b + k]];
+      for (int k = lv.sub_inc_ptr[s]; k < lv.sub_inc_ptr[s + 1]; ++k) {
+        const int e = lv.inc_edge[lv.sub_inc[k]];
+        for (int j = 0; j < lv.edge_m[e]; ++j) lv.cid[o++] = ebase[e] + j;
+      }
+      lv.ncsmax = std::max(lv.ncsmax, cnt[s]);
+    }
+    for (int k : lv.cid) ccnt[k]++;
+    lv.csh_ptr = prefix(ccnt);
+    lv.csh_flat.resize(lv.nflat_c);
+    {
+      std::vector<int32_t> pos(lv.csh_ptr.begin(), lv.csh_ptr.end() - 1);
+      for (int f = 0; f < lv.nflat_c; ++f) lv.csh_flat[pos[lv.cid[f]]++] = f;
+    }
+    // per-substructure offsets of constrained-factor data
+    lv.croff.assign(nsub + 1, 0);
+    lv.toff.assign(nsub + 1, 0);
+    lv.psioff.assign(nsub + 1, 0);
+    lv.acoff.assign(nsub + 1, 0);
+    lv.cwoff.assign(nsub + 1, 0);
+    for (int s = 0; s < nsub; ++s) {
+      const int64_t nr = T.n_r[s], ng = T.ngam(s), ncr = lv.ncr[s], ncs = cnt[s];
+      lv.croff[s + 1] = lv.croff[s] + ncr * nr;
+      lv.toff[s + 1] = lv.toff[s] + nr * nr;
+      lv.psioff[s + 1] = lv.psioff[s] + ng * ncs;
+      lv.acoff[s + 1] = lv.acoff[s] + ncs * ncs;
+      lv.cwoff[s + 1] = lv.cwoff[s] + nr * nr + 2 * nr * ncr + ncr * ncr + ng * ncs;
+    }
+  }
+
+  void alloc_b(Level& lv) {
+    Arena& A = lv.arena_b;
+    auto& d = lv.d;
+    const int nsub = lv.nsub;
+    const bool last = lv.ell == h_->L - 1;
+    auto layout = [&]() {
+      d.edge_m = A.take<int32_t>(lv.nedge);
+      d.coff = A.take<int32_t>(nsub + 1);
+      d.cid = A.take<int32_t>(lv.nflat_c);
+      d.csh_ptr = A.take<int32_t>(lv.nc + 1);
+      d.csh_flat = A.take<int32_t>(lv.nflat_c);
+      d.cd_dof = A.take<int32_t>(lv.nc);
+      d.cd_col = A.take<int32_t>(lv.nc);
+      d.ncr = A.take<int32_t>(nsub);
+      d.ncs = A.take<int32_t>(nsub);
+      d.croff = A.take<int64_t>(nsub + 1);
+      d.toff = A.take<int64_t>(nsub + 1);
+      d.psioff = A.take<int64_t>(nsub + 1);
+      d.acoff = A.take<int64_t>(nsub + 1);
+      d.cwoff = A.take<int64_t>(nsub + 1);
+      d.Cr = A.take<double>(lv.croff[nsub]);
+      d.T = A.take<double>(lv.toff[nsub]);
+      d.Psi = A.take<double>(lv.psioff[nsub]);
+      d.Ac = A.take<double>(lv.acoff[nsub]);
+      d.cwork = A.take<double>(lv.cwoff[nsub]);
+      d.znext = A.take<double>(lv.nc);
+      d.b = A.take<double>(lv.nflat_c);
+      d.rc = A.take<double>(lv.nc);
+      d.uc = A.take<double>(lv.nc);
+      if (last) h_->AL = A.take<double>((size_t)lv.nc * lv.nc);
+    };
+    A.reset_sizing();
+    layout();
+    A.allocate(st_);
+    layout();
+    h2d(d.edge_m, lv.edge_m, st_);
+    h2d(d.coff, lv.coff, st_);
+    h2d(d.cid, lv.cid, st_);
+    h2d(d.csh_ptr, lv.csh_ptr, st_);
+    h2d(d.csh_flat, lv.csh_flat, st_);
+    h2d(d.cd_dof, lv.cd_dof, st_);
+    h2d(d.cd_col, lv.cd_col, st_);
+    h2d(d.ncr, lv.ncr, st_);
+    std::vector<int32_t> ncs(nsub);
+    for (int s = 0; s < nsub; ++s) ncs[s] = lv.coff[s + 1] - lv.coff[s];
+    h2d(d.ncs, ncs, st_);
+    h2d(d.croff, lv.croff, st_);
+    h2d(d.toff, lv.toff, st_);
+    h2d(d.psioff, lv.psioff, st_);
+    h2d(d.acoff, lv.acoff, st_);
+    h2d(d.cwoff, lv.cwoff, st_);
+    BDDC_HIP(hipStreamSynchronize(st_));
+  }
+
+  void fill_dev(Level& lv) {
+    LevelDev& D = lv.dev;
+    auto& d = lv.d;
+    D.nsub = lv.nsub;
+    D.nc = lv.nc;
+    D.koff = d.koff;
+    D.loc_ptr = d.loc_ptr;
+    D.nint = d.nint;
+    D.nr = d.nr;
+    D.goff = d.goff;
+    D.ioff = d.ioff;
+    D.coff = d.coff;
+    D.int_gid = d.int_gid;
+    D.gam_gid = d.gam_gid;
+    D.gam_iid = d.gam_iid;
+    D.sh_ptr = d.sh_ptr;
+    D.sh_flat = d.sh_flat;
+    D.cid = d.cid;
+    D.K = d.K;
+    D.delta = d.delta;
+    D.T = d.T;
+    D.toff = d.toff;
+    D.Psi = d.Psi;
+    D.psioff = d.psioff;
+    D.y = d.y;
+    D.t = d.t;
+    D.a = d.a;
+    D.v = d.v;
+    D.b = d.b;
+  }
+
+  void coarsest() {
+    Level& lv = *h_->levels.back();
+    h_->ncL = lv.nc;
+    if (lv.nc > 0)
+      launch_coarsest_factor(st_, lv.nsub, lv.nc, lv.d.coff, lv.d.cid, lv.d.Ac, lv.d.acoff, h_->AL, h_->status);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// apply: Algorithm "Multilevel BDDC" from level li down and back up
+static void apply_level(bddc_ctx* h, int li, const double* r, double* u, bool interface_only) {
+  Level& lv = *h->levels[li];
+  hipStream_t st = h->stream;
+  const bool interior = !interface_only;
+  const int32_t* gmap = interface_only ? lv.d.gam_iid : lv.d.gam_gid;
+  if (interior) launch_apply_pre(st, lv.dev, lv.nImax, lv.ngmax, r);
+  launch_apply_restrict(st, lv.dev, lv.ngmax, r, gmap, interior ? 1 : 0);
+  launch_coarse_gather(st, lv.nc, lv.d.csh_ptr, lv.d.csh_flat, lv.d.b, lv.d.rc);
+  if (li + 1 == (int)h->levels.size())
+    launch_coarsest_solve(st, lv.nc, h->AL, lv.d.rc, lv.d.uc);
+  else
+    apply_level(h, li + 1, lv.d.rc, lv.d.uc, false);
+  launch_apply_prolong(st, lv.dev, lv.ncsmax, lv.d.uc);
+  launch_apply_post(st, lv.dev, lv.nImax, lv.ngmax, u, gmap, interior ? 1 : 0);
+}
+
+// symmetric tridiagonal extreme eigenvalues by Sturm bisection
+static double tri_eig(const std::vector<double>& a, const std::vector<double>& b, bool largest) {
+  const int n = (int)a.size();
+  double lo = 1e300, hi = -1e300;
+  for (int i = 0; i < n; ++i) {
+    const double r = (i > 0 ? std::fabs(b[i - 1]) : 0) + (i + 1 < n ? std::fabs(b[i]) : 0);
+    lo = std::min(lo, a[i] - r);
+    hi = std::max(hi, a[i] + r);
+  }
+  auto count_below = [&](double x) {
+    int c = 0;
+    double q = 1.0;
+    for (int i = 0; i < n; ++i) {
+      q = a[i] - x - (i > 0 ? b[i - 1] * b[i - 1] / q : 0.0);
+      if (q == 0.0) q = -1e-300;
+      if (q < 0) ++c;
+    }
+    return c;
+  };
+  const int target = largest ? n - 1 : 0;   // index of the eigenvalue
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (count_below(mid) > target) hi = mid; else lo = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+static double lanczos_kappa(const std::vector<double>& al, const std::vector<double>& be) {
+  const int k = (int)al.size();
+  if (k == 0) return 1.0;
+  std::vector<double> a(k), b(std::max(0, k - 1));
+  for (int i = 0; i < k; ++i) {
+    a[i] = 1.0 / al[i] + (i > 0 ? be[i - 1] / al[i - 1] : 0.0);
+    if (i + 1 < k) b[i] = std::sqrt(std::max(0.0, be[i])) / al[i];
+  }
+  const double mx = tri_eig(a, b, true), mn = tri_eig(a, b, false);
+  return mn > 0 ? mx / mn : 0.0;
+}
+
+static int pcg_one(bddc_ctx* h, const double* f, double* u, double rtol, int maxit, double* relres) {
+  hipStream_t st = h->stream;
+  Level& l1 = *h->levels[0];
+  const int nif = (int)l1.iface_dof.size();
+  const int nb = h->nblk;
+  const int nbf = std::min(1024, std::max(1, (int)((h->n_free + kNT - 1) / kNT)));
+  PcgScalars* sch = h->sc_host;
+  std::memset(sch, 0, offsetof(PcgScalars, alphas));
+  sch->maxit = maxit;
+  sch->rtol2 = rtol * rtol;   // thr2 = rtol^2 ||f||^2 is formed on the device
+  BDDC_HIP(hipMemcpyAsync(h->sc, sch, offsetof(PcgScalars, alphas), hipMemcpyHostToDevice, st));
+  launch_dot_partial(st, nbf, (int)h->n_free, f, f, h->partial);
+  launch_scalar(st, 4, nbf, h->partial, h->sc);                   // bb, thr2 = rtol^2 bb
+  launch_apply_pre(st, l1.dev, l1.nImax, l1.ngmax, f);            // y = L^{-1} f_I, t = L_GI y
+  launch_condense(st, nif, l1.d.sh_ptr, l1.d.sh_flat, l1.d.iface_dof, f, l1.d.t, h->r, h->x);
+  launch_dot_partial(st, nb, nif, h->r, h->r, h->partial);
+  launch_scalar(st, 5, nb, h->partial, h->sc);                    // rr0, done if already small
+  apply_level(h, 0, h->r, h->zv, true);
+  launch_dot_partial(st, nb, nif, h->r, h->zv, h->partial);
+  launch_scalar(st, 3, nb, h->partial, h->sc);                    // rz
+  launch_update_p(st, nb, nif, h->sc, h->zv, h->p, 1);
+  int it = 0;
+  int check = 1;
+  while (it < maxit) {
+    for (int k = 0; k < check && it < maxit; ++k, ++it) {
+      launch_schur_local(st, l1.dev, l1.ngmax, h->p, l1.d.qloc);
+      launch_gather_dot(st, nb, nif, l1.d.sh_ptr, l1.d.sh_flat, l1.d.qloc, h->p, h->q, h->partial);
+      launch_scalar(st, 0, nb, h->partial, h->sc);                // alpha
+      launch_update_xr(st, nb, nif, h->sc, h->p, h->q, h->x, h->r, h->partial);
+      launch_scalar(st, 1, nb, h->partial, h->sc);                // rr, convergence
+      apply_level(h, 0, h->r, h->zv, true);
+      launch_dot_partial(st, nb, nif, h->r, h->zv, h->partial);
+      launch_scalar(st, 2, nb, h->partial, h->sc);                // beta
+      launch_update_p(st, nb, nif, h->sc, h->zv, h->p, 0);
+    }
+    BDDC_HIP(hipMemcpyAsync(sch, h->sc, offsetof(PcgScalars, alphas), hipMemcpyDeviceToHost, st));
+    BDDC_HIP(hipStreamSynchronize(st));
+    if (sch->done) break;
+    check = std::min(16, check * 2);
+  }
+  launch_recover(st, l1.dev, l1.nImax, l1.ngmax, h->x, u);
+  BDDC_HIP(hipMemcpyAsync(sch, h->sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, st));
+  BDDC_HIP(hipStreamSynchronize(st));
+  const int iters = sch->iters;
+  *relres = sch->bb > 0 ? std::sqrt(sch->rr / sch->bb) : 0.0;
+  std::vector<double> al(sch->alphas, sch->alphas + std::min(iters, kMaxHist));
+  std::vector<double> be(sch->betas, sch->betas + std::max(0, std::min(iters, kMaxHist) - 1));
+  h->info.kappa = lanczos_kappa(al, be);
+  h->info.last_iters = iters;
+  return sch->done == 1 ? iters : -iters - 1;
+}
+
+static int64_t model_bytes(const bddc_ctx* h, bool apply) {
+  // algorithmic bytes of one interface operator product / one preconditioner apply
+  int64_t bytes = 0;
+  for (size_t li = 0; li < h->levels.size(); ++li) {
+    const Level& lv = *h->levels[li];
+    const Topology& T = lv.topo;
+    for (int s = 0; s < lv.nsub; ++s) {
+      const int64_t nI = T.n_int[s], ng = T.ngam(s), nr = T.n_r[s];
+      const int64_t ncs = lv.coff[s + 1] - lv.coff[s];
+      if (!apply) {
+        if (li == 0) bytes += 8 * ng * ng;
+        continue;
+      }
+      bytes += 8 * (nr * nr + 2 * ng * ncs);                       // T_rr once, Psi twice
+      if (li > 0) bytes += 8 * (nI * (nI + 1) + 2 * ng * nI);      // L_II two sweeps (lower), L_GI twice
+    }
+    if (!apply) {
+      if (li == 0) bytes += 8 * (int64_t)(3 * lv.nflat_g + 3 * lv.iface_dof.size());
+      break;
+    }
+    bytes += 8 * (int64_t)(6 * lv.nflat_g + 3 * lv.nflat_c + 2 * lv.iface_dof.size() + 2 * lv.nc);
+  }
+  if (apply) bytes += 8 * (int64_t)h->ncL * (h->ncL + 1);
+  return bytes;
+}
+
+}  // namespace bddc
+
+// ===========================================================================
+using namespace bddc;
+
+namespace {
+
+bddc_status guard(const std::function<void()>& fn) {
+  try {
+    fn();
+    return BDDC_OK;
+  } catch (const Error& e) {
+    if (getenv("BDDC_VERBOSE")) fprintf(stderr, "libbddc: %s\n", e.msg.c_str());
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    return BDDC_ENOMEM;
+  } catch (...) {
+    return BDDC_EDEVICE;
+  }
+}
+
+void release(bddc_ctx* h) {
+  if (!h) return;
+  hipStream_t st = h->stream;
+  (void)hipStreamSynchronize(st);
+  for (auto& lv : h->levels) {
+    lv->arena_a.release(st);
+    lv->arena_b.release(st);
+    lv->arena_pcg.release(st);
+  }
+  h->top.release(st);
+  if (h->sc_host) (void)hipHostFree(h->sc_host);
+  (void)hipStreamSynchronize(st);
+  delete h;
+}
+
+void fill_level_info(const Level& lv, int idx, bddc_info* info) {
+  info->nsub[idx] = lv.nsub;
+  info->n_dof[idx] = lv.n;
+  info->n_interface[idx] = (int32_t)lv.iface_dof.size();
+  info->n_corners[idx] = (int32_t)lv.topo.corners.size();
+  info->n_edges[idx] = lv.nedge;
+  info->nc[idx] = lv.nc;
+  info->n_adaptive[idx] = lv.n_adaptive;
+  info->omega[idx] = lv.omega;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* bddc_status_string(bddc_status s) {
+  switch (s) {
+    case BDDC_OK: return "ok";
+    case BDDC_EINVAL: return "invalid argument";
+    case BDDC_ENOMEM: return "out of device memory";
+    case BDDC_ESINGULAR: return "singular local or coarse problem";
+    case BDDC_EPARTITION: return "invalid partition";
+    case BDDC_ENOCONV: return "PCG did not converge within maxit";
+    case BDDC_EDEVICE: return "HIP runtime error";
+    case BDDC_EBUSY: return "busy";
+    case BDDC_EUNSUPPORTED: return "unsupported by this build";
+  }
+  return "unknown status";
+}
+
+bddc_status bddc_plan(const bddc_problem* p, bddc_info* info) {
+  return guard([&] {
+    validate(p);
+    if (!info) fail(BDDC_EINVAL, "info is NULL");
+    Level1Elements E = level1_elements(p);
+    Level lv;
+    lv.topo = classify((p->nx - 1) * (p->ny - 1), p->nsub, E.ptr, E.dof, E.sub, E.touch);
+    layout_level(lv);
+    std::memset(info, 0, sizeof(*info));
+    info->n_free = (int64_t)(p->nx - 1) * (p->ny - 1);
+    info->levels = p->levels;
+    fill_level_info(lv, 0, info);
+  });
+}
+
+bddc_status bddc_setup(const bddc_problem* p, void* hip_stream, bddc_handle* out) {
+  if (out) *out = nullptr;
+  bddc_ctx* h = nullptr;
+  bddc_status st = guard([&] {
+    validate(p);
+    if (!out) fail(BDDC_EINVAL, "out is NULL");
+    h = new bddc_ctx();
+    h->nx = p->nx;
+    h->ny = p->ny;
+    h->L = p->levels;
+    h->element = p->element;
+    h->constraints = p->constraints;
+    h->precision = p->precision;
+    h->tau = p->tau;
+    h->n_free = (int64_t)(p->nx - 1) * (p->ny - 1);
+    h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    Builder(h, p).run();
+    // PCG state on the level-1 interface
+    Level& l1 = *h->levels[0];
+    const int nif = (int)l1.iface_dof.size();
+    h->nblk = std::min(256, std::max(1, (nif + kNT - 1) / kNT));
+    Arena& B = h->levels[0]->arena_pcg;
+    auto lay = [&] {
+      h->x = B.take<double>(nif);
+      h->r = B.take<double>(nif);
+      h->p = B.take<double>(nif);
+      h->zv = B.take<double>(nif);
+      h->q = B.take<double>(nif);
+      h->partial = B.take<double>(1024);
+      h->sc = B.take<PcgScalars>(1);
+    };
+    B.reset_sizing();
+    lay();
+    B.allocate(h->stream);
+    lay();
+    BDDC_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->sc_host), sizeof(PcgScalars), hipHostMallocDefault));
+    BDDC_HIP(hipStreamSynchronize(h->stream));
+    // info
+    std::memset(&h->info, 0, sizeof(h->info));
+    h->info.n_free = h->n_free;
+    h->info.levels = h->L;
+    double ind = h->constraints == BDDC_ADAPTIVE ? 1.0 : 0.0;
+    size_t dev = 0;
+    for (size_t i = 0; i < h->levels.size(); ++i) {
+      fill_level_info(*h->levels[i], (int)i, &h->info);
+      if (h->constraints == BDDC_ADAPTIVE) ind *= h->levels[i]->omega;
+      dev += h->levels[i]->arena_a.size() + h->levels[i]->arena_b.size() + h->levels[i]->arena_pcg.size();
+    }
+    h->info.indicator = ind;
+    h->info.device_bytes = (int64_t)(dev + h->top.size());
+    h->info.apply_bytes = model_bytes(h, true);
+    h->info.matvec_bytes = model_bytes(h, false);
+    *out = h;
+  });
+  if (st != BDDC_OK && h) {
+    release(h);
+    if (out) *out = nullptr;
+  }
+  return st;
+}
+
+bddc_status bddc_apply(bddc_handle h, const double* r, double* z, int32_t nrhs, int64_t ld, void* hip_stream) {
+  return guard([&] {
+    if (!h || !r || !z || nrhs < 0 || ld < h->n_free) fail(BDDC_EINVAL, "bad apply arguments");
+    if (r == z) fail(BDDC_EINVAL, "r and z must not alias");
+    hipStream_t saved = h->stream;
+    h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    for (int c = 0; c < nrhs; ++c) apply_level(h, 0, r + (size_t)c * ld, z + (size_t)c * ld, false);
+    h->stream = saved;
+  });
+}
+
+bddc_status bddc_solve(bddc_handle h, const double* f, double* u, int32_t nrhs, int64_t ld, double rtol,
+                       int32_t maxit, int32_t* iters, double* relres, void* hip_stream) {
+  bool noconv = false;
+  bddc_status st = guard([&] {
+    if (!h || !f || !u || nrhs < 0 || ld < h->n_free || !(rtol >= 0) || maxit < 0 || !iters || !relres)
+      fail(BDDC_EINVAL, "bad solve arguments");
+    if (maxit > kMaxHist) fail(BDDC_EINVAL, "maxit too large");
+    hipStream_t saved = h->stream;
+    h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    for (int c = 0; c < nrhs; ++c) {
+      const int k = pcg_one(h, f + (size_t)c * ld, u + (size_t)c * ld, rtol, maxit, &relres[c]);
+      iters[c] = k >= 0 ? k : -k - 1;
+      if (k < 0) noconv = true;
+    }
+    h->stream = saved;
+  });
+  if (st == BDDC_OK && noconv) return BDDC_ENOCONV;
+  return st;
+}
+
+bddc_status bddc_query(bddc_handle h, bddc_info* info) {
+  if (!h || !info) return BDDC_EINVAL;
+  *info = h->info;
+  return BDDC_OK;
+}
+
+bddc_status bddc_edge_eigs(bddc_handle h, int32_t level, int32_t edge, double* lam, int32_t cap,
+                           int32_t* n_lam, int32_t* n_sel, int32_t* pair, int32_t* n_edge_dofs) {
+  if (!h || h->constraints != BDDC_ADAPTIVE || level < 1 || level > (int)h->levels.size()) return BDDC_EINVAL;
+  const Level& lv = *h->levels[level - 1];
+  if (edge < 0 || edge >= lv.nedge || cap < 0) return BDDC_EINVAL;
+  const int ne = lv.edge_ne[edge];
+  if (lam)
+    for (int i = 0; i < std::min(cap, ne); ++i) lam[i] = lv.lam[lv.lamoff[edge] + i];
+  if (n_lam) *n_lam = ne;
+  if (n_sel) *n_sel = lv.edge_nsel[edge];
+  if (pair) { pair[0] = lv.topo.edge_s[edge]; pair[1] = lv.topo.edge_t[edge]; }
+  if (n_edge_dofs) *n_edge_dofs = ne;
+  return BDDC_OK;
+}
+
+bddc_status bddc_edge_constraints(bddc_handle h, int32_t level, int32_t edge, int32_t* dofs, int32_t cap_dofs,
+                                  double* q, int32_t cap_q, int32_t* n_edge_dofs, int32_t* n_cols) {
+  if (!h || level < 1 || level > (int)h->levels.size()) return BDDC_EINVAL;
+  const Level& lv = *h->levels[level - 1];
+  if (edge < 0 || edge >= lv.nedge) return BDDC_EINVAL;
+  const int ne = lv.edge_ne[edge];
+  const int m = lv.edge_m.empty() ? 0 : lv.edge_m[edge];
+  if (n_edge_dofs) *n_edge_dofs = ne;
+  if (n_cols) *n_cols = m;
+  if (dofs) {
+    if (cap_dofs < ne) return BDDC_EINVAL;
+    for (int p = 0; p < ne; ++p) dofs[p] = lv.topo.edge_dof[lv.topo.edge_ptr[edge] + p];
+  }
+  if (q) {
+    if (cap_q < ne * m) return BDDC_EINVAL;
+    for (int i = 0; i < ne * m; ++i) q[i] = lv.qhost[lv.qoff[edge] + i];
+  }
+  return BDDC_OK;
+}
+
+void bddc_destroy(bddc_handle h) { release(h); }
+
+}  // extern "C"

@@ -1,0 +1,73 @@
+// Shared host-side definitions of libbddc: error type, HIP checks, device arena.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/bddc.h"
+
+namespace bddc {
+
+struct Error {
+  bddc_status status;
+  std::string msg;
+};
+
+[[noreturn]] inline void fail(bddc_status s, const std::string& msg) { throw Error{s, msg}; }
+
+#define BDDC_HIP(call)                                                                   \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      ::bddc::fail(BDDC_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));    \
+  } while (0)
+
+// One device allocation carved into aligned pieces.  Pieces are laid out by a
+// sizing pass (base == nullptr) and then a second pass after allocation.
+class Arena {
+ public:
+  void reset_sizing() { base_ = nullptr; used_ = 0; }
+  template <class T>
+  T* take(size_t count) {
+    size_t bytes = ((count * sizeof(T)) + 255) & ~size_t(255);
+    size_t off = used_;
+    used_ += bytes;
+    if (!base_) return nullptr;
+    return reinterpret_cast<T*>(base_ + off);
+  }
+  size_t used() const { return used_; }
+  void allocate(hipStream_t st) {
+    size_t n = used_ ? used_ : 256;
+    hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&base_), n, st);
+    if (e != hipSuccess) {
+      base_ = nullptr;
+      fail(e == hipErrorOutOfMemory ? BDDC_ENOMEM : BDDC_EDEVICE,
+           std::string("hipMallocAsync: ") + hipGetErrorString(e));
+    }
+    size_ = n;
+    used_ = 0;
+  }
+  void release(hipStream_t st) {
+    if (base_) (void)hipFreeAsync(base_, st);
+    base_ = nullptr;
+  }
+  size_t size() const { return size_; }
+
+ private:
+  char* base_ = nullptr;
+  size_t used_ = 0;
+  size_t size_ = 0;
+};
+
+template <class T>
+void h2d(T* dst, const std::vector<T>& src, hipStream_t st) {
+  if (!src.empty())
+    BDDC_HIP(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, st));
+}
+
+}  // namespace bddc

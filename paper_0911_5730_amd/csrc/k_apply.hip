@@ -1,0 +1,418 @@
+// Preconditioner apply (Algorithm "Multilevel BDDC", Section 2.1) and the PCG
+// vector kernels (Section 5).
+//
+// Per level, one workgroup per substructure:
+//   k_apply_pre      interior pre-correction and residual update (ML-uIi, ML-rBi):
+//                    y = L_II^{-1} r_I, t = L_GI y  (r_B on the interface = r - sum t)
+//   k_apply_restrict g = D R r_B on the interface; substructure correction
+//                    a = T_rr g_r (ML-wDi) and coarse right-hand side b = Psi^T g
+//   k_coarse_gather  r_{l+1} = sum_s R_cs^T b_s (ML-coarse, ML-ri+1)
+//   k_coarsest_solve direct solve at the last level
+//   k_apply_prolong  v = D (a + Psi u_{l+1})     (ML-uBi-1 before the sum)
+//   k_apply_post     u_B = sum_s R_s^T v_s; interior post-correction and
+//                    combination (ML-vIi, ML-ui): u_I = L_II^{-T}(y - L_GI^T u_B)
+// Interface sums run over the sharers of each dof in a fixed order: no atomics,
+// results are reproducible run to run.
+#include "dense.hpp"
+#include "kernels.hpp"
+
+namespace bddc {
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
+// y = L_II^{-1} r_I ; t = L_GI y
+__global__ void __launch_bounds__(kNT) k_apply_pre(LevelDev L, const double* __restrict__ r) {
+  extern __shared__ double sh[];
+  const int s = blockIdx.x;
+  const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
+  const int nI = L.nint[s];
+  const int ng = n - nI;
+  const double* A = L.K + L.koff[s];
+  double* y = sh;
+  double* part = sh + nI;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < nI; i += kNT) y[i] = r[L.int_gid[L.ioff[s] + i]];
+  __syncthreads();
+  wg_trsv_lower(A, n, nI, y);
+  for (int i = tid; i < nI; i += kNT) L.y[L.ioff[s] + i] = y[i];
+  if (ng == 0) return;
+  const int nch = max(1, kNT / ng);
+  for (int idx = tid; idx < ng * nch; idx += kNT) {
+    const int a = idx % ng, c = idx / ng;
+    double acc = 0.0;
+    for (int j = c; j < nI; j += nch) acc += A[(nI + a) + (size_t)j * n] * y[j];
+    part[idx] = acc;
+  }
+  __syncthreads();
+  for (int a = tid; a < ng; a += kNT) {
+    double acc = 0.0;
+    for (int c = 0; c < nch; ++c) acc += part[a + c * ng];
+    L.t[L.goff[s] + a] = acc;
+  }
+}
+
+// g = delta (r_Gamma - sum t);  a_r = T_rr g_r, a_c = 0;  b = Psi^T g
+__global__ void __launch_bounds__(kNT) k_apply_restrict(LevelDev L, const double* __restrict__ r,
+                                                        const int32_t* __restrict__ gam_map, int use_t) {
+  extern __shared__ double sh[];
+  const int s = blockIdx.x;
+  const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
+  const int nI = L.nint[s];
+  const int ng = n - nI;
+  const int n_r = L.nr[s];
+  const int ncs = L.coff[s + 1] - L.coff[s];
+  const int g0 = L.goff[s];
+  double* g = sh;
+  double* part = sh + ng;
+  const int tid = threadIdx.x;
+  for (int a = tid; a < ng; a += kNT) {
+    const int f = g0 + a;
+    double v = r[gam_map[f]];
+    if (use_t) {
+      const int gi = L.gam_iid[f];
+      for (int k = L.sh_ptr[gi]; k < L.sh_ptr[gi + 1]; ++k) v -= L.t[L.sh_flat[k]];
+    }
+    g[a] = L.delta[f] * v;
+  }
+  __syncthreads();
+  const double* T = L.T + L.toff[s];
+  if (n_r > 0) {
+    const int nch = max(1, kNT / n_r);
+    for (int idx = tid; idx < n_r * nch; idx += kNT) {
+      const int i = idx % n_r, c = idx / n_r;
+      double acc = 0.0;
+      for (int j = c; j < n_r; j += nch) acc += T[i + (size_t)j * n_r] * g[j];
+      part[idx] = acc;
+    }
+  }
+  // b = Psi^T g, one wave per coarse dof
+  const double* P = L.Psi + L.psioff[s];
+  const int wave = tid >> 6, lane = tid & 63;
+  for (int k = wave; k < ncs; k += kNT / 64) {
+    double acc = 0.0;
+    for (int a = lane; a < ng; a += 64) acc += P[a + (size_t)k * ng] * g[a];
+    acc = wave_sum(acc);
+    if (lane == 0) L.b[L.coff[s] + k] = acc;
+  }
+  __syncthreads();
+  if (n_r > 0) {
+    const int nch = max(1, kNT / n_r);
+    for (int i = tid; i < n_r; i += kNT) {
+      double acc = 0.0;
+      for (int c = 0; c < nch; ++c) acc += part[i + c * n_r];
+      L.a[g0 + i] = acc;
+    }
+  }
+  for (int a = n_r + tid; a < ng; a += kNT) L.a[g0 + a] = 0.0;
+}
+
+__global__ void k_coarse_gather(int nc, const int32_t* __restrict__ csh_ptr, const int32_t* __restrict__ csh_flat,
+                                const double* __restrict__ b, double* __restrict__ rc) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nc) return;
+  double acc = 0.0;
+  for (int q = csh_ptr[k]; q < csh_ptr[k + 1]; ++q) acc += b[csh_flat[q]];
+  rc[k] = acc;
+}
+
+__global__ void __launch_bounds__(kNT) k_coarsest_solve(int nc, const double* __restrict__ Lc,
+                                                        const double* __restrict__ rc, double* __restrict__ uc) {
+  extern __shared__ double y[];
+  for (int i = threadIdx.x; i < nc; i += kNT) y[i] = rc[i];
+  __syncthreads();
+  wg_trsv_lower(Lc, nc, nc, y);
+  wg_trsv_lower_trans(Lc, nc, nc, y);
+  for (int i = threadIdx.x; i < nc; i += kNT) uc[i] = y[i];
+}
+
+// v = delta (a + Psi u_c)
+__global__ void __launch_bounds__(kNT) k_apply_prolong(LevelDev L, const double* __restrict__ uc) {
+  extern __shared__ double sh[];
+  const int s = blockIdx.x;
+  const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
+  const int ng = n - L.nint[s];
+  const int ncs = L.coff[s + 1] - L.coff[s];
+  const int g0 = L.goff[s];
+  double* ul = sh;
+  for (int k = threadIdx.x; k < ncs; k += kNT) ul[k] = uc[L.cid[L.coff[s] + k]];
+  __syncthreads();
+  const double* P = L.Psi + L.psioff[s];
+  for (int a = threadIdx.x; a < ng; a += kNT) {
+    double w = L.a[g0 + a];
+    for (int k = 0; k < ncs; ++k) w += P[a + (size_t)k * ng] * ul[k];
+    L.v[g0 + a] = L.delta[g0 + a] * w;
+  }
+}
+
+// u_B = sum over sharers of v (owner writes); interior: u_I = L^{-T}(y - L_GI^T u_B)
+__global__ void __launch_bounds__(kNT) k_apply_post(LevelDev L, double* __restrict__ u,
+                                                    const int32_t* __restrict__ gam_map, int interior) {
+  extern __shared__ double sh[];
+  const int s = blockIdx.x;
+  const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
+  const int nI = L.nint[s];
+  const int ng = n - nI;
+  const int g0 = L.goff[s];
+  double* uB = sh;
+  double* yv = sh + ng;
+  const int tid = threadIdx.x;
+  for (int a = tid; a < ng; a += kNT) {
+    const int f = g0 + a;
+    const int gi = L.gam_iid[f];
+    double acc = 0.0;
+    for (int k = L.sh_ptr[gi]; k < L.sh_ptr[gi + 1]; ++k) acc += L.v[L.sh_flat[k]];
+    uB[a] = acc;
+    if (L.sh_flat[L.sh_ptr[gi]] == f) u[gam_map[f]] = acc;
+  }
+  if (!interior || nI == 0) return;
+  __syncthreads();
+  const double* A = L.K + L.koff[s];
+  for (int j = tid; j < nI; j += kNT) {
+    double acc = 0.0;
+    for (int a = 0; a < ng; ++a) acc += A[(nI + a) + (size_t)j * n] * uB[a];
+    yv[j] = L.y[L.ioff[s] + j] - acc;
+  }
+  __syncthreads();
+  wg_trsv_lower_trans(A, n, nI, yv);
+  for (int j = tid; j < nI; j += kNT) u[L.int_gid[L.ioff[s] + j]] = yv[j];
+}
+
+// Interface operator of the interface-reduced level 1: q_s = S_s p_s (local),
+// summed over sharers afterwards.
+__global__ void __launch_bounds__(kNT) k_schur_local(LevelDev L, const double* __restrict__ p,
+                                                     double* __restrict__ qloc) {
+  extern __shared__ double sh[];
+  const int s = blockIdx.x;
+  const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
+  const int nI = L.nint[s];
+  const int ng = n - nI;
+  const int g0 = L.goff[s];
+  const double* S = L.K + L.koff[s] + nI + (size_t)nI * n;
+  double* pl = sh;
+  double* part = sh + ng;
+  const int tid = threadIdx.x;
+  for (int a = tid; a < ng; a += kNT) pl[a] = p[L.gam_iid[g0 + a]];
+  __syncthreads();
+  const int nch = max(1, kNT / ng);
+  for (int idx = tid; idx < ng * nch; idx += kNT) {
+    const int i = idx % ng, c = idx / ng;
+    double acc = 0.0;
+    for (int j = c; j < ng; j += nch) acc += S[i + (size_t)j * n] * pl[j];
+    part[idx] = acc;
+  }
+  __syncthreads();
+  for (int i = tid; i < ng; i += kNT) {
+    double acc = 0.0;
+    for (int c = 0; c < nch; ++c) acc += part[i + c * ng];
+    qloc[g0 + i] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// PCG vector kernels on the level-1 interface.  Reductions: each block writes
+// one partial (tree in LDS), a single block sums the partials in a fixed order.
+// The scalars live in device memory; once `done` is set the update kernels
+// leave x, r, p unchanged, so extra queued iterations are harmless.
+
+__device__ inline double block_sum(double v, double* red) { return wg_sum(v, red); }
+
+__global__ void __launch_bounds__(kNT) k_gather_dot(int nif, const int32_t* __restrict__ sh_ptr,
+                                                    const int32_t* __restrict__ sh_flat,
+                                                    const double* __restrict__ qloc, const double* __restrict__ p,
+                                                    double* __restrict__ q, double* __restrict__ partial) {
+  __shared__ double red[kNT];
+  double acc = 0.0;
+  for (int g = blockIdx.x * kNT + threadIdx.x; g < nif; g += gridDim.x * kNT) {
+    double v = 0.0;
+    for (int k = sh_ptr[g]; k < sh_ptr[g + 1]; ++k) v += qloc[sh_flat[k]];
+    q[g] = v;
+    acc += v * p[g];
+  }
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
+__global__ void __launch_bounds__(kNT) k_dot_partial(int n, const double* __restrict__ a, const double* __restrict__ b,
+                                                     double* __restrict__ partial) {
+  __shared__ double red[kNT];
+  double acc = 0.0;
+  for (int i = blockIdx.x * kNT + threadIdx.x; i < n; i += gridDim.x * kNT) acc += a[i] * b[i];
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
+// single block: which = 0 -> pq, alpha = rz / pq ; 1 -> rr and convergence test ;
+// 2 -> rz_new, beta = rz_new / rz ; 3 -> rz (first) ; 4 -> bb = ||f||^2 and the
+// threshold rtol^2 bb ; 5 -> initial rr and the test before the first iteration
+__global__ void __launch_bounds__(kNT) k_scalar(int which, int nblk, const double* __restrict__ partial,
+                                                PcgScalars* sc) {
+  __shared__ double red[kNT];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += kNT) acc += partial[i];
+  acc = block_sum(acc, red);
+  if (threadIdx.x != 0) return;
+  if (which == 4) { sc->bb = acc; sc->thr2 = sc->rtol2 * acc; return; }
+  if (which == 3) { sc->rz = acc; return; }
+  if (which == 5) { sc->rr = acc; if (acc <= sc->thr2) sc->done = 1; return; }
+  if (sc->done) return;
+  if (which == 0) {
+    sc->pq = acc;
+    sc->alpha = sc->rz / acc;
+  } else if (which == 1) {
+    sc->rr = acc;
+    sc->iters += 1;
+    sc->alphas[min(sc->iters - 1, kMaxHist - 1)] = sc->alpha;
+    if (acc <= sc->thr2) sc->done = 1;
+    if (sc->iters >= sc->maxit) sc->done = (sc->done ? 1 : 2);
+  } else if (which == 2) {
+    sc->beta = acc / sc->rz;
+    sc->betas[min(sc->iters - 1, kMaxHist - 1)] = sc->beta;
+    sc->rz = acc;
+  }
+}
+
+__global__ void k_update_xr(int n, const PcgScalars* __restrict__ sc, const double* __restrict__ p,
+                            const double* __restrict__ q, double* __restrict__ x, double* __restrict__ r,
+                            double* __restrict__ partial) {
+  __shared__ double red[kNT];
+  const bool active = sc->done == 0;
+  const double al = sc->alpha;
+  double acc = 0.0;
+  for (int i = blockIdx.x * kNT + threadIdx.x; i < n; i += gridDim.x * kNT) {
+    double ri = r[i];
+    if (active) {
+      x[i] += al * p[i];
+      ri -= al * q[i];
+      r[i] = ri;
+    }
+    acc += ri * ri;
+  }
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
+__global__ void k_update_p(int n, const PcgScalars* __restrict__ sc, const double* __restrict__ z,
+                           double* __restrict__ p, int first) {
+  if (!first && sc->done) return;
+  const double be = first ? 0.0 : sc->beta;
+  for (int i = blockIdx.x * kNT + threadIdx.x; i < n; i += gridDim.x * kNT) p[i] = z[i] + be * p[i];
+}
+
+// r = f_Gamma - sum_s t_s (condensed right-hand side), x = 0
+__global__ void k_condense(int nif, const int32_t* __restrict__ sh_ptr, const int32_t* __restrict__ sh_flat,
+                           const int32_t* __restrict__ iface_gid, const double* __restrict__ f,
+                           const double* __restrict__ t, double* __restrict__ r, double* __restrict__ x) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= nif) return;
+  double v = f[iface_gid[g]];
+  for (int k = sh_ptr[g]; k < sh_ptr[g + 1]; ++k) v -= t[sh_flat[k]];
+  r[g] = v;
+  x[g] = 0.0;
+}
+
+// interior recovery: u_Gamma = x, u_I = L^{-T}(y - L_GI^T x_s) with y = L^{-1} f_I
+__global__ void __launch_bounds__(kNT) k_recover(LevelDev L, const double* __restrict__ x, double* __restrict__ u) {
+  extern __shared__ double sh[];
+  const int s = blockIdx.x;
+  const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
+  const int nI = L.nint[s];
+  const int ng = n - nI;
+  const int g0 = L.goff[s];
+  double* uB = sh;
+  double* yv = sh + ng;
+  const int tid = threadIdx.x;
+  for (int a = tid; a < ng; a += kNT) {
+    const int f = g0 + a;
+    const int gi = L.gam_iid[f];
+    const double v = x[gi];
+    uB[a] = v;
+    if (L.sh_flat[L.sh_ptr[gi]] == f) u[L.gam_gid[f]] = v;
+  }
+  if (nI == 0) return;
+  __syncthreads();
+  const double* A = L.K + L.koff[s];
+  for (int j = tid; j < nI; j += kNT) {
+    double acc = 0.0;
+    for (int a = 0; a < ng; ++a) acc += A[(nI + a) + (size_t)j * n] * uB[a];
+    yv[j] = L.y[L.ioff[s] + j] - acc;
+  }
+  __syncthreads();
+  wg_trsv_lower_trans(A, n, nI, yv);
+  for (int j = tid; j < nI; j += kNT) u[L.int_gid[L.ioff[s] + j]] = yv[j];
+}
+
+__global__ void k_copy(int n, const double* __restrict__ a, double* __restrict__ b) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i];
+}
+
+// ---------------------------------------------------------------------------
+static inline int blocks_for(int n) { return n <= 0 ? 1 : (n + kNT - 1) / kNT; }
+
+void launch_apply_pre(hipStream_t st, const LevelDev& L, int nImax, int ngmax, const double* r) {
+  const size_t lds = sizeof(double) * ((size_t)nImax + kNT + ngmax);
+  hipLaunchKernelGGL(k_apply_pre, dim3(L.nsub), dim3(kNT), lds, st, L, r);
+}
+void launch_apply_restrict(hipStream_t st, const LevelDev& L, int ngmax, const double* r,
+                           const int32_t* gam_map, int use_t) {
+  const size_t lds = sizeof(double) * ((size_t)ngmax + kNT + ngmax);
+  hipLaunchKernelGGL(k_apply_restrict, dim3(L.nsub), dim3(kNT), lds, st, L, r, gam_map, use_t);
+}
+void launch_coarse_gather(hipStream_t st, int nc, const int32_t* csh_ptr, const int32_t* csh_flat,
+                          const double* b, double* rc) {
+  if (nc == 0) return;
+  hipLaunchKernelGGL(k_coarse_gather, dim3(blocks_for(nc)), dim3(kNT), 0, st, nc, csh_ptr, csh_flat, b, rc);
+}
+void launch_coarsest_solve(hipStream_t st, int nc, const double* Lc, const double* rc, double* uc) {
+  if (nc == 0) return;
+  hipLaunchKernelGGL(k_coarsest_solve, dim3(1), dim3(kNT), sizeof(double) * (size_t)nc, st, nc, Lc, rc, uc);
+}
+void launch_apply_prolong(hipStream_t st, const LevelDev& L, int ncsmax, const double* uc) {
+  hipLaunchKernelGGL(k_apply_prolong, dim3(L.nsub), dim3(kNT), sizeof(double) * (size_t)(ncsmax + 1), st, L, uc);
+}
+void launch_apply_post(hipStream_t st, const LevelDev& L, int nImax, int ngmax, double* u,
+                       const int32_t* gam_map, int interior) {
+  const size_t lds = sizeof(double) * ((size_t)ngmax + nImax + 1);
+  hipLaunchKernelGGL(k_apply_post, dim3(L.nsub), dim3(kNT), lds, st, L, u, gam_map, interior);
+}
+void launch_schur_local(hipStream_t st, const LevelDev& L, int ngmax, const double* p, double* qloc) {
+  const size_t lds = sizeof(double) * ((size_t)ngmax + kNT + ngmax);
+  hipLaunchKernelGGL(k_schur_local, dim3(L.nsub), dim3(kNT), lds, st, L, p, qloc);
+}
+void launch_gather_dot(hipStream_t st, int nblk, int nif, const int32_t* sh_ptr, const int32_t* sh_flat,
+                       const double* qloc, const double* p, double* q, double* partial) {
+  hipLaunchKernelGGL(k_gather_dot, dim3(nblk), dim3(kNT), 0, st, nif, sh_ptr, sh_flat, qloc, p, q, partial);
+}
+void launch_dot_partial(hipStream_t st, int nblk, int n, const double* a, const double* b, double* partial) {
+  hipLaunchKernelGGL(k_dot_partial, dim3(nblk), dim3(kNT), 0, st, n, a, b, partial);
+}
+void launch_scalar(hipStream_t st, int which, int nblk, const double* partial, PcgScalars* sc) {
+  hipLaunchKernelGGL(k_scalar, dim3(1), dim3(kNT), 0, st, which, nblk, partial, sc);
+}
+void launch_update_xr(hipStream_t st, int nblk, int n, const PcgScalars* sc, const double* p, const double* q,
+                      double* x, double* r, double* partial) {
+  hipLaunchKernelGGL(k_update_xr, dim3(nblk), dim3(kNT), 0, st, n, sc, p, q, x, r, partial);
+}
+void launch_update_p(hipStream_t st, int nblk, int n, const PcgScalars* sc, const double* z, double* p, int first) {
+  hipLaunchKernelGGL(k_update_p, dim3(nblk), dim3(kNT), 0, st, n, sc, z, p, first);
+}
+void launch_condense(hipStream_t st, int nif, const int32_t* sh_ptr, const int32_t* sh_flat,
+                     const int32_t* iface_gid, const double* f, const double* t, double* r, double* x) {
+  if (nif == 0) return;
+  hipLaunchKernelGGL(k_condense, dim3(blocks_for(nif)), dim3(kNT), 0, st, nif, sh_ptr, sh_flat, iface_gid, f, t,
+                     r, x);
+}
+void launch_recover(hipStream_t st, const LevelDev& L, int nImax, int ngmax, const double* x, double* u) {
+  const size_t lds = sizeof(double) * ((size_t)ngmax + nImax + 1);
+  hipLaunchKernelGGL(k_recover, dim3(L.nsub), dim3(kNT), lds, st, L, x, u);
+}
+void launch_copy(hipStream_t st, int n, const double* a, double* b) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_copy, dim3(blocks_for(n)), dim3(kNT), 0, st, n, a, b);
+}
+
+}  // namespace bddc

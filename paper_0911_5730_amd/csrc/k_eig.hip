@@ -1,0 +1,376 @@
+// Adaptive setup: per-edge generalized eigenproblems (Section 3, Theorem
+// "local-est"; Section 4, Theorem "adaptive"; Section 5, adaptive setup).
+//
+// For the adjacent pair (s, t) let F be their shared dofs: the shared corners
+// (n_sc) followed by the edge dofs (n_e).  The stationary values of
+//   J(w) = |(I - E) w|_S^2 / |w|_S^2     on  (I - P) W-tilde^{st}
+// are computed here in a reduced but equivalent form:
+//   * the jump (I-E)w vanishes off the edge, so the numerator depends only on
+//     the jump j = w_s - w_t on the edge dofs:
+//         N_e = D_t S_s,ee D_t + D_s S_t,ee D_s   (S_. the interface Schur
+//     complements, D_. the pair weights d_s/(d_s+d_t), d the local diagonals);
+//   * minimising the denominator over the non-shared dofs replaces S_s by its
+//     Schur complement Shat_s onto F; with v = (shared corner values, s-edge,
+//     t-edge) the denominator is v^T M v, M = P_s^T Shat_s P_s + P_t^T Shat_t P_t;
+//   * if both substructures float, M has the null vector q = z|F (the
+//     constant, or its coarse values at higher levels); Y = M + a q q^T with
+//     any a > 0 (the role of Pi-bar in the theorem);
+//   * the nonzero eigenvalues of (B^T N_e B, Y), B v = jump, are the
+//     eigenvalues of G N_e with G = B Y^{-1} B^T, i.e. of H = R^T G R for
+//     N_e = R R^T, and the constraint row c^s = w^T X restricted to the edge
+//     is N_e j = R z for an eigenvector z of H.
+// Eigenvectors with lambda > tau are selected, the constraint columns R z are
+// orthonormalised by modified Gram-Schmidt, and lambda is returned in
+// decreasing order.
+#include "dense.hpp"
+#include "kernels.hpp"
+
+namespace bddc {
+
+// Schur complement of the interface Schur complement S_s onto the shared
+// dofs F of one (substructure, edge) incidence.  LDS holds the ng x ng matrix
+// reordered as [rest | F]; eliminating `rest` leaves Shat in the trailing block.
+__global__ void __launch_bounds__(kNT) k_pair_schur(
+    const int32_t* __restrict__ inc_sub, const int32_t* __restrict__ inc_fptr,
+    const int32_t* __restrict__ inc_fpos, const int64_t* __restrict__ koff,
+    const int32_t* __restrict__ loc_ptr, const int32_t* __restrict__ nint, const double* __restrict__ K,
+    const int64_t* __restrict__ inc_off, double* __restrict__ Shat, double* __restrict__ Sff, int* status) {
+  extern __shared__ double M[];
+  const int inc = blockIdx.x;
+  const int s = inc_sub[inc];
+  const int n = loc_ptr[s + 1] - loc_ptr[s];
+  const int nI = nint[s];
+  const int ng = n - nI;
+  const double* S = K + koff[s] + nI + (size_t)nI * n;
+  const int nF = inc_fptr[inc + 1] - inc_fptr[inc];
+  const int32_t* fpos = inc_fpos + inc_fptr[inc];
+  const int nR = ng - nF;
+  int* perm = reinterpret_cast<int*>(M + (size_t)ng * ng);
+  int* inF = perm + ng;
+  const int tid = threadIdx.x;
+  for (int a = tid; a < ng; a += kNT) inF[a] = -1;
+  __syncthreads();
+  for (int a = tid; a < nF; a += kNT) inF[fpos[a]] = a;
+  __syncthreads();
+  if (tid == 0) {
+    int r = 0;
+    for (int a = 0; a < ng; ++a)
+      if (inF[a] < 0) perm[r++] = a;
+    for (int a = 0; a < nF; ++a) perm[nR + a] = fpos[a];
+  }
+  __syncthreads();
+  for (int idx = tid; idx < ng * ng; idx += kNT) {
+    const int i = idx % ng, j = idx / ng;
+    M[idx] = S[perm[i] + (size_t)perm[j] * n];
+  }
+  __syncthreads();
+  double* sff = Sff + inc_off[inc];
+  for (int idx = tid; idx < nF * nF; idx += kNT) {
+    const int i = idx % nF, j = idx / nF;
+    sff[idx] = M[(nR + i) + (size_t)(nR + j) * ng];
+  }
+  wg_partial_potrf(M, ng, ng, nR, status);
+  double* sh = Shat + inc_off[inc];
+  for (int idx = tid; idx < nF * nF; idx += kNT) {
+    const int i = idx % nF, j = idx / nF;
+    const int a = max(i, j), b = min(i, j);
+    sh[idx] = M[(nR + a) + (size_t)(nR + b) * ng];
+  }
+}
+
+// One edge per workgroup.  Global scratch (per edge): Y (nv x nv), X (nv x ne),
+// R (ne x ne).  LDS: H and V (ne x ne each) for the Jacobi iteration, plus
+// small vectors.
+__global__ void __launch_bounds__(kNT) k_pair_eig(
+    int nedge, const int32_t* __restrict__ edge_s, const int32_t* __restrict__ edge_t,
+    const int32_t* __restrict__ edge_nsc, const int32_t* __restrict__ edge_ne,
+    const int32_t* __restrict__ edge_fdof, const int32_t* __restrict__ edge_fptr,
+    const int32_t* __restrict__ inc_fptr, const int32_t* __restrict__ inc_fpos,
+    const int32_t* __restrict__ goff, const double* __restrict__ diagK,
+    const uint8_t* __restrict__ floating, const double* __restrict__ z,
+    const double* __restrict__ Shat, const double* __restrict__ Sff, const int64_t* __restrict__ inc_off,
+    double* __restrict__ work, const int64_t* __restrict__ woff, double tau,
+    double* __restrict__ lam_out, const int64_t* __restrict__ lamoff, double* __restrict__ Q,
+    const int64_t* __restrict__ qoff, int32_t* __restrict__ nsel_out, int32_t* __restrict__ nkept_out,
+    int* status) {
+  extern __shared__ double lds[];
+  __shared__ double red[kNT];
+  const int e = blockIdx.x;
+  const int s = edge_s[e], t = edge_t[e];
+  const int nsc = edge_nsc[e], ne = edge_ne[e];
+  const int nF = nsc + ne;
+  const int nv = nsc + 2 * ne;
+  const int tid = threadIdx.x;
+  const int inc_s = 2 * e, inc_t = 2 * e + 1;
+  const int32_t* fps = inc_fpos + inc_fptr[inc_s];
+  const int32_t* fpt = inc_fpos + inc_fptr[inc_t];
+  const double* Shs = Shat + inc_off[inc_s];
+  const double* Sht = Shat + inc_off[inc_t];
+  const double* Sfs = Sff + inc_off[inc_s];
+  const double* Sft = Sff + inc_off[inc_t];
+
+  double* Y = work + woff[e];
+  double* X = Y + (size_t)nv * nv;
+  double* R = X + (size_t)nv * ne;
+  double* H = lds;                       // ne x ne
+  double* V = H + (size_t)ne * ne;       // ne x ne
+  double* ds = V + (size_t)ne * ne;      // pair weight of s on each edge dof
+  double* cs = ds + ne;                  // rotation cosines (ne/2+1)
+  double* sn = cs + (ne / 2 + 1);        // rotation sines (ne/2+1)
+  double* lam = sn + (ne / 2 + 1);       // ne
+  int* perm = reinterpret_cast<int*>(lam + ne);
+
+  // pair weights on the edge dofs: delta_s^{st} = d_s / (d_s + d_t)
+  for (int p = tid; p < ne; p += kNT) {
+    const double a = diagK[goff[s] + fps[nsc + p]];
+    const double b = diagK[goff[t] + fpt[nsc + p]];
+    ds[p] = a / (a + b);
+  }
+  // M in the coordinates v = [shared corners | s-edge | t-edge]
+  for (int idx = tid; idx < nv * nv; idx += kNT) Y[idx] = 0.0;
+  __syncthreads();
+  for (int idx = tid; idx < nF * nF; idx += kNT) {   // s side: F index i is v index i
+    const int i = idx % nF, j = idx / nF;
+    Y[i + (size_t)j * nv] += Shs[idx];
+  }
+  __syncthreads();
+  for (int idx = tid; idx < nF * nF; idx += kNT) {
+    const int i = idx % nF, j = idx / nF;
+    const int vi = i < nsc ? i : i + ne;      // t-edge dof p sits at nsc + ne + p
+    const int vj = j < nsc ? j : j + ne;
+    Y[vi + (size_t)vj * nv] += Sht[idx];
+  }
+  __syncthreads();
+  if (floating[s] && floating[t]) {
+    // q = z on F in v coordinates, shift a = max diag(M)
+    double nq = 0.0, amax = 0.0;
+    for (int i = tid; i < nv; i += kNT) {
+      const int f = i < nsc ? i : (i < nsc + ne ? i : i - ne);
+      const double qi = z[edge_fdof[edge_fptr[e] + f]];
+      nq += qi * qi;
+      amax = fmax(amax, Y[i + (size_t)i * nv]);
+    }
+    nq = wg_sum(nq, red);
+    // max reduction
+    red[tid] = amax;
+    __syncthreads();
+    for (int w = kNT / 2; w > 0; w >>= 1) {
+      if (tid < w) red[tid] = fmax(red[tid], red[tid + w]);
+      __syncthreads();
+    }
+    amax = red[0];
+    __syncthreads();
+    const double scale = amax / nq;
+    for (int idx = tid; idx < nv * nv; idx += kNT) {
+      const int i = idx % nv, j = idx / nv;
+      const int fi = i < nsc ? i : (i < nsc + ne ? i : i - ne);
+      const int fj = j < nsc ? j : (j < nsc + ne ? j : j - ne);
+      Y[idx] += scale * z[edge_fdof[edge_fptr[e] + fi]] * z[edge_fdof[edge_fptr[e] + fj]];
+    }
+    __syncthreads();
+  }
+  wg_potrf(Y, nv, nv, status);
+  // X = L^{-1} B^T,  B^T columns: +1 at the s-edge dof, -1 at the t-edge dof
+  for (int idx = tid; idx < nv * ne; idx += kNT) {
+    const int v = idx % nv, p = idx / nv;
+    X[idx] = (v == nsc + p) ? 1.0 : ((v == nsc + ne + p) ? -1.0 : 0.0);
+  }
+  __syncthreads();
+  wg_trsm_lower(Y, nv, nv, X, nv, ne);
+  // N_e = D_t S_s,ee D_t + D_s S_t,ee D_s  -> R (Cholesky)
+  for (int idx = tid; idx < ne * ne; idx += kNT) {
+    const int i = idx % ne, j = idx / ne;
+    const double ss = Sfs[(nsc + i) + (size_t)(nsc + j) * nF];
+    const double tt = Sft[(nsc + i) + (size_t)(nsc + j) * nF];
+    R[idx] = (1.0 - ds[i]) * ss * (1.0 - ds[j]) + ds[i] * tt * ds[j];
+  }
+  __syncthreads();
+  wg_potrf(R, ne, ne, status);
+  for (int idx = tid; idx < ne * ne; idx += kNT) {
+    const int i = idx % ne, j = idx / ne;
+    if (i < j) R[idx] = 0.0;
+  }
+  // V = G R with G = X^T X, then H = R^T V
+  __syncthreads();
+  for (int idx = tid; idx < ne * ne; idx += kNT) {
+    const int i = idx % ne, j = idx / ne;
+    double acc = 0.0;
+    for (int k = j; k < ne; ++k) {
+      double g = 0.0;
+      for (int v = 0; v < nv; ++v) g += X[v + (size_t)i * nv] * X[v + (size_t)k * nv];
+      acc += g * R[k + (size_t)j * ne];
+    }
+    V[idx] = acc;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < ne * ne; idx += kNT) {
+    const int i = idx % ne, j = idx / ne;
+    double acc = 0.0;
+    for (int k = i; k < ne; ++k) acc += R[k + (size_t)i * ne] * V[k + (size_t)j * ne];
+    H[idx] = acc;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < ne * ne; idx += kNT) {
+    const int i = idx % ne, j = idx / ne;
+    if (i > j) {
+      const double a = 0.5 * (H[idx] + H[j + (size_t)i * ne]);
+      H[idx] = a;
+      H[j + (size_t)i * ne] = a;
+    }
+    V[idx] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+
+  // cyclic Jacobi with round-robin ordering of disjoint rotation pairs
+  const int m = ne + (ne & 1);
+  const int npair = m / 2;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0, dia = 0.0;
+    for (int idx = tid; idx < ne * ne; idx += kNT) {
+      const int i = idx % ne, j = idx / ne;
+      const double h = H[idx];
+      if (i == j) dia += h * h; else off += h * h;
+    }
+    off = wg_sum(off, red);
+    dia = wg_sum(dia, red);
+    if (off <= 1e-30 * dia || ne < 2) break;
+    for (int r = 0; r < m - 1; ++r) {
+      for (int k = tid; k < npair; k += kNT) {
+        int a = (k == 0) ? 0 : ((k - 1 + r) % (m - 1)) + 1;
+        int b = ((m - 1 - k - 1 + r) % (m - 1)) + 1;
+        int p = min(a, b), q = max(a, b);
+        double c = 1.0, sv = 0.0;
+        if (q < ne) {
+          const double hpq = H[p + (size_t)q * ne];
+          if (fabs(hpq) > 1e-300) {
+            const double theta = (H[q + (size_t)q * ne] - H[p + (size_t)p * ne]) / (2.0 * hpq);
+            const double tt = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+            c = 1.0 / sqrt(tt * tt + 1.0);
+            sv = tt * c;
+          }
+        }
+        cs[k] = c;
+        sn[k] = sv;
+      }
+      __syncthreads();
+      // rows: H <- P^T H
+      for (int idx = tid; idx < npair * ne; idx += kNT) {
+        const int k = idx % npair, col = idx / npair;
+        int a = (k == 0) ? 0 : ((k - 1 + r) % (m - 1)) + 1;
+        int b = ((m - 1 - k - 1 + r) % (m - 1)) + 1;
+        int p = min(a, b), q = max(a, b);
+        if (q >= ne) continue;
+        const double c = cs[k], sv = sn[k];
+        const double hp = H[p + (size_t)col * ne], hq = H[q + (size_t)col * ne];
+        H[p + (size_t)col * ne] = c * hp - sv * hq;
+        H[q + (size_t)col * ne] = sv * hp + c * hq;
+      }
+      __syncthreads();
+      // columns: H <- H P, V <- V P
+      for (int idx = tid; idx < npair * ne; idx += kNT) {
+        const int k = idx % npair, row = idx / npair;
+        int a = (k == 0) ? 0 : ((k - 1 + r) % (m - 1)) + 1;
+        int b = ((m - 1 - k - 1 + r) % (m - 1)) + 1;
+        int p = min(a, b), q = max(a, b);
+        if (q >= ne) continue;
+        const double c = cs[k], sv = sn[k];
+        const double hp = H[row + (size_t)p * ne], hq = H[row + (size_t)q * ne];
+        H[row + (size_t)p * ne] = c * hp - sv * hq;
+        H[row + (size_t)q * ne] = sv * hp + c * hq;
+        const double vp = V[row + (size_t)p * ne], vq = V[row + (size_t)q * ne];
+        V[row + (size_t)p * ne] = c * vp - sv * vq;
+        V[row + (size_t)q * ne] = sv * vp + c * vq;
+      }
+      __syncthreads();
+    }
+  }
+  // eigenvalues in decreasing order
+  for (int i = tid; i < ne; i += kNT) lam[i] = H[i + (size_t)i * ne];
+  __syncthreads();
+  if (tid == 0) {
+    for (int i = 0; i < ne; ++i) perm[i] = i;
+    for (int i = 1; i < ne; ++i) {
+      const int key = perm[i];
+      int j = i - 1;
+      while (j >= 0 && lam[perm[j]] < lam[key]) { perm[j + 1] = perm[j]; --j; }
+      perm[j + 1] = key;
+    }
+  }
+  __syncthreads();
+  double* lo = lam_out + lamoff[e];
+  for (int i = tid; i < ne; i += kNT) lo[i] = lam[perm[i]];
+  int nsel = 0;
+  for (int i = 0; i < ne; ++i) nsel += (lam[perm[i]] > tau) ? 1 : 0;
+  // constraint columns c_k = R z_k, k < nsel, then modified Gram-Schmidt
+  double* Qe = Q + qoff[e];
+  for (int idx = tid; idx < ne * nsel; idx += kNT) {
+    const int i = idx % ne, k = idx / ne;
+    const double* zk = V + (size_t)perm[k] * ne;
+    double acc = 0.0;
+    for (int j = 0; j <= i; ++j) acc += R[i + (size_t)j * ne] * zk[j];
+    Qe[idx] = acc;
+  }
+  __syncthreads();
+  int kept = 0;
+  double maxnorm = 0.0;
+  for (int k = 0; k < nsel; ++k) {
+    double* ck = Qe + (size_t)k * ne;
+    for (int j = 0; j < kept; ++j) {
+      const double* qj = Qe + (size_t)j * ne;
+      double d = 0.0;
+      for (int i = tid; i < ne; i += kNT) d += qj[i] * ck[i];
+      d = wg_sum(d, red);
+      for (int i = tid; i < ne; i += kNT) ck[i] -= d * qj[i];
+      __syncthreads();
+    }
+    double nn = 0.0;
+    for (int i = tid; i < ne; i += kNT) nn += ck[i] * ck[i];
+    nn = sqrt(wg_sum(nn, red));
+    maxnorm = fmax(maxnorm, nn);
+    if (nn > 1e-10 * maxnorm && nn > 0.0) {
+      double* dst = Qe + (size_t)kept * ne;
+      for (int i = tid; i < ne; i += kNT) dst[i] = ck[i] / nn;
+      ++kept;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    nsel_out[e] = nsel;
+    nkept_out[e] = kept;
+  }
+  (void)nedge;
+}
+
+void launch_pair_schur(hipStream_t st, int ninc, int ngmax, const int32_t* inc_sub, const int32_t* inc_fptr,
+                       const int32_t* inc_fpos, const int64_t* koff, const int32_t* loc_ptr,
+                       const int32_t* nint, const double* K, const int64_t* inc_off, double* Shat,
+                       double* Sff, int* status) {
+  if (ninc == 0) return;
+  const size_t lds = pair_schur_lds(ngmax);
+  hipLaunchKernelGGL(k_pair_schur, dim3(ninc), dim3(kNT), lds, st, inc_sub, inc_fptr, inc_fpos, koff,
+                     loc_ptr, nint, K, inc_off, Shat, Sff, status);
+}
+
+size_t pair_schur_lds(int ngmax) {
+  return sizeof(double) * (size_t)ngmax * ngmax + sizeof(int) * 2 * (size_t)ngmax + 64;
+}
+
+size_t pair_eig_lds(int nemax) {
+  return sizeof(double) * (2 * (size_t)nemax * nemax + 2 * (size_t)nemax + 2 * (nemax / 2 + 1)) +
+         sizeof(int) * (nemax + 2) + 64;
+}
+
+void launch_pair_eig(hipStream_t st, int nedge, int nemax, const int32_t* edge_s, const int32_t* edge_t,
+                     const int32_t* edge_nsc, const int32_t* edge_ne, const int32_t* edge_fdof,
+                     const int32_t* edge_fptr, const int32_t* inc_fptr, const int32_t* inc_fpos,
+                     const int32_t* goff, const double* diagK, const uint8_t* floating, const double* z,
+                     const double* Shat, const double* Sff, const int64_t* inc_off, double* work,
+                     const int64_t* woff, double tau, double* lam, const int64_t* lamoff, double* Q,
+                     const int64_t* qoff, int32_t* nsel, int32_t* nkept, int* status) {
+  if (nedge == 0) return;
+  hipLaunchKernelGGL(k_pair_eig, dim3(nedge), dim3(kNT), pair_eig_lds(nemax), st, nedge, edge_s, edge_t,
+                     edge_nsc, edge_ne, edge_fdof, edge_fptr, inc_fptr, inc_fpos, goff, diagK, floating,
+                     z, Shat, Sff, inc_off, work, woff, tau, lam, lamoff, Q, qoff, nsel, nkept, status);
+}
+
+}  // namespace bddc

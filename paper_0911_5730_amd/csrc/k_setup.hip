@@ -1,0 +1,416 @@
+// Setup kernels: local assembly, stiffness-scaling weights, interior
+// elimination (partial Cholesky -> interior factor and interface Schur
+// complement), constraint matrices, constrained local factors with the
+// energy-minimal coarse basis, and the coarsest-level factor.
+//
+// One workgroup per substructure; every matrix is dense FP64, column-major,
+// with the substructure's local dofs ordered [interior | interface
+// non-corner | corner].
+#include "dense.hpp"
+#include "kernels.hpp"
+
+namespace bddc {
+
+// ---------------------------------------------------------------------------
+// Level-1 assembly (Section 2: a(u,v) = sum_e k_e int grad u . grad v):
+// K_s = sum over the elements of s of k_e * Khat.  Thread a owns row a, so the
+// accumulation order is fixed and no atomics are needed.  The interface part
+// of the diagonal is kept for the stiffness-scaling weights.
+__global__ void __launch_bounds__(kNT) k_assemble_l1(
+    const int64_t* __restrict__ koff, const int32_t* __restrict__ loc_ptr,
+    const int32_t* __restrict__ nint, const int32_t* __restrict__ node_el,
+    const int32_t* __restrict__ sub_el_ptr, const int32_t* __restrict__ el_gid,
+    const int32_t* __restrict__ el_loc, const double* __restrict__ coeff, Khat16 khat,
+    double* __restrict__ K, double* __restrict__ diagK, const int32_t* __restrict__ goff) {
+  const int s = blockIdx.x;
+  const int base = loc_ptr[s];
+  const int n = loc_ptr[s + 1] - base;
+  const int e0 = sub_el_ptr[s];
+  double* A = K + koff[s];
+  for (int a = threadIdx.x; a < n; a += kNT) {
+    for (int b = 0; b < n; ++b) A[a + (size_t)b * n] = 0.0;
+    for (int k = 0; k < 4; ++k) {
+      const int code = node_el[(size_t)(base + a) * 4 + k];
+      if (code < 0) continue;
+      const int le = code >> 2, pos = code & 3;
+      const double kk = coeff[el_gid[e0 + le]];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int b = el_loc[(size_t)(e0 + le) * 4 + q];
+        if (b >= 0) A[a + (size_t)b * n] += kk * khat.v[pos * 4 + q];
+      }
+    }
+    if (a >= nint[s]) diagK[goff[s] + a - nint[s]] = A[a + (size_t)a * n];
+  }
+}
+
+// Level >= 2 assembly (Section 2.1: level-l elements are level-(l-1)
+// substructures with the coarse element matrices A_c as element matrices).
+// Children are added one after another, so the sum order is fixed.
+__global__ void __launch_bounds__(kNT) k_assemble_coarse(
+    const int64_t* __restrict__ koff, const int32_t* __restrict__ loc_ptr,
+    const int32_t* __restrict__ nint, const int32_t* __restrict__ child_ptr,
+    const int32_t* __restrict__ child_id, const int32_t* __restrict__ child_map_off,
+    const int32_t* __restrict__ child_map, const double* __restrict__ Ac,
+    const int64_t* __restrict__ acoff, const int32_t* __restrict__ nc_child, double* __restrict__ K,
+    double* __restrict__ diagK, const int32_t* __restrict__ goff) {
+  const int s = blockIdx.x;
+  const int n = loc_ptr[s + 1] - loc_ptr[s];
+  double* A = K + koff[s];
+  for (int idx = threadIdx.x; idx < n * n; idx += kNT) A[idx] = 0.0;
+  __syncthreads();
+  for (int slot = child_ptr[s]; slot < child_ptr[s + 1]; ++slot) {
+    const int c = child_id[slot];
+    const int m = nc_child[c];
+    const double* Ae = Ac + acoff[c];
+    const int32_t* map = child_map + child_map_off[slot];
+    for (int idx = threadIdx.x; idx < m * m; idx += kNT) {
+      const int i = idx % m, j = idx / m;
+      A[map[i] + (size_t)map[j] * n] += Ae[idx];
+    }
+    __syncthreads();
+  }
+  for (int a = nint[s] + threadIdx.x; a < n; a += kNT) diagK[goff[s] + a - nint[s]] = A[a + (size_t)a * n];
+}
+
+// Stiffness scaling: delta_s(x) = K_s(x,x) / sum_{j in N_x} K_j(x,x) on the
+// interface (summed over the sharers of x in a fixed order).
+__global__ void k_weights(int nflat, const int32_t* __restrict__ flat_iid,
+                          const int32_t* __restrict__ sh_ptr, const int32_t* __restrict__ sh_flat,
+                          const double* __restrict__ diagK, double* __restrict__ delta) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nflat) return;
+  const int g = flat_iid[f];
+  double sum = 0.0;
+  for (int k = sh_ptr[g]; k < sh_ptr[g + 1]; ++k) sum += diagK[sh_flat[k]];
+  delta[f] = diagK[f] / sum;
+}
+
+// ---------------------------------------------------------------------------
+// Interior elimination, blocked right-looking Cholesky on the first nI columns
+// of K_s.  A panel of kPanel columns is factored in LDS, written back, and used
+// for the rank-kPanel update of the trailing lower triangle in 4x4 register
+// tiles.  On exit: L_II (lower), L_GI = K_GI L_II^{-T} below it, and the
+// interface Schur complement S = K_GG - L_GI L_GI^T, mirrored to full storage.
+constexpr int kPanel = 16;
+
+__global__ void __launch_bounds__(kNT) k_partial_chol(const int64_t* __restrict__ koff,
+                                                      const int32_t* __restrict__ loc_ptr,
+                                                      const int32_t* __restrict__ nint,
+                                                      double* __restrict__ K, int* status) {
+  extern __shared__ double P[];
+  const int s = blockIdx.x;
+  const int n = loc_ptr[s + 1] - loc_ptr[s];
+  const int nI = nint[s];
+  double* A = K + koff[s];
+  const int tid = threadIdx.x;
+  for (int k0 = 0; k0 < nI; k0 += kPanel) {
+    const int kb = min(kPanel, nI - k0);
+    const int m = n - k0;
+    for (int idx = tid; idx < m * kb; idx += kNT) {
+      const int i = idx % m, p = idx / m;
+      P[i + p * m] = A[(k0 + i) + (size_t)(k0 + p) * n];
+    }
+    __syncthreads();
+    for (int j = 0; j < kb; ++j) {
+      const double d = P[j + j * m];
+      const bool ok = d > 0.0 && d < 1e308;
+      if (!ok && tid == 0) flag_bad(status);
+      const double sq = ok ? sqrt(d) : 1.0;
+      const double inv = 1.0 / sq;
+      for (int i = j + 1 + tid; i < m; i += kNT) P[i + j * m] *= inv;
+      __syncthreads();
+      if (tid == 0) P[j + j * m] = sq;
+      const int w = kb - j - 1;
+      for (int idx = tid; idx < w * m; idx += kNT) {
+        const int i = idx % m, c = j + 1 + idx / m;
+        if (i >= c) P[i + c * m] -= P[i + j * m] * P[c + j * m];
+      }
+      __syncthreads();
+    }
+    for (int idx = tid; idx < m * kb; idx += kNT) {
+      const int i = idx % m, p = idx / m;
+      if (i >= p) A[(k0 + i) + (size_t)(k0 + p) * n] = P[i + p * m];
+    }
+    // trailing update of rows/cols [k0+kb, n), lower triangle, 4x4 tiles
+    const int mt = m - kb;
+    const int nt = (mt + 3) / 4;
+    const int ntiles = nt * (nt + 1) / 2;
+    for (int t = tid; t < ntiles; t += kNT) {
+      // tile (ti, tc) with ti >= tc from the linear index t
+      int tc = 0, rem = t;
+      while (rem >= nt - tc) { rem -= nt - tc; ++tc; }
+      const int ti = tc + rem;
+      double acc[4][4] = {};
+      for (int p = 0; p < kb; ++p) {
+        double a[4], b[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = kb + ti * 4 + r;
+          const int c = kb + tc * 4 + r;
+          a[r] = (i < m) ? P[i + p * m] : 0.0;
+          b[r] = (c < m) ? P[c + p * m] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[r][q] += a[r] * b[q];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = kb + tc * 4 + q;
+        if (c >= m) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = kb + ti * 4 + r;
+          if (i < m && i >= c) A[(k0 + i) + (size_t)(k0 + c) * n] -= acc[r][q];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // mirror the Schur complement block
+  const int ng = n - nI;
+  for (int idx = tid; idx < ng * ng; idx += kNT) {
+    const int i = idx % ng, c = idx / ng;
+    if (i < c) A[(nI + i) + (size_t)(nI + c) * n] = A[(nI + c) + (size_t)(nI + i) * n];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Constraint rows on the non-corner interface dofs of each substructure
+// (C_r, n_cr x n_r): the coarse dofs of its edges, in the order of the local
+// coarse dofs (after the corners).  Corner dofs are eliminated directly.
+__global__ void k_build_cr(const int32_t* __restrict__ sub_inc_ptr, const int32_t* __restrict__ sub_inc,
+                           const int32_t* __restrict__ inc_edge, const int32_t* __restrict__ inc_fptr,
+                           const int32_t* __restrict__ inc_fpos, const int32_t* __restrict__ edge_nsc,
+                           const int32_t* __restrict__ edge_ne, const int32_t* __restrict__ edge_m,
+                           const int64_t* __restrict__ qoff, const double* __restrict__ Q,
+                           const int32_t* __restrict__ nr, const int32_t* __restrict__ ncr,
+                           const int64_t* __restrict__ croff, double* __restrict__ Cr) {
+  const int s = blockIdx.x;
+  const int n_r = nr[s], n_cr = ncr[s];
+  double* C = Cr + croff[s];
+  for (int idx = threadIdx.x; idx < n_r * n_cr; idx += kNT) C[idx] = 0.0;
+  __syncthreads();
+  int row = 0;
+  for (int k = sub_inc_ptr[s]; k < sub_inc_ptr[s + 1]; ++k) {
+    const int inc = sub_inc[k];
+    const int e = inc_edge[inc];
+    const int ne = edge_ne[e], m = edge_m[e], nsc = edge_nsc[e];
+    const int32_t* rpos = inc_fpos + inc_fptr[inc] + nsc;
+    const double* Qe = Q + qoff[e];
+    for (int idx = threadIdx.x; idx < ne * m; idx += kNT) {
+      const int p = idx % ne, j = idx / ne;
+      C[(row + j) + (size_t)rpos[p] * n_cr] = Qe[p + (size_t)j * ne];
+    }
+    row += m;
+  }
+}
+
+// Values of the level's coarse dofs for the level's constant vector z: the
+// next level's null-space representative (corners copy z, edge functionals
+// apply their weights).
+__global__ void k_coarse_z(int nc, const int32_t* __restrict__ cd_dof, const int32_t* __restrict__ cd_col,
+                           const int32_t* __restrict__ edge_ptr, const int32_t* __restrict__ edge_dof,
+                           const int64_t* __restrict__ qoff, const double* __restrict__ Q,
+                           const double* __restrict__ z, double* __restrict__ znext) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nc) return;
+  if (cd_col[k] < 0) {
+    znext[k] = z[cd_dof[k]];
+    return;
+  }
+  const int e = cd_dof[k], j = cd_col[k];
+  const int ne = edge_ptr[e + 1] - edge_ptr[e];
+  const double* q = Q + qoff[e] + (size_t)j * ne;
+  double acc = 0.0;
+  for (int p = 0; p < ne; ++p) acc += q[p] * z[edge_dof[edge_ptr[e] + p]];
+  znext[k] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// Constrained local problem on the interface of s (eqs. ML-wDi, ML-coarse):
+//   min 1/2 w^T S w - g^T w  subject to  w_c = 0 (corners), C_r w_r = 0.
+// With X = S_rr^{-1} C_r^T and F = C_r X:
+//   T_rr = S_rr^{-1} - X F^{-1} X^T       (substructure correction operator)
+//   Psi  = [[-T_rr S_rc, X F^{-1}], [I, 0]]  (energy-minimal coarse basis, C Psi = I)
+//   A_c  = Psi^T S Psi                    (coarse element matrix)
+__global__ void __launch_bounds__(kNT) k_constrained_factor(
+    const int64_t* __restrict__ koff, const int32_t* __restrict__ loc_ptr,
+    const int32_t* __restrict__ nint, const int32_t* __restrict__ nr, const int32_t* __restrict__ ncr,
+    const int64_t* __restrict__ croff, const double* __restrict__ Cr, const double* __restrict__ K,
+    double* __restrict__ T, const int64_t* __restrict__ toff, double* __restrict__ Psi,
+    const int64_t* __restrict__ psioff, double* __restrict__ Ac, const int64_t* __restrict__ acoff,
+    double* __restrict__ work, const int64_t* __restrict__ woff, int* status) {
+  const int s = blockIdx.x;
+  const int n = loc_ptr[s + 1] - loc_ptr[s];
+  const int nI = nint[s];
+  const int ng = n - nI;
+  const int n_r = nr[s];
+  const int n_c = ng - n_r;
+  const int n_cr = ncr[s];
+  const int ncs = n_c + n_cr;
+  const double* S = K + koff[s] + nI + (size_t)nI * n;   // ld n, full symmetric
+  const double* C = Cr + croff[s];                       // n_cr x n_r
+  double* Tr = T + toff[s];                              // n_r x n_r
+  double* Ps = Psi + psioff[s];                          // ng x ncs
+  double* Acs = Ac + acoff[s];                           // ncs x ncs
+  double* Lr = work + woff[s];                           // n_r x n_r
+  double* X = Lr + (size_t)n_r * n_r;                    // n_r x n_cr
+  double* F = X + (size_t)n_r * n_cr;                    // n_cr x n_cr
+  double* Y = F + (size_t)n_cr * n_cr;                   // n_cr x n_r
+  double* W = Y + (size_t)n_cr * n_r;                    // ng x ncs
+  const int tid = threadIdx.x;
+
+  for (int idx = tid; idx < n_r * n_r; idx += kNT) {
+    const int i = idx % n_r, j = idx / n_r;
+    Lr[idx] = S[i + (size_t)j * n];
+    Tr[idx] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  wg_potrf(Lr, n_r, n_r, status);
+  wg_trsm_lower(Lr, n_r, n_r, Tr, n_r, n_r);
+  wg_trsm_lower_trans(Lr, n_r, n_r, Tr, n_r, n_r);       // Tr = S_rr^{-1}
+  if (n_cr > 0) {
+    for (int idx = tid; idx < n_r * n_cr; idx += kNT) {
+      const int i = idx % n_r, j = idx / n_r;
+      X[idx] = C[j + (size_t)i * n_cr];
+    }
+    __syncthreads();
+    wg_trsm_lower(Lr, n_r, n_r, X, n_r, n_cr);
+    wg_trsm_lower_trans(Lr, n_r, n_r, X, n_r, n_cr);     // X = S_rr^{-1} C_r^T
+    wg_gemm(false, false, n_cr, n_cr, n_r, 1.0, C, n_cr, X, n_r, 0.0, F, n_cr);
+    wg_potrf(F, n_cr, n_cr, status);                    // F = Lf Lf^T
+    for (int idx = tid; idx < n_cr * n_r; idx += kNT) {
+      const int i = idx % n_cr, j = idx / n_cr;
+      Y[idx] = X[j + (size_t)i * n_r];
+    }
+    __syncthreads();
+    wg_trsm_lower(F, n_cr, n_cr, Y, n_cr, n_r);         // Y = Lf^{-1} X^T
+    wg_gemm(true, false, n_r, n_r, n_cr, -1.0, Y, n_cr, Y, n_cr, 1.0, Tr, n_r);   // Tr -= Y^T Y
+    wg_trsm_lower_trans(F, n_cr, n_cr, Y, n_cr, n_r);   // Y = F^{-1} X^T
+  }
+  // Psi: rows r, corner columns = -Tr S_rc; edge columns = (F^{-1} X^T)^T
+  wg_gemm(false, false, n_r, n_c, n_r, -1.0, Tr, n_r, S + (size_t)n_r * n, n, 0.0, Ps, ng);
+  for (int idx = tid; idx < n_r * n_cr; idx += kNT) {
+    const int i = idx % n_r, j = idx / n_r;
+    Ps[i + (size_t)(n_c + j) * ng] = Y[j + (size_t)i * n_cr];
+  }
+  for (int idx = tid; idx < n_c * ncs; idx += kNT) {
+    const int i = idx % n_c, j = idx / n_c;
+    Ps[(n_r + i) + (size_t)j * ng] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  wg_gemm(false, false, ng, ncs, ng, 1.0, S, n, Ps, ng, 0.0, W, ng);            // W = S Psi
+  wg_gemm(true, false, ncs, ncs, ng, 1.0, Ps, ng, W, ng, 0.0, Acs, ncs);         // A_c = Psi^T W
+  // exact symmetry of A_c
+  for (int idx = tid; idx < ncs * ncs; idx += kNT) {
+    const int i = idx % ncs, j = idx / ncs;
+    if (i > j) {
+      const double v = 0.5 * (Acs[i + (size_t)j * ncs] + Acs[j + (size_t)i * ncs]);
+      Acs[i + (size_t)j * ncs] = v;
+      Acs[j + (size_t)i * ncs] = v;
+    }
+  }
+  // exact symmetry of T_rr
+  __syncthreads();
+  for (int idx = tid; idx < n_r * n_r; idx += kNT) {
+    const int i = idx % n_r, j = idx / n_r;
+    if (i > j) {
+      const double v = 0.5 * (Tr[i + (size_t)j * n_r] + Tr[j + (size_t)i * n_r]);
+      Tr[i + (size_t)j * n_r] = v;
+      Tr[j + (size_t)i * n_r] = v;
+    }
+  }
+}
+
+// Coarsest level (Algorithm "Multilevel BDDC", direct solve at level L):
+// A_L = sum_s R_cs^T A_cs R_cs assembled in substructure order, then factored.
+__global__ void __launch_bounds__(kNT) k_coarsest_factor(int nsub, int nc, const int32_t* __restrict__ cptr,
+                                                         const int32_t* __restrict__ cid,
+                                                         const double* __restrict__ Ac,
+                                                         const int64_t* __restrict__ acoff,
+                                                         double* __restrict__ AL, int* status) {
+  for (int idx = threadIdx.x; idx < nc * nc; idx += kNT) AL[idx] = 0.0;
+  __syncthreads();
+  for (int s = 0; s < nsub; ++s) {
+    const int m = cptr[s + 1] - cptr[s];
+    const int32_t* map = cid + cptr[s];
+    const double* Ae = Ac + acoff[s];
+    for (int idx = threadIdx.x; idx < m * m; idx += kNT) {
+      const int i = idx % m, j = idx / m;
+      AL[map[i] + (size_t)map[j] * nc] += Ae[idx];
+    }
+    __syncthreads();
+  }
+  wg_potrf(AL, nc, nc, status);
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+void launch_assemble_l1(hipStream_t st, int nsub, const int64_t* koff, const int32_t* loc_ptr,
+                        const int32_t* nint, const int32_t* node_el, const int32_t* sub_el_ptr,
+                        const int32_t* el_gid, const int32_t* el_loc, const double* coeff,
+                        const Khat16& khat, double* K, double* diagK, const int32_t* goff) {
+  hipLaunchKernelGGL(k_assemble_l1, dim3(nsub), dim3(kNT), 0, st, koff, loc_ptr, nint, node_el,
+                     sub_el_ptr, el_gid, el_loc, coeff, khat, K, diagK, goff);
+}
+
+void launch_assemble_coarse(hipStream_t st, int nsub, const int64_t* koff, const int32_t* loc_ptr,
+                            const int32_t* nint, const int32_t* child_ptr, const int32_t* child_id,
+                            const int32_t* child_map_off, const int32_t* child_map, const double* Ac,
+                            const int64_t* acoff, const int32_t* nc_child, double* K, double* diagK,
+                            const int32_t* goff) {
+  hipLaunchKernelGGL(k_assemble_coarse, dim3(nsub), dim3(kNT), 0, st, koff, loc_ptr, nint, child_ptr,
+                     child_id, child_map_off, child_map, Ac, acoff, nc_child, K, diagK, goff);
+}
+
+void launch_weights(hipStream_t st, int nflat, const int32_t* flat_iid, const int32_t* sh_ptr,
+                    const int32_t* sh_flat, const double* diagK, double* delta) {
+  if (nflat == 0) return;
+  hipLaunchKernelGGL(k_weights, dim3((nflat + kNT - 1) / kNT), dim3(kNT), 0, st, nflat, flat_iid, sh_ptr,
+                     sh_flat, diagK, delta);
+}
+
+void launch_partial_chol(hipStream_t st, int nsub, int nmax, const int64_t* koff, const int32_t* loc_ptr,
+                         const int32_t* nint, double* K, int* status) {
+  const size_t lds = sizeof(double) * (size_t)nmax * kPanel;
+  hipLaunchKernelGGL(k_partial_chol, dim3(nsub), dim3(kNT), lds, st, koff, loc_ptr, nint, K, status);
+}
+
+size_t partial_chol_lds(int nmax) { return sizeof(double) * (size_t)nmax * kPanel; }
+
+void launch_build_cr(hipStream_t st, int nsub, const int32_t* sub_inc_ptr, const int32_t* sub_inc,
+                     const int32_t* inc_edge, const int32_t* inc_fptr, const int32_t* inc_fpos,
+                     const int32_t* edge_nsc, const int32_t* edge_ne, const int32_t* edge_m,
+                     const int64_t* qoff, const double* Q, const int32_t* nr, const int32_t* ncr,
+                     const int64_t* croff, double* Cr) {
+  hipLaunchKernelGGL(k_build_cr, dim3(nsub), dim3(kNT), 0, st, sub_inc_ptr, sub_inc, inc_edge, inc_fptr,
+                     inc_fpos, edge_nsc, edge_ne, edge_m, qoff, Q, nr, ncr, croff, Cr);
+}
+
+void launch_coarse_z(hipStream_t st, int nc, const int32_t* cd_dof, const int32_t* cd_col,
+                     const int32_t* edge_ptr, const int32_t* edge_dof, const int64_t* qoff,
+                     const double* Q, const double* z, double* znext) {
+  if (nc == 0) return;
+  hipLaunchKernelGGL(k_coarse_z, dim3((nc + kNT - 1) / kNT), dim3(kNT), 0, st, nc, cd_dof, cd_col,
+                     edge_ptr, edge_dof, qoff, Q, z, znext);
+}
+
+void launch_constrained_factor(hipStream_t st, int nsub, const int64_t* koff, const int32_t* loc_ptr,
+                               const int32_t* nint, const int32_t* nr, const int32_t* ncr,
+                               const int64_t* croff, const double* Cr, const double* K, double* T,
+                               const int64_t* toff, double* Psi, const int64_t* psioff, double* Ac,
+                               const int64_t* acoff, double* work, const int64_t* woff, int* status) {
+  hipLaunchKernelGGL(k_constrained_factor, dim3(nsub), dim3(kNT), 0, st, koff, loc_ptr, nint, nr, ncr,
+                     croff, Cr, K, T, toff, Psi, psioff, Ac, acoff, work, woff, status);
+}
+
+void launch_coarsest_factor(hipStream_t st, int nsub, int nc, const int32_t* cptr, const int32_t* cid,
+                            const double* Ac, const int64_t* acoff, double* AL, int* status) {
+  hipLaunchKernelGGL(k_coarsest_factor, dim3(1), dim3(kNT), 0, st, nsub, nc, cptr, cid, Ac, acoff, AL,
+                     status);
+}
+
+}  // namespace bddc

@@ -1,0 +1,125 @@
+// Device data descriptors and host launchers of libbddc's kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace bddc {
+
+constexpr int kNT = 256;   // threads per workgroup (4 wave64)
+
+struct Khat16 {
+  double v[16];   // 4x4 reference element matrix (k = 1), row-major, local node order CCW from (i,j)
+};
+
+// Everything an apply kernel needs about one level, by value.
+struct LevelDev {
+  int nsub = 0;
+  int nc = 0;                         // global coarse dofs of the level
+  const int64_t* koff = nullptr;      // per substructure: offset of its dense matrix in K
+  const int32_t* loc_ptr = nullptr;   // per substructure: start of its local dofs (size nsub+1)
+  const int32_t* nint = nullptr;      // interior dofs
+  const int32_t* nr = nullptr;        // interface non-corner dofs
+  const int32_t* goff = nullptr;      // interface flat offset (size nsub+1)
+  const int32_t* ioff = nullptr;      // interior flat offset (size nsub+1)
+  const int32_t* coff = nullptr;      // local coarse flat offset (size nsub+1)
+  const int32_t* int_gid = nullptr;   // interior flat -> level dof
+  const int32_t* gam_gid = nullptr;   // interface flat -> level dof
+  const int32_t* gam_iid = nullptr;   // interface flat -> interface index
+  const int32_t* sh_ptr = nullptr;    // interface index -> sharers (flat interface entries)
+  const int32_t* sh_flat = nullptr;
+  const int32_t* cid = nullptr;       // local coarse flat -> global coarse id
+  const double* K = nullptr;          // factored local matrices: L_II, L_GI, S (full)
+  const double* delta = nullptr;      // stiffness-scaling weights, interface flat
+  const double* T = nullptr;          // T_rr per substructure
+  const int64_t* toff = nullptr;
+  const double* Psi = nullptr;        // coarse basis on the interface, ng x ncs
+  const int64_t* psioff = nullptr;
+  double* y = nullptr;                // scratch: interior flat
+  double* t = nullptr;                // scratch: interface flat
+  double* a = nullptr;                // scratch: interface flat
+  double* v = nullptr;                // scratch: interface flat
+  double* b = nullptr;                // scratch: local coarse flat
+};
+
+constexpr int kMaxHist = 4096;
+
+struct PcgScalars {
+  double rz, pq, alpha, beta, rr, bb, thr2, rtol2;
+  int32_t iters, maxit, done, pad;
+  double alphas[kMaxHist];
+  double betas[kMaxHist];
+};
+
+// setup
+void launch_assemble_l1(hipStream_t st, int nsub, const int64_t* koff, const int32_t* loc_ptr,
+                        const int32_t* nint, const int32_t* node_el, const int32_t* sub_el_ptr,
+                        const int32_t* el_gid, const int32_t* el_loc, const double* coeff,
+                        const Khat16& khat, double* K, double* diagK, const int32_t* goff);
+void launch_assemble_coarse(hipStream_t st, int nsub, const int64_t* koff, const int32_t* loc_ptr,
+                            const int32_t* nint, const int32_t* child_ptr, const int32_t* child_id,
+                            const int32_t* child_map_off, const int32_t* child_map, const double* Ac,
+                            const int64_t* acoff, const int32_t* nc_child, double* K, double* diagK,
+                            const int32_t* goff);
+void launch_weights(hipStream_t st, int nflat, const int32_t* flat_iid, const int32_t* sh_ptr,
+                    const int32_t* sh_flat, const double* diagK, double* delta);
+void launch_partial_chol(hipStream_t st, int nsub, int nmax, const int64_t* koff, const int32_t* loc_ptr,
+                         const int32_t* nint, double* K, int* status);
+size_t partial_chol_lds(int nmax);
+void launch_build_cr(hipStream_t st, int nsub, const int32_t* sub_inc_ptr, const int32_t* sub_inc,
+                     const int32_t* inc_edge, const int32_t* inc_fptr, const int32_t* inc_fpos,
+                     const int32_t* edge_nsc, const int32_t* edge_ne, const int32_t* edge_m,
+                     const int64_t* qoff, const double* Q, const int32_t* nr, const int32_t* ncr,
+                     const int64_t* croff, double* Cr);
+void launch_coarse_z(hipStream_t st, int nc, const int32_t* cd_dof, const int32_t* cd_col,
+                     const int32_t* edge_ptr, const int32_t* edge_dof, const int64_t* qoff,
+                     const double* Q, const double* z, double* znext);
+void launch_constrained_factor(hipStream_t st, int nsub, const int64_t* koff, const int32_t* loc_ptr,
+                               const int32_t* nint, const int32_t* nr, const int32_t* ncr,
+                               const int64_t* croff, const double* Cr, const double* K, double* T,
+                               const int64_t* toff, double* Psi, const int64_t* psioff, double* Ac,
+                               const int64_t* acoff, double* work, const int64_t* woff, int* status);
+void launch_coarsest_factor(hipStream_t st, int nsub, int nc, const int32_t* cptr, const int32_t* cid,
+                            const double* Ac, const int64_t* acoff, double* AL, int* status);
+
+// adaptive
+void launch_pair_schur(hipStream_t st, int ninc, int ngmax, const int32_t* inc_sub, const int32_t* inc_fptr,
+                       const int32_t* inc_fpos, const int64_t* koff, const int32_t* loc_ptr,
+                       const int32_t* nint, const double* K, const int64_t* inc_off, double* Shat,
+                       double* Sff, int* status);
+size_t pair_schur_lds(int ngmax);
+size_t pair_eig_lds(int nemax);
+void launch_pair_eig(hipStream_t st, int nedge, int nemax, const int32_t* edge_s, const int32_t* edge_t,
+                     const int32_t* edge_nsc, const int32_t* edge_ne, const int32_t* edge_fdof,
+                     const int32_t* edge_fptr, const int32_t* inc_fptr, const int32_t* inc_fpos,
+                     const int32_t* goff, const double* diagK, const uint8_t* floating, const double* z,
+                     const double* Shat, const double* Sff, const int64_t* inc_off, double* work,
+                     const int64_t* woff, double tau, double* lam, const int64_t* lamoff, double* Q,
+                     const int64_t* qoff, int32_t* nsel, int32_t* nkept, int* status);
+
+// apply and PCG
+void launch_apply_pre(hipStream_t st, const LevelDev& L, int nImax, int ngmax, const double* r);
+void launch_apply_restrict(hipStream_t st, const LevelDev& L, int ngmax, const double* r,
+                           const int32_t* gam_map, int use_t);
+void launch_coarse_gather(hipStream_t st, int nc, const int32_t* csh_ptr, const int32_t* csh_flat,
+                          const double* b, double* rc);
+void launch_coarsest_solve(hipStream_t st, int nc, const double* Lc, const double* rc, double* uc);
+void launch_apply_prolong(hipStream_t st, const LevelDev& L, int ncsmax, const double* uc);
+void launch_apply_post(hipStream_t st, const LevelDev& L, int nImax, int ngmax, double* u,
+                       const int32_t* gam_map, int interior);
+void launch_schur_local(hipStream_t st, const LevelDev& L, int ngmax, const double* p, double* qloc);
+void launch_gather_dot(hipStream_t st, int nblk, int nif, const int32_t* sh_ptr, const int32_t* sh_flat,
+                       const double* qloc, const double* p, double* q, double* partial);
+void launch_dot_partial(hipStream_t st, int nblk, int n, const double* a, const double* b, double* partial);
+void launch_scalar(hipStream_t st, int which, int nblk, const double* partial, PcgScalars* sc);
+void launch_update_xr(hipStream_t st, int nblk, int n, const PcgScalars* sc, const double* p, const double* q,
+                      double* x, double* r, double* partial);
+void launch_update_p(hipStream_t st, int nblk, int n, const PcgScalars* sc, const double* z, double* p, int first);
+void launch_condense(hipStream_t st, int nif, const int32_t* sh_ptr, const int32_t* sh_flat,
+                     const int32_t* iface_gid, const double* f, const double* t, double* r, double* x);
+void launch_recover(hipStream_t st, const LevelDev& L, int nImax, int ngmax, const double* x, double* u);
+void launch_copy(hipStream_t st, int n, const double* a, double* b);
+
+}  // namespace bddc

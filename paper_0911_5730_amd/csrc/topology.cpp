@@ -1,0 +1,162 @@
+// Host-side substructure topology (see topology.hpp for the classification rules).
+#include "topology.hpp"
+
+#include <algorithm>
+#include <string>
+#include <unordered_set>
+
+#include "common.hpp"
+
+namespace bddc {
+
+namespace {
+inline uint64_t pair_key(int s, int t) {
+  return (static_cast<uint64_t>(static_cast<uint32_t>(s)) << 32) | static_cast<uint32_t>(t);
+}
+}  // namespace
+
+Topology classify(int n, int nsub, const std::vector<int32_t>& elem_ptr,
+                  const std::vector<int32_t>& elem_dof, const std::vector<int32_t>& elem_sub,
+                  const std::vector<uint8_t>& elem_touch) {
+  Topology T;
+  T.n = n;
+  T.nsub = nsub;
+  T.nshare.assign(n, 0);
+  T.share.resize(n);
+  T.floating.assign(nsub, 1);
+  T.is_corner.assign(n, 0);
+  const int ne = static_cast<int>(elem_sub.size());
+
+  // elements grouped by substructure (stable counting sort)
+  std::vector<int32_t> sptr(nsub + 1, 0), order(ne);
+  for (int e = 0; e < ne; ++e) sptr[elem_sub[e] + 1]++;
+  for (int s = 0; s < nsub; ++s) {
+    if (sptr[s + 1] == 0) fail(BDDC_EPARTITION, "substructure " + std::to_string(s) + " owns no element");
+    sptr[s + 1] += sptr[s];
+  }
+  {
+    std::vector<int32_t> pos(sptr.begin(), sptr.end() - 1);
+    for (int e = 0; e < ne; ++e) order[pos[elem_sub[e]]++] = e;
+  }
+
+  // N_d (ascending because substructures are visited in order) and raw local dof lists
+  std::vector<int32_t> mark(n, -1);
+  std::vector<int32_t> raw_ptr(nsub + 1, 0), raw;
+  raw.reserve(elem_dof.size());
+  for (int s = 0; s < nsub; ++s) {
+    for (int k = sptr[s]; k < sptr[s + 1]; ++k) {
+      const int e = order[k];
+      if (elem_touch[e]) T.floating[s] = 0;
+      for (int q = elem_ptr[e]; q < elem_ptr[e + 1]; ++q) {
+        const int d = elem_dof[q];
+        if (mark[d] == s) continue;
+        mark[d] = s;
+        if (T.nshare[d] >= kMaxShare) fail(BDDC_EUNSUPPORTED, "a dof is shared by too many substructures");
+        T.share[d][T.nshare[d]++] = s;
+        raw.push_back(d);
+      }
+    }
+    raw_ptr[s + 1] = static_cast<int32_t>(raw.size());
+  }
+
+  // corners and edge candidates
+  std::vector<std::pair<uint64_t, int32_t>> cand;
+  for (int d = 0; d < n; ++d) {
+    if (T.nshare[d] >= 3) T.is_corner[d] = 1;
+    else if (T.nshare[d] == 2) cand.emplace_back(pair_key(T.share[d][0], T.share[d][1]), d);
+  }
+  std::sort(cand.begin(), cand.end());
+  // groups of candidates by pair
+  std::vector<size_t> gstart;
+  for (size_t i = 0; i < cand.size(); ++i)
+    if (i == 0 || cand[i].first != cand[i - 1].first) gstart.push_back(i);
+  gstart.push_back(cand.size());
+  const size_t ng = gstart.size() - 1;
+  std::vector<uint8_t> removed(cand.size(), 0);
+
+  std::unordered_set<uint64_t> covered;
+  for (int d = 0; d < n; ++d) {
+    if (!T.is_corner[d]) continue;
+    for (int a = 0; a < T.nshare[d]; ++a)
+      for (int b = a + 1; b < T.nshare[d]; ++b) covered.insert(pair_key(T.share[d][a], T.share[d][b]));
+  }
+  // rule: a pair with a floating member shares at least one corner
+  for (size_t g = 0; g < ng; ++g) {
+    const uint64_t key = cand[gstart[g]].first;
+    const int s = static_cast<int>(key >> 32), t = static_cast<int>(key & 0xffffffffu);
+    if (!(T.floating[s] || T.floating[t])) continue;
+    if (covered.count(key)) continue;
+    const size_t i = gstart[g];   // lowest dof of the group
+    T.is_corner[cand[i].second] = 1;
+    removed[i] = 1;
+    covered.insert(key);
+  }
+  // rule: a floating substructure owns at least one corner
+  for (int s = 0; s < nsub; ++s) {
+    if (!T.floating[s]) continue;
+    bool has = false;
+    for (int k = raw_ptr[s]; k < raw_ptr[s + 1] && !has; ++k) has = T.is_corner[raw[k]] != 0;
+    if (has) continue;
+    long best = -1;
+    size_t bestg = 0;
+    for (size_t g = 0; g < ng; ++g) {
+      const uint64_t key = cand[gstart[g]].first;
+      const int a = static_cast<int>(key >> 32), b = static_cast<int>(key & 0xffffffffu);
+      if (a != s && b != s) continue;
+      long cnt = 0;
+      for (size_t i = gstart[g]; i < gstart[g + 1]; ++i) cnt += !removed[i];
+      if (cnt > best) { best = cnt; bestg = g; }
+    }
+    if (best <= 0) fail(BDDC_EPARTITION, "floating substructure " + std::to_string(s) + " has no interface");
+    for (size_t i = gstart[bestg]; i < gstart[bestg + 1]; ++i)
+      if (!removed[i]) { T.is_corner[cand[i].second] = 1; removed[i] = 1; break; }
+  }
+
+  // final edges
+  T.edge_ptr.push_back(0);
+  for (size_t g = 0; g < ng; ++g) {
+    size_t before = T.edge_dof.size();
+    for (size_t i = gstart[g]; i < gstart[g + 1]; ++i)
+      if (!removed[i]) T.edge_dof.push_back(cand[i].second);
+    if (T.edge_dof.size() == before) continue;
+    const uint64_t key = cand[gstart[g]].first;
+    T.edge_s.push_back(static_cast<int32_t>(key >> 32));
+    T.edge_t.push_back(static_cast<int32_t>(key & 0xffffffffu));
+    T.edge_ptr.push_back(static_cast<int32_t>(T.edge_dof.size()));
+  }
+  for (int d = 0; d < n; ++d) {
+    if (T.is_corner[d]) T.corners.push_back(d);
+    if (T.nshare[d] >= 2) T.n_interface++;
+  }
+
+  // local ordering [interior | interface non-corner | corner]
+  T.loc_ptr.assign(nsub + 1, 0);
+  T.n_int.assign(nsub, 0);
+  T.n_r.assign(nsub, 0);
+  T.n_c.assign(nsub, 0);
+  T.loc_dof.resize(raw.size());
+  for (int s = 0; s < nsub; ++s) {
+    std::vector<int32_t> di, dr, dc;
+    for (int k = raw_ptr[s]; k < raw_ptr[s + 1]; ++k) {
+      const int d = raw[k];
+      if (T.nshare[d] == 1) di.push_back(d);
+      else if (T.is_corner[d]) dc.push_back(d);
+      else dr.push_back(d);
+    }
+    std::sort(di.begin(), di.end());
+    std::sort(dr.begin(), dr.end());
+    std::sort(dc.begin(), dc.end());
+    T.n_int[s] = static_cast<int32_t>(di.size());
+    T.n_r[s] = static_cast<int32_t>(dr.size());
+    T.n_c[s] = static_cast<int32_t>(dc.size());
+    int o = raw_ptr[s];
+    T.loc_ptr[s] = o;
+    for (int d : di) T.loc_dof[o++] = d;
+    for (int d : dr) T.loc_dof[o++] = d;
+    for (int d : dc) T.loc_dof[o++] = d;
+  }
+  T.loc_ptr[nsub] = raw_ptr[nsub];
+  return T;
+}
+
+}  // namespace bddc

@@ -1,0 +1,51 @@
+// Host-side substructure topology of one decomposition level (integer work).
+//
+// Section 2: substructures share interface dofs; coarse dofs are corner values
+// and edge functionals.  Section 2.1: at level l the elements are the level-(l-1)
+// substructures and the dofs are the level-(l-1) coarse dofs, so the same
+// classification runs at every level on an element -> dof incidence.
+//
+// Classification (the paper assumes a conforming triangulation and asks only for
+// "sufficient" corners, Section 5):
+//   interface dof: shared by >= 2 substructures; corner: shared by >= 3;
+//   edge of the pair (s,t): every non-corner dof shared by exactly s and t;
+//   a pair with a floating member that shares no corner gets the lowest dof
+//   of its edge promoted to a corner; a floating substructure with no corner
+//   gets the lowest dof of its largest edge promoted.
+#pragma once
+
+#include <array>
+#include <cstdint>
+#include <vector>
+
+namespace bddc {
+
+constexpr int kMaxShare = 8;   // substructures that may share one dof
+
+struct Topology {
+  int n = 0;                        // dofs of the level
+  int nsub = 0;
+  std::vector<uint8_t> nshare;      // |N_d|
+  std::vector<std::array<int32_t, kMaxShare>> share;  // N_d, ascending
+  std::vector<uint8_t> is_corner;
+  std::vector<uint8_t> floating;    // per substructure: no Dirichlet contact
+  // local dofs of each substructure ordered [interior | interface non-corner | corner], each ascending
+  std::vector<int32_t> loc_ptr, loc_dof;
+  std::vector<int32_t> n_int, n_r, n_c;
+  std::vector<int32_t> corners;     // ascending
+  std::vector<int32_t> edge_s, edge_t, edge_ptr, edge_dof;   // edges in (s,t) order, dofs ascending
+  int n_interface = 0;
+
+  int nedges() const { return static_cast<int>(edge_s.size()); }
+  int nloc(int s) const { return loc_ptr[s + 1] - loc_ptr[s]; }
+  int ngam(int s) const { return n_r[s] + n_c[s]; }
+};
+
+// elements given as CSR (elem_ptr, elem_dof); elem_sub[e] in [0, nsub);
+// elem_touch[e] != 0 if the element carries Dirichlet data (its substructure does not float).
+// Throws Error{BDDC_EPARTITION} on an empty substructure or too many sharers.
+Topology classify(int n, int nsub, const std::vector<int32_t>& elem_ptr,
+                  const std::vector<int32_t>& elem_dof, const std::vector<int32_t>& elem_sub,
+                  const std::vector<uint8_t>& elem_touch);
+
+}  // namespace bddc
