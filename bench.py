@@ -1,0 +1,226 @@
+#!/usr/bin/env python3
+"""Throughput of adaptive-multilevel BDDC PCG solves on one MI355X.
+
+Workload (default): Q1 diffusion on a 256 x 256 grid, 16 x 16 substructures
+(H/h = 16), three levels with 4 x 4 groups, k = 10^U(0,6) per element plus 8
+channels of k = 1e6, adaptive coarse dofs with tau = 10, f ~ U[-1, 1],
+PCG to relative residual 1e-8, FP64 throughout.
+
+One step is the whole hot path on one synthetic input: bddc_setup (local
+matrices, weights, interior elimination, per-edge eigenproblems, constrained
+factors, next level, coarsest factor), bddc_solve (PCG on the level-1
+interface with the three-level preconditioner, interior recovery) and
+bddc_destroy.  Coefficients and load are resident in HBM before timing; the
+partition (integer topology input) is read on the host.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6
+METRIC = "PCG solves/s to rel. residual 1e-8, mixed vs FP64 BDDC; p50/p99 solve latency"
+
+# which kernels are bound by HBM bytes and which by FP64 arithmetic
+KERNEL_BOUND = {"partial_chol": "alu", "partial_chol_l2": "alu"}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_0911_5730_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp", ".cpp")):
+            h.update(open(os.path.join(csrc, name), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when the kernels changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    data = json.load(open(path))
+    ent = data.get(workload, {}).get(kernel)
+    if not ent or ent.get("source_hash") != kernel_source_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def cpu_baseline(prob_full):
+    """The oracle on a bounded sample of the same workload: the lower-left
+    quarter of the 256 x 256 coefficient field (128 x 128 elements, 8 x 8
+    substructures with H/h = 16, three levels with 2 x 2 groups, tau = 10),
+    set up and solved to 1e-8; scaled by the substructure count (x4) to one
+    full solve."""
+    import numpy as np
+
+    import synth
+    from oracle import pcg
+    from oracle.bddc import BDDC
+
+    nx = prob_full.nx // 2
+    k = prob_full.coeff.reshape(prob_full.ny, prob_full.nx)[:nx, :nx].reshape(-1).copy()
+    sample = synth.square_problem(nx, 8, levels=3, groups=(2, 2), constraints="adaptive", tau=prob_full.tau,
+                                  seed=2000)
+    sample.coeff = k
+    threads = 1
+    try:
+        from threadpoolctl import threadpool_info
+        info = threadpool_info()
+        if info:
+            threads = max(int(p.get("num_threads", 1)) for p in info)
+    except Exception:
+        pass
+    t0 = time.perf_counter()
+    B = BDDC(sample)
+    out = pcg.solve(B, sample.f[0], rtol=prob_full.rtol)
+    t = time.perf_counter() - t0
+    scale = prob_full.nsub / sample.nsub
+    return {"value": 1.0 / (t * scale), "unit": "solves/s", "cores": threads, "kind": "oracle",
+            "sample": f"oracle setup+PCG on the 128x128 lower-left quarter of the workload's coefficient "
+                      f"field (64 substructures, 3 levels, tau=10): {t:.2f} s, {out['iters']} iterations; "
+                      f"scaled x{scale:g} by substructure count to one full solve",
+            "host_cpus": len(os.sched_getaffinity(0))}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--roofline-kernel", default="apply_restrict")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    ws = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or ws != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the substructures of one problem run on a single MI355X)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_0911_5730_amd as P
+    import synth
+
+    torch.cuda.set_device(0)
+    prob = synth.config(args.config)
+    coeff = torch.tensor(prob.coeff, dtype=torch.float64, device="cuda")
+    f = torch.tensor(prob.f[0], dtype=torch.float64, device="cuda")
+    u = torch.empty_like(f)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        S = P.Solver(prob, coeff=coeff, stream=stream)
+        _, it, rr = S.solve(f, u=u, rtol=prob.rtol, stream=stream)
+        info = S.info()
+        S.close()
+        return it[0], rr[0], info
+
+    log(f"bench: config {args.config} ({synth.CONFIG_NAMES[args.config]}), warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # ---- timed region: K whole steps
+    P.timing_start(args.roofline_kernel)
+    lat = []
+    iters = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        it, rr, info = step()
+        lat.append(time.perf_counter() - ts)
+        iters.append(it)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tm = P.timing_stop()
+    elapsed = t1 - t0
+    log(f"bench: {args.steps} steps in {elapsed:.3f} s, iterations {iters[0]}, relres {rr:.2e}")
+
+    # ---- solve-only and setup-only rates (outside the timed region)
+    S = P.Solver(prob, coeff=coeff, stream=stream)
+    S.solve(f, u=u)
+    torch.cuda.synchronize()
+    ns = max(5, args.steps)
+    s0 = time.perf_counter()
+    for _ in range(ns):
+        S.solve(f, u=u)
+    torch.cuda.synchronize()
+    solve_s = (time.perf_counter() - s0) / ns
+    S.close()
+    su0 = time.perf_counter()
+    for _ in range(ns):
+        P.Solver(prob, coeff=coeff, stream=stream).close()
+    torch.cuda.synchronize()
+    setup_s = (time.perf_counter() - su0) / ns
+
+    # ---- roofline of the chosen kernel, from the events of the timed region
+    kernel = args.roofline_kernel
+    bound = KERNEL_BOUND.get(kernel, "hbm")
+    per_launch_ms = tm["ms"] / max(1, tm["launches"])
+    workload = f"config{args.config}"
+    if bound == "hbm":
+        achieved = (tm["bytes"] / max(1, tm["launches"])) / (per_launch_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM_GBS}
+    else:
+        achieved = (tm["flops"] / max(1, tm["launches"])) / (per_launch_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP64_TFLOPS}
+    roof.update({"kernel": kernel, "launches": tm["launches"], "avg_launch_us": per_launch_ms * 1e3,
+                 "algorithmic_bytes_per_launch": tm["bytes"] / max(1, tm["launches"]),
+                 "traffic": measured_traffic(kernel, workload)})
+
+    lat_ms = np.array(lat) * 1e3
+    out = {
+        "metric": METRIC,
+        "value": args.steps / elapsed,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded coefficient field, partition and load)",
+        "config": {"workload": workload + ": " + synth.CONFIG_NAMES[args.config], "n_free": prob.n_free,
+                   "substructures": prob.nsub, "levels": prob.levels, "tau": prob.tau,
+                   "precision": "fp64", "rtol": prob.rtol, "step": "setup + PCG solve + destroy"},
+        "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
+        "solve_only_per_s": 1.0 / solve_s,
+        "setup_ms": setup_s * 1e3,
+        "iterations": iters[0],
+        "nc": info["nc"],
+        "indicator": info["indicator"],
+        "kappa": info["kappa"],
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        log("bench: timing the CPU oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(prob)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -56,7 +56,7 @@ typedef struct bddc_ctx* bddc_handle;   /* opaque, owned by the library */
 
 #define BDDC_MAX_LEVELS 8
 
-/* Problem description; every pointer is a HOST pointer read during the call only. */
+/* Problem description; pointers are HOST pointers read during the call only, except coeff_device. */
 typedef struct {
   int32_t nx, ny;              /* elements per side of the unit square, nx, ny >= 2 */
   int32_t element;             /* bddc_element */
@@ -69,6 +69,9 @@ typedef struct {
   int32_t constraints;         /* bddc_constraints; corners are always coarse dofs */
   double tau;                  /* ADAPTIVE threshold: eigenvectors with lambda > tau become coarse dofs */
   int32_t precision;           /* bddc_precision; this build implements BDDC_FP64 */
+  const double* coeff_device;  /* optional DEVICE pointer to the same nx*ny coefficients; when non-NULL it is
+                                  used instead of coeff (which may then be NULL) and the positivity check runs
+                                  on the device (BDDC_EINVAL after the device work) */
 } bddc_problem;
 
 /* Sizes and diagnostics of a set-up preconditioner (per level l = 1..levels-1 at index l-1). */
@@ -146,6 +149,23 @@ bddc_status bddc_edge_eigs(bddc_handle h, int32_t level, int32_t edge, double* l
 bddc_status bddc_edge_constraints(bddc_handle h, int32_t level, int32_t edge, int32_t* dofs,
                                   int32_t cap_dofs, double* q, int32_t cap_q,
                                   int32_t* n_edge_dofs, int32_t* n_cols);
+
+/* Kernel timing for measurement tools.  bddc_timing_start(name) arms HIP
+ * events around every later launch of the named kernel (on the stream it is
+ * launched on, on any handle); NULL or "" disarms.  Names: "schur_local",
+ * "apply_pre", "apply_restrict", "apply_prolong", "apply_post" (level 1;
+ * "_l2", "_l3" ... for deeper levels), "partial_chol", "partial_chol_l2".
+ * bddc_timing_stop synchronises those events and returns the summed kernel
+ * time in ms, the number of launches, and the summed algorithmic bytes and
+ * flops of those launches (each operator and vector entry the kernel must
+ * touch, counted once), then disarms.  Host arrays may be NULL.
+ * Errors: BDDC_EDEVICE. */
+bddc_status bddc_timing_start(const char* kernel);
+bddc_status bddc_timing_stop(double* total_ms, int64_t* launches, double* bytes, double* flops);
+
+/* Message of the last failed call on this thread ("" if none; never NULL;
+ * valid until the next failing call on the same thread). */
+const char* bddc_last_error(void);
 
 /* Static description of a status code (never NULL). */
 const char* bddc_status_string(bddc_status s);

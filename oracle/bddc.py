@@ -79,7 +79,6 @@ class Level:
             self.AII_lu = spla.splu(AII)
         else:
             self.AII_lu = None
-        self.pair_info = {}
 
     # ----- local Neumann matrices K_i (Section 2: a is assembled from them)
     def _local_matrices(self):
@@ -204,6 +203,7 @@ class BDDC:
         n = (nx - 1) * (ny - 1)
         self.levels: List[Level] = []
         self.eigs = []                       # per level: {(s,t): lambdas}
+        self.edge_Q = []                     # per level: {(s,t): orthonormal constraint columns}
         self.omega_levels = []               # per level: max_st lambda_{n+1}
         cur = Level(1, n, elems, prob.part, prob.nsub, ~touches, np.ones(n))
         from . import adaptive
@@ -216,6 +216,7 @@ class BDDC:
             if self.kind == "adaptive":
                 edge_Q, lam, omega = adaptive.select_level(cur, self.tau)
                 self.eigs.append(lam)
+                self.edge_Q.append(edge_Q)
                 self.omega_levels.append(omega)
             cur.build_coarse(self.kind, edge_Q)
             self.levels.append(cur)
@@ -228,7 +229,7 @@ class BDDC:
         last = self.levels[-1]
         Ac = assemble_elements(last.Nc, [(last.cids[s], last.Ac[s]) for s in range(last.nsub)])
         self.A_coarsest = Ac.toarray()
-        self.coarse_chol = sla.cho_factor(self.A_coarsest)
+        self.coarse_chol = sla.cho_factor(self.A_coarsest) if last.Nc else None
 
     @property
     def indicator(self) -> float:
@@ -249,7 +250,7 @@ class BDDC:
         for s in range(lv.nsub):
             np.add.at(rc, lv.cids[s], lv.Psi[s].T @ g[s])
         if li == len(self.levels) - 1:
-            uc = sla.cho_solve(self.coarse_chol, rc)
+            uc = sla.cho_solve(self.coarse_chol, rc) if lv.Nc else rc
         else:
             uc = self._apply_level(li + 1, rc)
         uB = np.zeros(lv.n)                                          # ML-uBi-1

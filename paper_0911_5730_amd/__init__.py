@@ -10,4 +10,6 @@ from .bddc import (  # noqa: F401
     load_library,
     plan,
     status_string,
+    timing_start,
+    timing_stop,
 )

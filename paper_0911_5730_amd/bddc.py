@@ -32,7 +32,8 @@ class BddcProblemC(ctypes.Structure):
                 ("coeff", ctypes.POINTER(ctypes.c_double)), ("part", ctypes.POINTER(ctypes.c_int32)),
                 ("nsub", ctypes.c_int32), ("levels", ctypes.c_int32),
                 ("agglom", ctypes.POINTER(ctypes.POINTER(ctypes.c_int32))),
-                ("constraints", ctypes.c_int32), ("tau", ctypes.c_double), ("precision", ctypes.c_int32)]
+                ("constraints", ctypes.c_int32), ("tau", ctypes.c_double), ("precision", ctypes.c_int32),
+                ("coeff_device", ctypes.c_void_p)]
 
 
 class BddcInfoC(ctypes.Structure):
@@ -47,7 +48,8 @@ class BddcInfoC(ctypes.Structure):
 
 
 SYMBOLS = ["bddc_plan", "bddc_setup", "bddc_apply", "bddc_solve", "bddc_query", "bddc_edge_eigs",
-           "bddc_edge_constraints", "bddc_status_string", "bddc_destroy"]
+           "bddc_edge_constraints", "bddc_timing_start", "bddc_timing_stop", "bddc_last_error",
+           "bddc_status_string", "bddc_destroy"]
 
 _lib = None
 
@@ -58,6 +60,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with `python -m paper_0911_5730_amd.build`")
+    # torch ships its own HIP runtime with the same soname; loading torch first
+    # makes the library bind to it, so the process holds a single HIP runtime
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     P = ctypes.POINTER
     i32, i64, dbl, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
@@ -68,13 +76,16 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.bddc_query.argtypes = [vp, P(BddcInfoC)]
     lib.bddc_edge_eigs.argtypes = [vp, i32, i32, P(dbl), i32, P(i32), P(i32), P(i32), P(i32)]
     lib.bddc_edge_constraints.argtypes = [vp, i32, i32, P(i32), i32, P(dbl), i32, P(i32), P(i32)]
+    lib.bddc_timing_start.argtypes = [ctypes.c_char_p]
+    lib.bddc_timing_stop.argtypes = [P(dbl), P(i64), P(dbl), P(dbl)]
     lib.bddc_status_string.argtypes = [i32]
     lib.bddc_status_string.restype = ctypes.c_char_p
     lib.bddc_destroy.argtypes = [vp]
     lib.bddc_destroy.restype = None
-    for name in SYMBOLS[:-2]:
-        if name != "bddc_status_string":
-            getattr(lib, name).restype = i32
+    lib.bddc_last_error.argtypes = []
+    lib.bddc_last_error.restype = ctypes.c_char_p
+    for name in SYMBOLS[:-3]:
+        getattr(lib, name).restype = i32
     _lib = lib
     return lib
 
@@ -83,7 +94,10 @@ class BDDCError(RuntimeError):
     def __init__(self, status: int, where: str):
         self.status = status
         self.name = STATUS.get(status, str(status))
-        super().__init__(f"{where}: {self.name}")
+        detail = ""
+        if _lib is not None:
+            detail = (_lib.bddc_last_error() or b"").decode(errors="replace")
+        super().__init__(f"{where}: {self.name}" + (f" ({detail})" if detail else ""))
 
 
 def _check(st: int, where: str):
@@ -94,10 +108,18 @@ def _check(st: int, where: str):
 class _Marshalled:
     """C view of a problem; keeps the numpy buffers alive while in use."""
 
-    def __init__(self, prob, tau=None, constraints=None, precision="fp64"):
+    def __init__(self, prob, tau=None, constraints=None, precision="fp64", coeff_device=None):
         self.coeff = np.ascontiguousarray(prob.coeff, dtype=np.float64)
         self.part = np.ascontiguousarray(prob.part, dtype=np.int32)
         self.agg = [np.ascontiguousarray(a, dtype=np.int32) for a in (prob.agglom or [])]
+        ne = int(prob.nx) * int(prob.ny)
+        if prob.nx >= 2 and prob.ny >= 2 and (self.coeff.size != ne or self.part.size != ne):
+            raise ValueError("coeff and part must have nx*ny entries")
+        nprev = prob.nsub
+        for a in self.agg:
+            if a.size != nprev:
+                raise ValueError("each agglomeration array needs one entry per substructure")
+            nprev = int(a.max()) + 1 if a.size else 0
         n = max(1, len(self.agg))
         self.agg_ptrs = (ctypes.POINTER(ctypes.c_int32) * n)()
         for i, a in enumerate(self.agg):
@@ -113,6 +135,8 @@ class _Marshalled:
             if self.agg else None,
             constraints=CONSTRAINTS[kind], tau=float(t) if math.isfinite(t) else float("inf"),
             precision=PRECISION[precision])
+        if coeff_device is not None:
+            self.c.coeff_device = ctypes.c_void_p(coeff_device)
 
 
 def info_dict(ci: BddcInfoC) -> dict:
@@ -158,9 +182,17 @@ def _vec_args(t, n_free):
 class Solver:
     """A set-up adaptive-multilevel BDDC preconditioner on the current GPU."""
 
-    def __init__(self, prob, *, tau=None, constraints=None, precision="fp64", stream=None):
+    def __init__(self, prob, *, tau=None, constraints=None, precision="fp64", stream=None, coeff=None):
+        """coeff: optional float64 CUDA tensor with the nx*ny coefficients (kept on the device)."""
         self.lib = load_library()
-        m = _Marshalled(prob, tau=tau, constraints=constraints, precision=precision)
+        dptr = None
+        if coeff is not None:
+            import torch
+            if not (coeff.is_cuda and coeff.dtype == torch.float64 and coeff.is_contiguous()
+                    and coeff.numel() == prob.nx * prob.ny):
+                raise TypeError("coeff must be a contiguous float64 CUDA tensor with nx*ny entries")
+            dptr = coeff.data_ptr()
+        m = _Marshalled(prob, tau=tau, constraints=constraints, precision=precision, coeff_device=dptr)
         h = ctypes.c_void_p()
         _check(self.lib.bddc_setup(ctypes.byref(m.c), ctypes.c_void_p(_stream_ptr(stream)), ctypes.byref(h)),
                "bddc_setup")
@@ -232,6 +264,19 @@ class Solver:
                                               None), "bddc_edge_constraints")
         Q = np.array(q[:ne.value * m.value]).reshape(m.value, ne.value).T
         return np.array(dofs[:ne.value]), Q
+
+
+def timing_start(kernel: str):
+    """Arm HIP-event timing around every launch of one library kernel."""
+    _check(load_library().bddc_timing_start(kernel.encode()), "bddc_timing_start")
+
+
+def timing_stop() -> dict:
+    """Summed kernel time (ms), launches, algorithmic bytes and flops since timing_start."""
+    ms, n, by, fl = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+    _check(load_library().bddc_timing_stop(ctypes.byref(ms), ctypes.byref(n), ctypes.byref(by),
+                                           ctypes.byref(fl)), "bddc_timing_stop")
+    return dict(ms=ms.value, launches=n.value, bytes=by.value, flops=fl.value)
 
 
 def status_string(code: int) -> str:

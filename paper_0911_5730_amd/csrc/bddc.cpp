@@ -11,8 +11,11 @@
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <numeric>
+#include <string>
 #include <unordered_map>
 
 #include "common.hpp"
@@ -20,6 +23,101 @@
 #include "topology.hpp"
 
 namespace bddc {
+
+hipMemPool_t device_pool() {
+  static std::mutex mu;
+  static std::map<int, hipMemPool_t> pools;
+  int dev = 0;
+  BDDC_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = pools.find(dev);
+  if (it != pools.end()) return it->second;
+  hipMemPoolProps props{};
+  props.allocType = hipMemAllocationTypePinned;
+  props.location.type = hipMemLocationTypeDevice;
+  props.location.id = dev;
+  hipMemPool_t pool;
+  BDDC_HIP(hipMemPoolCreate(&pool, &props));
+  uint64_t thr = UINT64_MAX;
+  BDDC_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr));
+  pools[dev] = pool;
+  return pool;
+}
+
+// ---------------------------------------------------------------------------
+// Kernel timing for measurement tools: while armed for one kernel name, every
+// launch of that kernel is bracketed by HIP events on its own stream, with the
+// launch's algorithmic bytes and flops recorded beside it.
+namespace timing {
+struct Rec {
+  hipEvent_t a, b;
+  double bytes, flops;
+  int tag;   // PCG iteration of the launch (-1 outside PCG)
+};
+std::mutex mu;
+std::string target;
+std::vector<Rec> recs;
+std::vector<hipEvent_t> pool;
+int current_tag = -1;     // set by the PCG driver while it enqueues an iteration
+
+size_t mark() {
+  std::lock_guard<std::mutex> lk(mu);
+  return recs.size();
+}
+
+// drop the records from `from` on whose tag is >= limit: launches enqueued
+// after convergence return at once and move no data
+void prune(size_t from, int limit) {
+  std::lock_guard<std::mutex> lk(mu);
+  if (from >= recs.size()) return;
+  std::vector<Rec> keep(recs.begin(), recs.begin() + from);
+  for (size_t i = from; i < recs.size(); ++i) {
+    if (recs[i].tag >= limit) {
+      pool.push_back(recs[i].a);
+      pool.push_back(recs[i].b);
+    } else {
+      keep.push_back(recs[i]);
+    }
+  }
+  recs.swap(keep);
+}
+
+hipEvent_t get_event() {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  BDDC_HIP(hipEventCreate(&e));
+  return e;
+}
+
+class Scope {
+ public:
+  Scope(const char* name, hipStream_t st, double bytes, double flops, int tag_shift = 0) {
+    std::lock_guard<std::mutex> lk(mu);
+    if (target.empty() || target != name) return;
+    rec_.a = get_event();
+    rec_.b = get_event();
+    rec_.bytes = bytes;
+    rec_.flops = flops;
+    rec_.tag = current_tag < 0 ? -1 : current_tag + tag_shift;
+    st_ = st;
+    on_ = hipEventRecord(rec_.a, st) == hipSuccess;
+  }
+  ~Scope() {
+    if (!on_) return;
+    std::lock_guard<std::mutex> lk(mu);
+    if (hipEventRecord(rec_.b, st_) == hipSuccess) recs.push_back(rec_);
+  }
+
+ private:
+  bool on_ = false;
+  Rec rec_{};
+  hipStream_t st_ = nullptr;
+};
+}  // namespace timing
 
 namespace {
 
@@ -86,6 +184,9 @@ struct Level {
   double omega = 0.0;
   int n_adaptive = 0;
   std::vector<int32_t> agglom_of;   // level-(l+1) substructure of each substructure
+  // algorithmic bytes / flops of one launch of each kernel at this level
+  double by_schur = 0, by_restrict_ir = 0, by_restrict_fs = 0, by_prolong = 0, by_post_ir = 0,
+         by_post_fs = 0, by_pre = 0, fl_chol = 0, by_chol = 0;
   // device
   Arena arena_a, arena_b, arena_pcg;
   struct {
@@ -144,7 +245,7 @@ static void validate(const bddc_problem* p) {
   if (p->nx < 2 || p->ny < 2) fail(BDDC_EINVAL, "nx and ny must be >= 2");
   if ((int64_t)p->nx * p->ny > (int64_t)1 << 30) fail(BDDC_EUNSUPPORTED, "mesh too large");
   if (p->element != BDDC_Q1 && p->element != BDDC_P1) fail(BDDC_EINVAL, "unknown element");
-  if (!p->coeff || !p->part) fail(BDDC_EINVAL, "coeff and part are required");
+  if ((!p->coeff && !p->coeff_device) || !p->part) fail(BDDC_EINVAL, "coeff and part are required");
   if (p->nsub < 1) fail(BDDC_EINVAL, "nsub must be >= 1");
   if (p->levels < 2 || p->levels > BDDC_MAX_LEVELS) fail(BDDC_EINVAL, "levels must be in [2, 8]");
   if (p->constraints < 0 || p->constraints > 2) fail(BDDC_EINVAL, "unknown constraint kind");
@@ -155,8 +256,10 @@ static void validate(const bddc_problem* p) {
   }
   const int64_t ne = (int64_t)p->nx * p->ny;
   for (int64_t e = 0; e < ne; ++e) {
-    const double k = p->coeff[e];
-    if (!(k > 0.0) || !std::isfinite(k)) fail(BDDC_EINVAL, "coefficients must be positive and finite");
+    if (!p->coeff_device) {
+      const double k = p->coeff[e];
+      if (!(k > 0.0) || !std::isfinite(k)) fail(BDDC_EINVAL, "coefficients must be positive and finite");
+    }
     if (p->part[e] < 0 || p->part[e] >= p->nsub) fail(BDDC_EPARTITION, "partition id out of range");
   }
   std::vector<char> used(p->nsub, 0);
@@ -347,6 +450,35 @@ static void layout_level(Level& lv) {
   lv.inc_off.push_back(io);
 }
 
+// algorithmic traffic of each kernel at one level: every operator entry and
+// vector entry the kernel must touch, counted once (FP64 = 8 bytes, index = 4)
+static void account(Level& lv) {
+  const Topology& T = lv.topo;
+  double nshare_sum = 0;
+  for (int g = 0; g + 1 < (int)lv.sh_ptr.size(); ++g) {
+    const double m = lv.sh_ptr[g + 1] - lv.sh_ptr[g];
+    nshare_sum += m * m;   // every sharer of g sums over all sharers of g
+  }
+  const double nif = (double)lv.iface_dof.size();
+  for (int s = 0; s < lv.nsub; ++s) {
+    const double nI = T.n_int[s], ng = T.ngam(s), nr = T.n_r[s], n = T.nloc(s);
+    const double ncs = lv.coff[s + 1] - lv.coff[s];
+    lv.by_schur += 8 * ng * ng + 20 * ng;
+    lv.by_restrict_ir += 8 * nr * nr + 8 * ng * ncs + 28 * ng + 8 * ncs;
+    lv.by_prolong += 8 * ng * ncs + 12 * ncs + 24 * ng;
+    lv.by_pre += 8 * nI * (nI + 1) / 2 + 8 * ng * nI + 20 * nI + 8 * ng;
+    lv.by_post_fs += 8 * nI * (nI + 1) / 2 + 8 * ng * nI + 20 * nI;
+    for (int j = 0; j < (int)nI; ++j) {
+      const double w = n - j - 1;
+      lv.fl_chol += w + w * (w + 1);
+    }
+    lv.by_chol += 16 * n * n;
+  }
+  lv.by_restrict_fs = lv.by_restrict_ir + 12 * nshare_sum;
+  lv.by_post_ir = 12 * nshare_sum + 12 * lv.nflat_g + 8 * nif;
+  lv.by_post_fs += lv.by_post_ir;
+}
+
 // ---------------------------------------------------------------------------
 class Builder {
  public:
@@ -390,6 +522,7 @@ class Builder {
     BDDC_HIP(hipStreamSynchronize(st_));
     int bad = 0;
     BDDC_HIP(hipMemcpy(&bad, h_->status, sizeof(int), hipMemcpyDeviceToHost));
+    if (bad & 2) fail(BDDC_EINVAL, "coefficients must be positive and finite");
     if (bad) fail(BDDC_ESINGULAR, "a local or coarse factorization met a non-positive pivot");
   }
 
@@ -572,7 +705,11 @@ class Builder {
     h2d(d.sub_el_ptr, sub_el_ptr, st_);
     h2d(d.el_gid, el_gid, st_);
     h2d(d.el_loc, el_loc, st_);
-    if (E) BDDC_HIP(hipMemcpyAsync(d.coeff, p_->coeff, sizeof(double) * h_->nx * h_->ny, hipMemcpyHostToDevice, st_));
+    if (E && p_->coeff_device)
+      BDDC_HIP(hipMemcpyAsync(d.coeff, p_->coeff_device, sizeof(double) * h_->nx * h_->ny,
+                              hipMemcpyDeviceToDevice, st_));
+    else if (E)
+      BDDC_HIP(hipMemcpyAsync(d.coeff, p_->coeff, sizeof(double) * h_->nx * h_->ny, hipMemcpyHostToDevice, st_));
     h2d(d.child_ptr, child_ptr, st_);
     h2d(d.child_id, child_id, st_);
     h2d(d.child_map_off, child_map_off, st_);
@@ -611,7 +748,7 @@ class Builder {
   void assemble_l1(Level& lv, const Level1Elements&) {
     const Khat16 kh = element_matrix(p_->element, h_->nx, h_->ny);
     launch_assemble_l1(st_, lv.nsub, lv.d.koff, lv.d.loc_ptr, lv.d.nint, lv.d.node_el, lv.d.sub_el_ptr,
-                       lv.d.el_gid, lv.d.el_loc, lv.d.coeff, kh, lv.d.K, lv.d.diagK, lv.d.goff);
+                       lv.d.el_gid, lv.d.el_loc, lv.d.coeff, kh, lv.d.K, lv.d.diagK, lv.d.goff, h_->status);
   }
 
   void assemble_coarse(Level& lv, const Level& prev) {
@@ -625,7 +762,18 @@ class Builder {
     auto& d = lv.d;
     const Topology& T = lv.topo;
     launch_weights(st_, lv.nflat_g, d.gam_iid, d.sh_ptr, d.sh_flat, d.diagK, d.delta);
-    launch_partial_chol(st_, lv.nsub, lv.nmax, d.koff, d.loc_ptr, d.nint, d.K, h_->status);
+    {
+      double fl = 0;
+      for (int s = 0; s < lv.nsub; ++s)
+        for (int j = 0; j < T.n_int[s]; ++j) {
+          const double w = T.nloc(s) - j - 1;
+          fl += w + w * (w + 1);
+        }
+      double by = 0;
+      for (int s = 0; s < lv.nsub; ++s) by += 16.0 * T.nloc(s) * T.nloc(s);
+      timing::Scope ts(lv.ell == 1 ? "partial_chol" : "partial_chol_l2", st_, by, fl);
+      launch_partial_chol(st_, lv.nsub, lv.nmax, d.koff, d.loc_ptr, d.nint, d.K, h_->status);
+    }
     const int ne_tot = lv.nedge;
     lv.edge_m.assign(ne_tot, 0);
     lv.edge_nsel.assign(ne_tot, 0);
@@ -661,6 +809,7 @@ class Builder {
       h2d(d.Q, qh, st_);
     }
     coarse_numbering(lv);
+    account(lv);
     alloc_b(lv);
     launch_build_cr(st_, lv.nsub, d.sub_inc_ptr, d.sub_inc, d.inc_edge, d.inc_fptr, d.inc_fpos, d.edge_nsc,
                     d.edge_ne, d.edge_m, d.qoff, d.Q, d.nr, d.ncr, d.croff, d.Cr);
@@ -839,15 +988,28 @@ static void apply_level(bddc_ctx* h, int li, const double* r, double* u, bool in
   hipStream_t st = h->stream;
   const bool interior = !interface_only;
   const int32_t* gmap = interface_only ? lv.d.gam_iid : lv.d.gam_gid;
-  if (interior) launch_apply_pre(st, lv.dev, lv.nImax, lv.ngmax, r);
-  launch_apply_restrict(st, lv.dev, lv.ngmax, r, gmap, interior ? 1 : 0);
-  launch_coarse_gather(st, lv.nc, lv.d.csh_ptr, lv.d.csh_flat, lv.d.b, lv.d.rc);
+  const std::string sfx = li == 0 ? "" : "_l" + std::to_string(li + 1);
+  if (interior) {
+    timing::Scope ts(("apply_pre" + sfx).c_str(), st, lv.by_pre, 0);
+    launch_apply_pre(st, lv.dev, lv.nImax, lv.ngmax, r);
+  }
+  {
+    timing::Scope ts(("apply_restrict" + sfx).c_str(), st, interior ? lv.by_restrict_fs : lv.by_restrict_ir, 0);
+    launch_apply_restrict(st, lv.dev, lv.ngmax, r, gmap, interior ? 1 : 0);
+  }
+  launch_coarse_gather(st, lv.nc, lv.d.csh_ptr, lv.d.csh_flat, lv.d.b, lv.d.rc, lv.dev.stop);
   if (li + 1 == (int)h->levels.size())
-    launch_coarsest_solve(st, lv.nc, h->AL, lv.d.rc, lv.d.uc);
+    launch_coarsest_solve(st, lv.nc, h->AL, lv.d.rc, lv.d.uc, lv.dev.stop);
   else
     apply_level(h, li + 1, lv.d.rc, lv.d.uc, false);
-  launch_apply_prolong(st, lv.dev, lv.ncsmax, lv.d.uc);
-  launch_apply_post(st, lv.dev, lv.nImax, lv.ngmax, u, gmap, interior ? 1 : 0);
+  {
+    timing::Scope ts(("apply_prolong" + sfx).c_str(), st, lv.by_prolong, 0);
+    launch_apply_prolong(st, lv.dev, lv.ncsmax, lv.d.uc);
+  }
+  {
+    timing::Scope ts(("apply_post" + sfx).c_str(), st, interior ? lv.by_post_fs : lv.by_post_ir, 0);
+    launch_apply_post(st, lv.dev, lv.nImax, lv.ngmax, u, gmap, interior ? 1 : 0);
+  }
 }
 
 // symmetric tridiagonal extreme eigenvalues by Sturm bisection
@@ -906,15 +1068,32 @@ static int pcg_one(bddc_ctx* h, const double* f, double* u, double rtol, int max
   launch_condense(st, nif, l1.d.sh_ptr, l1.d.sh_flat, l1.d.iface_dof, f, l1.d.t, h->r, h->x);
   launch_dot_partial(st, nb, nif, h->r, h->r, h->partial);
   launch_scalar(st, 5, nb, h->partial, h->sc);                    // rr0, done if already small
+  const size_t tmark = timing::mark();
+  timing::current_tag = 0;
   apply_level(h, 0, h->r, h->zv, true);
+  timing::current_tag = -1;
   launch_dot_partial(st, nb, nif, h->r, h->zv, h->partial);
   launch_scalar(st, 3, nb, h->partial, h->sc);                    // rz
   launch_update_p(st, nb, nif, h->sc, h->zv, h->p, 1);
+  // apply kernels inside the loop return at once after convergence
+  struct StopGuard {
+    bddc_ctx* h;
+    ~StopGuard() {
+      for (auto& lvp : h->levels) lvp->dev.stop = nullptr;
+      timing::current_tag = -1;
+    }
+  } guard_stop{h};
+  for (auto& lvp : h->levels) lvp->dev.stop = &h->sc->done;
   int it = 0;
-  int check = 1;
+  int check = 4;
   while (it < maxit) {
     for (int k = 0; k < check && it < maxit; ++k, ++it) {
-      launch_schur_local(st, l1.dev, l1.ngmax, h->p, l1.d.qloc);
+      timing::current_tag = it + 1;
+      {
+        // the product of iteration k works iff k <= K (K = converged iteration)
+        timing::Scope ts("schur_local", st, l1.by_schur, 0, -1);
+        launch_schur_local(st, l1.dev, l1.ngmax, h->p, l1.d.qloc);
+      }
       launch_gather_dot(st, nb, nif, l1.d.sh_ptr, l1.d.sh_flat, l1.d.qloc, h->p, h->q, h->partial);
       launch_scalar(st, 0, nb, h->partial, h->sc);                // alpha
       launch_update_xr(st, nb, nif, h->sc, h->p, h->q, h->x, h->r, h->partial);
@@ -927,12 +1106,15 @@ static int pcg_one(bddc_ctx* h, const double* f, double* u, double rtol, int max
     BDDC_HIP(hipMemcpyAsync(sch, h->sc, offsetof(PcgScalars, alphas), hipMemcpyDeviceToHost, st));
     BDDC_HIP(hipStreamSynchronize(st));
     if (sch->done) break;
-    check = std::min(16, check * 2);
+    check = std::min(8, check * 2);
   }
+  timing::current_tag = -1;
   launch_recover(st, l1.dev, l1.nImax, l1.ngmax, h->x, u);
   BDDC_HIP(hipMemcpyAsync(sch, h->sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, st));
   BDDC_HIP(hipStreamSynchronize(st));
   const int iters = sch->iters;
+  // the apply of iteration k (tag k) works iff k < K; the product of iteration k (tag k-1) iff k <= K
+  timing::prune(tmark, sch->done == 1 ? iters : iters + 1);
   *relres = sch->bb > 0 ? std::sqrt(sch->rr / sch->bb) : 0.0;
   std::vector<double> al(sch->alphas, sch->alphas + std::min(iters, kMaxHist));
   std::vector<double> be(sch->betas, sch->betas + std::max(0, std::min(iters, kMaxHist) - 1));
@@ -974,16 +1156,21 @@ using namespace bddc;
 
 namespace {
 
+thread_local std::string g_last_error;
+
 bddc_status guard(const std::function<void()>& fn) {
   try {
     fn();
     return BDDC_OK;
   } catch (const Error& e) {
+    g_last_error = e.msg;
     if (getenv("BDDC_VERBOSE")) fprintf(stderr, "libbddc: %s\n", e.msg.c_str());
     return e.status;
   } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
     return BDDC_ENOMEM;
   } catch (...) {
+    g_last_error = "unexpected exception";
     return BDDC_EDEVICE;
   }
 }
@@ -1017,6 +1204,8 @@ void fill_level_info(const Level& lv, int idx, bddc_info* info) {
 }  // namespace
 
 extern "C" {
+
+const char* bddc_last_error(void) { return g_last_error.c_str(); }
 
 const char* bddc_status_string(bddc_status s) {
   switch (s) {
@@ -1182,5 +1371,42 @@ bddc_status bddc_edge_constraints(bddc_handle h, int32_t level, int32_t edge, in
 }
 
 void bddc_destroy(bddc_handle h) { release(h); }
+
+bddc_status bddc_timing_start(const char* kernel) {
+  return guard([&] {
+    std::lock_guard<std::mutex> lk(timing::mu);
+    for (auto& r : timing::recs) {
+      timing::pool.push_back(r.a);
+      timing::pool.push_back(r.b);
+    }
+    timing::recs.clear();
+    timing::target = kernel ? kernel : "";
+  });
+}
+
+bddc_status bddc_timing_stop(double* total_ms, int64_t* launches, double* bytes, double* flops) {
+  return guard([&] {
+    std::lock_guard<std::mutex> lk(timing::mu);
+    double ms = 0, by = 0, fl = 0;
+    for (auto& r : timing::recs) {
+      BDDC_HIP(hipEventSynchronize(r.b));
+      float t = 0;
+      BDDC_HIP(hipEventElapsedTime(&t, r.a, r.b));
+      ms += t;
+      by += r.bytes;
+      fl += r.flops;
+    }
+    if (total_ms) *total_ms = ms;
+    if (launches) *launches = (int64_t)timing::recs.size();
+    if (bytes) *bytes = by;
+    if (flops) *flops = fl;
+    for (auto& r : timing::recs) {
+      timing::pool.push_back(r.a);
+      timing::pool.push_back(r.b);
+    }
+    timing::recs.clear();
+    timing::target.clear();
+  });
+}
 
 }  // extern "C"

@@ -27,6 +27,10 @@ struct Error {
       ::bddc::fail(BDDC_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));    \
   } while (0)
 
+// The library's stream-ordered memory pool on the current device; it keeps
+// freed memory (release threshold = max) so that repeated set-ups reuse it.
+hipMemPool_t device_pool();
+
 // One device allocation carved into aligned pieces.  Pieces are laid out by a
 // sizing pass (base == nullptr) and then a second pass after allocation.
 class Arena {
@@ -43,7 +47,7 @@ class Arena {
   size_t used() const { return used_; }
   void allocate(hipStream_t st) {
     size_t n = used_ ? used_ : 256;
-    hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&base_), n, st);
+    hipError_t e = hipMallocFromPoolAsync(reinterpret_cast<void**>(&base_), n, device_pool(), st);
     if (e != hipSuccess) {
       base_ = nullptr;
       fail(e == hipErrorOutOfMemory ? BDDC_ENOMEM : BDDC_EDEVICE,

@@ -12,7 +12,7 @@
 namespace bddc {
 
 __device__ inline void flag_bad(int* status) {
-  if (status) *status = 1;
+  if (status) atomicOr(status, 1);
 }
 
 // Eliminate the first m columns of the symmetric n x n matrix A (lower triangle

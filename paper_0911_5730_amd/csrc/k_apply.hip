@@ -27,6 +27,7 @@ __device__ inline double wave_sum(double v) {
 // y = L_II^{-1} r_I ; t = L_GI y
 __global__ void __launch_bounds__(kNT) k_apply_pre(LevelDev L, const double* __restrict__ r) {
   extern __shared__ double sh[];
+  if (L.stop && *L.stop) return;
   const int s = blockIdx.x;
   const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
   const int nI = L.nint[s];
@@ -56,9 +57,13 @@ __global__ void __launch_bounds__(kNT) k_apply_pre(LevelDev L, const double* __r
 }
 
 // g = delta (r_Gamma - sum t);  a_r = T_rr g_r, a_c = 0;  b = Psi^T g
+// kFS: full-space input (subtract the interior pre-correction t); otherwise the
+// input is an interface vector with zero interior residual.
+template <bool kFS>
 __global__ void __launch_bounds__(kNT) k_apply_restrict(LevelDev L, const double* __restrict__ r,
-                                                        const int32_t* __restrict__ gam_map, int use_t) {
+                                                        const int32_t* __restrict__ gam_map) {
   extern __shared__ double sh[];
+  if (L.stop && *L.stop) return;
   const int s = blockIdx.x;
   const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
   const int nI = L.nint[s];
@@ -72,7 +77,7 @@ __global__ void __launch_bounds__(kNT) k_apply_restrict(LevelDev L, const double
   for (int a = tid; a < ng; a += kNT) {
     const int f = g0 + a;
     double v = r[gam_map[f]];
-    if (use_t) {
+    if (kFS) {
       const int gi = L.gam_iid[f];
       for (int k = L.sh_ptr[gi]; k < L.sh_ptr[gi + 1]; ++k) v -= L.t[L.sh_flat[k]];
     }
@@ -111,7 +116,8 @@ __global__ void __launch_bounds__(kNT) k_apply_restrict(LevelDev L, const double
 }
 
 __global__ void k_coarse_gather(int nc, const int32_t* __restrict__ csh_ptr, const int32_t* __restrict__ csh_flat,
-                                const double* __restrict__ b, double* __restrict__ rc) {
+                                const double* __restrict__ b, double* __restrict__ rc, const int32_t* stop) {
+  if (stop && *stop) return;
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nc) return;
   double acc = 0.0;
@@ -120,8 +126,10 @@ __global__ void k_coarse_gather(int nc, const int32_t* __restrict__ csh_ptr, con
 }
 
 __global__ void __launch_bounds__(kNT) k_coarsest_solve(int nc, const double* __restrict__ Lc,
-                                                        const double* __restrict__ rc, double* __restrict__ uc) {
+                                                        const double* __restrict__ rc, double* __restrict__ uc,
+                                                        const int32_t* stop) {
   extern __shared__ double y[];
+  if (stop && *stop) return;
   for (int i = threadIdx.x; i < nc; i += kNT) y[i] = rc[i];
   __syncthreads();
   wg_trsv_lower(Lc, nc, nc, y);
@@ -132,6 +140,7 @@ __global__ void __launch_bounds__(kNT) k_coarsest_solve(int nc, const double* __
 // v = delta (a + Psi u_c)
 __global__ void __launch_bounds__(kNT) k_apply_prolong(LevelDev L, const double* __restrict__ uc) {
   extern __shared__ double sh[];
+  if (L.stop && *L.stop) return;
   const int s = blockIdx.x;
   const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
   const int ng = n - L.nint[s];
@@ -148,10 +157,12 @@ __global__ void __launch_bounds__(kNT) k_apply_prolong(LevelDev L, const double*
   }
 }
 
-// u_B = sum over sharers of v (owner writes); interior: u_I = L^{-T}(y - L_GI^T u_B)
+// u_B = sum over sharers of v (owner writes); kFS: interior u_I = L^{-T}(y - L_GI^T u_B)
+template <bool kFS>
 __global__ void __launch_bounds__(kNT) k_apply_post(LevelDev L, double* __restrict__ u,
-                                                    const int32_t* __restrict__ gam_map, int interior) {
+                                                    const int32_t* __restrict__ gam_map) {
   extern __shared__ double sh[];
+  if (L.stop && *L.stop) return;
   const int s = blockIdx.x;
   const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
   const int nI = L.nint[s];
@@ -168,7 +179,7 @@ __global__ void __launch_bounds__(kNT) k_apply_post(LevelDev L, double* __restri
     uB[a] = acc;
     if (L.sh_flat[L.sh_ptr[gi]] == f) u[gam_map[f]] = acc;
   }
-  if (!interior || nI == 0) return;
+  if (!kFS || nI == 0) return;
   __syncthreads();
   const double* A = L.K + L.koff[s];
   for (int j = tid; j < nI; j += kNT) {
@@ -186,6 +197,7 @@ __global__ void __launch_bounds__(kNT) k_apply_post(LevelDev L, double* __restri
 __global__ void __launch_bounds__(kNT) k_schur_local(LevelDev L, const double* __restrict__ p,
                                                      double* __restrict__ qloc) {
   extern __shared__ double sh[];
+  if (L.stop && *L.stop) return;
   const int s = blockIdx.x;
   const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
   const int nI = L.nint[s];
@@ -360,16 +372,22 @@ void launch_apply_pre(hipStream_t st, const LevelDev& L, int nImax, int ngmax, c
 void launch_apply_restrict(hipStream_t st, const LevelDev& L, int ngmax, const double* r,
                            const int32_t* gam_map, int use_t) {
   const size_t lds = sizeof(double) * ((size_t)ngmax + kNT + ngmax);
-  hipLaunchKernelGGL(k_apply_restrict, dim3(L.nsub), dim3(kNT), lds, st, L, r, gam_map, use_t);
+  if (use_t)
+    hipLaunchKernelGGL(k_apply_restrict<true>, dim3(L.nsub), dim3(kNT), lds, st, L, r, gam_map);
+  else
+    hipLaunchKernelGGL(k_apply_restrict<false>, dim3(L.nsub), dim3(kNT), lds, st, L, r, gam_map);
 }
 void launch_coarse_gather(hipStream_t st, int nc, const int32_t* csh_ptr, const int32_t* csh_flat,
-                          const double* b, double* rc) {
+                          const double* b, double* rc, const int32_t* stop) {
   if (nc == 0) return;
-  hipLaunchKernelGGL(k_coarse_gather, dim3(blocks_for(nc)), dim3(kNT), 0, st, nc, csh_ptr, csh_flat, b, rc);
+  hipLaunchKernelGGL(k_coarse_gather, dim3(blocks_for(nc)), dim3(kNT), 0, st, nc, csh_ptr, csh_flat, b, rc,
+                     stop);
 }
-void launch_coarsest_solve(hipStream_t st, int nc, const double* Lc, const double* rc, double* uc) {
+void launch_coarsest_solve(hipStream_t st, int nc, const double* Lc, const double* rc, double* uc,
+                           const int32_t* stop) {
   if (nc == 0) return;
-  hipLaunchKernelGGL(k_coarsest_solve, dim3(1), dim3(kNT), sizeof(double) * (size_t)nc, st, nc, Lc, rc, uc);
+  hipLaunchKernelGGL(k_coarsest_solve, dim3(1), dim3(kNT), sizeof(double) * (size_t)nc, st, nc, Lc, rc, uc,
+                     stop);
 }
 void launch_apply_prolong(hipStream_t st, const LevelDev& L, int ncsmax, const double* uc) {
   hipLaunchKernelGGL(k_apply_prolong, dim3(L.nsub), dim3(kNT), sizeof(double) * (size_t)(ncsmax + 1), st, L, uc);
@@ -377,7 +395,10 @@ void launch_apply_prolong(hipStream_t st, const LevelDev& L, int ncsmax, const d
 void launch_apply_post(hipStream_t st, const LevelDev& L, int nImax, int ngmax, double* u,
                        const int32_t* gam_map, int interior) {
   const size_t lds = sizeof(double) * ((size_t)ngmax + nImax + 1);
-  hipLaunchKernelGGL(k_apply_post, dim3(L.nsub), dim3(kNT), lds, st, L, u, gam_map, interior);
+  if (interior)
+    hipLaunchKernelGGL(k_apply_post<true>, dim3(L.nsub), dim3(kNT), lds, st, L, u, gam_map);
+  else
+    hipLaunchKernelGGL(k_apply_post<false>, dim3(L.nsub), dim3(kNT), lds, st, L, u, gam_map);
 }
 void launch_schur_local(hipStream_t st, const LevelDev& L, int ngmax, const double* p, double* qloc) {
   const size_t lds = sizeof(double) * ((size_t)ngmax + kNT + ngmax);

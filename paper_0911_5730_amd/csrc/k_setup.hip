@@ -21,7 +21,7 @@ __global__ void __launch_bounds__(kNT) k_assemble_l1(
     const int32_t* __restrict__ nint, const int32_t* __restrict__ node_el,
     const int32_t* __restrict__ sub_el_ptr, const int32_t* __restrict__ el_gid,
     const int32_t* __restrict__ el_loc, const double* __restrict__ coeff, Khat16 khat,
-    double* __restrict__ K, double* __restrict__ diagK, const int32_t* __restrict__ goff) {
+    double* __restrict__ K, double* __restrict__ diagK, const int32_t* __restrict__ goff, int* status) {
   const int s = blockIdx.x;
   const int base = loc_ptr[s];
   const int n = loc_ptr[s + 1] - base;
@@ -34,6 +34,7 @@ __global__ void __launch_bounds__(kNT) k_assemble_l1(
       if (code < 0) continue;
       const int le = code >> 2, pos = code & 3;
       const double kk = coeff[el_gid[e0 + le]];
+      if (!(kk > 0.0 && kk < 1e308)) atomicOr(status, 2);   // check of device-resident input
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int b = el_loc[(size_t)(e0 + le) * 4 + q];
@@ -352,9 +353,9 @@ __global__ void __launch_bounds__(kNT) k_coarsest_factor(int nsub, int nc, const
 void launch_assemble_l1(hipStream_t st, int nsub, const int64_t* koff, const int32_t* loc_ptr,
                         const int32_t* nint, const int32_t* node_el, const int32_t* sub_el_ptr,
                         const int32_t* el_gid, const int32_t* el_loc, const double* coeff,
-                        const Khat16& khat, double* K, double* diagK, const int32_t* goff) {
+                        const Khat16& khat, double* K, double* diagK, const int32_t* goff, int* status) {
   hipLaunchKernelGGL(k_assemble_l1, dim3(nsub), dim3(kNT), 0, st, koff, loc_ptr, nint, node_el,
-                     sub_el_ptr, el_gid, el_loc, coeff, khat, K, diagK, goff);
+                     sub_el_ptr, el_gid, el_loc, coeff, khat, K, diagK, goff, status);
 }
 
 void launch_assemble_coarse(hipStream_t st, int nsub, const int64_t* koff, const int32_t* loc_ptr,

@@ -42,6 +42,7 @@ struct LevelDev {
   double* a = nullptr;                // scratch: interface flat
   double* v = nullptr;                // scratch: interface flat
   double* b = nullptr;                // scratch: local coarse flat
+  const int32_t* stop = nullptr;      // when non-null and *stop != 0 the apply kernels return at once
 };
 
 constexpr int kMaxHist = 4096;
@@ -57,7 +58,7 @@ struct PcgScalars {
 void launch_assemble_l1(hipStream_t st, int nsub, const int64_t* koff, const int32_t* loc_ptr,
                         const int32_t* nint, const int32_t* node_el, const int32_t* sub_el_ptr,
                         const int32_t* el_gid, const int32_t* el_loc, const double* coeff,
-                        const Khat16& khat, double* K, double* diagK, const int32_t* goff);
+                        const Khat16& khat, double* K, double* diagK, const int32_t* goff, int* status);
 void launch_assemble_coarse(hipStream_t st, int nsub, const int64_t* koff, const int32_t* loc_ptr,
                             const int32_t* nint, const int32_t* child_ptr, const int32_t* child_id,
                             const int32_t* child_map_off, const int32_t* child_map, const double* Ac,
@@ -104,8 +105,9 @@ void launch_apply_pre(hipStream_t st, const LevelDev& L, int nImax, int ngmax, c
 void launch_apply_restrict(hipStream_t st, const LevelDev& L, int ngmax, const double* r,
                            const int32_t* gam_map, int use_t);
 void launch_coarse_gather(hipStream_t st, int nc, const int32_t* csh_ptr, const int32_t* csh_flat,
-                          const double* b, double* rc);
-void launch_coarsest_solve(hipStream_t st, int nc, const double* Lc, const double* rc, double* uc);
+                          const double* b, double* rc, const int32_t* stop);
+void launch_coarsest_solve(hipStream_t st, int nc, const double* Lc, const double* rc, double* uc,
+                           const int32_t* stop);
 void launch_apply_prolong(hipStream_t st, const LevelDev& L, int ncsmax, const double* uc);
 void launch_apply_post(hipStream_t st, const LevelDev& L, int nImax, int ngmax, double* u,
                        const int32_t* gam_map, int interior);

@@ -1,0 +1,85 @@
+"""Shared helpers of the GPU parity tests (test infrastructure)."""
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse.linalg as spla
+
+from oracle import pcg
+from oracle.bddc import BDDC
+
+
+def cuda_vec(x):
+    import torch
+    return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+TIGHT = 1e-10     # PCG tolerance at which the 1e-10 energy-norm bar is applied
+LAM_RTOL = 1e-7   # relative eigenvalue tolerance of the pair eigenproblems
+
+
+def run_pair(prob, rtol=1e-8, maxit=1000, oracle=None):
+    """Solve the same problem with the GPU library and the oracle."""
+    import paper_0911_5730_amd as P
+    B = oracle or BDDC(prob)
+    S = P.Solver(prob)
+    f = cuda_vec(prob.f[0])
+    u, it, rr = S.solve(f, rtol=rtol, maxit=maxit)
+    o = pcg.solve(B, prob.f[0], rtol=rtol, maxit=maxit)
+    return S, B, u.cpu().numpy(), it[0], rr[0], o
+
+
+def check_solution(S, B, ug, o, rtol=1e-8):
+    """Parity of the solutions.
+
+    At the production tolerance the iterates still carry an error of about
+    rtol * sqrt(cond) against the exact solution, and rounding-level changes
+    of either side move them by a fraction of it (measured on the oracle by
+    perturbing its own preconditioner output by 1e-15): there the difference
+    must stay below half the oracle's own error.  The 1e-10 energy-norm bar is
+    applied to both sides converged to rtol = 1e-10, with iteration counts
+    within +-1."""
+    A = B.A
+    f = B.prob.f[0]
+    r = A @ ug - f
+    assert np.linalg.norm(r) <= 2 * rtol * np.linalg.norm(f) + 1e-300
+    xs = direct(B)
+    e_or = pcg.energy_error(A, o["x"], xs)
+    e = pcg.energy_error(A, ug, o["x"])
+    assert e <= max(1e-10, 0.5 * e_or), f"difference {e:.3e} vs oracle error {e_or:.3e}"
+    ut, it, _ = S.solve(cuda_vec(f), rtol=TIGHT)
+    ot = pcg.solve(B, f, rtol=TIGHT)
+    assert abs(it[0] - ot["iters"]) <= 1, (it[0], ot["iters"])
+    et = pcg.energy_error(A, ut.cpu().numpy(), ot["x"])
+    assert et <= 1e-10, f"energy-norm difference at rtol {TIGHT}: {et:.3e}"
+
+
+def check_adaptive_edges(S, B, tau, levels_to_span=(1,)):
+    """Per-edge eigenvalues, selection counts and constraint spans against the oracle."""
+    for li, lv in enumerate(B.levels):
+        lam_o = B.eigs[li]
+        keys = list(lv.topo.edges.keys())
+        for e, key in enumerate(keys):
+            lam_g, nsel_g, pair = S.edge_eigs(li + 1, e)
+            assert tuple(pair) == key
+            lo = lam_o[key]
+            assert len(lam_g) == len(lo)
+            # FP64 roundoff times the pencil's condition (k contrast up to 1e6 times (H/h)^2)
+            scale = max(1.0, float(lo[0]))
+            tol = LAM_RTOL * np.maximum(1.0, np.abs(lo)) + 1e-10 * scale
+            assert np.all(np.abs(lam_g - lo) <= tol), (li, key, lam_g[:4], lo[:4])
+            near = np.any(np.abs(lo - tau) <= 1e-8 * max(1.0, tau))
+            if not near:
+                assert nsel_g == int(np.sum(lo > tau)), (li, key)
+            if (li + 1) in levels_to_span and not near:
+                dofs, Qg = S.edge_constraints(li + 1, e)
+                assert np.array_equal(dofs, lv.topo.edges[key])
+                Qo = B.edge_Q[li][key]
+                assert Qg.shape[1] == Qo.shape[1]
+                if Qo.shape[1]:
+                    assert np.allclose(Qg.T @ Qg, np.eye(Qg.shape[1]), atol=1e-10)
+                    ang = sla.subspace_angles(Qg, Qo)
+                    assert np.max(ang) < 1e-6, (li, key, np.max(ang))
+
+
+def direct(B):
+    return spla.spsolve(B.A.tocsc(), B.prob.f[0])

@@ -1,0 +1,112 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every
+symbol the header declares, validates its inputs, and its host topology
+agrees exactly with the oracle's classification."""
+
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import fem
+from oracle.topology import classify
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bddc.h")
+
+P = pytest.importorskip("paper_0911_5730_amd")
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const char\*|void|bddc_status)\s+(bddc_\w+)\s*\(", text, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    import ctypes
+    lib = P.load_library()
+    names = _declared()
+    assert len(names) >= 9
+    for n in names:
+        assert hasattr(lib, n), n
+    assert isinstance(ctypes.CDLL(P.bddc.LIB_PATH).bddc_status_string, object)
+
+
+def test_status_strings():
+    for code in (0, -1, -2, -3, -4, -5, -6, -7, -8):
+        assert P.status_string(code) != "unknown status"
+    assert P.status_string(-99) == "unknown status"
+
+
+def _oracle_counts(prob):
+    dofs = fem.element_dofs(prob.nx, prob.ny)
+    elems = [(d[d >= 0], None) for d in dofs]
+    touches = (dofs < 0).any(axis=1)
+    top = classify(prob.n_free, elems, prob.part, prob.nsub, ~touches)
+    return dict(n_interface=int((~top.interior).sum()), n_corners=len(top.corners),
+                n_edges=len(top.edges))
+
+
+@pytest.mark.parametrize("case", [
+    dict(nx=32, nsx=4),
+    dict(nx=18, nsx=4),                       # ragged blocks
+    dict(nx=20, ny=12, nsx=5, nsy=3),         # rectangular mesh and partition
+    dict(nx=256, nsx=16),                     # config-2 partition
+    dict(nx=12, nsx=1),                       # a single substructure
+])
+def test_plan_topology_matches_oracle(case):
+    prob = synth.square_problem(case["nx"], case["nsx"], ny=case.get("ny"), nsy=case.get("nsy"))
+    got = P.plan(prob)
+    want = _oracle_counts(prob)
+    assert got["n_free"] == prob.n_free
+    for k, v in want.items():
+        assert got[k] == v, (k, got[k], v)
+
+
+def test_plan_promotes_corner_for_island():
+    nx = 12
+    prob = synth.square_problem(nx, 1)
+    part = np.zeros((nx, nx), dtype=np.int32)
+    part[3:9, 3:9] = 1
+    prob.part = part.reshape(-1)
+    prob.nsub = 2
+    got = P.plan(prob)
+    want = _oracle_counts(prob)
+    assert got["n_corners"] == want["n_corners"] == 1
+    assert got["n_edges"] == want["n_edges"] == 1
+
+
+def _expect(code, prob, **kw):
+    with pytest.raises(P.BDDCError) as ei:
+        P.plan(prob, **kw)
+    assert ei.value.name == code
+
+
+def test_validation_errors():
+    base = synth.config(1)
+    bad = synth.config(1)
+    bad.coeff = bad.coeff.copy()
+    bad.coeff[5] = 0.0
+    _expect("BDDC_EINVAL", bad)
+    bad.coeff[5] = np.nan
+    _expect("BDDC_EINVAL", bad)
+    bad = synth.config(1)
+    bad.part = bad.part.copy()
+    bad.part[0] = 16
+    _expect("BDDC_EPARTITION", bad)
+    bad = synth.config(1)
+    bad.nsub = 17                                       # substructure 16 owns nothing
+    _expect("BDDC_EPARTITION", bad)
+    bad = synth.config(1)
+    bad.levels = 1
+    _expect("BDDC_EINVAL", bad)
+    bad = synth.config(1)
+    bad.levels = 3
+    bad.agglom = []
+    _expect("BDDC_EINVAL", bad)
+    _expect("BDDC_EUNSUPPORTED", base, precision="fp32")
+    bad = synth.config(1)
+    bad.nx = 1
+    _expect("BDDC_EINVAL", bad)
+    assert P.plan(base)["n_corners"] == 9

@@ -1,0 +1,90 @@
+"""GPU parity at the workload sizes.
+
+* 256 x 256, 16 x 16 substructures, three levels, adaptive tau = 10 with
+  coefficient jumps up to 1e6 and channels: the whole oracle runs (about a
+  minute on the host) and every edge's eigenvalues, selection and the solve
+  are compared.
+* 1024 x 1024, 64 x 64 substructures, three levels, k = 1: too large for the
+  oracle's setup, so the checks are properties that hold at any size (true
+  residual, symmetry of the preconditioner) and the interior-edge pair
+  eigenvalues, which for k = 1 coincide with those of the same floating pair
+  in a 4 x 4 partition that the oracle solves.
+"""
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg  # noqa: F401
+
+import synth
+from gpu_common import check_adaptive_edges, check_solution, cuda_vec, run_pair
+from oracle import adaptive, fem
+from oracle.bddc import BDDC
+
+pytestmark = pytest.mark.gpu
+
+
+def test_config2_full_parity():
+    prob = synth.config(2)
+    print("config2: oracle setup (about a minute)", flush=True)
+    S, B, ug, it, rr, o = run_pair(prob)
+    try:
+        print("config2 iters gpu", it, "oracle", o["iters"], flush=True)
+        assert abs(it - o["iters"]) <= 1
+        info = S.info()
+        check_solution(S, B, ug, o)
+        assert info["nc"] == B.nc_per_level()
+        check_adaptive_edges(S, B, prob.tau)
+        assert abs(info["indicator"] - B.indicator) <= 1e-7 * B.indicator
+        assert B.indicator <= prob.tau ** (prob.levels - 1)
+    finally:
+        S.close()
+
+
+def test_config3_properties_and_sampled_edges():
+    import paper_0911_5730_amd as P
+    prob = synth.config(3)
+    print("config3: GPU setup + solve", flush=True)
+    with P.Solver(prob) as S:
+        f = cuda_vec(prob.f[0])
+        u, it, rr = S.solve(f)
+        info = S.info()
+        ug = u.cpu().numpy()
+        A = fem.assemble(prob.nx, prob.ny, prob.coeff)
+        res = np.linalg.norm(A @ ug - prob.f[0]) / np.linalg.norm(prob.f[0])
+        print("config3 iters", it, "relres", rr, "true", res, "nc", info["nc"], flush=True)
+        assert rr[0] <= 1e-8 and res <= 2e-8
+        assert info["indicator"] <= prob.tau ** 2
+        # symmetry of the three-level preconditioner
+        rng = np.random.default_rng(9)
+        r, s = rng.standard_normal((2, prob.n_free))
+        a = s @ S.apply(cuda_vec(r)).cpu().numpy()
+        b = r @ S.apply(cuda_vec(s)).cpu().numpy()
+        assert abs(a - b) <= 1e-11 * max(abs(a), abs(b))
+        # interior floating pair vs the oracle on a 4 x 4 partition with H/h = 16
+        small = synth.square_problem(64, 4, constraints="adaptive", tau=10.0, kmode="one", seed=1)
+        lv = BDDC(small).levels[0]
+        lam_o = adaptive.pair_eig_full(lv, 5, 6)[0][:15]
+        ns = 64
+        for (bi, bj) in [(10, 20), (31, 31), (50, 7)]:
+            s_id = bj * ns + bi
+            key = (s_id, s_id + 1)
+            e = _edge_index(S, key)
+            lam_g, nsel, pair = S.edge_eigs(1, e)
+            assert tuple(pair) == key
+            assert np.allclose(lam_g, lam_o, atol=1e-9 * lam_o[0])
+            assert nsel == int(np.sum(lam_o > prob.tau))
+
+
+def _edge_index(S, key):
+    # edges are numbered in increasing (s, t) order; binary search through the ABI
+    lo, hi = 0, S.info()["n_edges"][0] - 1
+    while lo <= hi:
+        mid = (lo + hi) // 2
+        pair = S.edge_eigs(1, mid)[2]
+        if pair == key:
+            return mid
+        if pair < key:
+            lo = mid + 1
+        else:
+            hi = mid - 1
+    raise KeyError(key)

@@ -1,0 +1,106 @@
+"""GPU edge cases through the C ABI: non-convergence, zero load, several
+right-hand sides, reproducibility, symmetry and argument checks."""
+
+import ctypes
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_common import cuda_vec
+
+pytestmark = pytest.mark.gpu
+
+
+def _solver(prob):
+    import paper_0911_5730_amd as P
+    return P.Solver(prob)
+
+
+def test_maxit_reports_noconv_with_last_iterate():
+    import paper_0911_5730_amd as P
+    prob = synth.square_problem(32, 4, constraints="corners", kmode="loguniform", kmax_exp=3, seed=31)
+    with _solver(prob) as S:
+        f = cuda_vec(prob.f[0])
+        with pytest.raises(P.BDDCError) as ei:
+            S.solve(f, maxit=2)
+        assert ei.value.name == "BDDC_ENOCONV"
+        u, it, rr = S.solve(f, maxit=2, allow_noconv=True)
+        assert it == [2] and rr[0] > 1e-8
+        assert np.isfinite(u.cpu().numpy()).all()
+
+
+def test_zero_load_gives_zero_solution():
+    prob = synth.square_problem(16, 4, constraints="corners_edges", seed=32)
+    with _solver(prob) as S:
+        u, it, rr = S.solve(cuda_vec(np.zeros(prob.n_free)))
+        assert it == [0] and rr == [0.0]
+        assert not u.cpu().numpy().any()
+
+
+def test_several_rhs_equal_separate_solves_bitwise():
+    import torch
+    prob = synth.square_problem(48, 4, levels=3, groups=(2, 2), constraints="adaptive", tau=3.0,
+                                kmode="loguniform", kmax_exp=3, nrhs=3, seed=33)
+    with _solver(prob) as S:
+        F = cuda_vec(prob.f)
+        U, its, rrs = S.solve(F)
+        for c in range(3):
+            u, it, rr = S.solve(F[c].contiguous())
+            assert it[0] == its[c]
+            assert torch.equal(u, U[c])
+
+
+def test_repeated_setup_and_solve_are_bitwise_reproducible():
+    import torch
+    prob = synth.square_problem(64, 8, levels=3, groups=(2, 2), constraints="adaptive", tau=2.0,
+                                kmode="loguniform", kmax_exp=4, channels=2, seed=34)
+    f = cuda_vec(prob.f[0])
+    outs = []
+    for _ in range(2):
+        with _solver(prob) as S:
+            outs.append(S.solve(f)[0])
+    assert torch.equal(outs[0], outs[1])
+
+
+def test_preconditioner_is_symmetric():
+    prob = synth.square_problem(48, 6, levels=3, groups=(3, 3), constraints="adaptive", tau=2.0,
+                                kmode="loguniform", kmax_exp=5, channels=2, seed=35)
+    rng = np.random.default_rng(0)
+    r, s = rng.standard_normal((2, prob.n_free))
+    with _solver(prob) as S:
+        Mr = S.apply(cuda_vec(r)).cpu().numpy()
+        Ms = S.apply(cuda_vec(s)).cpu().numpy()
+    a, b = s @ Mr, r @ Ms
+    assert abs(a - b) <= 1e-12 * max(abs(a), abs(b))
+
+
+def test_smallest_mesh():
+    prob = synth.square_problem(2, 1, seed=36)          # one free node
+    with _solver(prob) as S:
+        u, it, rr = S.solve(cuda_vec(prob.f[0]))
+        assert abs(u.cpu().numpy()[0] - prob.f[0][0] / (8.0 / 3.0)) < 1e-14
+
+
+def test_device_argument_validation():
+    import paper_0911_5730_amd as P
+    prob = synth.config(1)
+    with _solver(prob) as S:
+        lib = S.lib
+        r = cuda_vec(np.ones(prob.n_free))
+        z = cuda_vec(np.zeros(prob.n_free))
+        st = lib.bddc_apply(S.h, ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(z.data_ptr()), 1,
+                            prob.n_free - 1, None)
+        assert st == -1
+        st = lib.bddc_apply(S.h, ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(r.data_ptr()), 1,
+                            prob.n_free, None)
+        assert st == -1
+        iters = (ctypes.c_int32 * 1)()
+        rel = (ctypes.c_double * 1)()
+        st = lib.bddc_solve(S.h, ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(z.data_ptr()), 1,
+                            prob.n_free, -1.0, 10, iters, rel, None)
+        assert st == -1
+        with pytest.raises(P.BDDCError):
+            S.edge_eigs(1, 0)                            # not an adaptive set-up
+        assert lib.bddc_query(None, None) == -1
+    lib.bddc_destroy(None)
