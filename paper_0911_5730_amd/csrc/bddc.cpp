@@ -212,7 +212,10 @@ struct Level {
     double *Cr, *T, *Psi, *Ac, *cwork, *znext;
     // scratch
     double *y, *t, *a, *v, *b, *rc, *uc, *qloc;
+    double* Linv;
+    int64_t* linvoff;
   } d{};
+  std::vector<int64_t> linvoff;
   LevelDev dev;
 };
 
@@ -233,6 +236,10 @@ struct bddc_ctx {
   bddc::PcgScalars* sc = nullptr;
   bddc::PcgScalars* sc_host = nullptr;   // pinned
   int nblk = 1;
+  bddc::PcgDev pcg;
+  // deep levels (2 .. L-1) and the coarsest solve in one workgroup when small
+  bool fused_deep = false;
+  bddc::DeepArgs deep;
   bddc_info info{};
 };
 
@@ -620,6 +627,9 @@ class Builder {
     }
     std::vector<int32_t> edge_ptr(T.edge_ptr), edge_dof(T.edge_dof);
     std::vector<uint8_t> floating(T.floating);
+    lv.linvoff.assign(nsub + 1, 0);
+    if (prev)
+      for (int s = 0; s < nsub; ++s) lv.linvoff[s + 1] = lv.linvoff[s] + (int64_t)T.n_int[s] * T.n_int[s];
 
     Arena& A = lv.arena_a;
     auto& d = lv.d;
@@ -682,6 +692,8 @@ class Builder {
       d.a = A.take<double>(lv.nflat_g);
       d.v = A.take<double>(lv.nflat_g);
       d.qloc = A.take<double>(lv.nflat_g);
+      d.Linv = A.take<double>((size_t)lv.linvoff[nsub]);
+      d.linvoff = A.take<int64_t>(nsub + 1);
     };
     A.reset_sizing();
     layout(false);
@@ -733,6 +745,7 @@ class Builder {
     h2d(d.eig_woff, lv.eig_woff, st_);
     h2d(d.lamoff, lv.lamoff, st_);
     h2d(d.qoff, lv.qoff, st_);
+    h2d(d.linvoff, lv.linvoff, st_);
     if (prev) {
       // the constant's coarse values, computed on the previous level
       BDDC_HIP(hipMemcpyAsync(d.z, prev->d.znext, sizeof(double) * lv.n, hipMemcpyDeviceToDevice, st_));
@@ -774,6 +787,7 @@ class Builder {
       timing::Scope ts(lv.ell == 1 ? "partial_chol" : "partial_chol_l2", st_, by, fl);
       launch_partial_chol(st_, lv.nsub, lv.nmax, d.koff, d.loc_ptr, d.nint, d.K, h_->status);
     }
+    if (lv.ell >= 2) launch_tri_inverse(st_, lv.nsub, d.koff, d.loc_ptr, d.nint, d.K, d.Linv, d.linvoff);
     const int ne_tot = lv.nedge;
     lv.edge_m.assign(ne_tot, 0);
     lv.edge_nsel.assign(ne_tot, 0);
@@ -966,6 +980,10 @@ class Builder {
     D.toff = d.toff;
     D.Psi = d.Psi;
     D.psioff = d.psioff;
+    D.Linv = d.Linv;
+    D.linvoff = d.linvoff;
+    D.csh_ptr = d.csh_ptr;
+    D.csh_flat = d.csh_flat;
     D.y = d.y;
     D.t = d.t;
     D.a = d.a;
@@ -982,34 +1000,114 @@ class Builder {
 };
 
 // ---------------------------------------------------------------------------
-// apply: Algorithm "Multilevel BDDC" from level li down and back up
-static void apply_level(bddc_ctx* h, int li, const double* r, double* u, bool interface_only) {
+// apply: Algorithm "Multilevel BDDC"
+//
+// Levels >= 2 run in full space with the explicit inverse of their interior
+// factors; level 1 runs in full space for bddc_apply and on the interface
+// inside bddc_solve.
+static void apply_deep_level(bddc_ctx* h, int li, const double* r, double* u) {
   Level& lv = *h->levels[li];
   hipStream_t st = h->stream;
-  const bool interior = !interface_only;
-  const int32_t* gmap = interface_only ? lv.d.gam_iid : lv.d.gam_gid;
-  const std::string sfx = li == 0 ? "" : "_l" + std::to_string(li + 1);
-  if (interior) {
+  const std::string sfx = "_l" + std::to_string(li + 1);
+  {
     timing::Scope ts(("apply_pre" + sfx).c_str(), st, lv.by_pre, 0);
-    launch_apply_pre(st, lv.dev, lv.nImax, lv.ngmax, r);
+    launch_apply_pre_inv(st, lv.dev, lv.nImax, lv.ngmax, r);
   }
   {
-    timing::Scope ts(("apply_restrict" + sfx).c_str(), st, interior ? lv.by_restrict_fs : lv.by_restrict_ir, 0);
-    launch_apply_restrict(st, lv.dev, lv.ngmax, r, gmap, interior ? 1 : 0);
+    timing::Scope ts(("apply_restrict" + sfx).c_str(), st, lv.by_restrict_fs, 0);
+    launch_apply_restrict(st, lv.dev, lv.ngmax, r, lv.d.gam_gid, 1);
   }
   launch_coarse_gather(st, lv.nc, lv.d.csh_ptr, lv.d.csh_flat, lv.d.b, lv.d.rc, lv.dev.stop);
   if (li + 1 == (int)h->levels.size())
     launch_coarsest_solve(st, lv.nc, h->AL, lv.d.rc, lv.d.uc, lv.dev.stop);
   else
-    apply_level(h, li + 1, lv.d.rc, lv.d.uc, false);
+    apply_deep_level(h, li + 1, lv.d.rc, lv.d.uc);
   {
     timing::Scope ts(("apply_prolong" + sfx).c_str(), st, lv.by_prolong, 0);
     launch_apply_prolong(st, lv.dev, lv.ncsmax, lv.d.uc);
   }
   {
-    timing::Scope ts(("apply_post" + sfx).c_str(), st, interior ? lv.by_post_fs : lv.by_post_ir, 0);
-    launch_apply_post(st, lv.dev, lv.nImax, lv.ngmax, u, gmap, interior ? 1 : 0);
+    timing::Scope ts(("apply_post" + sfx).c_str(), st, lv.by_post_fs, 0);
+    launch_apply_post_inv(st, lv.dev, lv.nImax, lv.ngmax, u);
   }
+}
+
+// level-1 coarse right-hand side (the level-1 b) -> level-1 coarse solution (level-1 uc)
+static void run_deep(bddc_ctx* h) {
+  Level& l1 = *h->levels[0];
+  hipStream_t st = h->stream;
+  if (h->levels.size() == 1) {
+    launch_coarse_gather(st, l1.nc, l1.d.csh_ptr, l1.d.csh_flat, l1.d.b, l1.d.rc, l1.dev.stop);
+    launch_coarsest_solve(st, l1.nc, h->AL, l1.d.rc, l1.d.uc, l1.dev.stop);
+    return;
+  }
+  if (h->fused_deep) {
+    DeepArgs A = h->deep;
+    A.stop = l1.dev.stop;
+    timing::Scope ts("deep", st, 0, 0);
+    launch_deep(st, A);
+    return;
+  }
+  launch_coarse_gather(st, l1.nc, l1.d.csh_ptr, l1.d.csh_flat, l1.d.b, l1.d.rc, l1.dev.stop);
+  apply_deep_level(h, 1, l1.d.rc, l1.d.uc);
+}
+
+// full-space preconditioner of the level-1 problem (bddc_apply)
+static void apply_full(bddc_ctx* h, const double* r, double* u) {
+  Level& l1 = *h->levels[0];
+  hipStream_t st = h->stream;
+  launch_apply_pre(st, l1.dev, l1.nImax, l1.ngmax, r);
+  launch_apply_restrict(st, l1.dev, l1.ngmax, r, l1.d.gam_gid, 1);
+  run_deep(h);
+  launch_apply_prolong(st, l1.dev, l1.ncsmax, l1.d.uc);
+  launch_apply_post(st, l1.dev, l1.nImax, l1.ngmax, u, l1.d.gam_gid, 1);
+}
+
+// decide whether the deep levels fit one workgroup and fill the fused-kernel arguments
+static void plan_deep(bddc_ctx* h) {
+  h->fused_deep = false;
+  const int L = (int)h->levels.size();
+  if (L < 2 || L - 1 > kMaxDeep) return;
+  const char* env = getenv("BDDC_DEEP_PATH");
+  if (env && std::string(env) == "levels") return;
+  double bytes = 0;
+  int wstride = 1;
+  for (int li = 1; li < L; ++li) {
+    const Level& lv = *h->levels[li];
+    const Topology& T = lv.topo;
+    for (int s = 0; s < lv.nsub; ++s) {
+      const double nI = T.n_int[s], ng = T.ngam(s), nr = T.n_r[s], ncs = lv.coff[s + 1] - lv.coff[s];
+      bytes += 8 * (nI * nI + ng * nI + nr * nr + 2 * ng * ncs);
+    }
+    wstride = std::max({wstride, 2 * lv.nImax, lv.ngmax + lv.nImax, lv.ncsmax, lv.ngmax});
+  }
+  const int ncL = h->levels.back()->nc;
+  const bool forced = env && std::string(env) == "fused";
+  if (!forced && bytes > 4.0e6) return;
+  if (deep_lds(wstride, ncL) > kLdsLimit) return;
+  DeepArgs& A = h->deep;
+  A = DeepArgs{};
+  A.nlev = L - 1;
+  for (int dl = 0; dl < A.nlev; ++dl) {
+    Level& lv = *h->levels[dl + 1];
+    Level& up = *h->levels[dl];
+    A.lv[dl] = lv.dev;
+    A.lv[dl].stop = nullptr;
+    A.rvec[dl] = up.d.rc;
+    A.uvec[dl] = up.d.uc;
+    A.nvec[dl] = up.nc;
+  }
+  A.rc_last = h->levels.back()->d.rc;
+  A.uc_last = h->levels.back()->d.uc;
+  A.ncL = ncL;
+  A.LL = h->AL;
+  Level& l1 = *h->levels[0];
+  A.n2 = l1.nc;
+  A.csh_ptr1 = l1.d.csh_ptr;
+  A.csh_flat1 = l1.d.csh_flat;
+  A.b1 = l1.d.b;
+  A.wstride = wstride;
+  h->fused_deep = true;
 }
 
 // symmetric tridiagonal extreme eigenvalues by Sturm bisection
@@ -1068,14 +1166,8 @@ static int pcg_one(bddc_ctx* h, const double* f, double* u, double rtol, int max
   launch_condense(st, nif, l1.d.sh_ptr, l1.d.sh_flat, l1.d.iface_dof, f, l1.d.t, h->r, h->x);
   launch_dot_partial(st, nb, nif, h->r, h->r, h->partial);
   launch_scalar(st, 5, nb, h->partial, h->sc);                    // rr0, done if already small
-  const size_t tmark = timing::mark();
-  timing::current_tag = 0;
-  apply_level(h, 0, h->r, h->zv, true);
-  timing::current_tag = -1;
-  launch_dot_partial(st, nb, nif, h->r, h->zv, h->partial);
-  launch_scalar(st, 3, nb, h->partial, h->sc);                    // rz
-  launch_update_p(st, nb, nif, h->sc, h->zv, h->p, 1);
-  // apply kernels inside the loop return at once after convergence
+
+  // every kernel below returns at once after convergence
   struct StopGuard {
     bddc_ctx* h;
     ~StopGuard() {
@@ -1084,37 +1176,53 @@ static int pcg_one(bddc_ctx* h, const double* f, double* u, double rtol, int max
     }
   } guard_stop{h};
   for (auto& lvp : h->levels) lvp->dev.stop = &h->sc->done;
+  const PcgDev& P = h->pcg;
+  const size_t tmark = timing::mark();
+
+  // z_0 = M r_0 and its r.z partials (parity 0)
+  auto apply_iface = [&](int it) {
+    timing::current_tag = it;
+    {
+      timing::Scope ts("apply_restrict", st, l1.by_restrict_ir, 0);
+      launch_pcg_restrict(st, l1.dev, l1.ngmax, P, it > 0 ? 1 : 0);
+    }
+    run_deep(h);
+    {
+      timing::Scope ts("apply_prolong", st, l1.by_prolong, 0);
+      launch_apply_prolong(st, l1.dev, l1.ncsmax, l1.d.uc);
+    }
+    {
+      timing::Scope ts("apply_post", st, l1.by_post_ir, 0);
+      launch_pcg_post(st, l1.dev, l1.ngmax, P, it & 1);
+    }
+  };
+  apply_iface(0);
   int it = 0;
-  int check = 4;
+  int check = 8;
   while (it < maxit) {
-    for (int k = 0; k < check && it < maxit; ++k, ++it) {
-      timing::current_tag = it + 1;
+    for (int k = 0; k < check && it < maxit; ++k) {
+      ++it;
+      timing::current_tag = it;
       {
         // the product of iteration k works iff k <= K (K = converged iteration)
         timing::Scope ts("schur_local", st, l1.by_schur, 0, -1);
-        launch_schur_local(st, l1.dev, l1.ngmax, h->p, l1.d.qloc);
+        launch_pcg_matvec(st, l1.dev, l1.ngmax, P, it);
       }
-      launch_gather_dot(st, nb, nif, l1.d.sh_ptr, l1.d.sh_flat, l1.d.qloc, h->p, h->q, h->partial);
-      launch_scalar(st, 0, nb, h->partial, h->sc);                // alpha
-      launch_update_xr(st, nb, nif, h->sc, h->p, h->q, h->x, h->r, h->partial);
-      launch_scalar(st, 1, nb, h->partial, h->sc);                // rr, convergence
-      apply_level(h, 0, h->r, h->zv, true);
-      launch_dot_partial(st, nb, nif, h->r, h->zv, h->partial);
-      launch_scalar(st, 2, nb, h->partial, h->sc);                // beta
-      launch_update_p(st, nb, nif, h->sc, h->zv, h->p, 0);
+      launch_pcg_gather_dot(st, l1.dev, P, it);
+      launch_pcg_update(st, P, it);
+      apply_iface(it);
     }
     BDDC_HIP(hipMemcpyAsync(sch, h->sc, offsetof(PcgScalars, alphas), hipMemcpyDeviceToHost, st));
     BDDC_HIP(hipStreamSynchronize(st));
     if (sch->done) break;
-    check = std::min(8, check * 2);
   }
   timing::current_tag = -1;
   launch_recover(st, l1.dev, l1.nImax, l1.ngmax, h->x, u);
   BDDC_HIP(hipMemcpyAsync(sch, h->sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, st));
   BDDC_HIP(hipStreamSynchronize(st));
   const int iters = sch->iters;
-  // the apply of iteration k (tag k) works iff k < K; the product of iteration k (tag k-1) iff k <= K
-  timing::prune(tmark, sch->done == 1 ? iters : iters + 1);
+  // launches of iteration k work iff k < K (the product: k <= K, tagged k-1)
+  timing::prune(tmark, iters);
   *relres = sch->bb > 0 ? std::sqrt(sch->rr / sch->bb) : 0.0;
   std::vector<double> al(sch->alphas, sch->alphas + std::min(iters, kMaxHist));
   std::vector<double> be(sch->betas, sch->betas + std::max(0, std::min(iters, kMaxHist) - 1));
@@ -1259,19 +1367,36 @@ bddc_status bddc_setup(const bddc_problem* p, void* hip_stream, bddc_handle* out
     const int nif = (int)l1.iface_dof.size();
     h->nblk = std::min(256, std::max(1, (nif + kNT - 1) / kNT));
     Arena& B = h->levels[0]->arena_pcg;
+    PcgDev& P = h->pcg;
     auto lay = [&] {
       h->x = B.take<double>(nif);
       h->r = B.take<double>(nif);
       h->p = B.take<double>(nif);
+      P.p[1] = B.take<double>(nif);
       h->zv = B.take<double>(nif);
       h->q = B.take<double>(nif);
       h->partial = B.take<double>(1024);
+      P.pq_part = B.take<double>(h->nblk);
+      P.rr_part = B.take<double>(h->nblk);
+      P.rz_part[0] = B.take<double>(l1.nsub);
+      P.rz_part[1] = B.take<double>(l1.nsub);
       h->sc = B.take<PcgScalars>(1);
     };
     B.reset_sizing();
     lay();
     B.allocate(h->stream);
     lay();
+    P.sc = h->sc;
+    P.x = h->x;
+    P.r = h->r;
+    P.z = h->zv;
+    P.q = h->q;
+    P.p[0] = h->p;
+    P.qloc = l1.d.qloc;
+    P.nif = nif;
+    P.nblk = h->nblk;
+    P.nsub1 = l1.nsub;
+    plan_deep(h);
     BDDC_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->sc_host), sizeof(PcgScalars), hipHostMallocDefault));
     BDDC_HIP(hipStreamSynchronize(h->stream));
     // info
@@ -1304,7 +1429,7 @@ bddc_status bddc_apply(bddc_handle h, const double* r, double* z, int32_t nrhs, 
     if (r == z) fail(BDDC_EINVAL, "r and z must not alias");
     hipStream_t saved = h->stream;
     h->stream = reinterpret_cast<hipStream_t>(hip_stream);
-    for (int c = 0; c < nrhs; ++c) apply_level(h, 0, r + (size_t)c * ld, z + (size_t)c * ld, false);
+    for (int c = 0; c < nrhs; ++c) apply_full(h, r + (size_t)c * ld, z + (size_t)c * ld);
     h->stream = saved;
   });
 }

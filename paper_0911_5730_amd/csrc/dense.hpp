@@ -98,6 +98,25 @@ __device__ inline void wg_gemm(bool ta, bool tb, int m, int n, int k, double alp
   __syncthreads();
 }
 
+// sum over j = j0, j0+step, ... < n of A[j*lda] * x[j], with eight independent
+// partial sums so that eight loads of A are in flight per thread (the small
+// kernels here are bound by memory latency, not bandwidth).
+__device__ inline double dot_strided(const double* __restrict__ A, size_t lda, const double* __restrict__ x,
+                                     int j0, int n, int step) {
+  double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int j = j0;
+  for (; j + 7 * step < n; j += 8 * step) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = A[(size_t)(j + u * step) * lda];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] += v[u] * x[j + u * step];
+  }
+  double rest = 0.0;
+  for (; j < n; j += step) rest += A[(size_t)j * lda] * x[j];
+  return (((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]))) + rest;
+}
+
 // Sum of one value per thread, returned to every thread (red: kNT doubles of LDS).
 __device__ inline double wg_sum(double v, double* red) {
   const int tid = threadIdx.x;

@@ -89,9 +89,7 @@ __global__ void __launch_bounds__(kNT) k_apply_restrict(LevelDev L, const double
     const int nch = max(1, kNT / n_r);
     for (int idx = tid; idx < n_r * nch; idx += kNT) {
       const int i = idx % n_r, c = idx / n_r;
-      double acc = 0.0;
-      for (int j = c; j < n_r; j += nch) acc += T[i + (size_t)j * n_r] * g[j];
-      part[idx] = acc;
+      part[idx] = dot_strided(T + i, n_r, g, c, n_r, nch);
     }
   }
   // b = Psi^T g, one wave per coarse dof
@@ -152,7 +150,7 @@ __global__ void __launch_bounds__(kNT) k_apply_prolong(LevelDev L, const double*
   const double* P = L.Psi + L.psioff[s];
   for (int a = threadIdx.x; a < ng; a += kNT) {
     double w = L.a[g0 + a];
-    for (int k = 0; k < ncs; ++k) w += P[a + (size_t)k * ng] * ul[k];
+    w += dot_strided(P + a, ng, ul, 0, ncs, 1);
     L.v[g0 + a] = L.delta[g0 + a] * w;
   }
 }

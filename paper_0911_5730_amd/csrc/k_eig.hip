@@ -115,7 +115,8 @@ __global__ void __launch_bounds__(kNT) k_pair_eig(
   double* H = lds;                       // ne x ne
   double* V = H + (size_t)ne * ne;       // ne x ne
   double* ds = V + (size_t)ne * ne;      // pair weight of s on each edge dof
-  double* cs = ds + ne;                  // rotation cosines (ne/2+1)
+  double* dt = ds + ne;                  // pair weight of t (computed directly, not as 1 - ds)
+  double* cs = dt + ne;                  // rotation cosines (ne/2+1)
   double* sn = cs + (ne / 2 + 1);        // rotation sines (ne/2+1)
   double* lam = sn + (ne / 2 + 1);       // ne
   int* perm = reinterpret_cast<int*>(lam + ne);
@@ -125,6 +126,7 @@ __global__ void __launch_bounds__(kNT) k_pair_eig(
     const double a = diagK[goff[s] + fps[nsc + p]];
     const double b = diagK[goff[t] + fpt[nsc + p]];
     ds[p] = a / (a + b);
+    dt[p] = b / (a + b);
   }
   // M in the coordinates v = [shared corners | s-edge | t-edge]
   for (int idx = tid; idx < nv * nv; idx += kNT) Y[idx] = 0.0;
@@ -182,7 +184,7 @@ __global__ void __launch_bounds__(kNT) k_pair_eig(
     const int i = idx % ne, j = idx / ne;
     const double ss = Sfs[(nsc + i) + (size_t)(nsc + j) * nF];
     const double tt = Sft[(nsc + i) + (size_t)(nsc + j) * nF];
-    R[idx] = (1.0 - ds[i]) * ss * (1.0 - ds[j]) + ds[i] * tt * ds[j];
+    R[idx] = dt[i] * ss * dt[j] + ds[i] * tt * ds[j];
   }
   __syncthreads();
   wg_potrf(R, ne, ne, status);
@@ -356,7 +358,7 @@ size_t pair_schur_lds(int ngmax) {
 }
 
 size_t pair_eig_lds(int nemax) {
-  return sizeof(double) * (2 * (size_t)nemax * nemax + 2 * (size_t)nemax + 2 * (nemax / 2 + 1)) +
+  return sizeof(double) * (2 * (size_t)nemax * nemax + 3 * (size_t)nemax + 2 * (nemax / 2 + 1)) +
          sizeof(int) * (nemax + 2) + 64;
 }
 

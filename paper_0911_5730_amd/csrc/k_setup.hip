@@ -415,3 +415,35 @@ void launch_coarsest_factor(hipStream_t st, int nsub, int nc, const int32_t* cpt
 }
 
 }  // namespace bddc
+
+namespace bddc {
+
+// Levels >= 2: explicit inverse of the interior Cholesky factor, Linv = L_II^{-1}
+// (lower, n_I x n_I, ld n_I), so that the interior corrections of the apply are
+// matrix-vector products.  One thread per column solves L x = e_j.
+__global__ void __launch_bounds__(kNT) k_tri_inverse(const int64_t* __restrict__ koff,
+                                                     const int32_t* __restrict__ loc_ptr,
+                                                     const int32_t* __restrict__ nint, const double* __restrict__ K,
+                                                     double* __restrict__ Linv, const int64_t* __restrict__ linvoff) {
+  const int s = blockIdx.x;
+  const int n = loc_ptr[s + 1] - loc_ptr[s];
+  const int nI = nint[s];
+  const double* L = K + koff[s];
+  double* X = Linv + linvoff[s];
+  for (int c = threadIdx.x; c < nI; c += kNT) {
+    double* x = X + (size_t)c * nI;
+    for (int i = 0; i < c; ++i) x[i] = 0.0;
+    for (int i = c; i < nI; ++i) {
+      double v = (i == c) ? 1.0 : 0.0;
+      for (int k = c; k < i; ++k) v -= L[i + (size_t)k * n] * x[k];
+      x[i] = v / L[i + (size_t)i * n];
+    }
+  }
+}
+
+void launch_tri_inverse(hipStream_t st, int nsub, const int64_t* koff, const int32_t* loc_ptr,
+                        const int32_t* nint, const double* K, double* Linv, const int64_t* linvoff) {
+  hipLaunchKernelGGL(k_tri_inverse, dim3(nsub), dim3(kNT), 0, st, koff, loc_ptr, nint, K, Linv, linvoff);
+}
+
+}  // namespace bddc

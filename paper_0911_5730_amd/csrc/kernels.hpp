@@ -43,6 +43,45 @@ struct LevelDev {
   double* v = nullptr;                // scratch: interface flat
   double* b = nullptr;                // scratch: local coarse flat
   const int32_t* stop = nullptr;      // when non-null and *stop != 0 the apply kernels return at once
+  const double* Linv = nullptr;       // levels >= 2: explicit inverse of L_II (lower, n_I x n_I)
+  const int64_t* linvoff = nullptr;
+  const int32_t* csh_ptr = nullptr;   // coarse dof -> local coarse flat entries (sharers)
+  const int32_t* csh_flat = nullptr;
+};
+
+// All levels >= 2 and the coarsest solve in one workgroup (used when they are small).
+constexpr int kMaxDeep = 6;
+constexpr int kDeepNT = 1024;   // 16 wave64
+struct DeepArgs {
+  int nlev = 0;                       // number of deep levels (levels 2 .. L-1)
+  LevelDev lv[kMaxDeep];
+  double* rvec[kMaxDeep] = {};        // level vectors r_l (r_2 = level-1 coarse right-hand side)
+  double* uvec[kMaxDeep] = {};        // u_l
+  int nvec[kMaxDeep] = {};
+  double* rc_last = nullptr;          // coarsest right-hand side and solution
+  double* uc_last = nullptr;
+  int ncL = 0;
+  const double* LL = nullptr;         // coarsest Cholesky factor
+  int n2 = 0;                         // r_2 gathered from the level-1 coarse sharers
+  const int32_t* csh_ptr1 = nullptr;
+  const int32_t* csh_flat1 = nullptr;
+  const double* b1 = nullptr;
+  const int32_t* stop = nullptr;
+  int wstride = 0;                    // per-wave LDS scratch (doubles)
+};
+
+// state of the fused PCG iteration on the level-1 interface
+struct PcgDev {
+  struct PcgScalars* sc = nullptr;
+  double *x = nullptr, *r = nullptr, *z = nullptr, *q = nullptr;
+  double* p[2] = {nullptr, nullptr};
+  double* pq_part = nullptr;          // per vector block
+  double* rr_part = nullptr;          // per vector block
+  double* rz_part[2] = {nullptr, nullptr};   // per level-1 substructure, by iteration parity
+  double* qloc = nullptr;             // local Schur products, level-1 interface flat
+  int nif = 0;
+  int nblk = 1;                       // blocks of the vector kernels
+  int nsub1 = 0;
 };
 
 constexpr int kMaxHist = 4096;
@@ -123,5 +162,20 @@ void launch_condense(hipStream_t st, int nif, const int32_t* sh_ptr, const int32
                      const int32_t* iface_gid, const double* f, const double* t, double* r, double* x);
 void launch_recover(hipStream_t st, const LevelDev& L, int nImax, int ngmax, const double* x, double* u);
 void launch_copy(hipStream_t st, int n, const double* a, double* b);
+
+// levels >= 2: explicit inverse of the interior factor; fused deep apply
+void launch_tri_inverse(hipStream_t st, int nsub, const int64_t* koff, const int32_t* loc_ptr,
+                        const int32_t* nint, const double* K, double* Linv, const int64_t* linvoff);
+size_t deep_lds(int wstride, int ncL);
+void launch_deep(hipStream_t st, const DeepArgs& A);
+void launch_apply_pre_inv(hipStream_t st, const LevelDev& L, int nImax, int ngmax, const double* r);
+void launch_apply_post_inv(hipStream_t st, const LevelDev& L, int nImax, int ngmax, double* u);
+
+// fused PCG iteration kernels (level-1 interface)
+void launch_pcg_matvec(hipStream_t st, const LevelDev& L, int ngmax, const PcgDev& P, int it);
+void launch_pcg_gather_dot(hipStream_t st, const LevelDev& L, const PcgDev& P, int it);
+void launch_pcg_update(hipStream_t st, const PcgDev& P, int it);
+void launch_pcg_restrict(hipStream_t st, const LevelDev& L, int ngmax, const PcgDev& P, int check);
+void launch_pcg_post(hipStream_t st, const LevelDev& L, int ngmax, const PcgDev& P, int parity);
 
 }  // namespace bddc
