@@ -105,7 +105,10 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", type=int, default=2)
-    ap.add_argument("--roofline-kernel", default="apply_restrict")
+    ap.add_argument("--roofline-kernel", default="deep",
+                    help="library kernel timed for the roofline (default: the one with the largest share of a step)")
+    ap.add_argument("--sample-every", type=int, default=8,
+                    help="time one in this many launches of the roofline kernel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     ws = int(os.environ.get("WORLD_SIZE", "1"))
@@ -140,7 +143,7 @@ def main():
     torch.cuda.synchronize()
 
     # ---- timed region: K whole steps
-    P.timing_start(args.roofline_kernel)
+    P.timing_start(args.roofline_kernel, args.sample_every)
     lat = []
     iters = []
     torch.cuda.synchronize()

@@ -150,17 +150,20 @@ bddc_status bddc_edge_constraints(bddc_handle h, int32_t level, int32_t edge, in
                                   int32_t cap_dofs, double* q, int32_t cap_q,
                                   int32_t* n_edge_dofs, int32_t* n_cols);
 
-/* Kernel timing for measurement tools.  bddc_timing_start(name) arms HIP
- * events around every later launch of the named kernel (on the stream it is
- * launched on, on any handle); NULL or "" disarms.  Names: "schur_local",
- * "apply_pre", "apply_restrict", "apply_prolong", "apply_post" (level 1;
- * "_l2", "_l3" ... for deeper levels), "partial_chol", "partial_chol_l2".
+/* Kernel timing for measurement tools.  bddc_timing_start(name, every) arms
+ * HIP events on one in `every` (>= 1) later launches of the named kernel, on
+ * any handle: the events are stamped by the dispatch itself, on the stream the
+ * kernel runs on, so they bracket the kernel's execution only; sampling keeps
+ * the events' own cost out of a timed loop.  NULL or "" disarms.  Names:
+ * "schur_local", "apply_pre", "apply_restrict", "apply_prolong", "apply_post"
+ * (level 1; "_l2", "_l3" ... for deeper levels), "deep" (levels >= 2 and the
+ * coarsest solve in one launch), "partial_chol", "partial_chol_l2".
  * bddc_timing_stop synchronises those events and returns the summed kernel
- * time in ms, the number of launches, and the summed algorithmic bytes and
- * flops of those launches (each operator and vector entry the kernel must
+ * time in ms, the number of timed launches, and the summed algorithmic bytes
+ * and flops of those launches (each operator and vector entry the kernel must
  * touch, counted once), then disarms.  Host arrays may be NULL.
- * Errors: BDDC_EDEVICE. */
-bddc_status bddc_timing_start(const char* kernel);
+ * Errors: BDDC_EINVAL (every < 1), BDDC_EDEVICE. */
+bddc_status bddc_timing_start(const char* kernel, int32_t every);
 bddc_status bddc_timing_stop(double* total_ms, int64_t* launches, double* bytes, double* flops);
 
 /* Message of the last failed call on this thread ("" if none; never NULL;

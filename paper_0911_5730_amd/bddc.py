@@ -76,7 +76,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.bddc_query.argtypes = [vp, P(BddcInfoC)]
     lib.bddc_edge_eigs.argtypes = [vp, i32, i32, P(dbl), i32, P(i32), P(i32), P(i32), P(i32)]
     lib.bddc_edge_constraints.argtypes = [vp, i32, i32, P(i32), i32, P(dbl), i32, P(i32), P(i32)]
-    lib.bddc_timing_start.argtypes = [ctypes.c_char_p]
+    lib.bddc_timing_start.argtypes = [ctypes.c_char_p, i32]
     lib.bddc_timing_stop.argtypes = [P(dbl), P(i64), P(dbl), P(dbl)]
     lib.bddc_status_string.argtypes = [i32]
     lib.bddc_status_string.restype = ctypes.c_char_p
@@ -266,9 +266,9 @@ class Solver:
         return np.array(dofs[:ne.value]), Q
 
 
-def timing_start(kernel: str):
-    """Arm HIP-event timing around every launch of one library kernel."""
-    _check(load_library().bddc_timing_start(kernel.encode()), "bddc_timing_start")
+def timing_start(kernel: str, every: int = 1):
+    """Arm HIP-event timing on one in `every` launches of one library kernel."""
+    _check(load_library().bddc_timing_start(kernel.encode(), int(every)), "bddc_timing_start")
 
 
 def timing_stop() -> dict:

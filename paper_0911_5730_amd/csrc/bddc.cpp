@@ -8,6 +8,7 @@
 // bddc_apply runs Algorithm "Multilevel BDDC"; bddc_solve runs PCG on the
 // level-1 interface (Section 5, reduction of level 1 to the interfaces).
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <functional>
@@ -59,6 +60,8 @@ std::string target;
 std::vector<Rec> recs;
 std::vector<hipEvent_t> pool;
 int current_tag = -1;     // set by the PCG driver while it enqueues an iteration
+int every = 1;            // time one in `every` launches of the target
+int64_t seen = 0;         // launches of the target since timing_start
 
 size_t mark() {
   std::lock_guard<std::mutex> lk(mu);
@@ -95,33 +98,71 @@ hipEvent_t get_event() {
 
 class Scope {
  public:
-  Scope(const char* name, hipStream_t st, double bytes, double flops, int tag_shift = 0) {
+  Scope(const char* name, double bytes, double flops, int tag_shift = 0) {
     std::lock_guard<std::mutex> lk(mu);
     if (target.empty() || target != name) return;
+    if (seen++ % every != 0) return;
     rec_.a = get_event();
     rec_.b = get_event();
     rec_.bytes = bytes;
     rec_.flops = flops;
     rec_.tag = current_tag < 0 ? -1 : current_tag + tag_shift;
-    st_ = st;
-    on_ = hipEventRecord(rec_.a, st) == hipSuccess;
+    g_launch_events = LaunchEvents{rec_.a, rec_.b};   // taken by the scope's first launch
+    on_ = true;
   }
   ~Scope() {
     if (!on_) return;
     std::lock_guard<std::mutex> lk(mu);
-    if (hipEventRecord(rec_.b, st_) == hipSuccess) recs.push_back(rec_);
+    if (g_launch_events.start == rec_.a) {   // nothing was launched
+      g_launch_events = LaunchEvents{};
+      pool.push_back(rec_.a);
+      pool.push_back(rec_.b);
+      return;
+    }
+    recs.push_back(rec_);
   }
 
  private:
   bool on_ = false;
   Rec rec_{};
-  hipStream_t st_ = nullptr;
 };
 }  // namespace timing
 
+// host wall-clock breakdown printed to stderr when BDDC_HOST_TIMING is set
+class HostClock {
+ public:
+  HostClock() : on_(getenv("BDDC_HOST_TIMING") != nullptr), t_(std::chrono::steady_clock::now()) {}
+  void lap(const char* what) {
+    if (!on_) return;
+    const auto now = std::chrono::steady_clock::now();
+    fprintf(stderr, "libbddc host %-18s %8.3f ms\n", what, std::chrono::duration<double, std::milli>(now - t_).count());
+    t_ = now;
+  }
+
+ private:
+  bool on_;
+  std::chrono::steady_clock::time_point t_;
+};
+
 namespace {
 
-constexpr size_t kLdsLimit = 64 * 1024 - 1024;   // dynamic LDS without an opt-in attribute
+constexpr size_t kLdsLimit = 64 * 1024 - 1024;   // dynamic LDS of the kernels sized for several blocks per CU
+constexpr size_t kLdsMax = 160 * 1024;          // LDS of one CU, all of it usable by one block on gfx950
+
+// Interior elimination: 64-wide LDS panels with an MFMA trailing update, unless
+// the substructure is too large for a 16-wide panel in LDS or BDDC_CHOL_PATH=lds16.
+bool use_mfma_chol(int nmax) {
+  const char* env = getenv("BDDC_CHOL_PATH");
+  if (env && std::string(env) == "lds16") return false;
+  return partial_chol_mfma_nb(nmax) >= 16 && partial_chol_mfma_lds(nmax) <= kLdsMax;
+}
+
+// Local coarse-space factorization and interior triangular inverse in LDS,
+// unless the substructure does not fit or BDDC_SETUP_PATH=global.
+bool use_lds_setup() {
+  const char* env = getenv("BDDC_SETUP_PATH");
+  return !(env && std::string(env) == "global");
+}
 
 inline uint64_t pkey(int s, int t) {
   return (static_cast<uint64_t>(static_cast<uint32_t>(s)) << 32) | static_cast<uint32_t>(t);
@@ -172,8 +213,8 @@ struct Level {
   std::vector<int32_t> edge_nsc, edge_ne, edge_fptr, edge_fdof;
   std::vector<int32_t> inc_sub, inc_edge, inc_fptr, inc_fpos;
   std::vector<int32_t> sub_inc_ptr, sub_inc;
-  std::vector<int64_t> inc_off, eig_woff, lamoff, qoff;
-  int nemax = 0;
+  std::vector<int64_t> inc_off, lamoff, qoff;
+  int nemax = 0, nvmax = 0;
   // coarse dofs
   std::vector<int32_t> edge_m, edge_nsel;
   std::vector<double> lam;
@@ -185,7 +226,7 @@ struct Level {
   int n_adaptive = 0;
   std::vector<int32_t> agglom_of;   // level-(l+1) substructure of each substructure
   // algorithmic bytes / flops of one launch of each kernel at this level
-  double by_schur = 0, by_restrict_ir = 0, by_restrict_fs = 0, by_prolong = 0, by_post_ir = 0,
+  double by_schur = 0, by_restrict_ir = 0, by_restrict_fs = 0, by_update_restrict = 0, by_prolong = 0, by_post_ir = 0,
          by_post_fs = 0, by_pre = 0, fl_chol = 0, by_chol = 0;
   // device
   Arena arena_a, arena_b, arena_pcg;
@@ -202,8 +243,8 @@ struct Level {
     int32_t *inc_sub, *inc_edge, *inc_fptr, *inc_fpos, *sub_inc_ptr, *sub_inc;
     int32_t *edge_s, *edge_t, *edge_nsc, *edge_ne, *edge_fdof, *edge_fptr, *edge_ptr, *edge_dof;
     uint8_t* floating;
-    int64_t *inc_off, *eig_woff, *lamoff, *qoff;
-    double *Shat, *Sff, *eig_work, *lam, *Q;
+    int64_t *inc_off, *lamoff, *qoff;
+    double *Shat, *Sff, *lam, *Q;
     int32_t *nsel, *nkept;
     double* z;
     // coarse
@@ -232,7 +273,7 @@ struct bddc_ctx {
   int ncL = 0;
   int* status = nullptr;
   // PCG on the level-1 interface
-  double *x = nullptr, *r = nullptr, *p = nullptr, *zv = nullptr, *q = nullptr, *partial = nullptr;
+  double *x = nullptr, *r = nullptr, *p = nullptr, *zv = nullptr, *partial = nullptr;
   bddc::PcgScalars* sc = nullptr;
   bddc::PcgScalars* sc_host = nullptr;   // pinned
   int nblk = 1;
@@ -240,6 +281,12 @@ struct bddc_ctx {
   // deep levels (2 .. L-1) and the coarsest solve in one workgroup when small
   bool fused_deep = false;
   bddc::DeepArgs deep;
+  // one deep level and the coarsest solve in one cooperative launch
+  bool coop_deep = false;
+  bool coop_launch = false;   // use the cooperative launch API
+  double coop_bytes = 0;      // algorithmic bytes of one launch
+  bddc::CoopDev coop;
+  bddc::Arena coop_arena;
   bddc_info info{};
 };
 
@@ -394,7 +441,7 @@ static void layout_level(Level& lv) {
   for (int c : T.corners)
     for (int a = 0; a < T.nshare[c]; ++a)
       for (int b2 = a + 1; b2 < T.nshare[c]; ++b2) {
-        auto it = eid.find(pkey(T.share[c][a], T.share[c][b2]));
+        auto it = eid.find(pkey(T.share(c)[a], T.share(c)[b2]));
         if (it != eid.end()) shared[it->second].push_back(c);
       }
   lv.edge_nsc.resize(lv.nedge);
@@ -407,6 +454,7 @@ static void layout_level(Level& lv) {
     for (int k = T.edge_ptr[e]; k < T.edge_ptr[e + 1]; ++k) lv.edge_fdof.push_back(T.edge_dof[k]);
     lv.edge_fptr.push_back((int32_t)lv.edge_fdof.size());
     lv.nemax = std::max(lv.nemax, (int)lv.edge_ne[e]);
+    lv.nvmax = std::max(lv.nvmax, (int)(lv.edge_nsc[e] + 2 * lv.edge_ne[e]));
   }
   // incidences: 2e = s side, 2e+1 = t side
   const int ninc = 2 * lv.nedge;
@@ -482,6 +530,9 @@ static void account(Level& lv) {
     lv.by_chol += 16 * n * n;
   }
   lv.by_restrict_fs = lv.by_restrict_ir + 12 * nshare_sum;
+  // PCG update folded into the interface restriction: the sharers' local
+  // products, r_{k-1}, and per owned dof r_k written, x read and written, p read
+  lv.by_update_restrict = lv.by_restrict_ir + 12 * nshare_sum + 32 * nif;
   lv.by_post_ir = 12 * nshare_sum + 12 * lv.nflat_g + 8 * nif;
   lv.by_post_fs += lv.by_post_ir;
 }
@@ -492,17 +543,23 @@ class Builder {
   Builder(bddc_ctx* h, const bddc_problem* p) : h_(h), p_(p), st_(h->stream) {}
 
   void run() {
+    HostClock clk;
     Level1Elements E = level1_elements(p_);
+    clk.lap("elements");
     // level 1
     auto lv = std::make_unique<Level>();
     lv->ell = 1;
     lv->topo = classify((int)h_->n_free, p_->nsub, E.ptr, E.dof, E.sub, E.touch);
+    clk.lap("classify l1");
     layout_level(*lv);
     check_limits(*lv);
+    clk.lap("layout l1");
     top_alloc();
     alloc_a(*lv, &E, nullptr);
+    clk.lap("alloc_a l1");
     assemble_l1(*lv, E);
     factor_level(*lv, nullptr);
+    clk.lap("factor l1");
     h_->levels.push_back(std::move(lv));
     for (int ell = 2; ell < h_->L; ++ell) {
       Level& prev = *h_->levels.back();
@@ -520,13 +577,17 @@ class Builder {
       nl->topo = classify(prev.nc, nsub_next, eptr, edof, esub, etouch);
       layout_level(*nl);
       check_limits(*nl);
+      clk.lap("classify+layout");
       alloc_a(*nl, nullptr, &prev);
+      clk.lap("alloc_a");
       assemble_coarse(*nl, prev);
       factor_level(*nl, &prev);
+      clk.lap("factor");
       h_->levels.push_back(std::move(nl));
     }
     coarsest();
     BDDC_HIP(hipStreamSynchronize(st_));
+    clk.lap("coarsest");
     int bad = 0;
     BDDC_HIP(hipMemcpy(&bad, h_->status, sizeof(int), hipMemcpyDeviceToHost));
     if (bad & 2) fail(BDDC_EINVAL, "coefficients must be positive and finite");
@@ -539,8 +600,8 @@ class Builder {
   hipStream_t st_;
 
   void check_limits(const Level& lv) {
-    if (pair_schur_lds(lv.ngmax) > kLdsLimit || partial_chol_lds(lv.nmax) > kLdsLimit ||
-        pair_eig_lds(lv.nemax) > kLdsLimit)
+    if (pair_schur_lds(lv.ngmax) > kLdsLimit || (partial_chol_lds(lv.nmax) > kLdsLimit && !use_mfma_chol(lv.nmax)) ||
+        pair_eig_lds(lv.nemax, lv.nvmax) > kLdsMax)
       fail(BDDC_EUNSUPPORTED, "substructure interface or edge too large for this build");
   }
 
@@ -616,12 +677,10 @@ class Builder {
       }
     }
     // eigen work sizes
-    lv.eig_woff.assign(lv.nedge + 1, 0);
     lv.lamoff.assign(lv.nedge + 1, 0);
     lv.qoff.assign(lv.nedge + 1, 0);
     for (int e = 0; e < lv.nedge; ++e) {
-      const int ne_ = lv.edge_ne[e], nv = lv.edge_nsc[e] + 2 * ne_;
-      lv.eig_woff[e + 1] = lv.eig_woff[e] + (adaptive ? (int64_t)nv * nv + (int64_t)nv * ne_ + (int64_t)ne_ * ne_ : 0);
+      const int ne_ = lv.edge_ne[e];
       lv.lamoff[e + 1] = lv.lamoff[e] + ne_;
       lv.qoff[e + 1] = lv.qoff[e] + (int64_t)ne_ * ne_;
     }
@@ -676,12 +735,10 @@ class Builder {
       d.edge_dof = A.take<int32_t>(edge_dof.size());
       d.floating = A.take<uint8_t>(nsub);
       d.inc_off = A.take<int64_t>(lv.inc_off.size());
-      d.eig_woff = A.take<int64_t>(lv.eig_woff.size());
       d.lamoff = A.take<int64_t>(lv.lamoff.size());
       d.qoff = A.take<int64_t>(lv.qoff.size());
       d.Shat = A.take<double>(adaptive ? (size_t)lv.inc_off.back() : 0);
       d.Sff = A.take<double>(adaptive ? (size_t)lv.inc_off.back() : 0);
-      d.eig_work = A.take<double>((size_t)lv.eig_woff.back());
       d.lam = A.take<double>((size_t)lv.lamoff.back());
       d.Q = A.take<double>((size_t)lv.qoff.back());
       d.nsel = A.take<int32_t>(lv.nedge);
@@ -742,7 +799,6 @@ class Builder {
     h2d(d.edge_dof, edge_dof, st_);
     h2d(d.floating, floating, st_);
     h2d(d.inc_off, lv.inc_off, st_);
-    h2d(d.eig_woff, lv.eig_woff, st_);
     h2d(d.lamoff, lv.lamoff, st_);
     h2d(d.qoff, lv.qoff, st_);
     h2d(d.linvoff, lv.linvoff, st_);
@@ -784,10 +840,18 @@ class Builder {
         }
       double by = 0;
       for (int s = 0; s < lv.nsub; ++s) by += 16.0 * T.nloc(s) * T.nloc(s);
-      timing::Scope ts(lv.ell == 1 ? "partial_chol" : "partial_chol_l2", st_, by, fl);
-      launch_partial_chol(st_, lv.nsub, lv.nmax, d.koff, d.loc_ptr, d.nint, d.K, h_->status);
+      timing::Scope ts(lv.ell == 1 ? "partial_chol" : "partial_chol_l2", by, fl);
+      if (use_mfma_chol(lv.nmax))
+        launch_partial_chol_mfma(st_, lv.nsub, lv.nmax, d.koff, d.loc_ptr, d.nint, d.K, h_->status);
+      else
+        launch_partial_chol(st_, lv.nsub, lv.nmax, d.koff, d.loc_ptr, d.nint, d.K, h_->status);
     }
-    if (lv.ell >= 2) launch_tri_inverse(st_, lv.nsub, d.koff, d.loc_ptr, d.nint, d.K, d.Linv, d.linvoff);
+    if (lv.ell >= 2) {
+      if (use_lds_setup() && tri_inverse_lds(lv.nImax) <= kLdsMax)
+        launch_tri_inverse_lds(st_, lv.nsub, lv.nImax, d.koff, d.loc_ptr, d.nint, d.K, d.Linv, d.linvoff);
+      else
+        launch_tri_inverse(st_, lv.nsub, d.koff, d.loc_ptr, d.nint, d.K, d.Linv, d.linvoff);
+    }
     const int ne_tot = lv.nedge;
     lv.edge_m.assign(ne_tot, 0);
     lv.edge_nsel.assign(ne_tot, 0);
@@ -795,10 +859,9 @@ class Builder {
     if (h_->constraints == BDDC_ADAPTIVE && ne_tot > 0) {
       launch_pair_schur(st_, 2 * ne_tot, lv.ngmax, d.inc_sub, d.inc_fptr, d.inc_fpos, d.koff, d.loc_ptr, d.nint,
                         d.K, d.inc_off, d.Shat, d.Sff, h_->status);
-      launch_pair_eig(st_, ne_tot, lv.nemax, d.edge_s, d.edge_t, d.edge_nsc, d.edge_ne, d.edge_fdof, d.edge_fptr,
-                      d.inc_fptr, d.inc_fpos, d.goff, d.diagK, d.floating, d.z, d.Shat, d.Sff, d.inc_off,
-                      d.eig_work, d.eig_woff, h_->tau, d.lam, d.lamoff, d.Q, d.qoff, d.nsel, d.nkept,
-                      h_->status);
+      launch_pair_eig(st_, ne_tot, lv.nemax, lv.nvmax, d.edge_s, d.edge_t, d.edge_nsc, d.edge_ne, d.edge_fdof,
+                      d.edge_fptr, d.inc_fptr, d.inc_fpos, d.goff, d.diagK, d.floating, d.z, d.Shat, d.Sff,
+                      d.inc_off, h_->tau, d.lam, d.lamoff, d.Q, d.qoff, d.nsel, d.nkept, h_->status);
       std::vector<int32_t> nkept(ne_tot);
       lv.lam.resize(lv.lamoff.back());
       BDDC_HIP(hipMemcpyAsync(nkept.data(), d.nkept, sizeof(int32_t) * ne_tot, hipMemcpyDeviceToHost, st_));
@@ -827,8 +890,15 @@ class Builder {
     alloc_b(lv);
     launch_build_cr(st_, lv.nsub, d.sub_inc_ptr, d.sub_inc, d.inc_edge, d.inc_fptr, d.inc_fpos, d.edge_nsc,
                     d.edge_ne, d.edge_m, d.qoff, d.Q, d.nr, d.ncr, d.croff, d.Cr);
-    launch_constrained_factor(st_, lv.nsub, d.koff, d.loc_ptr, d.nint, d.nr, d.ncr, d.croff, d.Cr, d.K, d.T,
-                              d.toff, d.Psi, d.psioff, d.Ac, d.acoff, d.cwork, d.cwoff, h_->status);
+    size_t cf_lds = 0;
+    for (int s = 0; s < lv.nsub; ++s)
+      cf_lds = std::max(cf_lds, constrained_factor_lds(T.ngam(s), T.n_r[s], lv.ncr[s], lv.coff[s + 1] - lv.coff[s]));
+    if (use_lds_setup() && cf_lds <= kLdsMax)
+      launch_constrained_factor_lds(st_, lv.nsub, cf_lds, d.koff, d.loc_ptr, d.nint, d.nr, d.ncr, d.croff, d.Cr,
+                                    d.K, d.T, d.toff, d.Psi, d.psioff, d.Ac, d.acoff, h_->status);
+    else
+      launch_constrained_factor(st_, lv.nsub, d.koff, d.loc_ptr, d.nint, d.nr, d.ncr, d.croff, d.Cr, d.K, d.T,
+                                d.toff, d.Psi, d.psioff, d.Ac, d.acoff, d.cwork, d.cwoff, h_->status);
     if (h_->constraints == BDDC_ADAPTIVE && lv.ell < h_->L - 1)
       launch_coarse_z(st_, lv.nc, d.cd_dof, d.cd_col, d.edge_ptr, d.edge_dof, d.qoff, d.Q, d.z, d.znext);
     // keep the installed constraint weights for queries
@@ -1010,11 +1080,11 @@ static void apply_deep_level(bddc_ctx* h, int li, const double* r, double* u) {
   hipStream_t st = h->stream;
   const std::string sfx = "_l" + std::to_string(li + 1);
   {
-    timing::Scope ts(("apply_pre" + sfx).c_str(), st, lv.by_pre, 0);
+    timing::Scope ts(("apply_pre" + sfx).c_str(), lv.by_pre, 0);
     launch_apply_pre_inv(st, lv.dev, lv.nImax, lv.ngmax, r);
   }
   {
-    timing::Scope ts(("apply_restrict" + sfx).c_str(), st, lv.by_restrict_fs, 0);
+    timing::Scope ts(("apply_restrict" + sfx).c_str(), lv.by_restrict_fs, 0);
     launch_apply_restrict(st, lv.dev, lv.ngmax, r, lv.d.gam_gid, 1);
   }
   launch_coarse_gather(st, lv.nc, lv.d.csh_ptr, lv.d.csh_flat, lv.d.b, lv.d.rc, lv.dev.stop);
@@ -1023,11 +1093,11 @@ static void apply_deep_level(bddc_ctx* h, int li, const double* r, double* u) {
   else
     apply_deep_level(h, li + 1, lv.d.rc, lv.d.uc);
   {
-    timing::Scope ts(("apply_prolong" + sfx).c_str(), st, lv.by_prolong, 0);
+    timing::Scope ts(("apply_prolong" + sfx).c_str(), lv.by_prolong, 0);
     launch_apply_prolong(st, lv.dev, lv.ncsmax, lv.d.uc);
   }
   {
-    timing::Scope ts(("apply_post" + sfx).c_str(), st, lv.by_post_fs, 0);
+    timing::Scope ts(("apply_post" + sfx).c_str(), lv.by_post_fs, 0);
     launch_apply_post_inv(st, lv.dev, lv.nImax, lv.ngmax, u);
   }
 }
@@ -1041,10 +1111,17 @@ static void run_deep(bddc_ctx* h) {
     launch_coarsest_solve(st, l1.nc, h->AL, l1.d.rc, l1.d.uc, l1.dev.stop);
     return;
   }
+  if (h->coop_deep) {
+    CoopDev C = h->coop;
+    C.stop = l1.dev.stop;
+    timing::Scope ts("deep", h->coop_bytes, 0);
+    launch_deep_coop(st, C, h->coop_launch);
+    return;
+  }
   if (h->fused_deep) {
     DeepArgs A = h->deep;
     A.stop = l1.dev.stop;
-    timing::Scope ts("deep", st, 0, 0);
+    timing::Scope ts("deep", 0, 0);
     launch_deep(st, A);
     return;
   }
@@ -1063,13 +1140,129 @@ static void apply_full(bddc_ctx* h, const double* r, double* u) {
   launch_apply_post(st, l1.dev, l1.nImax, l1.ngmax, u, l1.d.gam_gid, 1);
 }
 
+// One deep level and a small coarsest problem: pack the level-2 operators and
+// index lists per substructure and use the cooperative kernel if it fits.
+static bool plan_coop(bddc_ctx* h) {
+  h->coop_deep = false;
+  if (h->levels.size() != 2) return false;
+  const char* env = getenv("BDDC_DEEP_PATH");
+  if (env && std::string(env) != "coop") return false;
+  Level& l1 = *h->levels[0];
+  Level& lv = *h->levels[1];
+  const Topology& T = lv.topo;
+  const int nsub = lv.nsub;
+  const int ncL = lv.nc;
+  if (ncL < 1 || nsub < 1) return false;
+  if (sizeof(double) * ((size_t)ncL * ncL + 2 * (size_t)ncL) > kLdsMax) return false;
+  CoopDev C{};
+  C.nsub = nsub;
+  C.ncL = ncL;
+  std::vector<int32_t> meta((size_t)kCoopMeta * nsub);
+  std::vector<int64_t> opoff(nsub + 1, 0), idxoff(nsub + 1, 0);
+  std::vector<int32_t> idx;
+  for (int s = 0; s < nsub; ++s) {
+    const int nI = T.n_int[s], ng = T.ngam(s), nr = T.n_r[s], ncs = lv.coff[s + 1] - lv.coff[s];
+    const size_t i0 = idx.size();
+    for (int i = 0; i < nI; ++i) idx.push_back(lv.int_gid[lv.ioff[s] + i]);
+    for (int a = 0; a < ng; ++a) idx.push_back(lv.gam_gid[lv.goff[s] + a]);
+    for (int a = 0; a < ng; ++a) {
+      const int f = lv.goff[s] + a, gi = lv.gam_iid[f];
+      idx.push_back(lv.sh_flat[lv.sh_ptr[gi]] == f ? 1 : 0);
+    }
+    std::vector<int32_t> shp(ng + 1, 0), shf;
+    for (int a = 0; a < ng; ++a) {
+      const int gi = lv.gam_iid[lv.goff[s] + a];
+      for (int k = lv.sh_ptr[gi]; k < lv.sh_ptr[gi + 1]; ++k) shf.push_back(lv.sh_flat[k]);
+      shp[a + 1] = (int32_t)shf.size();
+    }
+    idx.insert(idx.end(), shp.begin(), shp.end());
+    idx.insert(idx.end(), shf.begin(), shf.end());
+    const int n = nI + ng;
+    std::vector<int32_t> gp(n + 1, 0), gf;
+    for (int p = 0; p < n; ++p) {
+      const int k = p < nI ? lv.int_gid[lv.ioff[s] + p] : lv.gam_gid[lv.goff[s] + p - nI];
+      for (int q = l1.csh_ptr[k]; q < l1.csh_ptr[k + 1]; ++q) gf.push_back(l1.csh_flat[q]);
+      gp[p + 1] = (int32_t)gf.size();
+    }
+    idx.insert(idx.end(), gp.begin(), gp.end());
+    idx.insert(idx.end(), gf.begin(), gf.end());
+    for (int k = lv.coff[s]; k < lv.coff[s + 1]; ++k) idx.push_back(lv.cid[k]);
+    idxoff[s + 1] = (int64_t)idx.size();
+    int32_t* m = meta.data() + (size_t)kCoopMeta * s;
+    m[0] = nI;
+    m[1] = ng;
+    m[2] = nr;
+    m[3] = ncs;
+    m[4] = (int32_t)shf.size();
+    m[5] = (int32_t)gf.size();
+    m[6] = lv.goff[s];
+    m[7] = lv.coff[s];
+    const int64_t ops = (int64_t)nI * nI + (int64_t)ng * nI + (int64_t)nr * nr + (int64_t)ng * ncs + ng;
+    opoff[s + 1] = opoff[s] + ops;
+    C.opmax = std::max<int>(C.opmax, (int)ops);
+    C.idxmax = std::max<int>(C.idxmax, (int)(idx.size() - i0));
+    C.nImax = std::max(C.nImax, nI);
+    C.ngmax = std::max(C.ngmax, ng);
+    C.ncsmax = std::max(C.ncsmax, ncs);
+  }
+  std::vector<int32_t> cg(lv.csh_ptr.begin(), lv.csh_ptr.end());
+  cg.insert(cg.end(), lv.csh_flat.begin(), lv.csh_flat.end());
+  C.cg_len = (int)cg.size();
+  const size_t lds = coop_lds(C);
+  if (lds > kLdsMax) return false;
+  if (coop_max_blocks(lds) < nsub) return false;
+  Arena& A = h->coop_arena;
+  auto lay = [&] {
+    C.ops = A.take<double>((size_t)opoff[nsub]);
+    C.opoff = A.take<int64_t>(nsub + 1);
+    C.idx = A.take<int32_t>(idx.size());
+    C.idxoff = A.take<int64_t>(nsub + 1);
+    C.meta = A.take<int32_t>(meta.size());
+    C.cg = A.take<int32_t>(cg.size());
+    C.LLinv = A.take<double>((size_t)ncL * ncL);
+    C.bar = A.take<unsigned>(2);
+  };
+  A.reset_sizing();
+  lay();
+  A.allocate(h->stream);
+  lay();
+  hipStream_t st = h->stream;
+  h2d(const_cast<int64_t*>(C.opoff), opoff, st);
+  h2d(const_cast<int32_t*>(C.idx), idx, st);
+  h2d(const_cast<int64_t*>(C.idxoff), idxoff, st);
+  h2d(const_cast<int32_t*>(C.meta), meta, st);
+  h2d(const_cast<int32_t*>(C.cg), cg, st);
+  BDDC_HIP(hipMemsetAsync(C.bar, 0, 2 * sizeof(unsigned), st));
+  launch_pack_coop(st, lv.dev, C);
+  launch_tri_inverse_dense(st, h->AL, ncL, ncL, const_cast<double*>(C.LLinv));
+  C.b1 = l1.d.b;
+  C.t = lv.d.t;
+  C.b = lv.d.b;
+  C.v = lv.d.v;
+  C.u2 = l1.d.uc;
+  C.stop = nullptr;
+  C.status = h->status;
+  BDDC_HIP(hipStreamSynchronize(st));
+  h->coop = C;
+  h->coop_deep = true;
+  const char* cl = getenv("BDDC_COOP_LAUNCH");
+  h->coop_launch = cl && std::string(cl) == "1";
+  // operators and index lists once per workgroup, the level-1 contributions,
+  // t / b / v written and read back, the level-2 solution written
+  h->coop_bytes = 8.0 * (double)opoff[nsub] + 4.0 * (double)idx.size() +
+                  (double)nsub * (4.0 * cg.size() + 8.0 * ncL * ncL) + 8.0 * (double)lv.nflat_c * 2 +
+                  8.0 * (double)lv.nflat_g * 4 + 8.0 * (double)l1.nflat_c + 8.0 * (double)lv.n;
+  return true;
+}
+
 // decide whether the deep levels fit one workgroup and fill the fused-kernel arguments
 static void plan_deep(bddc_ctx* h) {
   h->fused_deep = false;
   const int L = (int)h->levels.size();
   if (L < 2 || L - 1 > kMaxDeep) return;
+  if (plan_coop(h)) return;
   const char* env = getenv("BDDC_DEEP_PATH");
-  if (env && std::string(env) == "levels") return;
+  if (env && (std::string(env) == "levels" || std::string(env) == "coop")) return;
   double bytes = 0;
   int wstride = 1;
   for (int li = 1; li < L; ++li) {
@@ -1179,23 +1372,28 @@ static int pcg_one(bddc_ctx* h, const double* f, double* u, double rtol, int max
   const PcgDev& P = h->pcg;
   const size_t tmark = timing::mark();
 
-  // z_0 = M r_0 and its r.z partials (parity 0)
+  // Iteration k: matvec, update + restriction, deep levels, prolongation with
+  // the convergence test, post.  The test sits in the prolongation, so at the
+  // converged iteration K the update, restriction and deep levels still run
+  // (tagged k - 1: they work iff k <= K) and the rest return at once.
   auto apply_iface = [&](int it) {
-    timing::current_tag = it;
+    timing::current_tag = it - 1;
     {
-      timing::Scope ts("apply_restrict", st, l1.by_restrict_ir, 0);
-      launch_pcg_restrict(st, l1.dev, l1.ngmax, P, it > 0 ? 1 : 0);
+      timing::Scope ts("apply_restrict", it > 0 ? l1.by_update_restrict : l1.by_restrict_ir, 0);
+      launch_pcg_update_restrict(st, l1.dev, l1.ngmax, P, it);
     }
     run_deep(h);
+    timing::current_tag = it;
     {
-      timing::Scope ts("apply_prolong", st, l1.by_prolong, 0);
-      launch_apply_prolong(st, l1.dev, l1.ncsmax, l1.d.uc);
+      timing::Scope ts("apply_prolong", l1.by_prolong, 0);
+      launch_pcg_prolong(st, l1.dev, l1.ncsmax, P, l1.d.uc, it > 0 ? 1 : 0);
     }
     {
-      timing::Scope ts("apply_post", st, l1.by_post_ir, 0);
-      launch_pcg_post(st, l1.dev, l1.ngmax, P, it & 1);
+      timing::Scope ts("apply_post", l1.by_post_ir, 0);
+      launch_pcg_post(st, l1.dev, P, it & 1);
     }
   };
+  // z_0 = M r_0 and its r.z partials (parity 0)
   apply_iface(0);
   int it = 0;
   int check = 8;
@@ -1205,11 +1403,9 @@ static int pcg_one(bddc_ctx* h, const double* f, double* u, double rtol, int max
       timing::current_tag = it;
       {
         // the product of iteration k works iff k <= K (K = converged iteration)
-        timing::Scope ts("schur_local", st, l1.by_schur, 0, -1);
+        timing::Scope ts("schur_local", l1.by_schur, 0, -1);
         launch_pcg_matvec(st, l1.dev, l1.ngmax, P, it);
       }
-      launch_pcg_gather_dot(st, l1.dev, P, it);
-      launch_pcg_update(st, P, it);
       apply_iface(it);
     }
     BDDC_HIP(hipMemcpyAsync(sch, h->sc, offsetof(PcgScalars, alphas), hipMemcpyDeviceToHost, st));
@@ -1218,8 +1414,11 @@ static int pcg_one(bddc_ctx* h, const double* f, double* u, double rtol, int max
   }
   timing::current_tag = -1;
   launch_recover(st, l1.dev, l1.nImax, l1.ngmax, h->x, u);
+  int dev_status = 0;
   BDDC_HIP(hipMemcpyAsync(sch, h->sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, st));
+  BDDC_HIP(hipMemcpyAsync(&dev_status, h->status, sizeof(int), hipMemcpyDeviceToHost, st));
   BDDC_HIP(hipStreamSynchronize(st));
+  if (dev_status & 4) fail(BDDC_EDEVICE, "a grid barrier of the deep-level kernel timed out");
   const int iters = sch->iters;
   // launches of iteration k work iff k < K (the product: k <= K, tagged k-1)
   timing::prune(tmark, iters);
@@ -1293,6 +1492,7 @@ void release(bddc_ctx* h) {
     lv->arena_pcg.release(st);
   }
   h->top.release(st);
+  h->coop_arena.release(st);
   if (h->sc_host) (void)hipHostFree(h->sc_host);
   (void)hipStreamSynchronize(st);
   delete h;
@@ -1332,12 +1532,17 @@ const char* bddc_status_string(bddc_status s) {
 
 bddc_status bddc_plan(const bddc_problem* p, bddc_info* info) {
   return guard([&] {
+    HostClock clk;
     validate(p);
+    clk.lap("validate");
     if (!info) fail(BDDC_EINVAL, "info is NULL");
     Level1Elements E = level1_elements(p);
+    clk.lap("elements");
     Level lv;
     lv.topo = classify((p->nx - 1) * (p->ny - 1), p->nsub, E.ptr, E.dof, E.sub, E.touch);
+    clk.lap("classify");
     layout_level(lv);
+    clk.lap("layout");
     std::memset(info, 0, sizeof(*info));
     info->n_free = (int64_t)(p->nx - 1) * (p->ny - 1);
     info->levels = p->levels;
@@ -1371,13 +1576,13 @@ bddc_status bddc_setup(const bddc_problem* p, void* hip_stream, bddc_handle* out
     auto lay = [&] {
       h->x = B.take<double>(nif);
       h->r = B.take<double>(nif);
+      P.r[1] = B.take<double>(nif);
       h->p = B.take<double>(nif);
       P.p[1] = B.take<double>(nif);
       h->zv = B.take<double>(nif);
-      h->q = B.take<double>(nif);
       h->partial = B.take<double>(1024);
-      P.pq_part = B.take<double>(h->nblk);
-      P.rr_part = B.take<double>(h->nblk);
+      P.pq_part = B.take<double>(l1.nsub);
+      P.rr_part = B.take<double>(l1.nsub);
       P.rz_part[0] = B.take<double>(l1.nsub);
       P.rz_part[1] = B.take<double>(l1.nsub);
       h->sc = B.take<PcgScalars>(1);
@@ -1388,13 +1593,11 @@ bddc_status bddc_setup(const bddc_problem* p, void* hip_stream, bddc_handle* out
     lay();
     P.sc = h->sc;
     P.x = h->x;
-    P.r = h->r;
+    P.r[0] = h->r;
     P.z = h->zv;
-    P.q = h->q;
     P.p[0] = h->p;
     P.qloc = l1.d.qloc;
     P.nif = nif;
-    P.nblk = h->nblk;
     P.nsub1 = l1.nsub;
     plan_deep(h);
     BDDC_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->sc_host), sizeof(PcgScalars), hipHostMallocDefault));
@@ -1411,7 +1614,7 @@ bddc_status bddc_setup(const bddc_problem* p, void* hip_stream, bddc_handle* out
       dev += h->levels[i]->arena_a.size() + h->levels[i]->arena_b.size() + h->levels[i]->arena_pcg.size();
     }
     h->info.indicator = ind;
-    h->info.device_bytes = (int64_t)(dev + h->top.size());
+    h->info.device_bytes = (int64_t)(dev + h->top.size() + h->coop_arena.size());
     h->info.apply_bytes = model_bytes(h, true);
     h->info.matvec_bytes = model_bytes(h, false);
     *out = h;
@@ -1497,9 +1700,12 @@ bddc_status bddc_edge_constraints(bddc_handle h, int32_t level, int32_t edge, in
 
 void bddc_destroy(bddc_handle h) { release(h); }
 
-bddc_status bddc_timing_start(const char* kernel) {
+bddc_status bddc_timing_start(const char* kernel, int32_t every) {
   return guard([&] {
+    if (every < 1) fail(BDDC_EINVAL, "every must be >= 1");
     std::lock_guard<std::mutex> lk(timing::mu);
+    timing::every = every;
+    timing::seen = 0;
     for (auto& r : timing::recs) {
       timing::pool.push_back(r.a);
       timing::pool.push_back(r.b);

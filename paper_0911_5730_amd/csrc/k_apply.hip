@@ -365,73 +365,73 @@ static inline int blocks_for(int n) { return n <= 0 ? 1 : (n + kNT - 1) / kNT; }
 
 void launch_apply_pre(hipStream_t st, const LevelDev& L, int nImax, int ngmax, const double* r) {
   const size_t lds = sizeof(double) * ((size_t)nImax + kNT + ngmax);
-  hipLaunchKernelGGL(k_apply_pre, dim3(L.nsub), dim3(kNT), lds, st, L, r);
+  launch_kernel(k_apply_pre, dim3(L.nsub), dim3(kNT), lds, st, L, r);
 }
 void launch_apply_restrict(hipStream_t st, const LevelDev& L, int ngmax, const double* r,
                            const int32_t* gam_map, int use_t) {
   const size_t lds = sizeof(double) * ((size_t)ngmax + kNT + ngmax);
   if (use_t)
-    hipLaunchKernelGGL(k_apply_restrict<true>, dim3(L.nsub), dim3(kNT), lds, st, L, r, gam_map);
+    launch_kernel(k_apply_restrict<true>, dim3(L.nsub), dim3(kNT), lds, st, L, r, gam_map);
   else
-    hipLaunchKernelGGL(k_apply_restrict<false>, dim3(L.nsub), dim3(kNT), lds, st, L, r, gam_map);
+    launch_kernel(k_apply_restrict<false>, dim3(L.nsub), dim3(kNT), lds, st, L, r, gam_map);
 }
 void launch_coarse_gather(hipStream_t st, int nc, const int32_t* csh_ptr, const int32_t* csh_flat,
                           const double* b, double* rc, const int32_t* stop) {
   if (nc == 0) return;
-  hipLaunchKernelGGL(k_coarse_gather, dim3(blocks_for(nc)), dim3(kNT), 0, st, nc, csh_ptr, csh_flat, b, rc,
+  launch_kernel(k_coarse_gather, dim3(blocks_for(nc)), dim3(kNT), 0, st, nc, csh_ptr, csh_flat, b, rc,
                      stop);
 }
 void launch_coarsest_solve(hipStream_t st, int nc, const double* Lc, const double* rc, double* uc,
                            const int32_t* stop) {
   if (nc == 0) return;
-  hipLaunchKernelGGL(k_coarsest_solve, dim3(1), dim3(kNT), sizeof(double) * (size_t)nc, st, nc, Lc, rc, uc,
+  launch_kernel(k_coarsest_solve, dim3(1), dim3(kNT), sizeof(double) * (size_t)nc, st, nc, Lc, rc, uc,
                      stop);
 }
 void launch_apply_prolong(hipStream_t st, const LevelDev& L, int ncsmax, const double* uc) {
-  hipLaunchKernelGGL(k_apply_prolong, dim3(L.nsub), dim3(kNT), sizeof(double) * (size_t)(ncsmax + 1), st, L, uc);
+  launch_kernel(k_apply_prolong, dim3(L.nsub), dim3(kNT), sizeof(double) * (size_t)(ncsmax + 1), st, L, uc);
 }
 void launch_apply_post(hipStream_t st, const LevelDev& L, int nImax, int ngmax, double* u,
                        const int32_t* gam_map, int interior) {
   const size_t lds = sizeof(double) * ((size_t)ngmax + nImax + 1);
   if (interior)
-    hipLaunchKernelGGL(k_apply_post<true>, dim3(L.nsub), dim3(kNT), lds, st, L, u, gam_map);
+    launch_kernel(k_apply_post<true>, dim3(L.nsub), dim3(kNT), lds, st, L, u, gam_map);
   else
-    hipLaunchKernelGGL(k_apply_post<false>, dim3(L.nsub), dim3(kNT), lds, st, L, u, gam_map);
+    launch_kernel(k_apply_post<false>, dim3(L.nsub), dim3(kNT), lds, st, L, u, gam_map);
 }
 void launch_schur_local(hipStream_t st, const LevelDev& L, int ngmax, const double* p, double* qloc) {
   const size_t lds = sizeof(double) * ((size_t)ngmax + kNT + ngmax);
-  hipLaunchKernelGGL(k_schur_local, dim3(L.nsub), dim3(kNT), lds, st, L, p, qloc);
+  launch_kernel(k_schur_local, dim3(L.nsub), dim3(kNT), lds, st, L, p, qloc);
 }
 void launch_gather_dot(hipStream_t st, int nblk, int nif, const int32_t* sh_ptr, const int32_t* sh_flat,
                        const double* qloc, const double* p, double* q, double* partial) {
-  hipLaunchKernelGGL(k_gather_dot, dim3(nblk), dim3(kNT), 0, st, nif, sh_ptr, sh_flat, qloc, p, q, partial);
+  launch_kernel(k_gather_dot, dim3(nblk), dim3(kNT), 0, st, nif, sh_ptr, sh_flat, qloc, p, q, partial);
 }
 void launch_dot_partial(hipStream_t st, int nblk, int n, const double* a, const double* b, double* partial) {
-  hipLaunchKernelGGL(k_dot_partial, dim3(nblk), dim3(kNT), 0, st, n, a, b, partial);
+  launch_kernel(k_dot_partial, dim3(nblk), dim3(kNT), 0, st, n, a, b, partial);
 }
 void launch_scalar(hipStream_t st, int which, int nblk, const double* partial, PcgScalars* sc) {
-  hipLaunchKernelGGL(k_scalar, dim3(1), dim3(kNT), 0, st, which, nblk, partial, sc);
+  launch_kernel(k_scalar, dim3(1), dim3(kNT), 0, st, which, nblk, partial, sc);
 }
 void launch_update_xr(hipStream_t st, int nblk, int n, const PcgScalars* sc, const double* p, const double* q,
                       double* x, double* r, double* partial) {
-  hipLaunchKernelGGL(k_update_xr, dim3(nblk), dim3(kNT), 0, st, n, sc, p, q, x, r, partial);
+  launch_kernel(k_update_xr, dim3(nblk), dim3(kNT), 0, st, n, sc, p, q, x, r, partial);
 }
 void launch_update_p(hipStream_t st, int nblk, int n, const PcgScalars* sc, const double* z, double* p, int first) {
-  hipLaunchKernelGGL(k_update_p, dim3(nblk), dim3(kNT), 0, st, n, sc, z, p, first);
+  launch_kernel(k_update_p, dim3(nblk), dim3(kNT), 0, st, n, sc, z, p, first);
 }
 void launch_condense(hipStream_t st, int nif, const int32_t* sh_ptr, const int32_t* sh_flat,
                      const int32_t* iface_gid, const double* f, const double* t, double* r, double* x) {
   if (nif == 0) return;
-  hipLaunchKernelGGL(k_condense, dim3(blocks_for(nif)), dim3(kNT), 0, st, nif, sh_ptr, sh_flat, iface_gid, f, t,
+  launch_kernel(k_condense, dim3(blocks_for(nif)), dim3(kNT), 0, st, nif, sh_ptr, sh_flat, iface_gid, f, t,
                      r, x);
 }
 void launch_recover(hipStream_t st, const LevelDev& L, int nImax, int ngmax, const double* x, double* u) {
   const size_t lds = sizeof(double) * ((size_t)ngmax + nImax + 1);
-  hipLaunchKernelGGL(k_recover, dim3(L.nsub), dim3(kNT), lds, st, L, x, u);
+  launch_kernel(k_recover, dim3(L.nsub), dim3(kNT), lds, st, L, x, u);
 }
 void launch_copy(hipStream_t st, int n, const double* a, double* b) {
   if (n == 0) return;
-  hipLaunchKernelGGL(k_copy, dim3(blocks_for(n)), dim3(kNT), 0, st, n, a, b);
+  launch_kernel(k_copy, dim3(blocks_for(n)), dim3(kNT), 0, st, n, a, b);
 }
 
 }  // namespace bddc

@@ -1,0 +1,327 @@
+// Deep level and coarsest solve of Algorithm "Multilevel BDDC" (Section 2.1)
+// in one cooperative launch, for hierarchies with one level between the
+// level-1 interface problem and the coarsest direct solve.
+//
+// One workgroup per level-2 substructure.  Its operators (interior factor
+// inverse, L_GI, T_rr, Psi, stiffness weights) and index lists are packed at
+// setup into one contiguous block each, so the prefetch into LDS at the start
+// is a single coalesced copy.  Phases that read other substructures' results
+// (the interface sum of the interior corrections, the coarse gather, the
+// interface sum of the prolongation) are separated by grid barriers; every
+// workgroup solves the small coarsest problem redundantly with the explicit
+// inverse of its Cholesky factor, which saves a barrier.
+#include <string>
+
+#include "common.hpp"
+#include "dense.hpp"
+#include "kernels.hpp"
+
+namespace bddc {
+
+namespace {
+
+constexpr int kSpinLimit = 1 << 22;   // about 0.1 s of polling; past it the status flags a failure
+
+// Grid barrier (sense reversal).  The launch is cooperative, so every
+// workgroup is resident; the bounded spin only guards against a broken launch.
+__device__ void grid_barrier(unsigned* bar, unsigned nblocks, int* status) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned* count = bar;
+    unsigned* gen = bar + 1;
+    const unsigned g = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned arrived = __hip_atomic_fetch_add(count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (arrived == nblocks - 1) {
+      __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(gen, g + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      int spins = 0;
+      while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        if (++spins > kSpinLimit) {
+          atomicOr(status, 4);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// out(i) = sum_{j in [j0(i), j1(i))} A[i*rs + j*cs] x[j] for i < rows, eight
+// lanes per row (fixed reduction order), then store(i, value) on lane 0 of the eight.
+template <class J0, class J1, class Store>
+__device__ inline void mv8(int rows, const double* A, int rs, int cs, const double* x, J0 j0f, J1 j1f, Store store) {
+  const int sub = threadIdx.x & 7;
+  for (int i = threadIdx.x >> 3; i < rows; i += kCoopNT / 8) {
+    double acc = 0.0;
+    const int j1 = j1f(i);
+    for (int j = j0f(i) + sub; j < j1; j += 8) acc += A[(size_t)i * rs + (size_t)j * cs] * x[j];
+    acc += __shfl_xor(acc, 1);
+    acc += __shfl_xor(acc, 2);
+    acc += __shfl_xor(acc, 4);
+    if (sub == 0) store(i, acc);
+  }
+}
+
+template <class T>
+__device__ inline void copy_batched(T* dst, const T* __restrict__ src, int n) {
+  for (int base = threadIdx.x; base < n; base += 8 * kCoopNT) {
+    T v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = (base + u * kCoopNT < n) ? src[base + u * kCoopNT] : T(0);
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (base + u * kCoopNT < n) dst[base + u * kCoopNT] = v[u];
+  }
+}
+
+}  // namespace
+
+__global__ void __launch_bounds__(kCoopNT) k_deep_coop(CoopDev C) {
+  if (C.stop && *C.stop) return;
+  extern __shared__ double sh[];
+  const int s = blockIdx.x, tid = threadIdx.x;
+  const int32_t* me = C.meta + (size_t)kCoopMeta * s;
+  const int nI = me[0], ng = me[1], nr = me[2], ncs = me[3], nsh = me[4], ng1 = me[5], goff = me[6], coff = me[7];
+  const int n = nI + ng;
+  const int ncL = C.ncL;
+  // LDS: operator block | vectors | coarsest inverse factor | ints
+  double* Li = sh;                                   // nI x nI
+  double* G = Li + (size_t)nI * nI;                  // ng x nI
+  double* Tm = G + (size_t)ng * nI;                  // nr x nr
+  double* Ps = Tm + (size_t)nr * nr;                 // ng x ncs
+  double* dl = Ps + (size_t)ng * ncs;                // ng
+  double* rI = sh + C.opmax;
+  double* rG = rI + C.nImax;
+  double* y = rG + C.ngmax;
+  double* g = y + C.nImax;
+  double* av = g + C.ngmax;
+  double* uB = av + C.ngmax;
+  double* yv = uB + C.ngmax;
+  double* ul = yv + C.nImax;
+  double* LL = ul + C.ncsmax;
+  double* rc = LL + (size_t)ncL * ncL;
+  double* wc = rc + ncL;
+  double* uc = wc + ncL;
+  int32_t* ib = reinterpret_cast<int32_t*>(uc + ncL);
+  int32_t* int_gid = ib;
+  int32_t* gam_gid = int_gid + nI;
+  int32_t* own = gam_gid + ng;
+  int32_t* shp = own + ng;
+  int32_t* shf = shp + ng + 1;
+  int32_t* gp = shf + nsh;
+  int32_t* gf = gp + n + 1;
+  int32_t* cid = gf + ng1;
+  int32_t* cg = ib + C.idxmax;
+
+  // prefetch: operators + coarsest factor inverse, and index lists + coarse
+  // gather, with every load of the first kPD / kPI per thread issued before
+  // any store (one round of memory latency); larger blocks finish in a loop
+  {
+    const double* opg = C.ops + C.opoff[s];
+    const int nop = (int)(C.opoff[s + 1] - C.opoff[s]), nll = ncL * ncL;
+    const int32_t* ixg = C.idx + C.idxoff[s];
+    const int nix = (int)(C.idxoff[s + 1] - C.idxoff[s]), ncg = C.cg_len;
+    constexpr int kPD = 24, kPI = 8;
+    double vd[kPD];
+    int32_t vi[kPI];
+#pragma unroll
+    for (int u = 0; u < kPD; ++u) {
+      const int v = tid + u * kCoopNT;
+      vd[u] = v < nop ? opg[v] : (v < nop + nll ? C.LLinv[v - nop] : 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < kPI; ++u) {
+      const int v = tid + u * kCoopNT;
+      vi[u] = v < nix ? ixg[v] : (v < nix + ncg ? C.cg[v - nix] : 0);
+    }
+#pragma unroll
+    for (int u = 0; u < kPD; ++u) {
+      const int v = tid + u * kCoopNT;
+      if (v < nop) sh[v] = vd[u];
+      else if (v < nop + nll) LL[v - nop] = vd[u];
+    }
+#pragma unroll
+    for (int u = 0; u < kPI; ++u) {
+      const int v = tid + u * kCoopNT;
+      if (v < nix) ib[v] = vi[u];
+      else if (v < nix + ncg) cg[v - nix] = vi[u];
+    }
+    const int d0 = kPD * kCoopNT, i0 = kPI * kCoopNT;
+    if (nop > d0) copy_batched(sh + d0, opg + d0, nop - d0);
+    if (nop + nll > d0) {
+      const int l0 = d0 > nop ? d0 - nop : 0;
+      copy_batched(LL + l0, C.LLinv + l0, nll - l0);
+    }
+    if (nix > i0) copy_batched(ib + i0, ixg + i0, nix - i0);
+    if (nix + ncg > i0) {
+      const int c0 = i0 > nix ? i0 - nix : 0;
+      copy_batched(cg + c0, C.cg + c0, ncg - c0);
+    }
+  }
+  __syncthreads();
+  // r_2 on the local dofs: sums of the level-1 coarse contributions
+  for (int p = tid; p < n; p += kCoopNT) {
+    double acc = 0.0;
+    for (int q = gp[p]; q < gp[p + 1]; ++q) acc += C.b1[gf[q]];
+    if (p < nI) rI[p] = acc;
+    else rG[p - nI] = acc;
+  }
+  __syncthreads();
+  // interior correction: y = Linv r_I, t = L_GI y   (ML-uIi, ML-rBi)
+  mv8(nI, Li, 1, nI, rI, [](int) { return 0; }, [](int i) { return i + 1; }, [&](int i, double v) { y[i] = v; });
+  __syncthreads();
+  mv8(ng, G, 1, ng, y, [](int) { return 0; }, [&](int) { return nI; }, [&](int a, double v) { C.t[goff + a] = v; });
+  grid_barrier(C.bar, gridDim.x, C.status);
+  // g = delta (r_G - sum t);  a = T_rr g_r (ML-wDi);  b = Psi^T g (ML-coarse)
+  for (int a = tid; a < ng; a += kCoopNT) {
+    double v = rG[a];
+    for (int q = shp[a]; q < shp[a + 1]; ++q) v -= C.t[shf[q]];
+    g[a] = dl[a] * v;
+  }
+  __syncthreads();
+  mv8(nr, Tm, 1, nr, g, [](int) { return 0; }, [&](int) { return nr; }, [&](int a, double v) { av[a] = v; });
+  for (int a = nr + tid; a < ng; a += kCoopNT) av[a] = 0.0;
+  mv8(ncs, Ps, ng, 1, g, [](int) { return 0; }, [&](int) { return ng; },
+      [&](int k, double v) { C.b[coff + k] = v; });
+  grid_barrier(C.bar, gridDim.x, C.status);
+  // coarsest: r_c = sum of the coarse contributions, u_c = Linv^T (Linv r_c)
+  for (int k = tid; k < ncL; k += kCoopNT) {
+    double acc = 0.0;
+    for (int q = cg[k]; q < cg[k + 1]; ++q) acc += C.b[cg[ncL + 1 + q]];
+    rc[k] = acc;
+  }
+  __syncthreads();
+  mv8(ncL, LL, 1, ncL, rc, [](int) { return 0; }, [](int i) { return i + 1; }, [&](int i, double v) { wc[i] = v; });
+  __syncthreads();
+  mv8(ncL, LL, ncL, 1, wc, [](int i) { return i; }, [&](int) { return ncL; }, [&](int i, double v) { uc[i] = v; });
+  __syncthreads();
+  // v = delta (a + Psi u_c)   (ML-uBi-1 before the sum)
+  for (int k = tid; k < ncs; k += kCoopNT) ul[k] = uc[cid[k]];
+  __syncthreads();
+  mv8(ng, Ps, 1, ng, ul, [](int) { return 0; }, [&](int) { return ncs; },
+      [&](int a, double v) { C.v[goff + a] = dl[a] * (av[a] + v); });
+  grid_barrier(C.bar, gridDim.x, C.status);
+  // u_B = sum over sharers of v (owner writes);  u_I = Linv^T (y - L_GI^T u_B)   (ML-vIi, ML-ui)
+  for (int a = tid; a < ng; a += kCoopNT) {
+    double acc = 0.0;
+    for (int q = shp[a]; q < shp[a + 1]; ++q) acc += C.v[shf[q]];
+    uB[a] = acc;
+    if (own[a]) C.u2[gam_gid[a]] = acc;
+  }
+  __syncthreads();
+  mv8(nI, G, ng, 1, uB, [](int) { return 0; }, [&](int) { return ng; }, [&](int j, double v) { yv[j] = y[j] - v; });
+  __syncthreads();
+  mv8(nI, Li, nI, 1, yv, [](int i) { return i; }, [&](int) { return nI; },
+      [&](int i, double v) { C.u2[int_gid[i]] = v; });
+}
+
+size_t coop_lds(const CoopDev& C) {
+  const size_t dbl = (size_t)C.opmax + 3 * (size_t)C.nImax + 4 * (size_t)C.ngmax + (size_t)C.ncsmax +
+                     (size_t)C.ncL * C.ncL + 3 * (size_t)C.ncL;
+  return sizeof(double) * dbl + sizeof(int32_t) * ((size_t)C.idxmax + C.cg_len);
+}
+
+int coop_max_blocks(size_t lds) {
+  int dev = 0, ncu = 0, per = 0, coop = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_deep_coop, kCoopNT, lds) != hipSuccess) return 0;
+  return per * ncu;
+}
+
+// The grid barriers need every workgroup resident.  The grid is at most the
+// device's cooperative capacity (checked when the path is chosen) and follows
+// the previous kernel of the same stream, so an ordinary launch finds the
+// device free; the cooperative API guarantees residency but costs about 25 us
+// of queue synchronisation per launch, so it is used only on request
+// (BDDC_COOP_LAUNCH=1).  If residency ever failed, the bounded spin ends the
+// kernel and the status flag reports it.
+void launch_deep_coop(hipStream_t st, const CoopDev& C, bool cooperative) {
+  if (!cooperative) {
+    launch_kernel(k_deep_coop, dim3(C.nsub), dim3(kCoopNT), coop_lds(C), st, C);
+    return;
+  }
+  // a cooperative launch takes no dispatch events: record them around it instead
+  const LaunchEvents ev = g_launch_events;
+  g_launch_events = LaunchEvents{};
+  if (ev.start) (void)hipEventRecord(ev.start, st);
+  CoopDev arg = C;
+  void* args[] = {&arg};
+  const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_deep_coop), dim3(C.nsub),
+                                                  dim3(kCoopNT), args, coop_lds(C), st);
+  if (e != hipSuccess) fail(BDDC_EDEVICE, std::string("cooperative launch: ") + hipGetErrorString(e));
+  if (ev.stop) (void)hipEventRecord(ev.stop, st);
+}
+
+// pack the level-2 operators of one substructure per workgroup
+__global__ void __launch_bounds__(kNT) k_pack_coop(LevelDev L, CoopDev C) {
+  const int s = blockIdx.x;
+  const int32_t* me = C.meta + (size_t)kCoopMeta * s;
+  const int nI = me[0], ng = me[1], nr = me[2], ncs = me[3];
+  const int n = nI + ng;
+  double* o = const_cast<double*>(C.ops) + C.opoff[s];
+  const double* K = L.K + L.koff[s];
+  const double* Li = L.Linv + L.linvoff[s];
+  const double* T = L.T + L.toff[s];
+  const double* P = L.Psi + L.psioff[s];
+  for (int idx = threadIdx.x; idx < nI * nI; idx += kNT) o[idx] = Li[idx];
+  o += (size_t)nI * nI;
+  for (int idx = threadIdx.x; idx < ng * nI; idx += kNT) {
+    const int a = idx % ng, j = idx / ng;
+    o[idx] = K[nI + a + (size_t)j * n];
+  }
+  o += (size_t)ng * nI;
+  for (int idx = threadIdx.x; idx < nr * nr; idx += kNT) o[idx] = T[idx];
+  o += (size_t)nr * nr;
+  for (int idx = threadIdx.x; idx < ng * ncs; idx += kNT) o[idx] = P[idx];
+  o += (size_t)ng * ncs;
+  for (int a = threadIdx.x; a < ng; a += kNT) o[a] = L.delta[L.goff[s] + a];
+}
+
+void launch_pack_coop(hipStream_t st, const LevelDev& L, const CoopDev& C) {
+  launch_kernel(k_pack_coop, dim3(C.nsub), dim3(kNT), 0, st, L, C);
+}
+
+// X = L^{-1} for one dense lower-triangular matrix (ld ld, order m), by the
+// in-place Gauss-Jordan steps of the interior triangular inverse, in LDS
+__global__ void __launch_bounds__(kNT) k_tri_inverse_dense(const double* __restrict__ L, int ld, int m,
+                                                           double* __restrict__ X) {
+  extern __shared__ double sh[];
+  double* M = sh;
+  double* rowk = M + (size_t)m * m;
+  double* colk = rowk + m;
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < m * m; idx += kNT) {
+    const int i = idx % m, j = idx / m;
+    M[idx] = (i >= j) ? L[i + (size_t)j * ld] : 0.0;
+  }
+  __syncthreads();
+  for (int k = 0; k < m; ++k) {
+    const double d = 1.0 / M[k + (size_t)k * m];
+    for (int c = tid; c < k; c += kNT) rowk[c] = M[k + (size_t)c * m] * d;
+    for (int i = k + 1 + tid; i < m; i += kNT) colk[i] = M[i + (size_t)k * m];
+    __syncthreads();
+    for (int c = tid; c < k; c += kNT) M[k + (size_t)c * m] = rowk[c];
+    if (tid == 0) M[k + (size_t)k * m] = d;
+    const int rows = m - k - 1;
+    for (int idx = tid; idx < rows * (k + 1); idx += kNT) {
+      const int i = k + 1 + idx % rows, c = idx / rows;
+      M[i + (size_t)c * m] = (c == k) ? -colk[i] * d : M[i + (size_t)c * m] - colk[i] * rowk[c];
+    }
+    __syncthreads();
+  }
+  for (int idx = tid; idx < m * m; idx += kNT) X[idx] = M[idx];
+}
+
+void launch_tri_inverse_dense(hipStream_t st, const double* L, int ld, int m, double* X) {
+  if (m <= 0) return;
+  launch_kernel(k_tri_inverse_dense, dim3(1), dim3(kNT), sizeof(double) * ((size_t)m * m + 2 * (size_t)m), st, L,
+                ld, m, X);
+}
+
+}  // namespace bddc

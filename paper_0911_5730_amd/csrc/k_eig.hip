@@ -59,9 +59,17 @@ __global__ void __launch_bounds__(kNT) k_pair_schur(
     for (int a = 0; a < nF; ++a) perm[nR + a] = fpos[a];
   }
   __syncthreads();
-  for (int idx = tid; idx < ng * ng; idx += kNT) {
-    const int i = idx % ng, j = idx / ng;
-    M[idx] = S[perm[i] + (size_t)perm[j] * n];
+  // gather, eight loads in flight per thread
+  for (int base = tid; base < ng * ng; base += 8 * kNT) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = base + u * kNT;
+      v[u] = idx < ng * ng ? S[perm[idx % ng] + (size_t)perm[idx / ng] * n] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (base + u * kNT < ng * ng) M[base + u * kNT] = v[u];
   }
   __syncthreads();
   double* sff = Sff + inc_off[inc];
@@ -78,9 +86,8 @@ __global__ void __launch_bounds__(kNT) k_pair_schur(
   }
 }
 
-// One edge per workgroup.  Global scratch (per edge): Y (nv x nv), X (nv x ne),
-// R (ne x ne).  LDS: H and V (ne x ne each) for the Jacobi iteration, plus
-// small vectors.
+// One edge per workgroup, everything in LDS: Y (nv x nv), X (nv x ne), R, G,
+// H, V (ne x ne each), the constraint columns C (ne x ne) and small vectors.
 __global__ void __launch_bounds__(kNT) k_pair_eig(
     int nedge, const int32_t* __restrict__ edge_s, const int32_t* __restrict__ edge_t,
     const int32_t* __restrict__ edge_nsc, const int32_t* __restrict__ edge_ne,
@@ -89,8 +96,7 @@ __global__ void __launch_bounds__(kNT) k_pair_eig(
     const int32_t* __restrict__ goff, const double* __restrict__ diagK,
     const uint8_t* __restrict__ floating, const double* __restrict__ z,
     const double* __restrict__ Shat, const double* __restrict__ Sff, const int64_t* __restrict__ inc_off,
-    double* __restrict__ work, const int64_t* __restrict__ woff, double tau,
-    double* __restrict__ lam_out, const int64_t* __restrict__ lamoff, double* __restrict__ Q,
+    double tau, double* __restrict__ lam_out, const int64_t* __restrict__ lamoff, double* __restrict__ Q,
     const int64_t* __restrict__ qoff, int32_t* __restrict__ nsel_out, int32_t* __restrict__ nkept_out,
     int* status) {
   extern __shared__ double lds[];
@@ -109,17 +115,19 @@ __global__ void __launch_bounds__(kNT) k_pair_eig(
   const double* Sfs = Sff + inc_off[inc_s];
   const double* Sft = Sff + inc_off[inc_t];
 
-  double* Y = work + woff[e];
-  double* X = Y + (size_t)nv * nv;
-  double* R = X + (size_t)nv * ne;
-  double* H = lds;                       // ne x ne
+  double* Y = lds;                       // nv x nv
+  double* X = Y + (size_t)nv * nv;       // nv x ne
+  double* R = X + (size_t)nv * ne;       // ne x ne
+  double* G = R + (size_t)ne * ne;       // ne x ne, later the constraint columns
+  double* H = G + (size_t)ne * ne;       // ne x ne
   double* V = H + (size_t)ne * ne;       // ne x ne
   double* ds = V + (size_t)ne * ne;      // pair weight of s on each edge dof
   double* dt = ds + ne;                  // pair weight of t (computed directly, not as 1 - ds)
   double* cs = dt + ne;                  // rotation cosines (ne/2+1)
   double* sn = cs + (ne / 2 + 1);        // rotation sines (ne/2+1)
   double* lam = sn + (ne / 2 + 1);       // ne
-  int* perm = reinterpret_cast<int*>(lam + ne);
+  double* q = lam + ne;                  // nv: z on F in v coordinates
+  int* perm = reinterpret_cast<int*>(q + nv);
 
   // pair weights on the edge dofs: delta_s^{st} = d_s / (d_s + d_t)
   for (int p = tid; p < ne; p += kNT) {
@@ -128,32 +136,33 @@ __global__ void __launch_bounds__(kNT) k_pair_eig(
     ds[p] = a / (a + b);
     dt[p] = b / (a + b);
   }
-  // M in the coordinates v = [shared corners | s-edge | t-edge]
-  for (int idx = tid; idx < nv * nv; idx += kNT) Y[idx] = 0.0;
-  __syncthreads();
-  for (int idx = tid; idx < nF * nF; idx += kNT) {   // s side: F index i is v index i
-    const int i = idx % nF, j = idx / nF;
-    Y[i + (size_t)j * nv] += Shs[idx];
-  }
-  __syncthreads();
-  for (int idx = tid; idx < nF * nF; idx += kNT) {
-    const int i = idx % nF, j = idx / nF;
-    const int vi = i < nsc ? i : i + ne;      // t-edge dof p sits at nsc + ne + p
-    const int vj = j < nsc ? j : j + ne;
-    Y[vi + (size_t)vj * nv] += Sht[idx];
-  }
-  __syncthreads();
-  if (floating[s] && floating[t]) {
-    // q = z on F in v coordinates, shift a = max diag(M)
-    double nq = 0.0, amax = 0.0;
+  const bool both_float = floating[s] && floating[t];
+  if (both_float) {
     for (int i = tid; i < nv; i += kNT) {
       const int f = i < nsc ? i : (i < nsc + ne ? i : i - ne);
-      const double qi = z[edge_fdof[edge_fptr[e] + f]];
-      nq += qi * qi;
+      q[i] = z[edge_fdof[edge_fptr[e] + f]];
+    }
+  }
+  // M in the coordinates v = [shared corners | s-edge | t-edge]: s side at F
+  // index i = v index i, t side at v index i (corners) or i + ne (t-edge)
+  for (int idx = tid; idx < nv * nv; idx += kNT) {
+    const int vi = idx % nv, vj = idx / nv;
+    double y = 0.0;
+    if (vi < nF && vj < nF) y += Shs[vi + (size_t)vj * nF];
+    const int ti = vi < nsc ? vi : (vi >= nsc + ne ? vi - ne : -1);
+    const int tj = vj < nsc ? vj : (vj >= nsc + ne ? vj - ne : -1);
+    if (ti >= 0 && tj >= 0) y += Sht[ti + (size_t)tj * nF];
+    Y[idx] = y;
+  }
+  __syncthreads();
+  if (both_float) {
+    // Y = M + a q q^T with a = max diag(M) / |q|^2
+    double nq = 0.0, amax = 0.0;
+    for (int i = tid; i < nv; i += kNT) {
+      nq += q[i] * q[i];
       amax = fmax(amax, Y[i + (size_t)i * nv]);
     }
     nq = wg_sum(nq, red);
-    // max reduction
     red[tid] = amax;
     __syncthreads();
     for (int w = kNT / 2; w > 0; w >>= 1) {
@@ -165,9 +174,7 @@ __global__ void __launch_bounds__(kNT) k_pair_eig(
     const double scale = amax / nq;
     for (int idx = tid; idx < nv * nv; idx += kNT) {
       const int i = idx % nv, j = idx / nv;
-      const int fi = i < nsc ? i : (i < nsc + ne ? i : i - ne);
-      const int fj = j < nsc ? j : (j < nsc + ne ? j : j - ne);
-      Y[idx] += scale * z[edge_fdof[edge_fptr[e] + fi]] * z[edge_fdof[edge_fptr[e] + fj]];
+      Y[idx] += scale * q[i] * q[j];
     }
     __syncthreads();
   }
@@ -179,12 +186,15 @@ __global__ void __launch_bounds__(kNT) k_pair_eig(
   }
   __syncthreads();
   wg_trsm_lower(Y, nv, nv, X, nv, ne);
-  // N_e = D_t S_s,ee D_t + D_s S_t,ee D_s  -> R (Cholesky)
+  // N_e = D_t S_s,ee D_t + D_s S_t,ee D_s  -> R (Cholesky);  G = X^T X
   for (int idx = tid; idx < ne * ne; idx += kNT) {
     const int i = idx % ne, j = idx / ne;
     const double ss = Sfs[(nsc + i) + (size_t)(nsc + j) * nF];
     const double tt = Sft[(nsc + i) + (size_t)(nsc + j) * nF];
     R[idx] = dt[i] * ss * dt[j] + ds[i] * tt * ds[j];
+    double g = 0.0;
+    for (int v = 0; v < nv; ++v) g += X[v + (size_t)i * nv] * X[v + (size_t)j * nv];
+    G[idx] = g;
   }
   __syncthreads();
   wg_potrf(R, ne, ne, status);
@@ -192,16 +202,12 @@ __global__ void __launch_bounds__(kNT) k_pair_eig(
     const int i = idx % ne, j = idx / ne;
     if (i < j) R[idx] = 0.0;
   }
-  // V = G R with G = X^T X, then H = R^T V
   __syncthreads();
+  // V = G R, then H = R^T V
   for (int idx = tid; idx < ne * ne; idx += kNT) {
     const int i = idx % ne, j = idx / ne;
     double acc = 0.0;
-    for (int k = j; k < ne; ++k) {
-      double g = 0.0;
-      for (int v = 0; v < nv; ++v) g += X[v + (size_t)i * nv] * X[v + (size_t)k * nv];
-      acc += g * R[k + (size_t)j * ne];
-    }
+    for (int k = j; k < ne; ++k) acc += G[i + (size_t)k * ne] * R[k + (size_t)j * ne];
     V[idx] = acc;
   }
   __syncthreads();
@@ -240,12 +246,12 @@ __global__ void __launch_bounds__(kNT) k_pair_eig(
       for (int k = tid; k < npair; k += kNT) {
         int a = (k == 0) ? 0 : ((k - 1 + r) % (m - 1)) + 1;
         int b = ((m - 1 - k - 1 + r) % (m - 1)) + 1;
-        int p = min(a, b), q = max(a, b);
+        int p = min(a, b), q2 = max(a, b);
         double c = 1.0, sv = 0.0;
-        if (q < ne) {
-          const double hpq = H[p + (size_t)q * ne];
+        if (q2 < ne) {
+          const double hpq = H[p + (size_t)q2 * ne];
           if (fabs(hpq) > 1e-300) {
-            const double theta = (H[q + (size_t)q * ne] - H[p + (size_t)p * ne]) / (2.0 * hpq);
+            const double theta = (H[q2 + (size_t)q2 * ne] - H[p + (size_t)p * ne]) / (2.0 * hpq);
             const double tt = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
             c = 1.0 / sqrt(tt * tt + 1.0);
             sv = tt * c;
@@ -260,12 +266,12 @@ __global__ void __launch_bounds__(kNT) k_pair_eig(
         const int k = idx % npair, col = idx / npair;
         int a = (k == 0) ? 0 : ((k - 1 + r) % (m - 1)) + 1;
         int b = ((m - 1 - k - 1 + r) % (m - 1)) + 1;
-        int p = min(a, b), q = max(a, b);
-        if (q >= ne) continue;
+        int p = min(a, b), q2 = max(a, b);
+        if (q2 >= ne) continue;
         const double c = cs[k], sv = sn[k];
-        const double hp = H[p + (size_t)col * ne], hq = H[q + (size_t)col * ne];
+        const double hp = H[p + (size_t)col * ne], hq = H[q2 + (size_t)col * ne];
         H[p + (size_t)col * ne] = c * hp - sv * hq;
-        H[q + (size_t)col * ne] = sv * hp + c * hq;
+        H[q2 + (size_t)col * ne] = sv * hp + c * hq;
       }
       __syncthreads();
       // columns: H <- H P, V <- V P
@@ -273,15 +279,15 @@ __global__ void __launch_bounds__(kNT) k_pair_eig(
         const int k = idx % npair, row = idx / npair;
         int a = (k == 0) ? 0 : ((k - 1 + r) % (m - 1)) + 1;
         int b = ((m - 1 - k - 1 + r) % (m - 1)) + 1;
-        int p = min(a, b), q = max(a, b);
-        if (q >= ne) continue;
+        int p = min(a, b), q2 = max(a, b);
+        if (q2 >= ne) continue;
         const double c = cs[k], sv = sn[k];
-        const double hp = H[row + (size_t)p * ne], hq = H[row + (size_t)q * ne];
+        const double hp = H[row + (size_t)p * ne], hq = H[row + (size_t)q2 * ne];
         H[row + (size_t)p * ne] = c * hp - sv * hq;
-        H[row + (size_t)q * ne] = sv * hp + c * hq;
-        const double vp = V[row + (size_t)p * ne], vq = V[row + (size_t)q * ne];
+        H[row + (size_t)q2 * ne] = sv * hp + c * hq;
+        const double vp = V[row + (size_t)p * ne], vq = V[row + (size_t)q2 * ne];
         V[row + (size_t)p * ne] = c * vp - sv * vq;
-        V[row + (size_t)q * ne] = sv * vp + c * vq;
+        V[row + (size_t)q2 * ne] = sv * vp + c * vq;
       }
       __syncthreads();
     }
@@ -303,22 +309,22 @@ __global__ void __launch_bounds__(kNT) k_pair_eig(
   for (int i = tid; i < ne; i += kNT) lo[i] = lam[perm[i]];
   int nsel = 0;
   for (int i = 0; i < ne; ++i) nsel += (lam[perm[i]] > tau) ? 1 : 0;
-  // constraint columns c_k = R z_k, k < nsel, then modified Gram-Schmidt
-  double* Qe = Q + qoff[e];
+  // constraint columns c_k = R z_k, k < nsel (in G), then modified Gram-Schmidt
+  double* Cc = G;
   for (int idx = tid; idx < ne * nsel; idx += kNT) {
     const int i = idx % ne, k = idx / ne;
     const double* zk = V + (size_t)perm[k] * ne;
     double acc = 0.0;
     for (int j = 0; j <= i; ++j) acc += R[i + (size_t)j * ne] * zk[j];
-    Qe[idx] = acc;
+    Cc[idx] = acc;
   }
   __syncthreads();
   int kept = 0;
   double maxnorm = 0.0;
   for (int k = 0; k < nsel; ++k) {
-    double* ck = Qe + (size_t)k * ne;
+    double* ck = Cc + (size_t)k * ne;
     for (int j = 0; j < kept; ++j) {
-      const double* qj = Qe + (size_t)j * ne;
+      const double* qj = Cc + (size_t)j * ne;
       double d = 0.0;
       for (int i = tid; i < ne; i += kNT) d += qj[i] * ck[i];
       d = wg_sum(d, red);
@@ -330,12 +336,14 @@ __global__ void __launch_bounds__(kNT) k_pair_eig(
     nn = sqrt(wg_sum(nn, red));
     maxnorm = fmax(maxnorm, nn);
     if (nn > 1e-10 * maxnorm && nn > 0.0) {
-      double* dst = Qe + (size_t)kept * ne;
+      double* dst = Cc + (size_t)kept * ne;
       for (int i = tid; i < ne; i += kNT) dst[i] = ck[i] / nn;
       ++kept;
     }
     __syncthreads();
   }
+  double* Qe = Q + qoff[e];
+  for (int idx = tid; idx < ne * nsel; idx += kNT) Qe[idx] = idx < ne * kept ? Cc[idx] : 0.0;
   if (tid == 0) {
     nsel_out[e] = nsel;
     nkept_out[e] = kept;
@@ -349,7 +357,7 @@ void launch_pair_schur(hipStream_t st, int ninc, int ngmax, const int32_t* inc_s
                        double* Sff, int* status) {
   if (ninc == 0) return;
   const size_t lds = pair_schur_lds(ngmax);
-  hipLaunchKernelGGL(k_pair_schur, dim3(ninc), dim3(kNT), lds, st, inc_sub, inc_fptr, inc_fpos, koff,
+  launch_kernel(k_pair_schur, dim3(ninc), dim3(kNT), lds, st, inc_sub, inc_fptr, inc_fpos, koff,
                      loc_ptr, nint, K, inc_off, Shat, Sff, status);
 }
 
@@ -357,22 +365,23 @@ size_t pair_schur_lds(int ngmax) {
   return sizeof(double) * (size_t)ngmax * ngmax + sizeof(int) * 2 * (size_t)ngmax + 64;
 }
 
-size_t pair_eig_lds(int nemax) {
-  return sizeof(double) * (2 * (size_t)nemax * nemax + 3 * (size_t)nemax + 2 * (nemax / 2 + 1)) +
+size_t pair_eig_lds(int nemax, int nvmax) {
+  return sizeof(double) * ((size_t)nvmax * nvmax + (size_t)nvmax * nemax + 4 * (size_t)nemax * nemax +
+                           3 * (size_t)nemax + 2 * (nemax / 2 + 1) + (size_t)nvmax) +
          sizeof(int) * (nemax + 2) + 64;
 }
 
-void launch_pair_eig(hipStream_t st, int nedge, int nemax, const int32_t* edge_s, const int32_t* edge_t,
+void launch_pair_eig(hipStream_t st, int nedge, int nemax, int nvmax, const int32_t* edge_s, const int32_t* edge_t,
                      const int32_t* edge_nsc, const int32_t* edge_ne, const int32_t* edge_fdof,
                      const int32_t* edge_fptr, const int32_t* inc_fptr, const int32_t* inc_fpos,
                      const int32_t* goff, const double* diagK, const uint8_t* floating, const double* z,
-                     const double* Shat, const double* Sff, const int64_t* inc_off, double* work,
-                     const int64_t* woff, double tau, double* lam, const int64_t* lamoff, double* Q,
-                     const int64_t* qoff, int32_t* nsel, int32_t* nkept, int* status) {
+                     const double* Shat, const double* Sff, const int64_t* inc_off, double tau, double* lam,
+                     const int64_t* lamoff, double* Q, const int64_t* qoff, int32_t* nsel, int32_t* nkept,
+                     int* status) {
   if (nedge == 0) return;
-  hipLaunchKernelGGL(k_pair_eig, dim3(nedge), dim3(kNT), pair_eig_lds(nemax), st, nedge, edge_s, edge_t,
-                     edge_nsc, edge_ne, edge_fdof, edge_fptr, inc_fptr, inc_fpos, goff, diagK, floating,
-                     z, Shat, Sff, inc_off, work, woff, tau, lam, lamoff, Q, qoff, nsel, nkept, status);
+  launch_kernel(k_pair_eig, dim3(nedge), dim3(kNT), pair_eig_lds(nemax, nvmax), st, nedge, edge_s, edge_t,
+                edge_nsc, edge_ne, edge_fdof, edge_fptr, inc_fptr, inc_fpos, goff, diagK, floating, z, Shat, Sff,
+                inc_off, tau, lam, lamoff, Q, qoff, nsel, nkept, status);
 }
 
 }  // namespace bddc

@@ -182,7 +182,7 @@ size_t deep_lds(int wstride, int ncL) {
 }
 
 void launch_deep(hipStream_t st, const DeepArgs& A) {
-  hipLaunchKernelGGL(k_deep, dim3(1), dim3(kDeepNT), deep_lds(A.wstride, A.ncL), st, A);
+  launch_kernel(k_deep, dim3(1), dim3(kDeepNT), deep_lds(A.wstride, A.ncL), st, A);
 }
 
 // ---------------------------------------------------------------- deep levels, one workgroup per substructure
@@ -253,12 +253,12 @@ __global__ void __launch_bounds__(kNT) k_apply_post_inv(LevelDev L, double* __re
 
 void launch_apply_pre_inv(hipStream_t st, const LevelDev& L, int nImax, int ngmax, const double* r) {
   const size_t lds = sizeof(double) * (2 * (size_t)nImax + kNT + ngmax + 1);
-  hipLaunchKernelGGL(k_apply_pre_inv, dim3(L.nsub), dim3(kNT), lds, st, L, r);
+  launch_kernel(k_apply_pre_inv, dim3(L.nsub), dim3(kNT), lds, st, L, r);
 }
 
 void launch_apply_post_inv(hipStream_t st, const LevelDev& L, int nImax, int ngmax, double* u) {
   const size_t lds = sizeof(double) * ((size_t)ngmax + nImax + 1);
-  hipLaunchKernelGGL(k_apply_post_inv, dim3(L.nsub), dim3(kNT), lds, st, L, u);
+  launch_kernel(k_apply_post_inv, dim3(L.nsub), dim3(kNT), lds, st, L, u);
 }
 
 // ---------------------------------------------------------------- fused PCG iteration
@@ -269,8 +269,17 @@ __device__ inline double block_sum_of(const double* __restrict__ v, int n, doubl
   return wg_sum(acc, red);
 }
 
-// p = z + beta p_prev (beta = rz_k / rz_{k-1}; p = z at it == 1), then the local
-// Schur products q_s = S_s p_s.
+// PCG iteration k on the level-1 interface (Section 5) in five launches:
+//   matvec   p_k = z + beta p_{k-1};  q_s = S_s p_s;  partial p_s^T q_s
+//   update   alpha = rz / p^T S p;  r_k = r_{k-1} - alpha sum_s q_s (every sharer
+//            forms the same value, the owner stores it and x += alpha p);
+//            partial r.r;  then the restriction of r_k (g, T_rr g_r, Psi^T g)
+//   deep     levels >= 2 and the coarsest solve
+//   prolong  convergence test on r.r, then v = delta (a + Psi u_c)
+//   post     z = sum over sharers of v and the partial r.z
+// p^T S p is summed as the local energies p_s^T S_s p_s, so the assembled q is
+// never formed; r is double-buffered by iteration parity because sharers read
+// r_{k-1} while owners write r_k.
 __global__ void __launch_bounds__(kNT) k_pcg_matvec(LevelDev L, PcgDev P, int it) {
   extern __shared__ double sh[];
   __shared__ double red[kNT];
@@ -307,79 +316,26 @@ __global__ void __launch_bounds__(kNT) k_pcg_matvec(LevelDev L, PcgDev P, int it
     part[idx] = dot_strided(S + i, n, pl, c, ng, nch);
   }
   __syncthreads();
+  double e = 0.0;
   for (int i = tid; i < ng; i += kNT) {
     double acc = 0.0;
     for (int c = 0; c < nch; ++c) acc += part[i + c * ng];
     P.qloc[g0 + i] = acc;
+    e += pl[i] * acc;
   }
+  e = wg_sum(e, red);
+  if (tid == 0) P.pq_part[s] = e;
 }
 
-// q = sum over sharers of q_s ; partial p.q
-__global__ void __launch_bounds__(kNT) k_pcg_gather_dot(LevelDev L, PcgDev P, int it) {
-  __shared__ double red[kNT];
-  if (P.sc->done) return;
-  const double* p = P.p[it & 1];
-  double acc = 0.0;
-  for (int g = blockIdx.x * kNT + threadIdx.x; g < P.nif; g += gridDim.x * kNT) {
-    double v = 0.0;
-    for (int k = L.sh_ptr[g]; k < L.sh_ptr[g + 1]; ++k) v += P.qloc[L.sh_flat[k]];
-    P.q[g] = v;
-    acc += v * p[g];
-  }
-  acc = wg_sum(acc, red);
-  if (threadIdx.x == 0) P.pq_part[blockIdx.x] = acc;
-}
-
-// alpha = rz / pq ; x += alpha p ; r -= alpha q ; partial r.r
-__global__ void __launch_bounds__(kNT) k_pcg_update(PcgDev P, int it) {
-  __shared__ double red[kNT];
-  if (P.sc->done) return;
-  const double rz = block_sum_of(P.rz_part[(it - 1) & 1], P.nsub1, red);
-  const double pq = block_sum_of(P.pq_part, P.nblk, red);
-  const double alpha = rz / pq;
-  const double* p = P.p[it & 1];
-  double acc = 0.0;
-  for (int i = blockIdx.x * kNT + threadIdx.x; i < P.nif; i += gridDim.x * kNT) {
-    P.x[i] += alpha * p[i];
-    const double ri = P.r[i] - alpha * P.q[i];
-    P.r[i] = ri;
-    acc += ri * ri;
-  }
-  acc = wg_sum(acc, red);
-  if (threadIdx.x == 0) P.rr_part[blockIdx.x] = acc;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    P.sc->iters = it;
-    P.sc->alphas[min(it - 1, kMaxHist - 1)] = alpha;
-  }
-}
-
-// Convergence test on r.r (every block takes the same decision), then the
-// level-1 restriction of the interface residual: g = delta r_G, a = T_rr g_r, b = Psi^T g.
-__global__ void __launch_bounds__(kNT) k_pcg_restrict(LevelDev L, PcgDev P, int check) {
-  extern __shared__ double sh[];
-  __shared__ double red[kNT];
-  if (P.sc->done) return;
-  if (check) {
-    const double rr = block_sum_of(P.rr_part, P.nblk, red);
-    const bool conv = rr <= P.sc->thr2;
-    const bool maxed = P.sc->iters >= P.sc->maxit;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      P.sc->rr = rr;
-      if (conv || maxed) P.sc->done = conv ? 1 : 2;
-    }
-    if (conv || maxed) return;
-  }
-  const int s = blockIdx.x;
+// The level-1 restriction of the interface residual r: g = delta r_G,
+// a = T_rr g_r, b = Psi^T g (ML-wDi, ML-coarse); g is already in LDS.
+__device__ void pcg_restrict_body(const LevelDev& L, int s, const double* g, double* part) {
   const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
   const int ng = n - L.nint[s];
   const int n_r = L.nr[s];
   const int ncs = L.coff[s + 1] - L.coff[s];
   const int g0 = L.goff[s];
-  double* g = sh;
-  double* part = sh + ng;
   const int tid = threadIdx.x;
-  for (int a = tid; a < ng; a += kNT) g[a] = L.delta[g0 + a] * P.r[L.gam_iid[g0 + a]];
-  __syncthreads();
   const double* T = L.T + L.toff[s];
   const int nch = max(1, kNT / max(1, n_r));
   for (int idx = tid; idx < n_r * nch; idx += kNT) {
@@ -404,7 +360,85 @@ __global__ void __launch_bounds__(kNT) k_pcg_restrict(LevelDev L, PcgDev P, int 
   for (int a = n_r + tid; a < ng; a += kNT) L.a[g0 + a] = 0.0;
 }
 
-// z = sum over sharers of v (owner writes) and the per-substructure partial of r.z
+// it >= 1: alpha, the residual update (r_k into r[it & 1]) and x update by the
+// owners, the partial r.r; then the restriction of r_k.  it == 0: the
+// restriction of r_0 only.
+__global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev P, int it) {
+  extern __shared__ double sh[];
+  __shared__ double red[kNT];
+  if (P.sc->done) return;
+  const int s = blockIdx.x;
+  const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
+  const int ng = n - L.nint[s];
+  const int g0 = L.goff[s];
+  const int tid = threadIdx.x;
+  double* g = sh;
+  double* part = sh + ng;
+  if (it == 0) {
+    for (int a = tid; a < ng; a += kNT) g[a] = L.delta[g0 + a] * P.r[0][L.gam_iid[g0 + a]];
+  } else {
+    const double rz = block_sum_of(P.rz_part[(it - 1) & 1], P.nsub1, red);
+    const double pq = block_sum_of(P.pq_part, P.nsub1, red);
+    const double alpha = rz / pq;
+    const double* rold = P.r[(it - 1) & 1];
+    double* rnew = P.r[it & 1];
+    const double* p = P.p[it & 1];
+    double rr = 0.0;
+    for (int a = tid; a < ng; a += kNT) {
+      const int f = g0 + a;
+      const int gi = L.gam_iid[f];
+      double q = 0.0;
+      for (int k = L.sh_ptr[gi]; k < L.sh_ptr[gi + 1]; ++k) q += P.qloc[L.sh_flat[k]];
+      const double ri = rold[gi] - alpha * q;
+      g[a] = L.delta[f] * ri;
+      if (L.sh_flat[L.sh_ptr[gi]] == f) {
+        rnew[gi] = ri;
+        P.x[gi] += alpha * p[gi];
+        rr += ri * ri;
+      }
+    }
+    rr = wg_sum(rr, red);
+    if (tid == 0) P.rr_part[s] = rr;
+    if (s == 0 && tid == 0) {
+      P.sc->iters = it;
+      P.sc->alphas[min(it - 1, kMaxHist - 1)] = alpha;
+    }
+  }
+  __syncthreads();
+  pcg_restrict_body(L, s, g, part);
+}
+
+// Convergence test on r.r (every block takes the same decision; block 0
+// records it), then v = delta (a + Psi u_c)   (ML-uBi-1 before the sum).
+__global__ void __launch_bounds__(kNT) k_pcg_prolong(LevelDev L, PcgDev P, const double* __restrict__ uc, int check) {
+  extern __shared__ double ul[];
+  __shared__ double red[kNT];
+  if (P.sc->done) return;
+  if (check) {
+    const double rr = block_sum_of(P.rr_part, P.nsub1, red);
+    const bool conv = rr <= P.sc->thr2;
+    const bool maxed = P.sc->iters >= P.sc->maxit;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      P.sc->rr = rr;
+      if (conv || maxed) P.sc->done = conv ? 1 : 2;
+    }
+    if (conv || maxed) return;
+  }
+  const int s = blockIdx.x;
+  const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
+  const int ng = n - L.nint[s];
+  const int ncs = L.coff[s + 1] - L.coff[s];
+  const int g0 = L.goff[s];
+  for (int k = threadIdx.x; k < ncs; k += kNT) ul[k] = uc[L.cid[L.coff[s] + k]];
+  __syncthreads();
+  const double* Pp = L.Psi + L.psioff[s];
+  for (int a = threadIdx.x; a < ng; a += kNT) {
+    const double w = L.a[g0 + a] + dot_strided(Pp + a, ng, ul, 0, ncs, 1);
+    L.v[g0 + a] = L.delta[g0 + a] * w;
+  }
+}
+
+// z = sum over sharers of v (owner writes) and the per-substructure partial of r_k . z
 __global__ void __launch_bounds__(kNT) k_pcg_post(LevelDev L, PcgDev P, int parity) {
   __shared__ double red[kNT];
   if (P.sc->done) return;
@@ -412,6 +446,7 @@ __global__ void __launch_bounds__(kNT) k_pcg_post(LevelDev L, PcgDev P, int pari
   const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
   const int ng = n - L.nint[s];
   const int g0 = L.goff[s];
+  const double* r = P.r[parity];
   double acc = 0.0;
   for (int a = threadIdx.x; a < ng; a += kNT) {
     const int f = g0 + a;
@@ -420,7 +455,7 @@ __global__ void __launch_bounds__(kNT) k_pcg_post(LevelDev L, PcgDev P, int pari
     double v = 0.0;
     for (int k = L.sh_ptr[gi]; k < L.sh_ptr[gi + 1]; ++k) v += L.v[L.sh_flat[k]];
     P.z[gi] = v;
-    acc += v * P.r[gi];
+    acc += v * r[gi];
   }
   acc = wg_sum(acc, red);
   if (threadIdx.x == 0) P.rz_part[parity][s] = acc;
@@ -428,21 +463,17 @@ __global__ void __launch_bounds__(kNT) k_pcg_post(LevelDev L, PcgDev P, int pari
 
 void launch_pcg_matvec(hipStream_t st, const LevelDev& L, int ngmax, const PcgDev& P, int it) {
   const size_t lds = sizeof(double) * ((size_t)ngmax + kNT + ngmax);
-  hipLaunchKernelGGL(k_pcg_matvec, dim3(L.nsub), dim3(kNT), lds, st, L, P, it);
+  launch_kernel(k_pcg_matvec, dim3(L.nsub), dim3(kNT), lds, st, L, P, it);
 }
-void launch_pcg_gather_dot(hipStream_t st, const LevelDev& L, const PcgDev& P, int it) {
-  hipLaunchKernelGGL(k_pcg_gather_dot, dim3(P.nblk), dim3(kNT), 0, st, L, P, it);
-}
-void launch_pcg_update(hipStream_t st, const PcgDev& P, int it) {
-  hipLaunchKernelGGL(k_pcg_update, dim3(P.nblk), dim3(kNT), 0, st, P, it);
-}
-void launch_pcg_restrict(hipStream_t st, const LevelDev& L, int ngmax, const PcgDev& P, int check) {
+void launch_pcg_update_restrict(hipStream_t st, const LevelDev& L, int ngmax, const PcgDev& P, int it) {
   const size_t lds = sizeof(double) * ((size_t)ngmax + kNT + ngmax);
-  hipLaunchKernelGGL(k_pcg_restrict, dim3(L.nsub), dim3(kNT), lds, st, L, P, check);
+  launch_kernel(k_pcg_update_restrict, dim3(L.nsub), dim3(kNT), lds, st, L, P, it);
 }
-void launch_pcg_post(hipStream_t st, const LevelDev& L, int ngmax, const PcgDev& P, int parity) {
-  (void)ngmax;
-  hipLaunchKernelGGL(k_pcg_post, dim3(L.nsub), dim3(kNT), 0, st, L, P, parity);
+void launch_pcg_prolong(hipStream_t st, const LevelDev& L, int ncsmax, const PcgDev& P, const double* uc, int check) {
+  launch_kernel(k_pcg_prolong, dim3(L.nsub), dim3(kNT), sizeof(double) * ((size_t)ncsmax + 1), st, L, P, uc, check);
+}
+void launch_pcg_post(hipStream_t st, const LevelDev& L, const PcgDev& P, int parity) {
+  launch_kernel(k_pcg_post, dim3(L.nsub), dim3(kNT), 0, st, L, P, parity);
 }
 
 }  // namespace bddc

@@ -6,6 +6,8 @@
 // One workgroup per substructure; every matrix is dense FP64, column-major,
 // with the substructure's local dofs ordered [interior | interface
 // non-corner | corner].
+#include <algorithm>
+
 #include "dense.hpp"
 #include "kernels.hpp"
 
@@ -354,7 +356,7 @@ void launch_assemble_l1(hipStream_t st, int nsub, const int64_t* koff, const int
                         const int32_t* nint, const int32_t* node_el, const int32_t* sub_el_ptr,
                         const int32_t* el_gid, const int32_t* el_loc, const double* coeff,
                         const Khat16& khat, double* K, double* diagK, const int32_t* goff, int* status) {
-  hipLaunchKernelGGL(k_assemble_l1, dim3(nsub), dim3(kNT), 0, st, koff, loc_ptr, nint, node_el,
+  launch_kernel(k_assemble_l1, dim3(nsub), dim3(kNT), 0, st, koff, loc_ptr, nint, node_el,
                      sub_el_ptr, el_gid, el_loc, coeff, khat, K, diagK, goff, status);
 }
 
@@ -363,21 +365,21 @@ void launch_assemble_coarse(hipStream_t st, int nsub, const int64_t* koff, const
                             const int32_t* child_map_off, const int32_t* child_map, const double* Ac,
                             const int64_t* acoff, const int32_t* nc_child, double* K, double* diagK,
                             const int32_t* goff) {
-  hipLaunchKernelGGL(k_assemble_coarse, dim3(nsub), dim3(kNT), 0, st, koff, loc_ptr, nint, child_ptr,
+  launch_kernel(k_assemble_coarse, dim3(nsub), dim3(kNT), 0, st, koff, loc_ptr, nint, child_ptr,
                      child_id, child_map_off, child_map, Ac, acoff, nc_child, K, diagK, goff);
 }
 
 void launch_weights(hipStream_t st, int nflat, const int32_t* flat_iid, const int32_t* sh_ptr,
                     const int32_t* sh_flat, const double* diagK, double* delta) {
   if (nflat == 0) return;
-  hipLaunchKernelGGL(k_weights, dim3((nflat + kNT - 1) / kNT), dim3(kNT), 0, st, nflat, flat_iid, sh_ptr,
+  launch_kernel(k_weights, dim3((nflat + kNT - 1) / kNT), dim3(kNT), 0, st, nflat, flat_iid, sh_ptr,
                      sh_flat, diagK, delta);
 }
 
 void launch_partial_chol(hipStream_t st, int nsub, int nmax, const int64_t* koff, const int32_t* loc_ptr,
                          const int32_t* nint, double* K, int* status) {
   const size_t lds = sizeof(double) * (size_t)nmax * kPanel;
-  hipLaunchKernelGGL(k_partial_chol, dim3(nsub), dim3(kNT), lds, st, koff, loc_ptr, nint, K, status);
+  launch_kernel(k_partial_chol, dim3(nsub), dim3(kNT), lds, st, koff, loc_ptr, nint, K, status);
 }
 
 size_t partial_chol_lds(int nmax) { return sizeof(double) * (size_t)nmax * kPanel; }
@@ -387,7 +389,7 @@ void launch_build_cr(hipStream_t st, int nsub, const int32_t* sub_inc_ptr, const
                      const int32_t* edge_nsc, const int32_t* edge_ne, const int32_t* edge_m,
                      const int64_t* qoff, const double* Q, const int32_t* nr, const int32_t* ncr,
                      const int64_t* croff, double* Cr) {
-  hipLaunchKernelGGL(k_build_cr, dim3(nsub), dim3(kNT), 0, st, sub_inc_ptr, sub_inc, inc_edge, inc_fptr,
+  launch_kernel(k_build_cr, dim3(nsub), dim3(kNT), 0, st, sub_inc_ptr, sub_inc, inc_edge, inc_fptr,
                      inc_fpos, edge_nsc, edge_ne, edge_m, qoff, Q, nr, ncr, croff, Cr);
 }
 
@@ -395,7 +397,7 @@ void launch_coarse_z(hipStream_t st, int nc, const int32_t* cd_dof, const int32_
                      const int32_t* edge_ptr, const int32_t* edge_dof, const int64_t* qoff,
                      const double* Q, const double* z, double* znext) {
   if (nc == 0) return;
-  hipLaunchKernelGGL(k_coarse_z, dim3((nc + kNT - 1) / kNT), dim3(kNT), 0, st, nc, cd_dof, cd_col,
+  launch_kernel(k_coarse_z, dim3((nc + kNT - 1) / kNT), dim3(kNT), 0, st, nc, cd_dof, cd_col,
                      edge_ptr, edge_dof, qoff, Q, z, znext);
 }
 
@@ -404,13 +406,13 @@ void launch_constrained_factor(hipStream_t st, int nsub, const int64_t* koff, co
                                const int64_t* croff, const double* Cr, const double* K, double* T,
                                const int64_t* toff, double* Psi, const int64_t* psioff, double* Ac,
                                const int64_t* acoff, double* work, const int64_t* woff, int* status) {
-  hipLaunchKernelGGL(k_constrained_factor, dim3(nsub), dim3(kNT), 0, st, koff, loc_ptr, nint, nr, ncr,
+  launch_kernel(k_constrained_factor, dim3(nsub), dim3(kNT), 0, st, koff, loc_ptr, nint, nr, ncr,
                      croff, Cr, K, T, toff, Psi, psioff, Ac, acoff, work, woff, status);
 }
 
 void launch_coarsest_factor(hipStream_t st, int nsub, int nc, const int32_t* cptr, const int32_t* cid,
                             const double* Ac, const int64_t* acoff, double* AL, int* status) {
-  hipLaunchKernelGGL(k_coarsest_factor, dim3(1), dim3(kNT), 0, st, nsub, nc, cptr, cid, Ac, acoff, AL,
+  launch_kernel(k_coarsest_factor, dim3(1), dim3(kNT), 0, st, nsub, nc, cptr, cid, Ac, acoff, AL,
                      status);
 }
 
@@ -443,7 +445,442 @@ __global__ void __launch_bounds__(kNT) k_tri_inverse(const int64_t* __restrict__
 
 void launch_tri_inverse(hipStream_t st, int nsub, const int64_t* koff, const int32_t* loc_ptr,
                         const int32_t* nint, const double* K, double* Linv, const int64_t* linvoff) {
-  hipLaunchKernelGGL(k_tri_inverse, dim3(nsub), dim3(kNT), 0, st, koff, loc_ptr, nint, K, Linv, linvoff);
+  launch_kernel(k_tri_inverse, dim3(nsub), dim3(kNT), 0, st, koff, loc_ptr, nint, K, Linv, linvoff);
+}
+
+}  // namespace bddc
+
+namespace bddc {
+
+// ---------------------------------------------------------------------------
+// Interior elimination with FP64 MFMA (v_mfma_f64_16x16x4f64): blocked
+// right-looking Cholesky of the first nI columns of K_s.
+//  * A panel of nb (<= 64) columns and all rows below its top is staged in LDS.
+//  * The panel is factored in 16-column sub-panels: each thread holds one or two
+//    rows of the sub-panel in registers and the sub-panel's own column entries
+//    are broadcast through LDS, one step per column; the remaining panel columns
+//    are then updated with MFMA from LDS.
+//  * The rank-nb update of the trailing matrix runs on the matrix cores in
+//    16 x 16 tiles of the lower triangle, read-modify-write in global memory;
+//    operands are swapped so that 16 consecutive lanes hold 16 consecutive
+//    rows of one column (coalesced).
+// MFMA operand layout: lane l supplies A[l%16][l/16] and B[l/16][l%16]; register
+// r of lane l holds D[l/16 + 4r][l%16].
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+
+constexpr int kCholNT = 512;            // threads per workgroup: 8 waves, one panel row each
+constexpr int kCholRowsMax = kCholNT;   // panel rows held in registers
+
+__global__ void __launch_bounds__(kCholNT) k_partial_chol_mfma(const int64_t* __restrict__ koff,
+                                                               const int32_t* __restrict__ loc_ptr,
+                                                               const int32_t* __restrict__ nint,
+                                                               double* __restrict__ K, int nb, int* status) {
+  extern __shared__ double P[];
+  __shared__ double bc[2][16];
+  constexpr int NW = kCholNT / 64;
+  const int s = blockIdx.x;
+  const int n = loc_ptr[s + 1] - loc_ptr[s];
+  const int nI = nint[s];
+  double* A = K + koff[s];
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  for (int k0 = 0; k0 < nI; k0 += nb) {
+    const int kb = min(nb, nI - k0);
+    const int kb16 = (kb + 15) & ~15;          // panel width padded to the sub-panel width
+    const int m = n - k0;                       // panel rows
+    const int mp = (m + 15) & ~15;              // rows padded to the tile size
+    // panel load, eight loads in flight per thread
+    const int tot = mp * kb16;
+    for (int base = tid; base < tot; base += 8 * kCholNT) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int idx = base + u * kCholNT;
+        const int i = idx % mp, p = idx / mp;
+        v[u] = (idx < tot && i < m && p < kb) ? A[(k0 + i) + (size_t)(k0 + p) * n] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (base + u * kCholNT < tot) P[base + u * kCholNT] = v[u];
+    }
+    __syncthreads();
+    for (int jb = 0; jb < kb; jb += 16) {
+      const int w = min(16, kb - jb);
+      const int ia = jb + tid;                  // sub-panel row of this thread, in registers
+      double ra[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) ra[c] = ia < m ? P[ia + (jb + c) * mp] : 0.0;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        if (j < w) {
+          if (tid < w) bc[j & 1][tid] = ra[j];   // rows jb .. jb+w-1 are owned by threads 0 .. w-1
+          __syncthreads();
+          const double d = bc[j & 1][j];
+          const bool ok = d > 0.0 && d < 1e308;
+          if (!ok && tid == 0) flag_bad(status);
+          const double sq = ok ? sqrt(d) : 1.0;
+          const double inv = 1.0 / sq;
+          if (ia == jb + j) ra[j] = sq;
+          if (ia > jb + j && ia < m) {
+            const double l = ra[j] * inv;
+            ra[j] = l;
+#pragma unroll
+            for (int c = 0; c < 16; ++c)
+              if (c > j && c < w && ia - jb >= c) ra[c] -= l * (bc[j & 1][c] * inv);
+          }
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 16; ++c)
+        if (c < w && ia < m) P[ia + (jb + c) * mp] = ra[c];
+      __syncthreads();
+      // remaining panel columns [jb+16, kb): P[i][c] -= sum_{p<16} P[i][jb+p] P[c][jb+p], i >= c
+      const int ct0 = (jb + 16) / 16;
+      const int nct = kb16 / 16 - ct0;
+      const int nrt = mp / 16 - ct0;
+      if (nct > 0) {
+        const int ntiles = nct * nrt - nct * (nct - 1) / 2;   // row tile >= column tile
+        for (int t = wave; t < ntiles; t += NW) {
+          int tc = 0, rem = t;
+          while (rem >= nrt - tc) { rem -= nrt - tc; ++tc; }
+          const int ti = tc + rem;
+          const int rrow = (ct0 + ti) * 16, rcol = (ct0 + tc) * 16;
+          const int kq = lane >> 4;
+          mfma_d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int kk = 0; kk < 16; kk += 4) {
+            const double a = P[rrow + (lane & 15) + (jb + kk + kq) * mp];
+            const double b = P[rcol + (lane & 15) + (jb + kk + kq) * mp];
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+          }
+          const int col = rcol + (lane & 15);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = rrow + (lane >> 4) + 4 * r;
+            if (row < m && col < kb && row >= col) P[row + col * mp] -= acc[r];
+          }
+        }
+      }
+      __syncthreads();
+    }
+    for (int idx = tid; idx < m * kb; idx += kCholNT) {
+      const int i = idx % m, p = idx / m;
+      if (i >= p) A[(k0 + i) + (size_t)(k0 + p) * n] = P[i + p * mp];
+    }
+    // trailing update of rows/cols [kb, m) of the panel frame, lower tiles, two tiles per wave in flight
+    const int t0 = kb;
+    const int nt = (m - kb + 15) / 16;
+    const int ntiles = nt * (nt + 1) / 2;
+    const int kbp = (kb + 3) & ~3;
+    const int kq = lane >> 4;
+    for (int t = wave; t < ntiles; t += 2 * NW) {
+      int ti[2], tc[2];
+      bool live[2];
+      double cv[2][4];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int tt = t + h * NW;
+        live[h] = tt < ntiles;
+        int c = 0, rem = live[h] ? tt : 0;
+        while (rem >= nt - c) { rem -= nt - c; ++c; }
+        tc[h] = c;
+        ti[h] = c + rem;
+        const int row = t0 + ti[h] * 16 + (lane & 15);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int col = t0 + tc[h] * 16 + kq + 4 * r;
+          cv[h][r] = (live[h] && row < m && col < m && row >= col) ? A[(k0 + row) + (size_t)(k0 + col) * n] : 0.0;
+        }
+      }
+      mfma_d4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+      const int rc0 = t0 + tc[0] * 16 + (lane & 15), rr0 = t0 + ti[0] * 16 + (lane & 15);
+      const int rc1 = t0 + tc[1] * 16 + (lane & 15), rr1 = t0 + ti[1] * 16 + (lane & 15);
+      for (int kk = 0; kk < kbp; kk += 4) {
+        const int off = (kk + kq) * mp;
+        const double a0 = (rc0 < mp) ? P[rc0 + off] : 0.0;
+        const double b0 = (rr0 < mp) ? P[rr0 + off] : 0.0;
+        const double a1 = (rc1 < mp) ? P[rc1 + off] : 0.0;
+        const double b1 = (rr1 < mp) ? P[rr1 + off] : 0.0;
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc1, 0, 0, 0);
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int row = t0 + ti[h] * 16 + (lane & 15);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int col = t0 + tc[h] * 16 + kq + 4 * r;
+          if (live[h] && row < m && col < m && row >= col)
+            A[(k0 + row) + (size_t)(k0 + col) * n] = cv[h][r] - (h == 0 ? acc0[r] : acc1[r]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  const int ng = n - nI;
+  for (int idx = tid; idx < ng * ng; idx += kCholNT) {
+    const int i = idx % ng, c = idx / ng;
+    if (i < c) A[(nI + i) + (size_t)(nI + c) * n] = A[(nI + c) + (size_t)(nI + i) * n];
+  }
+}
+
+// panel width for substructures of at most nmax local dofs (0: not supported)
+int partial_chol_mfma_nb(int nmax) {
+  if (nmax > kCholRowsMax) return 0;
+  const int mp = (nmax + 15) & ~15;
+  int nb = (int)((160 * 1024 - 1024) / ((size_t)mp * sizeof(double)));
+  nb = std::min(64, nb) & ~15;
+  return nb;
+}
+
+size_t partial_chol_mfma_lds(int nmax) {
+  const int mp = (nmax + 15) & ~15;
+  return sizeof(double) * (size_t)mp * partial_chol_mfma_nb(nmax);
+}
+
+void launch_partial_chol_mfma(hipStream_t st, int nsub, int nmax, const int64_t* koff, const int32_t* loc_ptr,
+                              const int32_t* nint, double* K, int* status) {
+  const int nb = partial_chol_mfma_nb(nmax);
+  launch_kernel(k_partial_chol_mfma, dim3(nsub), dim3(kCholNT), partial_chol_mfma_lds(nmax), st, koff, loc_ptr,
+                nint, K, nb, status);
+}
+
+}  // namespace bddc
+
+namespace bddc {
+
+// ---------------------------------------------------------------------------
+// LDS-resident variants of the local coarse-space factorization and of the
+// interior triangular inverse: every intermediate stays in LDS, and each
+// elimination step is one parallel rank-1 update between two barriers.
+
+// In-place Gauss-Jordan inverse of an SPD matrix M (m x m, ld m) in LDS, no
+// pivoting (every pivot is a Schur complement diagonal of an SPD matrix).
+// tc, tr: 2m doubles of LDS scratch.
+__device__ void wg_gj_inverse_spd(double* M, int m, double* tc, double* tr, int* status) {
+  const int tid = threadIdx.x;
+  for (int k = 0; k < m; ++k) {
+    for (int i = tid; i < m; i += kNT) {
+      tc[i] = M[i + (size_t)k * m];
+      tr[i] = M[k + (size_t)i * m];
+    }
+    __syncthreads();
+    const double p = tc[k];
+    const bool ok = p > 0.0 && p < 1e308;
+    if (!ok && tid == 0) flag_bad(status);
+    const double ip = ok ? 1.0 / p : 0.0;
+    for (int idx = tid; idx < m * m; idx += kNT) {
+      const int i = idx % m, j = idx / m;
+      double v;
+      if (i == k) v = (j == k) ? ip : tr[j] * ip;
+      else if (j == k) v = -tc[i] * ip;
+      else v = M[idx] - tc[i] * tr[j] * ip;
+      M[idx] = v;
+    }
+    __syncthreads();
+  }
+}
+
+// C (m x n, ldc) = alpha * op(A) op(B) + beta * C with every operand in LDS or global
+__device__ inline void wg_gemm_nn(int m, int n, int k, double alpha, const double* A, int lda, const double* B, int ldb,
+                                  double beta, double* C, int ldc) {
+  for (int idx = threadIdx.x; idx < m * n; idx += kNT) {
+    const int i = idx % m, j = idx / m;
+    double acc = 0.0;
+    for (int p = 0; p < k; ++p) acc += A[i + (size_t)p * lda] * B[p + (size_t)j * ldb];
+    C[i + (size_t)j * ldc] = (beta == 0.0 ? 0.0 : beta * C[i + (size_t)j * ldc]) + alpha * acc;
+  }
+}
+
+// LDS doubles of k_constrained_factor_lds for one substructure
+__host__ __device__ inline size_t cf_lds_doubles(int ng, int n_r, int n_cr, int ncs) {
+  const size_t a = (size_t)n_r * n_r + 3 * (size_t)n_r * n_cr + (size_t)n_cr * n_cr + 2 * (size_t)(n_r > n_cr ? n_r : n_cr);
+  const size_t b = (size_t)ng * ncs;
+  return (size_t)ng * ng + b + (a > b ? a : b);
+}
+
+// Same outputs as k_constrained_factor (T_rr, Psi, A_c), computed as
+//   M = S_rr^{-1} (Gauss-Jordan), X = M C_r^T, F = C_r X, F^{-1} (Gauss-Jordan),
+//   Z = X F^{-1}, T_rr = M - Z X^T (symmetrized), Psi_r = [-T_rr S_rc, Z],
+//   A_c = Psi^T (S Psi) (symmetrized).
+__global__ void __launch_bounds__(kNT) k_constrained_factor_lds(
+    const int64_t* __restrict__ koff, const int32_t* __restrict__ loc_ptr, const int32_t* __restrict__ nint,
+    const int32_t* __restrict__ nr, const int32_t* __restrict__ ncr, const int64_t* __restrict__ croff,
+    const double* __restrict__ Cr, const double* __restrict__ K, double* __restrict__ T,
+    const int64_t* __restrict__ toff, double* __restrict__ Psi, const int64_t* __restrict__ psioff,
+    double* __restrict__ Ac, const int64_t* __restrict__ acoff, int* status) {
+  extern __shared__ double sh[];
+  const int s = blockIdx.x;
+  const int n = loc_ptr[s + 1] - loc_ptr[s];
+  const int nI = nint[s];
+  const int ng = n - nI;
+  const int n_r = nr[s];
+  const int n_c = ng - n_r;
+  const int n_cr = ncr[s];
+  const int ncs = n_c + n_cr;
+  const double* Sg = K + koff[s] + nI + (size_t)nI * n;  // ld n, full symmetric
+  const double* C = Cr + croff[s];                       // n_cr x n_r, ld n_cr
+  const int tid = threadIdx.x;
+  double* S = sh;                                        // ng x ng, ld ng (staged Schur complement)
+  double* Ps = S + (size_t)ng * ng;                      // ng x ncs
+  double* M = Ps + (size_t)ng * ncs;                     // n_r x n_r
+  double* Cl = M + (size_t)n_r * n_r;                    // n_cr x n_r
+  double* X = Cl + (size_t)n_cr * n_r;                   // n_r x n_cr
+  double* F = X + (size_t)n_r * n_cr;                    // n_cr x n_cr
+  double* Z = F + (size_t)n_cr * n_cr;                   // n_r x n_cr
+  double* tc = Z + (size_t)n_r * n_cr;
+  double* tr = tc + (n_r > n_cr ? n_r : n_cr);
+  double* W = M;                                         // ng x ncs, after M .. Z are dead
+
+  {
+    // stage S and C, eight loads in flight per thread
+    const int t1 = ng * ng, t2 = t1 + n_cr * n_r;
+    for (int base = tid; base < t2; base += 8 * kNT) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int idx = base + u * kNT;
+        v[u] = idx < t1 ? Sg[(idx % ng) + (size_t)(idx / ng) * n] : (idx < t2 ? C[idx - t1] : 0.0);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int idx = base + u * kNT;
+        if (idx < t1) S[idx] = v[u];
+        else if (idx < t2) Cl[idx - t1] = v[u];
+      }
+    }
+  }
+  __syncthreads();
+  for (int idx = tid; idx < n_r * n_r; idx += kNT) {
+    const int i = idx % n_r, j = idx / n_r;
+    M[idx] = S[i + (size_t)j * ng];
+  }
+  __syncthreads();
+  wg_gj_inverse_spd(M, n_r, tc, tr, status);             // M = S_rr^{-1}
+  if (n_cr > 0) {
+    for (int idx = tid; idx < n_r * n_cr; idx += kNT) {  // X = M C^T
+      const int i = idx % n_r, j = idx / n_r;
+      double acc = 0.0;
+      for (int p = 0; p < n_r; ++p) acc += M[i + (size_t)p * n_r] * Cl[j + (size_t)p * n_cr];
+      X[idx] = acc;
+    }
+    __syncthreads();
+    wg_gemm_nn(n_cr, n_cr, n_r, 1.0, Cl, n_cr, X, n_r, 0.0, F, n_cr);   // F = C X
+    __syncthreads();
+    wg_gj_inverse_spd(F, n_cr, tc, tr, status);
+    wg_gemm_nn(n_r, n_cr, n_cr, 1.0, X, n_r, F, n_cr, 0.0, Z, n_r);     // Z = X F^{-1}
+    __syncthreads();
+    for (int idx = tid; idx < n_r * n_r; idx += kNT) {   // M -= Z X^T
+      const int i = idx % n_r, j = idx / n_r;
+      double acc = 0.0;
+      for (int p = 0; p < n_cr; ++p) acc += Z[i + (size_t)p * n_r] * X[j + (size_t)p * n_r];
+      M[idx] -= acc;
+    }
+    __syncthreads();
+  }
+  for (int idx = tid; idx < n_r * n_r; idx += kNT) {     // exact symmetry of T_rr
+    const int i = idx % n_r, j = idx / n_r;
+    if (i > j) {
+      const double v = 0.5 * (M[idx] + M[j + (size_t)i * n_r]);
+      M[idx] = v;
+      M[j + (size_t)i * n_r] = v;
+    }
+  }
+  __syncthreads();
+  // Psi: rows r, corner columns -T_rr S_rc, edge columns Z; corner rows identity
+  for (int idx = tid; idx < n_r * n_c; idx += kNT) {
+    const int i = idx % n_r, j = idx / n_r;
+    double acc = 0.0;
+    for (int p = 0; p < n_r; ++p) acc += M[i + (size_t)p * n_r] * S[p + (size_t)(n_r + j) * ng];
+    Ps[i + (size_t)j * ng] = -acc;
+  }
+  for (int idx = tid; idx < n_r * n_cr; idx += kNT) {
+    const int i = idx % n_r, j = idx / n_r;
+    Ps[i + (size_t)(n_c + j) * ng] = Z[idx];
+  }
+  for (int idx = tid; idx < n_c * ncs; idx += kNT) {
+    const int i = idx % n_c, j = idx / n_c;
+    Ps[(n_r + i) + (size_t)j * ng] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  double* Tr = T + toff[s];
+  for (int idx = tid; idx < n_r * n_r; idx += kNT) Tr[idx] = M[idx];
+  double* Pg = Psi + psioff[s];
+  for (int idx = tid; idx < ng * ncs; idx += kNT) Pg[idx] = Ps[idx];
+  __syncthreads();
+  wg_gemm_nn(ng, ncs, ng, 1.0, S, ng, Ps, ng, 0.0, W, ng);            // W = S Psi
+  __syncthreads();
+  double* Acs = Ac + acoff[s];
+  for (int idx = tid; idx < ncs * ncs; idx += kNT) {     // A_c = Psi^T W, symmetrized
+    const int i = idx % ncs, j = idx / ncs;
+    if (i < j) continue;
+    double aij = 0.0, aji = 0.0;
+    for (int p = 0; p < ng; ++p) {
+      aij += Ps[p + (size_t)i * ng] * W[p + (size_t)j * ng];
+      aji += Ps[p + (size_t)j * ng] * W[p + (size_t)i * ng];
+    }
+    const double v = (i == j) ? aij : 0.5 * (aij + aji);
+    Acs[i + (size_t)j * ncs] = v;
+    Acs[j + (size_t)i * ncs] = v;
+  }
+}
+
+size_t constrained_factor_lds(int ng, int n_r, int n_cr, int ncs) {
+  return sizeof(double) * cf_lds_doubles(ng, n_r, n_cr, ncs);
+}
+
+void launch_constrained_factor_lds(hipStream_t st, int nsub, size_t lds, const int64_t* koff, const int32_t* loc_ptr,
+                                   const int32_t* nint, const int32_t* nr, const int32_t* ncr, const int64_t* croff,
+                                   const double* Cr, const double* K, double* T, const int64_t* toff, double* Psi,
+                                   const int64_t* psioff, double* Ac, const int64_t* acoff, int* status) {
+  launch_kernel(k_constrained_factor_lds, dim3(nsub), dim3(kNT), lds, st, koff, loc_ptr, nint, nr, ncr, croff, Cr, K,
+                T, toff, Psi, psioff, Ac, acoff, status);
+}
+
+// Linv = L_II^{-1} by in-place Gauss-Jordan on the lower triangle in LDS:
+// step k scales row k by 1/L_kk and eliminates column k below the diagonal.
+__global__ void __launch_bounds__(kNT) k_tri_inverse_lds(const int64_t* __restrict__ koff,
+                                                         const int32_t* __restrict__ loc_ptr,
+                                                         const int32_t* __restrict__ nint, const double* __restrict__ K,
+                                                         double* __restrict__ Linv, const int64_t* __restrict__ linvoff) {
+  extern __shared__ double sh[];
+  const int s = blockIdx.x;
+  const int n = loc_ptr[s + 1] - loc_ptr[s];
+  const int m = nint[s];
+  const double* L = K + koff[s];
+  double* M = sh;                 // m x m, ld m (lower triangle used)
+  double* rowk = M + (size_t)m * m;
+  double* colk = rowk + m;
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < m * m; idx += kNT) {
+    const int i = idx % m, j = idx / m;
+    M[idx] = (i >= j) ? L[i + (size_t)j * n] : 0.0;
+  }
+  __syncthreads();
+  for (int k = 0; k < m; ++k) {
+    const double d = 1.0 / M[k + (size_t)k * m];
+    for (int c = tid; c < k; c += kNT) rowk[c] = M[k + (size_t)c * m] * d;
+    for (int i = k + 1 + tid; i < m; i += kNT) colk[i] = M[i + (size_t)k * m];
+    __syncthreads();
+    for (int c = tid; c < k; c += kNT) M[k + (size_t)c * m] = rowk[c];
+    if (tid == 0) M[k + (size_t)k * m] = d;
+    const int rows = m - k - 1;
+    for (int idx = tid; idx < rows * (k + 1); idx += kNT) {
+      const int i = k + 1 + idx % rows, c = idx / rows;
+      M[i + (size_t)c * m] = (c == k) ? -colk[i] * d : M[i + (size_t)c * m] - colk[i] * rowk[c];
+    }
+    __syncthreads();
+  }
+  double* X = Linv + linvoff[s];
+  for (int idx = tid; idx < m * m; idx += kNT) X[idx] = M[idx];
+}
+
+size_t tri_inverse_lds(int nImax) { return sizeof(double) * ((size_t)nImax * nImax + 2 * (size_t)nImax); }
+
+void launch_tri_inverse_lds(hipStream_t st, int nsub, int nImax, const int64_t* koff, const int32_t* loc_ptr,
+                            const int32_t* nint, const double* K, double* Linv, const int64_t* linvoff) {
+  launch_kernel(k_tri_inverse_lds, dim3(nsub), dim3(kNT), tri_inverse_lds(nImax), st, koff, loc_ptr, nint, K, Linv,
+                linvoff);
 }
 
 }  // namespace bddc

@@ -1,6 +1,7 @@
 // Device data descriptors and host launchers of libbddc's kernels.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
@@ -9,6 +10,25 @@
 namespace bddc {
 
 constexpr int kNT = 256;   // threads per workgroup (4 wave64)
+
+// Event pair that the next kernel launched from this host thread records
+// around its own execution (set by the host timing facility, empty otherwise):
+// the events are stamped at the start and end of the dispatch itself, so the
+// interval excludes the launch gap before the kernel.
+struct LaunchEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+inline thread_local LaunchEvents g_launch_events;
+
+// Every launch of the library goes through here; arguments are converted to
+// the kernel's parameter types before they are packed.
+template <class... P, class... A>
+inline void launch_kernel(void (*k)(P...), dim3 grid, dim3 block, size_t shm, hipStream_t st, A... a) {
+  const LaunchEvents ev = g_launch_events;
+  g_launch_events = LaunchEvents{};
+  hipExtLaunchKernelGGL(k, grid, block, static_cast<std::uint32_t>(shm), st, ev.start, ev.stop, 0u,
+                        static_cast<P>(a)...);
+}
 
 struct Khat16 {
   double v[16];   // 4x4 reference element matrix (k = 1), row-major, local node order CCW from (i,j)
@@ -70,17 +90,51 @@ struct DeepArgs {
   int wstride = 0;                    // per-wave LDS scratch (doubles)
 };
 
+// One deep level (level 2) and the coarsest solve in one cooperative launch:
+// one workgroup per level-2 substructure, its operators prefetched to LDS,
+// three grid barriers between the phases that read other substructures' data.
+constexpr int kCoopNT = 512;
+constexpr int kCoopMeta = 8;   // per substructure: nI, ng, nr, ncs, n_sh, n_g1, goff, coff
+struct CoopDev {
+  int nsub = 0;
+  int ncL = 0;
+  int nImax = 0, ngmax = 0, ncsmax = 0;
+  int opmax = 0;                      // largest operator block (doubles)
+  int idxmax = 0;                     // largest index block (ints)
+  int cg_len = 0;                     // coarse gather block (ints)
+  const double* ops = nullptr;        // per substructure: Linv | L_GI (ng x nI) | T_rr | Psi | delta
+  const int64_t* opoff = nullptr;
+  const int32_t* idx = nullptr;       // per substructure: int_gid | gam_gid | own | shp | shf | gp | gf | cid
+  const int64_t* idxoff = nullptr;
+  const int32_t* meta = nullptr;      // kCoopMeta ints per substructure
+  const int32_t* cg = nullptr;        // coarsest gather: ptr (ncL+1) | flat coarse indices
+  const double* LLinv = nullptr;      // inverse of the coarsest Cholesky factor, ncL x ncL lower
+  const double* b1 = nullptr;         // level-1 coarse contributions (input)
+  double* t = nullptr;                // level-2 interface flat scratch
+  double* b = nullptr;                // level-2 coarse flat scratch
+  double* v = nullptr;                // level-2 interface flat scratch
+  double* u2 = nullptr;               // level-2 solution (output)
+  const int32_t* stop = nullptr;
+  unsigned* bar = nullptr;            // grid barrier: count, generation
+  int* status = nullptr;
+};
+size_t coop_lds(const CoopDev& C);
+void launch_deep_coop(hipStream_t st, const CoopDev& C, bool cooperative);
+void launch_pack_coop(hipStream_t st, const LevelDev& L, const CoopDev& C);
+void launch_tri_inverse_dense(hipStream_t st, const double* L, int ld, int m, double* X);
+int coop_max_blocks(size_t lds);
+
 // state of the fused PCG iteration on the level-1 interface
 struct PcgDev {
   struct PcgScalars* sc = nullptr;
-  double *x = nullptr, *r = nullptr, *z = nullptr, *q = nullptr;
-  double* p[2] = {nullptr, nullptr};
-  double* pq_part = nullptr;          // per vector block
-  double* rr_part = nullptr;          // per vector block
+  double *x = nullptr, *z = nullptr;
+  double* r[2] = {nullptr, nullptr};         // residual, by iteration parity
+  double* p[2] = {nullptr, nullptr};         // search direction, by iteration parity
+  double* pq_part = nullptr;                 // per level-1 substructure: p_s^T S_s p_s
+  double* rr_part = nullptr;                 // per level-1 substructure: owned r.r
   double* rz_part[2] = {nullptr, nullptr};   // per level-1 substructure, by iteration parity
-  double* qloc = nullptr;             // local Schur products, level-1 interface flat
+  double* qloc = nullptr;                    // local Schur products, level-1 interface flat
   int nif = 0;
-  int nblk = 1;                       // blocks of the vector kernels
   int nsub1 = 0;
 };
 
@@ -108,6 +162,18 @@ void launch_weights(hipStream_t st, int nflat, const int32_t* flat_iid, const in
 void launch_partial_chol(hipStream_t st, int nsub, int nmax, const int64_t* koff, const int32_t* loc_ptr,
                          const int32_t* nint, double* K, int* status);
 size_t partial_chol_lds(int nmax);
+int partial_chol_mfma_nb(int nmax);
+size_t constrained_factor_lds(int ng, int n_r, int n_cr, int ncs);
+void launch_constrained_factor_lds(hipStream_t st, int nsub, size_t lds, const int64_t* koff, const int32_t* loc_ptr,
+                                   const int32_t* nint, const int32_t* nr, const int32_t* ncr, const int64_t* croff,
+                                   const double* Cr, const double* K, double* T, const int64_t* toff, double* Psi,
+                                   const int64_t* psioff, double* Ac, const int64_t* acoff, int* status);
+size_t tri_inverse_lds(int nImax);
+void launch_tri_inverse_lds(hipStream_t st, int nsub, int nImax, const int64_t* koff, const int32_t* loc_ptr,
+                            const int32_t* nint, const double* K, double* Linv, const int64_t* linvoff);
+size_t partial_chol_mfma_lds(int nmax);
+void launch_partial_chol_mfma(hipStream_t st, int nsub, int nmax, const int64_t* koff, const int32_t* loc_ptr,
+                              const int32_t* nint, double* K, int* status);
 void launch_build_cr(hipStream_t st, int nsub, const int32_t* sub_inc_ptr, const int32_t* sub_inc,
                      const int32_t* inc_edge, const int32_t* inc_fptr, const int32_t* inc_fpos,
                      const int32_t* edge_nsc, const int32_t* edge_ne, const int32_t* edge_m,
@@ -130,14 +196,14 @@ void launch_pair_schur(hipStream_t st, int ninc, int ngmax, const int32_t* inc_s
                        const int32_t* nint, const double* K, const int64_t* inc_off, double* Shat,
                        double* Sff, int* status);
 size_t pair_schur_lds(int ngmax);
-size_t pair_eig_lds(int nemax);
-void launch_pair_eig(hipStream_t st, int nedge, int nemax, const int32_t* edge_s, const int32_t* edge_t,
+size_t pair_eig_lds(int nemax, int nvmax);
+void launch_pair_eig(hipStream_t st, int nedge, int nemax, int nvmax, const int32_t* edge_s, const int32_t* edge_t,
                      const int32_t* edge_nsc, const int32_t* edge_ne, const int32_t* edge_fdof,
                      const int32_t* edge_fptr, const int32_t* inc_fptr, const int32_t* inc_fpos,
                      const int32_t* goff, const double* diagK, const uint8_t* floating, const double* z,
-                     const double* Shat, const double* Sff, const int64_t* inc_off, double* work,
-                     const int64_t* woff, double tau, double* lam, const int64_t* lamoff, double* Q,
-                     const int64_t* qoff, int32_t* nsel, int32_t* nkept, int* status);
+                     const double* Shat, const double* Sff, const int64_t* inc_off, double tau, double* lam,
+                     const int64_t* lamoff, double* Q, const int64_t* qoff, int32_t* nsel, int32_t* nkept,
+                     int* status);
 
 // apply and PCG
 void launch_apply_pre(hipStream_t st, const LevelDev& L, int nImax, int ngmax, const double* r);
@@ -173,9 +239,8 @@ void launch_apply_post_inv(hipStream_t st, const LevelDev& L, int nImax, int ngm
 
 // fused PCG iteration kernels (level-1 interface)
 void launch_pcg_matvec(hipStream_t st, const LevelDev& L, int ngmax, const PcgDev& P, int it);
-void launch_pcg_gather_dot(hipStream_t st, const LevelDev& L, const PcgDev& P, int it);
-void launch_pcg_update(hipStream_t st, const PcgDev& P, int it);
-void launch_pcg_restrict(hipStream_t st, const LevelDev& L, int ngmax, const PcgDev& P, int check);
-void launch_pcg_post(hipStream_t st, const LevelDev& L, int ngmax, const PcgDev& P, int parity);
+void launch_pcg_update_restrict(hipStream_t st, const LevelDev& L, int ngmax, const PcgDev& P, int it);
+void launch_pcg_prolong(hipStream_t st, const LevelDev& L, int ncsmax, const PcgDev& P, const double* uc, int check);
+void launch_pcg_post(hipStream_t st, const LevelDev& L, const PcgDev& P, int parity);
 
 }  // namespace bddc

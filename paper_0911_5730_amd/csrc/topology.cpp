@@ -2,6 +2,9 @@
 #include "topology.hpp"
 
 #include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <string>
 #include <unordered_set>
 
@@ -18,11 +21,20 @@ inline uint64_t pair_key(int s, int t) {
 Topology classify(int n, int nsub, const std::vector<int32_t>& elem_ptr,
                   const std::vector<int32_t>& elem_dof, const std::vector<int32_t>& elem_sub,
                   const std::vector<uint8_t>& elem_touch) {
+  const bool timing = getenv("BDDC_HOST_TIMING") != nullptr;
+  auto t0 = std::chrono::steady_clock::now();
+  auto lap = [&](const char* what) {
+    if (!timing) return;
+    const auto now = std::chrono::steady_clock::now();
+    fprintf(stderr, "libbddc classify %-12s %8.3f ms\n", what, std::chrono::duration<double, std::milli>(now - t0).count());
+    t0 = now;
+  };
   Topology T;
   T.n = n;
   T.nsub = nsub;
   T.nshare.assign(n, 0);
-  T.share.resize(n);
+  T.share_.reset(new int32_t[(size_t)std::max(n, 1) * kMaxShare]);
+  int32_t* share = T.share_.get();
   T.floating.assign(nsub, 1);
   T.is_corner.assign(n, 0);
   const int ne = static_cast<int>(elem_sub.size());
@@ -38,6 +50,7 @@ Topology classify(int n, int nsub, const std::vector<int32_t>& elem_ptr,
     std::vector<int32_t> pos(sptr.begin(), sptr.end() - 1);
     for (int e = 0; e < ne; ++e) order[pos[elem_sub[e]]++] = e;
   }
+  lap("group");
 
   // N_d (ascending because substructures are visited in order) and raw local dof lists
   std::vector<int32_t> mark(n, -1);
@@ -52,20 +65,34 @@ Topology classify(int n, int nsub, const std::vector<int32_t>& elem_ptr,
         if (mark[d] == s) continue;
         mark[d] = s;
         if (T.nshare[d] >= kMaxShare) fail(BDDC_EUNSUPPORTED, "a dof is shared by too many substructures");
-        T.share[d][T.nshare[d]++] = s;
+        share[(size_t)d * kMaxShare + T.nshare[d]++] = s;
         raw.push_back(d);
       }
     }
     raw_ptr[s + 1] = static_cast<int32_t>(raw.size());
   }
+  lap("sharers");
 
-  // corners and edge candidates
-  std::vector<std::pair<uint64_t, int32_t>> cand;
+  // corners and edge candidates, ordered by (s, t, dof): counting sort by s
+  // (dofs visited in increasing order), then a small sort by t inside each bucket
+  std::vector<int32_t> bcnt(nsub + 1, 0);
+  size_t ncand = 0;
   for (int d = 0; d < n; ++d) {
     if (T.nshare[d] >= 3) T.is_corner[d] = 1;
-    else if (T.nshare[d] == 2) cand.emplace_back(pair_key(T.share[d][0], T.share[d][1]), d);
+    else if (T.nshare[d] == 2) { bcnt[T.share(d)[0] + 1]++; ++ncand; }
   }
-  std::sort(cand.begin(), cand.end());
+  for (int s = 0; s < nsub; ++s) bcnt[s + 1] += bcnt[s];
+  std::vector<std::pair<uint64_t, int32_t>> cand(ncand);
+  {
+    std::vector<int32_t> pos(bcnt.begin(), bcnt.end() - 1);
+    for (int d = 0; d < n; ++d)
+      if (T.nshare[d] == 2) cand[pos[T.share(d)[0]]++] = {pair_key(T.share(d)[0], T.share(d)[1]), d};
+  }
+  for (int s = 0; s < nsub; ++s)
+    std::stable_sort(cand.begin() + bcnt[s], cand.begin() + bcnt[s + 1],
+                     [](const std::pair<uint64_t, int32_t>& a, const std::pair<uint64_t, int32_t>& b) {
+                       return a.first < b.first;
+                     });
   // groups of candidates by pair
   std::vector<size_t> gstart;
   for (size_t i = 0; i < cand.size(); ++i)
@@ -73,12 +100,13 @@ Topology classify(int n, int nsub, const std::vector<int32_t>& elem_ptr,
   gstart.push_back(cand.size());
   const size_t ng = gstart.size() - 1;
   std::vector<uint8_t> removed(cand.size(), 0);
+  lap("candidates");
 
   std::unordered_set<uint64_t> covered;
   for (int d = 0; d < n; ++d) {
     if (!T.is_corner[d]) continue;
     for (int a = 0; a < T.nshare[d]; ++a)
-      for (int b = a + 1; b < T.nshare[d]; ++b) covered.insert(pair_key(T.share[d][a], T.share[d][b]));
+      for (int b = a + 1; b < T.nshare[d]; ++b) covered.insert(pair_key(T.share(d)[a], T.share(d)[b]));
   }
   // rule: a pair with a floating member shares at least one corner
   for (size_t g = 0; g < ng; ++g) {
@@ -112,6 +140,7 @@ Topology classify(int n, int nsub, const std::vector<int32_t>& elem_ptr,
       if (!removed[i]) { T.is_corner[cand[i].second] = 1; removed[i] = 1; break; }
   }
 
+  lap("rules");
   // final edges
   T.edge_ptr.push_back(0);
   for (size_t g = 0; g < ng; ++g) {
@@ -129,33 +158,35 @@ Topology classify(int n, int nsub, const std::vector<int32_t>& elem_ptr,
     if (T.nshare[d] >= 2) T.n_interface++;
   }
 
-  // local ordering [interior | interface non-corner | corner]
+  // local ordering [interior | interface non-corner | corner], each group in first-appearance order
   T.loc_ptr.assign(nsub + 1, 0);
   T.n_int.assign(nsub, 0);
   T.n_r.assign(nsub, 0);
   T.n_c.assign(nsub, 0);
   T.loc_dof.resize(raw.size());
   for (int s = 0; s < nsub; ++s) {
-    std::vector<int32_t> di, dr, dc;
+    int ni = 0, nr = 0, nc = 0;
     for (int k = raw_ptr[s]; k < raw_ptr[s + 1]; ++k) {
       const int d = raw[k];
-      if (T.nshare[d] == 1) di.push_back(d);
-      else if (T.is_corner[d]) dc.push_back(d);
-      else dr.push_back(d);
+      if (T.nshare[d] == 1) ++ni;
+      else if (T.is_corner[d]) ++nc;
+      else ++nr;
     }
-    std::sort(di.begin(), di.end());
-    std::sort(dr.begin(), dr.end());
-    std::sort(dc.begin(), dc.end());
-    T.n_int[s] = static_cast<int32_t>(di.size());
-    T.n_r[s] = static_cast<int32_t>(dr.size());
-    T.n_c[s] = static_cast<int32_t>(dc.size());
-    int o = raw_ptr[s];
-    T.loc_ptr[s] = o;
-    for (int d : di) T.loc_dof[o++] = d;
-    for (int d : dr) T.loc_dof[o++] = d;
-    for (int d : dc) T.loc_dof[o++] = d;
+    T.n_int[s] = ni;
+    T.n_r[s] = nr;
+    T.n_c[s] = nc;
+    const int b = raw_ptr[s];
+    T.loc_ptr[s] = b;
+    int oi = b, orr = b + ni, oc = b + ni + nr;
+    for (int k = raw_ptr[s]; k < raw_ptr[s + 1]; ++k) {
+      const int d = raw[k];
+      if (T.nshare[d] == 1) T.loc_dof[oi++] = d;
+      else if (T.is_corner[d]) T.loc_dof[oc++] = d;
+      else T.loc_dof[orr++] = d;
+    }
   }
   T.loc_ptr[nsub] = raw_ptr[nsub];
+  lap("local order");
   return T;
 }
 

@@ -16,20 +16,23 @@
 
 #include <array>
 #include <cstdint>
+#include <memory>
 #include <vector>
 
 namespace bddc {
 
-constexpr int kMaxShare = 8;   // substructures that may share one dof
+constexpr int kMaxShare = 4;   // substructures that may share one dof (a node of a 2D quad mesh touches <= 4 elements)
 
 struct Topology {
   int n = 0;                        // dofs of the level
   int nsub = 0;
   std::vector<uint8_t> nshare;      // |N_d|
-  std::vector<std::array<int32_t, kMaxShare>> share;  // N_d, ascending
+  std::unique_ptr<int32_t[]> share_;  // N_d, ascending: share(d)[0 .. nshare[d])
+  const int32_t* share(int d) const { return share_.get() + (size_t)d * kMaxShare; }
   std::vector<uint8_t> is_corner;
   std::vector<uint8_t> floating;    // per substructure: no Dirichlet contact
-  // local dofs of each substructure ordered [interior | interface non-corner | corner], each ascending
+  // local dofs of each substructure ordered [interior | interface non-corner | corner]; inside each
+  // group the order is that of first appearance in the substructure's elements (ascending element id)
   std::vector<int32_t> loc_ptr, loc_dof;
   std::vector<int32_t> n_int, n_r, n_c;
   std::vector<int32_t> corners;     // ascending

@@ -70,10 +70,11 @@ def test_solve_and_apply_match_oracle(name):
         S.close()
 
 
-@pytest.mark.parametrize("path", ["fused", "levels"])
+@pytest.mark.parametrize("path", ["coop", "fused", "levels"])
 def test_deep_level_paths(path, monkeypatch):
-    """Levels >= 2 run either in one fused workgroup or one workgroup per
-    substructure; both must match the oracle."""
+    """Levels >= 2 run in one cooperative launch with one workgroup per
+    level-2 substructure (one deep level), in one fused workgroup, or in one
+    launch per phase and level; all must match the oracle."""
     monkeypatch.setenv("BDDC_DEEP_PATH", path)
     prob = _case("adaptive3")
     S, B, ug, it, rr, o = run_pair(prob)
@@ -85,5 +86,29 @@ def test_deep_level_paths(path, monkeypatch):
         zo = B.apply(r)
         assert np.linalg.norm(zg - zo) <= 1e-11 * np.linalg.norm(zo)
         check_solution(S, B, ug, o)
+    finally:
+        S.close()
+
+
+@pytest.mark.parametrize("path", ["default", "lds16_global"])
+def test_setup_kernel_paths(path, monkeypatch):
+    """The setup runs with 64-wide Cholesky panels and a matrix-core trailing
+    update plus LDS-resident Gauss-Jordan factorizations (default), or with
+    16-wide panels on the vector units and global-memory factorizations; both
+    must give the oracle's preconditioner (H/h = 16, ragged 64-column panels)."""
+    if path == "lds16_global":
+        monkeypatch.setenv("BDDC_CHOL_PATH", "lds16")
+        monkeypatch.setenv("BDDC_SETUP_PATH", "global")
+    prob = _case("adaptive3_h16")
+    print(f"setup kernel path {path}", flush=True)
+    S, B, ug, it, rr, o = run_pair(prob)
+    try:
+        assert abs(it - o["iters"]) <= 1
+        rng = np.random.default_rng(7)
+        r = rng.standard_normal(prob.n_free)
+        zg = S.apply(cuda_vec(r)).cpu().numpy()
+        zo = B.apply(r)
+        assert np.linalg.norm(zg - zo) <= 1e-11 * np.linalg.norm(zo)
+        check_adaptive_edges(S, B, prob.tau)
     finally:
         S.close()
