@@ -155,9 +155,11 @@ bddc_status bddc_edge_constraints(bddc_handle h, int32_t level, int32_t edge, in
  * any handle: the events are stamped by the dispatch itself, on the stream the
  * kernel runs on, so they bracket the kernel's execution only; sampling keeps
  * the events' own cost out of a timed loop.  NULL or "" disarms.  Names:
- * "schur_local", "apply_pre", "apply_restrict", "apply_prolong", "apply_post"
- * (level 1; "_l2", "_l3" ... for deeper levels), "deep" (levels >= 2 and the
- * coarsest solve in one launch), "partial_chol", "partial_chol_l2".
+ * "schur_local" (PCG operator product), "apply_restrict" (PCG update and
+ * level-1 restriction), "deep" (levels >= 2 and the coarsest solve in one
+ * launch), "apply_average" (level-1 interface average), "apply_pre_l2",
+ * "apply_restrict_l2", "apply_prolong_l2", "apply_post_l2" ("_l3" ...; deep
+ * levels when they run one launch per phase), "partial_chol", "partial_chol_l2".
  * bddc_timing_stop synchronises those events and returns the summed kernel
  * time in ms, the number of timed launches, and the summed algorithmic bytes
  * and flops of those launches (each operator and vector entry the kernel must

@@ -25,6 +25,83 @@
 
 namespace bddc {
 
+namespace {
+std::mutex g_pinned_mu;
+std::vector<std::pair<void*, size_t>> g_pinned_free;   // buffers not in use
+std::map<void*, size_t> g_pinned_size;                 // every buffer ever made
+}  // namespace
+
+void* pinned_acquire(size_t bytes) {
+  std::lock_guard<std::mutex> lk(g_pinned_mu);
+  size_t best = g_pinned_free.size();
+  for (size_t i = 0; i < g_pinned_free.size(); ++i)
+    if (g_pinned_free[i].second >= bytes && (best == g_pinned_free.size() || g_pinned_free[i].second < g_pinned_free[best].second))
+      best = i;
+  if (best < g_pinned_free.size()) {
+    void* p = g_pinned_free[best].first;
+    g_pinned_free.erase(g_pinned_free.begin() + best);
+    return p;
+  }
+  size_t n = 1 << 20;
+  while (n < bytes) n <<= 1;
+  void* p = nullptr;
+  BDDC_HIP(hipHostMalloc(&p, n, hipHostMallocDefault));
+  g_pinned_size[p] = n;
+  return p;
+}
+
+void pinned_release(void* p) {
+  if (!p) return;
+  std::lock_guard<std::mutex> lk(g_pinned_mu);
+  auto it = g_pinned_size.find(p);
+  if (it != g_pinned_size.end()) g_pinned_free.push_back({p, it->second});
+}
+
+Staging::~Staging() {
+  if (!buf_) return;
+  if (deferred_) {
+    deferred_->push_back(buf_);
+    return;
+  }
+  (void)hipStreamSynchronize(st_);
+  pinned_release(buf_);
+}
+
+void Staging::flush() {
+  if (items_.empty()) return;
+  std::sort(items_.begin(), items_.end(), [](const Item& a, const Item& b) { return a.dst < b.dst; });
+  // runs of destinations separated by alignment padding only
+  std::vector<std::pair<size_t, size_t>> runs;   // [first item, last item]
+  size_t total = 0;
+  for (size_t i = 0; i < items_.size(); ++i) {
+    if (i > 0 && items_[i].dst >= items_[i - 1].dst + items_[i - 1].bytes &&
+        items_[i].dst - (items_[i - 1].dst + items_[i - 1].bytes) < 256)
+      runs.back().second = i;
+    else
+      runs.push_back({i, i});
+  }
+  for (auto& r : runs) total += (size_t)(items_[r.second].dst + items_[r.second].bytes - items_[r.first].dst);
+  if (buf_) {
+    if (deferred_) {
+      deferred_->push_back(buf_);
+    } else {
+      (void)hipStreamSynchronize(st_);
+      pinned_release(buf_);
+    }
+  }
+  buf_ = pinned_acquire(total);
+  char* host = static_cast<char*>(buf_);
+  size_t off = 0;
+  for (auto& r : runs) {
+    char* d0 = items_[r.first].dst;
+    const size_t len = (size_t)(items_[r.second].dst + items_[r.second].bytes - d0);
+    for (size_t i = r.first; i <= r.second; ++i) std::memcpy(host + off + (items_[i].dst - d0), items_[i].src, items_[i].bytes);
+    BDDC_HIP(hipMemcpyAsync(d0, host + off, len, hipMemcpyHostToDevice, st_));
+    off += len;
+  }
+  items_.clear();
+}
+
 hipMemPool_t device_pool() {
   static std::mutex mu;
   static std::map<int, hipMemPool_t> pools;
@@ -218,7 +295,6 @@ struct Level {
   // coarse dofs
   std::vector<int32_t> edge_m, edge_nsel;
   std::vector<double> lam;
-  std::vector<double> qhost;     // constraint weights, copied back for queries
   int nc = 0;
   std::vector<int32_t> cid, csh_ptr, csh_flat, cd_dof, cd_col, ncr;
   std::vector<int64_t> croff, toff, psioff, acoff, cwoff;
@@ -282,9 +358,11 @@ struct bddc_ctx {
   bool fused_deep = false;
   bddc::DeepArgs deep;
   // one deep level and the coarsest solve in one cooperative launch
+  std::vector<void*> staged;   // pinned upload buffers of the setup, released after it synchronises
   bool coop_deep = false;
   bool coop_launch = false;   // use the cooperative launch API
   double coop_bytes = 0;      // algorithmic bytes of one launch
+  double by_average = 0;      // algorithmic bytes of the level-1 interface average
   bddc::CoopDev coop;
   bddc::Arena coop_arena;
   bddc_info info{};
@@ -587,6 +665,8 @@ class Builder {
     }
     coarsest();
     BDDC_HIP(hipStreamSynchronize(st_));
+    for (void* b : h_->staged) pinned_release(b);
+    h_->staged.clear();
     clk.lap("coarsest");
     int bad = 0;
     BDDC_HIP(hipMemcpy(&bad, h_->status, sizeof(int), hipMemcpyDeviceToHost));
@@ -758,60 +838,61 @@ class Builder {
     layout(true);
 
     std::vector<int32_t> nint(T.n_int), nr(T.n_r);
-    h2d(d.loc_ptr, T.loc_ptr, st_);
-    h2d(d.nint, nint, st_);
-    h2d(d.nr, nr, st_);
-    h2d(d.goff, lv.goff, st_);
-    h2d(d.ioff, lv.ioff, st_);
-    h2d(d.koff, lv.koff, st_);
-    h2d(d.int_gid, lv.int_gid, st_);
-    h2d(d.gam_gid, lv.gam_gid, st_);
-    h2d(d.gam_iid, lv.gam_iid, st_);
-    h2d(d.iface_dof, lv.iface_dof, st_);
-    h2d(d.sh_ptr, lv.sh_ptr, st_);
-    h2d(d.sh_flat, lv.sh_flat, st_);
-    h2d(d.node_el, node_el, st_);
-    h2d(d.sub_el_ptr, sub_el_ptr, st_);
-    h2d(d.el_gid, el_gid, st_);
-    h2d(d.el_loc, el_loc, st_);
+    std::vector<double> ones;
+    Staging stg(st_, &h_->staged);
+    stg.add(d.loc_ptr, T.loc_ptr);
+    stg.add(d.nint, nint);
+    stg.add(d.nr, nr);
+    stg.add(d.goff, lv.goff);
+    stg.add(d.ioff, lv.ioff);
+    stg.add(d.koff, lv.koff);
+    stg.add(d.int_gid, lv.int_gid);
+    stg.add(d.gam_gid, lv.gam_gid);
+    stg.add(d.gam_iid, lv.gam_iid);
+    stg.add(d.iface_dof, lv.iface_dof);
+    stg.add(d.sh_ptr, lv.sh_ptr);
+    stg.add(d.sh_flat, lv.sh_flat);
+    stg.add(d.node_el, node_el);
+    stg.add(d.sub_el_ptr, sub_el_ptr);
+    stg.add(d.el_gid, el_gid);
+    stg.add(d.el_loc, el_loc);
     if (E && p_->coeff_device)
       BDDC_HIP(hipMemcpyAsync(d.coeff, p_->coeff_device, sizeof(double) * h_->nx * h_->ny,
                               hipMemcpyDeviceToDevice, st_));
     else if (E)
       BDDC_HIP(hipMemcpyAsync(d.coeff, p_->coeff, sizeof(double) * h_->nx * h_->ny, hipMemcpyHostToDevice, st_));
-    h2d(d.child_ptr, child_ptr, st_);
-    h2d(d.child_id, child_id, st_);
-    h2d(d.child_map_off, child_map_off, st_);
-    h2d(d.child_map, child_map, st_);
-    h2d(d.inc_sub, lv.inc_sub, st_);
-    h2d(d.inc_edge, lv.inc_edge, st_);
-    h2d(d.inc_fptr, lv.inc_fptr, st_);
-    h2d(d.inc_fpos, lv.inc_fpos, st_);
-    h2d(d.sub_inc_ptr, lv.sub_inc_ptr, st_);
-    h2d(d.sub_inc, lv.sub_inc, st_);
-    h2d(d.edge_s, T.edge_s, st_);
-    h2d(d.edge_t, T.edge_t, st_);
-    h2d(d.edge_nsc, lv.edge_nsc, st_);
-    h2d(d.edge_ne, lv.edge_ne, st_);
-    h2d(d.edge_fdof, lv.edge_fdof, st_);
-    h2d(d.edge_fptr, lv.edge_fptr, st_);
-    h2d(d.edge_ptr, edge_ptr, st_);
-    h2d(d.edge_dof, edge_dof, st_);
-    h2d(d.floating, floating, st_);
-    h2d(d.inc_off, lv.inc_off, st_);
-    h2d(d.lamoff, lv.lamoff, st_);
-    h2d(d.qoff, lv.qoff, st_);
-    h2d(d.linvoff, lv.linvoff, st_);
+    stg.add(d.child_ptr, child_ptr);
+    stg.add(d.child_id, child_id);
+    stg.add(d.child_map_off, child_map_off);
+    stg.add(d.child_map, child_map);
+    stg.add(d.inc_sub, lv.inc_sub);
+    stg.add(d.inc_edge, lv.inc_edge);
+    stg.add(d.inc_fptr, lv.inc_fptr);
+    stg.add(d.inc_fpos, lv.inc_fpos);
+    stg.add(d.sub_inc_ptr, lv.sub_inc_ptr);
+    stg.add(d.sub_inc, lv.sub_inc);
+    stg.add(d.edge_s, T.edge_s);
+    stg.add(d.edge_t, T.edge_t);
+    stg.add(d.edge_nsc, lv.edge_nsc);
+    stg.add(d.edge_ne, lv.edge_ne);
+    stg.add(d.edge_fdof, lv.edge_fdof);
+    stg.add(d.edge_fptr, lv.edge_fptr);
+    stg.add(d.edge_ptr, edge_ptr);
+    stg.add(d.edge_dof, edge_dof);
+    stg.add(d.floating, floating);
+    stg.add(d.inc_off, lv.inc_off);
+    stg.add(d.lamoff, lv.lamoff);
+    stg.add(d.qoff, lv.qoff);
+    stg.add(d.linvoff, lv.linvoff);
     if (prev) {
       // the constant's coarse values, computed on the previous level
       BDDC_HIP(hipMemcpyAsync(d.z, prev->d.znext, sizeof(double) * lv.n, hipMemcpyDeviceToDevice, st_));
     } else if (adaptive) {
-      std::vector<double> ones(lv.n, 1.0);
-      h2d(d.z, ones, st_);
-      BDDC_HIP(hipStreamSynchronize(st_));
+      ones.assign(lv.n, 1.0);
+      stg.add(d.z, ones);
     }
-    // keep the host staging vectors alive until the copies have been consumed
-    BDDC_HIP(hipStreamSynchronize(st_));
+    stg.flush();
+    // the staging buffer waits for its copies when it goes out of scope
   }
 
   void assemble_l1(Level& lv, const Level1Elements&) {
@@ -901,11 +982,6 @@ class Builder {
                                 d.toff, d.Psi, d.psioff, d.Ac, d.acoff, d.cwork, d.cwoff, h_->status);
     if (h_->constraints == BDDC_ADAPTIVE && lv.ell < h_->L - 1)
       launch_coarse_z(st_, lv.nc, d.cd_dof, d.cd_col, d.edge_ptr, d.edge_dof, d.qoff, d.Q, d.z, d.znext);
-    // keep the installed constraint weights for queries
-    lv.qhost.resize(lv.qoff.back());
-    if (!lv.qhost.empty())
-      BDDC_HIP(hipMemcpyAsync(lv.qhost.data(), d.Q, sizeof(double) * lv.qhost.size(), hipMemcpyDeviceToHost, st_));
-    BDDC_HIP(hipStreamSynchronize(st_));
     (void)T;
     // agglomeration towards the next level
     if (lv.ell < h_->L - 1) {
@@ -1007,23 +1083,24 @@ class Builder {
     layout();
     A.allocate(st_);
     layout();
-    h2d(d.edge_m, lv.edge_m, st_);
-    h2d(d.coff, lv.coff, st_);
-    h2d(d.cid, lv.cid, st_);
-    h2d(d.csh_ptr, lv.csh_ptr, st_);
-    h2d(d.csh_flat, lv.csh_flat, st_);
-    h2d(d.cd_dof, lv.cd_dof, st_);
-    h2d(d.cd_col, lv.cd_col, st_);
-    h2d(d.ncr, lv.ncr, st_);
+    Staging stg(st_, &h_->staged);
+    stg.add(d.edge_m, lv.edge_m);
+    stg.add(d.coff, lv.coff);
+    stg.add(d.cid, lv.cid);
+    stg.add(d.csh_ptr, lv.csh_ptr);
+    stg.add(d.csh_flat, lv.csh_flat);
+    stg.add(d.cd_dof, lv.cd_dof);
+    stg.add(d.cd_col, lv.cd_col);
+    stg.add(d.ncr, lv.ncr);
     std::vector<int32_t> ncs(nsub);
     for (int s = 0; s < nsub; ++s) ncs[s] = lv.coff[s + 1] - lv.coff[s];
-    h2d(d.ncs, ncs, st_);
-    h2d(d.croff, lv.croff, st_);
-    h2d(d.toff, lv.toff, st_);
-    h2d(d.psioff, lv.psioff, st_);
-    h2d(d.acoff, lv.acoff, st_);
-    h2d(d.cwoff, lv.cwoff, st_);
-    BDDC_HIP(hipStreamSynchronize(st_));
+    stg.add(d.ncs, ncs);
+    stg.add(d.croff, lv.croff);
+    stg.add(d.toff, lv.toff);
+    stg.add(d.psioff, lv.psioff);
+    stg.add(d.acoff, lv.acoff);
+    stg.add(d.cwoff, lv.cwoff);
+    stg.flush();
   }
 
   void fill_dev(Level& lv) {
@@ -1160,6 +1237,9 @@ static bool plan_coop(bddc_ctx* h) {
   std::vector<int32_t> meta((size_t)kCoopMeta * nsub);
   std::vector<int64_t> opoff(nsub + 1, 0), idxoff(nsub + 1, 0);
   std::vector<int32_t> idx;
+  std::vector<int32_t> sub_of_flat(lv.nflat_g);
+  for (int s = 0; s < nsub; ++s)
+    for (int f = lv.goff[s]; f < lv.goff[s + 1]; ++f) sub_of_flat[f] = s;
   for (int s = 0; s < nsub; ++s) {
     const int nI = T.n_int[s], ng = T.ngam(s), nr = T.n_r[s], ncs = lv.coff[s + 1] - lv.coff[s];
     const size_t i0 = idx.size();
@@ -1187,6 +1267,17 @@ static bool plan_coop(bddc_ctx* h) {
     idx.insert(idx.end(), gp.begin(), gp.end());
     idx.insert(idx.end(), gf.begin(), gf.end());
     for (int k = lv.coff[s]; k < lv.coff[s + 1]; ++k) idx.push_back(lv.cid[k]);
+    // rows of the delta-weighted coarse basis of all sharers of each interface dof
+    std::vector<int32_t> phi_ptr(ng + 1, 0), phi_ids;
+    for (int a = 0; a < ng; ++a) {
+      for (int q = shp[a]; q < shp[a + 1]; ++q) {
+        const int t = sub_of_flat[shf[q]];
+        for (int k = lv.coff[t]; k < lv.coff[t + 1]; ++k) phi_ids.push_back(lv.cid[k]);
+      }
+      phi_ptr[a + 1] = (int32_t)phi_ids.size();
+    }
+    idx.insert(idx.end(), phi_ptr.begin(), phi_ptr.end());
+    idx.insert(idx.end(), phi_ids.begin(), phi_ids.end());
     idxoff[s + 1] = (int64_t)idx.size();
     int32_t* m = meta.data() + (size_t)kCoopMeta * s;
     m[0] = nI;
@@ -1197,7 +1288,9 @@ static bool plan_coop(bddc_ctx* h) {
     m[5] = (int32_t)gf.size();
     m[6] = lv.goff[s];
     m[7] = lv.coff[s];
-    const int64_t ops = (int64_t)nI * nI + (int64_t)ng * nI + (int64_t)nr * nr + (int64_t)ng * ncs + ng;
+    m[8] = (int32_t)phi_ids.size();
+    const int64_t ops = (int64_t)nI * nI + (int64_t)ng * nI + (int64_t)nr * nr + (int64_t)ng * ncs + ng +
+                        (int64_t)phi_ids.size();
     opoff[s + 1] = opoff[s] + ops;
     C.opmax = std::max<int>(C.opmax, (int)ops);
     C.idxmax = std::max<int>(C.idxmax, (int)(idx.size() - i0));
@@ -1221,24 +1314,28 @@ static bool plan_coop(bddc_ctx* h) {
     C.cg = A.take<int32_t>(cg.size());
     C.LLinv = A.take<double>((size_t)ncL * ncL);
     C.bar = A.take<unsigned>(2);
+    C.sub_of_flat = A.take<int32_t>(sub_of_flat.size());
   };
   A.reset_sizing();
   lay();
   A.allocate(h->stream);
   lay();
   hipStream_t st = h->stream;
-  h2d(const_cast<int64_t*>(C.opoff), opoff, st);
-  h2d(const_cast<int32_t*>(C.idx), idx, st);
-  h2d(const_cast<int64_t*>(C.idxoff), idxoff, st);
-  h2d(const_cast<int32_t*>(C.meta), meta, st);
-  h2d(const_cast<int32_t*>(C.cg), cg, st);
+  Staging stg(st);
+  stg.add(const_cast<int64_t*>(C.opoff), opoff);
+  stg.add(const_cast<int32_t*>(C.idx), idx);
+  stg.add(const_cast<int64_t*>(C.idxoff), idxoff);
+  stg.add(const_cast<int32_t*>(C.meta), meta);
+  stg.add(const_cast<int32_t*>(C.cg), cg);
+  stg.add(const_cast<int32_t*>(C.sub_of_flat), sub_of_flat);
+  stg.flush();
   BDDC_HIP(hipMemsetAsync(C.bar, 0, 2 * sizeof(unsigned), st));
   launch_pack_coop(st, lv.dev, C);
   launch_tri_inverse_dense(st, h->AL, ncL, ncL, const_cast<double*>(C.LLinv));
   C.b1 = l1.d.b;
   C.t = lv.d.t;
   C.b = lv.d.b;
-  C.v = lv.d.v;
+  C.da = lv.d.v;
   C.u2 = l1.d.uc;
   C.stop = nullptr;
   C.status = h->status;
@@ -1248,7 +1345,7 @@ static bool plan_coop(bddc_ctx* h) {
   const char* cl = getenv("BDDC_COOP_LAUNCH");
   h->coop_launch = cl && std::string(cl) == "1";
   // operators and index lists once per workgroup, the level-1 contributions,
-  // t / b / v written and read back, the level-2 solution written
+  // t / b / delta T g written and read back, the level-2 solution written
   h->coop_bytes = 8.0 * (double)opoff[nsub] + 4.0 * (double)idx.size() +
                   (double)nsub * (4.0 * cg.size() + 8.0 * ncL * ncL) + 8.0 * (double)lv.nflat_c * 2 +
                   8.0 * (double)lv.nflat_g * 4 + 8.0 * (double)l1.nflat_c + 8.0 * (double)lv.n;
@@ -1385,12 +1482,8 @@ static int pcg_one(bddc_ctx* h, const double* f, double* u, double rtol, int max
     run_deep(h);
     timing::current_tag = it;
     {
-      timing::Scope ts("apply_prolong", l1.by_prolong, 0);
-      launch_pcg_prolong(st, l1.dev, l1.ncsmax, P, l1.d.uc, it > 0 ? 1 : 0);
-    }
-    {
-      timing::Scope ts("apply_post", l1.by_post_ir, 0);
-      launch_pcg_post(st, l1.dev, P, it & 1);
+      timing::Scope ts("apply_average", h->by_average, 0);
+      launch_pcg_prolong_post(st, l1.dev, P, l1.d.uc, it > 0 ? 1 : 0, it & 1);
     }
   };
   // z_0 = M r_0 and its r.z partials (parity 0)
@@ -1493,9 +1586,9 @@ void release(bddc_ctx* h) {
   }
   h->top.release(st);
   h->coop_arena.release(st);
-  if (h->sc_host) (void)hipHostFree(h->sc_host);
-  (void)hipStreamSynchronize(st);
-  delete h;
+  pinned_release(h->sc_host);
+  for (void* b : h->staged) pinned_release(b);
+  delete h;   // the pool frees above are stream-ordered
 }
 
 void fill_level_info(const Level& lv, int idx, bddc_info* info) {
@@ -1573,6 +1666,19 @@ bddc_status bddc_setup(const bddc_problem* p, void* hip_stream, bddc_handle* out
     h->nblk = std::min(256, std::max(1, (nif + kNT - 1) / kNT));
     Arena& B = h->levels[0]->arena_pcg;
     PcgDev& P = h->pcg;
+    // per interface dof: the sharers' rows of the delta-weighted coarse basis
+    std::vector<int32_t> sub_of_flat(l1.nflat_g), phi_ptr(nif + 1, 0), phi_ids;
+    for (int s = 0; s < l1.nsub; ++s)
+      for (int f = l1.goff[s]; f < l1.goff[s + 1]; ++f) sub_of_flat[f] = s;
+    for (int gi = 0; gi < nif; ++gi) {
+      for (int q = l1.sh_ptr[gi]; q < l1.sh_ptr[gi + 1]; ++q) {
+        const int t = sub_of_flat[l1.sh_flat[q]];
+        for (int k = l1.coff[t]; k < l1.coff[t + 1]; ++k) phi_ids.push_back(l1.cid[k]);
+      }
+      phi_ptr[gi + 1] = (int32_t)phi_ids.size();
+    }
+    int32_t* sub_flat_d = nullptr;
+    const int nblk_avg = std::max(1, (nif + kNT / 8 - 1) / (kNT / 8));   // eight lanes per interface dof
     auto lay = [&] {
       h->x = B.take<double>(nif);
       h->r = B.take<double>(nif);
@@ -1583,9 +1689,13 @@ bddc_status bddc_setup(const bddc_problem* p, void* hip_stream, bddc_handle* out
       h->partial = B.take<double>(1024);
       P.pq_part = B.take<double>(l1.nsub);
       P.rr_part = B.take<double>(l1.nsub);
-      P.rz_part[0] = B.take<double>(l1.nsub);
-      P.rz_part[1] = B.take<double>(l1.nsub);
+      P.rz_part[0] = B.take<double>(nblk_avg);
+      P.rz_part[1] = B.take<double>(nblk_avg);
       h->sc = B.take<PcgScalars>(1);
+      P.phi_ptr = B.take<int32_t>(phi_ptr.size());
+      P.phi_ids = B.take<int32_t>(phi_ids.size());
+      P.phi_w = B.take<double>(phi_ids.size());
+      sub_flat_d = B.take<int32_t>(sub_of_flat.size());
     };
     B.reset_sizing();
     lay();
@@ -1597,10 +1707,26 @@ bddc_status bddc_setup(const bddc_problem* p, void* hip_stream, bddc_handle* out
     P.z = h->zv;
     P.p[0] = h->p;
     P.qloc = l1.d.qloc;
+    P.da = l1.d.v;
+    P.nblk = nblk_avg;
     P.nif = nif;
+    {
+      Staging stg(h->stream);
+      stg.add(const_cast<int32_t*>(P.phi_ptr), phi_ptr);
+      stg.add(const_cast<int32_t*>(P.phi_ids), phi_ids);
+      stg.add(sub_flat_d, sub_of_flat);
+      stg.flush();
+      launch_build_phi(h->stream, l1.dev, nif, sub_flat_d, P.phi_ptr, const_cast<double*>(P.phi_w));
+    }
     P.nsub1 = l1.nsub;
+    {
+      double nshare = 0;
+      for (int gi = 0; gi < nif; ++gi) nshare += l1.sh_ptr[gi + 1] - l1.sh_ptr[gi];
+      // per interface dof: sharer indices and delta T g, phi row (id, weight, u_c), z and r
+      h->by_average = 12.0 * nshare + 20.0 * (double)phi_ids.size() + 8.0 * nif * 4;
+    }
     plan_deep(h);
-    BDDC_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->sc_host), sizeof(PcgScalars), hipHostMallocDefault));
+    h->sc_host = static_cast<PcgScalars*>(pinned_acquire(sizeof(PcgScalars)));
     BDDC_HIP(hipStreamSynchronize(h->stream));
     // info
     std::memset(&h->info, 0, sizeof(h->info));
@@ -1691,9 +1817,13 @@ bddc_status bddc_edge_constraints(bddc_handle h, int32_t level, int32_t edge, in
     if (cap_dofs < ne) return BDDC_EINVAL;
     for (int p = 0; p < ne; ++p) dofs[p] = lv.topo.edge_dof[lv.topo.edge_ptr[edge] + p];
   }
-  if (q) {
+  if (q && ne * m > 0) {
     if (cap_q < ne * m) return BDDC_EINVAL;
-    for (int i = 0; i < ne * m; ++i) q[i] = lv.qhost[lv.qoff[edge] + i];
+    // the installed weights stay on the device; read this edge's columns
+    return guard([&] {
+      BDDC_HIP(hipMemcpyAsync(q, lv.d.Q + lv.qoff[edge], sizeof(double) * ne * m, hipMemcpyDeviceToHost, h->stream));
+      BDDC_HIP(hipStreamSynchronize(h->stream));
+    });
   }
   return BDDC_OK;
 }

@@ -68,6 +68,45 @@ class Arena {
   size_t size_ = 0;
 };
 
+// Pinned host buffers, reused across handles: hipHostMalloc is slow and
+// hipHostFree synchronises the device, so buffers stay in a process-wide pool.
+void* pinned_acquire(size_t bytes);
+void pinned_release(void* p);
+
+// Host-to-device uploads staged through one pinned buffer.  add() records a
+// source that must stay alive until flush(); flush() packs the sources into a
+// pinned buffer laid out like their destinations and enqueues one copy per run
+// of destinations separated only by arena alignment padding (< 256 bytes, which
+// no other piece can occupy).  At destruction the buffer goes to `deferred`
+// (released by the owner after a later stream synchronisation) or, without
+// one, back to the pool once the copies are done.
+class Staging {
+ public:
+  explicit Staging(hipStream_t st, std::vector<void*>* deferred = nullptr) : st_(st), deferred_(deferred) {}
+  Staging(const Staging&) = delete;
+  Staging& operator=(const Staging&) = delete;
+  ~Staging();
+  void add(void* dst, const void* src, size_t bytes) {
+    if (bytes) items_.push_back({static_cast<char*>(dst), static_cast<const char*>(src), bytes});
+  }
+  template <class T>
+  void add(T* dst, const std::vector<T>& v) {
+    add(dst, v.data(), v.size() * sizeof(T));
+  }
+  void flush();
+
+ private:
+  struct Item {
+    char* dst;
+    const char* src;
+    size_t bytes;
+  };
+  hipStream_t st_;
+  std::vector<void*>* deferred_;
+  std::vector<Item> items_;
+  void* buf_ = nullptr;
+};
+
 template <class T>
 void h2d(T* dst, const std::vector<T>& src, hipStream_t st) {
   if (!src.empty())

@@ -5,11 +5,16 @@
 // One workgroup per level-2 substructure.  Its operators (interior factor
 // inverse, L_GI, T_rr, Psi, stiffness weights) and index lists are packed at
 // setup into one contiguous block each, so the prefetch into LDS at the start
-// is a single coalesced copy.  Phases that read other substructures' results
-// (the interface sum of the interior corrections, the coarse gather, the
-// interface sum of the prolongation) are separated by grid barriers; every
-// workgroup solves the small coarsest problem redundantly with the explicit
-// inverse of its Cholesky factor, which saves a barrier.
+// is a single coalesced copy.  Two grid barriers separate the phases that read
+// other substructures' results:
+//   1. after the interior corrections t (the restriction sums t over sharers);
+//   2. after the restriction (the coarse right-hand side sums b over sharers).
+// Every workgroup then solves the small coarsest problem redundantly with the
+// explicit inverse of its Cholesky factor.  The interface average of the
+// prolongation, u_B = sum_s delta_s (T_rr g_s + Psi_s u_c) over the sharers,
+// is split as sum_s delta_s T_rr g_s (published before barrier 2) plus a row
+// of the delta-weighted coarse basis of all sharers (packed at setup) times
+// u_c, so no barrier is needed after the coarse solve.
 #include <string>
 
 #include "common.hpp"
@@ -52,13 +57,15 @@ __device__ void grid_barrier(unsigned* bar, unsigned nblocks, int* status) {
 
 // out(i) = sum_{j in [j0(i), j1(i))} A[i*rs + j*cs] x[j] for i < rows, eight
 // lanes per row (fixed reduction order), then store(i, value) on lane 0 of the eight.
+// With xi, x is read at xi[j] (a gathered product).
 template <class J0, class J1, class Store>
-__device__ inline void mv8(int rows, const double* A, int rs, int cs, const double* x, J0 j0f, J1 j1f, Store store) {
+__device__ inline void mv8(int rows, const double* A, int rs, int cs, const double* x, J0 j0f, J1 j1f, Store store,
+                           const int32_t* xi = nullptr) {
   const int sub = threadIdx.x & 7;
   for (int i = threadIdx.x >> 3; i < rows; i += kCoopNT / 8) {
     double acc = 0.0;
     const int j1 = j1f(i);
-    for (int j = j0f(i) + sub; j < j1; j += 8) acc += A[(size_t)i * rs + (size_t)j * cs] * x[j];
+    for (int j = j0f(i) + sub; j < j1; j += 8) acc += A[(size_t)i * rs + (size_t)j * cs] * x[xi ? xi[j] : j];
     acc += __shfl_xor(acc, 1);
     acc += __shfl_xor(acc, 2);
     acc += __shfl_xor(acc, 4);
@@ -88,12 +95,14 @@ __global__ void __launch_bounds__(kCoopNT) k_deep_coop(CoopDev C) {
   const int nI = me[0], ng = me[1], nr = me[2], ncs = me[3], nsh = me[4], ng1 = me[5], goff = me[6], coff = me[7];
   const int n = nI + ng;
   const int ncL = C.ncL;
+  (void)me[8];
   // LDS: operator block | vectors | coarsest inverse factor | ints
   double* Li = sh;                                   // nI x nI
   double* G = Li + (size_t)nI * nI;                  // ng x nI
   double* Tm = G + (size_t)ng * nI;                  // nr x nr
   double* Ps = Tm + (size_t)nr * nr;                 // ng x ncs
   double* dl = Ps + (size_t)ng * ncs;                // ng
+  double* phw = dl + ng;                             // phi weights
   double* rI = sh + C.opmax;
   double* rG = rI + C.nImax;
   double* y = rG + C.ngmax;
@@ -101,8 +110,7 @@ __global__ void __launch_bounds__(kCoopNT) k_deep_coop(CoopDev C) {
   double* av = g + C.ngmax;
   double* uB = av + C.ngmax;
   double* yv = uB + C.ngmax;
-  double* ul = yv + C.nImax;
-  double* LL = ul + C.ncsmax;
+  double* LL = yv + C.nImax;
   double* rc = LL + (size_t)ncL * ncL;
   double* wc = rc + ncL;
   double* uc = wc + ncL;
@@ -115,7 +123,10 @@ __global__ void __launch_bounds__(kCoopNT) k_deep_coop(CoopDev C) {
   int32_t* gp = shf + nsh;
   int32_t* gf = gp + n + 1;
   int32_t* cid = gf + ng1;
+  int32_t* phi_ptr = cid + ncs;
+  int32_t* phi_ids = phi_ptr + ng + 1;
   int32_t* cg = ib + C.idxmax;
+  (void)cid;
 
   // prefetch: operators + coarsest factor inverse, and index lists + coarse
   // gather, with every load of the first kPD / kPI per thread issued before
@@ -183,36 +194,39 @@ __global__ void __launch_bounds__(kCoopNT) k_deep_coop(CoopDev C) {
     g[a] = dl[a] * v;
   }
   __syncthreads();
-  mv8(nr, Tm, 1, nr, g, [](int) { return 0; }, [&](int) { return nr; }, [&](int a, double v) { av[a] = v; });
-  for (int a = nr + tid; a < ng; a += kCoopNT) av[a] = 0.0;
+  mv8(nr, Tm, 1, nr, g, [](int) { return 0; }, [&](int) { return nr; },
+      [&](int a, double v) { C.da[goff + a] = dl[a] * v; });
+  for (int a = nr + tid; a < ng; a += kCoopNT) C.da[goff + a] = 0.0;
   mv8(ncs, Ps, ng, 1, g, [](int) { return 0; }, [&](int) { return ng; },
       [&](int k, double v) { C.b[coff + k] = v; });
   grid_barrier(C.bar, gridDim.x, C.status);
-  // coarsest: r_c = sum of the coarse contributions, u_c = Linv^T (Linv r_c)
+  // coarsest right-hand side r_c = sum of the coarse contributions, and the
+  // sharers' sum of delta T_rr g on the interface, in one round of loads
   for (int k = tid; k < ncL; k += kCoopNT) {
     double acc = 0.0;
     for (int q = cg[k]; q < cg[k + 1]; ++q) acc += C.b[cg[ncL + 1 + q]];
     rc[k] = acc;
+  }
+  for (int a = tid; a < ng; a += kCoopNT) {
+    double acc = 0.0;
+    for (int q = shp[a]; q < shp[a + 1]; ++q) acc += C.da[shf[q]];
+    av[a] = acc;
   }
   __syncthreads();
   mv8(ncL, LL, 1, ncL, rc, [](int) { return 0; }, [](int i) { return i + 1; }, [&](int i, double v) { wc[i] = v; });
   __syncthreads();
   mv8(ncL, LL, ncL, 1, wc, [](int i) { return i; }, [&](int) { return ncL; }, [&](int i, double v) { uc[i] = v; });
   __syncthreads();
-  // v = delta (a + Psi u_c)   (ML-uBi-1 before the sum)
-  for (int k = tid; k < ncs; k += kCoopNT) ul[k] = uc[cid[k]];
+  // u_B = sum over sharers of delta (T_rr g + Psi u_c)   (ML-uBi-1), owner writes
+  mv8(ng, phw, 0, 1, uc, [&](int a) { return phi_ptr[a]; }, [&](int a) { return phi_ptr[a + 1]; },
+      [&](int a, double v) {
+        const double u = av[a] + v;
+        uB[a] = u;
+        if (own[a]) C.u2[gam_gid[a]] = u;
+      },
+      phi_ids);
   __syncthreads();
-  mv8(ng, Ps, 1, ng, ul, [](int) { return 0; }, [&](int) { return ncs; },
-      [&](int a, double v) { C.v[goff + a] = dl[a] * (av[a] + v); });
-  grid_barrier(C.bar, gridDim.x, C.status);
-  // u_B = sum over sharers of v (owner writes);  u_I = Linv^T (y - L_GI^T u_B)   (ML-vIi, ML-ui)
-  for (int a = tid; a < ng; a += kCoopNT) {
-    double acc = 0.0;
-    for (int q = shp[a]; q < shp[a + 1]; ++q) acc += C.v[shf[q]];
-    uB[a] = acc;
-    if (own[a]) C.u2[gam_gid[a]] = acc;
-  }
-  __syncthreads();
+  // u_I = Linv^T (y - L_GI^T u_B)   (ML-vIi, ML-ui)
   mv8(nI, G, ng, 1, uB, [](int) { return 0; }, [&](int) { return ng; }, [&](int j, double v) { yv[j] = y[j] - v; });
   __syncthreads();
   mv8(nI, Li, nI, 1, yv, [](int i) { return i; }, [&](int) { return nI; },
@@ -220,8 +234,8 @@ __global__ void __launch_bounds__(kCoopNT) k_deep_coop(CoopDev C) {
 }
 
 size_t coop_lds(const CoopDev& C) {
-  const size_t dbl = (size_t)C.opmax + 3 * (size_t)C.nImax + 4 * (size_t)C.ngmax + (size_t)C.ncsmax +
-                     (size_t)C.ncL * C.ncL + 3 * (size_t)C.ncL;
+  const size_t dbl = (size_t)C.opmax + 3 * (size_t)C.nImax + 4 * (size_t)C.ngmax + (size_t)C.ncL * C.ncL +
+                     3 * (size_t)C.ncL;
   return sizeof(double) * dbl + sizeof(int32_t) * ((size_t)C.idxmax + C.cg_len);
 }
 
@@ -281,6 +295,25 @@ __global__ void __launch_bounds__(kNT) k_pack_coop(LevelDev L, CoopDev C) {
   for (int idx = threadIdx.x; idx < ng * ncs; idx += kNT) o[idx] = P[idx];
   o += (size_t)ng * ncs;
   for (int a = threadIdx.x; a < ng; a += kNT) o[a] = L.delta[L.goff[s] + a];
+  o += ng;
+  // phi rows: for each interface dof, delta_{s'} Psi_{s'} row of every sharer s'
+  const int32_t* ib = C.idx + C.idxoff[s];
+  const int nsh = me[4], ng1 = me[5];
+  const int32_t* shp = ib + nI + 2 * ng;
+  const int32_t* shf = shp + ng + 1;
+  const int32_t* phi_ptr = shf + nsh + (n + 1) + ng1 + ncs;
+  for (int a = threadIdx.x; a < ng; a += kNT) {
+    int j = phi_ptr[a];
+    for (int q = shp[a]; q < shp[a + 1]; ++q) {
+      const int f = shf[q];
+      const int t = C.sub_of_flat[f];
+      const int at = f - L.goff[t];
+      const int ngt = (L.loc_ptr[t + 1] - L.loc_ptr[t]) - L.nint[t];
+      const int ncst = L.coff[t + 1] - L.coff[t];
+      const double* Pt = L.Psi + L.psioff[t];
+      for (int k = 0; k < ncst; ++k) o[j++] = L.delta[f] * Pt[at + (size_t)k * ngt];
+    }
+  }
 }
 
 void launch_pack_coop(hipStream_t st, const LevelDev& L, const CoopDev& C) {

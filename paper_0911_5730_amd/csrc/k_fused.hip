@@ -269,25 +269,28 @@ __device__ inline double block_sum_of(const double* __restrict__ v, int n, doubl
   return wg_sum(acc, red);
 }
 
-// PCG iteration k on the level-1 interface (Section 5) in five launches:
+// PCG iteration k on the level-1 interface (Section 5) in four launches:
 //   matvec   p_k = z + beta p_{k-1};  q_s = S_s p_s;  partial p_s^T q_s
 //   update   alpha = rz / p^T S p;  r_k = r_{k-1} - alpha sum_s q_s (every sharer
 //            forms the same value, the owner stores it and x += alpha p);
-//            partial r.r;  then the restriction of r_k (g, T_rr g_r, Psi^T g)
+//            partial r.r;  then the restriction of r_k: g = delta r, b = Psi^T g,
+//            and delta T_rr g_r published for the interface average
 //   deep     levels >= 2 and the coarsest solve
-//   prolong  convergence test on r.r, then v = delta (a + Psi u_c)
-//   post     z = sum over sharers of v and the partial r.z
+//   average  convergence test on r.r, then z = sum over the sharers s of
+//            delta_s (T_rr g_s + Psi_s u_c) and the partial r.z, per interface dof
 // p^T S p is summed as the local energies p_s^T S_s p_s, so the assembled q is
 // never formed; r is double-buffered by iteration parity because sharers read
-// r_{k-1} while owners write r_k.
+// r_{k-1} while owners write r_k.  The average uses, per interface dof, the
+// sharers' rows of the delta-weighted coarse basis (built at setup), so the
+// prolongation needs no pass of its own.
 __global__ void __launch_bounds__(kNT) k_pcg_matvec(LevelDev L, PcgDev P, int it) {
   extern __shared__ double sh[];
   __shared__ double red[kNT];
   if (P.sc->done) return;
   double beta = 0.0;
   if (it >= 2) {
-    const double rz = block_sum_of(P.rz_part[(it - 1) & 1], P.nsub1, red);
-    const double rz0 = block_sum_of(P.rz_part[(it - 2) & 1], P.nsub1, red);
+    const double rz = block_sum_of(P.rz_part[(it - 1) & 1], P.nblk, red);
+    const double rz0 = block_sum_of(P.rz_part[(it - 2) & 1], P.nblk, red);
     beta = rz / rz0;
     if (blockIdx.x == 0 && threadIdx.x == 0) P.sc->betas[min(it - 2, kMaxHist - 1)] = beta;
   }
@@ -328,8 +331,9 @@ __global__ void __launch_bounds__(kNT) k_pcg_matvec(LevelDev L, PcgDev P, int it
 }
 
 // The level-1 restriction of the interface residual r: g = delta r_G,
-// a = T_rr g_r, b = Psi^T g (ML-wDi, ML-coarse); g is already in LDS.
-__device__ void pcg_restrict_body(const LevelDev& L, int s, const double* g, double* part) {
+// b = Psi^T g (ML-coarse) and da = delta T_rr g_r (ML-wDi, weighted for the
+// average); g is already in LDS.
+__device__ void pcg_restrict_body(const LevelDev& L, int s, const double* g, double* part, double* da) {
   const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
   const int ng = n - L.nint[s];
   const int n_r = L.nr[s];
@@ -355,9 +359,9 @@ __device__ void pcg_restrict_body(const LevelDev& L, int s, const double* g, dou
   for (int i = tid; i < n_r; i += kNT) {
     double acc = 0.0;
     for (int c = 0; c < nch; ++c) acc += part[i + c * n_r];
-    L.a[g0 + i] = acc;
+    da[g0 + i] = L.delta[g0 + i] * acc;
   }
-  for (int a = n_r + tid; a < ng; a += kNT) L.a[g0 + a] = 0.0;
+  for (int a = n_r + tid; a < ng; a += kNT) da[g0 + a] = 0.0;
 }
 
 // it >= 1: alpha, the residual update (r_k into r[it & 1]) and x update by the
@@ -377,7 +381,7 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
   if (it == 0) {
     for (int a = tid; a < ng; a += kNT) g[a] = L.delta[g0 + a] * P.r[0][L.gam_iid[g0 + a]];
   } else {
-    const double rz = block_sum_of(P.rz_part[(it - 1) & 1], P.nsub1, red);
+    const double rz = block_sum_of(P.rz_part[(it - 1) & 1], P.nblk, red);
     const double pq = block_sum_of(P.pq_part, P.nsub1, red);
     const double alpha = rz / pq;
     const double* rold = P.r[(it - 1) & 1];
@@ -405,13 +409,15 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
     }
   }
   __syncthreads();
-  pcg_restrict_body(L, s, g, part);
+  pcg_restrict_body(L, s, g, part, P.da);
 }
 
 // Convergence test on r.r (every block takes the same decision; block 0
-// records it), then v = delta (a + Psi u_c)   (ML-uBi-1 before the sum).
-__global__ void __launch_bounds__(kNT) k_pcg_prolong(LevelDev L, PcgDev P, const double* __restrict__ uc, int check) {
-  extern __shared__ double ul[];
+// records it), then per interface dof z = sum over sharers of delta T_rr g plus
+// the dof's row of the delta-weighted coarse basis times u_c  (ML-uBi-1), and
+// the per-block partial of r_k . z.
+__global__ void __launch_bounds__(kNT) k_pcg_prolong_post(LevelDev L, PcgDev P, const double* __restrict__ uc,
+                                                          int check, int parity) {
   __shared__ double red[kNT];
   if (P.sc->done) return;
   if (check) {
@@ -424,41 +430,44 @@ __global__ void __launch_bounds__(kNT) k_pcg_prolong(LevelDev L, PcgDev P, const
     }
     if (conv || maxed) return;
   }
-  const int s = blockIdx.x;
-  const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
-  const int ng = n - L.nint[s];
-  const int ncs = L.coff[s + 1] - L.coff[s];
-  const int g0 = L.goff[s];
-  for (int k = threadIdx.x; k < ncs; k += kNT) ul[k] = uc[L.cid[L.coff[s] + k]];
-  __syncthreads();
-  const double* Pp = L.Psi + L.psioff[s];
-  for (int a = threadIdx.x; a < ng; a += kNT) {
-    const double w = L.a[g0 + a] + dot_strided(Pp + a, ng, ul, 0, ncs, 1);
-    L.v[g0 + a] = L.delta[g0 + a] * w;
+  // eight lanes per interface dof, fixed-order reduction over the eight
+  const double* r = P.r[parity];
+  const int gi = (blockIdx.x * kNT + threadIdx.x) >> 3;
+  const int sub = threadIdx.x & 7;
+  double acc = 0.0;
+  if (gi < P.nif) {
+    const int k0 = L.sh_ptr[gi], k1 = L.sh_ptr[gi + 1];
+    for (int k = k0 + sub; k < k1; k += 8) acc += P.da[L.sh_flat[k]];
+    for (int j = P.phi_ptr[gi] + sub; j < P.phi_ptr[gi + 1]; j += 8) acc += P.phi_w[j] * uc[P.phi_ids[j]];
   }
+  acc += __shfl_xor(acc, 1);
+  acc += __shfl_xor(acc, 2);
+  acc += __shfl_xor(acc, 4);
+  double rz = 0.0;
+  if (gi < P.nif && sub == 0) {
+    P.z[gi] = acc;
+    rz = acc * r[gi];
+  }
+  rz = wg_sum(rz, red);
+  if (threadIdx.x == 0) P.rz_part[parity][blockIdx.x] = rz;
 }
 
-// z = sum over sharers of v (owner writes) and the per-substructure partial of r_k . z
-__global__ void __launch_bounds__(kNT) k_pcg_post(LevelDev L, PcgDev P, int parity) {
-  __shared__ double red[kNT];
-  if (P.sc->done) return;
-  const int s = blockIdx.x;
-  const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
-  const int ng = n - L.nint[s];
-  const int g0 = L.goff[s];
-  const double* r = P.r[parity];
-  double acc = 0.0;
-  for (int a = threadIdx.x; a < ng; a += kNT) {
-    const int f = g0 + a;
-    const int gi = L.gam_iid[f];
-    if (L.sh_flat[L.sh_ptr[gi]] != f) continue;
-    double v = 0.0;
-    for (int k = L.sh_ptr[gi]; k < L.sh_ptr[gi + 1]; ++k) v += L.v[L.sh_flat[k]];
-    P.z[gi] = v;
-    acc += v * r[gi];
+// Weights of the averaged coarse-basis rows: for interface dof gi, in sharer
+// order, delta_s(gi) Psi_s(row of gi, :) of every sharer s.
+__global__ void __launch_bounds__(kNT) k_build_phi(LevelDev L, int nif, const int32_t* __restrict__ sub_of_flat,
+                                                   const int32_t* __restrict__ phi_ptr, double* __restrict__ phi_w) {
+  const int gi = blockIdx.x * kNT + threadIdx.x;
+  if (gi >= nif) return;
+  int j = phi_ptr[gi];
+  for (int q = L.sh_ptr[gi]; q < L.sh_ptr[gi + 1]; ++q) {
+    const int f = L.sh_flat[q];
+    const int t = sub_of_flat[f];
+    const int at = f - L.goff[t];
+    const int ngt = (L.loc_ptr[t + 1] - L.loc_ptr[t]) - L.nint[t];
+    const int ncst = L.coff[t + 1] - L.coff[t];
+    const double* Pt = L.Psi + L.psioff[t];
+    for (int k = 0; k < ncst; ++k) phi_w[j++] = L.delta[f] * Pt[at + (size_t)k * ngt];
   }
-  acc = wg_sum(acc, red);
-  if (threadIdx.x == 0) P.rz_part[parity][s] = acc;
 }
 
 void launch_pcg_matvec(hipStream_t st, const LevelDev& L, int ngmax, const PcgDev& P, int it) {
@@ -469,11 +478,14 @@ void launch_pcg_update_restrict(hipStream_t st, const LevelDev& L, int ngmax, co
   const size_t lds = sizeof(double) * ((size_t)ngmax + kNT + ngmax);
   launch_kernel(k_pcg_update_restrict, dim3(L.nsub), dim3(kNT), lds, st, L, P, it);
 }
-void launch_pcg_prolong(hipStream_t st, const LevelDev& L, int ncsmax, const PcgDev& P, const double* uc, int check) {
-  launch_kernel(k_pcg_prolong, dim3(L.nsub), dim3(kNT), sizeof(double) * ((size_t)ncsmax + 1), st, L, P, uc, check);
+void launch_pcg_prolong_post(hipStream_t st, const LevelDev& L, const PcgDev& P, const double* uc, int check,
+                            int parity) {
+  launch_kernel(k_pcg_prolong_post, dim3(P.nblk), dim3(kNT), 0, st, L, P, uc, check, parity);
 }
-void launch_pcg_post(hipStream_t st, const LevelDev& L, const PcgDev& P, int parity) {
-  launch_kernel(k_pcg_post, dim3(L.nsub), dim3(kNT), 0, st, L, P, parity);
+void launch_build_phi(hipStream_t st, const LevelDev& L, int nif, const int32_t* sub_of_flat, const int32_t* phi_ptr,
+                      double* phi_w) {
+  if (nif == 0) return;
+  launch_kernel(k_build_phi, dim3((nif + kNT - 1) / kNT), dim3(kNT), 0, st, L, nif, sub_of_flat, phi_ptr, phi_w);
 }
 
 }  // namespace bddc

@@ -94,7 +94,7 @@ struct DeepArgs {
 // one workgroup per level-2 substructure, its operators prefetched to LDS,
 // three grid barriers between the phases that read other substructures' data.
 constexpr int kCoopNT = 512;
-constexpr int kCoopMeta = 8;   // per substructure: nI, ng, nr, ncs, n_sh, n_g1, goff, coff
+constexpr int kCoopMeta = 9;   // per substructure: nI, ng, nr, ncs, n_sh, n_g1, goff, coff, n_phi
 struct CoopDev {
   int nsub = 0;
   int ncL = 0;
@@ -102,9 +102,11 @@ struct CoopDev {
   int opmax = 0;                      // largest operator block (doubles)
   int idxmax = 0;                     // largest index block (ints)
   int cg_len = 0;                     // coarse gather block (ints)
-  const double* ops = nullptr;        // per substructure: Linv | L_GI (ng x nI) | T_rr | Psi | delta
+  // per substructure: Linv | L_GI (ng x nI) | T_rr | Psi | delta | phi weights
+  const double* ops = nullptr;
   const int64_t* opoff = nullptr;
-  const int32_t* idx = nullptr;       // per substructure: int_gid | gam_gid | own | shp | shf | gp | gf | cid
+  // per substructure: int_gid | gam_gid | own | shp | shf | gp | gf | cid | phi_ptr | phi_ids
+  const int32_t* idx = nullptr;
   const int64_t* idxoff = nullptr;
   const int32_t* meta = nullptr;      // kCoopMeta ints per substructure
   const int32_t* cg = nullptr;        // coarsest gather: ptr (ncL+1) | flat coarse indices
@@ -112,7 +114,8 @@ struct CoopDev {
   const double* b1 = nullptr;         // level-1 coarse contributions (input)
   double* t = nullptr;                // level-2 interface flat scratch
   double* b = nullptr;                // level-2 coarse flat scratch
-  double* v = nullptr;                // level-2 interface flat scratch
+  double* da = nullptr;               // level-2 interface flat scratch: delta T_rr g
+  const int32_t* sub_of_flat = nullptr;   // level-2 interface flat entry -> substructure (setup only)
   double* u2 = nullptr;               // level-2 solution (output)
   const int32_t* stop = nullptr;
   unsigned* bar = nullptr;            // grid barrier: count, generation
@@ -134,8 +137,13 @@ struct PcgDev {
   double* rr_part = nullptr;                 // per level-1 substructure: owned r.r
   double* rz_part[2] = {nullptr, nullptr};   // per level-1 substructure, by iteration parity
   double* qloc = nullptr;                    // local Schur products, level-1 interface flat
+  double* da = nullptr;                      // delta T_rr g, level-1 interface flat
+  const int32_t* phi_ptr = nullptr;          // per interface dof: its row of the delta-weighted
+  const int32_t* phi_ids = nullptr;          //   coarse basis of all sharers (coarse ids, weights)
+  const double* phi_w = nullptr;
   int nif = 0;
   int nsub1 = 0;
+  int nblk = 1;                              // blocks of the interface average (rz partials)
 };
 
 constexpr int kMaxHist = 4096;
@@ -240,7 +248,9 @@ void launch_apply_post_inv(hipStream_t st, const LevelDev& L, int nImax, int ngm
 // fused PCG iteration kernels (level-1 interface)
 void launch_pcg_matvec(hipStream_t st, const LevelDev& L, int ngmax, const PcgDev& P, int it);
 void launch_pcg_update_restrict(hipStream_t st, const LevelDev& L, int ngmax, const PcgDev& P, int it);
-void launch_pcg_prolong(hipStream_t st, const LevelDev& L, int ncsmax, const PcgDev& P, const double* uc, int check);
-void launch_pcg_post(hipStream_t st, const LevelDev& L, const PcgDev& P, int parity);
+void launch_pcg_prolong_post(hipStream_t st, const LevelDev& L, const PcgDev& P, const double* uc, int check,
+                            int parity);
+void launch_build_phi(hipStream_t st, const LevelDev& L, int nif, const int32_t* sub_of_flat, const int32_t* phi_ptr,
+                      double* phi_w);
 
 }  // namespace bddc
