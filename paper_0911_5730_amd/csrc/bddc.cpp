@@ -102,24 +102,60 @@ void Staging::flush() {
   items_.clear();
 }
 
-hipMemPool_t device_pool() {
-  static std::mutex mu;
-  static std::map<int, hipMemPool_t> pools;
+namespace {
+struct DevBlock {
+  int dev;
+  size_t size;
+};
+std::mutex g_dev_mu;
+std::multimap<size_t, std::pair<int, void*>> g_dev_free;   // size -> (device, pointer)
+std::map<void*, DevBlock> g_dev_blocks;                     // every block made
+}  // namespace
+
+void* device_acquire(size_t bytes) {
   int dev = 0;
   BDDC_HIP(hipGetDevice(&dev));
-  std::lock_guard<std::mutex> lk(mu);
-  auto it = pools.find(dev);
-  if (it != pools.end()) return it->second;
-  hipMemPoolProps props{};
-  props.allocType = hipMemAllocationTypePinned;
-  props.location.type = hipMemLocationTypeDevice;
-  props.location.id = dev;
-  hipMemPool_t pool;
-  BDDC_HIP(hipMemPoolCreate(&pool, &props));
-  uint64_t thr = UINT64_MAX;
-  BDDC_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr));
-  pools[dev] = pool;
-  return pool;
+  {
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    for (auto it = g_dev_free.lower_bound(bytes); it != g_dev_free.end() && it->first <= 2 * bytes + (1 << 20); ++it) {
+      if (it->second.first != dev) continue;
+      void* p = it->second.second;
+      g_dev_free.erase(it);
+      return p;
+    }
+  }
+  void* p = nullptr;
+  const size_t n = (bytes + 4095) & ~size_t(4095);
+  hipError_t e = hipMalloc(&p, n);
+  if (e != hipSuccess) {
+    // give the cached blocks back and try once more
+    {
+      std::lock_guard<std::mutex> lk(g_dev_mu);
+      for (auto it = g_dev_free.begin(); it != g_dev_free.end();) {
+        if (it->second.first == dev) {
+          (void)hipFree(it->second.second);
+          g_dev_blocks.erase(it->second.second);
+          it = g_dev_free.erase(it);
+        } else {
+          ++it;
+        }
+      }
+    }
+    (void)hipGetLastError();
+    e = hipMalloc(&p, n);
+    if (e != hipSuccess)
+      fail(e == hipErrorOutOfMemory ? BDDC_ENOMEM : BDDC_EDEVICE, std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  std::lock_guard<std::mutex> lk(g_dev_mu);
+  g_dev_blocks[p] = DevBlock{dev, n};
+  return p;
+}
+
+void device_release(void* p) {
+  if (!p) return;
+  std::lock_guard<std::mutex> lk(g_dev_mu);
+  auto it = g_dev_blocks.find(p);
+  if (it != g_dev_blocks.end()) g_dev_free.insert({it->second.size, {it->second.dev, p}});
 }
 
 // ---------------------------------------------------------------------------
@@ -425,6 +461,8 @@ struct Level1Elements {
   std::vector<int32_t> nodes;   // 4 per element, -1 = Dirichlet
 };
 
+// level-1 elements as a general element list (used by bddc_plan to check the
+// grid classification against the general one)
 static Level1Elements level1_elements(const bddc_problem* p) {
   const int nx = p->nx, ny = p->ny;
   Level1Elements E;
@@ -622,20 +660,19 @@ class Builder {
 
   void run() {
     HostClock clk;
-    Level1Elements E = level1_elements(p_);
-    clk.lap("elements");
     // level 1
+    GridMaps G;
     auto lv = std::make_unique<Level>();
     lv->ell = 1;
-    lv->topo = classify((int)h_->n_free, p_->nsub, E.ptr, E.dof, E.sub, E.touch);
+    lv->topo = classify_grid(p_->nx, p_->ny, p_->part, p_->nsub, &G);
     clk.lap("classify l1");
     layout_level(*lv);
     check_limits(*lv);
     clk.lap("layout l1");
     top_alloc();
-    alloc_a(*lv, &E, nullptr);
+    alloc_a(*lv, &G, nullptr);
     clk.lap("alloc_a l1");
-    assemble_l1(*lv, E);
+    assemble_l1(*lv);
     factor_level(*lv, nullptr);
     clk.lap("factor l1");
     h_->levels.push_back(std::move(lv));
@@ -664,12 +701,17 @@ class Builder {
       h_->levels.push_back(std::move(nl));
     }
     coarsest();
-    BDDC_HIP(hipStreamSynchronize(st_));
-    for (void* b : h_->staged) pinned_release(b);
-    h_->staged.clear();
     clk.lap("coarsest");
+  }
+
+  // Wait for the set-up's device work, release its staging buffers and check
+  // the factorizations (called once everything of the set-up is enqueued).
+  static void finish(bddc_ctx* h) {
     int bad = 0;
-    BDDC_HIP(hipMemcpy(&bad, h_->status, sizeof(int), hipMemcpyDeviceToHost));
+    BDDC_HIP(hipMemcpyAsync(&bad, h->status, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    BDDC_HIP(hipStreamSynchronize(h->stream));
+    for (void* b : h->staged) pinned_release(b);
+    h->staged.clear();
     if (bad & 2) fail(BDDC_EINVAL, "coefficients must be positive and finite");
     if (bad) fail(BDDC_ESINGULAR, "a local or coarse factorization met a non-positive pivot");
   }
@@ -694,45 +736,20 @@ class Builder {
   }
 
   // device allocation of everything known before the coarse dofs are chosen
-  void alloc_a(Level& lv, const Level1Elements* E, const Level* prev) {
+  void alloc_a(Level& lv, GridMaps* G, const Level* prev) {
+    HostClock clk;
     const Topology& T = lv.topo;
     const int nsub = lv.nsub;
     const int ninc = 2 * lv.nedge;
     const bool adaptive = h_->constraints == BDDC_ADAPTIVE;
-    // level-1 assembly maps
+    // level-1 assembly maps (from the grid classification)
     std::vector<int32_t> node_el, sub_el_ptr, el_gid, el_loc;
     std::vector<int32_t> child_ptr, child_id, child_map_off, child_map;
-    if (E) {
-      const int ne = h_->nx * h_->ny;
-      std::vector<int32_t> cnt(nsub, 0);
-      for (int e = 0; e < ne; ++e) cnt[E->sub[e]]++;
-      sub_el_ptr = prefix(cnt);
-      el_gid.resize(ne);
-      {
-        std::vector<int32_t> pos(sub_el_ptr.begin(), sub_el_ptr.end() - 1);
-        for (int e = 0; e < ne; ++e) el_gid[pos[E->sub[e]]++] = e;
-      }
-      el_loc.assign((size_t)ne * 4, -1);
-      node_el.assign((size_t)T.loc_ptr[nsub] * 4, -1);
-      std::vector<int32_t> posin(T.n, -1);
-      for (int s = 0; s < nsub; ++s) {
-        const int b = T.loc_ptr[s];
-        for (int a = 0; a < T.nloc(s); ++a) posin[T.loc_dof[b + a]] = a;
-        for (int le = 0; le < sub_el_ptr[s + 1] - sub_el_ptr[s]; ++le) {
-          const int e = el_gid[sub_el_ptr[s] + le];
-          for (int q = 0; q < 4; ++q) {
-            const int d = E->nodes[(size_t)e * 4 + q];
-            if (d < 0) continue;
-            const int a = posin[d];
-            el_loc[(size_t)(sub_el_ptr[s] + le) * 4 + q] = a;
-            int32_t* slot = &node_el[(size_t)(b + a) * 4];
-            int k = 0;
-            while (slot[k] >= 0) ++k;
-            slot[k] = (le << 2) | q;
-          }
-        }
-        for (int a = 0; a < T.nloc(s); ++a) posin[T.loc_dof[b + a]] = -1;
-      }
+    if (G) {
+      node_el.swap(G->node_el);
+      sub_el_ptr.swap(G->sub_el_ptr);
+      el_gid.swap(G->el_gid);
+      el_loc.swap(G->el_loc);
     }
     if (prev) {
       // children of each level-l substructure and their coarse dofs in its local numbering
@@ -770,6 +787,7 @@ class Builder {
     if (prev)
       for (int s = 0; s < nsub; ++s) lv.linvoff[s + 1] = lv.linvoff[s] + (int64_t)T.n_int[s] * T.n_int[s];
 
+    clk.lap("  maps");
     Arena& A = lv.arena_a;
     auto& d = lv.d;
     // the same layout runs twice: sizing (null base), then on the allocation
@@ -794,7 +812,7 @@ class Builder {
       d.sub_el_ptr = A.take<int32_t>(sub_el_ptr.size());
       d.el_gid = A.take<int32_t>(el_gid.size());
       d.el_loc = A.take<int32_t>(el_loc.size());
-      d.coeff = A.take<double>(E ? (size_t)h_->nx * h_->ny : 0);
+      d.coeff = A.take<double>(G ? (size_t)h_->nx * h_->ny : 0);
       d.child_ptr = A.take<int32_t>(child_ptr.size());
       d.child_id = A.take<int32_t>(child_id.size());
       d.child_map_off = A.take<int32_t>(child_map_off.size());
@@ -836,6 +854,7 @@ class Builder {
     layout(false);
     A.allocate(st_);
     layout(true);
+    clk.lap("  allocate");
 
     std::vector<int32_t> nint(T.n_int), nr(T.n_r);
     std::vector<double> ones;
@@ -856,10 +875,10 @@ class Builder {
     stg.add(d.sub_el_ptr, sub_el_ptr);
     stg.add(d.el_gid, el_gid);
     stg.add(d.el_loc, el_loc);
-    if (E && p_->coeff_device)
+    if (G && p_->coeff_device)
       BDDC_HIP(hipMemcpyAsync(d.coeff, p_->coeff_device, sizeof(double) * h_->nx * h_->ny,
                               hipMemcpyDeviceToDevice, st_));
-    else if (E)
+    else if (G)
       BDDC_HIP(hipMemcpyAsync(d.coeff, p_->coeff, sizeof(double) * h_->nx * h_->ny, hipMemcpyHostToDevice, st_));
     stg.add(d.child_ptr, child_ptr);
     stg.add(d.child_id, child_id);
@@ -892,10 +911,11 @@ class Builder {
       stg.add(d.z, ones);
     }
     stg.flush();
+    clk.lap("  staging");
     // the staging buffer waits for its copies when it goes out of scope
   }
 
-  void assemble_l1(Level& lv, const Level1Elements&) {
+  void assemble_l1(Level& lv) {
     const Khat16 kh = element_matrix(p_->element, h_->nx, h_->ny);
     launch_assemble_l1(st_, lv.nsub, lv.d.koff, lv.d.loc_ptr, lv.d.nint, lv.d.node_el, lv.d.sub_el_ptr,
                        lv.d.el_gid, lv.d.el_loc, lv.d.coeff, kh, lv.d.K, lv.d.diagK, lv.d.goff, h_->status);
@@ -909,6 +929,7 @@ class Builder {
 
   // weights, interior elimination, constraint selection, constrained factors
   void factor_level(Level& lv, const Level*) {
+    HostClock clk;
     auto& d = lv.d;
     const Topology& T = lv.topo;
     launch_weights(st_, lv.nflat_g, d.gam_iid, d.sh_ptr, d.sh_flat, d.diagK, d.delta);
@@ -948,7 +969,9 @@ class Builder {
       BDDC_HIP(hipMemcpyAsync(nkept.data(), d.nkept, sizeof(int32_t) * ne_tot, hipMemcpyDeviceToHost, st_));
       BDDC_HIP(hipMemcpyAsync(lv.edge_nsel.data(), d.nsel, sizeof(int32_t) * ne_tot, hipMemcpyDeviceToHost, st_));
       BDDC_HIP(hipMemcpyAsync(lv.lam.data(), d.lam, sizeof(double) * lv.lam.size(), hipMemcpyDeviceToHost, st_));
+      clk.lap("  enqueue factor+eig");
       BDDC_HIP(hipStreamSynchronize(st_));
+      clk.lap("  wait eig");
       lv.omega = 0.0;
       for (int e = 0; e < ne_tot; ++e) {
         lv.edge_m[e] = nkept[e];
@@ -967,8 +990,11 @@ class Builder {
       h2d(d.Q, qh, st_);
     }
     coarse_numbering(lv);
+    clk.lap("  coarse numbering");
     account(lv);
+    clk.lap("  account");
     alloc_b(lv);
+    clk.lap("  alloc_b");
     launch_build_cr(st_, lv.nsub, d.sub_inc_ptr, d.sub_inc, d.inc_edge, d.inc_fptr, d.inc_fpos, d.edge_nsc,
                     d.edge_ne, d.edge_m, d.qoff, d.Q, d.nr, d.ncr, d.croff, d.Cr);
     size_t cf_lds = 0;
@@ -1321,7 +1347,7 @@ static bool plan_coop(bddc_ctx* h) {
   A.allocate(h->stream);
   lay();
   hipStream_t st = h->stream;
-  Staging stg(st);
+  Staging stg(st, &h->staged);
   stg.add(const_cast<int64_t*>(C.opoff), opoff);
   stg.add(const_cast<int32_t*>(C.idx), idx);
   stg.add(const_cast<int64_t*>(C.idxoff), idxoff);
@@ -1339,7 +1365,6 @@ static bool plan_coop(bddc_ctx* h) {
   C.u2 = l1.d.uc;
   C.stop = nullptr;
   C.status = h->status;
-  BDDC_HIP(hipStreamSynchronize(st));
   h->coop = C;
   h->coop_deep = true;
   const char* cl = getenv("BDDC_COOP_LAUNCH");
@@ -1629,10 +1654,15 @@ bddc_status bddc_plan(const bddc_problem* p, bddc_info* info) {
     validate(p);
     clk.lap("validate");
     if (!info) fail(BDDC_EINVAL, "info is NULL");
-    Level1Elements E = level1_elements(p);
-    clk.lap("elements");
     Level lv;
-    lv.topo = classify((p->nx - 1) * (p->ny - 1), p->nsub, E.ptr, E.dof, E.sub, E.touch);
+    const char* how = getenv("BDDC_CLASSIFY");
+    if (how && std::string(how) == "elements") {
+      // the general element-list classification (the one levels >= 2 use)
+      Level1Elements E = level1_elements(p);
+      lv.topo = classify((p->nx - 1) * (p->ny - 1), p->nsub, E.ptr, E.dof, E.sub, E.touch);
+    } else {
+      lv.topo = classify_grid(p->nx, p->ny, p->part, p->nsub, nullptr);
+    }
     clk.lap("classify");
     layout_level(lv);
     clk.lap("layout");
@@ -1659,7 +1689,9 @@ bddc_status bddc_setup(const bddc_problem* p, void* hip_stream, bddc_handle* out
     h->tau = p->tau;
     h->n_free = (int64_t)(p->nx - 1) * (p->ny - 1);
     h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    HostClock clk;
     Builder(h, p).run();
+    clk.lap("builder");
     // PCG state on the level-1 interface
     Level& l1 = *h->levels[0];
     const int nif = (int)l1.iface_dof.size();
@@ -1667,16 +1699,19 @@ bddc_status bddc_setup(const bddc_problem* p, void* hip_stream, bddc_handle* out
     Arena& B = h->levels[0]->arena_pcg;
     PcgDev& P = h->pcg;
     // per interface dof: the sharers' rows of the delta-weighted coarse basis
-    std::vector<int32_t> sub_of_flat(l1.nflat_g), phi_ptr(nif + 1, 0), phi_ids;
+    // (row offsets here; the device fills the coarse ids and weights)
+    std::vector<int32_t> sub_of_flat(l1.nflat_g), phi_ptr(nif + 1, 0);
     for (int s = 0; s < l1.nsub; ++s)
       for (int f = l1.goff[s]; f < l1.goff[s + 1]; ++f) sub_of_flat[f] = s;
     for (int gi = 0; gi < nif; ++gi) {
+      int len = 0;
       for (int q = l1.sh_ptr[gi]; q < l1.sh_ptr[gi + 1]; ++q) {
         const int t = sub_of_flat[l1.sh_flat[q]];
-        for (int k = l1.coff[t]; k < l1.coff[t + 1]; ++k) phi_ids.push_back(l1.cid[k]);
+        len += l1.coff[t + 1] - l1.coff[t];
       }
-      phi_ptr[gi + 1] = (int32_t)phi_ids.size();
+      phi_ptr[gi + 1] = phi_ptr[gi] + len;
     }
+    const size_t nphi = (size_t)phi_ptr[nif];
     int32_t* sub_flat_d = nullptr;
     const int nblk_avg = std::max(1, (nif + kNT / 8 - 1) / (kNT / 8));   // eight lanes per interface dof
     auto lay = [&] {
@@ -1693,8 +1728,8 @@ bddc_status bddc_setup(const bddc_problem* p, void* hip_stream, bddc_handle* out
       P.rz_part[1] = B.take<double>(nblk_avg);
       h->sc = B.take<PcgScalars>(1);
       P.phi_ptr = B.take<int32_t>(phi_ptr.size());
-      P.phi_ids = B.take<int32_t>(phi_ids.size());
-      P.phi_w = B.take<double>(phi_ids.size());
+      P.phi_ids = B.take<int32_t>(nphi);
+      P.phi_w = B.take<double>(nphi);
       sub_flat_d = B.take<int32_t>(sub_of_flat.size());
     };
     B.reset_sizing();
@@ -1711,23 +1746,26 @@ bddc_status bddc_setup(const bddc_problem* p, void* hip_stream, bddc_handle* out
     P.nblk = nblk_avg;
     P.nif = nif;
     {
-      Staging stg(h->stream);
+      Staging stg(h->stream, &h->staged);
       stg.add(const_cast<int32_t*>(P.phi_ptr), phi_ptr);
-      stg.add(const_cast<int32_t*>(P.phi_ids), phi_ids);
       stg.add(sub_flat_d, sub_of_flat);
       stg.flush();
-      launch_build_phi(h->stream, l1.dev, nif, sub_flat_d, P.phi_ptr, const_cast<double*>(P.phi_w));
+      launch_build_phi(h->stream, l1.dev, nif, sub_flat_d, P.phi_ptr, const_cast<int32_t*>(P.phi_ids),
+                       const_cast<double*>(P.phi_w));
     }
     P.nsub1 = l1.nsub;
     {
       double nshare = 0;
       for (int gi = 0; gi < nif; ++gi) nshare += l1.sh_ptr[gi + 1] - l1.sh_ptr[gi];
       // per interface dof: sharer indices and delta T g, phi row (id, weight, u_c), z and r
-      h->by_average = 12.0 * nshare + 20.0 * (double)phi_ids.size() + 8.0 * nif * 4;
+      h->by_average = 12.0 * nshare + 20.0 * (double)nphi + 8.0 * nif * 4;
     }
+    clk.lap("pcg state + phi");
     plan_deep(h);
+    clk.lap("plan deep");
+    Builder::finish(h);
+    clk.lap("finish");
     h->sc_host = static_cast<PcgScalars*>(pinned_acquire(sizeof(PcgScalars)));
-    BDDC_HIP(hipStreamSynchronize(h->stream));
     // info
     std::memset(&h->info, 0, sizeof(h->info));
     h->info.n_free = h->n_free;

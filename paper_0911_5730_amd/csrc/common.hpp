@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <functional>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -27,9 +28,12 @@ struct Error {
       ::bddc::fail(BDDC_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));    \
   } while (0)
 
-// The library's stream-ordered memory pool on the current device; it keeps
-// freed memory (release threshold = max) so that repeated set-ups reuse it.
-hipMemPool_t device_pool();
+// Device memory of the library: blocks from hipMalloc are kept in a
+// process-wide cache per device after release and reused (best fit, at most
+// twice the request) by later allocations, so repeated set-ups allocate and
+// free nothing.  Release only memory that no queued work still uses.
+void* device_acquire(size_t bytes);
+void device_release(void* p);
 
 // One device allocation carved into aligned pieces.  Pieces are laid out by a
 // sizing pass (base == nullptr) and then a second pass after allocation.
@@ -46,18 +50,16 @@ class Arena {
   }
   size_t used() const { return used_; }
   void allocate(hipStream_t st) {
+    (void)st;
     size_t n = used_ ? used_ : 256;
-    hipError_t e = hipMallocFromPoolAsync(reinterpret_cast<void**>(&base_), n, device_pool(), st);
-    if (e != hipSuccess) {
-      base_ = nullptr;
-      fail(e == hipErrorOutOfMemory ? BDDC_ENOMEM : BDDC_EDEVICE,
-           std::string("hipMallocAsync: ") + hipGetErrorString(e));
-    }
+    base_ = static_cast<char*>(device_acquire(n));
     size_ = n;
     used_ = 0;
   }
+  // the caller has synchronised the stream that used the memory
   void release(hipStream_t st) {
-    if (base_) (void)hipFreeAsync(base_, st);
+    (void)st;
+    if (base_) device_release(base_);
     base_ = nullptr;
   }
   size_t size() const { return size_; }
@@ -67,6 +69,11 @@ class Arena {
   size_t used_ = 0;
   size_t size_ = 0;
 };
+
+// body(begin, end) over [0, n) in chunks of `chunk`, on a persistent pool of
+// up to 8 host threads (the caller takes part).  The body must not throw and
+// must write disjoint data for disjoint ranges.
+void parallel_for(int n, int chunk, const std::function<void(int, int)>& body);
 
 // Pinned host buffers, reused across handles: hipHostMalloc is slow and
 // hipHostFree synchronises the device, so buffers stay in a process-wide pool.

@@ -452,10 +452,11 @@ __global__ void __launch_bounds__(kNT) k_pcg_prolong_post(LevelDev L, PcgDev P, 
   if (threadIdx.x == 0) P.rz_part[parity][blockIdx.x] = rz;
 }
 
-// Weights of the averaged coarse-basis rows: for interface dof gi, in sharer
-// order, delta_s(gi) Psi_s(row of gi, :) of every sharer s.
+// Rows of the averaged coarse basis: for interface dof gi, in sharer order,
+// the coarse ids and delta_s(gi) Psi_s(row of gi, :) of every sharer s.
 __global__ void __launch_bounds__(kNT) k_build_phi(LevelDev L, int nif, const int32_t* __restrict__ sub_of_flat,
-                                                   const int32_t* __restrict__ phi_ptr, double* __restrict__ phi_w) {
+                                                   const int32_t* __restrict__ phi_ptr, int32_t* __restrict__ phi_ids,
+                                                   double* __restrict__ phi_w) {
   const int gi = blockIdx.x * kNT + threadIdx.x;
   if (gi >= nif) return;
   int j = phi_ptr[gi];
@@ -466,7 +467,10 @@ __global__ void __launch_bounds__(kNT) k_build_phi(LevelDev L, int nif, const in
     const int ngt = (L.loc_ptr[t + 1] - L.loc_ptr[t]) - L.nint[t];
     const int ncst = L.coff[t + 1] - L.coff[t];
     const double* Pt = L.Psi + L.psioff[t];
-    for (int k = 0; k < ncst; ++k) phi_w[j++] = L.delta[f] * Pt[at + (size_t)k * ngt];
+    for (int k = 0; k < ncst; ++k) {
+      phi_ids[j] = L.cid[L.coff[t] + k];
+      phi_w[j++] = L.delta[f] * Pt[at + (size_t)k * ngt];
+    }
   }
 }
 
@@ -483,9 +487,10 @@ void launch_pcg_prolong_post(hipStream_t st, const LevelDev& L, const PcgDev& P,
   launch_kernel(k_pcg_prolong_post, dim3(P.nblk), dim3(kNT), 0, st, L, P, uc, check, parity);
 }
 void launch_build_phi(hipStream_t st, const LevelDev& L, int nif, const int32_t* sub_of_flat, const int32_t* phi_ptr,
-                      double* phi_w) {
+                      int32_t* phi_ids, double* phi_w) {
   if (nif == 0) return;
-  launch_kernel(k_build_phi, dim3((nif + kNT - 1) / kNT), dim3(kNT), 0, st, L, nif, sub_of_flat, phi_ptr, phi_w);
+  launch_kernel(k_build_phi, dim3((nif + kNT - 1) / kNT), dim3(kNT), 0, st, L, nif, sub_of_flat, phi_ptr, phi_ids,
+                phi_w);
 }
 
 }  // namespace bddc

@@ -29,8 +29,9 @@ __global__ void __launch_bounds__(kNT) k_assemble_l1(
   const int n = loc_ptr[s + 1] - base;
   const int e0 = sub_el_ptr[s];
   double* A = K + koff[s];
+  for (int idx = threadIdx.x; idx < n * n; idx += kNT) A[idx] = 0.0;
+  __syncthreads();
   for (int a = threadIdx.x; a < n; a += kNT) {
-    for (int b = 0; b < n; ++b) A[a + (size_t)b * n] = 0.0;
     for (int k = 0; k < 4; ++k) {
       const int code = node_el[(size_t)(base + a) * 4 + k];
       if (code < 0) continue;

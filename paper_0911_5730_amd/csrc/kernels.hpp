@@ -251,6 +251,6 @@ void launch_pcg_update_restrict(hipStream_t st, const LevelDev& L, int ngmax, co
 void launch_pcg_prolong_post(hipStream_t st, const LevelDev& L, const PcgDev& P, const double* uc, int check,
                             int parity);
 void launch_build_phi(hipStream_t st, const LevelDev& L, int nif, const int32_t* sub_of_flat, const int32_t* phi_ptr,
-                      double* phi_w);
+                      int32_t* phi_ids, double* phi_w);
 
 }  // namespace bddc

@@ -72,7 +72,13 @@ Topology classify(int n, int nsub, const std::vector<int32_t>& elem_ptr,
     raw_ptr[s + 1] = static_cast<int32_t>(raw.size());
   }
   lap("sharers");
+  classify_rules(T, raw_ptr, raw);
+  lap("rules");
+  return T;
+}
 
+void classify_rules(Topology& T, const std::vector<int32_t>& raw_ptr, const std::vector<int32_t>& raw) {
+  const int n = T.n, nsub = T.nsub;
   // corners and edge candidates, ordered by (s, t, dof): counting sort by s
   // (dofs visited in increasing order), then a small sort by t inside each bucket
   std::vector<int32_t> bcnt(nsub + 1, 0);
@@ -100,7 +106,6 @@ Topology classify(int n, int nsub, const std::vector<int32_t>& elem_ptr,
   gstart.push_back(cand.size());
   const size_t ng = gstart.size() - 1;
   std::vector<uint8_t> removed(cand.size(), 0);
-  lap("candidates");
 
   std::unordered_set<uint64_t> covered;
   for (int d = 0; d < n; ++d) {
@@ -140,7 +145,6 @@ Topology classify(int n, int nsub, const std::vector<int32_t>& elem_ptr,
       if (!removed[i]) { T.is_corner[cand[i].second] = 1; removed[i] = 1; break; }
   }
 
-  lap("rules");
   // final edges
   T.edge_ptr.push_back(0);
   for (size_t g = 0; g < ng; ++g) {
@@ -158,13 +162,14 @@ Topology classify(int n, int nsub, const std::vector<int32_t>& elem_ptr,
     if (T.nshare[d] >= 2) T.n_interface++;
   }
 
-  // local ordering [interior | interface non-corner | corner], each group in first-appearance order
+  // local ordering [interior | interface non-corner | corner], each group in the order of raw
   T.loc_ptr.assign(nsub + 1, 0);
   T.n_int.assign(nsub, 0);
   T.n_r.assign(nsub, 0);
   T.n_c.assign(nsub, 0);
   T.loc_dof.resize(raw.size());
-  for (int s = 0; s < nsub; ++s) {
+  parallel_for(nsub, 8, [&](int s0, int s1) {
+  for (int s = s0; s < s1; ++s) {
     int ni = 0, nr = 0, nc = 0;
     for (int k = raw_ptr[s]; k < raw_ptr[s + 1]; ++k) {
       const int d = raw[k];
@@ -185,8 +190,151 @@ Topology classify(int n, int nsub, const std::vector<int32_t>& elem_ptr,
       else T.loc_dof[orr++] = d;
     }
   }
+  });
   T.loc_ptr[nsub] = raw_ptr[nsub];
-  lap("local order");
+}
+
+Topology classify_grid(int nx, int ny, const int32_t* part, int nsub, GridMaps* maps) {
+  const bool timing = getenv("BDDC_HOST_TIMING") != nullptr;
+  auto t0 = std::chrono::steady_clock::now();
+  auto lap = [&](const char* what) {
+    if (!timing) return;
+    const auto now = std::chrono::steady_clock::now();
+    fprintf(stderr, "libbddc classify_grid %-12s %8.3f ms\n", what, std::chrono::duration<double, std::milli>(now - t0).count());
+    t0 = now;
+  };
+  Topology T;
+  const int ne = nx * ny;
+  const int mx = nx - 1;
+  const int n = (nx - 1) * (ny - 1);
+  T.n = n;
+  T.nsub = nsub;
+  T.nshare.assign(n, 0);
+  T.share_.reset(new int32_t[(size_t)std::max(n, 1) * kMaxShare]);
+  int32_t* share = T.share_.get();
+  T.floating.assign(nsub, 1);
+  T.is_corner.assign(n, 0);
+  // elements per substructure; an element on the outer ring carries Dirichlet nodes
+  std::vector<int32_t> ecnt(nsub + 1, 0);
+  for (int e = 0; e < ne; ++e) {
+    const int s = part[e];
+    if (s < 0 || s >= nsub) fail(BDDC_EPARTITION, "part entries must lie in [0, nsub)");
+    ecnt[s + 1]++;
+  }
+  for (int s = 0; s < nsub; ++s) {
+    if (ecnt[s + 1] == 0) fail(BDDC_EPARTITION, "substructure " + std::to_string(s) + " owns no element");
+    ecnt[s + 1] += ecnt[s];
+  }
+  for (int i = 0; i < nx; ++i) {
+    T.floating[part[i]] = 0;
+    T.floating[part[(ny - 1) * nx + i]] = 0;
+  }
+  for (int j = 0; j < ny; ++j) {
+    T.floating[part[j * nx]] = 0;
+    T.floating[part[j * nx + nx - 1]] = 0;
+  }
+  lap("elements");
+  // N_d from the four elements around node (i, j): (i-1,j-1), (i,j-1), (i-1,j), (i,j)
+  parallel_for(ny - 1, 8, [&](int r0, int r1) {
+    for (int j = r0 + 1; j <= r1; ++j)
+      for (int i = 1; i < nx; ++i) {
+        const int d = (j - 1) * mx + (i - 1);
+        const int p4[4] = {part[(j - 1) * nx + i - 1], part[(j - 1) * nx + i], part[j * nx + i - 1], part[j * nx + i]};
+        int32_t* sh = share + (size_t)d * kMaxShare;
+        int m = 0;
+        for (int q = 0; q < 4; ++q) {
+          int k = 0;
+          while (k < m && sh[k] < p4[q]) ++k;
+          if (k < m && sh[k] == p4[q]) continue;
+          for (int r = m; r > k; --r) sh[r] = sh[r - 1];
+          sh[k] = p4[q];
+          ++m;
+        }
+        T.nshare[d] = (uint8_t)m;
+      }
+  });
+  std::vector<int32_t> rcnt(nsub + 1, 0);
+  for (int d = 0; d < n; ++d)
+    for (int k = 0; k < T.nshare[d]; ++k) rcnt[T.share(d)[k] + 1]++;
+  // each substructure's dofs in ascending order
+  for (int s = 0; s < nsub; ++s) rcnt[s + 1] += rcnt[s];
+  std::vector<int32_t> raw_ptr(rcnt), raw(rcnt[nsub]);
+  {
+    std::vector<int32_t> pos(rcnt.begin(), rcnt.end() - 1);
+    for (int d = 0; d < n; ++d)
+      for (int k = 0; k < T.nshare[d]; ++k) raw[pos[T.share(d)[k]]++] = d;
+  }
+  lap("sharers");
+  classify_rules(T, raw_ptr, raw);
+  lap("rules");
+  if (!maps) return T;
+  // assembly maps: elements per substructure (ascending), the local position of
+  // each element node, and for each local dof the (element, corner) pairs
+  GridMaps& M = *maps;
+  M.sub_el_ptr = ecnt;
+  M.el_gid.resize(ne);
+  std::vector<int32_t> loc_e(ne);
+  {
+    std::vector<int32_t> pos(ecnt.begin(), ecnt.end() - 1);
+    for (int e = 0; e < ne; ++e) {
+      const int s = part[e];
+      loc_e[e] = pos[s] - ecnt[s];
+      M.el_gid[pos[s]++] = e;
+    }
+  }
+  lap("el_gid");
+  // posk[d * kMaxShare + k]: local position of d in its k-th sharer
+  std::vector<int32_t> posk((size_t)n * kMaxShare, -1);
+  parallel_for(nsub, 4, [&](int s0, int s1) {
+    for (int s = s0; s < s1; ++s) {
+      const int b = T.loc_ptr[s];
+      for (int a = 0; a < T.nloc(s); ++a) {
+        const int d = T.loc_dof[b + a];
+        const int32_t* sh = T.share(d);
+        int k = 0;
+        while (sh[k] != s) ++k;
+        posk[(size_t)d * kMaxShare + k] = a;
+      }
+    }
+  });
+  auto pos_in = [&](int d, int s) {
+    const int32_t* sh = T.share(d);
+    int k = 0;
+    while (sh[k] != s) ++k;
+    return posk[(size_t)d * kMaxShare + k];
+  };
+  auto fid = [&](int i, int j) -> int {
+    if (i <= 0 || j <= 0 || i >= nx || j >= ny) return -1;
+    return (j - 1) * mx + (i - 1);
+  };
+  lap("posk");
+  M.el_loc.assign((size_t)ne * 4, -1);
+  M.node_el.assign((size_t)T.loc_ptr[nsub] * 4, -1);
+  parallel_for(nsub, 4, [&](int s0, int s1) {
+    for (int s = s0; s < s1; ++s) {
+      // element nodes in local numbering
+      for (int le = 0; le < ecnt[s + 1] - ecnt[s]; ++le) {
+        const int e = M.el_gid[ecnt[s] + le];
+        const int i = e % nx, j = e / nx;
+        const int nd[4] = {fid(i, j), fid(i + 1, j), fid(i + 1, j + 1), fid(i, j + 1)};
+        int32_t* el = &M.el_loc[(size_t)(ecnt[s] + le) * 4];
+        for (int q = 0; q < 4; ++q) el[q] = nd[q] >= 0 ? pos_in(nd[q], s) : -1;
+      }
+      // for each local dof, its elements in s in ascending id with the dof's corner
+      const int b = T.loc_ptr[s];
+      for (int a = 0; a < T.nloc(s); ++a) {
+        const int d = T.loc_dof[b + a];
+        const int i = d % mx + 1, j = d / mx + 1;
+        const int es[4] = {(j - 1) * nx + i - 1, (j - 1) * nx + i, j * nx + i - 1, j * nx + i};
+        const int qs[4] = {2, 3, 1, 0};
+        int32_t* slot = &M.node_el[(size_t)(b + a) * 4];
+        int t = 0;
+        for (int k = 0; k < 4; ++k)
+          if (part[es[k]] == s) slot[t++] = (loc_e[es[k]] << 2) | qs[k];
+      }
+    }
+  });
+  lap("node_el");
   return T;
 }
 

@@ -51,4 +51,26 @@ Topology classify(int n, int nsub, const std::vector<int32_t>& elem_ptr,
                   const std::vector<int32_t>& elem_dof, const std::vector<int32_t>& elem_sub,
                   const std::vector<uint8_t>& elem_touch);
 
+// The rules above applied to given sharer lists (T.nshare, T.share_), floating
+// flags and each substructure's dof list (raw_ptr, raw): corners, edges and the
+// local ordering.
+void classify_rules(Topology& T, const std::vector<int32_t>& raw_ptr, const std::vector<int32_t>& raw);
+
+// Assembly maps of the level-1 grid: elements of each substructure in
+// ascending id (sub_el_ptr, el_gid), the local position of each element node
+// (el_loc, 4 per element, -1 for Dirichlet nodes) and for each local dof the
+// (local element << 2 | corner) entries of its elements (node_el, 4 per dof,
+// -1 padded, elements in ascending id).
+struct GridMaps {
+  std::vector<int32_t> sub_el_ptr, el_gid, el_loc, node_el;
+};
+
+// Level 1 on the nx x ny element grid of the unit square with zero Dirichlet
+// data on the boundary: free node (i, j), 1 <= i < nx, 1 <= j < ny, has id
+// (j-1)(nx-1) + (i-1); element (i, j) has id j nx + i and nodes (i,j), (i+1,j),
+// (i+1,j+1), (i,j+1).  The sharers of a node are the parts of its four
+// elements, so everything is computed node by node; each substructure's dofs
+// are taken in ascending id.  Same rules and errors as classify; maps may be null.
+Topology classify_grid(int nx, int ny, const int32_t* part, int nsub, GridMaps* maps);
+
 }  // namespace bddc

@@ -110,3 +110,34 @@ def test_validation_errors():
     bad.nx = 1
     _expect("BDDC_EINVAL", bad)
     assert P.plan(base)["n_corners"] == 9
+
+
+def _random_partition(nx, nsub, seed):
+    """Irregular partition: each element takes the part of its nearest seed point."""
+    rng = np.random.default_rng(seed)
+    pts = rng.random((nsub, 2))
+    c = (np.arange(nx) + 0.5) / nx
+    X, Y = np.meshgrid(c, c)
+    d = (X.reshape(-1, 1) - pts[:, 0]) ** 2 + (Y.reshape(-1, 1) - pts[:, 1]) ** 2
+    part = np.argmin(d, axis=1).astype(np.int32)
+    used = np.unique(part)
+    remap = np.full(nsub, -1, dtype=np.int32)
+    remap[used] = np.arange(used.size, dtype=np.int32)
+    return remap[part], int(used.size)
+
+
+@pytest.mark.parametrize("nx,nsub,seed", [(24, 9, 1), (40, 23, 2), (17, 6, 3), (64, 50, 4)])
+def test_grid_and_element_list_classifications_agree(nx, nsub, seed, monkeypatch):
+    """Level 1 is classified node by node on the grid; the general
+    element-list classification (used at levels >= 2) must give the same
+    topology, and both must match the oracle, on irregular partitions."""
+    prob = synth.square_problem(nx, 1)
+    prob.part, prob.nsub = _random_partition(nx, nsub, seed)
+    grid = P.plan(prob)
+    monkeypatch.setenv("BDDC_CLASSIFY", "elements")
+    general = P.plan(prob)
+    for k in ("n_free", "nsub", "n_dof", "n_interface", "n_corners", "n_edges"):
+        assert grid[k] == general[k], (k, grid[k], general[k])
+    want = _oracle_counts(prob)
+    for k, v in want.items():
+        assert grid[k] == v, (k, grid[k], v)
