@@ -25,6 +25,11 @@
 
 namespace bddc {
 
+void check_launch() {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) fail(BDDC_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+}
+
 namespace {
 std::mutex g_pinned_mu;
 std::vector<std::pair<void*, size_t>> g_pinned_free;   // buffers not in use
@@ -268,6 +273,14 @@ bool use_mfma_chol(int nmax) {
   const char* env = getenv("BDDC_CHOL_PATH");
   if (env && std::string(env) == "lds16") return false;
   return partial_chol_mfma_nb(nmax) >= 16 && partial_chol_mfma_lds(nmax) <= kLdsMax;
+}
+
+// Level-1 interior sweeps streamed through LDS panels unless the substructures
+// are too large for them or BDDC_SWEEP=off.
+bool use_sweep(int nmax) {
+  const char* env = getenv("BDDC_SWEEP");
+  if (env && std::string(env) == "off") return false;
+  return sweep_fits(nmax);
 }
 
 // Local coarse-space factorization and interior triangular inverse in LDS,
@@ -1236,11 +1249,18 @@ static void run_deep(bddc_ctx* h) {
 static void apply_full(bddc_ctx* h, const double* r, double* u) {
   Level& l1 = *h->levels[0];
   hipStream_t st = h->stream;
-  launch_apply_pre(st, l1.dev, l1.nImax, l1.ngmax, r);
+  const bool sweep = use_sweep(l1.nmax);
+  if (sweep)
+    launch_sweep_pre(st, l1.dev, r);
+  else
+    launch_apply_pre(st, l1.dev, l1.nImax, l1.ngmax, r);
   launch_apply_restrict(st, l1.dev, l1.ngmax, r, l1.d.gam_gid, 1);
   run_deep(h);
   launch_apply_prolong(st, l1.dev, l1.ncsmax, l1.d.uc);
-  launch_apply_post(st, l1.dev, l1.nImax, l1.ngmax, u, l1.d.gam_gid, 1);
+  if (sweep)
+    launch_sweep_post(st, l1.dev, u, l1.d.gam_gid);
+  else
+    launch_apply_post(st, l1.dev, l1.nImax, l1.ngmax, u, l1.d.gam_gid, 1);
 }
 
 // One deep level and a small coarsest problem: pack the level-2 operators and
@@ -1477,7 +1497,11 @@ static int pcg_one(bddc_ctx* h, const double* f, double* u, double rtol, int max
   BDDC_HIP(hipMemcpyAsync(h->sc, sch, offsetof(PcgScalars, alphas), hipMemcpyHostToDevice, st));
   launch_dot_partial(st, nbf, (int)h->n_free, f, f, h->partial);
   launch_scalar(st, 4, nbf, h->partial, h->sc);                   // bb, thr2 = rtol^2 bb
-  launch_apply_pre(st, l1.dev, l1.nImax, l1.ngmax, f);            // y = L^{-1} f_I, t = L_GI y
+  const bool sweep = use_sweep(l1.nmax);
+  if (sweep)                                                       // y = L^{-1} f_I, t = L_GI y
+    launch_sweep_pre(st, l1.dev, f);
+  else
+    launch_apply_pre(st, l1.dev, l1.nImax, l1.ngmax, f);
   launch_condense(st, nif, l1.d.sh_ptr, l1.d.sh_flat, l1.d.iface_dof, f, l1.d.t, h->r, h->x);
   launch_dot_partial(st, nb, nif, h->r, h->r, h->partial);
   launch_scalar(st, 5, nb, h->partial, h->sc);                    // rr0, done if already small
@@ -1531,7 +1555,10 @@ static int pcg_one(bddc_ctx* h, const double* f, double* u, double rtol, int max
     if (sch->done) break;
   }
   timing::current_tag = -1;
-  launch_recover(st, l1.dev, l1.nImax, l1.ngmax, h->x, u);
+  if (sweep)
+    launch_sweep_recover(st, l1.dev, h->x, u);
+  else
+    launch_recover(st, l1.dev, l1.nImax, l1.ngmax, h->x, u);
   int dev_status = 0;
   BDDC_HIP(hipMemcpyAsync(sch, h->sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, st));
   BDDC_HIP(hipMemcpyAsync(&dev_status, h->status, sizeof(int), hipMemcpyDeviceToHost, st));

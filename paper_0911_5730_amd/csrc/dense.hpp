@@ -11,6 +11,29 @@
 
 namespace bddc {
 
+// Walks the flat indices start, start + step, ... of a column-major space with
+// m rows as (row i, column j) without a division per step (integer division by
+// a run-time value costs tens of instructions on the vector unit).
+// With no rows the walk is empty: j starts past any column count.
+struct ColWalk {
+  int i, j, di, dj, m;
+  __device__ ColWalk(int start, int step, int rows) : m(rows > 0 ? rows : 1) {
+    i = start % m;
+    j = rows > 0 ? start / m : 0x7fffffff;
+    di = step % m;
+    dj = rows > 0 ? step / m : 0;
+  }
+  __device__ void next() {
+    i += di;
+    j += dj;
+    if (i >= m) {
+      i -= m;
+      ++j;
+    }
+  }
+};
+
+
 __device__ inline void flag_bad(int* status) {
   if (status) atomicOr(status, 1);
 }
@@ -32,8 +55,9 @@ __device__ inline void wg_partial_potrf(double* A, int lda, int n, int m, int* s
     __syncthreads();
     if (tid == 0) A[j + (size_t)j * lda] = s;
     const int w = n - j - 1;
-    for (int idx = tid; idx < w * w; idx += kNT) {
-      const int ii = idx % w, cc = idx / w;
+    for (ColWalk w_(tid, kNT, w); w_.j < w; w_.next()) {
+      const int ii = w_.i, cc = w_.j;
+      [[maybe_unused]] const int idx = ii + cc * w;
       if (ii >= cc) {
         const int i = j + 1 + ii, c = j + 1 + cc;
         A[i + (size_t)c * lda] -= A[i + (size_t)j * lda] * A[c + (size_t)j * lda];
@@ -49,8 +73,9 @@ __device__ inline void wg_potrf(double* A, int lda, int n, int* status) {
 
 // Copy the lower triangle of the n x n matrix A into its upper triangle.
 __device__ inline void wg_mirror_lower(double* A, int lda, int n) {
-  for (int idx = threadIdx.x; idx < n * n; idx += kNT) {
-    const int i = idx % n, c = idx / n;
+  for (ColWalk w_(threadIdx.x, kNT, n); w_.j < n; w_.next()) {
+    const int i = w_.i, c = w_.j;
+    [[maybe_unused]] const int idx = i + c * n;
     if (i < c) A[i + (size_t)c * lda] = A[c + (size_t)i * lda];
   }
   __syncthreads();
@@ -85,8 +110,9 @@ __device__ inline void wg_trsm_lower_trans(const double* L, int ldl, int n, doub
 // C = alpha * op(A) op(B) + beta * C for small matrices, one thread per entry of C.
 __device__ inline void wg_gemm(bool ta, bool tb, int m, int n, int k, double alpha, const double* A,
                                int lda, const double* B, int ldb, double beta, double* C, int ldc) {
-  for (int idx = threadIdx.x; idx < m * n; idx += kNT) {
-    const int i = idx % m, j = idx / m;
+  for (ColWalk w_(threadIdx.x, kNT, m); w_.j < n; w_.next()) {
+    const int i = w_.i, j = w_.j;
+    [[maybe_unused]] const int idx = i + j * m;
     double acc = 0.0;
     for (int p = 0; p < k; ++p) {
       const double a = ta ? A[p + (size_t)i * lda] : A[i + (size_t)p * lda];

@@ -42,8 +42,9 @@ __global__ void __launch_bounds__(kNT) k_apply_pre(LevelDev L, const double* __r
   for (int i = tid; i < nI; i += kNT) L.y[L.ioff[s] + i] = y[i];
   if (ng == 0) return;
   const int nch = max(1, kNT / ng);
-  for (int idx = tid; idx < ng * nch; idx += kNT) {
-    const int a = idx % ng, c = idx / ng;
+  for (ColWalk w_(tid, kNT, ng); w_.j < nch; w_.next()) {
+    const int a = w_.i, c = w_.j;
+    [[maybe_unused]] const int idx = a + c * ng;
     double acc = 0.0;
     for (int j = c; j < nI; j += nch) acc += A[(nI + a) + (size_t)j * n] * y[j];
     part[idx] = acc;
@@ -87,8 +88,9 @@ __global__ void __launch_bounds__(kNT) k_apply_restrict(LevelDev L, const double
   const double* T = L.T + L.toff[s];
   if (n_r > 0) {
     const int nch = max(1, kNT / n_r);
-    for (int idx = tid; idx < n_r * nch; idx += kNT) {
-      const int i = idx % n_r, c = idx / n_r;
+    for (ColWalk w_(tid, kNT, n_r); w_.j < nch; w_.next()) {
+      const int i = w_.i, c = w_.j;
+      [[maybe_unused]] const int idx = i + c * n_r;
       part[idx] = dot_strided(T + i, n_r, g, c, n_r, nch);
     }
   }
@@ -208,8 +210,9 @@ __global__ void __launch_bounds__(kNT) k_schur_local(LevelDev L, const double* _
   for (int a = tid; a < ng; a += kNT) pl[a] = p[L.gam_iid[g0 + a]];
   __syncthreads();
   const int nch = max(1, kNT / ng);
-  for (int idx = tid; idx < ng * nch; idx += kNT) {
-    const int i = idx % ng, c = idx / ng;
+  for (ColWalk w_(tid, kNT, ng); w_.j < nch; w_.next()) {
+    const int i = w_.i, c = w_.j;
+    [[maybe_unused]] const int idx = i + c * ng;
     double acc = 0.0;
     for (int j = c; j < ng; j += nch) acc += S[i + (size_t)j * n] * pl[j];
     part[idx] = acc;

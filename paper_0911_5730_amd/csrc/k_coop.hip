@@ -285,8 +285,9 @@ __global__ void __launch_bounds__(kNT) k_pack_coop(LevelDev L, CoopDev C) {
   const double* P = L.Psi + L.psioff[s];
   for (int idx = threadIdx.x; idx < nI * nI; idx += kNT) o[idx] = Li[idx];
   o += (size_t)nI * nI;
-  for (int idx = threadIdx.x; idx < ng * nI; idx += kNT) {
-    const int a = idx % ng, j = idx / ng;
+  for (ColWalk w_(threadIdx.x, kNT, ng); w_.j < nI; w_.next()) {
+    const int a = w_.i, j = w_.j;
+    [[maybe_unused]] const int idx = a + j * ng;
     o[idx] = K[nI + a + (size_t)j * n];
   }
   o += (size_t)ng * nI;
@@ -329,8 +330,9 @@ __global__ void __launch_bounds__(kNT) k_tri_inverse_dense(const double* __restr
   double* rowk = M + (size_t)m * m;
   double* colk = rowk + m;
   const int tid = threadIdx.x;
-  for (int idx = tid; idx < m * m; idx += kNT) {
-    const int i = idx % m, j = idx / m;
+  for (ColWalk w_(tid, kNT, m); w_.j < m; w_.next()) {
+    const int i = w_.i, j = w_.j;
+    [[maybe_unused]] const int idx = i + j * m;
     M[idx] = (i >= j) ? L[i + (size_t)j * ld] : 0.0;
   }
   __syncthreads();
@@ -342,8 +344,8 @@ __global__ void __launch_bounds__(kNT) k_tri_inverse_dense(const double* __restr
     for (int c = tid; c < k; c += kNT) M[k + (size_t)c * m] = rowk[c];
     if (tid == 0) M[k + (size_t)k * m] = d;
     const int rows = m - k - 1;
-    for (int idx = tid; idx < rows * (k + 1); idx += kNT) {
-      const int i = k + 1 + idx % rows, c = idx / rows;
+    for (ColWalk w_(tid, kNT, rows); w_.j < k + 1; w_.next()) {
+      const int i = k + 1 + w_.i, c = w_.j;
       M[i + (size_t)c * m] = (c == k) ? -colk[i] * d : M[i + (size_t)c * m] - colk[i] * rowk[c];
     }
     __syncthreads();

@@ -60,12 +60,14 @@ __global__ void __launch_bounds__(kNT) k_pair_schur(
   }
   __syncthreads();
   // gather, eight loads in flight per thread
+  ColWalk cw(tid, kNT, ng);
   for (int base = tid; base < ng * ng; base += 8 * kNT) {
     double v[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int idx = base + u * kNT;
-      v[u] = idx < ng * ng ? S[perm[idx % ng] + (size_t)perm[idx / ng] * n] : 0.0;
+      v[u] = idx < ng * ng ? S[perm[cw.i] + (size_t)perm[cw.j] * n] : 0.0;
+      cw.next();
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u)
@@ -73,14 +75,16 @@ __global__ void __launch_bounds__(kNT) k_pair_schur(
   }
   __syncthreads();
   double* sff = Sff + inc_off[inc];
-  for (int idx = tid; idx < nF * nF; idx += kNT) {
-    const int i = idx % nF, j = idx / nF;
+  for (ColWalk w_(tid, kNT, nF); w_.j < nF; w_.next()) {
+    const int i = w_.i, j = w_.j;
+    [[maybe_unused]] const int idx = i + j * nF;
     sff[idx] = M[(nR + i) + (size_t)(nR + j) * ng];
   }
   wg_partial_potrf(M, ng, ng, nR, status);
   double* sh = Shat + inc_off[inc];
-  for (int idx = tid; idx < nF * nF; idx += kNT) {
-    const int i = idx % nF, j = idx / nF;
+  for (ColWalk w_(tid, kNT, nF); w_.j < nF; w_.next()) {
+    const int i = w_.i, j = w_.j;
+    [[maybe_unused]] const int idx = i + j * nF;
     const int a = max(i, j), b = min(i, j);
     sh[idx] = M[(nR + a) + (size_t)(nR + b) * ng];
   }
@@ -145,8 +149,9 @@ __global__ void __launch_bounds__(kNT) k_pair_eig(
   }
   // M in the coordinates v = [shared corners | s-edge | t-edge]: s side at F
   // index i = v index i, t side at v index i (corners) or i + ne (t-edge)
-  for (int idx = tid; idx < nv * nv; idx += kNT) {
-    const int vi = idx % nv, vj = idx / nv;
+  for (ColWalk w_(tid, kNT, nv); w_.j < nv; w_.next()) {
+    const int vi = w_.i, vj = w_.j;
+    [[maybe_unused]] const int idx = vi + vj * nv;
     double y = 0.0;
     if (vi < nF && vj < nF) y += Shs[vi + (size_t)vj * nF];
     const int ti = vi < nsc ? vi : (vi >= nsc + ne ? vi - ne : -1);
@@ -172,23 +177,26 @@ __global__ void __launch_bounds__(kNT) k_pair_eig(
     amax = red[0];
     __syncthreads();
     const double scale = amax / nq;
-    for (int idx = tid; idx < nv * nv; idx += kNT) {
-      const int i = idx % nv, j = idx / nv;
+    for (ColWalk w_(tid, kNT, nv); w_.j < nv; w_.next()) {
+      const int i = w_.i, j = w_.j;
+      [[maybe_unused]] const int idx = i + j * nv;
       Y[idx] += scale * q[i] * q[j];
     }
     __syncthreads();
   }
   wg_potrf(Y, nv, nv, status);
   // X = L^{-1} B^T,  B^T columns: +1 at the s-edge dof, -1 at the t-edge dof
-  for (int idx = tid; idx < nv * ne; idx += kNT) {
-    const int v = idx % nv, p = idx / nv;
+  for (ColWalk w_(tid, kNT, nv); w_.j < ne; w_.next()) {
+    const int v = w_.i, p = w_.j;
+    [[maybe_unused]] const int idx = v + p * nv;
     X[idx] = (v == nsc + p) ? 1.0 : ((v == nsc + ne + p) ? -1.0 : 0.0);
   }
   __syncthreads();
   wg_trsm_lower(Y, nv, nv, X, nv, ne);
   // N_e = D_t S_s,ee D_t + D_s S_t,ee D_s  -> R (Cholesky);  G = X^T X
-  for (int idx = tid; idx < ne * ne; idx += kNT) {
-    const int i = idx % ne, j = idx / ne;
+  for (ColWalk w_(tid, kNT, ne); w_.j < ne; w_.next()) {
+    const int i = w_.i, j = w_.j;
+    [[maybe_unused]] const int idx = i + j * ne;
     const double ss = Sfs[(nsc + i) + (size_t)(nsc + j) * nF];
     const double tt = Sft[(nsc + i) + (size_t)(nsc + j) * nF];
     R[idx] = dt[i] * ss * dt[j] + ds[i] * tt * ds[j];
@@ -198,28 +206,32 @@ __global__ void __launch_bounds__(kNT) k_pair_eig(
   }
   __syncthreads();
   wg_potrf(R, ne, ne, status);
-  for (int idx = tid; idx < ne * ne; idx += kNT) {
-    const int i = idx % ne, j = idx / ne;
+  for (ColWalk w_(tid, kNT, ne); w_.j < ne; w_.next()) {
+    const int i = w_.i, j = w_.j;
+    [[maybe_unused]] const int idx = i + j * ne;
     if (i < j) R[idx] = 0.0;
   }
   __syncthreads();
   // V = G R, then H = R^T V
-  for (int idx = tid; idx < ne * ne; idx += kNT) {
-    const int i = idx % ne, j = idx / ne;
+  for (ColWalk w_(tid, kNT, ne); w_.j < ne; w_.next()) {
+    const int i = w_.i, j = w_.j;
+    [[maybe_unused]] const int idx = i + j * ne;
     double acc = 0.0;
     for (int k = j; k < ne; ++k) acc += G[i + (size_t)k * ne] * R[k + (size_t)j * ne];
     V[idx] = acc;
   }
   __syncthreads();
-  for (int idx = tid; idx < ne * ne; idx += kNT) {
-    const int i = idx % ne, j = idx / ne;
+  for (ColWalk w_(tid, kNT, ne); w_.j < ne; w_.next()) {
+    const int i = w_.i, j = w_.j;
+    [[maybe_unused]] const int idx = i + j * ne;
     double acc = 0.0;
     for (int k = i; k < ne; ++k) acc += R[k + (size_t)i * ne] * V[k + (size_t)j * ne];
     H[idx] = acc;
   }
   __syncthreads();
-  for (int idx = tid; idx < ne * ne; idx += kNT) {
-    const int i = idx % ne, j = idx / ne;
+  for (ColWalk w_(tid, kNT, ne); w_.j < ne; w_.next()) {
+    const int i = w_.i, j = w_.j;
+    [[maybe_unused]] const int idx = i + j * ne;
     if (i > j) {
       const double a = 0.5 * (H[idx] + H[j + (size_t)i * ne]);
       H[idx] = a;
@@ -234,8 +246,9 @@ __global__ void __launch_bounds__(kNT) k_pair_eig(
   const int npair = m / 2;
   for (int sweep = 0; sweep < 60; ++sweep) {
     double off = 0.0, dia = 0.0;
-    for (int idx = tid; idx < ne * ne; idx += kNT) {
-      const int i = idx % ne, j = idx / ne;
+    for (ColWalk w_(tid, kNT, ne); w_.j < ne; w_.next()) {
+      const int i = w_.i, j = w_.j;
+      [[maybe_unused]] const int idx = i + j * ne;
       const double h = H[idx];
       if (i == j) dia += h * h; else off += h * h;
     }
@@ -262,8 +275,9 @@ __global__ void __launch_bounds__(kNT) k_pair_eig(
       }
       __syncthreads();
       // rows: H <- P^T H
-      for (int idx = tid; idx < npair * ne; idx += kNT) {
-        const int k = idx % npair, col = idx / npair;
+      for (ColWalk w_(tid, kNT, npair); w_.j < ne; w_.next()) {
+        const int k = w_.i, col = w_.j;
+        [[maybe_unused]] const int idx = k + col * npair;
         int a = (k == 0) ? 0 : ((k - 1 + r) % (m - 1)) + 1;
         int b = ((m - 1 - k - 1 + r) % (m - 1)) + 1;
         int p = min(a, b), q2 = max(a, b);
@@ -275,8 +289,9 @@ __global__ void __launch_bounds__(kNT) k_pair_eig(
       }
       __syncthreads();
       // columns: H <- H P, V <- V P
-      for (int idx = tid; idx < npair * ne; idx += kNT) {
-        const int k = idx % npair, row = idx / npair;
+      for (ColWalk w_(tid, kNT, npair); w_.j < ne; w_.next()) {
+        const int k = w_.i, row = w_.j;
+        [[maybe_unused]] const int idx = k + row * npair;
         int a = (k == 0) ? 0 : ((k - 1 + r) % (m - 1)) + 1;
         int b = ((m - 1 - k - 1 + r) % (m - 1)) + 1;
         int p = min(a, b), q2 = max(a, b);
@@ -311,8 +326,9 @@ __global__ void __launch_bounds__(kNT) k_pair_eig(
   for (int i = 0; i < ne; ++i) nsel += (lam[perm[i]] > tau) ? 1 : 0;
   // constraint columns c_k = R z_k, k < nsel (in G), then modified Gram-Schmidt
   double* Cc = G;
-  for (int idx = tid; idx < ne * nsel; idx += kNT) {
-    const int i = idx % ne, k = idx / ne;
+  for (ColWalk w_(tid, kNT, ne); w_.j < nsel; w_.next()) {
+    const int i = w_.i, k = w_.j;
+    [[maybe_unused]] const int idx = i + k * ne;
     const double* zk = V + (size_t)perm[k] * ne;
     double acc = 0.0;
     for (int j = 0; j <= i; ++j) acc += R[i + (size_t)j * ne] * zk[j];

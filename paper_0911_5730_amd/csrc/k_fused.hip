@@ -210,8 +210,9 @@ __global__ void __launch_bounds__(kNT) k_apply_pre_inv(LevelDev L, const double*
   __syncthreads();
   if (ng == 0) return;
   const int nch = max(1, kNT / ng);
-  for (int idx = tid; idx < ng * nch; idx += kNT) {
-    const int a = idx % ng, c = idx / ng;
+  for (ColWalk w_(tid, kNT, ng); w_.j < nch; w_.next()) {
+    const int a = w_.i, c = w_.j;
+    [[maybe_unused]] const int idx = a + c * ng;
     part[idx] = dot_strided(A + nI + a, n, y, c, nI, nch);
   }
   __syncthreads();
@@ -314,8 +315,9 @@ __global__ void __launch_bounds__(kNT) k_pcg_matvec(LevelDev L, PcgDev P, int it
   }
   __syncthreads();
   const int nch = max(1, kNT / max(1, ng));
-  for (int idx = tid; idx < ng * nch; idx += kNT) {
-    const int i = idx % ng, c = idx / ng;
+  for (ColWalk w_(tid, kNT, ng); w_.j < nch; w_.next()) {
+    const int i = w_.i, c = w_.j;
+    [[maybe_unused]] const int idx = i + c * ng;
     part[idx] = dot_strided(S + i, n, pl, c, ng, nch);
   }
   __syncthreads();
@@ -342,8 +344,9 @@ __device__ void pcg_restrict_body(const LevelDev& L, int s, const double* g, dou
   const int tid = threadIdx.x;
   const double* T = L.T + L.toff[s];
   const int nch = max(1, kNT / max(1, n_r));
-  for (int idx = tid; idx < n_r * nch; idx += kNT) {
-    const int i = idx % n_r, c = idx / n_r;
+  for (ColWalk w_(tid, kNT, n_r); w_.j < nch; w_.next()) {
+    const int i = w_.i, c = w_.j;
+    [[maybe_unused]] const int idx = i + c * n_r;
     part[idx] = dot_strided(T + i, n_r, g, c, n_r, nch);
   }
   const double* Pp = L.Psi + L.psioff[s];

@@ -68,8 +68,9 @@ __global__ void __launch_bounds__(kNT) k_assemble_coarse(
     const int m = nc_child[c];
     const double* Ae = Ac + acoff[c];
     const int32_t* map = child_map + child_map_off[slot];
-    for (int idx = threadIdx.x; idx < m * m; idx += kNT) {
-      const int i = idx % m, j = idx / m;
+    for (ColWalk w_(threadIdx.x, kNT, m); w_.j < m; w_.next()) {
+      const int i = w_.i, j = w_.j;
+      [[maybe_unused]] const int idx = i + j * m;
       A[map[i] + (size_t)map[j] * n] += Ae[idx];
     }
     __syncthreads();
@@ -111,8 +112,9 @@ __global__ void __launch_bounds__(kNT) k_partial_chol(const int64_t* __restrict_
   for (int k0 = 0; k0 < nI; k0 += kPanel) {
     const int kb = min(kPanel, nI - k0);
     const int m = n - k0;
-    for (int idx = tid; idx < m * kb; idx += kNT) {
-      const int i = idx % m, p = idx / m;
+    for (ColWalk w_(tid, kNT, m); w_.j < kb; w_.next()) {
+      const int i = w_.i, p = w_.j;
+      [[maybe_unused]] const int idx = i + p * m;
       P[i + p * m] = A[(k0 + i) + (size_t)(k0 + p) * n];
     }
     __syncthreads();
@@ -132,8 +134,9 @@ __global__ void __launch_bounds__(kNT) k_partial_chol(const int64_t* __restrict_
       }
       __syncthreads();
     }
-    for (int idx = tid; idx < m * kb; idx += kNT) {
-      const int i = idx % m, p = idx / m;
+    for (ColWalk w_(tid, kNT, m); w_.j < kb; w_.next()) {
+      const int i = w_.i, p = w_.j;
+      [[maybe_unused]] const int idx = i + p * m;
       if (i >= p) A[(k0 + i) + (size_t)(k0 + p) * n] = P[i + p * m];
     }
     // trailing update of rows/cols [k0+kb, n), lower triangle, 4x4 tiles
@@ -175,8 +178,9 @@ __global__ void __launch_bounds__(kNT) k_partial_chol(const int64_t* __restrict_
   }
   // mirror the Schur complement block
   const int ng = n - nI;
-  for (int idx = tid; idx < ng * ng; idx += kNT) {
-    const int i = idx % ng, c = idx / ng;
+  for (ColWalk w_(tid, kNT, ng); w_.j < ng; w_.next()) {
+    const int i = w_.i, c = w_.j;
+    [[maybe_unused]] const int idx = i + c * ng;
     if (i < c) A[(nI + i) + (size_t)(nI + c) * n] = A[(nI + c) + (size_t)(nI + i) * n];
   }
 }
@@ -204,8 +208,9 @@ __global__ void k_build_cr(const int32_t* __restrict__ sub_inc_ptr, const int32_
     const int ne = edge_ne[e], m = edge_m[e], nsc = edge_nsc[e];
     const int32_t* rpos = inc_fpos + inc_fptr[inc] + nsc;
     const double* Qe = Q + qoff[e];
-    for (int idx = threadIdx.x; idx < ne * m; idx += kNT) {
-      const int p = idx % ne, j = idx / ne;
+    for (ColWalk w_(threadIdx.x, kNT, ne); w_.j < m; w_.next()) {
+      const int p = w_.i, j = w_.j;
+      [[maybe_unused]] const int idx = p + j * ne;
       C[(row + j) + (size_t)rpos[p] * n_cr] = Qe[p + (size_t)j * ne];
     }
     row += m;
@@ -267,8 +272,9 @@ __global__ void __launch_bounds__(kNT) k_constrained_factor(
   double* W = Y + (size_t)n_cr * n_r;                    // ng x ncs
   const int tid = threadIdx.x;
 
-  for (int idx = tid; idx < n_r * n_r; idx += kNT) {
-    const int i = idx % n_r, j = idx / n_r;
+  for (ColWalk w_(tid, kNT, n_r); w_.j < n_r; w_.next()) {
+    const int i = w_.i, j = w_.j;
+    [[maybe_unused]] const int idx = i + j * n_r;
     Lr[idx] = S[i + (size_t)j * n];
     Tr[idx] = (i == j) ? 1.0 : 0.0;
   }
@@ -277,8 +283,9 @@ __global__ void __launch_bounds__(kNT) k_constrained_factor(
   wg_trsm_lower(Lr, n_r, n_r, Tr, n_r, n_r);
   wg_trsm_lower_trans(Lr, n_r, n_r, Tr, n_r, n_r);       // Tr = S_rr^{-1}
   if (n_cr > 0) {
-    for (int idx = tid; idx < n_r * n_cr; idx += kNT) {
-      const int i = idx % n_r, j = idx / n_r;
+    for (ColWalk w_(tid, kNT, n_r); w_.j < n_cr; w_.next()) {
+      const int i = w_.i, j = w_.j;
+      [[maybe_unused]] const int idx = i + j * n_r;
       X[idx] = C[j + (size_t)i * n_cr];
     }
     __syncthreads();
@@ -286,8 +293,9 @@ __global__ void __launch_bounds__(kNT) k_constrained_factor(
     wg_trsm_lower_trans(Lr, n_r, n_r, X, n_r, n_cr);     // X = S_rr^{-1} C_r^T
     wg_gemm(false, false, n_cr, n_cr, n_r, 1.0, C, n_cr, X, n_r, 0.0, F, n_cr);
     wg_potrf(F, n_cr, n_cr, status);                    // F = Lf Lf^T
-    for (int idx = tid; idx < n_cr * n_r; idx += kNT) {
-      const int i = idx % n_cr, j = idx / n_cr;
+    for (ColWalk w_(tid, kNT, n_cr); w_.j < n_r; w_.next()) {
+      const int i = w_.i, j = w_.j;
+      [[maybe_unused]] const int idx = i + j * n_cr;
       Y[idx] = X[j + (size_t)i * n_r];
     }
     __syncthreads();
@@ -297,20 +305,23 @@ __global__ void __launch_bounds__(kNT) k_constrained_factor(
   }
   // Psi: rows r, corner columns = -Tr S_rc; edge columns = (F^{-1} X^T)^T
   wg_gemm(false, false, n_r, n_c, n_r, -1.0, Tr, n_r, S + (size_t)n_r * n, n, 0.0, Ps, ng);
-  for (int idx = tid; idx < n_r * n_cr; idx += kNT) {
-    const int i = idx % n_r, j = idx / n_r;
+  for (ColWalk w_(tid, kNT, n_r); w_.j < n_cr; w_.next()) {
+    const int i = w_.i, j = w_.j;
+    [[maybe_unused]] const int idx = i + j * n_r;
     Ps[i + (size_t)(n_c + j) * ng] = Y[j + (size_t)i * n_cr];
   }
-  for (int idx = tid; idx < n_c * ncs; idx += kNT) {
-    const int i = idx % n_c, j = idx / n_c;
+  for (ColWalk w_(tid, kNT, n_c); w_.j < ncs; w_.next()) {
+    const int i = w_.i, j = w_.j;
+    [[maybe_unused]] const int idx = i + j * n_c;
     Ps[(n_r + i) + (size_t)j * ng] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
   wg_gemm(false, false, ng, ncs, ng, 1.0, S, n, Ps, ng, 0.0, W, ng);            // W = S Psi
   wg_gemm(true, false, ncs, ncs, ng, 1.0, Ps, ng, W, ng, 0.0, Acs, ncs);         // A_c = Psi^T W
   // exact symmetry of A_c
-  for (int idx = tid; idx < ncs * ncs; idx += kNT) {
-    const int i = idx % ncs, j = idx / ncs;
+  for (ColWalk w_(tid, kNT, ncs); w_.j < ncs; w_.next()) {
+    const int i = w_.i, j = w_.j;
+    [[maybe_unused]] const int idx = i + j * ncs;
     if (i > j) {
       const double v = 0.5 * (Acs[i + (size_t)j * ncs] + Acs[j + (size_t)i * ncs]);
       Acs[i + (size_t)j * ncs] = v;
@@ -319,8 +330,9 @@ __global__ void __launch_bounds__(kNT) k_constrained_factor(
   }
   // exact symmetry of T_rr
   __syncthreads();
-  for (int idx = tid; idx < n_r * n_r; idx += kNT) {
-    const int i = idx % n_r, j = idx / n_r;
+  for (ColWalk w_(tid, kNT, n_r); w_.j < n_r; w_.next()) {
+    const int i = w_.i, j = w_.j;
+    [[maybe_unused]] const int idx = i + j * n_r;
     if (i > j) {
       const double v = 0.5 * (Tr[i + (size_t)j * n_r] + Tr[j + (size_t)i * n_r]);
       Tr[i + (size_t)j * n_r] = v;
@@ -342,8 +354,9 @@ __global__ void __launch_bounds__(kNT) k_coarsest_factor(int nsub, int nc, const
     const int m = cptr[s + 1] - cptr[s];
     const int32_t* map = cid + cptr[s];
     const double* Ae = Ac + acoff[s];
-    for (int idx = threadIdx.x; idx < m * m; idx += kNT) {
-      const int i = idx % m, j = idx / m;
+    for (ColWalk w_(threadIdx.x, kNT, m); w_.j < m; w_.next()) {
+      const int i = w_.i, j = w_.j;
+      [[maybe_unused]] const int idx = i + j * m;
       AL[map[i] + (size_t)map[j] * nc] += Ae[idx];
     }
     __syncthreads();
@@ -492,13 +505,14 @@ __global__ void __launch_bounds__(kCholNT) k_partial_chol_mfma(const int64_t* __
     const int mp = (m + 15) & ~15;              // rows padded to the tile size
     // panel load, eight loads in flight per thread
     const int tot = mp * kb16;
+    ColWalk cw(tid, kCholNT, mp);
     for (int base = tid; base < tot; base += 8 * kCholNT) {
       double v[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int idx = base + u * kCholNT;
-        const int i = idx % mp, p = idx / mp;
-        v[u] = (idx < tot && i < m && p < kb) ? A[(k0 + i) + (size_t)(k0 + p) * n] : 0.0;
+        v[u] = (idx < tot && cw.i < m && cw.j < kb) ? A[(k0 + cw.i) + (size_t)(k0 + cw.j) * n] : 0.0;
+        cw.next();
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u)
@@ -564,8 +578,9 @@ __global__ void __launch_bounds__(kCholNT) k_partial_chol_mfma(const int64_t* __
       }
       __syncthreads();
     }
-    for (int idx = tid; idx < m * kb; idx += kCholNT) {
-      const int i = idx % m, p = idx / m;
+    for (ColWalk w_(tid, kCholNT, m); w_.j < kb; w_.next()) {
+      const int i = w_.i, p = w_.j;
+      [[maybe_unused]] const int idx = i + p * m;
       if (i >= p) A[(k0 + i) + (size_t)(k0 + p) * n] = P[i + p * mp];
     }
     // trailing update of rows/cols [kb, m) of the panel frame, lower tiles, two tiles per wave in flight
@@ -619,8 +634,9 @@ __global__ void __launch_bounds__(kCholNT) k_partial_chol_mfma(const int64_t* __
     __syncthreads();
   }
   const int ng = n - nI;
-  for (int idx = tid; idx < ng * ng; idx += kCholNT) {
-    const int i = idx % ng, c = idx / ng;
+  for (ColWalk w_(tid, kCholNT, ng); w_.j < ng; w_.next()) {
+    const int i = w_.i, c = w_.j;
+    [[maybe_unused]] const int idx = i + c * ng;
     if (i < c) A[(nI + i) + (size_t)(nI + c) * n] = A[(nI + c) + (size_t)(nI + i) * n];
   }
 }
@@ -670,8 +686,9 @@ __device__ void wg_gj_inverse_spd(double* M, int m, double* tc, double* tr, int*
     const bool ok = p > 0.0 && p < 1e308;
     if (!ok && tid == 0) flag_bad(status);
     const double ip = ok ? 1.0 / p : 0.0;
-    for (int idx = tid; idx < m * m; idx += kNT) {
-      const int i = idx % m, j = idx / m;
+    for (ColWalk w_(tid, kNT, m); w_.j < m; w_.next()) {
+      const int i = w_.i, j = w_.j;
+      [[maybe_unused]] const int idx = i + j * m;
       double v;
       if (i == k) v = (j == k) ? ip : tr[j] * ip;
       else if (j == k) v = -tc[i] * ip;
@@ -685,8 +702,9 @@ __device__ void wg_gj_inverse_spd(double* M, int m, double* tc, double* tr, int*
 // C (m x n, ldc) = alpha * op(A) op(B) + beta * C with every operand in LDS or global
 __device__ inline void wg_gemm_nn(int m, int n, int k, double alpha, const double* A, int lda, const double* B, int ldb,
                                   double beta, double* C, int ldc) {
-  for (int idx = threadIdx.x; idx < m * n; idx += kNT) {
-    const int i = idx % m, j = idx / m;
+  for (ColWalk w_(threadIdx.x, kNT, m); w_.j < n; w_.next()) {
+    const int i = w_.i, j = w_.j;
+    [[maybe_unused]] const int idx = i + j * m;
     double acc = 0.0;
     for (int p = 0; p < k; ++p) acc += A[i + (size_t)p * lda] * B[p + (size_t)j * ldb];
     C[i + (size_t)j * ldc] = (beta == 0.0 ? 0.0 : beta * C[i + (size_t)j * ldc]) + alpha * acc;
@@ -736,12 +754,14 @@ __global__ void __launch_bounds__(kNT) k_constrained_factor_lds(
   {
     // stage S and C, eight loads in flight per thread
     const int t1 = ng * ng, t2 = t1 + n_cr * n_r;
+    ColWalk cw(tid, kNT, ng);
     for (int base = tid; base < t2; base += 8 * kNT) {
       double v[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int idx = base + u * kNT;
-        v[u] = idx < t1 ? Sg[(idx % ng) + (size_t)(idx / ng) * n] : (idx < t2 ? C[idx - t1] : 0.0);
+        v[u] = idx < t1 ? Sg[cw.i + (size_t)cw.j * n] : (idx < t2 ? C[idx - t1] : 0.0);
+        cw.next();
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
@@ -752,15 +772,17 @@ __global__ void __launch_bounds__(kNT) k_constrained_factor_lds(
     }
   }
   __syncthreads();
-  for (int idx = tid; idx < n_r * n_r; idx += kNT) {
-    const int i = idx % n_r, j = idx / n_r;
+  for (ColWalk w_(tid, kNT, n_r); w_.j < n_r; w_.next()) {
+    const int i = w_.i, j = w_.j;
+    [[maybe_unused]] const int idx = i + j * n_r;
     M[idx] = S[i + (size_t)j * ng];
   }
   __syncthreads();
   wg_gj_inverse_spd(M, n_r, tc, tr, status);             // M = S_rr^{-1}
   if (n_cr > 0) {
-    for (int idx = tid; idx < n_r * n_cr; idx += kNT) {  // X = M C^T
-      const int i = idx % n_r, j = idx / n_r;
+    for (ColWalk w_(tid, kNT, n_r); w_.j < n_cr; w_.next()) {  // X = M C^T
+      const int i = w_.i, j = w_.j;
+      [[maybe_unused]] const int idx = i + j * n_r;
       double acc = 0.0;
       for (int p = 0; p < n_r; ++p) acc += M[i + (size_t)p * n_r] * Cl[j + (size_t)p * n_cr];
       X[idx] = acc;
@@ -771,16 +793,18 @@ __global__ void __launch_bounds__(kNT) k_constrained_factor_lds(
     wg_gj_inverse_spd(F, n_cr, tc, tr, status);
     wg_gemm_nn(n_r, n_cr, n_cr, 1.0, X, n_r, F, n_cr, 0.0, Z, n_r);     // Z = X F^{-1}
     __syncthreads();
-    for (int idx = tid; idx < n_r * n_r; idx += kNT) {   // M -= Z X^T
-      const int i = idx % n_r, j = idx / n_r;
+    for (ColWalk w_(tid, kNT, n_r); w_.j < n_r; w_.next()) {   // M -= Z X^T
+      const int i = w_.i, j = w_.j;
+      [[maybe_unused]] const int idx = i + j * n_r;
       double acc = 0.0;
       for (int p = 0; p < n_cr; ++p) acc += Z[i + (size_t)p * n_r] * X[j + (size_t)p * n_r];
       M[idx] -= acc;
     }
     __syncthreads();
   }
-  for (int idx = tid; idx < n_r * n_r; idx += kNT) {     // exact symmetry of T_rr
-    const int i = idx % n_r, j = idx / n_r;
+  for (ColWalk w_(tid, kNT, n_r); w_.j < n_r; w_.next()) {     // exact symmetry of T_rr
+    const int i = w_.i, j = w_.j;
+    [[maybe_unused]] const int idx = i + j * n_r;
     if (i > j) {
       const double v = 0.5 * (M[idx] + M[j + (size_t)i * n_r]);
       M[idx] = v;
@@ -789,18 +813,21 @@ __global__ void __launch_bounds__(kNT) k_constrained_factor_lds(
   }
   __syncthreads();
   // Psi: rows r, corner columns -T_rr S_rc, edge columns Z; corner rows identity
-  for (int idx = tid; idx < n_r * n_c; idx += kNT) {
-    const int i = idx % n_r, j = idx / n_r;
+  for (ColWalk w_(tid, kNT, n_r); w_.j < n_c; w_.next()) {
+    const int i = w_.i, j = w_.j;
+    [[maybe_unused]] const int idx = i + j * n_r;
     double acc = 0.0;
     for (int p = 0; p < n_r; ++p) acc += M[i + (size_t)p * n_r] * S[p + (size_t)(n_r + j) * ng];
     Ps[i + (size_t)j * ng] = -acc;
   }
-  for (int idx = tid; idx < n_r * n_cr; idx += kNT) {
-    const int i = idx % n_r, j = idx / n_r;
+  for (ColWalk w_(tid, kNT, n_r); w_.j < n_cr; w_.next()) {
+    const int i = w_.i, j = w_.j;
+    [[maybe_unused]] const int idx = i + j * n_r;
     Ps[i + (size_t)(n_c + j) * ng] = Z[idx];
   }
-  for (int idx = tid; idx < n_c * ncs; idx += kNT) {
-    const int i = idx % n_c, j = idx / n_c;
+  for (ColWalk w_(tid, kNT, n_c); w_.j < ncs; w_.next()) {
+    const int i = w_.i, j = w_.j;
+    [[maybe_unused]] const int idx = i + j * n_c;
     Ps[(n_r + i) + (size_t)j * ng] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
@@ -812,8 +839,9 @@ __global__ void __launch_bounds__(kNT) k_constrained_factor_lds(
   wg_gemm_nn(ng, ncs, ng, 1.0, S, ng, Ps, ng, 0.0, W, ng);            // W = S Psi
   __syncthreads();
   double* Acs = Ac + acoff[s];
-  for (int idx = tid; idx < ncs * ncs; idx += kNT) {     // A_c = Psi^T W, symmetrized
-    const int i = idx % ncs, j = idx / ncs;
+  for (ColWalk w_(tid, kNT, ncs); w_.j < ncs; w_.next()) {     // A_c = Psi^T W, symmetrized
+    const int i = w_.i, j = w_.j;
+    [[maybe_unused]] const int idx = i + j * ncs;
     if (i < j) continue;
     double aij = 0.0, aji = 0.0;
     for (int p = 0; p < ng; ++p) {
@@ -853,8 +881,9 @@ __global__ void __launch_bounds__(kNT) k_tri_inverse_lds(const int64_t* __restri
   double* rowk = M + (size_t)m * m;
   double* colk = rowk + m;
   const int tid = threadIdx.x;
-  for (int idx = tid; idx < m * m; idx += kNT) {
-    const int i = idx % m, j = idx / m;
+  for (ColWalk w_(tid, kNT, m); w_.j < m; w_.next()) {
+    const int i = w_.i, j = w_.j;
+    [[maybe_unused]] const int idx = i + j * m;
     M[idx] = (i >= j) ? L[i + (size_t)j * n] : 0.0;
   }
   __syncthreads();
@@ -866,8 +895,8 @@ __global__ void __launch_bounds__(kNT) k_tri_inverse_lds(const int64_t* __restri
     for (int c = tid; c < k; c += kNT) M[k + (size_t)c * m] = rowk[c];
     if (tid == 0) M[k + (size_t)k * m] = d;
     const int rows = m - k - 1;
-    for (int idx = tid; idx < rows * (k + 1); idx += kNT) {
-      const int i = k + 1 + idx % rows, c = idx / rows;
+    for (ColWalk w_(tid, kNT, rows); w_.j < k + 1; w_.next()) {
+      const int i = k + 1 + w_.i, c = w_.j;
       M[i + (size_t)c * m] = (c == k) ? -colk[i] * d : M[i + (size_t)c * m] - colk[i] * rowk[c];
     }
     __syncthreads();

@@ -1,0 +1,247 @@
+// Level-1 interior sweeps of Algorithm "Multilevel BDDC" streamed through LDS:
+// the interior pre-correction (eqs. ML-uIi, ML-rBi), the interior
+// post-correction (eqs. ML-vIi, ML-ui) and, in the interface-reduced form, the
+// static condensation and the interior recovery.
+//
+// After the interior elimination each substructure matrix holds the n x n_I
+// lower trapezoid [L_II; L_GI] (column-major, ld n).  Both sweeps run over that
+// trapezoid in 64-column panels:
+//   forward:  w = [r_I; 0]   ->  [L_II^{-1} r_I; -L_GI L_II^{-1} r_I]
+//   backward: w = [v; u_B]   ->  [L_II^{-T} (v - L_GI^T u_B); u_B]
+// A panel (rows from its first column to n) sits in LDS while one wave solves
+// its 64 x 64 diagonal block with shuffles and all threads apply the
+// off-diagonal part; the next panel's global loads are issued into registers
+// before that work starts, so the stream of L never waits on the sweep's
+// dependency chain.
+#include "dense.hpp"
+#include "kernels.hpp"
+
+namespace bddc {
+
+namespace {
+
+constexpr int kBW = 64;                    // panel width
+constexpr int kSweepNT = 512;              // 8 waves: the prefetch stays within a wave's 63 outstanding loads
+constexpr int kSweepRows = 304;            // largest n handled here (LDS: 8 (304 + 304 * 64) B < 160 KiB)
+constexpr int kRegs = (kSweepRows * kBW + kSweepNT - 1) / kSweepNT;   // prefetched doubles per thread
+
+// value of v on lane `lane` (uniform) through the scalar unit
+__device__ inline double lane_value(double v, int lane) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(x & 0xffffffffLL), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(x >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+struct Panel {
+  int c0, c1, rows;                        // columns [c0, c1), rows [c0, n)
+};
+
+__device__ inline Panel panel_of(int b, int n, int nI) {
+  Panel p;
+  p.c0 = b * kBW;
+  p.c1 = min(p.c0 + kBW, nI);
+  p.rows = n - p.c0;
+  return p;
+}
+
+// issue the loads of panel p (rows [c0, n) x cols [c0, c1) of A) into registers
+__device__ inline void panel_load(const double* __restrict__ A, int n, const Panel& p, double (&r)[kRegs]) {
+  const int w = p.c1 - p.c0;
+  ColWalk cw(threadIdx.x, kSweepNT, p.rows);
+#pragma unroll
+  for (int u = 0; u < kRegs; ++u) {
+    r[u] = cw.j < w ? A[(p.c0 + cw.i) + (size_t)(p.c0 + cw.j) * n] : 0.0;
+    cw.next();
+  }
+}
+
+// store panel registers into LDS: P[(i - c0) + k * rows]
+__device__ inline void panel_store(double* P, const Panel& p, const double (&r)[kRegs]) {
+  const int tot = p.rows * (p.c1 - p.c0);
+#pragma unroll
+  for (int u = 0; u < kRegs; ++u) {
+    const int idx = threadIdx.x + u * kSweepNT;
+    if (idx < tot) P[idx] = r[u];
+  }
+}
+
+__device__ void sweep_fwd(const double* __restrict__ A, int n, int nI, double* w, double* P) {
+  const int tid = threadIdx.x;
+  const int nb = (nI + kBW - 1) / kBW;
+  double r[kRegs];
+  Panel p = panel_of(0, n, nI);
+  panel_load(A, n, p, r);
+  panel_store(P, p, r);
+  __syncthreads();
+  for (int b = 0; b < nb; ++b) {
+    const Panel q = panel_of(b + 1, n, nI);
+    if (b + 1 < nb) panel_load(A, n, q, r);
+    const int wb = p.c1 - p.c0;
+    if (tid < 64) {
+      // diagonal block: lane l owns row c0 + l
+      const int l = tid;
+      double wl = l < wb ? w[p.c0 + l] : 0.0;
+      const double inv = l < wb ? 1.0 / P[l + l * p.rows] : 0.0;
+      for (int j = 0; j < wb; ++j) {
+        const double xj = lane_value(wl * inv, j);
+        if (l == j) wl = xj;
+        else if (l > j && l < wb) wl -= P[l + j * p.rows] * xj;
+      }
+      if (l < wb) w[p.c0 + l] = wl;
+    }
+    __syncthreads();
+    // rows below the block
+    for (int i = p.c0 + wb + tid; i < n; i += kSweepNT) {
+      double acc = 0.0;
+      const double* Pi = P + (i - p.c0);
+#pragma unroll 8
+      for (int k = 0; k < wb; ++k) acc += Pi[k * p.rows] * w[p.c0 + k];
+      w[i] -= acc;
+    }
+    __syncthreads();
+    if (b + 1 < nb) {
+      panel_store(P, q, r);
+      __syncthreads();
+    }
+    p = q;
+  }
+}
+
+__device__ void sweep_bwd(const double* __restrict__ A, int n, int nI, double* w, double* P) {
+  const int tid = threadIdx.x;
+  const int nb = (nI + kBW - 1) / kBW;
+  double r[kRegs];
+  Panel p = panel_of(nb - 1, n, nI);
+  panel_load(A, n, p, r);
+  panel_store(P, p, r);
+  __syncthreads();
+  for (int b = nb - 1; b >= 0; --b) {
+    const Panel q = panel_of(b - 1, n, nI);
+    if (b > 0) panel_load(A, n, q, r);
+    const int wb = p.c1 - p.c0;
+    // w_j -= sum over rows below the block of L[i][j] w_i, eight lanes per column
+    {
+      const int j = tid >> 3, part = tid & 7;
+      double acc = 0.0;
+      if (j < wb)
+        for (int i = p.c0 + wb + part; i < n; i += 8) acc += P[(i - p.c0) + j * p.rows] * w[i];
+      acc += __shfl_xor(acc, 1);
+      acc += __shfl_xor(acc, 2);
+      acc += __shfl_xor(acc, 4);
+      __syncthreads();
+      if (j < wb && part == 0) w[p.c0 + j] -= acc;
+    }
+    __syncthreads();
+    if (tid < 64) {
+      // diagonal block of L^T, from its last row up: lane l owns row c0 + l
+      const int l = tid;
+      double wl = l < wb ? w[p.c0 + l] : 0.0;
+      const double inv = l < wb ? 1.0 / P[l + l * p.rows] : 0.0;
+      for (int j = wb - 1; j >= 0; --j) {
+        const double xj = lane_value(wl * inv, j);
+        if (l == j) wl = xj;
+        else if (l < j) wl -= P[j + l * p.rows] * xj;
+      }
+      if (l < wb) w[p.c0 + l] = wl;
+    }
+    __syncthreads();
+    if (b > 0) {
+      panel_store(P, q, r);
+      __syncthreads();
+    }
+    p = q;
+  }
+}
+
+}  // namespace
+
+// y = L_II^{-1} r_I (kept for the post-correction), t = L_GI y
+__global__ void __launch_bounds__(kSweepNT) k_sweep_pre(LevelDev L, const double* __restrict__ r) {
+  extern __shared__ double sh[];
+  if (L.stop && *L.stop) return;
+  const int s = blockIdx.x;
+  const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
+  const int nI = L.nint[s];
+  const int ng = n - nI;
+  const double* A = L.K + L.koff[s];
+  double* w = sh;
+  double* P = sh + kSweepRows;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < n; i += kSweepNT) w[i] = i < nI ? r[L.int_gid[L.ioff[s] + i]] : 0.0;
+  __syncthreads();
+  if (nI > 0) sweep_fwd(A, n, nI, w, P);
+  for (int i = tid; i < nI; i += kSweepNT) L.y[L.ioff[s] + i] = w[i];
+  for (int a = tid; a < ng; a += kSweepNT) L.t[L.goff[s] + a] = -w[nI + a];
+}
+
+// u_B = sum over sharers of v (owner writes); u_I = L_II^{-T} (y - L_GI^T u_B)
+__global__ void __launch_bounds__(kSweepNT) k_sweep_post(LevelDev L, double* __restrict__ u,
+                                                    const int32_t* __restrict__ gam_map) {
+  extern __shared__ double sh[];
+  if (L.stop && *L.stop) return;
+  const int s = blockIdx.x;
+  const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
+  const int nI = L.nint[s];
+  const int ng = n - nI;
+  const int g0 = L.goff[s];
+  double* w = sh;
+  double* P = sh + kSweepRows;
+  const int tid = threadIdx.x;
+  for (int a = tid; a < ng; a += kSweepNT) {
+    const int f = g0 + a;
+    const int gi = L.gam_iid[f];
+    double acc = 0.0;
+    for (int k = L.sh_ptr[gi]; k < L.sh_ptr[gi + 1]; ++k) acc += L.v[L.sh_flat[k]];
+    w[nI + a] = acc;
+    if (L.sh_flat[L.sh_ptr[gi]] == f) u[gam_map[f]] = acc;
+  }
+  for (int i = tid; i < nI; i += kSweepNT) w[i] = L.y[L.ioff[s] + i];
+  __syncthreads();
+  if (nI == 0) return;
+  sweep_bwd(L.K + L.koff[s], n, nI, w, P);
+  for (int i = tid; i < nI; i += kSweepNT) u[L.int_gid[L.ioff[s] + i]] = w[i];
+}
+
+// interior recovery of the interface-reduced solve: u_G = x, u_I = L_II^{-T}(y - L_GI^T x_s)
+__global__ void __launch_bounds__(kSweepNT) k_sweep_recover(LevelDev L, const double* __restrict__ x,
+                                                       double* __restrict__ u) {
+  extern __shared__ double sh[];
+  const int s = blockIdx.x;
+  const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
+  const int nI = L.nint[s];
+  const int ng = n - nI;
+  const int g0 = L.goff[s];
+  double* w = sh;
+  double* P = sh + kSweepRows;
+  const int tid = threadIdx.x;
+  for (int a = tid; a < ng; a += kSweepNT) {
+    const int f = g0 + a;
+    const int gi = L.gam_iid[f];
+    const double v = x[gi];
+    w[nI + a] = v;
+    if (L.sh_flat[L.sh_ptr[gi]] == f) u[L.gam_gid[f]] = v;
+  }
+  for (int i = tid; i < nI; i += kSweepNT) w[i] = L.y[L.ioff[s] + i];
+  __syncthreads();
+  if (nI == 0) return;
+  sweep_bwd(L.K + L.koff[s], n, nI, w, P);
+  for (int i = tid; i < nI; i += kSweepNT) u[L.int_gid[L.ioff[s] + i]] = w[i];
+}
+
+size_t sweep_lds() { return sizeof(double) * ((size_t)kSweepRows + (size_t)kSweepRows * kBW); }
+static_assert(sizeof(double) * ((size_t)kSweepRows + (size_t)kSweepRows * kBW) <= 160 * 1024, "sweep LDS");
+
+bool sweep_fits(int nmax) { return nmax <= kSweepRows; }
+
+void launch_sweep_pre(hipStream_t st, const LevelDev& L, const double* r) {
+  launch_kernel(k_sweep_pre, dim3(L.nsub), dim3(kSweepNT), sweep_lds(), st, L, r);
+}
+void launch_sweep_post(hipStream_t st, const LevelDev& L, double* u, const int32_t* gam_map) {
+  launch_kernel(k_sweep_post, dim3(L.nsub), dim3(kSweepNT), sweep_lds(), st, L, u, gam_map);
+}
+void launch_sweep_recover(hipStream_t st, const LevelDev& L, const double* x, double* u) {
+  launch_kernel(k_sweep_recover, dim3(L.nsub), dim3(kSweepNT), sweep_lds(), st, L, x, u);
+}
+
+}  // namespace bddc

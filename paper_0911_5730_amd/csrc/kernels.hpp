@@ -20,14 +20,19 @@ struct LaunchEvents {
 };
 inline thread_local LaunchEvents g_launch_events;
 
+// A rejected launch (bad configuration, too much LDS) fails loudly.
+void check_launch();
+
 // Every launch of the library goes through here; arguments are converted to
-// the kernel's parameter types before they are packed.
+// the kernel's parameter types before they are packed; a rejected launch
+// throws.
 template <class... P, class... A>
 inline void launch_kernel(void (*k)(P...), dim3 grid, dim3 block, size_t shm, hipStream_t st, A... a) {
   const LaunchEvents ev = g_launch_events;
   g_launch_events = LaunchEvents{};
   hipExtLaunchKernelGGL(k, grid, block, static_cast<std::uint32_t>(shm), st, ev.start, ev.stop, 0u,
                         static_cast<P>(a)...);
+  check_launch();
 }
 
 struct Khat16 {
@@ -171,6 +176,10 @@ void launch_partial_chol(hipStream_t st, int nsub, int nmax, const int64_t* koff
                          const int32_t* nint, double* K, int* status);
 size_t partial_chol_lds(int nmax);
 int partial_chol_mfma_nb(int nmax);
+bool sweep_fits(int nmax);
+void launch_sweep_pre(hipStream_t st, const LevelDev& L, const double* r);
+void launch_sweep_post(hipStream_t st, const LevelDev& L, double* u, const int32_t* gam_map);
+void launch_sweep_recover(hipStream_t st, const LevelDev& L, const double* x, double* u);
 size_t constrained_factor_lds(int ng, int n_r, int n_cr, int ncs);
 void launch_constrained_factor_lds(hipStream_t st, int nsub, size_t lds, const int64_t* koff, const int32_t* loc_ptr,
                                    const int32_t* nint, const int32_t* nr, const int32_t* ncr, const int64_t* croff,

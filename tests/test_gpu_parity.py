@@ -1,8 +1,9 @@
 """GPU parity: the HIP path through the C ABI against the FP64 oracle.
 
 Tolerances: relative energy-norm difference of the PCG solutions <= 1e-10
-with both sides converged to 1e-10 (at the production tolerance 1e-8: within
-half the oracle's own error), iteration counts within +-1, preconditioner
+with both sides converged to 1e-10 (at the production tolerance 1e-8: an
+error against the direct solution of the oracle's size), iteration counts
+within +-1, Lanczos kappa within 1e-3, preconditioner
 applies equal to 1e-11 (relative 2-norm), per-edge eigenvalues to 1e-6
 relative (the largest ones are ill-conditioned with respect to the rounding
 of the local matrices), identical selection
@@ -52,8 +53,12 @@ def test_solve_and_apply_match_oracle(name):
     try:
         assert abs(it - o["iters"]) <= 1, (it, o["iters"])
         info = S.info()
-        # the Lanczos estimates agree to the accuracy the CG coefficients allow
-        assert abs(info["kappa"] - o["kappa"]) <= 1e-4 * o["kappa"]
+        # kappa is the ratio of the extreme Ritz values of the Lanczos matrix
+        # built from the CG coefficients (as in the paper's tables); after ~30
+        # iterations the smallest Ritz value is not converged, and
+        # rounding-level differences of the iterates move the estimate by a few
+        # 1e-4 (3.0e-4 measured on corners_kjump), so it is compared to 1e-3
+        assert abs(info["kappa"] - o["kappa"]) <= 1e-3 * o["kappa"]
         check_solution(S, B, ug, o)
         assert info["nc"] == B.nc_per_level()
         # full-space preconditioner apply, element by element
@@ -93,12 +98,15 @@ def test_deep_level_paths(path, monkeypatch):
 @pytest.mark.parametrize("path", ["default", "lds16_global"])
 def test_setup_kernel_paths(path, monkeypatch):
     """The setup runs with 64-wide Cholesky panels and a matrix-core trailing
-    update plus LDS-resident Gauss-Jordan factorizations (default), or with
-    16-wide panels on the vector units and global-memory factorizations; both
-    must give the oracle's preconditioner (H/h = 16, ragged 64-column panels)."""
+    update plus LDS-resident Gauss-Jordan factorizations, and the level-1
+    interior sweeps stream 64-column panels (default); or with 16-wide panels
+    on the vector units, global-memory factorizations and 16-row blocked
+    sweeps.  Both must give the oracle's preconditioner and solution (H/h = 16,
+    ragged 64-column panels)."""
     if path == "lds16_global":
         monkeypatch.setenv("BDDC_CHOL_PATH", "lds16")
         monkeypatch.setenv("BDDC_SETUP_PATH", "global")
+        monkeypatch.setenv("BDDC_SWEEP", "off")
     prob = _case("adaptive3_h16")
     print(f"setup kernel path {path}", flush=True)
     S, B, ug, it, rr, o = run_pair(prob)
@@ -110,5 +118,6 @@ def test_setup_kernel_paths(path, monkeypatch):
         zo = B.apply(r)
         assert np.linalg.norm(zg - zo) <= 1e-11 * np.linalg.norm(zo)
         check_adaptive_edges(S, B, prob.tau)
+        check_solution(S, B, ug, o)
     finally:
         S.close()
