@@ -1526,7 +1526,7 @@ static int pcg_one(bddc_ctx* h, const double* f, double* u, double rtol, int max
     timing::current_tag = it - 1;
     {
       timing::Scope ts("apply_restrict", it > 0 ? l1.by_update_restrict : l1.by_restrict_ir, 0);
-      launch_pcg_update_restrict(st, l1.dev, l1.ngmax, P, it);
+      launch_pcg_update_restrict(st, l1.dev, l1.ngmax, l1.nrmax, l1.ncsmax, P, it);
     }
     run_deep(h);
     timing::current_tag = it;

@@ -144,15 +144,17 @@ __device__ inline double dot_strided(const double* __restrict__ A, size_t lda, c
 }
 
 // Sum of one value per thread, returned to every thread (red: kNT doubles of LDS).
+// Sum over the workgroup, identical on every thread: butterfly shuffles inside
+// each wave, then the wave sums in wave order (fixed, so bitwise reproducible).
+// red needs one double per wave.
 __device__ inline double wg_sum(double v, double* red) {
-  const int tid = threadIdx.x;
-  red[tid] = v;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int nw = blockDim.x >> 6;
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int w = kNT / 2; w > 0; w >>= 1) {
-    if (tid < w) red[tid] += red[tid + w];
-    __syncthreads();
-  }
-  const double r = red[0];
+  double r = 0.0;
+  for (int w = 0; w < nw; ++w) r += red[w];
   __syncthreads();
   return r;
 }

@@ -332,24 +332,54 @@ __global__ void __launch_bounds__(kNT) k_pcg_matvec(LevelDev L, PcgDev P, int it
   if (tid == 0) P.pq_part[s] = e;
 }
 
+// Copy n doubles from global src to LDS dst: the first kPre per thread are
+// loaded into registers by fetch() (issued early, before other work), the
+// rest by finish(), which also stores everything.
+template <int kPre>
+struct Prefetch {
+  double v[kPre];
+  const double* src;
+  double* dst;
+  int n;
+  __device__ void fetch(const double* s, double* d, int count) {
+    src = s;
+    dst = d;
+    n = count;
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) {
+      const int i = threadIdx.x + u * kNT;
+      v[u] = i < n ? src[i] : 0.0;
+    }
+  }
+  __device__ void finish() {
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) {
+      const int i = threadIdx.x + u * kNT;
+      if (i < n) dst[i] = v[u];
+    }
+    for (int i = threadIdx.x + kPre * kNT; i < n; i += kNT) dst[i] = src[i];
+  }
+};
+
 // The level-1 restriction of the interface residual r: g = delta r_G,
 // b = Psi^T g (ML-coarse) and da = delta T_rr g_r (ML-wDi, weighted for the
-// average); g is already in LDS.
-__device__ void pcg_restrict_body(const LevelDev& L, int s, const double* g, double* part, double* da) {
+// average); g, T_rr (Tl) and Psi (Pl) are already in LDS.
+__device__ void pcg_restrict_body(const LevelDev& L, int s, const double* g, double* part, double* da,
+                                  const double* T, const double* Pp) {
   const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
   const int ng = n - L.nint[s];
   const int n_r = L.nr[s];
   const int ncs = L.coff[s + 1] - L.coff[s];
   const int g0 = L.goff[s];
   const int tid = threadIdx.x;
-  const double* T = L.T + L.toff[s];
   const int nch = max(1, kNT / max(1, n_r));
   for (ColWalk w_(tid, kNT, n_r); w_.j < nch; w_.next()) {
     const int i = w_.i, c = w_.j;
     [[maybe_unused]] const int idx = i + c * n_r;
-    part[idx] = dot_strided(T + i, n_r, g, c, n_r, nch);
+    double acc = 0.0;
+    for (int k = c; k < n_r; k += nch) acc += T[i + k * n_r] * g[k];
+    part[idx] = acc;
   }
-  const double* Pp = L.Psi + L.psioff[s];
   const int wave = tid >> 6, lane = tid & 63;
   for (int k = wave; k < ncs; k += kNT / 64) {
     double acc = 0.0;
@@ -370,7 +400,7 @@ __device__ void pcg_restrict_body(const LevelDev& L, int s, const double* g, dou
 // it >= 1: alpha, the residual update (r_k into r[it & 1]) and x update by the
 // owners, the partial r.r; then the restriction of r_k.  it == 0: the
 // restriction of r_0 only.
-__global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev P, int it) {
+__global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev P, int it, int nrmax, int ngmax) {
   extern __shared__ double sh[];
   __shared__ double red[kNT];
   if (P.sc->done) return;
@@ -379,8 +409,17 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
   const int ng = n - L.nint[s];
   const int g0 = L.goff[s];
   const int tid = threadIdx.x;
+  const int n_r = L.nr[s];
+  const int ncs = L.coff[s + 1] - L.coff[s];
   double* g = sh;
-  double* part = sh + ng;
+  double* part = sh + ngmax;
+  double* Tl = part + kNT + ngmax;
+  double* Pl = Tl + (size_t)nrmax * nrmax;
+  // the operators' loads go out first and land while the scalars are formed
+  Prefetch<16> pt;
+  Prefetch<4> pp;
+  pt.fetch(L.T + L.toff[s], Tl, n_r * n_r);
+  pp.fetch(L.Psi + L.psioff[s], Pl, ng * ncs);
   if (it == 0) {
     for (int a = tid; a < ng; a += kNT) g[a] = L.delta[g0 + a] * P.r[0][L.gam_iid[g0 + a]];
   } else {
@@ -411,8 +450,10 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
       P.sc->alphas[min(it - 1, kMaxHist - 1)] = alpha;
     }
   }
+  pt.finish();
+  pp.finish();
   __syncthreads();
-  pcg_restrict_body(L, s, g, part, P.da);
+  pcg_restrict_body(L, s, g, part, P.da, Tl, Pl);
 }
 
 // Convergence test on r.r (every block takes the same decision; block 0
@@ -481,9 +522,10 @@ void launch_pcg_matvec(hipStream_t st, const LevelDev& L, int ngmax, const PcgDe
   const size_t lds = sizeof(double) * ((size_t)ngmax + kNT + ngmax);
   launch_kernel(k_pcg_matvec, dim3(L.nsub), dim3(kNT), lds, st, L, P, it);
 }
-void launch_pcg_update_restrict(hipStream_t st, const LevelDev& L, int ngmax, const PcgDev& P, int it) {
-  const size_t lds = sizeof(double) * ((size_t)ngmax + kNT + ngmax);
-  launch_kernel(k_pcg_update_restrict, dim3(L.nsub), dim3(kNT), lds, st, L, P, it);
+void launch_pcg_update_restrict(hipStream_t st, const LevelDev& L, int ngmax, int nrmax, int ncsmax, const PcgDev& P,
+                                int it) {
+  const size_t lds = sizeof(double) * ((size_t)ngmax + kNT + ngmax + (size_t)nrmax * nrmax + (size_t)ngmax * ncsmax);
+  launch_kernel(k_pcg_update_restrict, dim3(L.nsub), dim3(kNT), lds, st, L, P, it, nrmax, ngmax);
 }
 void launch_pcg_prolong_post(hipStream_t st, const LevelDev& L, const PcgDev& P, const double* uc, int check,
                             int parity) {

@@ -256,7 +256,8 @@ void launch_apply_post_inv(hipStream_t st, const LevelDev& L, int nImax, int ngm
 
 // fused PCG iteration kernels (level-1 interface)
 void launch_pcg_matvec(hipStream_t st, const LevelDev& L, int ngmax, const PcgDev& P, int it);
-void launch_pcg_update_restrict(hipStream_t st, const LevelDev& L, int ngmax, const PcgDev& P, int it);
+void launch_pcg_update_restrict(hipStream_t st, const LevelDev& L, int ngmax, int nrmax, int ncsmax, const PcgDev& P,
+                                int it);
 void launch_pcg_prolong_post(hipStream_t st, const LevelDev& L, const PcgDev& P, const double* uc, int check,
                             int parity);
 void launch_build_phi(hipStream_t st, const LevelDev& L, int nif, const int32_t* sub_of_flat, const int32_t* phi_ptr,
