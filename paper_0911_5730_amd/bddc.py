@@ -134,7 +134,7 @@ class _Marshalled:
             agglom=ctypes.cast(self.agg_ptrs, ctypes.POINTER(ctypes.POINTER(ctypes.c_int32)))
             if self.agg else None,
             constraints=CONSTRAINTS[kind], tau=float(t) if math.isfinite(t) else float("inf"),
-            precision=PRECISION[precision])
+            precision=PRECISION[precision] if isinstance(precision, str) else int(precision))
         if coeff_device is not None:
             self.c.coeff_device = ctypes.c_void_p(coeff_device)
 

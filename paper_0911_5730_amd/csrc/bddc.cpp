@@ -431,10 +431,8 @@ static void validate(const bddc_problem* p) {
   if (p->levels < 2 || p->levels > BDDC_MAX_LEVELS) fail(BDDC_EINVAL, "levels must be in [2, 8]");
   if (p->constraints < 0 || p->constraints > 2) fail(BDDC_EINVAL, "unknown constraint kind");
   if (std::isnan(p->tau) || p->tau < 0) fail(BDDC_EINVAL, "tau must be >= 0");
-  if (p->precision != BDDC_FP64) {
-    if (p->precision == BDDC_FP32 || p->precision == BDDC_BF16) fail(BDDC_EUNSUPPORTED, "only FP64 is implemented");
+  if (p->precision != BDDC_FP64 && p->precision != BDDC_FP32 && p->precision != BDDC_BF16)
     fail(BDDC_EINVAL, "unknown precision");
-  }
   const int64_t ne = (int64_t)p->nx * p->ny;
   for (int64_t e = 0; e < ne; ++e) {
     if (!p->coeff_device) {
@@ -1528,12 +1526,14 @@ static int pcg_one(bddc_ctx* h, const double* f, double* u, double rtol, int max
       timing::Scope ts("apply_restrict", it > 0 ? l1.by_update_restrict : l1.by_restrict_ir, 0);
       launch_pcg_update_restrict(st, l1.dev, l1.ngmax, l1.nrmax, l1.ncsmax, P, it);
     }
+    if (P.fin && it > 0) launch_pcg_sum(st, P, P.rr_part, P.nsub1, &P.sc->rrs);
     run_deep(h);
     timing::current_tag = it;
     {
       timing::Scope ts("apply_average", h->by_average, 0);
       launch_pcg_prolong_post(st, l1.dev, P, l1.d.uc, it > 0 ? 1 : 0, it & 1);
     }
+    if (P.fin) launch_pcg_sum(st, P, P.rz_part[it & 1], P.nblk, &P.sc->rzs[it & 1]);
   };
   // z_0 = M r_0 and its r.z partials (parity 0)
   apply_iface(0);
@@ -1548,6 +1548,7 @@ static int pcg_one(bddc_ctx* h, const double* f, double* u, double rtol, int max
         timing::Scope ts("schur_local", l1.by_schur, 0, -1);
         launch_pcg_matvec(st, l1.dev, l1.ngmax, P, it);
       }
+      if (P.fin) launch_pcg_sum(st, P, P.pq_part, P.nsub1, &P.sc->pqs);
       apply_iface(it);
     }
     BDDC_HIP(hipMemcpyAsync(sch, h->sc, offsetof(PcgScalars, alphas), hipMemcpyDeviceToHost, st));
@@ -1758,6 +1759,16 @@ bddc_status bddc_setup(const bddc_problem* p, void* hip_stream, bddc_handle* out
       P.phi_ids = B.take<int32_t>(nphi);
       P.phi_w = B.take<double>(nphi);
       sub_flat_d = B.take<int32_t>(sub_of_flat.size());
+      if (h->precision != BDDC_FP64) {
+        P.Psi32 = B.take<float>((size_t)l1.psioff.back());
+        if (h->precision == BDDC_FP32) {
+          P.T32 = B.take<float>((size_t)l1.toff.back());
+        } else {
+          P.W16 = B.take<uint16_t>((size_t)l1.toff.back());
+          P.Q32 = B.take<float>(std::max<size_t>(1, (size_t)l1.croff.back()));
+          P.Dinv = B.take<float>(l1.nflat_g);
+        }
+      }
     };
     B.reset_sizing();
     lay();
@@ -1773,12 +1784,25 @@ bddc_status bddc_setup(const bddc_problem* p, void* hip_stream, bddc_handle* out
     P.nblk = nblk_avg;
     P.nif = nif;
     {
+      // sum the PCG partials once, in a one-block launch, when the consuming
+      // blocks would each re-read more than a thousand of them
+      // (BDDC_PCG_FINALIZE=0/1 forces either form)
+      const char* env = getenv("BDDC_PCG_FINALIZE");
+      P.fin = env ? (std::string(env) == "1" ? 1 : 0) : (std::max(nblk_avg, l1.nsub) > 1024 ? 1 : 0);
+    }
+    {
       Staging stg(h->stream, &h->staged);
       stg.add(const_cast<int32_t*>(P.phi_ptr), phi_ptr);
       stg.add(sub_flat_d, sub_of_flat);
       stg.flush();
+      P.prec = h->precision == BDDC_FP32 ? 1 : (h->precision == BDDC_BF16 ? 2 : 0);
+      P.ncr = l1.d.ncr;
+      P.croff = l1.d.croff;
+      int ncrmax = 0;
+      for (int v : l1.ncr) ncrmax = std::max(ncrmax, v);
+      launch_round_factors(h->stream, l1.dev, P, l1.nrmax, ncrmax, l1.d.Cr, h->status);
       launch_build_phi(h->stream, l1.dev, nif, sub_flat_d, P.phi_ptr, const_cast<int32_t*>(P.phi_ids),
-                       const_cast<double*>(P.phi_w));
+                       const_cast<double*>(P.phi_w), P.Psi32);
     }
     P.nsub1 = l1.nsub;
     {

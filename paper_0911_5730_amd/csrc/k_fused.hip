@@ -270,6 +270,17 @@ __device__ inline double block_sum_of(const double* __restrict__ v, int n, doubl
   return wg_sum(acc, red);
 }
 
+// One block: the sum of n partials in the order of block_sum_of (bitwise the
+// same value) into *out.  With many blocks on both sides this replaces every
+// consuming block's own pass over all the partials.
+__global__ void __launch_bounds__(kNT) k_pcg_sum(const PcgScalars* __restrict__ sc, const double* __restrict__ part,
+                                                 int n, double* __restrict__ out) {
+  __shared__ double red[kNT];
+  if (sc->done) return;
+  const double v = block_sum_of(part, n, red);
+  if (threadIdx.x == 0) *out = v;
+}
+
 // PCG iteration k on the level-1 interface (Section 5) in four launches:
 //   matvec   p_k = z + beta p_{k-1};  q_s = S_s p_s;  partial p_s^T q_s
 //   update   alpha = rz / p^T S p;  r_k = r_{k-1} - alpha sum_s q_s (every sharer
@@ -288,24 +299,45 @@ __global__ void __launch_bounds__(kNT) k_pcg_matvec(LevelDev L, PcgDev P, int it
   extern __shared__ double sh[];
   __shared__ double red[kNT];
   if (P.sc->done) return;
-  double beta = 0.0;
-  if (it >= 2) {
-    const double rz = block_sum_of(P.rz_part[(it - 1) & 1], P.nblk, red);
-    const double rz0 = block_sum_of(P.rz_part[(it - 2) & 1], P.nblk, red);
-    beta = rz / rz0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) P.sc->betas[min(it - 2, kMaxHist - 1)] = beta;
-  }
-  const double* pold = P.p[(it - 1) & 1];
-  double* pnew = P.p[it & 1];
   const int s = blockIdx.x;
   const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
   const int nI = L.nint[s];
   const int ng = n - nI;
   const int g0 = L.goff[s];
   const double* S = L.K + L.koff[s] + nI + (size_t)nI * n;
+  const int tid = threadIdx.x;
+  // thread (mi, mc) forms the partial row sum of row mi over the columns
+  // mc, mc + nch, ...; its first kMV entries of S are loaded before the
+  // scalars and p are formed, so HBM latency overlaps that work
+  constexpr int kMV = 16;
+  const int nch = max(1, kNT / max(1, ng));
+  const bool narrow = ng <= kNT;
+  const int mi = narrow && ng > 0 ? tid % ng : 0;
+  const int mc = narrow && ng > 0 ? tid / ng : nch;
+  const bool act = narrow && mc < nch;
+  double sv[kMV];
+#pragma unroll
+  for (int k = 0; k < kMV; ++k) {
+    const int j = mc + k * nch;
+    sv[k] = (act && j < ng) ? S[mi + (size_t)j * n] : 0.0;
+  }
+  double beta = 0.0;
+  if (it >= 2) {
+    double rz, rz0;
+    if (P.fin) {
+      rz = P.sc->rzs[(it - 1) & 1];
+      rz0 = P.sc->rzs[(it - 2) & 1];
+    } else {
+      rz = block_sum_of(P.rz_part[(it - 1) & 1], P.nblk, red);
+      rz0 = block_sum_of(P.rz_part[(it - 2) & 1], P.nblk, red);
+    }
+    beta = rz / rz0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) P.sc->betas[min(it - 2, kMaxHist - 1)] = beta;
+  }
+  const double* pold = P.p[(it - 1) & 1];
+  double* pnew = P.p[it & 1];
   double* pl = sh;
   double* part = sh + ng;
-  const int tid = threadIdx.x;
   for (int a = tid; a < ng; a += kNT) {
     const int f = g0 + a;
     const int gi = L.gam_iid[f];
@@ -314,17 +346,26 @@ __global__ void __launch_bounds__(kNT) k_pcg_matvec(LevelDev L, PcgDev P, int it
     if (L.sh_flat[L.sh_ptr[gi]] == f) pnew[gi] = pv;
   }
   __syncthreads();
-  const int nch = max(1, kNT / max(1, ng));
-  for (ColWalk w_(tid, kNT, ng); w_.j < nch; w_.next()) {
-    const int i = w_.i, c = w_.j;
-    [[maybe_unused]] const int idx = i + c * ng;
-    part[idx] = dot_strided(S + i, n, pl, c, ng, nch);
+  if (narrow) {
+    if (act) {
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < kMV; ++k) {
+        const int j = mc + k * nch;
+        if (j < ng) acc += sv[k] * pl[j];
+      }
+      for (int j = mc + kMV * nch; j < ng; j += nch) acc += S[mi + (size_t)j * n] * pl[j];
+      part[mi + mc * ng] = acc;
+    }
+  } else {
+    for (int i = tid; i < ng; i += kNT) part[i] = dot_strided(S + i, n, pl, 0, ng, 1);
   }
   __syncthreads();
   double e = 0.0;
+  const int nc = narrow ? nch : 1;
   for (int i = tid; i < ng; i += kNT) {
     double acc = 0.0;
-    for (int c = 0; c < nch; ++c) acc += part[i + c * ng];
+    for (int c = 0; c < nc; ++c) acc += part[i + c * ng];
     P.qloc[g0 + i] = acc;
     e += pl[i] * acc;
   }
@@ -332,75 +373,77 @@ __global__ void __launch_bounds__(kNT) k_pcg_matvec(LevelDev L, PcgDev P, int it
   if (tid == 0) P.pq_part[s] = e;
 }
 
-// Copy n doubles from global src to LDS dst: the first kPre per thread are
-// loaded into registers by fetch() (issued early, before other work), the
-// rest by finish(), which also stores everything.
-template <int kPre>
+// BF16 storage: the upper half of the IEEE binary32 pattern, rounded to
+// nearest with ties to even (finite inputs only).
+__device__ inline uint16_t f32_to_bf16(float x) {
+  const uint32_t b = __float_as_uint(x);
+  return static_cast<uint16_t>((b + 0x7fffu + ((b >> 16) & 1u)) >> 16);
+}
+__device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float(static_cast<uint32_t>(h) << 16); }
+
+template <class D, class S>
+__device__ inline D widen(S v) { return static_cast<D>(v); }
+template <>
+__device__ inline float widen<float, uint16_t>(uint16_t v) { return bf16_to_f32(v); }
+template <>
+__device__ inline double widen<double, uint16_t>(uint16_t v) { return static_cast<double>(bf16_to_f32(v)); }
+
+// Copy n values from global src (type S) to LDS dst (type D): the first kPre
+// per thread are loaded into registers by fetch() (issued early, before other
+// work), the rest by finish(), which also stores everything.
+template <int kPre, class S = double, class D = double>
 struct Prefetch {
-  double v[kPre];
-  const double* src;
-  double* dst;
+  S v[kPre];
+  const S* src;
+  D* dst;
   int n;
-  __device__ void fetch(const double* s, double* d, int count) {
+  __device__ void fetch(const S* s, D* d, int count) {
     src = s;
     dst = d;
     n = count;
 #pragma unroll
     for (int u = 0; u < kPre; ++u) {
       const int i = threadIdx.x + u * kNT;
-      v[u] = i < n ? src[i] : 0.0;
+      v[u] = i < n ? src[i] : S(0);
     }
   }
   __device__ void finish() {
 #pragma unroll
     for (int u = 0; u < kPre; ++u) {
       const int i = threadIdx.x + u * kNT;
-      if (i < n) dst[i] = v[u];
+      if (i < n) dst[i] = widen<D>(v[u]);
     }
-    for (int i = threadIdx.x + kPre * kNT; i < n; i += kNT) dst[i] = src[i];
+    for (int i = threadIdx.x + kPre * kNT; i < n; i += kNT) dst[i] = widen<D>(src[i]);
   }
 };
 
-// The level-1 restriction of the interface residual r: g = delta r_G,
-// b = Psi^T g (ML-coarse) and da = delta T_rr g_r (ML-wDi, weighted for the
-// average); g, T_rr (Tl) and Psi (Pl) are already in LDS.
-__device__ void pcg_restrict_body(const LevelDev& L, int s, const double* g, double* part, double* da,
-                                  const double* T, const double* Pp) {
-  const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
-  const int ng = n - L.nint[s];
-  const int n_r = L.nr[s];
-  const int ncs = L.coff[s + 1] - L.coff[s];
-  const int g0 = L.goff[s];
-  const int tid = threadIdx.x;
-  const int nch = max(1, kNT / max(1, n_r));
-  for (ColWalk w_(tid, kNT, n_r); w_.j < nch; w_.next()) {
-    const int i = w_.i, c = w_.j;
-    [[maybe_unused]] const int idx = i + c * n_r;
-    double acc = 0.0;
-    for (int k = c; k < n_r; k += nch) acc += T[i + k * n_r] * g[k];
-    part[idx] = acc;
-  }
-  const int wave = tid >> 6, lane = tid & 63;
-  for (int k = wave; k < ncs; k += kNT / 64) {
-    double acc = 0.0;
-    for (int a = lane; a < ng; a += 64) acc += Pp[a + (size_t)k * ng] * g[a];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
-    if (lane == 0) L.b[L.coff[s] + k] = acc;
-  }
-  __syncthreads();
-  for (int i = tid; i < n_r; i += kNT) {
-    double acc = 0.0;
-    for (int c = 0; c < nch; ++c) acc += part[i + c * n_r];
-    da[g0 + i] = L.delta[g0 + i] * acc;
-  }
-  for (int a = n_r + tid; a < ng; a += kNT) da[g0 + a] = 0.0;
-}
+// Storage of T_rr and Psi in the precision forms: FP64 (kPrec 0), FP32 (1),
+// factored T_rr with a BF16 inverse Cholesky factor (2).  The products are
+// formed in FP64 in every form: the reduced forms cut the bytes streamed per
+// iteration, and FP64 arithmetic keeps the preconditioner a fixed symmetric
+// operator (FP32 arithmetic measurably adds PCG iterations).
+template <int kPrec> struct PrecForm;
+template <> struct PrecForm<0> { using TS = double; using PS = double; };
+template <> struct PrecForm<1> { using TS = float; using PS = float; };
+template <> struct PrecForm<2> { using TS = uint16_t; using PS = float; };
+
+// Column j of the packed lower triangle of an m x m matrix starts here.
+__device__ inline int packed_col(int j, int m) { return j * m - (j * (j - 1)) / 2; }
 
 // it >= 1: alpha, the residual update (r_k into r[it & 1]) and x update by the
-// owners, the partial r.r; then the restriction of r_k.  it == 0: the
-// restriction of r_0 only.
-__global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev P, int it, int nrmax, int ngmax) {
+// owners, the partial r.r; then the level-1 restriction of r_k (it == 0: of
+// r_0 only): g = delta r_G, b = Psi^T g (ML-coarse) and da = delta T_rr g_r
+// (ML-wDi, weighted for the interface average).
+//   FP64 / FP32 forms: thread (ti, tc) forms row ti of T_rr g_r over the
+//   columns tc, tc + nch, ... from registers loaded at the start, so the
+//   operator's HBM latency overlaps the residual update; LDS holds vectors only.
+//   Factored BF16 form: x = D^-1 g_r, v = W x, v = (I - Q Q^T)^2 v, y = W^T v,
+//   T_rr g_r = D^-1 y, with W staged in LDS (two passes over it).
+template <int kPrec>
+__global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev P, int it, int nrmax, int ngmax,
+                                                             int ncsmax) {
+  using TS = typename PrecForm<kPrec>::TS;
+  using PS = typename PrecForm<kPrec>::PS;
   extern __shared__ double sh[];
   __shared__ double red[kNT];
   if (P.sc->done) return;
@@ -409,22 +452,57 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
   const int ng = n - L.nint[s];
   const int g0 = L.goff[s];
   const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
   const int n_r = L.nr[s];
   const int ncs = L.coff[s + 1] - L.coff[s];
-  double* g = sh;
-  double* part = sh + ngmax;
-  double* Tl = part + kNT + ngmax;
-  double* Pl = Tl + (size_t)nrmax * nrmax;
+  double* g = sh;                        // ngmax
+  double* part = sh + ngmax;             // kNT + ngmax
+  double* xv = part + kNT + ngmax;       // factored form: x, then v (nrmax)
+  float* Wl = reinterpret_cast<float*>(xv + nrmax);                       // packed W
+  float* Ql = Wl + (size_t)nrmax * (nrmax + 1) / 2;                       // Q
+  float* dinv = Ql + (size_t)nrmax * ncsmax;                              // D^-1
+  const int nch = max(1, kNT / max(1, n_r));
+  const bool narrow = n_r <= kNT;
+  const int ti = narrow && n_r > 0 ? tid % n_r : 0;
+  const int tc = narrow && n_r > 0 ? tid / n_r : nch;
+  const bool act = narrow && tc < nch;
   // the operators' loads go out first and land while the scalars are formed
-  Prefetch<16> pt;
-  Prefetch<4> pp;
-  pt.fetch(L.T + L.toff[s], Tl, n_r * n_r);
-  pp.fetch(L.Psi + L.psioff[s], Pl, ng * ncs);
+  constexpr int kTV = 16, kPV = 2;
+  const TS* Tg = nullptr;
+  if constexpr (kPrec == 0) Tg = L.T + L.toff[s];
+  else if constexpr (kPrec == 1) Tg = P.T32 + L.toff[s];
+  const PS* Pg;
+  if constexpr (kPrec == 0) Pg = L.Psi + L.psioff[s];
+  else Pg = P.Psi32 + L.psioff[s];
+  TS tv[kTV];
+  if constexpr (kPrec != 2) {
+#pragma unroll
+    for (int k = 0; k < kTV; ++k) {
+      const int j = tc + k * nch;
+      tv[k] = (act && j < n_r) ? Tg[ti + (size_t)j * n_r] : TS(0);
+    }
+  }
+  PS pv[kPV][2];
+#pragma unroll
+  for (int m = 0; m < kPV; ++m)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int k = wave + 4 * m, a = lane + 64 * q;
+      pv[m][q] = (k < ncs && a < ng) ? Pg[a + (size_t)k * ng] : PS(0);
+    }
+  Prefetch<8, uint16_t, float> pw;
+  if constexpr (kPrec == 2) {
+    pw.fetch(P.W16 + L.toff[s], Wl, n_r * (n_r + 1) / 2);
+    for (int a = tid; a < n_r; a += kNT) dinv[a] = P.Dinv[g0 + a];
+    const int nq = n_r * P.ncr[s];
+    const float* Qg = P.Q32 + P.croff[s];
+    for (int a = tid; a < nq; a += kNT) Ql[a] = Qg[a];
+  }
   if (it == 0) {
     for (int a = tid; a < ng; a += kNT) g[a] = L.delta[g0 + a] * P.r[0][L.gam_iid[g0 + a]];
   } else {
-    const double rz = block_sum_of(P.rz_part[(it - 1) & 1], P.nblk, red);
-    const double pq = block_sum_of(P.pq_part, P.nsub1, red);
+    const double rz = P.fin ? P.sc->rzs[(it - 1) & 1] : block_sum_of(P.rz_part[(it - 1) & 1], P.nblk, red);
+    const double pq = P.fin ? P.sc->pqs : block_sum_of(P.pq_part, P.nsub1, red);
     const double alpha = rz / pq;
     const double* rold = P.r[(it - 1) & 1];
     double* rnew = P.r[it & 1];
@@ -450,10 +528,192 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
       P.sc->alphas[min(it - 1, kMaxHist - 1)] = alpha;
     }
   }
-  pt.finish();
-  pp.finish();
+  if constexpr (kPrec == 2) pw.finish();
   __syncthreads();
-  pcg_restrict_body(L, s, g, part, P.da, Tl, Pl);
+  // b = Psi^T g, one wave per coarse dof
+  for (int k = wave, m = 0; k < ncs; k += kNT / 64, ++m) {
+    double acc = 0.0;
+    if (m < kPV) {
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int a = lane + 64 * q;
+        if (a < ng) acc += static_cast<double>(pv[m][q]) * g[a];
+      }
+      for (int a = lane + 128; a < ng; a += 64) acc += static_cast<double>(Pg[a + (size_t)k * ng]) * g[a];
+    } else {
+      for (int a = lane; a < ng; a += 64) acc += static_cast<double>(Pg[a + (size_t)k * ng]) * g[a];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+    if (lane == 0) L.b[L.coff[s] + k] = acc;
+  }
+  if constexpr (kPrec == 2) {
+    const int n_cr = P.ncr[s];
+    for (ColWalk w_(tid, kNT, n_r); w_.j < nch; w_.next()) {
+      const int i = w_.i, c = w_.j;
+      [[maybe_unused]] const int idx = i + c * n_r;
+      double acc = 0.0;
+      for (int j = c; j <= i; j += nch)
+        acc += static_cast<double>(Wl[packed_col(j, n_r) + (i - j)]) * (g[j] * static_cast<double>(dinv[j]));
+      part[idx] = acc;
+    }
+    __syncthreads();
+    for (int i = tid; i < n_r; i += kNT) {
+      double acc = 0.0;
+      for (int c = 0; c < nch; ++c) acc += part[i + c * n_r];
+      xv[i] = acc;
+    }
+    __syncthreads();
+    if (n_cr > 0 && wave == 0) {
+      for (int rep = 0; rep < 2; ++rep)
+        for (int m = 0; m < n_cr; ++m) {
+          const float* q = Ql + (size_t)m * n_r;
+          double d = 0.0;
+          for (int a = lane; a < n_r; a += 64) d += static_cast<double>(q[a]) * xv[a];
+#pragma unroll
+          for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
+          for (int a = lane; a < n_r; a += 64) xv[a] -= d * static_cast<double>(q[a]);
+        }
+    }
+    __syncthreads();
+    for (ColWalk w_(tid, kNT, n_r); w_.j < nch; w_.next()) {
+      const int j = w_.i, c = w_.j;
+      [[maybe_unused]] const int idx = j + c * n_r;
+      const int cj = packed_col(j, n_r) - j;
+      double acc = 0.0;
+      for (int i = j + c; i < n_r; i += nch) acc += static_cast<double>(Wl[cj + i]) * xv[i];
+      part[idx] = acc;
+    }
+    __syncthreads();
+    for (int i = tid; i < n_r; i += kNT) {
+      double acc = 0.0;
+      for (int c = 0; c < nch; ++c) acc += part[i + c * n_r];
+      P.da[g0 + i] = L.delta[g0 + i] * (acc * static_cast<double>(dinv[i]));
+    }
+  } else {
+    if (narrow) {
+      if (act) {
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < kTV; ++k) {
+          const int j = tc + k * nch;
+          if (j < n_r) acc += static_cast<double>(tv[k]) * g[j];
+        }
+        for (int j = tc + kTV * nch; j < n_r; j += nch) acc += static_cast<double>(Tg[ti + (size_t)j * n_r]) * g[j];
+        part[ti + tc * n_r] = acc;
+      }
+    } else {
+      for (int i = tid; i < n_r; i += kNT) {
+        double acc = 0.0;
+        for (int j = 0; j < n_r; ++j) acc += static_cast<double>(Tg[i + (size_t)j * n_r]) * g[j];
+        part[i] = acc;
+      }
+    }
+    __syncthreads();
+    const int nc = narrow ? nch : 1;
+    for (int i = tid; i < n_r; i += kNT) {
+      double acc = 0.0;
+      for (int c = 0; c < nc; ++c) acc += part[i + c * n_r];
+      P.da[g0 + i] = L.delta[g0 + i] * acc;
+    }
+  }
+  for (int a = n_r + tid; a < ng; a += kNT) P.da[g0 + a] = 0.0;
+}
+
+// The reduced-precision forms of the level-1 T_rr and Psi, one workgroup per
+// substructure.  FP32 form: rounded copies.  Factored BF16 form: with S_rr the
+// leading n_r x n_r block of S and C_r the constraint rows on the r dofs,
+//   D = diag(S_rr)^(1/2),  R R^T = D^-1 S_rr D^-1 (Cholesky),  W = R^-1,
+//   Q = orthonormal basis (modified Gram-Schmidt) of Y = W D^-1 C_r^T,
+// so that T_rr = S_rr^-1 - S_rr^-1 C_r^T (C_r S_rr^-1 C_r^T)^-1 C_r S_rr^-1
+// = D^-1 W^T (I - Q Q^T) W D^-1.  W is rounded to BF16 (packed lower
+// triangle), Q and D^-1 to FP32; whatever the rounding, the applied operator
+// keeps the Gram form M^T M and so stays symmetric positive semidefinite.
+// LDS (doubles): A (n_r x n_r), Wm (n_r x n_r), Y (n_r x ncrmax), C (ncrmax x n_r), d (n_r).
+__global__ void __launch_bounds__(kNT) k_round_factors(LevelDev L, PcgDev P, int nrmax, int ncrmax,
+                                                       const double* __restrict__ Cr, int* status) {
+  extern __shared__ double shf[];
+  __shared__ double red[kNT];
+  const int s = blockIdx.x;
+  const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
+  const int nI = L.nint[s];
+  const int ng = n - nI;
+  const int n_r = L.nr[s];
+  const int ncs = L.coff[s + 1] - L.coff[s];
+  const int g0 = L.goff[s];
+  const int tid = threadIdx.x;
+  const double* Psi = L.Psi + L.psioff[s];
+  float* Psi32 = const_cast<float*>(P.Psi32) + L.psioff[s];
+  for (int k = tid; k < ng * ncs; k += kNT) Psi32[k] = static_cast<float>(Psi[k]);
+  if (P.prec == 1) {
+    const double* T = L.T + L.toff[s];
+    float* T32 = const_cast<float*>(P.T32) + L.toff[s];
+    for (int k = tid; k < n_r * n_r; k += kNT) T32[k] = static_cast<float>(T[k]);
+    return;
+  }
+  const int n_cr = P.ncr[s];
+  double* A = shf;
+  double* Wm = A + (size_t)nrmax * nrmax;
+  double* Y = Wm + (size_t)nrmax * nrmax;
+  double* C = Y + (size_t)nrmax * ncrmax;
+  double* d = C + (size_t)ncrmax * nrmax;
+  const double* Sg = L.K + L.koff[s] + nI + (size_t)nI * n;
+  for (ColWalk w_(tid, kNT, n_r); w_.j < n_r; w_.next()) {
+    const int i = w_.i, j = w_.j;
+    [[maybe_unused]] const int idx = i + j * n_r;
+    A[idx] = Sg[i + (size_t)j * n];
+    Wm[idx] = (i == j) ? 1.0 : 0.0;
+  }
+  const double* Cg = Cr + P.croff[s];
+  for (int k = tid; k < n_cr * n_r; k += kNT) C[k] = Cg[k];
+  __syncthreads();
+  for (int i = tid; i < n_r; i += kNT) d[i] = sqrt(A[i + (size_t)i * n_r]);
+  __syncthreads();
+  for (ColWalk w_(tid, kNT, n_r); w_.j < n_r; w_.next()) {
+    const int i = w_.i, j = w_.j;
+    [[maybe_unused]] const int idx = i + j * n_r;
+    A[idx] /= d[i] * d[j];
+  }
+  __syncthreads();
+  wg_potrf(A, n_r, n_r, status);
+  wg_trsm_lower(A, n_r, n_r, Wm, n_r, n_r);          // Wm = R^-1 (lower)
+  for (ColWalk w_(tid, kNT, n_r); w_.j < n_cr; w_.next()) {
+    const int i = w_.i, k = w_.j;
+    [[maybe_unused]] const int idx = i + k * n_r;
+    double acc = 0.0;
+    for (int j = 0; j <= i; ++j) acc += Wm[i + (size_t)j * n_r] * (C[k + (size_t)j * n_cr] / d[j]);
+    Y[idx] = acc;
+  }
+  __syncthreads();
+  for (int k = 0; k < n_cr; ++k) {
+    double* yk = Y + (size_t)k * n_r;
+    for (int m = 0; m < k; ++m) {
+      const double* qm = Y + (size_t)m * n_r;
+      double dot = 0.0;
+      for (int i = tid; i < n_r; i += kNT) dot += qm[i] * yk[i];
+      dot = wg_sum(dot, red);
+      for (int i = tid; i < n_r; i += kNT) yk[i] -= dot * qm[i];
+      __syncthreads();
+    }
+    double nn = 0.0;
+    for (int i = tid; i < n_r; i += kNT) nn += yk[i] * yk[i];
+    nn = sqrt(wg_sum(nn, red));
+    if (!(nn > 0.0)) {
+      if (tid == 0) flag_bad(status);
+      nn = 1.0;
+    }
+    for (int i = tid; i < n_r; i += kNT) yk[i] /= nn;
+    __syncthreads();
+  }
+  uint16_t* W16 = const_cast<uint16_t*>(P.W16) + L.toff[s];
+  for (ColWalk w_(tid, kNT, n_r); w_.j < n_r; w_.next()) {
+    const int i = w_.i, j = w_.j;
+    if (i >= j) W16[packed_col(j, n_r) + (i - j)] = f32_to_bf16(static_cast<float>(Wm[i + (size_t)j * n_r]));
+  }
+  float* Q32 = const_cast<float*>(P.Q32) + P.croff[s];
+  for (int k = tid; k < n_cr * n_r; k += kNT) Q32[k] = static_cast<float>(Y[k]);
+  float* Dv = const_cast<float*>(P.Dinv) + g0;
+  for (int i = tid; i < n_r; i += kNT) Dv[i] = static_cast<float>(1.0 / d[i]);
 }
 
 // Convergence test on r.r (every block takes the same decision; block 0
@@ -465,7 +725,7 @@ __global__ void __launch_bounds__(kNT) k_pcg_prolong_post(LevelDev L, PcgDev P, 
   __shared__ double red[kNT];
   if (P.sc->done) return;
   if (check) {
-    const double rr = block_sum_of(P.rr_part, P.nsub1, red);
+    const double rr = P.fin ? P.sc->rrs : block_sum_of(P.rr_part, P.nsub1, red);
     const bool conv = rr <= P.sc->thr2;
     const bool maxed = P.sc->iters >= P.sc->maxit;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -497,10 +757,12 @@ __global__ void __launch_bounds__(kNT) k_pcg_prolong_post(LevelDev L, PcgDev P, 
 }
 
 // Rows of the averaged coarse basis: for interface dof gi, in sharer order,
-// the coarse ids and delta_s(gi) Psi_s(row of gi, :) of every sharer s.
+// the coarse ids and delta_s(gi) Psi_s(row of gi, :) of every sharer s; with
+// psi32, Psi is taken as its FP32 copy so that prolongation and restriction
+// use the same basis.
 __global__ void __launch_bounds__(kNT) k_build_phi(LevelDev L, int nif, const int32_t* __restrict__ sub_of_flat,
                                                    const int32_t* __restrict__ phi_ptr, int32_t* __restrict__ phi_ids,
-                                                   double* __restrict__ phi_w) {
+                                                   double* __restrict__ phi_w, const float* __restrict__ psi32) {
   const int gi = blockIdx.x * kNT + threadIdx.x;
   if (gi >= nif) return;
   int j = phi_ptr[gi];
@@ -511,9 +773,11 @@ __global__ void __launch_bounds__(kNT) k_build_phi(LevelDev L, int nif, const in
     const int ngt = (L.loc_ptr[t + 1] - L.loc_ptr[t]) - L.nint[t];
     const int ncst = L.coff[t + 1] - L.coff[t];
     const double* Pt = L.Psi + L.psioff[t];
+    const float* Pf = psi32 ? psi32 + L.psioff[t] : nullptr;
     for (int k = 0; k < ncst; ++k) {
       phi_ids[j] = L.cid[L.coff[t] + k];
-      phi_w[j++] = L.delta[f] * Pt[at + (size_t)k * ngt];
+      const double w = Pf ? static_cast<double>(Pf[at + (size_t)k * ngt]) : Pt[at + (size_t)k * ngt];
+      phi_w[j++] = L.delta[f] * w;
     }
   }
 }
@@ -522,20 +786,38 @@ void launch_pcg_matvec(hipStream_t st, const LevelDev& L, int ngmax, const PcgDe
   const size_t lds = sizeof(double) * ((size_t)ngmax + kNT + ngmax);
   launch_kernel(k_pcg_matvec, dim3(L.nsub), dim3(kNT), lds, st, L, P, it);
 }
+void launch_pcg_sum(hipStream_t st, const PcgDev& P, const double* part, int n, double* out) {
+  launch_kernel(k_pcg_sum, dim3(1), dim3(kNT), 0, st, P.sc, part, n, out);
+}
 void launch_pcg_update_restrict(hipStream_t st, const LevelDev& L, int ngmax, int nrmax, int ncsmax, const PcgDev& P,
                                 int it) {
-  const size_t lds = sizeof(double) * ((size_t)ngmax + kNT + ngmax + (size_t)nrmax * nrmax + (size_t)ngmax * ncsmax);
-  launch_kernel(k_pcg_update_restrict, dim3(L.nsub), dim3(kNT), lds, st, L, P, it, nrmax, ngmax);
+  // doubles: g | part | x/v ; floats: packed W | Q | D^-1 (factored form only)
+  size_t lds = sizeof(double) * ((size_t)ngmax + kNT + ngmax);
+  if (P.prec == 2)
+    lds += sizeof(double) * nrmax +
+           sizeof(float) * ((size_t)nrmax * (nrmax + 1) / 2 + (size_t)nrmax * ncsmax + nrmax);
+  if (P.prec == 0)
+    launch_kernel(k_pcg_update_restrict<0>, dim3(L.nsub), dim3(kNT), lds, st, L, P, it, nrmax, ngmax, ncsmax);
+  else if (P.prec == 1)
+    launch_kernel(k_pcg_update_restrict<1>, dim3(L.nsub), dim3(kNT), lds, st, L, P, it, nrmax, ngmax, ncsmax);
+  else
+    launch_kernel(k_pcg_update_restrict<2>, dim3(L.nsub), dim3(kNT), lds, st, L, P, it, nrmax, ngmax, ncsmax);
+}
+void launch_round_factors(hipStream_t st, const LevelDev& L, const PcgDev& P, int nrmax, int ncrmax, const double* Cr,
+                          int* status) {
+  if (P.prec == 0 || L.nsub == 0) return;
+  const size_t lds = P.prec == 2 ? sizeof(double) * (2 * (size_t)nrmax * nrmax + 2 * (size_t)nrmax * ncrmax + nrmax) : 0;
+  launch_kernel(k_round_factors, dim3(L.nsub), dim3(kNT), lds, st, L, P, nrmax, ncrmax, Cr, status);
 }
 void launch_pcg_prolong_post(hipStream_t st, const LevelDev& L, const PcgDev& P, const double* uc, int check,
                             int parity) {
   launch_kernel(k_pcg_prolong_post, dim3(P.nblk), dim3(kNT), 0, st, L, P, uc, check, parity);
 }
 void launch_build_phi(hipStream_t st, const LevelDev& L, int nif, const int32_t* sub_of_flat, const int32_t* phi_ptr,
-                      int32_t* phi_ids, double* phi_w) {
+                      int32_t* phi_ids, double* phi_w, const float* psi32) {
   if (nif == 0) return;
   launch_kernel(k_build_phi, dim3((nif + kNT - 1) / kNT), dim3(kNT), 0, st, L, nif, sub_of_flat, phi_ptr, phi_ids,
-                phi_w);
+                phi_w, psi32);
 }
 
 }  // namespace bddc

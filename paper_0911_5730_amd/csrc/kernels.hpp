@@ -149,12 +149,32 @@ struct PcgDev {
   int nif = 0;
   int nsub1 = 0;
   int nblk = 1;                              // blocks of the interface average (rz partials)
+  // 1: a one-block launch after each producing launch sums its partials once
+  // into PcgScalars (rzs, pqs, rrs) and the consumers read that scalar; 0:
+  // every consuming block sums the partials itself (cheaper when there are few)
+  int fin = 0;
+  // precision form of the interface preconditioner (bddc_precision): 0 FP64
+  // T_rr and Psi; 1 FP32 copies of both; 2 T_rr in factored form
+  //   T_rr = D^-1 W^T (I - Q Q^T) W D^-1,
+  // D = diag(S_rr)^(1/2), W = inverse Cholesky factor of D^-1 S_rr D^-1 stored
+  // as BF16 (packed lower triangle), Q an orthonormal basis of W D^-1 C_r^T in
+  // FP32, D^-1 in FP32, Psi FP32.  Products of the reduced forms are formed in
+  // FP64 (reduced storage, FP64 arithmetic); every vector stays FP64.
+  int prec = 0;
+  const float* T32 = nullptr;       // FP32 T_rr (offsets toff)
+  const uint16_t* W16 = nullptr;    // BF16 packed lower W, column-major (offsets toff)
+  const float* Q32 = nullptr;       // FP32 Q, n_r x n_cr column-major (offsets croff)
+  const float* Dinv = nullptr;      // D^-1 on the interface flat (first n_r entries of each substructure)
+  const float* Psi32 = nullptr;     // FP32 Psi (offsets psioff)
+  const int32_t* ncr = nullptr;     // constraint rows on the r dofs, per substructure
+  const int64_t* croff = nullptr;
 };
 
 constexpr int kMaxHist = 4096;
 
 struct PcgScalars {
   double rz, pq, alpha, beta, rr, bb, thr2, rtol2;
+  double rzs[2], pqs, rrs;   // summed partials of the fused iteration (r.z by parity, p^T S p, r.r)
   int32_t iters, maxit, done, pad;
   double alphas[kMaxHist];
   double betas[kMaxHist];
@@ -256,11 +276,14 @@ void launch_apply_post_inv(hipStream_t st, const LevelDev& L, int nImax, int ngm
 
 // fused PCG iteration kernels (level-1 interface)
 void launch_pcg_matvec(hipStream_t st, const LevelDev& L, int ngmax, const PcgDev& P, int it);
+void launch_pcg_sum(hipStream_t st, const PcgDev& P, const double* part, int n, double* out);
+void launch_round_factors(hipStream_t st, const LevelDev& L, const PcgDev& P, int nrmax, int ncrmax, const double* Cr,
+                          int* status);
 void launch_pcg_update_restrict(hipStream_t st, const LevelDev& L, int ngmax, int nrmax, int ncsmax, const PcgDev& P,
                                 int it);
 void launch_pcg_prolong_post(hipStream_t st, const LevelDev& L, const PcgDev& P, const double* uc, int check,
                             int parity);
 void launch_build_phi(hipStream_t st, const LevelDev& L, int nif, const int32_t* sub_of_flat, const int32_t* phi_ptr,
-                      int32_t* phi_ids, double* phi_w);
+                      int32_t* phi_ids, double* phi_w, const float* psi32);
 
 }  // namespace bddc

@@ -105,7 +105,9 @@ def test_validation_errors():
     bad.levels = 3
     bad.agglom = []
     _expect("BDDC_EINVAL", bad)
-    _expect("BDDC_EUNSUPPORTED", base, precision="fp32")
+    _expect("BDDC_EINVAL", base, precision=7)
+    for prec in ("fp32", "bf16"):
+        assert P.plan(base, precision=prec)["n_corners"] == 9
     bad = synth.config(1)
     bad.nx = 1
     _expect("BDDC_EINVAL", bad)

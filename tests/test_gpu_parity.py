@@ -95,6 +95,28 @@ def test_deep_level_paths(path, monkeypatch):
         S.close()
 
 
+def test_pcg_scalar_finalize(monkeypatch):
+    """The PCG scalars (r.z, p^T S p, r.r) are summed either by every consuming
+    block or once, by a one-block launch after the producing launch, in the
+    same fixed order: the iterates must be bitwise identical, and match the
+    oracle."""
+    prob = _case("adaptive3")
+    out = {}
+    B = None
+    for fin in ("0", "1"):
+        monkeypatch.setenv("BDDC_PCG_FINALIZE", fin)
+        print(f"pcg finalize {fin}", flush=True)
+        S, B, ug, it, rr, o = run_pair(prob, oracle=B)
+        try:
+            assert abs(it - o["iters"]) <= 1
+            check_solution(S, B, ug, o)
+            out[fin] = (ug.copy(), it, rr)
+        finally:
+            S.close()
+    assert out["0"][1] == out["1"][1]
+    assert np.array_equal(out["0"][0], out["1"][0])
+
+
 @pytest.mark.parametrize("path", ["default", "lds16_global"])
 def test_setup_kernel_paths(path, monkeypatch):
     """The setup runs with 64-wide Cholesky panels and a matrix-core trailing
