@@ -100,6 +100,54 @@ def cpu_baseline(prob_full):
             "host_cpus": len(os.sched_getaffinity(0))}
 
 
+def precision_forms(P, synth, torch, cid: int, stream, precs=("fp64", "fp32", "bf16")) -> dict:
+    """Setup time, solves/s (preconditioner reused) and the level-1 apply
+    kernels' HBM rates for each precision form of one workload.  The reduced
+    forms store the level-1 T_rr and Psi in FP32 or BF16 (inverse Cholesky
+    factor) and keep the outer PCG, S, averaging, deeper levels and coarsest
+    factor in FP64."""
+    prob = synth.config(cid)
+    coeff = torch.tensor(prob.coeff, dtype=torch.float64, device="cuda")
+    f = torch.tensor(prob.f[0], dtype=torch.float64, device="cuda")
+    u = torch.empty_like(f)
+    out = {}
+    for prec in precs:
+        P.Solver(prob, coeff=coeff, stream=stream, precision=prec).close()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            P.Solver(prob, coeff=coeff, stream=stream, precision=prec).close()
+        torch.cuda.synchronize()
+        setup_ms = (time.perf_counter() - t0) / 3 * 1e3
+        S = P.Solver(prob, coeff=coeff, stream=stream, precision=prec)
+        _, it, rr = S.solve(f, u=u, rtol=prob.rtol, stream=stream)
+        torch.cuda.synchronize()
+        ns = 8
+        t0 = time.perf_counter()
+        for _ in range(ns):
+            S.solve(f, u=u, rtol=prob.rtol, stream=stream)
+        torch.cuda.synchronize()
+        solve_s = (time.perf_counter() - t0) / ns
+        kern = {}
+        for name, label in (("schur_local", "matvec"), ("apply_restrict", "update_restrict")):
+            P.timing_start(name, 1)
+            S.solve(f, u=u, rtol=prob.rtol, stream=stream)
+            tm = P.timing_stop()
+            us = tm["ms"] / max(1, tm["launches"]) * 1e3
+            by = tm["bytes"] / max(1, tm["launches"])
+            gbs = by / (us * 1e-6) / 1e9 if us > 0 else 0.0
+            kern[label] = {"avg_launch_us": us, "algorithmic_bytes_per_launch": by, "achieved_GBs": gbs,
+                           "frac_of_hbm_peak": gbs / PEAK_HBM_GBS, "launches": tm["launches"]}
+        S.close()
+        out[prec] = {"solves_per_s": 1.0 / solve_s, "solve_ms": solve_s * 1e3, "iterations": int(it[0]),
+                     "relres": float(rr[0]), "setup_ms": setup_ms, "apply_kernels": kern}
+        log(f"bench: config {cid} {prec}: {1.0 / solve_s:.1f} solves/s, {int(it[0])} iterations, "
+            f"setup {setup_ms:.2f} ms")
+    for prec in precs:
+        out[prec]["solves_vs_fp64"] = out[prec]["solves_per_s"] / out["fp64"]["solves_per_s"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,6 +159,8 @@ def main():
     ap.add_argument("--sample-every", type=int, default=8,
                     help="time one in this many launches of the roofline kernel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-precision-forms", action="store_true",
+                    help="skip the FP64 / FP32 / BF16 comparison on configs 2 and 3")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 256 MiB device buffer three times (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -251,6 +301,13 @@ def main():
         "roofline": roof,
         "setup_roofline": setup_roof,
     }
+    if not args.no_precision_forms:
+        out["precision_forms"] = {
+            "note": "solves/s with the preconditioner set up once; FP32 / BF16 = reduced storage of the level-1 "
+                    "T_rr and Psi streamed every iteration (BF16: inverse Cholesky factor), FP64 outer PCG",
+            "config2": precision_forms(P, synth, torch, 2, stream),
+            "config3": precision_forms(P, synth, torch, 3, stream),
+        }
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(prob)

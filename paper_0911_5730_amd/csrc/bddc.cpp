@@ -412,6 +412,8 @@ struct bddc_ctx {
   bool coop_launch = false;   // use the cooperative launch API
   double coop_bytes = 0;      // algorithmic bytes of one launch
   double by_average = 0;      // algorithmic bytes of the level-1 interface average
+  double by_ur_prec = 0;      // update + restriction (it >= 1), T_rr and Psi in the precision form's storage
+  double by_r_prec = 0;       // restriction of r_0 alone, likewise
   bddc::CoopDev coop;
   bddc::Arena coop_arena;
   bddc_info info{};
@@ -1523,7 +1525,7 @@ static int pcg_one(bddc_ctx* h, const double* f, double* u, double rtol, int max
   auto apply_iface = [&](int it) {
     timing::current_tag = it - 1;
     {
-      timing::Scope ts("apply_restrict", it > 0 ? l1.by_update_restrict : l1.by_restrict_ir, 0);
+      timing::Scope ts("apply_restrict", it > 0 ? h->by_ur_prec : h->by_r_prec, 0);
       launch_pcg_update_restrict(st, l1.dev, l1.ngmax, l1.nrmax, l1.ncsmax, P, it);
     }
     if (P.fin && it > 0) launch_pcg_sum(st, P, P.rr_part, P.nsub1, &P.sc->rrs);
@@ -1740,6 +1742,17 @@ bddc_status bddc_setup(const bddc_problem* p, void* hip_stream, bddc_handle* out
       phi_ptr[gi + 1] = phi_ptr[gi] + len;
     }
     const size_t nphi = (size_t)phi_ptr[nif];
+    // every sharer's flat entry of each flat entry's dof, padded to four
+    bool fits4 = true;
+    for (int gi = 0; gi < nif; ++gi) fits4 = fits4 && l1.sh_ptr[gi + 1] - l1.sh_ptr[gi] <= 4;
+    std::vector<int32_t> shf4;
+    if (fits4) {
+      shf4.assign((size_t)4 * l1.nflat_g, -1);
+      for (int f = 0; f < l1.nflat_g; ++f) {
+        const int gi = l1.gam_iid[f];
+        for (int k = l1.sh_ptr[gi]; k < l1.sh_ptr[gi + 1]; ++k) shf4[(size_t)4 * f + (k - l1.sh_ptr[gi])] = l1.sh_flat[k];
+      }
+    }
     int32_t* sub_flat_d = nullptr;
     const int nblk_avg = std::max(1, (nif + kNT / 8 - 1) / (kNT / 8));   // eight lanes per interface dof
     auto lay = [&] {
@@ -1759,6 +1772,7 @@ bddc_status bddc_setup(const bddc_problem* p, void* hip_stream, bddc_handle* out
       P.phi_ids = B.take<int32_t>(nphi);
       P.phi_w = B.take<double>(nphi);
       sub_flat_d = B.take<int32_t>(sub_of_flat.size());
+      if (fits4) P.shf4 = B.take<int4>(l1.nflat_g);
       if (h->precision != BDDC_FP64) {
         P.Psi32 = B.take<float>((size_t)l1.psioff.back());
         if (h->precision == BDDC_FP32) {
@@ -1794,6 +1808,7 @@ bddc_status bddc_setup(const bddc_problem* p, void* hip_stream, bddc_handle* out
       Staging stg(h->stream, &h->staged);
       stg.add(const_cast<int32_t*>(P.phi_ptr), phi_ptr);
       stg.add(sub_flat_d, sub_of_flat);
+      if (fits4) stg.add(reinterpret_cast<int32_t*>(const_cast<int4*>(P.shf4)), shf4);
       stg.flush();
       P.prec = h->precision == BDDC_FP32 ? 1 : (h->precision == BDDC_BF16 ? 2 : 0);
       P.ncr = l1.d.ncr;
@@ -1810,6 +1825,20 @@ bddc_status bddc_setup(const bddc_problem* p, void* hip_stream, bddc_handle* out
       for (int gi = 0; gi < nif; ++gi) nshare += l1.sh_ptr[gi + 1] - l1.sh_ptr[gi];
       // per interface dof: sharer indices and delta T g, phi row (id, weight, u_c), z and r
       h->by_average = 12.0 * nshare + 20.0 * (double)nphi + 8.0 * nif * 4;
+    }
+    {
+      // the restriction's operator bytes in the storage of the precision form
+      double op64 = 0, opp = 0;
+      for (int s = 0; s < l1.nsub; ++s) {
+        const double nr = l1.topo.n_r[s], ng = l1.topo.ngam(s), ncs = l1.coff[s + 1] - l1.coff[s];
+        const double ncr = l1.ncr[s];
+        op64 += 8 * nr * nr + 8 * ng * ncs;
+        if (P.prec == 1) opp += 4 * nr * nr + 4 * ng * ncs;
+        else if (P.prec == 2) opp += 2 * nr * (nr + 1) / 2 + 4 * nr * ncr + 4 * nr + 4 * ng * ncs;
+        else opp += 8 * nr * nr + 8 * ng * ncs;
+      }
+      h->by_ur_prec = l1.by_update_restrict - op64 + opp;
+      h->by_r_prec = l1.by_restrict_ir - op64 + opp;
     }
     clk.lap("pcg state + phi");
     plan_deep(h);

@@ -264,9 +264,18 @@ void launch_apply_post_inv(hipStream_t st, const LevelDev& L, int nImax, int ngm
 
 // ---------------------------------------------------------------- fused PCG iteration
 // Sum of n partials by every block in the same fixed order.
+// Eight loads in flight per thread; the additions keep the plain strided order.
 __device__ inline double block_sum_of(const double* __restrict__ v, int n, double* red) {
   double acc = 0.0;
-  for (int i = threadIdx.x; i < n; i += kNT) acc += v[i];
+  int i = threadIdx.x;
+  for (; i + 7 * kNT < n; i += 8 * kNT) {
+    double t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t[u] = v[i + u * kNT];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += t[u];
+  }
+  for (; i < n; i += kNT) acc += v[i];
   return wg_sum(acc, red);
 }
 
@@ -341,9 +350,10 @@ __global__ void __launch_bounds__(kNT) k_pcg_matvec(LevelDev L, PcgDev P, int it
   for (int a = tid; a < ng; a += kNT) {
     const int f = g0 + a;
     const int gi = L.gam_iid[f];
+    const bool own = P.shf4 ? P.shf4[f].x == f : L.sh_flat[L.sh_ptr[gi]] == f;
     const double pv = (it >= 2) ? P.z[gi] + beta * pold[gi] : P.z[gi];
     pl[a] = pv;
-    if (L.sh_flat[L.sh_ptr[gi]] == f) pnew[gi] = pv;
+    if (own) pnew[gi] = pv;
   }
   __syncthreads();
   if (narrow) {
@@ -474,22 +484,28 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
   const PS* Pg;
   if constexpr (kPrec == 0) Pg = L.Psi + L.psioff[s];
   else Pg = P.Psi32 + L.psioff[s];
+  // (the loads are unconditional, at clamped in-block addresses, so that
+  // they issue back to back; entries outside the block are never used)
   TS tv[kTV];
   if constexpr (kPrec != 2) {
+    if (n_r > 0) {
 #pragma unroll
-    for (int k = 0; k < kTV; ++k) {
-      const int j = tc + k * nch;
-      tv[k] = (act && j < n_r) ? Tg[ti + (size_t)j * n_r] : TS(0);
+      for (int k = 0; k < kTV; ++k) {
+        const int j = min(tc + k * nch, n_r - 1);
+        tv[k] = Tg[ti + (size_t)j * n_r];
+      }
     }
   }
   PS pv[kPV][2];
+  if (ng > 0 && ncs > 0) {
 #pragma unroll
-  for (int m = 0; m < kPV; ++m)
+    for (int m = 0; m < kPV; ++m)
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int k = wave + 4 * m, a = lane + 64 * q;
-      pv[m][q] = (k < ncs && a < ng) ? Pg[a + (size_t)k * ng] : PS(0);
-    }
+      for (int q = 0; q < 2; ++q) {
+        const int k = min(wave + 4 * m, ncs - 1), a = min(lane + 64 * q, ng - 1);
+        pv[m][q] = Pg[a + (size_t)k * ng];
+      }
+  }
   Prefetch<8, uint16_t, float> pw;
   if constexpr (kPrec == 2) {
     pw.fetch(P.W16 + L.toff[s], Wl, n_r * (n_r + 1) / 2);
@@ -512,10 +528,22 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
       const int f = g0 + a;
       const int gi = L.gam_iid[f];
       double q = 0.0;
-      for (int k = L.sh_ptr[gi]; k < L.sh_ptr[gi + 1]; ++k) q += P.qloc[L.sh_flat[k]];
+      bool own;
+      if (P.shf4) {
+        // the sharers' flat entries in one 16-byte load (-1 past the last)
+        const int4 sf = P.shf4[f];
+        q += P.qloc[sf.x];
+        if (sf.y >= 0) q += P.qloc[sf.y];
+        if (sf.z >= 0) q += P.qloc[sf.z];
+        if (sf.w >= 0) q += P.qloc[sf.w];
+        own = sf.x == f;
+      } else {
+        for (int k = L.sh_ptr[gi]; k < L.sh_ptr[gi + 1]; ++k) q += P.qloc[L.sh_flat[k]];
+        own = L.sh_flat[L.sh_ptr[gi]] == f;
+      }
       const double ri = rold[gi] - alpha * q;
       g[a] = L.delta[f] * ri;
-      if (L.sh_flat[L.sh_ptr[gi]] == f) {
+      if (own) {
         rnew[gi] = ri;
         P.x[gi] += alpha * p[gi];
         rr += ri * ri;

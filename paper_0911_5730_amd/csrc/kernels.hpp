@@ -146,6 +146,9 @@ struct PcgDev {
   const int32_t* phi_ptr = nullptr;          // per interface dof: its row of the delta-weighted
   const int32_t* phi_ids = nullptr;          //   coarse basis of all sharers (coarse ids, weights)
   const double* phi_w = nullptr;
+  // per level-1 interface flat entry: the flat entries of all sharers of its
+  // dof in sharer order, -1 past the last (null when a dof has more than four)
+  const int4* shf4 = nullptr;
   int nif = 0;
   int nsub1 = 0;
   int nblk = 1;                              // blocks of the interface average (rz partials)
