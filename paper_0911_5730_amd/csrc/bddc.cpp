@@ -411,6 +411,10 @@ struct bddc_ctx {
   bool coop_deep = false;
   bool coop_launch = false;   // use the cooperative launch API
   double coop_bytes = 0;      // algorithmic bytes of one launch
+  bool wide_deep = false;     // one deep level in row-block launches (WideDev)
+  bddc::WideDev wide;
+  double wide_bytes = 0;      // algorithmic bytes of the four launches
+  bddc::Arena wide_arena;
   double by_average = 0;      // algorithmic bytes of the level-1 interface average
   double by_ur_prec = 0;      // update + restriction (it >= 1), T_rr and Psi in the precision form's storage
   double by_r_prec = 0;       // restriction of r_0 alone, likewise
@@ -1234,6 +1238,19 @@ static void run_deep(bddc_ctx* h) {
     launch_deep_coop(st, C, h->coop_launch);
     return;
   }
+  if (h->wide_deep) {
+    Level& l2 = *h->levels[1];
+    WideDev W = h->wide;
+    W.stop = l1.dev.stop;
+    W.L.stop = l1.dev.stop;
+    LevelDev L2 = l2.dev;
+    L2.stop = l1.dev.stop;
+    launch_wide_pre(st, W);
+    launch_apply_restrict(st, L2, l2.ngmax, W.r2, l2.d.gam_gid, 1);
+    launch_wide_coarse(st, W);
+    launch_wide_post(st, W);
+    return;
+  }
   if (h->fused_deep) {
     DeepArgs A = h->deep;
     A.stop = l1.dev.stop;
@@ -1397,14 +1414,90 @@ static bool plan_coop(bddc_ctx* h) {
   return true;
 }
 
+// One deep level whose substructures do not fit the cooperative kernel: dense
+// K_II^-1 and M^T per level-2 substructure, applied in row blocks.
+static bool plan_wide(bddc_ctx* h) {
+  h->wide_deep = false;
+  if (h->levels.size() != 2) return false;
+  const char* env = getenv("BDDC_DEEP_PATH");
+  if (env && std::string(env) != "wide") return false;
+  Level& l1 = *h->levels[0];
+  Level& lv = *h->levels[1];
+  const Topology& T = lv.topo;
+  const int nsub = lv.nsub;
+  if (nsub < 1 || lv.nc < 1) return false;
+  std::vector<int64_t> kioff(nsub + 1, 0), moff(nsub + 1, 0);
+  int nmax_ops = 0;
+  for (int s = 0; s < nsub; ++s) {
+    const int64_t nI = T.n_int[s], ng = T.ngam(s);
+    kioff[s + 1] = kioff[s] + nI * nI;
+    moff[s + 1] = moff[s] + nI * ng;
+    nmax_ops = std::max<int>(nmax_ops, (int)(nI * nI + nI * ng));
+  }
+  // the coarsest solve and the level-2 interface live in one workgroup's LDS
+  if (sizeof(double) * (size_t)lv.nc > kLdsLimit || sizeof(double) * ((size_t)lv.ngmax + kNT) > kLdsLimit ||
+      sizeof(double) * (size_t)lv.nImax > kLdsLimit)
+    return false;
+  std::vector<int32_t> sub_of_flat(lv.nflat_g);
+  for (int s = 0; s < nsub; ++s)
+    for (int f = lv.goff[s]; f < lv.goff[s + 1]; ++f) sub_of_flat[f] = s;
+  WideDev W{};
+  Arena& A = h->wide_arena;
+  auto lay = [&] {
+    W.Kinv = A.take<double>(std::max<int64_t>(1, kioff[nsub]));
+    W.kioff = A.take<int64_t>(nsub + 1);
+    W.Mt = A.take<double>(std::max<int64_t>(1, moff[nsub]));
+    W.moff = A.take<int64_t>(nsub + 1);
+    W.sub_of_flat = A.take<int32_t>(std::max(1, lv.nflat_g));
+  };
+  A.reset_sizing();
+  lay();
+  A.allocate(h->stream);
+  lay();
+  hipStream_t st = h->stream;
+  {
+    Staging stg(st, &h->staged);
+    stg.add(const_cast<int64_t*>(W.kioff), kioff);
+    stg.add(const_cast<int64_t*>(W.moff), moff);
+    stg.add(const_cast<int32_t*>(W.sub_of_flat), sub_of_flat);
+    stg.flush();
+  }
+  launch_wide_ops(st, lv.dev, nmax_ops, const_cast<double*>(W.Kinv), W.kioff, const_cast<double*>(W.Mt), W.moff);
+  W.L = lv.dev;
+  W.nImax = lv.nImax;
+  W.ngmax = lv.ngmax;
+  W.rows1 = 8;
+  W.nchunk1 = std::max(1, (lv.nmax + W.rows1 - 1) / W.rows1);
+  W.nchunk4 = std::max(1, (lv.nImax + 63) / 64);
+  W.b1 = l1.d.b;
+  W.csh_ptr1 = l1.d.csh_ptr;
+  W.csh_flat1 = l1.d.csh_flat;
+  W.r2 = l1.d.rc;
+  W.u2 = l1.d.uc;
+  W.ncL = lv.nc;
+  W.AL = h->AL;
+  W.nflat = lv.nflat_g;
+  h->wide = W;
+  h->wide_deep = true;
+  // K_II^-1, M^T twice, T_rr, Psi twice, and the level vectors
+  double by = 0;
+  for (int s = 0; s < nsub; ++s) {
+    const double nI = T.n_int[s], ng = T.ngam(s), nr = T.n_r[s], ncs = lv.coff[s + 1] - lv.coff[s];
+    by += 8 * (nI * nI + 2 * nI * ng + nr * nr + 2 * ng * ncs);
+  }
+  h->wide_bytes = by + 8.0 * (2.0 * l1.nflat_c + 3.0 * lv.n + 6.0 * lv.nflat_g + lv.nflat_c + lv.nc);
+  return true;
+}
+
 // decide whether the deep levels fit one workgroup and fill the fused-kernel arguments
 static void plan_deep(bddc_ctx* h) {
   h->fused_deep = false;
   const int L = (int)h->levels.size();
   if (L < 2 || L - 1 > kMaxDeep) return;
   if (plan_coop(h)) return;
+  if (plan_wide(h)) return;
   const char* env = getenv("BDDC_DEEP_PATH");
-  if (env && (std::string(env) == "levels" || std::string(env) == "coop")) return;
+  if (env && (std::string(env) == "levels" || std::string(env) == "coop" || std::string(env) == "wide")) return;
   double bytes = 0;
   int wstride = 1;
   for (int li = 1; li < L; ++li) {
@@ -1641,6 +1734,7 @@ void release(bddc_ctx* h) {
   }
   h->top.release(st);
   h->coop_arena.release(st);
+  h->wide_arena.release(st);
   pinned_release(h->sc_host);
   for (void* b : h->staged) pinned_release(b);
   delete h;   // the pool frees above are stream-ordered
@@ -1858,7 +1952,7 @@ bddc_status bddc_setup(const bddc_problem* p, void* hip_stream, bddc_handle* out
       dev += h->levels[i]->arena_a.size() + h->levels[i]->arena_b.size() + h->levels[i]->arena_pcg.size();
     }
     h->info.indicator = ind;
-    h->info.device_bytes = (int64_t)(dev + h->top.size() + h->coop_arena.size());
+    h->info.device_bytes = (int64_t)(dev + h->top.size() + h->coop_arena.size() + h->wide_arena.size());
     h->info.apply_bytes = model_bytes(h, true);
     h->info.matvec_bytes = model_bytes(h, false);
     *out = h;

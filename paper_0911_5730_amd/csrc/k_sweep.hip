@@ -13,6 +13,9 @@
 // off-diagonal part; the next panel's global loads are issued into registers
 // before that work starts, so the stream of L never waits on the sweep's
 // dependency chain.
+#include <cstdlib>
+#include <string>
+
 #include "dense.hpp"
 #include "kernels.hpp"
 
@@ -20,10 +23,12 @@ namespace bddc {
 
 namespace {
 
-constexpr int kBW = 64;                    // panel width
+// Panel width BW = 64 (one workgroup per CU, fewest panels) or 32 (LDS of
+// 80 KB, two workgroups per CU: for grids of several rounds of workgroups)
 constexpr int kSweepNT = 512;              // 8 waves: the prefetch stays within a wave's 63 outstanding loads
 constexpr int kSweepRows = 304;            // largest n handled here (LDS: 8 (304 + 304 * 64) B < 160 KiB)
-constexpr int kRegs = (kSweepRows * kBW + kSweepNT - 1) / kSweepNT;   // prefetched doubles per thread
+template <int BW>
+constexpr int kRegs = (kSweepRows * BW + kSweepNT - 1) / kSweepNT;   // prefetched doubles per thread
 
 // value of v on lane `lane` (uniform) through the scalar unit
 __device__ inline double lane_value(double v, int lane) {
@@ -37,46 +42,50 @@ struct Panel {
   int c0, c1, rows;                        // columns [c0, c1), rows [c0, n)
 };
 
+template <int BW>
 __device__ inline Panel panel_of(int b, int n, int nI) {
   Panel p;
-  p.c0 = b * kBW;
-  p.c1 = min(p.c0 + kBW, nI);
+  p.c0 = b * BW;
+  p.c1 = min(p.c0 + BW, nI);
   p.rows = n - p.c0;
   return p;
 }
 
 // issue the loads of panel p (rows [c0, n) x cols [c0, c1) of A) into registers
-__device__ inline void panel_load(const double* __restrict__ A, int n, const Panel& p, double (&r)[kRegs]) {
+template <int BW>
+__device__ inline void panel_load(const double* __restrict__ A, int n, const Panel& p, double (&r)[kRegs<BW>]) {
   const int w = p.c1 - p.c0;
   ColWalk cw(threadIdx.x, kSweepNT, p.rows);
 #pragma unroll
-  for (int u = 0; u < kRegs; ++u) {
+  for (int u = 0; u < kRegs<BW>; ++u) {
     r[u] = cw.j < w ? A[(p.c0 + cw.i) + (size_t)(p.c0 + cw.j) * n] : 0.0;
     cw.next();
   }
 }
 
 // store panel registers into LDS: P[(i - c0) + k * rows]
-__device__ inline void panel_store(double* P, const Panel& p, const double (&r)[kRegs]) {
+template <int BW>
+__device__ inline void panel_store(double* P, const Panel& p, const double (&r)[kRegs<BW>]) {
   const int tot = p.rows * (p.c1 - p.c0);
 #pragma unroll
-  for (int u = 0; u < kRegs; ++u) {
+  for (int u = 0; u < kRegs<BW>; ++u) {
     const int idx = threadIdx.x + u * kSweepNT;
     if (idx < tot) P[idx] = r[u];
   }
 }
 
+template <int BW>
 __device__ void sweep_fwd(const double* __restrict__ A, int n, int nI, double* w, double* P) {
   const int tid = threadIdx.x;
-  const int nb = (nI + kBW - 1) / kBW;
-  double r[kRegs];
-  Panel p = panel_of(0, n, nI);
-  panel_load(A, n, p, r);
-  panel_store(P, p, r);
+  const int nb = (nI + BW - 1) / BW;
+  double r[kRegs<BW>];
+  Panel p = panel_of<BW>(0, n, nI);
+  panel_load<BW>(A, n, p, r);
+  panel_store<BW>(P, p, r);
   __syncthreads();
   for (int b = 0; b < nb; ++b) {
-    const Panel q = panel_of(b + 1, n, nI);
-    if (b + 1 < nb) panel_load(A, n, q, r);
+    const Panel q = panel_of<BW>(b + 1, n, nI);
+    if (b + 1 < nb) panel_load<BW>(A, n, q, r);
     const int wb = p.c1 - p.c0;
     if (tid < 64) {
       // diagonal block: lane l owns row c0 + l
@@ -101,24 +110,25 @@ __device__ void sweep_fwd(const double* __restrict__ A, int n, int nI, double* w
     }
     __syncthreads();
     if (b + 1 < nb) {
-      panel_store(P, q, r);
+      panel_store<BW>(P, q, r);
       __syncthreads();
     }
     p = q;
   }
 }
 
+template <int BW>
 __device__ void sweep_bwd(const double* __restrict__ A, int n, int nI, double* w, double* P) {
   const int tid = threadIdx.x;
-  const int nb = (nI + kBW - 1) / kBW;
-  double r[kRegs];
-  Panel p = panel_of(nb - 1, n, nI);
-  panel_load(A, n, p, r);
-  panel_store(P, p, r);
+  const int nb = (nI + BW - 1) / BW;
+  double r[kRegs<BW>];
+  Panel p = panel_of<BW>(nb - 1, n, nI);
+  panel_load<BW>(A, n, p, r);
+  panel_store<BW>(P, p, r);
   __syncthreads();
   for (int b = nb - 1; b >= 0; --b) {
-    const Panel q = panel_of(b - 1, n, nI);
-    if (b > 0) panel_load(A, n, q, r);
+    const Panel q = panel_of<BW>(b - 1, n, nI);
+    if (b > 0) panel_load<BW>(A, n, q, r);
     const int wb = p.c1 - p.c0;
     // w_j -= sum over rows below the block of L[i][j] w_i, eight lanes per column
     {
@@ -147,7 +157,7 @@ __device__ void sweep_bwd(const double* __restrict__ A, int n, int nI, double* w
     }
     __syncthreads();
     if (b > 0) {
-      panel_store(P, q, r);
+      panel_store<BW>(P, q, r);
       __syncthreads();
     }
     p = q;
@@ -157,6 +167,7 @@ __device__ void sweep_bwd(const double* __restrict__ A, int n, int nI, double* w
 }  // namespace
 
 // y = L_II^{-1} r_I (kept for the post-correction), t = L_GI y
+template <int BW>
 __global__ void __launch_bounds__(kSweepNT) k_sweep_pre(LevelDev L, const double* __restrict__ r) {
   extern __shared__ double sh[];
   if (L.stop && *L.stop) return;
@@ -170,12 +181,13 @@ __global__ void __launch_bounds__(kSweepNT) k_sweep_pre(LevelDev L, const double
   const int tid = threadIdx.x;
   for (int i = tid; i < n; i += kSweepNT) w[i] = i < nI ? r[L.int_gid[L.ioff[s] + i]] : 0.0;
   __syncthreads();
-  if (nI > 0) sweep_fwd(A, n, nI, w, P);
+  if (nI > 0) sweep_fwd<BW>(A, n, nI, w, P);
   for (int i = tid; i < nI; i += kSweepNT) L.y[L.ioff[s] + i] = w[i];
   for (int a = tid; a < ng; a += kSweepNT) L.t[L.goff[s] + a] = -w[nI + a];
 }
 
 // u_B = sum over sharers of v (owner writes); u_I = L_II^{-T} (y - L_GI^T u_B)
+template <int BW>
 __global__ void __launch_bounds__(kSweepNT) k_sweep_post(LevelDev L, double* __restrict__ u,
                                                     const int32_t* __restrict__ gam_map) {
   extern __shared__ double sh[];
@@ -199,11 +211,12 @@ __global__ void __launch_bounds__(kSweepNT) k_sweep_post(LevelDev L, double* __r
   for (int i = tid; i < nI; i += kSweepNT) w[i] = L.y[L.ioff[s] + i];
   __syncthreads();
   if (nI == 0) return;
-  sweep_bwd(L.K + L.koff[s], n, nI, w, P);
+  sweep_bwd<BW>(L.K + L.koff[s], n, nI, w, P);
   for (int i = tid; i < nI; i += kSweepNT) u[L.int_gid[L.ioff[s] + i]] = w[i];
 }
 
 // interior recovery of the interface-reduced solve: u_G = x, u_I = L_II^{-T}(y - L_GI^T x_s)
+template <int BW>
 __global__ void __launch_bounds__(kSweepNT) k_sweep_recover(LevelDev L, const double* __restrict__ x,
                                                        double* __restrict__ u) {
   extern __shared__ double sh[];
@@ -225,23 +238,42 @@ __global__ void __launch_bounds__(kSweepNT) k_sweep_recover(LevelDev L, const do
   for (int i = tid; i < nI; i += kSweepNT) w[i] = L.y[L.ioff[s] + i];
   __syncthreads();
   if (nI == 0) return;
-  sweep_bwd(L.K + L.koff[s], n, nI, w, P);
+  sweep_bwd<BW>(L.K + L.koff[s], n, nI, w, P);
   for (int i = tid; i < nI; i += kSweepNT) u[L.int_gid[L.ioff[s] + i]] = w[i];
 }
 
-size_t sweep_lds() { return sizeof(double) * ((size_t)kSweepRows + (size_t)kSweepRows * kBW); }
-static_assert(sizeof(double) * ((size_t)kSweepRows + (size_t)kSweepRows * kBW) <= 160 * 1024, "sweep LDS");
+template <int BW>
+constexpr size_t sweep_lds_bytes() { return sizeof(double) * ((size_t)kSweepRows + (size_t)kSweepRows * BW); }
+static_assert(sweep_lds_bytes<64>() <= 160 * 1024, "sweep LDS");
+static_assert(2 * sweep_lds_bytes<32>() <= 160 * 1024, "two 32-wide sweep workgroups per CU");
 
 bool sweep_fits(int nmax) { return nmax <= kSweepRows; }
 
+// 32-wide panels once the grid takes more than one round of one workgroup per
+// CU (BDDC_SWEEP_BW=32/64 forces either width)
+static bool narrow_panels(int nsub) {
+  const char* env = getenv("BDDC_SWEEP_BW");
+  if (env) return std::string(env) == "32";
+  return nsub > 256;
+}
+
 void launch_sweep_pre(hipStream_t st, const LevelDev& L, const double* r) {
-  launch_kernel(k_sweep_pre, dim3(L.nsub), dim3(kSweepNT), sweep_lds(), st, L, r);
+  if (narrow_panels(L.nsub))
+    launch_kernel(k_sweep_pre<32>, dim3(L.nsub), dim3(kSweepNT), sweep_lds_bytes<32>(), st, L, r);
+  else
+    launch_kernel(k_sweep_pre<64>, dim3(L.nsub), dim3(kSweepNT), sweep_lds_bytes<64>(), st, L, r);
 }
 void launch_sweep_post(hipStream_t st, const LevelDev& L, double* u, const int32_t* gam_map) {
-  launch_kernel(k_sweep_post, dim3(L.nsub), dim3(kSweepNT), sweep_lds(), st, L, u, gam_map);
+  if (narrow_panels(L.nsub))
+    launch_kernel(k_sweep_post<32>, dim3(L.nsub), dim3(kSweepNT), sweep_lds_bytes<32>(), st, L, u, gam_map);
+  else
+    launch_kernel(k_sweep_post<64>, dim3(L.nsub), dim3(kSweepNT), sweep_lds_bytes<64>(), st, L, u, gam_map);
 }
 void launch_sweep_recover(hipStream_t st, const LevelDev& L, const double* x, double* u) {
-  launch_kernel(k_sweep_recover, dim3(L.nsub), dim3(kSweepNT), sweep_lds(), st, L, x, u);
+  if (narrow_panels(L.nsub))
+    launch_kernel(k_sweep_recover<32>, dim3(L.nsub), dim3(kSweepNT), sweep_lds_bytes<32>(), st, L, x, u);
+  else
+    launch_kernel(k_sweep_recover<64>, dim3(L.nsub), dim3(kSweepNT), sweep_lds_bytes<64>(), st, L, x, u);
 }
 
 }  // namespace bddc

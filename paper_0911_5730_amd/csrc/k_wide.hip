@@ -1,0 +1,205 @@
+// One deep level whose substructures are too large for one workgroup each
+// (Algorithm "Multilevel BDDC" at level 2 with a direct coarsest solve), as
+// four launches of many workgroups:
+//   pre      r_2 gathered from the level-1 coarse contributions (ML-ri+1);
+//            z_I = K_II^-1 r_I and t = K_GI K_II^-1 r_I (ML-uIi, ML-rBi) as
+//            row blocks of dense products, several workgroups per substructure
+//   restrict g = D (r_G - sum t), a = T_rr g_r, b = Psi^T g (k_apply_restrict)
+//   coarse   r_3 = sum of b, u_3 = A_3^-1 r_3 (in every workgroup), and
+//            v = D (a + Psi u_3) for every level-2 interface entry
+//   post     u_B = sum over sharers of v (ML-uBi-1); u_I = z_I - K_II^-1 K_IG u_B
+//            (ML-vIi, ML-ui), row blocks again
+// Combining the interior pre- and post-corrections into z_I - M^T u_B with
+// M = K_GI K_II^-1 = L_GI L^-1 removes the dependent triangular sweeps: every
+// phase is a set of independent dense rows.
+#include "dense.hpp"
+#include "kernels.hpp"
+
+namespace bddc {
+
+// r_2 at level-2 dof k: the sum of the level-1 coarse contributions
+__device__ inline double wide_r2(const WideDev& W, int k) {
+  double acc = 0.0;
+  for (int q = W.csh_ptr1[k]; q < W.csh_ptr1[k + 1]; ++q) acc += W.b1[W.csh_flat1[q]];
+  return acc;
+}
+
+// grid (chunks, substructures): rows [chunk*rows1, ...) of [K_II^-1 ; M]
+__global__ void __launch_bounds__(kNT) k_wide_pre(WideDev W) {
+  extern __shared__ double sh[];
+  if (W.stop && *W.stop) return;
+  const LevelDev& L = W.L;
+  const int s = blockIdx.y, chunk = blockIdx.x;
+  const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
+  const int nI = L.nint[s];
+  const int ng = n - nI;
+  const int r0 = chunk * W.rows1;
+  if (r0 >= n) return;
+  const int r1 = min(n, r0 + W.rows1);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  double* rI = sh;
+  for (int i = tid; i < nI; i += kNT) {
+    const int k = L.int_gid[L.ioff[s] + i];
+    const double v = wide_r2(W, k);
+    rI[i] = v;
+    if (chunk == 0) W.r2[k] = v;
+  }
+  if (chunk == 0)
+    for (int a = tid; a < ng; a += kNT) {
+      const int k = L.gam_gid[L.goff[s] + a];
+      W.r2[k] = wide_r2(W, k);   // every sharer stores the same value
+    }
+  __syncthreads();
+  const double* Ki = W.Kinv + W.kioff[s];
+  const double* Mt = W.Mt + W.moff[s];
+  // one wave per row; rows < nI: column rho of the symmetric K_II^-1, else
+  // column rho - nI of M^T (row of M): both contiguous
+  for (int rho = r0 + wave; rho < r1; rho += kNT / 64) {
+    const double* col = rho < nI ? Ki + (size_t)rho * nI : Mt + (size_t)(rho - nI) * nI;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    int j = lane;
+    for (; j + 192 < nI; j += 256) {
+      const double c0 = col[j], c1 = col[j + 64], c2 = col[j + 128], c3 = col[j + 192];
+      acc[0] += c0 * rI[j];
+      acc[1] += c1 * rI[j + 64];
+      acc[2] += c2 * rI[j + 128];
+      acc[3] += c3 * rI[j + 192];
+    }
+    for (; j < nI; j += 64) acc[0] += col[j] * rI[j];
+    double v = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (lane == 0) {
+      if (rho < nI) L.y[L.ioff[s] + rho] = v;
+      else L.t[L.goff[s] + rho - nI] = v;
+    }
+  }
+}
+
+// the coarsest problem (solved by every workgroup, it is small) and the
+// prolongation of its solution to the workgroup's slice of interface entries
+__global__ void __launch_bounds__(kNT) k_wide_coarse(WideDev W) {
+  extern __shared__ double sh[];
+  if (W.stop && *W.stop) return;
+  const LevelDev& L = W.L;
+  double* u3 = sh;
+  for (int k = threadIdx.x; k < W.ncL; k += kNT) {
+    double acc = 0.0;
+    for (int q = L.csh_ptr[k]; q < L.csh_ptr[k + 1]; ++q) acc += L.b[L.csh_flat[q]];
+    u3[k] = acc;
+  }
+  __syncthreads();
+  wg_trsv_lower(W.AL, W.ncL, W.ncL, u3);
+  wg_trsv_lower_trans(W.AL, W.ncL, W.ncL, u3);
+  for (int f = blockIdx.x * kNT + threadIdx.x; f < W.nflat; f += gridDim.x * kNT) {
+    const int s = W.sub_of_flat[f];
+    const int a = f - L.goff[s];
+    const int ng = (L.loc_ptr[s + 1] - L.loc_ptr[s]) - L.nint[s];
+    const int c0 = L.coff[s], ncs = L.coff[s + 1] - c0;
+    const double* P = L.Psi + L.psioff[s];
+    double w = L.a[f];
+    for (int k = 0; k < ncs; ++k) w += P[a + (size_t)k * ng] * u3[L.cid[c0 + k]];
+    L.v[f] = L.delta[f] * w;
+  }
+}
+
+// grid (chunks of 64 interior rows, substructures): u_B, then
+// u_I = z_I - M^T u_B with four threads per row (fixed-order reduction)
+__global__ void __launch_bounds__(kNT) k_wide_post(WideDev W) {
+  extern __shared__ double sh[];
+  if (W.stop && *W.stop) return;
+  const LevelDev& L = W.L;
+  const int s = blockIdx.y, chunk = blockIdx.x;
+  const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
+  const int nI = L.nint[s];
+  const int ng = n - nI;
+  const int g0 = L.goff[s];
+  const int tid = threadIdx.x;
+  double* uB = sh;
+  double* part = sh + ng;
+  if (chunk * 64 >= max(nI, 1)) return;
+  for (int a = tid; a < ng; a += kNT) {
+    const int f = g0 + a;
+    const int gi = L.gam_iid[f];
+    double acc = 0.0;
+    for (int k = L.sh_ptr[gi]; k < L.sh_ptr[gi + 1]; ++k) acc += L.v[L.sh_flat[k]];
+    uB[a] = acc;
+    if (chunk == 0 && L.sh_flat[L.sh_ptr[gi]] == f) W.u2[L.gam_gid[f]] = acc;
+  }
+  __syncthreads();
+  const int il = tid & 63, ag = tid >> 6;
+  const int i = chunk * 64 + il;
+  const double* Mt = W.Mt + W.moff[s];
+  double acc = 0.0;
+  if (i < nI)
+    for (int a = ag; a < ng; a += 4) acc += Mt[i + (size_t)a * nI] * uB[a];
+  part[tid] = acc;
+  __syncthreads();
+  if (ag == 0 && i < nI) {
+    const double m = (part[il] + part[il + 64]) + (part[il + 128] + part[il + 192]);
+    W.u2[L.int_gid[L.ioff[s] + i]] = L.y[L.ioff[s] + i] - m;
+  }
+}
+
+// setup: K_II^-1 = L^-T L^-1 and M^T = L^-T L_GI^T from the explicit L^-1
+// (column-major, lower) and the factored K (L_GI in rows nI.. of the first nI
+// columns); one thread per entry, grid (blocks, substructures)
+__global__ void __launch_bounds__(kNT) k_wide_ops(LevelDev L, double* __restrict__ Kinv,
+                                                  const int64_t* __restrict__ kioff, double* __restrict__ Mt,
+                                                  const int64_t* __restrict__ moff) {
+  const int s = blockIdx.y;
+  const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
+  const int nI = L.nint[s];
+  const int ng = n - nI;
+  const int e = blockIdx.x * kNT + threadIdx.x;
+  const double* Li = L.Linv + L.linvoff[s];
+  const double* A = L.K + L.koff[s];
+  if (e < nI * nI) {
+    const int i = e % nI, j = e / nI;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    int p = max(i, j);
+    for (; p + 3 < nI; p += 4) {
+      acc[0] += Li[p + (size_t)i * nI] * Li[p + (size_t)j * nI];
+      acc[1] += Li[p + 1 + (size_t)i * nI] * Li[p + 1 + (size_t)j * nI];
+      acc[2] += Li[p + 2 + (size_t)i * nI] * Li[p + 2 + (size_t)j * nI];
+      acc[3] += Li[p + 3 + (size_t)i * nI] * Li[p + 3 + (size_t)j * nI];
+    }
+    for (; p < nI; ++p) acc[0] += Li[p + (size_t)i * nI] * Li[p + (size_t)j * nI];
+    Kinv[kioff[s] + e] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  } else if (e < nI * nI + nI * ng) {
+    const int e2 = e - nI * nI;
+    const int j = e2 % nI, a = e2 / nI;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    int p = j;
+    for (; p + 3 < nI; p += 4) {
+      acc[0] += A[(nI + a) + (size_t)p * n] * Li[p + (size_t)j * nI];
+      acc[1] += A[(nI + a) + (size_t)(p + 1) * n] * Li[p + 1 + (size_t)j * nI];
+      acc[2] += A[(nI + a) + (size_t)(p + 2) * n] * Li[p + 2 + (size_t)j * nI];
+      acc[3] += A[(nI + a) + (size_t)(p + 3) * n] * Li[p + 3 + (size_t)j * nI];
+    }
+    for (; p < nI; ++p) acc[0] += A[(nI + a) + (size_t)p * n] * Li[p + (size_t)j * nI];
+    Mt[moff[s] + e2] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  }
+}
+
+void launch_wide_ops(hipStream_t st, const LevelDev& L, int nmax_ops, double* Kinv, const int64_t* kioff, double* Mt,
+                     const int64_t* moff) {
+  if (L.nsub == 0 || nmax_ops == 0) return;
+  launch_kernel(k_wide_ops, dim3((nmax_ops + kNT - 1) / kNT, L.nsub), dim3(kNT), 0, st, L, Kinv, kioff, Mt, moff);
+}
+
+void launch_wide_pre(hipStream_t st, const WideDev& W) {
+  launch_kernel(k_wide_pre, dim3(W.nchunk1, W.L.nsub), dim3(kNT), sizeof(double) * (size_t)max(W.nImax, 1), st, W);
+}
+
+void launch_wide_coarse(hipStream_t st, const WideDev& W) {
+  const int nb = max(1, min(64, (W.nflat + kNT - 1) / kNT));
+  launch_kernel(k_wide_coarse, dim3(nb), dim3(kNT), sizeof(double) * (size_t)max(W.ncL, 1), st, W);
+}
+
+void launch_wide_post(hipStream_t st, const WideDev& W) {
+  launch_kernel(k_wide_post, dim3(W.nchunk4, W.L.nsub), dim3(kNT), sizeof(double) * ((size_t)W.ngmax + kNT), st,
+                W);
+}
+
+}  // namespace bddc

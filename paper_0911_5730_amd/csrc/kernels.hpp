@@ -132,6 +132,34 @@ void launch_pack_coop(hipStream_t st, const LevelDev& L, const CoopDev& C);
 void launch_tri_inverse_dense(hipStream_t st, const double* L, int ld, int m, double* X);
 int coop_max_blocks(size_t lds);
 
+// One deep level with substructures too large for the cooperative kernel:
+// row blocks of dense K_II^-1 and M^T = (K_GI K_II^-1)^T over many workgroups.
+struct WideDev {
+  LevelDev L;                         // level 2
+  int nImax = 0, ngmax = 0;
+  int rows1 = 8;                      // rows of [K_II^-1 ; M] per workgroup of the pre kernel
+  int nchunk1 = 1, nchunk4 = 1;       // row chunks per substructure (pre, post)
+  const double* Kinv = nullptr;       // n_I x n_I per substructure, column-major
+  const int64_t* kioff = nullptr;
+  const double* Mt = nullptr;         // M^T, n_I x n_G per substructure, column-major
+  const int64_t* moff = nullptr;
+  const double* b1 = nullptr;         // level-1 coarse contributions
+  const int32_t* csh_ptr1 = nullptr;  // level-2 dof -> level-1 coarse flat entries
+  const int32_t* csh_flat1 = nullptr;
+  double* r2 = nullptr;               // level-2 right-hand side
+  double* u2 = nullptr;               // level-2 solution
+  int ncL = 0;
+  const double* AL = nullptr;         // coarsest Cholesky factor
+  const int32_t* sub_of_flat = nullptr;   // level-2 interface flat entry -> substructure
+  int nflat = 0;
+  const int32_t* stop = nullptr;
+};
+void launch_wide_ops(hipStream_t st, const LevelDev& L, int nmax_ops, double* Kinv, const int64_t* kioff, double* Mt,
+                     const int64_t* moff);
+void launch_wide_pre(hipStream_t st, const WideDev& W);
+void launch_wide_coarse(hipStream_t st, const WideDev& W);
+void launch_wide_post(hipStream_t st, const WideDev& W);
+
 // state of the fused PCG iteration on the level-1 interface
 struct PcgDev {
   struct PcgScalars* sc = nullptr;

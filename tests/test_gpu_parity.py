@@ -75,11 +75,12 @@ def test_solve_and_apply_match_oracle(name):
         S.close()
 
 
-@pytest.mark.parametrize("path", ["coop", "fused", "levels"])
+@pytest.mark.parametrize("path", ["coop", "fused", "levels", "wide"])
 def test_deep_level_paths(path, monkeypatch):
     """Levels >= 2 run in one cooperative launch with one workgroup per
-    level-2 substructure (one deep level), in one fused workgroup, or in one
-    launch per phase and level; all must match the oracle."""
+    level-2 substructure (one deep level), in one fused workgroup, in one
+    launch per phase and level, or (one deep level) as row blocks of dense
+    K_II^-1 and K_GI K_II^-1 over many workgroups; all must match the oracle."""
     monkeypatch.setenv("BDDC_DEEP_PATH", path)
     prob = _case("adaptive3")
     S, B, ug, it, rr, o = run_pair(prob)
@@ -117,18 +118,20 @@ def test_pcg_scalar_finalize(monkeypatch):
     assert np.array_equal(out["0"][0], out["1"][0])
 
 
-@pytest.mark.parametrize("path", ["default", "lds16_global"])
+@pytest.mark.parametrize("path", ["default", "lds16_global", "sweep32"])
 def test_setup_kernel_paths(path, monkeypatch):
     """The setup runs with 64-wide Cholesky panels and a matrix-core trailing
     update plus LDS-resident Gauss-Jordan factorizations, and the level-1
-    interior sweeps stream 64-column panels (default); or with 16-wide panels
-    on the vector units, global-memory factorizations and 16-row blocked
-    sweeps.  Both must give the oracle's preconditioner and solution (H/h = 16,
+    interior sweeps stream 64-column panels (default; 32-column panels,
+    two workgroups per CU, on large grids); or with 16-wide panels on the
+    vector units, global-memory factorizations and 16-row blocked sweeps.  Both must give the oracle's preconditioner and solution (H/h = 16,
     ragged 64-column panels)."""
     if path == "lds16_global":
         monkeypatch.setenv("BDDC_CHOL_PATH", "lds16")
         monkeypatch.setenv("BDDC_SETUP_PATH", "global")
         monkeypatch.setenv("BDDC_SWEEP", "off")
+    if path == "sweep32":
+        monkeypatch.setenv("BDDC_SWEEP_BW", "32")
     prob = _case("adaptive3_h16")
     print(f"setup kernel path {path}", flush=True)
     S, B, ug, it, rr, o = run_pair(prob)
