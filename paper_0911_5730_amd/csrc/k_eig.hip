@@ -22,6 +22,9 @@
 // Eigenvectors with lambda > tau are selected, the constraint columns R z are
 // orthonormalised by modified Gram-Schmidt, and lambda is returned in
 // decreasing order.
+#include <cstdlib>
+#include <string>
+
 #include "dense.hpp"
 #include "kernels.hpp"
 
@@ -367,6 +370,313 @@ __global__ void __launch_bounds__(kNT) k_pair_eig(
   (void)nedge;
 }
 
+// ---------------------------------------------------------------------------
+// The same eigenproblem with one wave64 per edge: every phase is spread over
+// the 64 lanes and ordered by wave-level fences instead of workgroup barriers.
+// The cyclic Jacobi method keeps the round-robin ordering of disjoint pairs;
+// in each round a lane owns 2 x 2 blocks (row pair, column pair) of H and V
+// and applies both one-sided rotations to them at once, the rotation of pair
+// k being formed on the lane that owns the diagonal block (k, k).
+namespace {
+
+__device__ inline void wsync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ inline double wv_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ inline double wv_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// lower Cholesky of the n x n matrix A (ld n) in place, one wave
+__device__ void wv_potrf(double* A, int n, int* status) {
+  const int lane = threadIdx.x;
+  for (int j = 0; j < n; ++j) {
+    const double d = A[j + j * n];
+    const bool ok = d > 0.0 && d < 1e308;
+    if (!ok && lane == 0) flag_bad(status);
+    const double sq = ok ? sqrt(d) : 1.0;
+    const double inv = 1.0 / sq;
+    for (int i = j + 1 + lane; i < n; i += 64) A[i + j * n] *= inv;
+    wsync();
+    if (lane == 0) A[j + j * n] = sq;
+    const int w = n - j - 1;
+    for (ColWalk c(lane, 64, w); c.j < w; c.next())
+      if (c.i >= c.j) A[(j + 1 + c.i) + (j + 1 + c.j) * n] -= A[(j + 1 + c.i) + j * n] * A[(j + 1 + c.j) + j * n];
+    wsync();
+  }
+}
+
+// Round-robin ordering of disjoint pairs over m (even) indices: pair k of round r.
+__device__ inline void rr_pair(int k, int r, int m, int& p, int& q) {
+  const int a = (k == 0) ? 0 : ((k - 1 + r) % (m - 1)) + 1;
+  const int b = ((m - 1 - k - 1 + r) % (m - 1)) + 1;
+  p = min(a, b);
+  q = max(a, b);
+}
+
+}  // namespace
+
+__global__ void __launch_bounds__(64) k_pair_eig_wave(
+    const int32_t* __restrict__ edge_s, const int32_t* __restrict__ edge_t,
+    const int32_t* __restrict__ edge_nsc, const int32_t* __restrict__ edge_ne,
+    const int32_t* __restrict__ edge_fdof, const int32_t* __restrict__ edge_fptr,
+    const int32_t* __restrict__ inc_fptr, const int32_t* __restrict__ inc_fpos,
+    const int32_t* __restrict__ goff, const double* __restrict__ diagK,
+    const uint8_t* __restrict__ floating, const double* __restrict__ z,
+    const double* __restrict__ Shat, const double* __restrict__ Sff, const int64_t* __restrict__ inc_off,
+    double tau, double* __restrict__ lam_out, const int64_t* __restrict__ lamoff, double* __restrict__ Q,
+    const int64_t* __restrict__ qoff, int32_t* __restrict__ nsel_out, int32_t* __restrict__ nkept_out,
+    int* status) {
+  extern __shared__ double lds[];
+  const int e = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int s = edge_s[e], t = edge_t[e];
+  const int nsc = edge_nsc[e], ne = edge_ne[e];
+  const int nF = nsc + ne;
+  const int nv = nsc + 2 * ne;
+  const int inc_s = 2 * e, inc_t = 2 * e + 1;
+  const int32_t* fps = inc_fpos + inc_fptr[inc_s];
+  const int32_t* fpt = inc_fpos + inc_fptr[inc_t];
+  const double* Shs = Shat + inc_off[inc_s];
+  const double* Sht = Shat + inc_off[inc_t];
+  const double* Sfs = Sff + inc_off[inc_s];
+  const double* Sft = Sff + inc_off[inc_t];
+  const int m = ne + (ne & 1);
+  const int npair = m / 2;
+
+  double* Y = lds;                        // nv x nv
+  double* Xt = Y + (size_t)nv * nv;       // X^T: ne x nv (X = L^-1 B^T), entry (p, v) at p + v * ne
+  double* R = Xt + (size_t)nv * ne;       // ne x ne
+  double* G = R + (size_t)ne * ne;        // ne x ne, later the constraint columns
+  double* H = G + (size_t)ne * ne;        // ne x ne
+  double* V = H + (size_t)ne * ne;        // ne x ne
+  double* ds = V + (size_t)ne * ne;       // ne
+  double* dt = ds + ne;                   // ne
+  double* lam = dt + ne;                  // ne
+  double* q = lam + ne;                   // nv
+  int* perm = reinterpret_cast<int*>(q + nv);
+
+  for (int p = lane; p < ne; p += 64) {
+    const double a = diagK[goff[s] + fps[nsc + p]];
+    const double b = diagK[goff[t] + fpt[nsc + p]];
+    ds[p] = a / (a + b);
+    dt[p] = b / (a + b);
+  }
+  const bool both_float = floating[s] && floating[t];
+  if (both_float)
+    for (int i = lane; i < nv; i += 64) {
+      const int f = i < nsc ? i : (i < nsc + ne ? i : i - ne);
+      q[i] = z[edge_fdof[edge_fptr[e] + f]];
+    }
+  for (ColWalk w_(lane, 64, nv); w_.j < nv; w_.next()) {
+    const int vi = w_.i, vj = w_.j;
+    double y = 0.0;
+    if (vi < nF && vj < nF) y += Shs[vi + (size_t)vj * nF];
+    const int ti = vi < nsc ? vi : (vi >= nsc + ne ? vi - ne : -1);
+    const int tj = vj < nsc ? vj : (vj >= nsc + ne ? vj - ne : -1);
+    if (ti >= 0 && tj >= 0) y += Sht[ti + (size_t)tj * nF];
+    Y[vi + vj * nv] = y;
+  }
+  wsync();
+  if (both_float) {
+    // Y = M + a q q^T with a = max diag(M) / |q|^2
+    double nq = 0.0, amax = 0.0;
+    for (int i = lane; i < nv; i += 64) {
+      nq += q[i] * q[i];
+      amax = fmax(amax, Y[i + i * nv]);
+    }
+    nq = wv_sum(nq);
+    amax = wv_max(amax);
+    const double scale = amax / nq;
+    for (ColWalk w_(lane, 64, nv); w_.j < nv; w_.next()) Y[w_.i + w_.j * nv] += scale * q[w_.i] * q[w_.j];
+    wsync();
+  }
+  wv_potrf(Y, nv, status);
+  // X = L^{-1} B^T, B^T column p: +1 at the s-edge dof, -1 at the t-edge dof;
+  // row by row, the lanes over the columns p
+  // (each lane reads back only its own column)
+  for (int v = 0; v < nv; ++v)
+    for (int p = lane; p < ne; p += 64) {
+      double x = (v == nsc + p) ? 1.0 : ((v == nsc + ne + p) ? -1.0 : 0.0);
+      for (int k = 0; k < v; ++k) x -= Y[v + k * nv] * Xt[p + k * ne];
+      Xt[p + v * ne] = x / Y[v + v * nv];
+    }
+  wsync();
+  // N_e = D_t S_s,ee D_t + D_s S_t,ee D_s -> R;  G = X^T X
+  for (ColWalk w_(lane, 64, ne); w_.j < ne; w_.next()) {
+    const int i = w_.i, j = w_.j;
+    const double ss = Sfs[(nsc + i) + (size_t)(nsc + j) * nF];
+    const double tt = Sft[(nsc + i) + (size_t)(nsc + j) * nF];
+    R[i + j * ne] = dt[i] * ss * dt[j] + ds[i] * tt * ds[j];
+    double g = 0.0;
+    for (int v = 0; v < nv; ++v) g += Xt[i + v * ne] * Xt[j + v * ne];
+    G[i + j * ne] = g;
+  }
+  wsync();
+  wv_potrf(R, ne, status);
+  for (ColWalk w_(lane, 64, ne); w_.j < ne; w_.next())
+    if (w_.i < w_.j) R[w_.i + w_.j * ne] = 0.0;
+  wsync();
+  // V = G R, then H = R^T V (symmetrized), V = I
+  for (ColWalk w_(lane, 64, ne); w_.j < ne; w_.next()) {
+    const int i = w_.i, j = w_.j;
+    double acc = 0.0;
+    for (int k = j; k < ne; ++k) acc += G[i + k * ne] * R[k + j * ne];
+    V[i + j * ne] = acc;
+  }
+  wsync();
+  for (ColWalk w_(lane, 64, ne); w_.j < ne; w_.next()) {
+    const int i = w_.i, j = w_.j;
+    double acc = 0.0;
+    for (int k = i; k < ne; ++k) acc += R[k + i * ne] * V[k + j * ne];
+    H[i + j * ne] = acc;
+  }
+  wsync();
+  for (ColWalk w_(lane, 64, ne); w_.j < ne; w_.next()) {
+    const int i = w_.i, j = w_.j;
+    if (i > j) {
+      const double a = 0.5 * (H[i + j * ne] + H[j + i * ne]);
+      H[i + j * ne] = a;
+      H[j + i * ne] = a;
+    }
+  }
+  wsync();
+  for (ColWalk w_(lane, 64, ne); w_.j < ne; w_.next()) V[w_.i + w_.j * ne] = (w_.i == w_.j) ? 1.0 : 0.0;
+  wsync();
+
+  // cyclic Jacobi; lane handles blocks (k, l) = (b % npair, b / npair), b = lane, lane + 64, ...
+  const int nblk = npair * npair;
+  for (int sweep = 0; sweep < 60 && ne >= 2; ++sweep) {
+    double off = 0.0, dia = 0.0;
+    for (ColWalk w_(lane, 64, ne); w_.j < ne; w_.next()) {
+      const double h = H[w_.i + w_.j * ne];
+      if (w_.i == w_.j) dia += h * h; else off += h * h;
+    }
+    off = wv_sum(off);
+    dia = wv_sum(dia);
+    if (off <= 1e-30 * dia) break;
+    double* cs = G;   // rotation table in the (dead) G: cos at 2k, sin at 2k + 1
+    for (int r = 0; r < m - 1; ++r) {
+      // the rotation of every pair from its diagonal 2 x 2 block
+      for (int k = lane; k < npair; k += 64) {
+        int pk, qk;
+        rr_pair(k, r, m, pk, qk);
+        double c = 1.0, sn = 0.0;
+        if (qk < ne) {
+          const double hpq = H[pk + qk * ne];
+          if (fabs(hpq) > 1e-300) {
+            const double theta = (H[qk + qk * ne] - H[pk + pk * ne]) / (2.0 * hpq);
+            const double tt = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+            c = 1.0 / sqrt(tt * tt + 1.0);
+            sn = tt * c;
+          }
+        }
+        cs[2 * k] = c;
+        cs[2 * k + 1] = sn;
+      }
+      wsync();
+      // every 2 x 2 block (row pair k, column pair l) of H and V: rows by
+      // pair k, columns by pair l; blocks are disjoint, a lane stores only
+      // what it loaded
+      for (int b = lane; b < nblk; b += 64) {
+        const int k = b % npair, l = b / npair;
+        int pk, qk, pl, ql;
+        rr_pair(k, r, m, pk, qk);
+        rr_pair(l, r, m, pl, ql);
+        const bool rq = qk < ne, cq = ql < ne;   // an index >= ne is the padding of odd ne
+        const double ck = cs[2 * k], sk = cs[2 * k + 1], cl = cs[2 * l], sl = cs[2 * l + 1];
+        const double h00 = H[pk + pl * ne];
+        const double h01 = cq ? H[pk + ql * ne] : 0.0;
+        const double h10 = rq ? H[qk + pl * ne] : 0.0;
+        const double h11 = rq && cq ? H[qk + ql * ne] : 0.0;
+        const double v00 = V[pk + pl * ne];
+        const double v01 = cq ? V[pk + ql * ne] : 0.0;
+        const double v10 = rq ? V[qk + pl * ne] : 0.0;
+        const double v11 = rq && cq ? V[qk + ql * ne] : 0.0;
+        // rows: [h0.; h1.] <- [ck h0. - sk h1.; sk h0. + ck h1.]
+        const double a00 = ck * h00 - sk * h10, a01 = ck * h01 - sk * h11;
+        const double a10 = sk * h00 + ck * h10, a11 = sk * h01 + ck * h11;
+        // columns of H and V: [.0 .1] <- [cl .0 - sl .1, sl .0 + cl .1]
+        H[pk + pl * ne] = cl * a00 - sl * a01;
+        V[pk + pl * ne] = cl * v00 - sl * v01;
+        if (cq) {
+          H[pk + ql * ne] = sl * a00 + cl * a01;
+          V[pk + ql * ne] = sl * v00 + cl * v01;
+        }
+        if (rq) {
+          H[qk + pl * ne] = cl * a10 - sl * a11;
+          V[qk + pl * ne] = cl * v10 - sl * v11;
+        }
+        if (rq && cq) {
+          H[qk + ql * ne] = sl * a10 + cl * a11;
+          V[qk + ql * ne] = sl * v10 + cl * v11;
+        }
+      }
+      wsync();
+    }
+  }
+  // eigenvalues in decreasing order: rank by comparison (ties by index)
+  for (int i = lane; i < ne; i += 64) lam[i] = H[i + i * ne];
+  wsync();
+  for (int i = lane; i < ne; i += 64) {
+    int rank = 0;
+    for (int j = 0; j < ne; ++j) rank += (lam[j] > lam[i] || (lam[j] == lam[i] && j < i)) ? 1 : 0;
+    perm[rank] = i;
+  }
+  wsync();
+  double* lo = lam_out + lamoff[e];
+  for (int i = lane; i < ne; i += 64) lo[i] = lam[perm[i]];
+  int nsel = 0;
+  for (int i = 0; i < ne; ++i) nsel += (lam[i] > tau) ? 1 : 0;
+  // constraint columns c_k = R z_k, k < nsel (in G), then modified Gram-Schmidt
+  double* Cc = G;
+  for (ColWalk w_(lane, 64, ne); w_.j < nsel; w_.next()) {
+    const int i = w_.i, k = w_.j;
+    const double* zk = V + (size_t)perm[k] * ne;
+    double acc = 0.0;
+    for (int j = 0; j <= i; ++j) acc += R[i + j * ne] * zk[j];
+    Cc[i + k * ne] = acc;
+  }
+  wsync();
+  int kept = 0;
+  double maxnorm = 0.0;
+  for (int k = 0; k < nsel; ++k) {
+    double* ck = Cc + (size_t)k * ne;
+    for (int j = 0; j < kept; ++j) {
+      const double* qj = Cc + (size_t)j * ne;
+      double d = 0.0;
+      for (int i = lane; i < ne; i += 64) d += qj[i] * ck[i];
+      d = wv_sum(d);
+      for (int i = lane; i < ne; i += 64) ck[i] -= d * qj[i];
+      wsync();
+    }
+    double nn = 0.0;
+    for (int i = lane; i < ne; i += 64) nn += ck[i] * ck[i];
+    nn = sqrt(wv_sum(nn));
+    maxnorm = fmax(maxnorm, nn);
+    if (nn > 1e-10 * maxnorm && nn > 0.0) {
+      double* dst = Cc + (size_t)kept * ne;
+      for (int i = lane; i < ne; i += 64) dst[i] = ck[i] / nn;
+      ++kept;
+    }
+    wsync();
+  }
+  double* Qe = Q + qoff[e];
+  for (int idx = lane; idx < ne * nsel; idx += 64) Qe[idx] = idx < ne * kept ? Cc[idx] : 0.0;
+  if (lane == 0) {
+    nsel_out[e] = nsel;
+    nkept_out[e] = kept;
+  }
+}
+
 void launch_pair_schur(hipStream_t st, int ninc, int ngmax, const int32_t* inc_sub, const int32_t* inc_fptr,
                        const int32_t* inc_fpos, const int64_t* koff, const int32_t* loc_ptr,
                        const int32_t* nint, const double* K, const int64_t* inc_off, double* Shat,
@@ -395,6 +705,13 @@ void launch_pair_eig(hipStream_t st, int nedge, int nemax, int nvmax, const int3
                      const int64_t* lamoff, double* Q, const int64_t* qoff, int32_t* nsel, int32_t* nkept,
                      int* status) {
   if (nedge == 0) return;
+  const char* env = getenv("BDDC_EIG_PATH");
+  if (!(env && std::string(env) == "wg")) {
+    launch_kernel(k_pair_eig_wave, dim3(nedge), dim3(64), pair_eig_lds(nemax, nvmax), st, edge_s, edge_t, edge_nsc,
+                  edge_ne, edge_fdof, edge_fptr, inc_fptr, inc_fpos, goff, diagK, floating, z, Shat, Sff, inc_off, tau,
+                  lam, lamoff, Q, qoff, nsel, nkept, status);
+    return;
+  }
   launch_kernel(k_pair_eig, dim3(nedge), dim3(kNT), pair_eig_lds(nemax, nvmax), st, nedge, edge_s, edge_t,
                 edge_nsc, edge_ne, edge_fdof, edge_fptr, inc_fptr, inc_fpos, goff, diagK, floating, z, Shat, Sff,
                 inc_off, tau, lam, lamoff, Q, qoff, nsel, nkept, status);

@@ -118,13 +118,15 @@ def test_pcg_scalar_finalize(monkeypatch):
     assert np.array_equal(out["0"][0], out["1"][0])
 
 
-@pytest.mark.parametrize("path", ["default", "lds16_global", "sweep32"])
+@pytest.mark.parametrize("path", ["default", "lds16_global", "sweep32", "eig_workgroup"])
 def test_setup_kernel_paths(path, monkeypatch):
     """The setup runs with 64-wide Cholesky panels and a matrix-core trailing
     update plus LDS-resident Gauss-Jordan factorizations, and the level-1
     interior sweeps stream 64-column panels (default; 32-column panels,
     two workgroups per CU, on large grids); or with 16-wide panels on the
-    vector units, global-memory factorizations and 16-row blocked sweeps.  Both must give the oracle's preconditioner and solution (H/h = 16,
+    vector units, global-memory factorizations and 16-row blocked sweeps.
+    The pair eigenproblems run one wave per edge (default) or one
+    256-thread workgroup per edge.  Both must give the oracle's preconditioner and solution (H/h = 16,
     ragged 64-column panels)."""
     if path == "lds16_global":
         monkeypatch.setenv("BDDC_CHOL_PATH", "lds16")
@@ -132,6 +134,8 @@ def test_setup_kernel_paths(path, monkeypatch):
         monkeypatch.setenv("BDDC_SWEEP", "off")
     if path == "sweep32":
         monkeypatch.setenv("BDDC_SWEEP_BW", "32")
+    if path == "eig_workgroup":
+        monkeypatch.setenv("BDDC_EIG_PATH", "wg")
     prob = _case("adaptive3_h16")
     print(f"setup kernel path {path}", flush=True)
     S, B, ug, it, rr, o = run_pair(prob)
