@@ -186,6 +186,11 @@ size_t mark() {
   return recs.size();
 }
 
+bool active() {
+  std::lock_guard<std::mutex> lk(mu);
+  return !target.empty();
+}
+
 // drop the records from `from` on whose tag is >= limit: launches enqueued
 // after convergence return at once and move no data
 void prune(size_t from, int limit) {
@@ -411,6 +416,8 @@ struct bddc_ctx {
   bool coop_deep = false;
   bool coop_launch = false;   // use the cooperative launch API
   double coop_bytes = 0;      // algorithmic bytes of one launch
+  hipGraphExec_t graph_exec = nullptr;   // one chunk of PCG launches (captured on first use)
+  bool graph_off = false;
   bool wide_deep = false;     // one deep level in row-block launches (WideDev)
   bddc::WideDev wide;
   double wide_bytes = 0;      // algorithmic bytes of the four launches
@@ -1195,9 +1202,8 @@ class Builder {
 // Levels >= 2 run in full space with the explicit inverse of their interior
 // factors; level 1 runs in full space for bddc_apply and on the interface
 // inside bddc_solve.
-static void apply_deep_level(bddc_ctx* h, int li, const double* r, double* u) {
+static void apply_deep_level(bddc_ctx* h, int li, const double* r, double* u, hipStream_t st) {
   Level& lv = *h->levels[li];
-  hipStream_t st = h->stream;
   const std::string sfx = "_l" + std::to_string(li + 1);
   {
     timing::Scope ts(("apply_pre" + sfx).c_str(), lv.by_pre, 0);
@@ -1211,7 +1217,7 @@ static void apply_deep_level(bddc_ctx* h, int li, const double* r, double* u) {
   if (li + 1 == (int)h->levels.size())
     launch_coarsest_solve(st, lv.nc, h->AL, lv.d.rc, lv.d.uc, lv.dev.stop);
   else
-    apply_deep_level(h, li + 1, lv.d.rc, lv.d.uc);
+    apply_deep_level(h, li + 1, lv.d.rc, lv.d.uc, st);
   {
     timing::Scope ts(("apply_prolong" + sfx).c_str(), lv.by_prolong, 0);
     launch_apply_prolong(st, lv.dev, lv.ncsmax, lv.d.uc);
@@ -1223,9 +1229,8 @@ static void apply_deep_level(bddc_ctx* h, int li, const double* r, double* u) {
 }
 
 // level-1 coarse right-hand side (the level-1 b) -> level-1 coarse solution (level-1 uc)
-static void run_deep(bddc_ctx* h) {
+static void run_deep(bddc_ctx* h, hipStream_t st) {
   Level& l1 = *h->levels[0];
-  hipStream_t st = h->stream;
   if (h->levels.size() == 1) {
     launch_coarse_gather(st, l1.nc, l1.d.csh_ptr, l1.d.csh_flat, l1.d.b, l1.d.rc, l1.dev.stop);
     launch_coarsest_solve(st, l1.nc, h->AL, l1.d.rc, l1.d.uc, l1.dev.stop);
@@ -1259,7 +1264,7 @@ static void run_deep(bddc_ctx* h) {
     return;
   }
   launch_coarse_gather(st, l1.nc, l1.d.csh_ptr, l1.d.csh_flat, l1.d.b, l1.d.rc, l1.dev.stop);
-  apply_deep_level(h, 1, l1.d.rc, l1.d.uc);
+  apply_deep_level(h, 1, l1.d.rc, l1.d.uc, st);
 }
 
 // full-space preconditioner of the level-1 problem (bddc_apply)
@@ -1272,7 +1277,7 @@ static void apply_full(bddc_ctx* h, const double* r, double* u) {
   else
     launch_apply_pre(st, l1.dev, l1.nImax, l1.ngmax, r);
   launch_apply_restrict(st, l1.dev, l1.ngmax, r, l1.d.gam_gid, 1);
-  run_deep(h);
+  run_deep(h, st);
   launch_apply_prolong(st, l1.dev, l1.ncsmax, l1.d.uc);
   if (sweep)
     launch_sweep_post(st, l1.dev, u, l1.d.gam_gid);
@@ -1367,8 +1372,20 @@ static bool plan_coop(bddc_ctx* h) {
   const size_t lds = coop_lds(C);
   if (lds > kLdsMax) return false;
   if (coop_max_blocks(lds) < nsub) return false;
+  std::vector<int64_t> kioff(nsub + 1, 0), moff(nsub + 1, 0);
+  int nmax_ops = 0;
+  for (int s = 0; s < nsub; ++s) {
+    const int64_t nI = T.n_int[s], ng = T.ngam(s);
+    kioff[s + 1] = kioff[s] + nI * nI;
+    moff[s + 1] = moff[s] + nI * ng;
+    nmax_ops = std::max<int>(nmax_ops, (int)(nI * nI + nI * ng));
+  }
   Arena& A = h->coop_arena;
   auto lay = [&] {
+    C.Kinv = A.take<double>(std::max<int64_t>(1, kioff[nsub]));
+    C.kioff = A.take<int64_t>(nsub + 1);
+    C.Mt = A.take<double>(std::max<int64_t>(1, moff[nsub]));
+    C.moff = A.take<int64_t>(nsub + 1);
     C.ops = A.take<double>((size_t)opoff[nsub]);
     C.opoff = A.take<int64_t>(nsub + 1);
     C.idx = A.take<int32_t>(idx.size());
@@ -1391,8 +1408,11 @@ static bool plan_coop(bddc_ctx* h) {
   stg.add(const_cast<int32_t*>(C.meta), meta);
   stg.add(const_cast<int32_t*>(C.cg), cg);
   stg.add(const_cast<int32_t*>(C.sub_of_flat), sub_of_flat);
+  stg.add(const_cast<int64_t*>(C.kioff), kioff);
+  stg.add(const_cast<int64_t*>(C.moff), moff);
   stg.flush();
   BDDC_HIP(hipMemsetAsync(C.bar, 0, 2 * sizeof(unsigned), st));
+  launch_wide_ops(st, lv.dev, nmax_ops, const_cast<double*>(C.Kinv), C.kioff, const_cast<double*>(C.Mt), C.moff);
   launch_pack_coop(st, lv.dev, C);
   launch_tri_inverse_dense(st, h->AL, ncL, ncL, const_cast<double*>(C.LLinv));
   C.b1 = l1.d.b;
@@ -1577,6 +1597,60 @@ static double lanczos_kappa(const std::vector<double>& al, const std::vector<dou
   return mn > 0 ? mx / mn : 0.0;
 }
 
+// One chunk of PCG launches as a HIP graph, captured on first use and kept by
+// the handle (its launches have fixed arguments).  Not while kernel timing is
+// armed (its events cannot be captured), nor with BDDC_PCG_GRAPH=0; returns
+// false when the chunk must be launched directly.
+template <class F>
+static bool graph_chunk(bddc_ctx* h, hipStream_t st, F&& enqueue) {
+  if (h->graph_off || timing::active()) return false;
+  if (!h->graph_exec) {
+    const char* env = getenv("BDDC_PCG_GRAPH");
+    if (env && std::string(env) == "0") {
+      h->graph_off = true;
+      return false;
+    }
+    // captured on a stream of the library's own (the caller's may be the
+    // null stream, which cannot be captured); replayed on the caller's
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      (void)hipGetLastError();
+      if (cs) (void)hipStreamDestroy(cs);
+      h->graph_off = true;
+      return false;
+    }
+    hipGraph_t g = nullptr;
+    try {
+      enqueue(cs);
+    } catch (...) {
+      (void)hipStreamEndCapture(cs, &g);
+      if (g) (void)hipGraphDestroy(g);
+      (void)hipStreamDestroy(cs);
+      (void)hipGetLastError();
+      throw;
+    }
+    const hipError_t e1 = hipStreamEndCapture(cs, &g);
+    (void)hipStreamDestroy(cs);
+    hipGraphExec_t ex = nullptr;
+    const hipError_t e2 = (e1 == hipSuccess && g) ? hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) : e1;
+    size_t nodes = 0;
+    if (g) (void)hipGraphGetNodes(g, nullptr, &nodes);
+    if (g) (void)hipGraphDestroy(g);
+    if (getenv("BDDC_HOST_TIMING"))
+      fprintf(stderr, "libbddc pcg graph: %s (%zu nodes)\n", e2 == hipSuccess ? "captured" : hipGetErrorString(e2),
+              nodes);
+    if (e2 != hipSuccess || !ex) {
+      (void)hipGetLastError();
+      h->graph_off = true;
+      return false;
+    }
+    h->graph_exec = ex;
+  }
+  BDDC_HIP(hipGraphLaunch(h->graph_exec, st));
+  return true;
+}
+
 static int pcg_one(bddc_ctx* h, const double* f, double* u, double rtol, int maxit, double* relres) {
   hipStream_t st = h->stream;
   Level& l1 = *h->levels[0];
@@ -1587,6 +1661,7 @@ static int pcg_one(bddc_ctx* h, const double* f, double* u, double rtol, int max
   std::memset(sch, 0, offsetof(PcgScalars, alphas));
   sch->maxit = maxit;
   sch->rtol2 = rtol * rtol;   // thr2 = rtol^2 ||f||^2 is formed on the device
+  sch->it_base = 1;
   BDDC_HIP(hipMemcpyAsync(h->sc, sch, offsetof(PcgScalars, alphas), hipMemcpyHostToDevice, st));
   launch_dot_partial(st, nbf, (int)h->n_free, f, f, h->partial);
   launch_scalar(st, 4, nbf, h->partial, h->sc);                   // bb, thr2 = rtol^2 bb
@@ -1614,38 +1689,47 @@ static int pcg_one(bddc_ctx* h, const double* f, double* u, double rtol, int max
   // Iteration k: matvec, update + restriction, deep levels, prolongation with
   // the convergence test, post.  The test sits in the prolongation, so at the
   // converged iteration K the update, restriction and deep levels still run
-  // (tagged k - 1: they work iff k <= K) and the rest return at once.
-  auto apply_iface = [&](int it) {
+  // (tagged k - 1: they work iff k <= K) and the rest return at once.  The
+  // kernels take their iteration as sc->it_base + u (u < 0: iteration 0), so
+  // one chunk of launches is the same for every chunk and can be replayed as a
+  // HIP graph.
+  auto apply_iface = [&](hipStream_t q, int u, int it) {
     timing::current_tag = it - 1;
     {
       timing::Scope ts("apply_restrict", it > 0 ? h->by_ur_prec : h->by_r_prec, 0);
-      launch_pcg_update_restrict(st, l1.dev, l1.ngmax, l1.nrmax, l1.ncsmax, P, it);
+      launch_pcg_update_restrict(q, l1.dev, l1.ngmax, l1.nrmax, l1.ncsmax, P, u);
     }
-    if (P.fin && it > 0) launch_pcg_sum(st, P, P.rr_part, P.nsub1, &P.sc->rrs);
-    run_deep(h);
+    if (P.fin && it > 0) launch_pcg_sum(q, P, 1, u);
+    run_deep(h, q);
     timing::current_tag = it;
     {
       timing::Scope ts("apply_average", h->by_average, 0);
-      launch_pcg_prolong_post(st, l1.dev, P, l1.d.uc, it > 0 ? 1 : 0, it & 1);
+      launch_pcg_prolong_post(q, l1.dev, P, l1.d.uc, u);
     }
-    if (P.fin) launch_pcg_sum(st, P, P.rz_part[it & 1], P.nblk, &P.sc->rzs[it & 1]);
+    if (P.fin) launch_pcg_sum(q, P, 2, u);
   };
-  // z_0 = M r_0 and its r.z partials (parity 0)
-  apply_iface(0);
-  int it = 0;
-  int check = 8;
-  while (it < maxit) {
-    for (int k = 0; k < check && it < maxit; ++k) {
-      ++it;
+  const int check = 8;   // iterations between host convergence checks
+  auto chunk = [&](hipStream_t q, int it0) {
+    for (int u = 0; u < check; ++u) {
+      const int it = it0 + u;
       timing::current_tag = it;
       {
         // the product of iteration k works iff k <= K (K = converged iteration)
         timing::Scope ts("schur_local", l1.by_schur, 0, -1);
-        launch_pcg_matvec(st, l1.dev, l1.ngmax, P, it);
+        launch_pcg_matvec(q, l1.dev, l1.ngmax, P, u);
       }
-      if (P.fin) launch_pcg_sum(st, P, P.pq_part, P.nsub1, &P.sc->pqs);
-      apply_iface(it);
+      if (P.fin) launch_pcg_sum(q, P, 0, u);
+      apply_iface(q, u, it);
     }
+    launch_pcg_advance(q, P, check);
+  };
+  // z_0 = M r_0 and its r.z partials (parity 0)
+  apply_iface(st, -1, 0);
+  int it = 0;
+  while (it < maxit) {
+    // iterations past maxit or convergence return at once (sc->done)
+    if (!graph_chunk(h, st, [&](hipStream_t q) { chunk(q, it + 1); })) chunk(st, it + 1);
+    it += check;
     BDDC_HIP(hipMemcpyAsync(sch, h->sc, offsetof(PcgScalars, alphas), hipMemcpyDeviceToHost, st));
     BDDC_HIP(hipStreamSynchronize(st));
     if (sch->done) break;
@@ -1735,6 +1819,8 @@ void release(bddc_ctx* h) {
   h->top.release(st);
   h->coop_arena.release(st);
   h->wide_arena.release(st);
+  if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+  h->graph_exec = nullptr;
   pinned_release(h->sc_host);
   for (void* b : h->staged) pinned_release(b);
   delete h;   // the pool frees above are stream-ordered

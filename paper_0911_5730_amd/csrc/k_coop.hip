@@ -97,8 +97,8 @@ __global__ void __launch_bounds__(kCoopNT) k_deep_coop(CoopDev C) {
   const int ncL = C.ncL;
   (void)me[8];
   // LDS: operator block | vectors | coarsest inverse factor | ints
-  double* Li = sh;                                   // nI x nI
-  double* G = Li + (size_t)nI * nI;                  // ng x nI
+  double* Li = sh;                                   // K_II^-1, nI x nI
+  double* G = Li + (size_t)nI * nI;                  // M^T = (K_GI K_II^-1)^T, nI x ng
   double* Tm = G + (size_t)ng * nI;                  // nr x nr
   double* Ps = Tm + (size_t)nr * nr;                 // ng x ncs
   double* dl = Ps + (size_t)ng * ncs;                // ng
@@ -182,10 +182,13 @@ __global__ void __launch_bounds__(kCoopNT) k_deep_coop(CoopDev C) {
     else rG[p - nI] = acc;
   }
   __syncthreads();
-  // interior correction: y = Linv r_I, t = L_GI y   (ML-uIi, ML-rBi)
-  mv8(nI, Li, 1, nI, rI, [](int) { return 0; }, [](int i) { return i + 1; }, [&](int i, double v) { y[i] = v; });
-  __syncthreads();
-  mv8(ng, G, 1, ng, y, [](int) { return 0; }, [&](int) { return nI; }, [&](int a, double v) { C.t[goff + a] = v; });
+  // interior correction (ML-uIi, ML-rBi): y = K_II^-1 r_I and t = K_GI K_II^-1 r_I
+  // in one pass: row rho of [K_II^-1 ; M] is column rho of [K_II^-1  M^T]
+  mv8(nI + ng, Li, nI, 1, rI, [](int) { return 0; }, [&](int) { return nI; },
+      [&](int i, double v) {
+        if (i < nI) y[i] = v;
+        else C.t[goff + i - nI] = v;
+      });
   grid_barrier(C.bar, gridDim.x, C.status);
   // g = delta (r_G - sum t);  a = T_rr g_r (ML-wDi);  b = Psi^T g (ML-coarse)
   for (int a = tid; a < ng; a += kCoopNT) {
@@ -226,11 +229,9 @@ __global__ void __launch_bounds__(kCoopNT) k_deep_coop(CoopDev C) {
       },
       phi_ids);
   __syncthreads();
-  // u_I = Linv^T (y - L_GI^T u_B)   (ML-vIi, ML-ui)
-  mv8(nI, G, ng, 1, uB, [](int) { return 0; }, [&](int) { return ng; }, [&](int j, double v) { yv[j] = y[j] - v; });
-  __syncthreads();
-  mv8(nI, Li, nI, 1, yv, [](int i) { return i; }, [&](int) { return nI; },
-      [&](int i, double v) { C.u2[int_gid[i]] = v; });
+  // u_I = K_II^-1 (r_I - K_IG u_B) = y - M^T u_B   (ML-vIi, ML-ui)
+  mv8(nI, G, 1, nI, uB, [](int) { return 0; }, [&](int) { return ng; },
+      [&](int i, double v) { C.u2[int_gid[i]] = y[i] - v; });
 }
 
 size_t coop_lds(const CoopDev& C) {
@@ -279,17 +280,13 @@ __global__ void __launch_bounds__(kNT) k_pack_coop(LevelDev L, CoopDev C) {
   const int nI = me[0], ng = me[1], nr = me[2], ncs = me[3];
   const int n = nI + ng;
   double* o = const_cast<double*>(C.ops) + C.opoff[s];
-  const double* K = L.K + L.koff[s];
-  const double* Li = L.Linv + L.linvoff[s];
+  const double* Ki = C.Kinv + C.kioff[s];
+  const double* Mt = C.Mt + C.moff[s];
   const double* T = L.T + L.toff[s];
   const double* P = L.Psi + L.psioff[s];
-  for (int idx = threadIdx.x; idx < nI * nI; idx += kNT) o[idx] = Li[idx];
+  for (int idx = threadIdx.x; idx < nI * nI; idx += kNT) o[idx] = Ki[idx];
   o += (size_t)nI * nI;
-  for (ColWalk w_(threadIdx.x, kNT, ng); w_.j < nI; w_.next()) {
-    const int a = w_.i, j = w_.j;
-    [[maybe_unused]] const int idx = a + j * ng;
-    o[idx] = K[nI + a + (size_t)j * n];
-  }
+  for (int idx = threadIdx.x; idx < nI * ng; idx += kNT) o[idx] = Mt[idx];
   o += (size_t)ng * nI;
   for (int idx = threadIdx.x; idx < nr * nr; idx += kNT) o[idx] = T[idx];
   o += (size_t)nr * nr;

@@ -280,14 +280,26 @@ __device__ inline double block_sum_of(const double* __restrict__ v, int n, doubl
 }
 
 // One block: the sum of n partials in the order of block_sum_of (bitwise the
-// same value) into *out.  With many blocks on both sides this replaces every
-// consuming block's own pass over all the partials.
-__global__ void __launch_bounds__(kNT) k_pcg_sum(const PcgScalars* __restrict__ sc, const double* __restrict__ part,
-                                                 int n, double* __restrict__ out) {
+// same value) into the scalar `which` (0 p^T S p, 1 r.r, 2 r.z of iteration
+// it).  With many blocks on both sides this replaces every consuming block's
+// own pass over all the partials.
+__global__ void __launch_bounds__(kNT) k_pcg_sum(PcgDev P, int which, int u) {
   __shared__ double red[kNT];
-  if (sc->done) return;
+  if (P.sc->done) return;
+  const int it = u < 0 ? 0 : P.sc->it_base + u;
+  const double* part = which == 0 ? P.pq_part : (which == 1 ? P.rr_part : P.rz_part[it & 1]);
+  const int n = which == 2 ? P.nblk : P.nsub1;
   const double v = block_sum_of(part, n, red);
-  if (threadIdx.x == 0) *out = v;
+  if (threadIdx.x == 0) {
+    if (which == 0) P.sc->pqs = v;
+    else if (which == 1) P.sc->rrs = v;
+    else P.sc->rzs[it & 1] = v;
+  }
+}
+
+// the next chunk of PCG launches starts n iterations later
+__global__ void k_pcg_advance(PcgScalars* sc, int n) {
+  if (threadIdx.x == 0) sc->it_base += n;
 }
 
 // PCG iteration k on the level-1 interface (Section 5) in four launches:
@@ -304,10 +316,11 @@ __global__ void __launch_bounds__(kNT) k_pcg_sum(const PcgScalars* __restrict__ 
 // r_{k-1} while owners write r_k.  The average uses, per interface dof, the
 // sharers' rows of the delta-weighted coarse basis (built at setup), so the
 // prolongation needs no pass of its own.
-__global__ void __launch_bounds__(kNT) k_pcg_matvec(LevelDev L, PcgDev P, int it) {
+__global__ void __launch_bounds__(kNT) k_pcg_matvec(LevelDev L, PcgDev P, int u) {
   extern __shared__ double sh[];
   __shared__ double red[kNT];
   if (P.sc->done) return;
+  const int it = P.sc->it_base + u;
   const int s = blockIdx.x;
   const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
   const int nI = L.nint[s];
@@ -450,13 +463,14 @@ __device__ inline int packed_col(int j, int m) { return j * m - (j * (j - 1)) / 
 //   Factored BF16 form: x = D^-1 g_r, v = W x, v = (I - Q Q^T)^2 v, y = W^T v,
 //   T_rr g_r = D^-1 y, with W staged in LDS (two passes over it).
 template <int kPrec>
-__global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev P, int it, int nrmax, int ngmax,
+__global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev P, int u, int nrmax, int ngmax,
                                                              int ncsmax) {
   using TS = typename PrecForm<kPrec>::TS;
   using PS = typename PrecForm<kPrec>::PS;
   extern __shared__ double sh[];
   __shared__ double red[kNT];
   if (P.sc->done) return;
+  const int it = u < 0 ? 0 : P.sc->it_base + u;
   const int s = blockIdx.x;
   const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
   const int ng = n - L.nint[s];
@@ -749,9 +763,12 @@ __global__ void __launch_bounds__(kNT) k_round_factors(LevelDev L, PcgDev P, int
 // the dof's row of the delta-weighted coarse basis times u_c  (ML-uBi-1), and
 // the per-block partial of r_k . z.
 __global__ void __launch_bounds__(kNT) k_pcg_prolong_post(LevelDev L, PcgDev P, const double* __restrict__ uc,
-                                                          int check, int parity) {
+                                                          int u) {
   __shared__ double red[kNT];
   if (P.sc->done) return;
+  const int it = u < 0 ? 0 : P.sc->it_base + u;
+  const bool check = it > 0;
+  const int parity = it & 1;
   if (check) {
     const double rr = P.fin ? P.sc->rrs : block_sum_of(P.rr_part, P.nsub1, red);
     const bool conv = rr <= P.sc->thr2;
@@ -810,26 +827,29 @@ __global__ void __launch_bounds__(kNT) k_build_phi(LevelDev L, int nif, const in
   }
 }
 
-void launch_pcg_matvec(hipStream_t st, const LevelDev& L, int ngmax, const PcgDev& P, int it) {
+void launch_pcg_matvec(hipStream_t st, const LevelDev& L, int ngmax, const PcgDev& P, int u) {
   const size_t lds = sizeof(double) * ((size_t)ngmax + kNT + ngmax);
-  launch_kernel(k_pcg_matvec, dim3(L.nsub), dim3(kNT), lds, st, L, P, it);
+  launch_kernel(k_pcg_matvec, dim3(L.nsub), dim3(kNT), lds, st, L, P, u);
 }
-void launch_pcg_sum(hipStream_t st, const PcgDev& P, const double* part, int n, double* out) {
-  launch_kernel(k_pcg_sum, dim3(1), dim3(kNT), 0, st, P.sc, part, n, out);
+void launch_pcg_sum(hipStream_t st, const PcgDev& P, int which, int u) {
+  launch_kernel(k_pcg_sum, dim3(1), dim3(kNT), 0, st, P, which, u);
+}
+void launch_pcg_advance(hipStream_t st, const PcgDev& P, int n) {
+  launch_kernel(k_pcg_advance, dim3(1), dim3(64), 0, st, P.sc, n);
 }
 void launch_pcg_update_restrict(hipStream_t st, const LevelDev& L, int ngmax, int nrmax, int ncsmax, const PcgDev& P,
-                                int it) {
+                                int u) {
   // doubles: g | part | x/v ; floats: packed W | Q | D^-1 (factored form only)
   size_t lds = sizeof(double) * ((size_t)ngmax + kNT + ngmax);
   if (P.prec == 2)
     lds += sizeof(double) * nrmax +
            sizeof(float) * ((size_t)nrmax * (nrmax + 1) / 2 + (size_t)nrmax * ncsmax + nrmax);
   if (P.prec == 0)
-    launch_kernel(k_pcg_update_restrict<0>, dim3(L.nsub), dim3(kNT), lds, st, L, P, it, nrmax, ngmax, ncsmax);
+    launch_kernel(k_pcg_update_restrict<0>, dim3(L.nsub), dim3(kNT), lds, st, L, P, u, nrmax, ngmax, ncsmax);
   else if (P.prec == 1)
-    launch_kernel(k_pcg_update_restrict<1>, dim3(L.nsub), dim3(kNT), lds, st, L, P, it, nrmax, ngmax, ncsmax);
+    launch_kernel(k_pcg_update_restrict<1>, dim3(L.nsub), dim3(kNT), lds, st, L, P, u, nrmax, ngmax, ncsmax);
   else
-    launch_kernel(k_pcg_update_restrict<2>, dim3(L.nsub), dim3(kNT), lds, st, L, P, it, nrmax, ngmax, ncsmax);
+    launch_kernel(k_pcg_update_restrict<2>, dim3(L.nsub), dim3(kNT), lds, st, L, P, u, nrmax, ngmax, ncsmax);
 }
 void launch_round_factors(hipStream_t st, const LevelDev& L, const PcgDev& P, int nrmax, int ncrmax, const double* Cr,
                           int* status) {
@@ -837,9 +857,8 @@ void launch_round_factors(hipStream_t st, const LevelDev& L, const PcgDev& P, in
   const size_t lds = P.prec == 2 ? sizeof(double) * (2 * (size_t)nrmax * nrmax + 2 * (size_t)nrmax * ncrmax + nrmax) : 0;
   launch_kernel(k_round_factors, dim3(L.nsub), dim3(kNT), lds, st, L, P, nrmax, ncrmax, Cr, status);
 }
-void launch_pcg_prolong_post(hipStream_t st, const LevelDev& L, const PcgDev& P, const double* uc, int check,
-                            int parity) {
-  launch_kernel(k_pcg_prolong_post, dim3(P.nblk), dim3(kNT), 0, st, L, P, uc, check, parity);
+void launch_pcg_prolong_post(hipStream_t st, const LevelDev& L, const PcgDev& P, const double* uc, int u) {
+  launch_kernel(k_pcg_prolong_post, dim3(P.nblk), dim3(kNT), 0, st, L, P, uc, u);
 }
 void launch_build_phi(hipStream_t st, const LevelDev& L, int nif, const int32_t* sub_of_flat, const int32_t* phi_ptr,
                       int32_t* phi_ids, double* phi_w, const float* psi32) {

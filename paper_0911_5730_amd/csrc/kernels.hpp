@@ -107,8 +107,12 @@ struct CoopDev {
   int opmax = 0;                      // largest operator block (doubles)
   int idxmax = 0;                     // largest index block (ints)
   int cg_len = 0;                     // coarse gather block (ints)
-  // per substructure: Linv | L_GI (ng x nI) | T_rr | Psi | delta | phi weights
+  // per substructure: K_II^-1 | M^T (nI x ng) | T_rr | Psi | delta | phi weights
   const double* ops = nullptr;
+  const double* Kinv = nullptr;       // setup only: K_II^-1 and M^T to pack (as in WideDev)
+  const int64_t* kioff = nullptr;
+  const double* Mt = nullptr;
+  const int64_t* moff = nullptr;
   const int64_t* opoff = nullptr;
   // per substructure: int_gid | gam_gid | own | shp | shf | gp | gf | cid | phi_ptr | phi_ids
   const int32_t* idx = nullptr;
@@ -206,6 +210,8 @@ constexpr int kMaxHist = 4096;
 struct PcgScalars {
   double rz, pq, alpha, beta, rr, bb, thr2, rtol2;
   double rzs[2], pqs, rrs;   // summed partials of the fused iteration (r.z by parity, p^T S p, r.r)
+  int32_t it_base;           // PCG iteration of offset 0 in the launches of the current chunk
+  int32_t pad2;
   int32_t iters, maxit, done, pad;
   double alphas[kMaxHist];
   double betas[kMaxHist];
@@ -306,14 +312,16 @@ void launch_apply_pre_inv(hipStream_t st, const LevelDev& L, int nImax, int ngma
 void launch_apply_post_inv(hipStream_t st, const LevelDev& L, int nImax, int ngmax, double* u);
 
 // fused PCG iteration kernels (level-1 interface)
-void launch_pcg_matvec(hipStream_t st, const LevelDev& L, int ngmax, const PcgDev& P, int it);
-void launch_pcg_sum(hipStream_t st, const PcgDev& P, const double* part, int n, double* out);
+void launch_pcg_matvec(hipStream_t st, const LevelDev& L, int ngmax, const PcgDev& P, int u);
+// which: 0 p^T S p (-> pqs), 1 r.r (-> rrs), 2 r.z of iteration it (-> rzs[it & 1]);
+// iteration numbers are it = sc->it_base + u, or 0 for u < 0
+void launch_pcg_sum(hipStream_t st, const PcgDev& P, int which, int u);
+void launch_pcg_advance(hipStream_t st, const PcgDev& P, int n);
 void launch_round_factors(hipStream_t st, const LevelDev& L, const PcgDev& P, int nrmax, int ncrmax, const double* Cr,
                           int* status);
 void launch_pcg_update_restrict(hipStream_t st, const LevelDev& L, int ngmax, int nrmax, int ncsmax, const PcgDev& P,
-                                int it);
-void launch_pcg_prolong_post(hipStream_t st, const LevelDev& L, const PcgDev& P, const double* uc, int check,
-                            int parity);
+                                int u);
+void launch_pcg_prolong_post(hipStream_t st, const LevelDev& L, const PcgDev& P, const double* uc, int u);
 void launch_build_phi(hipStream_t st, const LevelDev& L, int nif, const int32_t* sub_of_flat, const int32_t* phi_ptr,
                       int32_t* phi_ids, double* phi_w, const float* psi32);
 

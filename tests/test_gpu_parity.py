@@ -118,6 +118,43 @@ def test_pcg_scalar_finalize(monkeypatch):
     assert np.array_equal(out["0"][0], out["1"][0])
 
 
+@pytest.mark.parametrize("deep", ["coop", "wide"])
+def test_pcg_graph_replays_match_direct_launches(deep, monkeypatch):
+    """The PCG iterations run as replays of one captured chunk of launches
+    (a HIP graph; the kernels read their iteration number on the device).
+    Every replay must give what launching the same kernels directly gives:
+    two solves with the graph (several replays each, host synchronisation
+    between them) against one without, bitwise, and the oracle's solution."""
+    prob = _case("adaptive3")
+    monkeypatch.setenv("BDDC_DEEP_PATH", deep)
+    monkeypatch.setenv("BDDC_PCG_FINALIZE", "1")
+    import paper_0911_5730_amd as P
+    f = cuda_vec(prob.f[0])
+    monkeypatch.setenv("BDDC_PCG_GRAPH", "0")
+    S0 = P.Solver(prob)
+    try:
+        u0, it0, _ = S0.solve(f, rtol=1e-10)
+        u0 = u0.cpu().numpy()
+    finally:
+        S0.close()
+    monkeypatch.delenv("BDDC_PCG_GRAPH")
+    print(f"graph replays, deep path {deep}", flush=True)
+    S1 = P.Solver(prob)
+    try:
+        for rep in range(2):
+            u1, it1, _ = S1.solve(f, rtol=1e-10)
+            assert it1[0] == it0[0]
+            assert np.array_equal(u1.cpu().numpy(), u0), rep
+    finally:
+        S1.close()
+    S, B, ug, it, rr, o = run_pair(prob)
+    try:
+        assert abs(it - o["iters"]) <= 1
+        check_solution(S, B, ug, o)
+    finally:
+        S.close()
+
+
 @pytest.mark.parametrize("path", ["default", "lds16_global", "sweep32", "eig_workgroup"])
 def test_setup_kernel_paths(path, monkeypatch):
     """The setup runs with 64-wide Cholesky panels and a matrix-core trailing
