@@ -154,6 +154,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"],
+                    help="storage of the level-1 preconditioner operators in the timed steps")
     ap.add_argument("--roofline-kernel", default="deep",
                     help="library kernel timed for the roofline (default: the one with the largest share of a step)")
     ap.add_argument("--sample-every", type=int, default=8,
@@ -193,7 +195,7 @@ def main():
     stream = torch.cuda.current_stream()
 
     def step():
-        S = P.Solver(prob, coeff=coeff, stream=stream)
+        S = P.Solver(prob, coeff=coeff, stream=stream, precision=args.precision)
         _, it, rr = S.solve(f, u=u, rtol=prob.rtol, stream=stream)
         info = S.info()
         S.close()
@@ -222,7 +224,7 @@ def main():
     log(f"bench: {args.steps} steps in {elapsed:.3f} s, iterations {iters[0]}, relres {rr:.2e}")
 
     # ---- solve-only, apply-only and setup-only rates (outside the timed region)
-    S = P.Solver(prob, coeff=coeff, stream=stream)
+    S = P.Solver(prob, coeff=coeff, stream=stream, precision=args.precision)
     S.solve(f, u=u)
     torch.cuda.synchronize()
     ns = max(5, args.steps)
@@ -246,7 +248,7 @@ def main():
     P.timing_start("partial_chol", 1)
     su0 = time.perf_counter()
     for _ in range(ns):
-        P.Solver(prob, coeff=coeff, stream=stream).close()
+        P.Solver(prob, coeff=coeff, stream=stream, precision=args.precision).close()
     torch.cuda.synchronize()
     setup_s = (time.perf_counter() - su0) / ns
     tch = P.timing_stop()
@@ -289,7 +291,7 @@ def main():
         "data": "synthetic (seeded coefficient field, partition and load)",
         "config": {"workload": workload + ": " + synth.CONFIG_NAMES[args.config], "n_free": prob.n_free,
                    "substructures": prob.nsub, "levels": prob.levels, "tau": prob.tau,
-                   "precision": "fp64", "rtol": prob.rtol, "step": "setup + PCG solve + destroy"},
+                   "precision": args.precision, "rtol": prob.rtol, "step": "setup + PCG solve + destroy"},
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
         "solve_only_per_s": 1.0 / solve_s,
         "applies_per_s": 1.0 / apply_s,

@@ -29,6 +29,10 @@ constexpr int kSweepNT = 512;              // 8 waves: the prefetch stays within
 constexpr int kSweepRows = 304;            // largest n handled here (LDS: 8 (304 + 304 * 64) B < 160 KiB)
 template <int BW>
 constexpr int kRegs = (kSweepRows * BW + kSweepNT - 1) / kSweepNT;   // prefetched doubles per thread
+// minimum waves per SIMD the register allocation must allow (32-wide: four,
+// i.e. two 8-wave workgroups per CU, at most 128 VGPRs per thread)
+template <int BW>
+constexpr int kSweepBlocks = BW == 32 ? 4 : 1;
 
 // value of v on lane `lane` (uniform) through the scalar unit
 __device__ inline double lane_value(double v, int lane) {
@@ -75,7 +79,7 @@ __device__ inline void panel_store(double* P, const Panel& p, const double (&r)[
 }
 
 template <int BW>
-__device__ void sweep_fwd(const double* __restrict__ A, int n, int nI, double* w, double* P) {
+__device__ __forceinline__ void sweep_fwd(const double* __restrict__ A, int n, int nI, double* w, double* P) {
   const int tid = threadIdx.x;
   const int nb = (nI + BW - 1) / BW;
   double r[kRegs<BW>];
@@ -118,7 +122,7 @@ __device__ void sweep_fwd(const double* __restrict__ A, int n, int nI, double* w
 }
 
 template <int BW>
-__device__ void sweep_bwd(const double* __restrict__ A, int n, int nI, double* w, double* P) {
+__device__ __forceinline__ void sweep_bwd(const double* __restrict__ A, int n, int nI, double* w, double* P) {
   const int tid = threadIdx.x;
   const int nb = (nI + BW - 1) / BW;
   double r[kRegs<BW>];
@@ -168,7 +172,7 @@ __device__ void sweep_bwd(const double* __restrict__ A, int n, int nI, double* w
 
 // y = L_II^{-1} r_I (kept for the post-correction), t = L_GI y
 template <int BW>
-__global__ void __launch_bounds__(kSweepNT) k_sweep_pre(LevelDev L, const double* __restrict__ r) {
+__global__ void __launch_bounds__(kSweepNT, kSweepBlocks<BW>) k_sweep_pre(LevelDev L, const double* __restrict__ r) {
   extern __shared__ double sh[];
   if (L.stop && *L.stop) return;
   const int s = blockIdx.x;
@@ -188,7 +192,7 @@ __global__ void __launch_bounds__(kSweepNT) k_sweep_pre(LevelDev L, const double
 
 // u_B = sum over sharers of v (owner writes); u_I = L_II^{-T} (y - L_GI^T u_B)
 template <int BW>
-__global__ void __launch_bounds__(kSweepNT) k_sweep_post(LevelDev L, double* __restrict__ u,
+__global__ void __launch_bounds__(kSweepNT, kSweepBlocks<BW>) k_sweep_post(LevelDev L, double* __restrict__ u,
                                                     const int32_t* __restrict__ gam_map) {
   extern __shared__ double sh[];
   if (L.stop && *L.stop) return;
@@ -217,7 +221,7 @@ __global__ void __launch_bounds__(kSweepNT) k_sweep_post(LevelDev L, double* __r
 
 // interior recovery of the interface-reduced solve: u_G = x, u_I = L_II^{-T}(y - L_GI^T x_s)
 template <int BW>
-__global__ void __launch_bounds__(kSweepNT) k_sweep_recover(LevelDev L, const double* __restrict__ x,
+__global__ void __launch_bounds__(kSweepNT, kSweepBlocks<BW>) k_sweep_recover(LevelDev L, const double* __restrict__ x,
                                                        double* __restrict__ u) {
   extern __shared__ double sh[];
   const int s = blockIdx.x;
