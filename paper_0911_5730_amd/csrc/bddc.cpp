@@ -424,6 +424,7 @@ struct bddc_ctx {
   bddc::Arena wide_arena;
   double by_average = 0;      // algorithmic bytes of the level-1 interface average
   double by_ur_prec = 0;      // update + restriction (it >= 1), T_rr and Psi in the precision form's storage
+  double by_schur_packed = 0; // the PCG product with S_s as packed lower triangles
   double by_r_prec = 0;       // restriction of r_0 alone, likewise
   bddc::CoopDev coop;
   bddc::Arena coop_arena;
@@ -1715,7 +1716,7 @@ static int pcg_one(bddc_ctx* h, const double* f, double* u, double rtol, int max
       timing::current_tag = it;
       {
         // the product of iteration k works iff k <= K (K = converged iteration)
-        timing::Scope ts("schur_local", l1.by_schur, 0, -1);
+        timing::Scope ts("schur_local", h->by_schur_packed, 0, -1);
         launch_pcg_matvec(q, l1.dev, l1.ngmax, P, u);
       }
       if (P.fin) launch_pcg_sum(q, P, 0, u);
@@ -1922,6 +1923,13 @@ bddc_status bddc_setup(const bddc_problem* p, void* hip_stream, bddc_handle* out
       phi_ptr[gi + 1] = phi_ptr[gi] + len;
     }
     const size_t nphi = (size_t)phi_ptr[nif];
+    // packed lower triangles of S_s and T_rr
+    std::vector<int64_t> spoff(l1.nsub + 1, 0), tpoff(l1.nsub + 1, 0);
+    for (int s = 0; s < l1.nsub; ++s) {
+      const int64_t ng = l1.topo.ngam(s), nr = l1.topo.n_r[s];
+      spoff[s + 1] = spoff[s] + ng * (ng + 1) / 2;
+      tpoff[s + 1] = tpoff[s] + nr * (nr + 1) / 2;
+    }
     // every sharer's flat entry of each flat entry's dof, padded to four
     bool fits4 = true;
     for (int gi = 0; gi < nif; ++gi) fits4 = fits4 && l1.sh_ptr[gi + 1] - l1.sh_ptr[gi] <= 4;
@@ -1953,10 +1961,14 @@ bddc_status bddc_setup(const bddc_problem* p, void* hip_stream, bddc_handle* out
       P.phi_w = B.take<double>(nphi);
       sub_flat_d = B.take<int32_t>(sub_of_flat.size());
       if (fits4) P.shf4 = B.take<int4>(l1.nflat_g);
+      P.Sp = B.take<double>(std::max<size_t>(1, (size_t)spoff.back()));
+      P.spoff = B.take<int64_t>(spoff.size());
+      P.tpoff = B.take<int64_t>(tpoff.size());
+      if (h->precision == BDDC_FP64) P.Tp = B.take<double>(std::max<size_t>(1, (size_t)tpoff.back()));
       if (h->precision != BDDC_FP64) {
         P.Psi32 = B.take<float>((size_t)l1.psioff.back());
         if (h->precision == BDDC_FP32) {
-          P.T32 = B.take<float>((size_t)l1.toff.back());
+          P.Tp32 = B.take<float>(std::max<size_t>(1, (size_t)tpoff.back()));
         } else {
           P.W16 = B.take<uint16_t>((size_t)l1.toff.back());
           P.Q32 = B.take<float>(std::max<size_t>(1, (size_t)l1.croff.back()));
@@ -1989,12 +2001,15 @@ bddc_status bddc_setup(const bddc_problem* p, void* hip_stream, bddc_handle* out
       stg.add(const_cast<int32_t*>(P.phi_ptr), phi_ptr);
       stg.add(sub_flat_d, sub_of_flat);
       if (fits4) stg.add(reinterpret_cast<int32_t*>(const_cast<int4*>(P.shf4)), shf4);
+      stg.add(const_cast<int64_t*>(P.spoff), spoff);
+      stg.add(const_cast<int64_t*>(P.tpoff), tpoff);
       stg.flush();
       P.prec = h->precision == BDDC_FP32 ? 1 : (h->precision == BDDC_BF16 ? 2 : 0);
       P.ncr = l1.d.ncr;
       P.croff = l1.d.croff;
       int ncrmax = 0;
       for (int v : l1.ncr) ncrmax = std::max(ncrmax, v);
+      launch_pack_pcg(h->stream, l1.dev, P);
       launch_round_factors(h->stream, l1.dev, P, l1.nrmax, ncrmax, l1.d.Cr, h->status);
       launch_build_phi(h->stream, l1.dev, nif, sub_flat_d, P.phi_ptr, const_cast<int32_t*>(P.phi_ids),
                        const_cast<double*>(P.phi_w), P.Psi32);
@@ -2008,17 +2023,20 @@ bddc_status bddc_setup(const bddc_problem* p, void* hip_stream, bddc_handle* out
     }
     {
       // the restriction's operator bytes in the storage of the precision form
-      double op64 = 0, opp = 0;
+      double op64 = 0, opp = 0, s64 = 0, sp = 0;
       for (int s = 0; s < l1.nsub; ++s) {
         const double nr = l1.topo.n_r[s], ng = l1.topo.ngam(s), ncs = l1.coff[s + 1] - l1.coff[s];
         const double ncr = l1.ncr[s];
         op64 += 8 * nr * nr + 8 * ng * ncs;
-        if (P.prec == 1) opp += 4 * nr * nr + 4 * ng * ncs;
+        if (P.prec == 1) opp += 4 * nr * (nr + 1) / 2 + 4 * ng * ncs;
         else if (P.prec == 2) opp += 2 * nr * (nr + 1) / 2 + 4 * nr * ncr + 4 * nr + 4 * ng * ncs;
-        else opp += 8 * nr * nr + 8 * ng * ncs;
+        else opp += 8 * nr * (nr + 1) / 2 + 8 * ng * ncs;
+        s64 += 8 * ng * ng;
+        sp += 8 * ng * (ng + 1) / 2;
       }
       h->by_ur_prec = l1.by_update_restrict - op64 + opp;
       h->by_r_prec = l1.by_restrict_ir - op64 + opp;
+      h->by_schur_packed = l1.by_schur - s64 + sp;
     }
     clk.lap("pcg state + phi");
     plan_deep(h);

@@ -316,86 +316,6 @@ __global__ void k_pcg_advance(PcgScalars* sc, int n) {
 // r_{k-1} while owners write r_k.  The average uses, per interface dof, the
 // sharers' rows of the delta-weighted coarse basis (built at setup), so the
 // prolongation needs no pass of its own.
-__global__ void __launch_bounds__(kNT) k_pcg_matvec(LevelDev L, PcgDev P, int u) {
-  extern __shared__ double sh[];
-  __shared__ double red[kNT];
-  if (P.sc->done) return;
-  const int it = P.sc->it_base + u;
-  const int s = blockIdx.x;
-  const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
-  const int nI = L.nint[s];
-  const int ng = n - nI;
-  const int g0 = L.goff[s];
-  const double* S = L.K + L.koff[s] + nI + (size_t)nI * n;
-  const int tid = threadIdx.x;
-  // thread (mi, mc) forms the partial row sum of row mi over the columns
-  // mc, mc + nch, ...; its first kMV entries of S are loaded before the
-  // scalars and p are formed, so HBM latency overlaps that work
-  constexpr int kMV = 16;
-  const int nch = max(1, kNT / max(1, ng));
-  const bool narrow = ng <= kNT;
-  const int mi = narrow && ng > 0 ? tid % ng : 0;
-  const int mc = narrow && ng > 0 ? tid / ng : nch;
-  const bool act = narrow && mc < nch;
-  double sv[kMV];
-#pragma unroll
-  for (int k = 0; k < kMV; ++k) {
-    const int j = mc + k * nch;
-    sv[k] = (act && j < ng) ? S[mi + (size_t)j * n] : 0.0;
-  }
-  double beta = 0.0;
-  if (it >= 2) {
-    double rz, rz0;
-    if (P.fin) {
-      rz = P.sc->rzs[(it - 1) & 1];
-      rz0 = P.sc->rzs[(it - 2) & 1];
-    } else {
-      rz = block_sum_of(P.rz_part[(it - 1) & 1], P.nblk, red);
-      rz0 = block_sum_of(P.rz_part[(it - 2) & 1], P.nblk, red);
-    }
-    beta = rz / rz0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) P.sc->betas[min(it - 2, kMaxHist - 1)] = beta;
-  }
-  const double* pold = P.p[(it - 1) & 1];
-  double* pnew = P.p[it & 1];
-  double* pl = sh;
-  double* part = sh + ng;
-  for (int a = tid; a < ng; a += kNT) {
-    const int f = g0 + a;
-    const int gi = L.gam_iid[f];
-    const bool own = P.shf4 ? P.shf4[f].x == f : L.sh_flat[L.sh_ptr[gi]] == f;
-    const double pv = (it >= 2) ? P.z[gi] + beta * pold[gi] : P.z[gi];
-    pl[a] = pv;
-    if (own) pnew[gi] = pv;
-  }
-  __syncthreads();
-  if (narrow) {
-    if (act) {
-      double acc = 0.0;
-#pragma unroll
-      for (int k = 0; k < kMV; ++k) {
-        const int j = mc + k * nch;
-        if (j < ng) acc += sv[k] * pl[j];
-      }
-      for (int j = mc + kMV * nch; j < ng; j += nch) acc += S[mi + (size_t)j * n] * pl[j];
-      part[mi + mc * ng] = acc;
-    }
-  } else {
-    for (int i = tid; i < ng; i += kNT) part[i] = dot_strided(S + i, n, pl, 0, ng, 1);
-  }
-  __syncthreads();
-  double e = 0.0;
-  const int nc = narrow ? nch : 1;
-  for (int i = tid; i < ng; i += kNT) {
-    double acc = 0.0;
-    for (int c = 0; c < nc; ++c) acc += part[i + c * ng];
-    P.qloc[g0 + i] = acc;
-    e += pl[i] * acc;
-  }
-  e = wg_sum(e, red);
-  if (tid == 0) P.pq_part[s] = e;
-}
-
 // BF16 storage: the upper half of the IEEE binary32 pattern, rounded to
 // nearest with ties to even (finite inputs only).
 __device__ inline uint16_t f32_to_bf16(float x) {
@@ -440,6 +360,119 @@ struct Prefetch {
   }
 };
 
+// Column j of the packed lower triangle of an m x m matrix starts here.
+__device__ inline int packed_col(int j, int m) { return j * m - (j * (j - 1)) / 2; }
+
+// Entry (i, j) of a symmetric m x m matrix held as its packed lower triangle.
+__device__ inline int sym_index(int i, int j, int m) {
+  return i >= j ? packed_col(j, m) + (i - j) : packed_col(i, m) + (j - i);
+}
+
+// Thread (i, c) of a row-partial product loads the entries (i, c + k nch),
+// k < K, of a packed symmetric operator into registers (unconditional loads at
+// clamped in-block addresses, so they issue back to back), and later forms its
+// partial row sum with them.
+template <int K, class T>
+struct SymRowRegs {
+  T v[K];
+  __device__ void load(const T* A, int m, int i, int c, int nch) {
+    if (m <= 0) return;
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = A[sym_index(i, min(c + k * nch, m - 1), m)];
+  }
+  __device__ double dot(const T* A, int m, int i, int c, int nch, const double* x) const {
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int j = c + k * nch;
+      // keeps a widening conversion here instead of right after the load
+      // (which would wait for the load before the work it should overlap)
+      T r = v[k];
+      __asm__ volatile("" : "+v"(r));
+      if (j < m) acc += static_cast<double>(r) * x[j];
+    }
+    for (int j = c + K * nch; j < m; j += nch) acc += static_cast<double>(A[sym_index(i, j, m)]) * x[j];
+    return acc;
+  }
+};
+
+// Partial row sum over the columns c, c + nch, ... of row i of the symmetric
+// m x m matrix held as its packed lower triangle A (column-major), times x.
+__device__ inline double sym_row_part(const double* A, int m, int i, int c, int nch, const double* x) {
+  double acc = 0.0;
+  int j = c;
+  for (; j <= i; j += nch) acc += A[packed_col(j, m) + (i - j)] * x[j];
+  const double* Ai = A + packed_col(i, m) - i;   // row i, columns j > i
+  for (; j < m; j += nch) acc += Ai[j] * x[j];
+  return acc;
+}
+
+__global__ void __launch_bounds__(kNT) k_pcg_matvec(LevelDev L, PcgDev P, int u) {
+  extern __shared__ double sh[];
+  __shared__ double red[kNT];
+  if (P.sc->done) return;
+  const int it = P.sc->it_base + u;
+  const int s = blockIdx.x;
+  const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
+  const int nI = L.nint[s];
+  const int ng = n - nI;
+  const int g0 = L.goff[s];
+  const int tid = threadIdx.x;
+  double* pl = sh;
+  double* part = sh + ng;
+  // thread (mi, mc) forms the partial row sum of row mi over the columns mc,
+  // mc + nch, ...; its entries of S_s (packed symmetric) are loaded before the
+  // scalars and p are formed, so HBM latency overlaps that work
+  const double* Sg = P.Sp + P.spoff[s];
+  const int nch = max(1, kNT / max(1, ng));
+  const bool narrow = ng <= kNT;
+  const int mi = narrow && ng > 0 ? tid % ng : 0;
+  const int mc = narrow && ng > 0 ? tid / ng : nch;
+  const bool act = narrow && mc < nch;
+  SymRowRegs<16, double> sv;
+  if (narrow) sv.load(Sg, ng, mi, mc, nch);
+  double beta = 0.0;
+  if (it >= 2) {
+    double rz, rz0;
+    if (P.fin) {
+      rz = P.sc->rzs[(it - 1) & 1];
+      rz0 = P.sc->rzs[(it - 2) & 1];
+    } else {
+      rz = block_sum_of(P.rz_part[(it - 1) & 1], P.nblk, red);
+      rz0 = block_sum_of(P.rz_part[(it - 2) & 1], P.nblk, red);
+    }
+    beta = rz / rz0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) P.sc->betas[min(it - 2, kMaxHist - 1)] = beta;
+  }
+  const double* pold = P.p[(it - 1) & 1];
+  double* pnew = P.p[it & 1];
+  for (int a = tid; a < ng; a += kNT) {
+    const int f = g0 + a;
+    const int gi = L.gam_iid[f];
+    const bool own = P.shf4 ? P.shf4[f].x == f : L.sh_flat[L.sh_ptr[gi]] == f;
+    const double pv = (it >= 2) ? P.z[gi] + beta * pold[gi] : P.z[gi];
+    pl[a] = pv;
+    if (own) pnew[gi] = pv;
+  }
+  __syncthreads();
+  if (narrow) {
+    if (act) part[mi + mc * ng] = sv.dot(Sg, ng, mi, mc, nch, pl);
+  } else {
+    for (int i = tid; i < ng; i += kNT) part[i] = sym_row_part(Sg, ng, i, 0, 1, pl);
+  }
+  __syncthreads();
+  double e = 0.0;
+  const int nc = narrow ? nch : 1;
+  for (int i = tid; i < ng; i += kNT) {
+    double acc = 0.0;
+    for (int c = 0; c < nc; ++c) acc += part[i + c * ng];
+    P.qloc[g0 + i] = acc;
+    e += pl[i] * acc;
+  }
+  e = wg_sum(e, red);
+  if (tid == 0) P.pq_part[s] = e;
+}
+
 // Storage of T_rr and Psi in the precision forms: FP64 (kPrec 0), FP32 (1),
 // factored T_rr with a BF16 inverse Cholesky factor (2).  The products are
 // formed in FP64 in every form: the reduced forms cut the bytes streamed per
@@ -450,18 +483,16 @@ template <> struct PrecForm<0> { using TS = double; using PS = double; };
 template <> struct PrecForm<1> { using TS = float; using PS = float; };
 template <> struct PrecForm<2> { using TS = uint16_t; using PS = float; };
 
-// Column j of the packed lower triangle of an m x m matrix starts here.
-__device__ inline int packed_col(int j, int m) { return j * m - (j * (j - 1)) / 2; }
 
 // it >= 1: alpha, the residual update (r_k into r[it & 1]) and x update by the
 // owners, the partial r.r; then the level-1 restriction of r_k (it == 0: of
 // r_0 only): g = delta r_G, b = Psi^T g (ML-coarse) and da = delta T_rr g_r
 // (ML-wDi, weighted for the interface average).
+//   The operator's loads (packed symmetric T_rr, or the factored form's W) are
+//   issued first and land in LDS while the scalars and the residual update run.
 //   FP64 / FP32 forms: thread (ti, tc) forms row ti of T_rr g_r over the
-//   columns tc, tc + nch, ... from registers loaded at the start, so the
-//   operator's HBM latency overlaps the residual update; LDS holds vectors only.
-//   Factored BF16 form: x = D^-1 g_r, v = W x, v = (I - Q Q^T)^2 v, y = W^T v,
-//   T_rr g_r = D^-1 y, with W staged in LDS (two passes over it).
+//   columns tc, tc + nch, ...  Factored BF16 form: x = D^-1 g_r, v = W x,
+//   v = (I - Q Q^T)^2 v, y = W^T v, T_rr g_r = D^-1 y (two passes over W).
 template <int kPrec>
 __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev P, int u, int nrmax, int ngmax,
                                                              int ncsmax) {
@@ -482,34 +513,32 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
   double* g = sh;                        // ngmax
   double* part = sh + ngmax;             // kNT + ngmax
   double* xv = part + kNT + ngmax;       // factored form: x, then v (nrmax)
-  float* Wl = reinterpret_cast<float*>(xv + nrmax);                       // packed W
-  float* Ql = Wl + (size_t)nrmax * (nrmax + 1) / 2;                       // Q
+  float* Tl = reinterpret_cast<float*>(xv + nrmax);                       // factored form: packed W
+  float* Ql = reinterpret_cast<float*>(xv + nrmax + ((size_t)nrmax * (nrmax + 1) / 2));   // Q
   float* dinv = Ql + (size_t)nrmax * ncsmax;                              // D^-1
   const int nch = max(1, kNT / max(1, n_r));
+  const int ntri = n_r * (n_r + 1) / 2;
+  // the operators' loads go out first and land while the scalars are formed
+  constexpr int kPV = 2;
+  const PS* Pg;
+  if constexpr (kPrec == 0) Pg = L.Psi + L.psioff[s];
+  else Pg = P.Psi32 + L.psioff[s];
+  // FP64 / FP32 forms: thread (ti, tc) holds its entries of the packed
+  // symmetric T_rr in registers; factored form: W staged in LDS
+  const TS* Tg = nullptr;
+  if constexpr (kPrec == 0) Tg = P.Tp + P.tpoff[s];
+  else if constexpr (kPrec == 1) Tg = P.Tp32 + P.tpoff[s];
   const bool narrow = n_r <= kNT;
   const int ti = narrow && n_r > 0 ? tid % n_r : 0;
   const int tc = narrow && n_r > 0 ? tid / n_r : nch;
   const bool act = narrow && tc < nch;
-  // the operators' loads go out first and land while the scalars are formed
-  constexpr int kTV = 16, kPV = 2;
-  const TS* Tg = nullptr;
-  if constexpr (kPrec == 0) Tg = L.T + L.toff[s];
-  else if constexpr (kPrec == 1) Tg = P.T32 + L.toff[s];
-  const PS* Pg;
-  if constexpr (kPrec == 0) Pg = L.Psi + L.psioff[s];
-  else Pg = P.Psi32 + L.psioff[s];
+  SymRowRegs<16, TS> tv;
+  if constexpr (kPrec != 2)
+    if (narrow) tv.load(Tg, n_r, ti, tc, nch);   // every thread: no divergent region to merge
+  Prefetch<8, uint16_t, float> pt;
+  if constexpr (kPrec == 2) pt.fetch(P.W16 + L.toff[s], reinterpret_cast<float*>(Tl), ntri);
   // (the loads are unconditional, at clamped in-block addresses, so that
   // they issue back to back; entries outside the block are never used)
-  TS tv[kTV];
-  if constexpr (kPrec != 2) {
-    if (n_r > 0) {
-#pragma unroll
-      for (int k = 0; k < kTV; ++k) {
-        const int j = min(tc + k * nch, n_r - 1);
-        tv[k] = Tg[ti + (size_t)j * n_r];
-      }
-    }
-  }
   PS pv[kPV][2];
   if (ng > 0 && ncs > 0) {
 #pragma unroll
@@ -520,9 +549,7 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
         pv[m][q] = Pg[a + (size_t)k * ng];
       }
   }
-  Prefetch<8, uint16_t, float> pw;
   if constexpr (kPrec == 2) {
-    pw.fetch(P.W16 + L.toff[s], Wl, n_r * (n_r + 1) / 2);
     for (int a = tid; a < n_r; a += kNT) dinv[a] = P.Dinv[g0 + a];
     const int nq = n_r * P.ncr[s];
     const float* Qg = P.Q32 + P.croff[s];
@@ -570,7 +597,7 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
       P.sc->alphas[min(it - 1, kMaxHist - 1)] = alpha;
     }
   }
-  if constexpr (kPrec == 2) pw.finish();
+  if constexpr (kPrec == 2) pt.finish();
   __syncthreads();
   // b = Psi^T g, one wave per coarse dof
   for (int k = wave, m = 0; k < ncs; k += kNT / 64, ++m) {
@@ -596,7 +623,7 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
       [[maybe_unused]] const int idx = i + c * n_r;
       double acc = 0.0;
       for (int j = c; j <= i; j += nch)
-        acc += static_cast<double>(Wl[packed_col(j, n_r) + (i - j)]) * (g[j] * static_cast<double>(dinv[j]));
+        acc += static_cast<double>(Tl[packed_col(j, n_r) + (i - j)]) * (g[j] * static_cast<double>(dinv[j]));
       part[idx] = acc;
     }
     __syncthreads();
@@ -623,7 +650,7 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
       [[maybe_unused]] const int idx = j + c * n_r;
       const int cj = packed_col(j, n_r) - j;
       double acc = 0.0;
-      for (int i = j + c; i < n_r; i += nch) acc += static_cast<double>(Wl[cj + i]) * xv[i];
+      for (int i = j + c; i < n_r; i += nch) acc += static_cast<double>(Tl[cj + i]) * xv[i];
       part[idx] = acc;
     }
     __syncthreads();
@@ -634,20 +661,11 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
     }
   } else {
     if (narrow) {
-      if (act) {
-        double acc = 0.0;
-#pragma unroll
-        for (int k = 0; k < kTV; ++k) {
-          const int j = tc + k * nch;
-          if (j < n_r) acc += static_cast<double>(tv[k]) * g[j];
-        }
-        for (int j = tc + kTV * nch; j < n_r; j += nch) acc += static_cast<double>(Tg[ti + (size_t)j * n_r]) * g[j];
-        part[ti + tc * n_r] = acc;
-      }
+      if (act) part[ti + tc * n_r] = tv.dot(Tg, n_r, ti, tc, nch, g);
     } else {
       for (int i = tid; i < n_r; i += kNT) {
         double acc = 0.0;
-        for (int j = 0; j < n_r; ++j) acc += static_cast<double>(Tg[i + (size_t)j * n_r]) * g[j];
+        for (int j = 0; j < n_r; ++j) acc += static_cast<double>(Tg[sym_index(i, j, n_r)]) * g[j];
         part[i] = acc;
       }
     }
@@ -687,12 +705,7 @@ __global__ void __launch_bounds__(kNT) k_round_factors(LevelDev L, PcgDev P, int
   const double* Psi = L.Psi + L.psioff[s];
   float* Psi32 = const_cast<float*>(P.Psi32) + L.psioff[s];
   for (int k = tid; k < ng * ncs; k += kNT) Psi32[k] = static_cast<float>(Psi[k]);
-  if (P.prec == 1) {
-    const double* T = L.T + L.toff[s];
-    float* T32 = const_cast<float*>(P.T32) + L.toff[s];
-    for (int k = tid; k < n_r * n_r; k += kNT) T32[k] = static_cast<float>(T[k]);
-    return;
-  }
+  if (P.prec == 1) return;   // T_rr in FP32 is written by k_pack_pcg
   const int n_cr = P.ncr[s];
   double* A = shf;
   double* Wm = A + (size_t)nrmax * nrmax;
@@ -756,6 +769,29 @@ __global__ void __launch_bounds__(kNT) k_round_factors(LevelDev L, PcgDev P, int
   for (int k = tid; k < n_cr * n_r; k += kNT) Q32[k] = static_cast<float>(Y[k]);
   float* Dv = const_cast<float*>(P.Dinv) + g0;
   for (int i = tid; i < n_r; i += kNT) Dv[i] = static_cast<float>(1.0 / d[i]);
+}
+
+// The level-1 operators of the PCG iteration as packed lower triangles,
+// one workgroup per substructure: S_s always, T_rr in FP64 or FP32 by form.
+__global__ void __launch_bounds__(kNT) k_pack_pcg(LevelDev L, PcgDev P) {
+  const int s = blockIdx.x;
+  const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
+  const int nI = L.nint[s];
+  const int ng = n - nI;
+  const int n_r = L.nr[s];
+  const double* S = L.K + L.koff[s] + nI + (size_t)nI * n;
+  double* Sp = const_cast<double*>(P.Sp) + P.spoff[s];
+  for (ColWalk w_(threadIdx.x, kNT, ng); w_.j < ng; w_.next())
+    if (w_.i >= w_.j) Sp[packed_col(w_.j, ng) + (w_.i - w_.j)] = S[w_.i + (size_t)w_.j * n];
+  if (P.prec == 2) return;
+  const double* T = L.T + L.toff[s];
+  for (ColWalk w_(threadIdx.x, kNT, n_r); w_.j < n_r; w_.next()) {
+    if (w_.i < w_.j) continue;
+    const int k = packed_col(w_.j, n_r) + (w_.i - w_.j);
+    const double v = T[w_.i + (size_t)w_.j * n_r];
+    if (P.prec == 0) const_cast<double*>(P.Tp)[P.tpoff[s] + k] = v;
+    else const_cast<float*>(P.Tp32)[P.tpoff[s] + k] = static_cast<float>(v);
+  }
 }
 
 // Convergence test on r.r (every block takes the same decision; block 0
@@ -839,17 +875,21 @@ void launch_pcg_advance(hipStream_t st, const PcgDev& P, int n) {
 }
 void launch_pcg_update_restrict(hipStream_t st, const LevelDev& L, int ngmax, int nrmax, int ncsmax, const PcgDev& P,
                                 int u) {
-  // doubles: g | part | x/v ; floats: packed W | Q | D^-1 (factored form only)
+  // doubles: g | part ; factored form also: x/v (doubles) | W | Q | D^-1 (floats)
   size_t lds = sizeof(double) * ((size_t)ngmax + kNT + ngmax);
   if (P.prec == 2)
-    lds += sizeof(double) * nrmax +
-           sizeof(float) * ((size_t)nrmax * (nrmax + 1) / 2 + (size_t)nrmax * ncsmax + nrmax);
+    lds += sizeof(double) * (nrmax + (size_t)nrmax * (nrmax + 1) / 2) +
+           sizeof(float) * ((size_t)nrmax * ncsmax + nrmax);
   if (P.prec == 0)
     launch_kernel(k_pcg_update_restrict<0>, dim3(L.nsub), dim3(kNT), lds, st, L, P, u, nrmax, ngmax, ncsmax);
   else if (P.prec == 1)
     launch_kernel(k_pcg_update_restrict<1>, dim3(L.nsub), dim3(kNT), lds, st, L, P, u, nrmax, ngmax, ncsmax);
   else
     launch_kernel(k_pcg_update_restrict<2>, dim3(L.nsub), dim3(kNT), lds, st, L, P, u, nrmax, ngmax, ncsmax);
+}
+void launch_pack_pcg(hipStream_t st, const LevelDev& L, const PcgDev& P) {
+  if (L.nsub == 0) return;
+  launch_kernel(k_pack_pcg, dim3(L.nsub), dim3(kNT), 0, st, L, P);
 }
 void launch_round_factors(hipStream_t st, const LevelDev& L, const PcgDev& P, int nrmax, int ncrmax, const double* Cr,
                           int* status) {

@@ -196,7 +196,11 @@ struct PcgDev {
   // FP32, D^-1 in FP32, Psi FP32.  Products of the reduced forms are formed in
   // FP64 (reduced storage, FP64 arithmetic); every vector stays FP64.
   int prec = 0;
-  const float* T32 = nullptr;       // FP32 T_rr (offsets toff)
+  const double* Sp = nullptr;       // S_s, packed lower triangle (column-major), offsets spoff
+  const int64_t* spoff = nullptr;
+  const double* Tp = nullptr;       // FP64 form: T_rr packed lower triangle, offsets tpoff
+  const float* Tp32 = nullptr;      // FP32 form: T_rr packed lower triangle, offsets tpoff
+  const int64_t* tpoff = nullptr;
   const uint16_t* W16 = nullptr;    // BF16 packed lower W, column-major (offsets toff)
   const float* Q32 = nullptr;       // FP32 Q, n_r x n_cr column-major (offsets croff)
   const float* Dinv = nullptr;      // D^-1 on the interface flat (first n_r entries of each substructure)
@@ -319,6 +323,7 @@ void launch_pcg_sum(hipStream_t st, const PcgDev& P, int which, int u);
 void launch_pcg_advance(hipStream_t st, const PcgDev& P, int n);
 void launch_round_factors(hipStream_t st, const LevelDev& L, const PcgDev& P, int nrmax, int ncrmax, const double* Cr,
                           int* status);
+void launch_pack_pcg(hipStream_t st, const LevelDev& L, const PcgDev& P);
 void launch_pcg_update_restrict(hipStream_t st, const LevelDev& L, int ngmax, int nrmax, int ncsmax, const PcgDev& P,
                                 int u);
 void launch_pcg_prolong_post(hipStream_t st, const LevelDev& L, const PcgDev& P, const double* uc, int u);
