@@ -991,11 +991,23 @@ class Builder {
                       d.inc_off, h_->tau, d.lam, d.lamoff, d.Q, d.qoff, d.nsel, d.nkept, h_->status);
       std::vector<int32_t> nkept(ne_tot);
       lv.lam.resize(lv.lamoff.back());
-      BDDC_HIP(hipMemcpyAsync(nkept.data(), d.nkept, sizeof(int32_t) * ne_tot, hipMemcpyDeviceToHost, st_));
-      BDDC_HIP(hipMemcpyAsync(lv.edge_nsel.data(), d.nsel, sizeof(int32_t) * ne_tot, hipMemcpyDeviceToHost, st_));
-      BDDC_HIP(hipMemcpyAsync(lv.lam.data(), d.lam, sizeof(double) * lv.lam.size(), hipMemcpyDeviceToHost, st_));
-      clk.lap("  enqueue factor+eig");
-      BDDC_HIP(hipStreamSynchronize(st_));
+      {
+        // one pinned buffer, so the three copies are asynchronous and one wait covers them
+        const size_t bl = sizeof(double) * lv.lam.size(), bi = sizeof(int32_t) * (size_t)ne_tot;
+        char* pin = static_cast<char*>(pinned_acquire(bl + 2 * bi + 16));
+        BDDC_HIP(hipMemcpyAsync(pin, d.lam, bl, hipMemcpyDeviceToHost, st_));
+        BDDC_HIP(hipMemcpyAsync(pin + bl, d.nkept, bi, hipMemcpyDeviceToHost, st_));
+        BDDC_HIP(hipMemcpyAsync(pin + bl + bi, d.nsel, bi, hipMemcpyDeviceToHost, st_));
+        clk.lap("  enqueue factor+eig");
+        const hipError_t we = hipStreamSynchronize(st_);
+        if (we == hipSuccess) {
+          std::memcpy(lv.lam.data(), pin, bl);
+          std::memcpy(nkept.data(), pin + bl, bi);
+          std::memcpy(lv.edge_nsel.data(), pin + bl + bi, bi);
+        }
+        pinned_release(pin);
+        BDDC_HIP(we);
+      }
       clk.lap("  wait eig");
       lv.omega = 0.0;
       for (int e = 0; e < ne_tot; ++e) {

@@ -31,13 +31,13 @@ class Pool {
       n_ = n;
       chunk_ = chunk;
       next_.store(0);
-      active_ = nthreads_ - 1;
-      ++gen_;
+      active_.store(nthreads_ - 1);
+      gen_.fetch_add(1, std::memory_order_release);
     }
     cv_.notify_all();
     work();
-    std::unique_lock<std::mutex> lk(mu_);
-    done_cv_.wait(lk, [this] { return active_ == 0; });
+    // the loops of a set-up are short: wait for the workers by spinning
+    while (active_.load(std::memory_order_acquire) != 0) std::this_thread::yield();
     body_ = nullptr;
   }
 
@@ -52,25 +52,30 @@ class Pool {
   void worker() {
     unsigned seen = 0;
     for (;;) {
-      {
+      // a set-up issues its parallel loops in quick succession: spin for a
+      // while (about a millisecond) before sleeping on the condition variable
+      bool got = false;
+      for (int i = 0; i < 20000 && !got; ++i) {
+        got = gen_.load(std::memory_order_acquire) != seen;
+        if (!got && (i & 63) == 63) std::this_thread::yield();
+      }
+      if (!got) {
         std::unique_lock<std::mutex> lk(mu_);
-        cv_.wait(lk, [&] { return gen_ != seen; });
-        seen = gen_;
+        cv_.wait(lk, [&] { return gen_.load(std::memory_order_acquire) != seen; });
       }
+      seen = gen_.load(std::memory_order_acquire);
       work();
-      {
-        std::lock_guard<std::mutex> lk(mu_);
-        if (--active_ == 0) done_cv_.notify_one();
-      }
+      active_.fetch_sub(1, std::memory_order_acq_rel);
     }
   }
   int nthreads_ = 1;
   std::mutex run_mu_, mu_;
-  std::condition_variable cv_, done_cv_;
+  std::condition_variable cv_;
   const std::function<void(int, int)>* body_ = nullptr;
   std::atomic<int> next_{0};
-  int n_ = 0, chunk_ = 1, active_ = 0;
-  unsigned gen_ = 0;
+  int n_ = 0, chunk_ = 1;
+  std::atomic<int> active_{0};
+  std::atomic<unsigned> gen_{0};
 };
 
 Pool& pool() {
