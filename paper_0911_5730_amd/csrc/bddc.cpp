@@ -177,7 +177,7 @@ std::mutex mu;
 std::string target;
 std::vector<Rec> recs;
 std::vector<hipEvent_t> pool;
-int current_tag = -1;     // set by the PCG driver while it enqueues an iteration
+thread_local int current_tag = -1;   // set by the PCG driver while it enqueues an iteration
 int every = 1;            // time one in `every` launches of the target
 int64_t seen = 0;         // launches of the target since timing_start
 
@@ -1624,10 +1624,12 @@ static bool graph_chunk(bddc_ctx* h, hipStream_t st, F&& enqueue) {
       return false;
     }
     // captured on a stream of the library's own (the caller's may be the
-    // null stream, which cannot be captured); replayed on the caller's
+    // null stream, which cannot be captured); replayed on the caller's.
+    // Relaxed mode: other threads' synchronising calls stay legal meanwhile
+    // (the capture itself only enqueues kernels)
     hipStream_t cs = nullptr;
     if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess ||
-        hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) != hipSuccess) {
       (void)hipGetLastError();
       if (cs) (void)hipStreamDestroy(cs);
       h->graph_off = true;

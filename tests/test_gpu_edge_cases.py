@@ -104,3 +104,56 @@ def test_device_argument_validation():
             S.edge_eigs(1, 0)                            # not an adaptive set-up
         assert lib.bddc_query(None, None) == -1
     lib.bddc_destroy(None)
+
+
+def test_concurrent_handles_on_two_streams_match_alone():
+    """Independent problems set up and solved from two host threads, each with
+    its own stream and handles, interleave on the device; every result must
+    equal (bitwise) the same problem solved alone."""
+    import threading
+
+    import torch
+
+    import paper_0911_5730_amd as P
+    from test_gpu_parity import _case
+
+    probs = [_case("adaptive3"), _case("corners_kjump")]
+    alone = []
+    for prob in probs:
+        S = P.Solver(prob)
+        try:
+            u, it, _ = S.solve(cuda_vec(prob.f[0]))
+            alone.append((u.cpu().numpy(), int(it[0])))
+        finally:
+            S.close()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    results = [[], []]
+    errors = []
+
+    def worker(k):
+        try:
+            prob = probs[k]
+            f = cuda_vec(prob.f[0])
+            torch.cuda.synchronize()
+            for _ in range(3):
+                S = P.Solver(prob, stream=streams[k])
+                try:
+                    u, it, _ = S.solve(f, stream=streams[k])
+                    torch.cuda.synchronize()
+                    results[k].append((u.cpu().numpy(), int(it[0])))
+                finally:
+                    S.close()
+        except Exception as e:
+            errors.append(e)
+
+    th = [threading.Thread(target=worker, args=(k,)) for k in range(2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert not errors, errors
+    for k in range(2):
+        assert len(results[k]) == 3
+        for u, it in results[k]:
+            assert it == alone[k][1]
+            assert np.array_equal(u, alone[k][0])
