@@ -180,6 +180,32 @@ def concurrent_steps(P, prob, coeff, f, torch, nsteps: int, nstreams: int = 2) -
     return nsteps / (t1 - t0)
 
 
+def serving(synth, count: int = 40, rate: float = 200.0, slots: int = 2, precision: str = "fp32") -> dict:
+    """A seeded Poisson stream of independent requests (grid side 128 or 256,
+    H/h 8 or 16, 2-3 levels, k = 10^U(0,m), m in 0..6, 1-4 right-hand sides,
+    adaptive tau = 10) submitted at their arrival times to the serving loop."""
+    from paper_0911_5730_amd.serve import Request, Server
+    stream = synth.request_stream(count, rate=rate)
+    srv = Server(slots=slots)
+    try:
+        t0 = srv.now()
+        for t, prob in stream:
+            wait = t - (srv.now() - t0)
+            if wait > 0:
+                time.sleep(wait)
+            srv.submit(Request(prob=prob, rhs=prob.f, precision=precision, arrival=srv.now()))
+        srv.drain()
+    finally:
+        srv.close()
+    bad = [r for r in srv.finished if r.error is not None]
+    if bad:
+        raise bad[0].error
+    st = srv.stats()
+    st.update({"rate_per_s": rate, "precision": precision,
+               "rhs": int(sum(p.f.shape[0] for _, p in stream))})
+    return st
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -193,6 +219,7 @@ def main():
     ap.add_argument("--sample-every", type=int, default=8,
                     help="time one in this many launches of the roofline kernel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true", help="skip the request-stream measurement")
     ap.add_argument("--no-precision-forms", action="store_true",
                     help="skip the FP64 / FP32 / BF16 comparison on configs 2 and 3")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -341,6 +368,11 @@ def main():
         "roofline": roof,
         "setup_roofline": setup_roof,
     }
+    if not args.no_serving:
+        out["serving"] = {"two_slots": serving(synth, slots=2), "one_slot": serving(synth, slots=1),
+                          "note": "requests/s over the stream and arrival-to-completion latency; each request is "
+                                  "set up, solved to 1e-8 and released on a slot with its own stream"}
+        log(f"bench: serving {out['serving']['two_slots']['solves_per_s']:.1f} req/s (two slots)")
     if not args.no_precision_forms:
         out["precision_forms"] = {
             "note": "solves/s with the preconditioner set up once; FP32 / BF16 = reduced storage of the level-1 "

@@ -12,5 +12,6 @@ from .configs import (  # noqa: F401
     add_channels,
     square_problem,
     config,
+    request_stream,
     CONFIG_NAMES,
 )

@@ -153,3 +153,31 @@ def config(cid: int, nrhs: int = 1) -> Problem:
         return square_problem(1024, 64, levels=3, groups=(4, 4), constraints="adaptive",
                               tau=10.0, kmode="one", nrhs=nrhs, seed=seed, name="config3")
     raise ValueError(f"unknown config {cid}")
+
+
+def request_stream(count: int, *, rate: float = 200.0, sides=(128, 256), hh=(8, 16), seed: int = 5000,
+                   max_rhs: int = 4):
+    """A seeded stream of independent solve requests shaped like the serving
+    workload: Poisson arrivals (mean `rate` per second), grid side and H/h
+    drawn uniformly from `sides` and `hh`, 3 levels (level-2 substructures of
+    4 x 4 level-1 substructures) from 16 x 16 substructures on, else 2, k = 10^U(0, m) with m uniform in 0..6,
+    adaptive tau = 10, 1 to
+    `max_rhs` right-hand sides U[-1, 1].  Returns [(arrival_seconds, Problem)]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    t = 0.0
+    out = []
+    for r in range(count):
+        t += rng.exponential(1.0 / rate)
+        nx = int(rng.choice(sides))
+        h = int(rng.choice(hh))
+        nsx = nx // h
+        # two levels only while the coarse problem stays small (<= 8 x 8
+        # substructures): the coarsest problem is factored densely
+        levels = 3 if nsx >= 16 and nsx % 4 == 0 else 2
+        m = int(rng.integers(0, 7))
+        nrhs = int(rng.integers(1, max_rhs + 1))
+        prob = square_problem(nx, nsx, levels=levels, groups=(nsx // 4, nsx // 4), constraints="adaptive", tau=10.0,
+                              kmode="loguniform" if m else "one", kmax_exp=float(m), nrhs=nrhs,
+                              seed=int(rng.integers(1 << 30)), name=f"request{r}")
+        out.append((t, prob))
+    return out

@@ -157,3 +157,37 @@ def test_concurrent_handles_on_two_streams_match_alone():
         for u, it in results[k]:
             assert it == alone[k][1]
             assert np.array_equal(u, alone[k][0])
+
+
+def test_serving_loop_results_alone_equal_in_the_mix():
+    """Requests of different sizes admitted onto two concurrent slots: every
+    solution equals (bitwise) the same request solved alone; with an HBM
+    budget below two requests' footprint only one is admitted at a time."""
+    import synth
+    from paper_0911_5730_amd.serve import Request, Server
+
+    import paper_0911_5730_amd as P
+
+    stream = synth.request_stream(6, seed=77)
+    alone = []
+    for _, prob in stream:
+        S = P.Solver(prob, precision="fp32")
+        try:
+            u, it, _ = S.solve(cuda_vec(prob.f).reshape(prob.f.shape))
+            alone.append((u.cpu().numpy(), it))
+        finally:
+            S.close()
+    for budget, limit in ((None, 2), (1, 1)):
+        srv = Server(slots=2, hbm_budget=budget)
+        try:
+            reqs = [srv.submit(Request(prob=p, rhs=p.f, precision="fp32")) for _, p in stream]
+            srv.drain()
+        finally:
+            srv.close()
+        assert srv.max_active <= limit
+        for r, (u, it) in zip(reqs, alone):
+            assert r.error is None, r.error
+            assert r.iterations == it
+            assert np.array_equal(r.solution, u)
+        st = srv.stats()
+        assert st["requests"] == len(stream) and st["latency_ms"]["p99"] >= st["latency_ms"]["p50"]
