@@ -699,6 +699,75 @@ __device__ void wg_gj_inverse_spd(double* M, int m, double* tc, double* tr, int*
   }
 }
 
+// The same Gauss-Jordan inverse with the matrix held in registers: thread t
+// owns the entries t + u kNT (u < kGJ) of the column-major m x m matrix
+// (m * m <= kGJ kNT, m <= 64).  Each step updates the owned entries from the
+// pivot column and row in LDS without branches, and the owners of column / row
+// k + 1 publish them into the other half of the double buffers tc, tr (halves
+// of m + 64: every entry is stored, those of no use to the lane's own dump
+// slot) in the same pass, so a step costs one barrier and no read-modify-write
+// of LDS.  The arithmetic is that of wg_gj_inverse_spd, entry by entry
+// (bitwise the same result).
+constexpr int kGJ = 16;
+__device__ void wg_gj_inverse_spd_regs(double* M, int m, double* tc, double* tr, int* status) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int mm = m * m;
+  double v[kGJ];
+  int ii[kGJ], jj[kGJ];
+  ColWalk cw(tid, kNT, m);
+#pragma unroll
+  for (int u = 0; u < kGJ; ++u) {
+    const bool in = tid + u * kNT < mm;
+    v[u] = in ? M[tid + u * kNT] : 0.0;
+    ii[u] = in ? cw.i : -1;
+    jj[u] = in ? cw.j : -1;
+    cw.next();
+  }
+#pragma unroll
+  for (int u = 0; u < kGJ; ++u) {
+    if (jj[u] == 0) tc[ii[u]] = v[u];
+    if (ii[u] == 0) tr[jj[u]] = v[u];
+  }
+  __syncthreads();
+  // (the dump slots of the two halves absorb the stores below)
+  const int h = m + 64;  // half of each double buffer; entries m + lane are dump slots
+  for (int k = 0; k < m; ++k) {
+    const double* c = tc + (k & 1) * h;
+    const double* r = tr + (k & 1) * h;
+    double* cn = tc + ((k + 1) & 1) * h;
+    double* rn = tr + ((k + 1) & 1) * h;
+    const double p = c[k];
+    const bool ok = p > 0.0 && p < 1e308;
+    if (!ok && tid == 0) flag_bad(status);
+    const double ip = ok ? 1.0 / p : 0.0;
+    // branch-free: every case is formed and selected; entries of column /
+    // row k + 1 are published, every other entry goes to the dump slot
+#pragma unroll
+    for (int u = 0; u < kGJ; ++u) {
+      const int i = ii[u], j = jj[u];
+      const double cv = c[max(i, 0)], rv = r[max(j, 0)];
+      const double gen = v[u] - cv * rv * ip;
+      const double rowk = rv * ip;
+      const double colk = -cv * ip;
+      const double x = (i == k) ? ((j == k) ? ip : rowk) : ((j == k) ? colk : gen);
+      v[u] = x;
+      cn[(j == k + 1 && i >= 0) ? i : m + lane] = x;
+      rn[(i == k + 1) ? j : m + lane] = x;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < kGJ; ++u)
+    if (ii[u] >= 0) M[tid + u * kNT] = v[u];
+  __syncthreads();
+}
+
+// the register form when the matrix fits it, else the LDS form (tc, tr: 2 (m + 64) each)
+__device__ inline void wg_gj_inverse(double* M, int m, double* tc, double* tr, int* status) {
+  if (m <= 64 && m * m <= kGJ * kNT) wg_gj_inverse_spd_regs(M, m, tc, tr, status);
+  else wg_gj_inverse_spd(M, m, tc, tr, status);
+}
+
 // C (m x n, ldc) = alpha * op(A) op(B) + beta * C with every operand in LDS or global
 __device__ inline void wg_gemm_nn(int m, int n, int k, double alpha, const double* A, int lda, const double* B, int ldb,
                                   double beta, double* C, int ldc) {
@@ -713,7 +782,7 @@ __device__ inline void wg_gemm_nn(int m, int n, int k, double alpha, const doubl
 
 // LDS doubles of k_constrained_factor_lds for one substructure
 __host__ __device__ inline size_t cf_lds_doubles(int ng, int n_r, int n_cr, int ncs) {
-  const size_t a = (size_t)n_r * n_r + 3 * (size_t)n_r * n_cr + (size_t)n_cr * n_cr + 2 * (size_t)(n_r > n_cr ? n_r : n_cr);
+  const size_t a = (size_t)n_r * n_r + 3 * (size_t)n_r * n_cr + (size_t)n_cr * n_cr + 4 * (size_t)((n_r > n_cr ? n_r : n_cr) + 64);
   const size_t b = (size_t)ng * ncs;
   return (size_t)ng * ng + b + (a > b ? a : b);
 }
@@ -748,7 +817,7 @@ __global__ void __launch_bounds__(kNT) k_constrained_factor_lds(
   double* F = X + (size_t)n_r * n_cr;                    // n_cr x n_cr
   double* Z = F + (size_t)n_cr * n_cr;                   // n_r x n_cr
   double* tc = Z + (size_t)n_r * n_cr;
-  double* tr = tc + (n_r > n_cr ? n_r : n_cr);
+  double* tr = tc + 2 * ((n_r > n_cr ? n_r : n_cr) + 64);
   double* W = M;                                         // ng x ncs, after M .. Z are dead
 
   {
@@ -778,7 +847,7 @@ __global__ void __launch_bounds__(kNT) k_constrained_factor_lds(
     M[idx] = S[i + (size_t)j * ng];
   }
   __syncthreads();
-  wg_gj_inverse_spd(M, n_r, tc, tr, status);             // M = S_rr^{-1}
+  wg_gj_inverse(M, n_r, tc, tr, status);                 // M = S_rr^{-1}
   if (n_cr > 0) {
     for (ColWalk w_(tid, kNT, n_r); w_.j < n_cr; w_.next()) {  // X = M C^T
       const int i = w_.i, j = w_.j;
@@ -790,7 +859,7 @@ __global__ void __launch_bounds__(kNT) k_constrained_factor_lds(
     __syncthreads();
     wg_gemm_nn(n_cr, n_cr, n_r, 1.0, Cl, n_cr, X, n_r, 0.0, F, n_cr);   // F = C X
     __syncthreads();
-    wg_gj_inverse_spd(F, n_cr, tc, tr, status);
+    wg_gj_inverse_spd(F, n_cr, tc, tr, status);           // small: the LDS form
     wg_gemm_nn(n_r, n_cr, n_cr, 1.0, X, n_r, F, n_cr, 0.0, Z, n_r);     // Z = X F^{-1}
     __syncthreads();
     for (ColWalk w_(tid, kNT, n_r); w_.j < n_r; w_.next()) {   // M -= Z X^T
