@@ -346,6 +346,9 @@ struct Level {
   std::vector<int32_t> sub_inc_ptr, sub_inc;
   std::vector<int64_t> inc_off, lamoff, qoff;
   int nemax = 0, nvmax = 0;
+  // pair Schur complements / pair eigenproblems too large for LDS work in a
+  // global workspace: per incidence / per edge offsets (doubles), empty if not
+  std::vector<int64_t> schws_off, eigws_off;
   // coarse dofs
   std::vector<int32_t> edge_m, edge_nsel;
   std::vector<double> lam;
@@ -373,8 +376,8 @@ struct Level {
     int32_t *inc_sub, *inc_edge, *inc_fptr, *inc_fpos, *sub_inc_ptr, *sub_inc;
     int32_t *edge_s, *edge_t, *edge_nsc, *edge_ne, *edge_fdof, *edge_fptr, *edge_ptr, *edge_dof;
     uint8_t* floating;
-    int64_t *inc_off, *lamoff, *qoff;
-    double *Shat, *Sff, *lam, *Q;
+    int64_t *inc_off, *lamoff, *qoff, *schws_off, *eigws_off;
+    double *Shat, *Sff, *lam, *Q, *schws, *eigws;
     int32_t *nsel, *nkept;
     double* z;
     // coarse
@@ -644,6 +647,29 @@ static void layout_level(Level& lv) {
     io += (int64_t)nf * nf;
   }
   lv.inc_off.push_back(io);
+  // workspaces (in doubles, 256-byte aligned blocks) when LDS is too small
+  // (BDDC_PAIR_WS=global: always)
+  auto ws_doubles = [](size_t bytes) { return (int64_t)((bytes + 255) / 256 * 32); };
+  const char* wenv = getenv("BDDC_PAIR_WS");
+  const bool force = wenv && std::string(wenv) == "global";
+  lv.schws_off.clear();
+  lv.eigws_off.clear();
+  if (force || pair_schur_lds(lv.ngmax) > kLdsMax) {
+    int64_t o = 0;
+    for (int i = 0; i < ninc; ++i) {
+      lv.schws_off.push_back(o);
+      o += ws_doubles(pair_schur_lds(T.ngam(lv.inc_sub[i])));
+    }
+    lv.schws_off.push_back(o);
+  }
+  if (force || pair_eig_lds(lv.nemax, lv.nvmax) > kLdsMax) {
+    int64_t o = 0;
+    for (int e = 0; e < lv.nedge; ++e) {
+      lv.eigws_off.push_back(o);
+      o += ws_doubles(pair_eig_lds(lv.edge_ne[e], lv.edge_nsc[e] + 2 * lv.edge_ne[e]));
+    }
+    lv.eigws_off.push_back(o);
+  }
 }
 
 // algorithmic traffic of each kernel at one level: every operator entry and
@@ -747,9 +773,8 @@ class Builder {
   hipStream_t st_;
 
   void check_limits(const Level& lv) {
-    if (pair_schur_lds(lv.ngmax) > kLdsLimit || (partial_chol_lds(lv.nmax) > kLdsLimit && !use_mfma_chol(lv.nmax)) ||
-        pair_eig_lds(lv.nemax, lv.nvmax) > kLdsMax)
-      fail(BDDC_EUNSUPPORTED, "substructure interface or edge too large for this build");
+    if (partial_chol_lds(lv.nmax) > kLdsMax && !use_mfma_chol(lv.nmax))
+      fail(BDDC_EUNSUPPORTED, "substructure too large for this build");
   }
 
   void top_alloc() {
@@ -862,6 +887,10 @@ class Builder {
       d.qoff = A.take<int64_t>(lv.qoff.size());
       d.Shat = A.take<double>(adaptive ? (size_t)lv.inc_off.back() : 0);
       d.Sff = A.take<double>(adaptive ? (size_t)lv.inc_off.back() : 0);
+      d.schws_off = A.take<int64_t>(adaptive ? lv.schws_off.size() : 0);
+      d.eigws_off = A.take<int64_t>(adaptive ? lv.eigws_off.size() : 0);
+      d.schws = A.take<double>(adaptive && !lv.schws_off.empty() ? (size_t)lv.schws_off.back() : 0);
+      d.eigws = A.take<double>(adaptive && !lv.eigws_off.empty() ? (size_t)lv.eigws_off.back() : 0);
       d.lam = A.take<double>((size_t)lv.lamoff.back());
       d.Q = A.take<double>((size_t)lv.qoff.back());
       d.nsel = A.take<int32_t>(lv.nedge);
@@ -925,6 +954,10 @@ class Builder {
     stg.add(d.edge_dof, edge_dof);
     stg.add(d.floating, floating);
     stg.add(d.inc_off, lv.inc_off);
+    if (adaptive) {
+      stg.add(d.schws_off, lv.schws_off);
+      stg.add(d.eigws_off, lv.eigws_off);
+    }
     stg.add(d.lamoff, lv.lamoff);
     stg.add(d.qoff, lv.qoff);
     stg.add(d.linvoff, lv.linvoff);
@@ -985,10 +1018,12 @@ class Builder {
     std::vector<double> qh;
     if (h_->constraints == BDDC_ADAPTIVE && ne_tot > 0) {
       launch_pair_schur(st_, 2 * ne_tot, lv.ngmax, d.inc_sub, d.inc_fptr, d.inc_fpos, d.koff, d.loc_ptr, d.nint,
-                        d.K, d.inc_off, d.Shat, d.Sff, h_->status);
+                        d.K, d.inc_off, d.Shat, d.Sff, h_->status, lv.schws_off.empty() ? nullptr : d.schws,
+                        d.schws_off);
       launch_pair_eig(st_, ne_tot, lv.nemax, lv.nvmax, d.edge_s, d.edge_t, d.edge_nsc, d.edge_ne, d.edge_fdof,
                       d.edge_fptr, d.inc_fptr, d.inc_fpos, d.goff, d.diagK, d.floating, d.z, d.Shat, d.Sff,
-                      d.inc_off, h_->tau, d.lam, d.lamoff, d.Q, d.qoff, d.nsel, d.nkept, h_->status);
+                      d.inc_off, h_->tau, d.lam, d.lamoff, d.Q, d.qoff, d.nsel, d.nkept, h_->status,
+                      lv.eigws_off.empty() ? nullptr : d.eigws, d.eigws_off);
       std::vector<int32_t> nkept(ne_tot);
       lv.lam.resize(lv.lamoff.back());
       {

@@ -33,13 +33,20 @@ namespace bddc {
 // Schur complement of the interface Schur complement S_s onto the shared
 // dofs F of one (substructure, edge) incidence.  LDS holds the ng x ng matrix
 // reordered as [rest | F]; eliminating `rest` leaves Shat in the trailing block.
+// kGlobal: the working copy lives in a global workspace (ws + wsoff[inc])
+// instead of LDS, for interfaces too large for one CU's LDS.
+template <bool kGlobal>
 __global__ void __launch_bounds__(kNT) k_pair_schur(
     const int32_t* __restrict__ inc_sub, const int32_t* __restrict__ inc_fptr,
     const int32_t* __restrict__ inc_fpos, const int64_t* __restrict__ koff,
     const int32_t* __restrict__ loc_ptr, const int32_t* __restrict__ nint, const double* __restrict__ K,
-    const int64_t* __restrict__ inc_off, double* __restrict__ Shat, double* __restrict__ Sff, int* status) {
-  extern __shared__ double M[];
+    const int64_t* __restrict__ inc_off, double* __restrict__ Shat, double* __restrict__ Sff, int* status,
+    double* __restrict__ ws, const int64_t* __restrict__ wsoff) {
+  extern __shared__ double lds_m[];
   const int inc = blockIdx.x;
+  double* M;
+  if constexpr (kGlobal) M = ws + wsoff[inc];
+  else M = lds_m;
   const int s = inc_sub[inc];
   const int n = loc_ptr[s + 1] - loc_ptr[s];
   const int nI = nint[s];
@@ -424,6 +431,9 @@ __device__ inline void rr_pair(int k, int r, int m, int& p, int& q) {
 
 }  // namespace
 
+// kGlobal: the edge's working arrays live in a global workspace (ws +
+// wsoff[e]) instead of LDS, for edges too long for one CU's LDS.
+template <bool kGlobal>
 __global__ void __launch_bounds__(64) k_pair_eig_wave(
     const int32_t* __restrict__ edge_s, const int32_t* __restrict__ edge_t,
     const int32_t* __restrict__ edge_nsc, const int32_t* __restrict__ edge_ne,
@@ -434,9 +444,12 @@ __global__ void __launch_bounds__(64) k_pair_eig_wave(
     const double* __restrict__ Shat, const double* __restrict__ Sff, const int64_t* __restrict__ inc_off,
     double tau, double* __restrict__ lam_out, const int64_t* __restrict__ lamoff, double* __restrict__ Q,
     const int64_t* __restrict__ qoff, int32_t* __restrict__ nsel_out, int32_t* __restrict__ nkept_out,
-    int* status) {
-  extern __shared__ double lds[];
+    int* status, double* __restrict__ ws, const int64_t* __restrict__ wsoff) {
+  extern __shared__ double lds_w[];
   const int e = blockIdx.x;
+  double* lds;
+  if constexpr (kGlobal) lds = ws + wsoff[e];
+  else lds = lds_w;
   const int lane = threadIdx.x;
   const int s = edge_s[e], t = edge_t[e];
   const int nsc = edge_nsc[e], ne = edge_ne[e];
@@ -680,11 +693,16 @@ __global__ void __launch_bounds__(64) k_pair_eig_wave(
 void launch_pair_schur(hipStream_t st, int ninc, int ngmax, const int32_t* inc_sub, const int32_t* inc_fptr,
                        const int32_t* inc_fpos, const int64_t* koff, const int32_t* loc_ptr,
                        const int32_t* nint, const double* K, const int64_t* inc_off, double* Shat,
-                       double* Sff, int* status) {
+                       double* Sff, int* status, double* ws, const int64_t* wsoff) {
   if (ninc == 0) return;
+  if (ws) {
+    launch_kernel(k_pair_schur<true>, dim3(ninc), dim3(kNT), 0, st, inc_sub, inc_fptr, inc_fpos, koff, loc_ptr, nint,
+                  K, inc_off, Shat, Sff, status, ws, wsoff);
+    return;
+  }
   const size_t lds = pair_schur_lds(ngmax);
-  launch_kernel(k_pair_schur, dim3(ninc), dim3(kNT), lds, st, inc_sub, inc_fptr, inc_fpos, koff,
-                     loc_ptr, nint, K, inc_off, Shat, Sff, status);
+  launch_kernel(k_pair_schur<false>, dim3(ninc), dim3(kNT), lds, st, inc_sub, inc_fptr, inc_fpos, koff, loc_ptr,
+                nint, K, inc_off, Shat, Sff, status, ws, wsoff);
 }
 
 size_t pair_schur_lds(int ngmax) {
@@ -703,13 +721,19 @@ void launch_pair_eig(hipStream_t st, int nedge, int nemax, int nvmax, const int3
                      const int32_t* goff, const double* diagK, const uint8_t* floating, const double* z,
                      const double* Shat, const double* Sff, const int64_t* inc_off, double tau, double* lam,
                      const int64_t* lamoff, double* Q, const int64_t* qoff, int32_t* nsel, int32_t* nkept,
-                     int* status) {
+                     int* status, double* ws, const int64_t* wsoff) {
   if (nedge == 0) return;
+  if (ws) {
+    launch_kernel(k_pair_eig_wave<true>, dim3(nedge), dim3(64), 0, st, edge_s, edge_t, edge_nsc, edge_ne, edge_fdof,
+                  edge_fptr, inc_fptr, inc_fpos, goff, diagK, floating, z, Shat, Sff, inc_off, tau, lam, lamoff, Q,
+                  qoff, nsel, nkept, status, ws, wsoff);
+    return;
+  }
   const char* env = getenv("BDDC_EIG_PATH");
   if (!(env && std::string(env) == "wg")) {
-    launch_kernel(k_pair_eig_wave, dim3(nedge), dim3(64), pair_eig_lds(nemax, nvmax), st, edge_s, edge_t, edge_nsc,
-                  edge_ne, edge_fdof, edge_fptr, inc_fptr, inc_fpos, goff, diagK, floating, z, Shat, Sff, inc_off, tau,
-                  lam, lamoff, Q, qoff, nsel, nkept, status);
+    launch_kernel(k_pair_eig_wave<false>, dim3(nedge), dim3(64), pair_eig_lds(nemax, nvmax), st, edge_s, edge_t,
+                  edge_nsc, edge_ne, edge_fdof, edge_fptr, inc_fptr, inc_fpos, goff, diagK, floating, z, Shat, Sff,
+                  inc_off, tau, lam, lamoff, Q, qoff, nsel, nkept, status, ws, wsoff);
     return;
   }
   launch_kernel(k_pair_eig, dim3(nedge), dim3(kNT), pair_eig_lds(nemax, nvmax), st, nedge, edge_s, edge_t,

@@ -272,7 +272,10 @@ void launch_coarsest_factor(hipStream_t st, int nsub, int nc, const int32_t* cpt
 void launch_pair_schur(hipStream_t st, int ninc, int ngmax, const int32_t* inc_sub, const int32_t* inc_fptr,
                        const int32_t* inc_fpos, const int64_t* koff, const int32_t* loc_ptr,
                        const int32_t* nint, const double* K, const int64_t* inc_off, double* Shat,
-                       double* Sff, int* status);
+                       double* Sff, int* status, double* ws = nullptr, const int64_t* wsoff = nullptr);
+// LDS bytes of one pair Schur complement (interface of ngmax dofs) and one
+// pair eigenproblem; with a global workspace each block takes the same
+// number of bytes from it instead
 size_t pair_schur_lds(int ngmax);
 size_t pair_eig_lds(int nemax, int nvmax);
 void launch_pair_eig(hipStream_t st, int nedge, int nemax, int nvmax, const int32_t* edge_s, const int32_t* edge_t,
@@ -281,7 +284,7 @@ void launch_pair_eig(hipStream_t st, int nedge, int nemax, int nvmax, const int3
                      const int32_t* goff, const double* diagK, const uint8_t* floating, const double* z,
                      const double* Shat, const double* Sff, const int64_t* inc_off, double tau, double* lam,
                      const int64_t* lamoff, double* Q, const int64_t* qoff, int32_t* nsel, int32_t* nkept,
-                     int* status);
+                     int* status, double* ws = nullptr, const int64_t* wsoff = nullptr);
 
 // apply and PCG
 void launch_apply_pre(hipStream_t st, const LevelDev& L, int nImax, int ngmax, const double* r);

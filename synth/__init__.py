@@ -11,6 +11,9 @@ from .configs import (  # noqa: F401
     square_agglomeration,
     add_channels,
     square_problem,
+    voronoi_partition,
+    voronoi_agglomeration,
+    voronoi_problem,
     config,
     request_stream,
     CONFIG_NAMES,

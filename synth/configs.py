@@ -131,6 +131,71 @@ def square_problem(nx: int, nsx: int, *, ny: Optional[int] = None, nsy: Optional
                    name=name, meta={"channels": ch, "nsx": nsx, "nsy": nsy, "groups": groups})
 
 
+def voronoi_partition(rng: np.random.Generator, nx: int, ny: int, nsub: int):
+    """Element -> region of the nearest of `nsub` seed points drawn uniformly in
+    the unit square (nearest to the element centre, ties to the lower seed).
+    Seeds whose region holds no element are dropped and the ids renumbered in
+    seed order.  Returns (part, seed points of the kept regions)."""
+    from scipy.spatial import cKDTree
+
+    pts = rng.uniform(0.0, 1.0, size=(nsub, 2))
+    cx = (np.arange(nx) + 0.5) / nx
+    cy = (np.arange(ny) + 0.5) / ny
+    X, Y = np.meshgrid(cx, cy)
+    _, near = cKDTree(pts).query(np.column_stack([X.reshape(-1), Y.reshape(-1)]))
+    used = np.unique(near)
+    remap = np.full(nsub, -1, dtype=np.int64)
+    remap[used] = np.arange(used.size)
+    return remap[near].astype(np.int32), pts[used]
+
+
+def voronoi_agglomeration(rng: np.random.Generator, nx: int, ny: int, part: np.ndarray, nsub: int,
+                          ngroups: int) -> np.ndarray:
+    """Level-1 region -> group of the nearest of `ngroups` uniform seed points
+    to the region's centroid (mean element centre); empty groups dropped."""
+    from scipy.spatial import cKDTree
+
+    pts = rng.uniform(0.0, 1.0, size=(ngroups, 2))
+    cx = np.tile((np.arange(nx) + 0.5) / nx, ny)
+    cy = np.repeat((np.arange(ny) + 0.5) / ny, nx)
+    cnt = np.bincount(part, minlength=nsub).astype(np.float64)
+    cen = np.column_stack([np.bincount(part, cx, nsub) / cnt, np.bincount(part, cy, nsub) / cnt])
+    _, near = cKDTree(pts).query(cen)
+    used = np.unique(near)
+    remap = np.full(ngroups, -1, dtype=np.int64)
+    remap[used] = np.arange(used.size)
+    return remap[near].astype(np.int32)
+
+
+def voronoi_problem(nx: int, nsub: int, *, levels: int = 2, ngroups: int = 1, constraints: str = "corners",
+                    tau: float = float("inf"), kmode: str = "one", kmax_exp: float = 0.0, channels: int = 0,
+                    nrhs: int = 1, seed: int = 0, element: str = "Q1", name: str = "") -> Problem:
+    """A seeded problem on an irregular partition of uneven substructures:
+    Voronoi regions of `nsub` uniform seed points (level 1) and, for three
+    levels, Voronoi groups of their centroids around `ngroups` further seeds.
+    Draw order: coefficient, channels, partition seeds, group seeds, loads."""
+    assert constraints in CONSTRAINT_KINDS and levels in (2, 3)
+    ny = nx
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if kmode == "one":
+        coeff = np.ones(nx * ny)
+    elif kmode == "loguniform":
+        coeff = 10.0 ** rng.uniform(0.0, kmax_exp, size=nx * ny)
+    else:
+        raise ValueError(kmode)
+    ch = add_channels(rng, nx, ny, coeff, count=channels) if channels else []
+    part, _ = voronoi_partition(rng, nx, ny, nsub)
+    nkept = int(part.max()) + 1
+    agg = [voronoi_agglomeration(rng, nx, ny, part, nkept, ngroups)] if levels == 3 else []
+    nfree = (nx - 1) * (ny - 1)
+    f = rng.uniform(-1.0, 1.0, size=(nrhs, nfree))
+    sizes = np.bincount(part, minlength=nkept)
+    return Problem(nx=nx, ny=ny, coeff=coeff, part=part, nsub=nkept, levels=levels, agglom=agg,
+                   constraints=constraints, tau=tau, f=f, element=element, name=name,
+                   meta={"channels": ch, "voronoi": True, "elements_min": int(sizes.min()),
+                         "elements_max": int(sizes.max())})
+
+
 CONFIG_NAMES = {
     1: "two-level c+e, 32x32 Q1, 4x4 subs (H/h=8), k=1",
     2: "adaptive three-level, 256x256 Q1, 16x16 subs (H/h=16), 4x4 groups, "

@@ -22,6 +22,7 @@ pytestmark = pytest.mark.gpu
 
 def _case(name):
     sq = synth.square_problem
+    vo = synth.voronoi_problem
     return {
         "config1": lambda: synth.config(1),
         "corners_kjump": lambda: sq(24, 3, kmode="loguniform", kmax_exp=4, seed=21),
@@ -38,11 +39,23 @@ def _case(name):
                                     kmode="loguniform", kmax_exp=6, channels=3, seed=27),
         "corners3": lambda: sq(48, 6, levels=3, groups=(3, 3), kmode="loguniform", kmax_exp=2, seed=28),
         "single_sub": lambda: sq(10, 1, kmode="loguniform", kmax_exp=1, seed=29),
+        # H/h = 32: 1089 local dofs, edges of 31 nodes
+        "adaptive2_h32": lambda: sq(128, 4, constraints="adaptive", tau=10.0, kmode="loguniform", kmax_exp=4,
+                                    channels=2, seed=35),
+        # uneven substructures: Voronoi regions of uniform seed points
+        "voronoi2": lambda: vo(40, 12, seed=31),
+        "voronoi_adaptive2": lambda: vo(48, 20, constraints="adaptive", tau=3.0, kmode="loguniform",
+                                        kmax_exp=3, channels=2, seed=32),
+        "voronoi_adaptive3": lambda: vo(64, 40, levels=3, ngroups=6, constraints="adaptive", tau=4.0,
+                                        kmode="loguniform", kmax_exp=3, channels=2, seed=33),
+        "voronoi_adaptive3_large": lambda: vo(128, 48, levels=3, ngroups=8, constraints="adaptive", tau=10.0,
+                                              kmode="loguniform", kmax_exp=4, channels=2, seed=34),
     }[name]()
 
 
 CASES = ["config1", "corners_kjump", "ce_ragged", "rect", "p1", "adaptive2", "adaptive3", "adaptive3_h16",
-         "corners3", "single_sub"]
+         "corners3", "single_sub", "adaptive2_h32", "voronoi2", "voronoi_adaptive2", "voronoi_adaptive3",
+         "voronoi_adaptive3_large"]
 
 
 @pytest.mark.parametrize("name", CASES)
@@ -75,14 +88,16 @@ def test_solve_and_apply_match_oracle(name):
         S.close()
 
 
+@pytest.mark.parametrize("case", ["adaptive3", "voronoi_adaptive3"])
 @pytest.mark.parametrize("path", ["coop", "fused", "levels", "wide"])
-def test_deep_level_paths(path, monkeypatch):
+def test_deep_level_paths(path, case, monkeypatch):
     """Levels >= 2 run in one cooperative launch with one workgroup per
     level-2 substructure (one deep level), in one fused workgroup, in one
     launch per phase and level, or (one deep level) as row blocks of dense
     K_II^-1 and K_GI K_II^-1 over many workgroups; all must match the oracle."""
     monkeypatch.setenv("BDDC_DEEP_PATH", path)
-    prob = _case("adaptive3")
+    prob = _case(case)
+    print(f"deep path {path} case {case}", flush=True)
     S, B, ug, it, rr, o = run_pair(prob)
     try:
         assert abs(it - o["iters"]) <= 1
@@ -155,7 +170,7 @@ def test_pcg_graph_replays_match_direct_launches(deep, monkeypatch):
         S.close()
 
 
-@pytest.mark.parametrize("path", ["default", "lds16_global", "sweep32", "eig_workgroup"])
+@pytest.mark.parametrize("path", ["default", "lds16_global", "sweep32", "eig_workgroup", "pair_global"])
 def test_setup_kernel_paths(path, monkeypatch):
     """The setup runs with 64-wide Cholesky panels and a matrix-core trailing
     update plus LDS-resident Gauss-Jordan factorizations, and the level-1
@@ -163,7 +178,9 @@ def test_setup_kernel_paths(path, monkeypatch):
     two workgroups per CU, on large grids); or with 16-wide panels on the
     vector units, global-memory factorizations and 16-row blocked sweeps.
     The pair eigenproblems run one wave per edge (default) or one
-    256-thread workgroup per edge.  Both must give the oracle's preconditioner and solution (H/h = 16,
+    256-thread workgroup per edge; the pair Schur complements and
+    eigenproblems work in LDS (default) or in a global workspace (used for
+    interfaces and edges too large for LDS).  Both must give the oracle's preconditioner and solution (H/h = 16,
     ragged 64-column panels)."""
     if path == "lds16_global":
         monkeypatch.setenv("BDDC_CHOL_PATH", "lds16")
@@ -173,6 +190,8 @@ def test_setup_kernel_paths(path, monkeypatch):
         monkeypatch.setenv("BDDC_SWEEP_BW", "32")
     if path == "eig_workgroup":
         monkeypatch.setenv("BDDC_EIG_PATH", "wg")
+    if path == "pair_global":
+        monkeypatch.setenv("BDDC_PAIR_WS", "global")
     prob = _case("adaptive3_h16")
     print(f"setup kernel path {path}", flush=True)
     S, B, ug, it, rr, o = run_pair(prob)

@@ -411,3 +411,25 @@ def test_p1_elements_run_through_bddc():
     ev = _dense_MA_eigs(B)
     assert ev[0] >= 1 - 1e-10
     assert abs(ev[-1] - _brute_omega(B.levels[0])) <= 1e-8 * ev[-1]
+
+
+@pytest.mark.parametrize("seed", [41, 42])
+def test_voronoi_partition_spectrum_and_adaptive_target(seed):
+    """Uneven substructures (Voronoi regions, promoted corners where a pair
+    shares none): lambda_min(M^-1 A) >= 1, two-level lambda_max = omega, and
+    the adaptive selection brings every pair bound down to tau."""
+    p = synth.voronoi_problem(16, 6, constraints="corners", kmode="loguniform", kmax_exp=2.0, seed=seed)
+    B = BDDC(p)
+    ev = _dense_MA_eigs(B)
+    assert ev[0] >= 1.0 - 1e-10
+    om = _brute_omega(B.levels[0])
+    assert abs(ev[-1] - om) <= 1e-8 * om
+    tau = 1.5
+    pa = synth.voronoi_problem(16, 6, constraints="adaptive", tau=tau, kmode="loguniform", kmax_exp=2.0,
+                               seed=seed)
+    Ba = BDDC(pa)
+    assert all(w <= tau * (1 + 1e-9) for w in Ba.omega_levels)
+    eva = _dense_MA_eigs(Ba)
+    assert eva[0] >= 1.0 - 1e-10
+    assert eva[-1] <= _brute_omega(Ba.levels[0]) * (1 + 1e-8)
+    assert eva[-1] <= ev[-1] + 1e-9
