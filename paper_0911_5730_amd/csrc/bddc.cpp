@@ -405,10 +405,12 @@ struct bddc_ctx {
   double* AL = nullptr;
   int ncL = 0;
   int* status = nullptr;
-  // PCG on the level-1 interface
-  double *x = nullptr, *r = nullptr, *p = nullptr, *zv = nullptr, *partial = nullptr;
-  bddc::PcgScalars* sc = nullptr;
-  bddc::PcgScalars* sc_host = nullptr;   // pinned
+  // PCG on the level-1 interface; the per-column state (vectors, partials,
+  // scalars) sits in its own arena, sized for cols_cap columns
+  double* partial = nullptr;
+  bddc::PcgScalars* sc_host = nullptr;   // pinned, kMaxRhs columns
+  bddc::Arena cols_arena;
+  int cols_cap = 0;
   int nblk = 1;
   bddc::PcgDev pcg;
   // deep levels (2 .. L-1) and the coarsest solve in one workgroup when small
@@ -420,6 +422,7 @@ struct bddc_ctx {
   bool coop_launch = false;   // use the cooperative launch API
   double coop_bytes = 0;      // algorithmic bytes of one launch
   hipGraphExec_t graph_exec = nullptr;   // one chunk of PCG launches (captured on first use)
+  int graph_nrhs = 0;                    // columns of the captured chunk
   bool graph_off = false;
   bool wide_deep = false;     // one deep level in row-block launches (WideDev)
   bddc::WideDev wide;
@@ -1277,16 +1280,20 @@ static void apply_deep_level(bddc_ctx* h, int li, const double* r, double* u, hi
 }
 
 // level-1 coarse right-hand side (the level-1 b) -> level-1 coarse solution (level-1 uc)
-static void run_deep(bddc_ctx* h, hipStream_t st) {
+// Levels >= 2 and the coarsest solve for the level-1 coarse contributions b1
+// (local coarse flat), leaving the level-1 coarse correction in uc.
+static void run_deep_at(bddc_ctx* h, hipStream_t st, const double* b1, double* uc) {
   Level& l1 = *h->levels[0];
   if (h->levels.size() == 1) {
-    launch_coarse_gather(st, l1.nc, l1.d.csh_ptr, l1.d.csh_flat, l1.d.b, l1.d.rc, l1.dev.stop);
-    launch_coarsest_solve(st, l1.nc, h->AL, l1.d.rc, l1.d.uc, l1.dev.stop);
+    launch_coarse_gather(st, l1.nc, l1.d.csh_ptr, l1.d.csh_flat, b1, l1.d.rc, l1.dev.stop);
+    launch_coarsest_solve(st, l1.nc, h->AL, l1.d.rc, uc, l1.dev.stop);
     return;
   }
   if (h->coop_deep) {
     CoopDev C = h->coop;
     C.stop = l1.dev.stop;
+    C.b1 = b1;
+    C.u2 = uc;
     timing::Scope ts("deep", h->coop_bytes, 0);
     launch_deep_coop(st, C, h->coop_launch);
     return;
@@ -1294,6 +1301,8 @@ static void run_deep(bddc_ctx* h, hipStream_t st) {
   if (h->wide_deep) {
     Level& l2 = *h->levels[1];
     WideDev W = h->wide;
+    W.b1 = b1;
+    W.u2 = uc;
     W.stop = l1.dev.stop;
     W.L.stop = l1.dev.stop;
     LevelDev L2 = l2.dev;
@@ -1307,12 +1316,19 @@ static void run_deep(bddc_ctx* h, hipStream_t st) {
   if (h->fused_deep) {
     DeepArgs A = h->deep;
     A.stop = l1.dev.stop;
+    A.b1 = b1;
+    A.uvec[0] = uc;
     timing::Scope ts("deep", 0, 0);
     launch_deep(st, A);
     return;
   }
-  launch_coarse_gather(st, l1.nc, l1.d.csh_ptr, l1.d.csh_flat, l1.d.b, l1.d.rc, l1.dev.stop);
-  apply_deep_level(h, 1, l1.d.rc, l1.d.uc, st);
+  launch_coarse_gather(st, l1.nc, l1.d.csh_ptr, l1.d.csh_flat, b1, l1.d.rc, l1.dev.stop);
+  apply_deep_level(h, 1, l1.d.rc, uc, st);
+}
+
+static void run_deep(bddc_ctx* h, hipStream_t st) {
+  Level& l1 = *h->levels[0];
+  run_deep_at(h, st, l1.d.b, l1.d.uc);
 }
 
 // full-space preconditioner of the level-1 problem (bddc_apply)
@@ -1701,30 +1717,88 @@ static bool graph_chunk(bddc_ctx* h, hipStream_t st, F&& enqueue) {
   return true;
 }
 
-static int pcg_one(bddc_ctx* h, const double* f, double* u, double rtol, int maxit, double* relres) {
+// The per-column PCG state for R columns (reallocated when a solve needs more
+// columns than the arena holds; a captured chunk keeps the old addresses, so
+// it is dropped).
+static void ensure_columns(bddc_ctx* h, int R) {
+  if (h->cols_cap >= R) return;
+  Level& l1 = *h->levels[0];
+  PcgDev& P = h->pcg;
+  BDDC_HIP(hipStreamSynchronize(h->stream));
+  h->cols_arena.release(h->stream);
+  if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+  h->graph_exec = nullptr;
+  h->graph_nrhs = 0;
+  auto pad = [](int64_t n) { return (int)(((std::max<int64_t>(n, 1) * 8 + 255) / 256) * 32); };   // 256-byte columns
+  P.ld_if = pad(P.nif);
+  P.ld_flat = pad(l1.nflat_g);
+  P.ld_cflat = pad(l1.nflat_c);
+  P.ld_coarse = pad(l1.nc);
+  P.ld_sub = pad(P.nsub1);
+  P.ld_blk = pad(P.nblk);
+  Arena& A = h->cols_arena;
+  auto lay = [&] {
+    P.x = A.take<double>((size_t)R * P.ld_if);
+    P.r[0] = A.take<double>((size_t)R * P.ld_if);
+    P.r[1] = A.take<double>((size_t)R * P.ld_if);
+    P.p[0] = A.take<double>((size_t)R * P.ld_if);
+    P.p[1] = A.take<double>((size_t)R * P.ld_if);
+    P.z = A.take<double>((size_t)R * P.ld_if);
+    P.pq_part = A.take<double>((size_t)R * P.ld_sub);
+    P.rr_part = A.take<double>((size_t)R * P.ld_sub);
+    P.rz_part[0] = A.take<double>((size_t)R * P.ld_blk);
+    P.rz_part[1] = A.take<double>((size_t)R * P.ld_blk);
+    P.qloc = A.take<double>((size_t)R * P.ld_flat);
+    P.da = A.take<double>((size_t)R * P.ld_flat);
+    P.b = A.take<double>((size_t)R * P.ld_cflat);
+    P.uc = A.take<double>((size_t)R * P.ld_coarse);
+    P.sc = A.take<PcgScalars>(R);
+  };
+  A.reset_sizing();
+  lay();
+  A.allocate(h->stream);
+  lay();
+  h->cols_cap = R;
+}
+
+// PCG on the level-1 interface for R <= kMaxRhs right-hand sides at once
+// (columns of f and u at stride ld).  Each column runs its own recurrences
+// and convergence test; the launches of one iteration serve every column
+// still iterating.  Returns the number of columns that did not converge.
+static int pcg_block(bddc_ctx* h, const double* f, double* u, int64_t ld, int R, double rtol, int maxit,
+                     int32_t* iters_out, double* relres) {
   hipStream_t st = h->stream;
   Level& l1 = *h->levels[0];
+  ensure_columns(h, R);
+  PcgDev& P = h->pcg;
+  P.nrhs = R;
   const int nif = (int)l1.iface_dof.size();
   const int nb = h->nblk;
   const int nbf = std::min(1024, std::max(1, (int)((h->n_free + kNT - 1) / kNT)));
   PcgScalars* sch = h->sc_host;
-  std::memset(sch, 0, offsetof(PcgScalars, alphas));
-  sch->maxit = maxit;
-  sch->rtol2 = rtol * rtol;   // thr2 = rtol^2 ||f||^2 is formed on the device
-  sch->it_base = 1;
-  BDDC_HIP(hipMemcpyAsync(h->sc, sch, offsetof(PcgScalars, alphas), hipMemcpyHostToDevice, st));
-  launch_dot_partial(st, nbf, (int)h->n_free, f, f, h->partial);
-  launch_scalar(st, 4, nbf, h->partial, h->sc);                   // bb, thr2 = rtol^2 bb
+  for (int c = 0; c < R; ++c) {
+    std::memset(&sch[c], 0, offsetof(PcgScalars, alphas));
+    sch[c].maxit = maxit;
+    sch[c].rtol2 = rtol * rtol;   // thr2 = rtol^2 ||f||^2 is formed on the device
+    sch[c].it_base = 1;
+    BDDC_HIP(hipMemcpyAsync(P.sc + c, sch + c, offsetof(PcgScalars, alphas), hipMemcpyHostToDevice, st));
+  }
   const bool sweep = use_sweep(l1.nmax);
-  if (sweep)                                                       // y = L^{-1} f_I, t = L_GI y
-    launch_sweep_pre(st, l1.dev, f);
-  else
-    launch_apply_pre(st, l1.dev, l1.nImax, l1.ngmax, f);
-  launch_condense(st, nif, l1.d.sh_ptr, l1.d.sh_flat, l1.d.iface_dof, f, l1.d.t, h->r, h->x);
-  launch_dot_partial(st, nb, nif, h->r, h->r, h->partial);
-  launch_scalar(st, 5, nb, h->partial, h->sc);                    // rr0, done if already small
+  for (int c = 0; c < R; ++c) {
+    const double* fc = f + (size_t)c * ld;
+    double* rc = P.r[0] + (size_t)c * P.ld_if;
+    launch_dot_partial(st, nbf, (int)h->n_free, fc, fc, h->partial);
+    launch_scalar(st, 4, nbf, h->partial, P.sc + c);                 // bb, thr2 = rtol^2 bb
+    if (sweep)                                                       // y = L^{-1} f_I, t = L_GI y
+      launch_sweep_pre(st, l1.dev, fc);
+    else
+      launch_apply_pre(st, l1.dev, l1.nImax, l1.ngmax, fc);
+    launch_condense(st, nif, l1.d.sh_ptr, l1.d.sh_flat, l1.d.iface_dof, fc, l1.d.t, rc, P.x + (size_t)c * P.ld_if);
+    launch_dot_partial(st, nb, nif, rc, rc, h->partial);
+    launch_scalar(st, 5, nb, h->partial, P.sc + c);                  // rr0, done if already small
+  }
 
-  // every kernel below returns at once after convergence
+  // every kernel below returns at once once every column has finished
   struct StopGuard {
     bddc_ctx* h;
     ~StopGuard() {
@@ -1732,77 +1806,105 @@ static int pcg_one(bddc_ctx* h, const double* f, double* u, double rtol, int max
       timing::current_tag = -1;
     }
   } guard_stop{h};
-  for (auto& lvp : h->levels) lvp->dev.stop = &h->sc->done;
-  const PcgDev& P = h->pcg;
+  for (auto& lvp : h->levels) lvp->dev.stop = &P.sc[0].all_done;
   const size_t tmark = timing::mark();
 
   // Iteration k: matvec, update + restriction, deep levels, prolongation with
   // the convergence test, post.  The test sits in the prolongation, so at the
   // converged iteration K the update, restriction and deep levels still run
   // (tagged k - 1: they work iff k <= K) and the rest return at once.  The
-  // kernels take their iteration as sc->it_base + u (u < 0: iteration 0), so
+  // kernels take their iteration as sc[0].it_base + u (u < 0: iteration 0), so
   // one chunk of launches is the same for every chunk and can be replayed as a
-  // HIP graph.
-  auto apply_iface = [&](hipStream_t q, int u, int it) {
+  // HIP graph.  The deep levels run once per column.
+  auto apply_iface = [&](hipStream_t q, int uu, int it) {
     timing::current_tag = it - 1;
     {
       timing::Scope ts("apply_restrict", it > 0 ? h->by_ur_prec : h->by_r_prec, 0);
-      launch_pcg_update_restrict(q, l1.dev, l1.ngmax, l1.nrmax, l1.ncsmax, P, u);
+      launch_pcg_update_restrict(q, l1.dev, l1.ngmax, l1.nrmax, l1.ncsmax, P, uu);
     }
-    if (P.fin && it > 0) launch_pcg_sum(q, P, 1, u);
-    run_deep(h, q);
+    if (P.fin && it > 0) launch_pcg_sum(q, P, 1, uu);
+    for (int c = 0; c < R; ++c)
+      run_deep_at(h, q, P.b + (size_t)c * P.ld_cflat, const_cast<double*>(P.uc) + (size_t)c * P.ld_coarse);
     timing::current_tag = it;
     {
       timing::Scope ts("apply_average", h->by_average, 0);
-      launch_pcg_prolong_post(q, l1.dev, P, l1.d.uc, u);
+      launch_pcg_prolong_post(q, l1.dev, P, uu);
     }
-    if (P.fin) launch_pcg_sum(q, P, 2, u);
+    if (P.fin) launch_pcg_sum(q, P, 2, uu);
   };
   const int check = 8;   // iterations between host convergence checks
   auto chunk = [&](hipStream_t q, int it0) {
-    for (int u = 0; u < check; ++u) {
-      const int it = it0 + u;
+    for (int uu = 0; uu < check; ++uu) {
+      const int it = it0 + uu;
       timing::current_tag = it;
       {
         // the product of iteration k works iff k <= K (K = converged iteration)
         timing::Scope ts("schur_local", h->by_schur_packed, 0, -1);
-        launch_pcg_matvec(q, l1.dev, l1.ngmax, P, u);
+        launch_pcg_matvec(q, l1.dev, l1.ngmax, P, uu);
       }
-      if (P.fin) launch_pcg_sum(q, P, 0, u);
-      apply_iface(q, u, it);
+      if (P.fin) launch_pcg_sum(q, P, 0, uu);
+      apply_iface(q, uu, it);
     }
     launch_pcg_advance(q, P, check);
   };
   // z_0 = M r_0 and its r.z partials (parity 0)
   apply_iface(st, -1, 0);
+  if (h->graph_exec && h->graph_nrhs != R) {
+    (void)hipGraphExecDestroy(h->graph_exec);
+    h->graph_exec = nullptr;
+  }
   int it = 0;
   while (it < maxit) {
-    // iterations past maxit or convergence return at once (sc->done)
-    if (!graph_chunk(h, st, [&](hipStream_t q) { chunk(q, it + 1); })) chunk(st, it + 1);
+    // iterations past maxit or convergence return at once (sc[c].done)
+    if (graph_chunk(h, st, [&](hipStream_t q) { chunk(q, it + 1); }))
+      h->graph_nrhs = R;
+    else
+      chunk(st, it + 1);
     it += check;
-    BDDC_HIP(hipMemcpyAsync(sch, h->sc, offsetof(PcgScalars, alphas), hipMemcpyDeviceToHost, st));
+    BDDC_HIP(hipMemcpyAsync(sch, P.sc, offsetof(PcgScalars, alphas), hipMemcpyDeviceToHost, st));
     BDDC_HIP(hipStreamSynchronize(st));
-    if (sch->done) break;
+    if (sch[0].all_done) break;
   }
   timing::current_tag = -1;
-  if (sweep)
-    launch_sweep_recover(st, l1.dev, h->x, u);
-  else
-    launch_recover(st, l1.dev, l1.nImax, l1.ngmax, h->x, u);
+  // interior recovery u_I = L^-T (y - L_GI^T x) needs y = L^-1 f_I of its own
+  // column: the set-up pass above left the last column's y (the level's stop
+  // flag is raised by now, so these launches go without it)
+  LevelDev L1 = l1.dev;
+  L1.stop = nullptr;
+  for (int c = R - 1; c >= 0; --c) {
+    const double* xc = P.x + (size_t)c * P.ld_if;
+    if (c < R - 1) {
+      if (sweep)
+        launch_sweep_pre(st, L1, f + (size_t)c * ld);
+      else
+        launch_apply_pre(st, L1, l1.nImax, l1.ngmax, f + (size_t)c * ld);
+    }
+    if (sweep)
+      launch_sweep_recover(st, L1, xc, u + (size_t)c * ld);
+    else
+      launch_recover(st, L1, l1.nImax, l1.ngmax, xc, u + (size_t)c * ld);
+  }
   int dev_status = 0;
-  BDDC_HIP(hipMemcpyAsync(sch, h->sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, st));
+  for (int c = 0; c < R; ++c) BDDC_HIP(hipMemcpyAsync(sch + c, P.sc + c, sizeof(PcgScalars), hipMemcpyDeviceToHost, st));
   BDDC_HIP(hipMemcpyAsync(&dev_status, h->status, sizeof(int), hipMemcpyDeviceToHost, st));
   BDDC_HIP(hipStreamSynchronize(st));
   if (dev_status & 4) fail(BDDC_EDEVICE, "a grid barrier of the deep-level kernel timed out");
-  const int iters = sch->iters;
+  int maxiters = 0, failed = 0;
+  for (int c = 0; c < R; ++c) {
+    const PcgScalars& S = sch[c];
+    iters_out[c] = S.iters;
+    relres[c] = S.bb > 0 ? std::sqrt(S.rr / S.bb) : 0.0;
+    if (S.done != 1) ++failed;
+    maxiters = std::max(maxiters, S.iters);
+  }
   // launches of iteration k work iff k < K (the product: k <= K, tagged k-1)
-  timing::prune(tmark, iters);
-  *relres = sch->bb > 0 ? std::sqrt(sch->rr / sch->bb) : 0.0;
-  std::vector<double> al(sch->alphas, sch->alphas + std::min(iters, kMaxHist));
-  std::vector<double> be(sch->betas, sch->betas + std::max(0, std::min(iters, kMaxHist) - 1));
+  timing::prune(tmark, maxiters);
+  const PcgScalars& S = sch[R - 1];
+  std::vector<double> al(S.alphas, S.alphas + std::min(S.iters, kMaxHist));
+  std::vector<double> be(S.betas, S.betas + std::max(0, std::min(S.iters, kMaxHist) - 1));
   h->info.kappa = lanczos_kappa(al, be);
-  h->info.last_iters = iters;
-  return sch->done == 1 ? iters : -iters - 1;
+  h->info.last_iters = S.iters;
+  return failed;
 }
 
 static int64_t model_bytes(const bddc_ctx* h, bool apply) {
@@ -1869,6 +1971,7 @@ void release(bddc_ctx* h) {
   h->top.release(st);
   h->coop_arena.release(st);
   h->wide_arena.release(st);
+  h->cols_arena.release(st);
   if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
   h->graph_exec = nullptr;
   pinned_release(h->sc_host);
@@ -1993,18 +2096,7 @@ bddc_status bddc_setup(const bddc_problem* p, void* hip_stream, bddc_handle* out
     int32_t* sub_flat_d = nullptr;
     const int nblk_avg = std::max(1, (nif + kNT / 8 - 1) / (kNT / 8));   // eight lanes per interface dof
     auto lay = [&] {
-      h->x = B.take<double>(nif);
-      h->r = B.take<double>(nif);
-      P.r[1] = B.take<double>(nif);
-      h->p = B.take<double>(nif);
-      P.p[1] = B.take<double>(nif);
-      h->zv = B.take<double>(nif);
       h->partial = B.take<double>(1024);
-      P.pq_part = B.take<double>(l1.nsub);
-      P.rr_part = B.take<double>(l1.nsub);
-      P.rz_part[0] = B.take<double>(nblk_avg);
-      P.rz_part[1] = B.take<double>(nblk_avg);
-      h->sc = B.take<PcgScalars>(1);
       P.phi_ptr = B.take<int32_t>(phi_ptr.size());
       P.phi_ids = B.take<int32_t>(nphi);
       P.phi_w = B.take<double>(nphi);
@@ -2029,15 +2121,10 @@ bddc_status bddc_setup(const bddc_problem* p, void* hip_stream, bddc_handle* out
     lay();
     B.allocate(h->stream);
     lay();
-    P.sc = h->sc;
-    P.x = h->x;
-    P.r[0] = h->r;
-    P.z = h->zv;
-    P.p[0] = h->p;
-    P.qloc = l1.d.qloc;
-    P.da = l1.d.v;
     P.nblk = nblk_avg;
     P.nif = nif;
+    P.nsub1 = l1.nsub;
+    ensure_columns(h, 1);
     {
       // sum the PCG partials once, in a one-block launch, when the consuming
       // blocks would each re-read more than a thousand of them
@@ -2092,7 +2179,7 @@ bddc_status bddc_setup(const bddc_problem* p, void* hip_stream, bddc_handle* out
     clk.lap("plan deep");
     Builder::finish(h);
     clk.lap("finish");
-    h->sc_host = static_cast<PcgScalars*>(pinned_acquire(sizeof(PcgScalars)));
+    h->sc_host = static_cast<PcgScalars*>(pinned_acquire(sizeof(PcgScalars) * kMaxRhs));
     // info
     std::memset(&h->info, 0, sizeof(h->info));
     h->info.n_free = h->n_free;
@@ -2137,10 +2224,13 @@ bddc_status bddc_solve(bddc_handle h, const double* f, double* u, int32_t nrhs, 
     if (maxit > kMaxHist) fail(BDDC_EINVAL, "maxit too large");
     hipStream_t saved = h->stream;
     h->stream = reinterpret_cast<hipStream_t>(hip_stream);
-    for (int c = 0; c < nrhs; ++c) {
-      const int k = pcg_one(h, f + (size_t)c * ld, u + (size_t)c * ld, rtol, maxit, &relres[c]);
-      iters[c] = k >= 0 ? k : -k - 1;
-      if (k < 0) noconv = true;
+    // blocks of up to kMaxRhs columns (BDDC_SOLVE_BLOCK=1: one column at a time)
+    const char* env = getenv("BDDC_SOLVE_BLOCK");
+    const int blk = env ? std::max(1, std::min(kMaxRhs, atoi(env))) : kMaxRhs;
+    for (int c = 0; c < nrhs; c += blk) {
+      const int R = std::min(blk, nrhs - c);
+      if (pcg_block(h, f + (size_t)c * ld, u + (size_t)c * ld, ld, R, rtol, maxit, iters + c, relres + c) > 0)
+        noconv = true;
     }
     h->stream = saved;
   });

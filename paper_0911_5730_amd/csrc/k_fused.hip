@@ -283,23 +283,28 @@ __device__ inline double block_sum_of(const double* __restrict__ v, int n, doubl
 // same value) into the scalar `which` (0 p^T S p, 1 r.r, 2 r.z of iteration
 // it).  With many blocks on both sides this replaces every consuming block's
 // own pass over all the partials.
+// One block per column.
 __global__ void __launch_bounds__(kNT) k_pcg_sum(PcgDev P, int which, int u) {
   __shared__ double red[kNT];
-  if (P.sc->done) return;
-  const int it = u < 0 ? 0 : P.sc->it_base + u;
-  const double* part = which == 0 ? P.pq_part : (which == 1 ? P.rr_part : P.rz_part[it & 1]);
+  const int c = blockIdx.x;
+  PcgScalars* S = P.sc + c;
+  if (P.sc[0].all_done || S->done) return;
+  const int it = u < 0 ? 0 : P.sc[0].it_base + u;
+  const double* part = which == 0 ? P.pq_part + (size_t)c * P.ld_sub
+                                  : (which == 1 ? P.rr_part + (size_t)c * P.ld_sub
+                                                : P.rz_part[it & 1] + (size_t)c * P.ld_blk);
   const int n = which == 2 ? P.nblk : P.nsub1;
   const double v = block_sum_of(part, n, red);
   if (threadIdx.x == 0) {
-    if (which == 0) P.sc->pqs = v;
-    else if (which == 1) P.sc->rrs = v;
-    else P.sc->rzs[it & 1] = v;
+    if (which == 0) S->pqs = v;
+    else if (which == 1) S->rrs = v;
+    else S->rzs[it & 1] = v;
   }
 }
 
 // the next chunk of PCG launches starts n iterations later
 __global__ void k_pcg_advance(PcgScalars* sc, int n) {
-  if (threadIdx.x == 0) sc->it_base += n;
+  if (threadIdx.x == 0) sc[0].it_base += n;
 }
 
 // PCG iteration k on the level-1 interface (Section 5) in four launches:
@@ -315,7 +320,11 @@ __global__ void k_pcg_advance(PcgScalars* sc, int n) {
 // never formed; r is double-buffered by iteration parity because sharers read
 // r_{k-1} while owners write r_k.  The average uses, per interface dof, the
 // sharers' rows of the delta-weighted coarse basis (built at setup), so the
-// prolongation needs no pass of its own.
+// prolongation needs no pass of its own.  With several right-hand sides every
+// launch loops over the columns still iterating with its operator entries
+// already loaded (registers or LDS): the operators are read once per
+// iteration for all columns, and each column's arithmetic is the
+// single-column arithmetic.
 // BF16 storage: the upper half of the IEEE binary32 pattern, rounded to
 // nearest with ties to even (finite inputs only).
 __device__ inline uint16_t f32_to_bf16(float x) {
@@ -410,8 +419,8 @@ __device__ inline double sym_row_part(const double* A, int m, int i, int c, int 
 __global__ void __launch_bounds__(kNT) k_pcg_matvec(LevelDev L, PcgDev P, int u) {
   extern __shared__ double sh[];
   __shared__ double red[kNT];
-  if (P.sc->done) return;
-  const int it = P.sc->it_base + u;
+  if (P.sc[0].all_done) return;
+  const int it = P.sc[0].it_base + u;
   const int s = blockIdx.x;
   const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
   const int nI = L.nint[s];
@@ -431,46 +440,53 @@ __global__ void __launch_bounds__(kNT) k_pcg_matvec(LevelDev L, PcgDev P, int u)
   const bool act = narrow && mc < nch;
   SymRowRegs<16, double> sv;
   if (narrow) sv.load(Sg, ng, mi, mc, nch);
-  double beta = 0.0;
-  if (it >= 2) {
-    double rz, rz0;
-    if (P.fin) {
-      rz = P.sc->rzs[(it - 1) & 1];
-      rz0 = P.sc->rzs[(it - 2) & 1];
-    } else {
-      rz = block_sum_of(P.rz_part[(it - 1) & 1], P.nblk, red);
-      rz0 = block_sum_of(P.rz_part[(it - 2) & 1], P.nblk, red);
+  for (int col = 0; col < P.nrhs; ++col) {
+    PcgScalars* S = P.sc + col;
+    if (S->done) continue;
+    double beta = 0.0;
+    if (it >= 2) {
+      double rz, rz0;
+      if (P.fin) {
+        rz = S->rzs[(it - 1) & 1];
+        rz0 = S->rzs[(it - 2) & 1];
+      } else {
+        rz = block_sum_of(P.rz_part[(it - 1) & 1] + (size_t)col * P.ld_blk, P.nblk, red);
+        rz0 = block_sum_of(P.rz_part[(it - 2) & 1] + (size_t)col * P.ld_blk, P.nblk, red);
+      }
+      beta = rz / rz0;
+      if (blockIdx.x == 0 && threadIdx.x == 0) S->betas[min(it - 2, kMaxHist - 1)] = beta;
     }
-    beta = rz / rz0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) P.sc->betas[min(it - 2, kMaxHist - 1)] = beta;
+    const size_t ci = (size_t)col * P.ld_if;
+    const double* pold = P.p[(it - 1) & 1] + ci;
+    double* pnew = P.p[it & 1] + ci;
+    const double* z = P.z + ci;
+    for (int a = tid; a < ng; a += kNT) {
+      const int f = g0 + a;
+      const int gi = L.gam_iid[f];
+      const bool own = P.shf4 ? P.shf4[f].x == f : L.sh_flat[L.sh_ptr[gi]] == f;
+      const double pv = (it >= 2) ? z[gi] + beta * pold[gi] : z[gi];
+      pl[a] = pv;
+      if (own) pnew[gi] = pv;
+    }
+    __syncthreads();
+    if (narrow) {
+      if (act) part[mi + mc * ng] = sv.dot(Sg, ng, mi, mc, nch, pl);
+    } else {
+      for (int i = tid; i < ng; i += kNT) part[i] = sym_row_part(Sg, ng, i, 0, 1, pl);
+    }
+    __syncthreads();
+    double e = 0.0;
+    const int nc = narrow ? nch : 1;
+    double* q = P.qloc + (size_t)col * P.ld_flat;
+    for (int i = tid; i < ng; i += kNT) {
+      double acc = 0.0;
+      for (int c = 0; c < nc; ++c) acc += part[i + c * ng];
+      q[g0 + i] = acc;
+      e += pl[i] * acc;
+    }
+    e = wg_sum(e, red);   // (ends with a barrier: pl and part are free again)
+    if (tid == 0) P.pq_part[(size_t)col * P.ld_sub + s] = e;
   }
-  const double* pold = P.p[(it - 1) & 1];
-  double* pnew = P.p[it & 1];
-  for (int a = tid; a < ng; a += kNT) {
-    const int f = g0 + a;
-    const int gi = L.gam_iid[f];
-    const bool own = P.shf4 ? P.shf4[f].x == f : L.sh_flat[L.sh_ptr[gi]] == f;
-    const double pv = (it >= 2) ? P.z[gi] + beta * pold[gi] : P.z[gi];
-    pl[a] = pv;
-    if (own) pnew[gi] = pv;
-  }
-  __syncthreads();
-  if (narrow) {
-    if (act) part[mi + mc * ng] = sv.dot(Sg, ng, mi, mc, nch, pl);
-  } else {
-    for (int i = tid; i < ng; i += kNT) part[i] = sym_row_part(Sg, ng, i, 0, 1, pl);
-  }
-  __syncthreads();
-  double e = 0.0;
-  const int nc = narrow ? nch : 1;
-  for (int i = tid; i < ng; i += kNT) {
-    double acc = 0.0;
-    for (int c = 0; c < nc; ++c) acc += part[i + c * ng];
-    P.qloc[g0 + i] = acc;
-    e += pl[i] * acc;
-  }
-  e = wg_sum(e, red);
-  if (tid == 0) P.pq_part[s] = e;
 }
 
 // Storage of T_rr and Psi in the precision forms: FP64 (kPrec 0), FP32 (1),
@@ -500,8 +516,8 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
   using PS = typename PrecForm<kPrec>::PS;
   extern __shared__ double sh[];
   __shared__ double red[kNT];
-  if (P.sc->done) return;
-  const int it = u < 0 ? 0 : P.sc->it_base + u;
+  if (P.sc[0].all_done) return;
+  const int it = u < 0 ? 0 : P.sc[0].it_base + u;
   const int s = blockIdx.x;
   const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
   const int ng = n - L.nint[s];
@@ -555,15 +571,23 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
     const float* Qg = P.Q32 + P.croff[s];
     for (int a = tid; a < nq; a += kNT) Ql[a] = Qg[a];
   }
+  bool staged = false;
+  for (int col = 0; col < P.nrhs; ++col) {
+  PcgScalars* S = P.sc + col;
+  if (S->done) continue;
+  const size_t ci = (size_t)col * P.ld_if, cf = (size_t)col * P.ld_flat;
   if (it == 0) {
-    for (int a = tid; a < ng; a += kNT) g[a] = L.delta[g0 + a] * P.r[0][L.gam_iid[g0 + a]];
+    for (int a = tid; a < ng; a += kNT) g[a] = L.delta[g0 + a] * P.r[0][ci + L.gam_iid[g0 + a]];
   } else {
-    const double rz = P.fin ? P.sc->rzs[(it - 1) & 1] : block_sum_of(P.rz_part[(it - 1) & 1], P.nblk, red);
-    const double pq = P.fin ? P.sc->pqs : block_sum_of(P.pq_part, P.nsub1, red);
+    const double rz = P.fin ? S->rzs[(it - 1) & 1]
+                            : block_sum_of(P.rz_part[(it - 1) & 1] + (size_t)col * P.ld_blk, P.nblk, red);
+    const double pq = P.fin ? S->pqs : block_sum_of(P.pq_part + (size_t)col * P.ld_sub, P.nsub1, red);
     const double alpha = rz / pq;
-    const double* rold = P.r[(it - 1) & 1];
-    double* rnew = P.r[it & 1];
-    const double* p = P.p[it & 1];
+    const double* rold = P.r[(it - 1) & 1] + ci;
+    double* rnew = P.r[it & 1] + ci;
+    const double* p = P.p[it & 1] + ci;
+    double* x = P.x + ci;
+    const double* ql = P.qloc + cf;
     double rr = 0.0;
     for (int a = tid; a < ng; a += kNT) {
       const int f = g0 + a;
@@ -573,31 +597,34 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
       if (P.shf4) {
         // the sharers' flat entries in one 16-byte load (-1 past the last)
         const int4 sf = P.shf4[f];
-        q += P.qloc[sf.x];
-        if (sf.y >= 0) q += P.qloc[sf.y];
-        if (sf.z >= 0) q += P.qloc[sf.z];
-        if (sf.w >= 0) q += P.qloc[sf.w];
+        q += ql[sf.x];
+        if (sf.y >= 0) q += ql[sf.y];
+        if (sf.z >= 0) q += ql[sf.z];
+        if (sf.w >= 0) q += ql[sf.w];
         own = sf.x == f;
       } else {
-        for (int k = L.sh_ptr[gi]; k < L.sh_ptr[gi + 1]; ++k) q += P.qloc[L.sh_flat[k]];
+        for (int k = L.sh_ptr[gi]; k < L.sh_ptr[gi + 1]; ++k) q += ql[L.sh_flat[k]];
         own = L.sh_flat[L.sh_ptr[gi]] == f;
       }
       const double ri = rold[gi] - alpha * q;
       g[a] = L.delta[f] * ri;
       if (own) {
         rnew[gi] = ri;
-        P.x[gi] += alpha * p[gi];
+        x[gi] += alpha * p[gi];
         rr += ri * ri;
       }
     }
     rr = wg_sum(rr, red);
-    if (tid == 0) P.rr_part[s] = rr;
+    if (tid == 0) P.rr_part[(size_t)col * P.ld_sub + s] = rr;
     if (s == 0 && tid == 0) {
-      P.sc->iters = it;
-      P.sc->alphas[min(it - 1, kMaxHist - 1)] = alpha;
+      S->iters = it;
+      S->alphas[min(it - 1, kMaxHist - 1)] = alpha;
     }
   }
-  if constexpr (kPrec == 2) pt.finish();
+  if constexpr (kPrec == 2) {
+    if (!staged) pt.finish();
+  }
+  staged = true;
   __syncthreads();
   // b = Psi^T g, one wave per coarse dof
   for (int k = wave, m = 0; k < ncs; k += kNT / 64, ++m) {
@@ -614,7 +641,7 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
-    if (lane == 0) L.b[L.coff[s] + k] = acc;
+    if (lane == 0) P.b[(size_t)col * P.ld_cflat + L.coff[s] + k] = acc;
   }
   if constexpr (kPrec == 2) {
     const int n_cr = P.ncr[s];
@@ -657,7 +684,7 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
     for (int i = tid; i < n_r; i += kNT) {
       double acc = 0.0;
       for (int c = 0; c < nch; ++c) acc += part[i + c * n_r];
-      P.da[g0 + i] = L.delta[g0 + i] * (acc * static_cast<double>(dinv[i]));
+      P.da[cf + g0 + i] = L.delta[g0 + i] * (acc * static_cast<double>(dinv[i]));
     }
   } else {
     if (narrow) {
@@ -674,10 +701,12 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
     for (int i = tid; i < n_r; i += kNT) {
       double acc = 0.0;
       for (int c = 0; c < nc; ++c) acc += part[i + c * n_r];
-      P.da[g0 + i] = L.delta[g0 + i] * acc;
+      P.da[cf + g0 + i] = L.delta[g0 + i] * acc;
     }
   }
-  for (int a = n_r + tid; a < ng; a += kNT) P.da[g0 + a] = 0.0;
+  for (int a = n_r + tid; a < ng; a += kNT) P.da[cf + g0 + a] = 0.0;
+  __syncthreads();   // g, part and x/v are taken by the next column
+  }
 }
 
 // The reduced-precision forms of the level-1 T_rr and Psi, one workgroup per
@@ -798,43 +827,56 @@ __global__ void __launch_bounds__(kNT) k_pack_pcg(LevelDev L, PcgDev P) {
 // records it), then per interface dof z = sum over sharers of delta T_rr g plus
 // the dof's row of the delta-weighted coarse basis times u_c  (ML-uBi-1), and
 // the per-block partial of r_k . z.
-__global__ void __launch_bounds__(kNT) k_pcg_prolong_post(LevelDev L, PcgDev P, const double* __restrict__ uc,
-                                                          int u) {
+__global__ void __launch_bounds__(kNT) k_pcg_prolong_post(LevelDev L, PcgDev P, int u) {
   __shared__ double red[kNT];
-  if (P.sc->done) return;
-  const int it = u < 0 ? 0 : P.sc->it_base + u;
+  __shared__ int live[kMaxRhs];
+  if (P.sc[0].all_done) return;
+  const int it = u < 0 ? 0 : P.sc[0].it_base + u;
   const bool check = it > 0;
   const int parity = it & 1;
-  if (check) {
-    const double rr = P.fin ? P.sc->rrs : block_sum_of(P.rr_part, P.nsub1, red);
-    const bool conv = rr <= P.sc->thr2;
-    const bool maxed = P.sc->iters >= P.sc->maxit;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      P.sc->rr = rr;
-      if (conv || maxed) P.sc->done = conv ? 1 : 2;
+  // the columns' states on entry (block 0 updates them below)
+  if (threadIdx.x < P.nrhs) live[threadIdx.x] = P.sc[threadIdx.x].done == 0;
+  __syncthreads();
+  int going = 0;
+  for (int col = 0; col < P.nrhs; ++col) {
+    if (!live[col]) continue;
+    PcgScalars* S = P.sc + col;
+    if (check) {
+      const double rr = P.fin ? S->rrs : block_sum_of(P.rr_part + (size_t)col * P.ld_sub, P.nsub1, red);
+      const bool conv = rr <= S->thr2;
+      const bool maxed = S->iters >= S->maxit;
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        S->rr = rr;
+        if (conv || maxed) S->done = conv ? 1 : 2;
+      }
+      if (conv || maxed) continue;
     }
-    if (conv || maxed) return;
+    ++going;
+    // eight lanes per interface dof, fixed-order reduction over the eight
+    const size_t ci = (size_t)col * P.ld_if;
+    const double* r = P.r[parity] + ci;
+    const double* da = P.da + (size_t)col * P.ld_flat;
+    const double* uc = P.uc + (size_t)col * P.ld_coarse;
+    const int gi = (blockIdx.x * kNT + threadIdx.x) >> 3;
+    const int sub = threadIdx.x & 7;
+    double acc = 0.0;
+    if (gi < P.nif) {
+      const int k0 = L.sh_ptr[gi], k1 = L.sh_ptr[gi + 1];
+      for (int k = k0 + sub; k < k1; k += 8) acc += da[L.sh_flat[k]];
+      for (int j = P.phi_ptr[gi] + sub; j < P.phi_ptr[gi + 1]; j += 8) acc += P.phi_w[j] * uc[P.phi_ids[j]];
+    }
+    acc += __shfl_xor(acc, 1);
+    acc += __shfl_xor(acc, 2);
+    acc += __shfl_xor(acc, 4);
+    double rz = 0.0;
+    if (gi < P.nif && sub == 0) {
+      P.z[ci + gi] = acc;
+      rz = acc * r[gi];
+    }
+    rz = wg_sum(rz, red);
+    if (threadIdx.x == 0) P.rz_part[parity][(size_t)col * P.ld_blk + blockIdx.x] = rz;
   }
-  // eight lanes per interface dof, fixed-order reduction over the eight
-  const double* r = P.r[parity];
-  const int gi = (blockIdx.x * kNT + threadIdx.x) >> 3;
-  const int sub = threadIdx.x & 7;
-  double acc = 0.0;
-  if (gi < P.nif) {
-    const int k0 = L.sh_ptr[gi], k1 = L.sh_ptr[gi + 1];
-    for (int k = k0 + sub; k < k1; k += 8) acc += P.da[L.sh_flat[k]];
-    for (int j = P.phi_ptr[gi] + sub; j < P.phi_ptr[gi + 1]; j += 8) acc += P.phi_w[j] * uc[P.phi_ids[j]];
-  }
-  acc += __shfl_xor(acc, 1);
-  acc += __shfl_xor(acc, 2);
-  acc += __shfl_xor(acc, 4);
-  double rz = 0.0;
-  if (gi < P.nif && sub == 0) {
-    P.z[gi] = acc;
-    rz = acc * r[gi];
-  }
-  rz = wg_sum(rz, red);
-  if (threadIdx.x == 0) P.rz_part[parity][blockIdx.x] = rz;
+  if (going == 0 && blockIdx.x == 0 && threadIdx.x == 0) P.sc[0].all_done = 1;
 }
 
 // Rows of the averaged coarse basis: for interface dof gi, in sharer order,
@@ -868,7 +910,7 @@ void launch_pcg_matvec(hipStream_t st, const LevelDev& L, int ngmax, const PcgDe
   launch_kernel(k_pcg_matvec, dim3(L.nsub), dim3(kNT), lds, st, L, P, u);
 }
 void launch_pcg_sum(hipStream_t st, const PcgDev& P, int which, int u) {
-  launch_kernel(k_pcg_sum, dim3(1), dim3(kNT), 0, st, P, which, u);
+  launch_kernel(k_pcg_sum, dim3(P.nrhs), dim3(kNT), 0, st, P, which, u);
 }
 void launch_pcg_advance(hipStream_t st, const PcgDev& P, int n) {
   launch_kernel(k_pcg_advance, dim3(1), dim3(64), 0, st, P.sc, n);
@@ -897,8 +939,8 @@ void launch_round_factors(hipStream_t st, const LevelDev& L, const PcgDev& P, in
   const size_t lds = P.prec == 2 ? sizeof(double) * (2 * (size_t)nrmax * nrmax + 2 * (size_t)nrmax * ncrmax + nrmax) : 0;
   launch_kernel(k_round_factors, dim3(L.nsub), dim3(kNT), lds, st, L, P, nrmax, ncrmax, Cr, status);
 }
-void launch_pcg_prolong_post(hipStream_t st, const LevelDev& L, const PcgDev& P, const double* uc, int u) {
-  launch_kernel(k_pcg_prolong_post, dim3(P.nblk), dim3(kNT), 0, st, L, P, uc, u);
+void launch_pcg_prolong_post(hipStream_t st, const LevelDev& L, const PcgDev& P, int u) {
+  launch_kernel(k_pcg_prolong_post, dim3(P.nblk), dim3(kNT), 0, st, L, P, u);
 }
 void launch_build_phi(hipStream_t st, const LevelDev& L, int nif, const int32_t* sub_of_flat, const int32_t* phi_ptr,
                       int32_t* phi_ids, double* phi_w, const float* psi32) {

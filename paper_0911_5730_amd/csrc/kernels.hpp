@@ -207,7 +207,22 @@ struct PcgDev {
   const float* Psi32 = nullptr;     // FP32 Psi (offsets psioff)
   const int32_t* ncr = nullptr;     // constraint rows on the r dofs, per substructure
   const int64_t* croff = nullptr;
+  // Blocked right-hand sides: column c of every PCG vector sits at c times
+  // the stride of its kind, and sc[c] holds column c's scalars (sc[0] also
+  // the chunk's iteration base and the all-columns-finished flag).  Each
+  // launch reads an operator block once and applies it to every column still
+  // iterating; a finished column's state is left as it was.
+  int nrhs = 1;
+  int ld_if = 0;       // interface vectors x, r, p, z
+  int ld_flat = 0;     // interface flat: qloc, da
+  int ld_cflat = 0;    // local coarse flat: b (level-1 coarse contributions)
+  int ld_coarse = 0;   // level-1 coarse dofs: uc
+  int ld_sub = 0;      // per-substructure partials: pq_part, rr_part
+  int ld_blk = 0;      // per-block partials: rz_part
+  double* b = nullptr;         // level-1 coarse contributions Psi^T g, per column
+  const double* uc = nullptr;  // level-1 coarse correction, per column
 };
+constexpr int kMaxRhs = 8;   // columns of one blocked solve
 
 constexpr int kMaxHist = 4096;
 
@@ -216,7 +231,8 @@ struct PcgScalars {
   double rzs[2], pqs, rrs;   // summed partials of the fused iteration (r.z by parity, p^T S p, r.r)
   int32_t it_base;           // PCG iteration of offset 0 in the launches of the current chunk
   int32_t pad2;
-  int32_t iters, maxit, done, pad;
+  int32_t iters, maxit, done;
+  int32_t all_done;          // column 0 only: every column of the blocked solve has finished
   double alphas[kMaxHist];
   double betas[kMaxHist];
 };
@@ -329,7 +345,7 @@ void launch_round_factors(hipStream_t st, const LevelDev& L, const PcgDev& P, in
 void launch_pack_pcg(hipStream_t st, const LevelDev& L, const PcgDev& P);
 void launch_pcg_update_restrict(hipStream_t st, const LevelDev& L, int ngmax, int nrmax, int ncsmax, const PcgDev& P,
                                 int u);
-void launch_pcg_prolong_post(hipStream_t st, const LevelDev& L, const PcgDev& P, const double* uc, int u);
+void launch_pcg_prolong_post(hipStream_t st, const LevelDev& L, const PcgDev& P, int u);
 void launch_build_phi(hipStream_t st, const LevelDev& L, int nif, const int32_t* sub_of_flat, const int32_t* phi_ptr,
                       int32_t* phi_ids, double* phi_w, const float* psi32);
 

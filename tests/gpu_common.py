@@ -88,5 +88,5 @@ def check_adaptive_edges(S, B, tau, levels_to_span=(1,)):
                     assert np.max(ang) < 1e-6, (li, key, np.max(ang))
 
 
-def direct(B):
-    return spla.spsolve(B.A.tocsc(), B.prob.f[0])
+def direct(B, b=None):
+    return spla.spsolve(B.A.tocsc(), B.prob.f[0] if b is None else b)
