@@ -148,6 +148,41 @@ def precision_forms(P, synth, torch, cid: int, stream, precs=("fp64", "fp32", "b
     return out
 
 
+def blocked_rhs(P, synth, torch, cid: int, stream, nrhs: int = 8, precs=("fp64", "fp32")) -> dict:
+    """Right-hand sides solved per second (preconditioner set up once) with
+    `nrhs` seeded loads in one blocked solve, against the same loads solved one
+    at a time (BDDC_SOLVE_BLOCK=1); the iterates are the same bitwise."""
+    prob = synth.config(cid, nrhs=nrhs)
+    coeff = torch.tensor(prob.coeff, dtype=torch.float64, device="cuda")
+    F = torch.tensor(prob.f, dtype=torch.float64, device="cuda")
+    U = torch.empty_like(F)
+    out = {}
+    for prec in precs:
+        S = P.Solver(prob, coeff=coeff, stream=stream, precision=prec)
+        res = {}
+        for mode in ("blocked", "one_at_a_time"):
+            if mode == "one_at_a_time":
+                os.environ["BDDC_SOLVE_BLOCK"] = "1"
+            try:
+                _, it, _ = S.solve(F, u=U, rtol=prob.rtol, stream=stream)
+                torch.cuda.synchronize()
+                reps = 3
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    S.solve(F, u=U, rtol=prob.rtol, stream=stream)
+                torch.cuda.synchronize()
+                dt = (time.perf_counter() - t0) / reps
+            finally:
+                os.environ.pop("BDDC_SOLVE_BLOCK", None)
+            res[mode] = {"rhs_per_s": nrhs / dt, "ms_per_solve_call": dt * 1e3, "iterations_max": int(max(it))}
+        S.close()
+        res["speedup"] = res["blocked"]["rhs_per_s"] / res["one_at_a_time"]["rhs_per_s"]
+        out[prec] = res
+        log(f"bench: config {cid} {prec}: {nrhs} rhs blocked {res['blocked']['rhs_per_s']:.1f}/s, one at a time "
+            f"{res['one_at_a_time']['rhs_per_s']:.1f}/s")
+    return out
+
+
 def concurrent_steps(P, prob, coeff, f, torch, nsteps: int, nstreams: int = 2) -> float:
     """Whole steps (set-up, solve, destroy) of independent problems issued from
     `nstreams` host threads, each with a stream and handles of its own, so one
@@ -220,6 +255,7 @@ def main():
                     help="time one in this many launches of the roofline kernel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="skip the request-stream measurement")
+    ap.add_argument("--no-blocked", action="store_true", help="skip the blocked right-hand-side measurement")
     ap.add_argument("--no-precision-forms", action="store_true",
                     help="skip the FP64 / FP32 / BF16 comparison on configs 2 and 3")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -379,6 +415,13 @@ def main():
                     "T_rr and Psi streamed every iteration (BF16: inverse Cholesky factor), FP64 outer PCG",
             "config2": precision_forms(P, synth, torch, 2, stream),
             "config3": precision_forms(P, synth, torch, 3, stream),
+        }
+    if not args.no_blocked:
+        out["blocked_rhs"] = {
+            "note": "right-hand sides per second, 8 seeded loads in one blocked PCG (each launch applies its "
+                    "operator block to every column still iterating) against the same loads one at a time",
+            "config2": blocked_rhs(P, synth, torch, 2, stream),
+            "config3": blocked_rhs(P, synth, torch, 3, stream),
         }
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle on a bounded sample")

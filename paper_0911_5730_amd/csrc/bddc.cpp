@@ -420,6 +420,7 @@ struct bddc_ctx {
   std::vector<void*> staged;   // pinned upload buffers of the setup, released after it synchronises
   bool coop_deep = false;
   bool coop_launch = false;   // use the cooperative launch API
+  int coop_rmax = 1;          // most columns one cooperative launch serves (LDS and residency)
   double coop_bytes = 0;      // algorithmic bytes of one launch
   hipGraphExec_t graph_exec = nullptr;   // one chunk of PCG launches (captured on first use)
   int graph_nrhs = 0;                    // columns of the captured chunk
@@ -1331,6 +1332,29 @@ static void run_deep(bddc_ctx* h, hipStream_t st) {
   run_deep_at(h, st, l1.d.b, l1.d.uc);
 }
 
+// The deep levels for R columns of b1 / uc (strides ldb, ldu): one
+// cooperative launch for all of them when it fits, else column by column.
+static void run_deep_cols(bddc_ctx* h, hipStream_t st, const double* b1, int ldb, double* uc, int ldu, int R) {
+  Level& l1 = *h->levels[0];
+  if (h->levels.size() == 1) {
+    launch_coarse_direct_cols(st, l1.nc, l1.d.csh_ptr, l1.d.csh_flat, b1, ldb, h->AL, uc, ldu, R, l1.dev.stop);
+    return;
+  }
+  if (h->coop_deep && h->levels.size() > 1 && R <= h->coop_rmax) {
+    CoopDev C = h->coop;
+    C.stop = h->levels[0]->dev.stop;
+    C.nrhs = R;
+    C.b1 = b1;
+    C.ld_b1 = ldb;
+    C.u2 = uc;
+    C.ld_u2 = ldu;
+    timing::Scope ts("deep", h->coop_bytes, 0);
+    launch_deep_coop(st, C, h->coop_launch);
+    return;
+  }
+  for (int c = 0; c < R; ++c) run_deep_at(h, st, b1 + (size_t)c * ldb, uc + (size_t)c * ldu);
+}
+
 // full-space preconditioner of the level-1 problem (bddc_apply)
 static void apply_full(bddc_ctx* h, const double* r, double* u) {
   Level& l1 = *h->levels[0];
@@ -1436,6 +1460,18 @@ static bool plan_coop(bddc_ctx* h) {
   const size_t lds = coop_lds(C);
   if (lds > kLdsMax) return false;
   if (coop_max_blocks(lds) < nsub) return false;
+  // blocked right-hand sides: as many columns per launch as LDS and
+  // residency allow
+  int rmax = 1;
+  for (int R = 2; R <= kMaxRhs; ++R) {
+    CoopDev CR = C;
+    CR.nrhs = R;
+    const size_t l = coop_lds(CR);
+    if (l > kLdsMax || coop_max_blocks(l) < nsub) break;
+    rmax = R;
+  }
+  C.ld_t = (int)(((std::max(1, lv.nflat_g) * 8 + 255) / 256) * 32);
+  C.ld_b = (int)(((std::max(1, lv.nflat_c) * 8 + 255) / 256) * 32);
   std::vector<int64_t> kioff(nsub + 1, 0), moff(nsub + 1, 0);
   int nmax_ops = 0;
   for (int s = 0; s < nsub; ++s) {
@@ -1459,6 +1495,9 @@ static bool plan_coop(bddc_ctx* h) {
     C.LLinv = A.take<double>((size_t)ncL * ncL);
     C.bar = A.take<unsigned>(2);
     C.sub_of_flat = A.take<int32_t>(sub_of_flat.size());
+    C.t = A.take<double>((size_t)rmax * C.ld_t);
+    C.da = A.take<double>((size_t)rmax * C.ld_t);
+    C.b = A.take<double>((size_t)rmax * C.ld_b);
   };
   A.reset_sizing();
   lay();
@@ -1480,14 +1519,12 @@ static bool plan_coop(bddc_ctx* h) {
   launch_pack_coop(st, lv.dev, C);
   launch_tri_inverse_dense(st, h->AL, ncL, ncL, const_cast<double*>(C.LLinv));
   C.b1 = l1.d.b;
-  C.t = lv.d.t;
-  C.b = lv.d.b;
-  C.da = lv.d.v;
   C.u2 = l1.d.uc;
   C.stop = nullptr;
   C.status = h->status;
   h->coop = C;
   h->coop_deep = true;
+  h->coop_rmax = rmax;
   const char* cl = getenv("BDDC_COOP_LAUNCH");
   h->coop_launch = cl && std::string(cl) == "1";
   // operators and index lists once per workgroup, the level-1 contributions,
@@ -1815,7 +1852,7 @@ static int pcg_block(bddc_ctx* h, const double* f, double* u, int64_t ld, int R,
   // (tagged k - 1: they work iff k <= K) and the rest return at once.  The
   // kernels take their iteration as sc[0].it_base + u (u < 0: iteration 0), so
   // one chunk of launches is the same for every chunk and can be replayed as a
-  // HIP graph.  The deep levels run once per column.
+  // HIP graph.
   auto apply_iface = [&](hipStream_t q, int uu, int it) {
     timing::current_tag = it - 1;
     {
@@ -1823,8 +1860,7 @@ static int pcg_block(bddc_ctx* h, const double* f, double* u, int64_t ld, int R,
       launch_pcg_update_restrict(q, l1.dev, l1.ngmax, l1.nrmax, l1.ncsmax, P, uu);
     }
     if (P.fin && it > 0) launch_pcg_sum(q, P, 1, uu);
-    for (int c = 0; c < R; ++c)
-      run_deep_at(h, q, P.b + (size_t)c * P.ld_cflat, const_cast<double*>(P.uc) + (size_t)c * P.ld_coarse);
+    run_deep_cols(h, q, P.b, P.ld_cflat, const_cast<double*>(P.uc), P.ld_coarse, R);
     timing::current_tag = it;
     {
       timing::Scope ts("apply_average", h->by_average, 0);

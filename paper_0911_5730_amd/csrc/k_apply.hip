@@ -137,6 +137,29 @@ __global__ void __launch_bounds__(kNT) k_coarsest_solve(int nc, const double* __
   for (int i = threadIdx.x; i < nc; i += kNT) uc[i] = y[i];
 }
 
+// Coarse gather and direct coarsest solve in one launch, one workgroup per
+// column c of b / uc (strides ldb / ldu): the arithmetic of k_coarse_gather
+// followed by k_coarsest_solve.
+__global__ void __launch_bounds__(kNT) k_coarse_direct_cols(int nc, const int32_t* __restrict__ csh_ptr,
+                                                            const int32_t* __restrict__ csh_flat,
+                                                            const double* __restrict__ b, int ldb,
+                                                            const double* __restrict__ Lc, double* __restrict__ uc,
+                                                            int ldu, const int32_t* stop) {
+  extern __shared__ double y[];
+  if (stop && *stop) return;
+  const double* bc = b + (size_t)blockIdx.x * ldb;
+  for (int k = threadIdx.x; k < nc; k += kNT) {
+    double acc = 0.0;
+    for (int q = csh_ptr[k]; q < csh_ptr[k + 1]; ++q) acc += bc[csh_flat[q]];
+    y[k] = acc;
+  }
+  __syncthreads();
+  wg_trsv_lower(Lc, nc, nc, y);
+  wg_trsv_lower_trans(Lc, nc, nc, y);
+  double* u = uc + (size_t)blockIdx.x * ldu;
+  for (int i = threadIdx.x; i < nc; i += kNT) u[i] = y[i];
+}
+
 // v = delta (a + Psi u_c)
 __global__ void __launch_bounds__(kNT) k_apply_prolong(LevelDev L, const double* __restrict__ uc) {
   extern __shared__ double sh[];
@@ -389,6 +412,13 @@ void launch_coarsest_solve(hipStream_t st, int nc, const double* Lc, const doubl
   if (nc == 0) return;
   launch_kernel(k_coarsest_solve, dim3(1), dim3(kNT), sizeof(double) * (size_t)nc, st, nc, Lc, rc, uc,
                      stop);
+}
+void launch_coarse_direct_cols(hipStream_t st, int nc, const int32_t* csh_ptr, const int32_t* csh_flat,
+                               const double* b, int ldb, const double* Lc, double* uc, int ldu, int ncols,
+                               const int32_t* stop) {
+  if (nc == 0 || ncols == 0) return;
+  launch_kernel(k_coarse_direct_cols, dim3(ncols), dim3(kNT), sizeof(double) * (size_t)nc, st, nc, csh_ptr, csh_flat,
+                b, ldb, Lc, uc, ldu, stop);
 }
 void launch_apply_prolong(hipStream_t st, const LevelDev& L, int ncsmax, const double* uc) {
   launch_kernel(k_apply_prolong, dim3(L.nsub), dim3(kNT), sizeof(double) * (size_t)(ncsmax + 1), st, L, uc);

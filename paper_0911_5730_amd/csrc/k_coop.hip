@@ -55,21 +55,25 @@ __device__ void grid_barrier(unsigned* bar, unsigned nblocks, int* status) {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
-// out(i) = sum_{j in [j0(i), j1(i))} A[i*rs + j*cs] x[j] for i < rows, eight
-// lanes per row (fixed reduction order), then store(i, value) on lane 0 of the eight.
-// With xi, x is read at xi[j] (a gathered product).
+// out(c, i) = sum_{j in [j0(i), j1(i))} A[i*rs + j*cs] x_c[j] for i < rows and
+// the R columns x_c = x + c * xs, eight lanes per row (fixed reduction order),
+// then store(c, i, value) on lane 0 of the eight: row t of the combined loop
+// is row i = t mod rows of column c = t / rows.  With xi, x_c is read at
+// xi[j] (a gathered product).
 template <class J0, class J1, class Store>
-__device__ inline void mv8(int rows, const double* A, int rs, int cs, const double* x, J0 j0f, J1 j1f, Store store,
-                           const int32_t* xi = nullptr) {
+__device__ inline void mv8c(int rows, int R, const double* A, int rs, int cs, const double* x, int xs, J0 j0f,
+                            J1 j1f, Store store, const int32_t* xi = nullptr) {
   const int sub = threadIdx.x & 7;
-  for (int i = threadIdx.x >> 3; i < rows; i += kCoopNT / 8) {
+  for (int t = threadIdx.x >> 3; t < rows * R; t += kCoopNT / 8) {
+    const int c = t / rows, i = t - c * rows;
+    const double* xc = x + (size_t)c * xs;
     double acc = 0.0;
     const int j1 = j1f(i);
-    for (int j = j0f(i) + sub; j < j1; j += 8) acc += A[(size_t)i * rs + (size_t)j * cs] * x[xi ? xi[j] : j];
+    for (int j = j0f(i) + sub; j < j1; j += 8) acc += A[(size_t)i * rs + (size_t)j * cs] * xc[xi ? xi[j] : j];
     acc += __shfl_xor(acc, 1);
     acc += __shfl_xor(acc, 2);
     acc += __shfl_xor(acc, 4);
-    if (sub == 0) store(i, acc);
+    if (sub == 0) store(c, i, acc);
   }
 }
 
@@ -95,6 +99,8 @@ __global__ void __launch_bounds__(kCoopNT) k_deep_coop(CoopDev C) {
   const int nI = me[0], ng = me[1], nr = me[2], ncs = me[3], nsh = me[4], ng1 = me[5], goff = me[6], coff = me[7];
   const int n = nI + ng;
   const int ncL = C.ncL;
+  const int R = C.nrhs;                  // columns: vectors below hold R columns each
+  const int mI = C.nImax, mG = C.ngmax;  // their column strides
   (void)me[8];
   // LDS: operator block | vectors | coarsest inverse factor | ints
   double* Li = sh;                                   // K_II^-1, nI x nI
@@ -103,18 +109,17 @@ __global__ void __launch_bounds__(kCoopNT) k_deep_coop(CoopDev C) {
   double* Ps = Tm + (size_t)nr * nr;                 // ng x ncs
   double* dl = Ps + (size_t)ng * ncs;                // ng
   double* phw = dl + ng;                             // phi weights
-  double* rI = sh + C.opmax;
-  double* rG = rI + C.nImax;
-  double* y = rG + C.ngmax;
-  double* g = y + C.nImax;
-  double* av = g + C.ngmax;
-  double* uB = av + C.ngmax;
-  double* yv = uB + C.ngmax;
-  double* LL = yv + C.nImax;
-  double* rc = LL + (size_t)ncL * ncL;
-  double* wc = rc + ncL;
-  double* uc = wc + ncL;
-  int32_t* ib = reinterpret_cast<int32_t*>(uc + ncL);
+  double* rI = sh + C.opmax;                         // R x nImax
+  double* rG = rI + (size_t)R * mI;                  // R x ngmax
+  double* y = rG + (size_t)R * mG;                   // R x nImax
+  double* g = y + (size_t)R * mI;                    // R x ngmax
+  double* av = g + (size_t)R * mG;                   // R x ngmax
+  double* uB = av + (size_t)R * mG;                  // R x ngmax
+  double* LL = uB + (size_t)R * mG;
+  double* rc = LL + (size_t)ncL * ncL;               // R x ncL
+  double* wc = rc + (size_t)R * ncL;                 // R x ncL
+  double* uc = wc + (size_t)R * ncL;                 // R x ncL
+  int32_t* ib = reinterpret_cast<int32_t*>(uc + (size_t)R * ncL);
   int32_t* int_gid = ib;
   int32_t* gam_gid = int_gid + nI;
   int32_t* own = gam_gid + ng;
@@ -174,69 +179,86 @@ __global__ void __launch_bounds__(kCoopNT) k_deep_coop(CoopDev C) {
     }
   }
   __syncthreads();
+  // Every phase below runs for all R columns before the next barrier (column
+  // c of a global vector at c times its stride), so R columns cost the
+  // barriers of one.
   // r_2 on the local dofs: sums of the level-1 coarse contributions
-  for (int p = tid; p < n; p += kCoopNT) {
+  for (int t = tid; t < n * R; t += kCoopNT) {
+    const int c = t / n, p = t - c * n;
+    const double* b1 = C.b1 + (size_t)c * C.ld_b1;
     double acc = 0.0;
-    for (int q = gp[p]; q < gp[p + 1]; ++q) acc += C.b1[gf[q]];
-    if (p < nI) rI[p] = acc;
-    else rG[p - nI] = acc;
+    for (int q = gp[p]; q < gp[p + 1]; ++q) acc += b1[gf[q]];
+    if (p < nI) rI[c * mI + p] = acc;
+    else rG[c * mG + p - nI] = acc;
   }
   __syncthreads();
   // interior correction (ML-uIi, ML-rBi): y = K_II^-1 r_I and t = K_GI K_II^-1 r_I
   // in one pass: row rho of [K_II^-1 ; M] is column rho of [K_II^-1  M^T]
-  mv8(nI + ng, Li, nI, 1, rI, [](int) { return 0; }, [&](int) { return nI; },
-      [&](int i, double v) {
-        if (i < nI) y[i] = v;
-        else C.t[goff + i - nI] = v;
-      });
+  mv8c(nI + ng, R, Li, nI, 1, rI, mI, [](int) { return 0; }, [&](int) { return nI; },
+       [&](int c, int i, double v) {
+         if (i < nI) y[c * mI + i] = v;
+         else C.t[(size_t)c * C.ld_t + goff + i - nI] = v;
+       });
   grid_barrier(C.bar, gridDim.x, C.status);
   // g = delta (r_G - sum t);  a = T_rr g_r (ML-wDi);  b = Psi^T g (ML-coarse)
-  for (int a = tid; a < ng; a += kCoopNT) {
-    double v = rG[a];
-    for (int q = shp[a]; q < shp[a + 1]; ++q) v -= C.t[shf[q]];
-    g[a] = dl[a] * v;
+  for (int t = tid; t < ng * R; t += kCoopNT) {
+    const int c = t / ng, a = t - c * ng;
+    const double* tc = C.t + (size_t)c * C.ld_t;
+    double v = rG[c * mG + a];
+    for (int q = shp[a]; q < shp[a + 1]; ++q) v -= tc[shf[q]];
+    g[c * mG + a] = dl[a] * v;
   }
   __syncthreads();
-  mv8(nr, Tm, 1, nr, g, [](int) { return 0; }, [&](int) { return nr; },
-      [&](int a, double v) { C.da[goff + a] = dl[a] * v; });
-  for (int a = nr + tid; a < ng; a += kCoopNT) C.da[goff + a] = 0.0;
-  mv8(ncs, Ps, ng, 1, g, [](int) { return 0; }, [&](int) { return ng; },
-      [&](int k, double v) { C.b[coff + k] = v; });
+  mv8c(nr, R, Tm, 1, nr, g, mG, [](int) { return 0; }, [&](int) { return nr; },
+       [&](int c, int a, double v) { C.da[(size_t)c * C.ld_t + goff + a] = dl[a] * v; });
+  for (int t = tid; t < (ng - nr) * R; t += kCoopNT) {
+    const int c = t / (ng - nr), a = nr + t - c * (ng - nr);
+    C.da[(size_t)c * C.ld_t + goff + a] = 0.0;
+  }
+  mv8c(ncs, R, Ps, ng, 1, g, mG, [](int) { return 0; }, [&](int) { return ng; },
+       [&](int c, int k, double v) { C.b[(size_t)c * C.ld_b + coff + k] = v; });
   grid_barrier(C.bar, gridDim.x, C.status);
   // coarsest right-hand side r_c = sum of the coarse contributions, and the
   // sharers' sum of delta T_rr g on the interface, in one round of loads
-  for (int k = tid; k < ncL; k += kCoopNT) {
+  for (int t = tid; t < ncL * R; t += kCoopNT) {
+    const int c = t / ncL, k = t - c * ncL;
+    const double* bc = C.b + (size_t)c * C.ld_b;
     double acc = 0.0;
-    for (int q = cg[k]; q < cg[k + 1]; ++q) acc += C.b[cg[ncL + 1 + q]];
-    rc[k] = acc;
+    for (int q = cg[k]; q < cg[k + 1]; ++q) acc += bc[cg[ncL + 1 + q]];
+    rc[c * ncL + k] = acc;
   }
-  for (int a = tid; a < ng; a += kCoopNT) {
+  for (int t = tid; t < ng * R; t += kCoopNT) {
+    const int c = t / ng, a = t - c * ng;
+    const double* dc = C.da + (size_t)c * C.ld_t;
     double acc = 0.0;
-    for (int q = shp[a]; q < shp[a + 1]; ++q) acc += C.da[shf[q]];
-    av[a] = acc;
+    for (int q = shp[a]; q < shp[a + 1]; ++q) acc += dc[shf[q]];
+    av[c * mG + a] = acc;
   }
   __syncthreads();
-  mv8(ncL, LL, 1, ncL, rc, [](int) { return 0; }, [](int i) { return i + 1; }, [&](int i, double v) { wc[i] = v; });
+  mv8c(ncL, R, LL, 1, ncL, rc, ncL, [](int) { return 0; }, [](int i) { return i + 1; },
+       [&](int c, int i, double v) { wc[c * ncL + i] = v; });
   __syncthreads();
-  mv8(ncL, LL, ncL, 1, wc, [](int i) { return i; }, [&](int) { return ncL; }, [&](int i, double v) { uc[i] = v; });
+  mv8c(ncL, R, LL, ncL, 1, wc, ncL, [](int i) { return i; }, [&](int) { return ncL; },
+       [&](int c, int i, double v) { uc[c * ncL + i] = v; });
   __syncthreads();
   // u_B = sum over sharers of delta (T_rr g + Psi u_c)   (ML-uBi-1), owner writes
-  mv8(ng, phw, 0, 1, uc, [&](int a) { return phi_ptr[a]; }, [&](int a) { return phi_ptr[a + 1]; },
-      [&](int a, double v) {
-        const double u = av[a] + v;
-        uB[a] = u;
-        if (own[a]) C.u2[gam_gid[a]] = u;
-      },
-      phi_ids);
+  mv8c(ng, R, phw, 0, 1, uc, ncL, [&](int a) { return phi_ptr[a]; }, [&](int a) { return phi_ptr[a + 1]; },
+       [&](int c, int a, double v) {
+         const double u = av[c * mG + a] + v;
+         uB[c * mG + a] = u;
+         if (own[a]) C.u2[(size_t)c * C.ld_u2 + gam_gid[a]] = u;
+       },
+       phi_ids);
   __syncthreads();
   // u_I = K_II^-1 (r_I - K_IG u_B) = y - M^T u_B   (ML-vIi, ML-ui)
-  mv8(nI, G, 1, nI, uB, [](int) { return 0; }, [&](int) { return ng; },
-      [&](int i, double v) { C.u2[int_gid[i]] = y[i] - v; });
+  mv8c(nI, R, G, 1, nI, uB, mG, [](int) { return 0; }, [&](int) { return ng; },
+       [&](int c, int i, double v) { C.u2[(size_t)c * C.ld_u2 + int_gid[i]] = y[c * mI + i] - v; });
 }
 
 size_t coop_lds(const CoopDev& C) {
-  const size_t dbl = (size_t)C.opmax + 3 * (size_t)C.nImax + 4 * (size_t)C.ngmax + (size_t)C.ncL * C.ncL +
-                     3 * (size_t)C.ncL;
+  const size_t R = (size_t)std::max(1, C.nrhs);
+  const size_t dbl = (size_t)C.opmax + R * (2 * (size_t)C.nImax + 4 * (size_t)C.ngmax + 3 * (size_t)C.ncL) +
+                     (size_t)C.ncL * C.ncL;
   return sizeof(double) * dbl + sizeof(int32_t) * ((size_t)C.idxmax + C.cg_len);
 }
 

@@ -129,6 +129,10 @@ struct CoopDev {
   const int32_t* stop = nullptr;
   unsigned* bar = nullptr;            // grid barrier: count, generation
   int* status = nullptr;
+  // columns: b1 and u2 hold nrhs columns at strides ld_b1 and ld_u2, the
+  // scratch t and da at ld_t, b at ld_b (every phase serves all columns)
+  int nrhs = 1;
+  int ld_b1 = 0, ld_u2 = 0, ld_t = 0, ld_b = 0;
 };
 size_t coop_lds(const CoopDev& C);
 void launch_deep_coop(hipStream_t st, const CoopDev& C, bool cooperative);
@@ -310,6 +314,9 @@ void launch_coarse_gather(hipStream_t st, int nc, const int32_t* csh_ptr, const 
                           const double* b, double* rc, const int32_t* stop);
 void launch_coarsest_solve(hipStream_t st, int nc, const double* Lc, const double* rc, double* uc,
                            const int32_t* stop);
+void launch_coarse_direct_cols(hipStream_t st, int nc, const int32_t* csh_ptr, const int32_t* csh_flat,
+                               const double* b, int ldb, const double* Lc, double* uc, int ldu, int ncols,
+                               const int32_t* stop);
 void launch_apply_prolong(hipStream_t st, const LevelDev& L, int ncsmax, const double* uc);
 void launch_apply_post(hipStream_t st, const LevelDev& L, int nImax, int ngmax, double* u,
                        const int32_t* gam_map, int interior);
