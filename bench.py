@@ -166,7 +166,7 @@ def blocked_rhs(P, synth, torch, cid: int, stream, nrhs: int = 8, precs=("fp64",
             try:
                 _, it, _ = S.solve(F, u=U, rtol=prob.rtol, stream=stream)
                 torch.cuda.synchronize()
-                reps = 3
+                reps = 5
                 t0 = time.perf_counter()
                 for _ in range(reps):
                     S.solve(F, u=U, rtol=prob.rtol, stream=stream)

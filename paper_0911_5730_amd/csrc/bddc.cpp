@@ -411,6 +411,9 @@ struct bddc_ctx {
   bddc::PcgScalars* sc_host = nullptr;   // pinned, kMaxRhs columns
   bddc::Arena cols_arena;
   int cols_cap = 0;
+  double* cy = nullptr;   // per column: L_II^-1 f_I (interior flat) and L_GI L_II^-1 f_I (interface flat)
+  double* ct = nullptr;
+  int ld_cy = 0;
   int nblk = 1;
   bddc::PcgDev pcg;
   // deep levels (2 .. L-1) and the coarsest solve in one workgroup when small
@@ -1304,12 +1307,11 @@ static void run_deep_at(bddc_ctx* h, hipStream_t st, const double* b1, double* u
     WideDev W = h->wide;
     W.b1 = b1;
     W.u2 = uc;
+    W.nrhs = 1;
     W.stop = l1.dev.stop;
     W.L.stop = l1.dev.stop;
-    LevelDev L2 = l2.dev;
-    L2.stop = l1.dev.stop;
     launch_wide_pre(st, W);
-    launch_apply_restrict(st, L2, l2.ngmax, W.r2, l2.d.gam_gid, 1);
+    launch_wide_restrict(st, W, l2.d.gam_gid);
     launch_wide_coarse(st, W);
     launch_wide_post(st, W);
     return;
@@ -1338,6 +1340,22 @@ static void run_deep_cols(bddc_ctx* h, hipStream_t st, const double* b1, int ldb
   Level& l1 = *h->levels[0];
   if (h->levels.size() == 1) {
     launch_coarse_direct_cols(st, l1.nc, l1.d.csh_ptr, l1.d.csh_flat, b1, ldb, h->AL, uc, ldu, R, l1.dev.stop);
+    return;
+  }
+  if (h->wide_deep && R <= kMaxRhs) {
+    Level& l2 = *h->levels[1];
+    WideDev W = h->wide;
+    W.nrhs = R;
+    W.b1 = b1;
+    W.ld_b1 = ldb;
+    W.u2 = uc;
+    W.ld_u2 = ldu;
+    W.stop = l1.dev.stop;
+    W.L.stop = l1.dev.stop;
+    launch_wide_pre(st, W);
+    launch_wide_restrict(st, W, l2.d.gam_gid);
+    launch_wide_coarse(st, W);
+    launch_wide_post(st, W);
     return;
   }
   if (h->coop_deep && h->levels.size() > 1 && R <= h->coop_rmax) {
@@ -1564,12 +1582,22 @@ static bool plan_wide(bddc_ctx* h) {
     for (int f = lv.goff[s]; f < lv.goff[s + 1]; ++f) sub_of_flat[f] = s;
   WideDev W{};
   Arena& A = h->wide_arena;
+  auto colpad = [](int64_t n) { return (int)(((std::max<int64_t>(n, 1) * 8 + 255) / 256) * 32); };
+  const int ldi = colpad(lv.nflat_i), ldg = colpad(lv.nflat_g), ldc = colpad(lv.nflat_c), ldr = colpad(lv.n);
+  double *cy = nullptr, *ct = nullptr, *ca = nullptr, *cv = nullptr, *cb = nullptr, *cr = nullptr;
   auto lay = [&] {
     W.Kinv = A.take<double>(std::max<int64_t>(1, kioff[nsub]));
     W.kioff = A.take<int64_t>(nsub + 1);
     W.Mt = A.take<double>(std::max<int64_t>(1, moff[nsub]));
     W.moff = A.take<int64_t>(nsub + 1);
     W.sub_of_flat = A.take<int32_t>(std::max(1, lv.nflat_g));
+    // level-2 scratch and r_2 for up to kMaxRhs columns
+    cy = A.take<double>((size_t)kMaxRhs * ldi);
+    ct = A.take<double>((size_t)kMaxRhs * ldg);
+    ca = A.take<double>((size_t)kMaxRhs * ldg);
+    cv = A.take<double>((size_t)kMaxRhs * ldg);
+    cb = A.take<double>((size_t)kMaxRhs * ldc);
+    cr = A.take<double>((size_t)kMaxRhs * ldr);
   };
   A.reset_sizing();
   lay();
@@ -1585,6 +1613,15 @@ static bool plan_wide(bddc_ctx* h) {
   }
   launch_wide_ops(st, lv.dev, nmax_ops, const_cast<double*>(W.Kinv), W.kioff, const_cast<double*>(W.Mt), W.moff);
   W.L = lv.dev;
+  W.L.y = cy;
+  W.L.t = ct;
+  W.L.a = ca;
+  W.L.v = cv;
+  W.L.b = cb;
+  W.ld_i = ldi;
+  W.ld_g = ldg;
+  W.ld_c = ldc;
+  W.ld_r2 = ldr;
   W.nImax = lv.nImax;
   W.ngmax = lv.ngmax;
   W.rows1 = 8;
@@ -1593,7 +1630,7 @@ static bool plan_wide(bddc_ctx* h) {
   W.b1 = l1.d.b;
   W.csh_ptr1 = l1.d.csh_ptr;
   W.csh_flat1 = l1.d.csh_flat;
-  W.r2 = l1.d.rc;
+  W.r2 = cr;
   W.u2 = l1.d.uc;
   W.ncL = lv.nc;
   W.AL = h->AL;
@@ -1773,6 +1810,7 @@ static void ensure_columns(bddc_ctx* h, int R) {
   P.ld_coarse = pad(l1.nc);
   P.ld_sub = pad(P.nsub1);
   P.ld_blk = pad(P.nblk);
+  h->ld_cy = pad(l1.nflat_i);
   Arena& A = h->cols_arena;
   auto lay = [&] {
     P.x = A.take<double>((size_t)R * P.ld_if);
@@ -1790,6 +1828,8 @@ static void ensure_columns(bddc_ctx* h, int R) {
     P.b = A.take<double>((size_t)R * P.ld_cflat);
     P.uc = A.take<double>((size_t)R * P.ld_coarse);
     P.sc = A.take<PcgScalars>(R);
+    h->cy = A.take<double>((size_t)R * h->ld_cy);
+    h->ct = A.take<double>((size_t)R * P.ld_flat);
   };
   A.reset_sizing();
   lay();
@@ -1820,17 +1860,18 @@ static int pcg_block(bddc_ctx* h, const double* f, double* u, int64_t ld, int R,
     sch[c].it_base = 1;
     BDDC_HIP(hipMemcpyAsync(P.sc + c, sch + c, offsetof(PcgScalars, alphas), hipMemcpyHostToDevice, st));
   }
+  // the condensation: with the streamed sweeps all columns in one pass over
+  // L (y = L^{-1} f_I, t = L_GI y per column), else column by column
   const bool sweep = use_sweep(l1.nmax);
+  if (sweep) launch_sweep_pre_cols(st, l1.dev, f, ld, h->cy, h->ld_cy, h->ct, P.ld_flat, R);
   for (int c = 0; c < R; ++c) {
     const double* fc = f + (size_t)c * ld;
     double* rc = P.r[0] + (size_t)c * P.ld_if;
     launch_dot_partial(st, nbf, (int)h->n_free, fc, fc, h->partial);
     launch_scalar(st, 4, nbf, h->partial, P.sc + c);                 // bb, thr2 = rtol^2 bb
-    if (sweep)                                                       // y = L^{-1} f_I, t = L_GI y
-      launch_sweep_pre(st, l1.dev, fc);
-    else
-      launch_apply_pre(st, l1.dev, l1.nImax, l1.ngmax, fc);
-    launch_condense(st, nif, l1.d.sh_ptr, l1.d.sh_flat, l1.d.iface_dof, fc, l1.d.t, rc, P.x + (size_t)c * P.ld_if);
+    if (!sweep) launch_apply_pre(st, l1.dev, l1.nImax, l1.ngmax, fc);
+    const double* tc = sweep ? h->ct + (size_t)c * P.ld_flat : l1.d.t;
+    launch_condense(st, nif, l1.d.sh_ptr, l1.d.sh_flat, l1.d.iface_dof, fc, tc, rc, P.x + (size_t)c * P.ld_if);
     launch_dot_partial(st, nb, nif, rc, rc, h->partial);
     launch_scalar(st, 5, nb, h->partial, P.sc + c);                  // rr0, done if already small
   }
@@ -1902,23 +1943,19 @@ static int pcg_block(bddc_ctx* h, const double* f, double* u, int64_t ld, int R,
     if (sch[0].all_done) break;
   }
   timing::current_tag = -1;
-  // interior recovery u_I = L^-T (y - L_GI^T x) needs y = L^-1 f_I of its own
-  // column: the set-up pass above left the last column's y (the level's stop
-  // flag is raised by now, so these launches go without it)
+  // interior recovery u_I = L^-T (y - L_GI^T x) with each column's own y:
+  // the column sweeps kept every column's y; column by column, the set-up
+  // pass above left the last column's y (the level's stop flag is raised by
+  // now, so these launches go without it)
   LevelDev L1 = l1.dev;
   L1.stop = nullptr;
-  for (int c = R - 1; c >= 0; --c) {
-    const double* xc = P.x + (size_t)c * P.ld_if;
-    if (c < R - 1) {
-      if (sweep)
-        launch_sweep_pre(st, L1, f + (size_t)c * ld);
-      else
-        launch_apply_pre(st, L1, l1.nImax, l1.ngmax, f + (size_t)c * ld);
+  if (sweep) {
+    launch_sweep_recover_cols(st, L1, P.x, P.ld_if, h->cy, h->ld_cy, u, ld, R);
+  } else {
+    for (int c = R - 1; c >= 0; --c) {
+      if (c < R - 1) launch_apply_pre(st, L1, l1.nImax, l1.ngmax, f + (size_t)c * ld);
+      launch_recover(st, L1, l1.nImax, l1.ngmax, P.x + (size_t)c * P.ld_if, u + (size_t)c * ld);
     }
-    if (sweep)
-      launch_sweep_recover(st, L1, xc, u + (size_t)c * ld);
-    else
-      launch_recover(st, L1, l1.nImax, l1.ngmax, xc, u + (size_t)c * ld);
   }
   int dev_status = 0;
   for (int c = 0; c < R; ++c) BDDC_HIP(hipMemcpyAsync(sch + c, P.sc + c, sizeof(PcgScalars), hipMemcpyDeviceToHost, st));

@@ -59,13 +59,23 @@ __global__ void __launch_bounds__(kNT) k_apply_pre(LevelDev L, const double* __r
 
 // g = delta (r_Gamma - sum t);  a_r = T_rr g_r, a_c = 0;  b = Psi^T g
 // kFS: full-space input (subtract the interior pre-correction t); otherwise the
-// input is an interface vector with zero interior residual.
+// input is an interface vector with zero interior residual.  Grid
+// (substructures, columns): column c reads r + c ldr and L.t + c ldg, writes
+// L.a + c ldg and L.b + c ldc.
 template <bool kFS>
 __global__ void __launch_bounds__(kNT) k_apply_restrict(LevelDev L, const double* __restrict__ r,
-                                                        const int32_t* __restrict__ gam_map) {
+                                                        const int32_t* __restrict__ gam_map, int ldr, int ldg,
+                                                        int ldc) {
   extern __shared__ double sh[];
   if (L.stop && *L.stop) return;
   const int s = blockIdx.x;
+  {
+    const size_t col = blockIdx.y;
+    r += col * ldr;
+    L.t += col * ldg;
+    L.a += col * ldg;
+    L.b += col * ldc;
+  }
   const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
   const int nI = L.nint[s];
   const int ng = n - nI;
@@ -397,9 +407,16 @@ void launch_apply_restrict(hipStream_t st, const LevelDev& L, int ngmax, const d
                            const int32_t* gam_map, int use_t) {
   const size_t lds = sizeof(double) * ((size_t)ngmax + kNT + ngmax);
   if (use_t)
-    launch_kernel(k_apply_restrict<true>, dim3(L.nsub), dim3(kNT), lds, st, L, r, gam_map);
+    launch_kernel(k_apply_restrict<true>, dim3(L.nsub), dim3(kNT), lds, st, L, r, gam_map, 0, 0, 0);
   else
-    launch_kernel(k_apply_restrict<false>, dim3(L.nsub), dim3(kNT), lds, st, L, r, gam_map);
+    launch_kernel(k_apply_restrict<false>, dim3(L.nsub), dim3(kNT), lds, st, L, r, gam_map, 0, 0, 0);
+}
+void launch_wide_restrict(hipStream_t st, const WideDev& W, const int32_t* gam_map) {
+  LevelDev L = W.L;
+  L.stop = W.stop;
+  const size_t lds = sizeof(double) * ((size_t)W.ngmax + kNT + W.ngmax);
+  launch_kernel(k_apply_restrict<true>, dim3(L.nsub, W.nrhs), dim3(kNT), lds, st, L, W.r2, gam_map, W.ld_r2, W.ld_g,
+                W.ld_c);
 }
 void launch_coarse_gather(hipStream_t st, int nc, const int32_t* csh_ptr, const int32_t* csh_flat,
                           const double* b, double* rc, const int32_t* stop) {

@@ -168,7 +168,171 @@ __device__ __forceinline__ void sweep_bwd(const double* __restrict__ A, int n, i
   }
 }
 
+// The same sweeps for R columns of w (column c at w + c kSweepRows), 32-wide
+// panels: each panel is read once for all columns; wave c solves column c's
+// diagonal block, and every column's arithmetic is that of the one-column
+// sweep with 32-wide panels.
+constexpr int kCBW = 32;
+
+__device__ __forceinline__ void sweep_fwd_cols(const double* __restrict__ A, int n, int nI, double* w, int R,
+                                               double* P) {
+  const int tid = threadIdx.x, wave = tid >> 6;
+  const int nb = (nI + kCBW - 1) / kCBW;
+  double r[kRegs<kCBW>];
+  Panel p = panel_of<kCBW>(0, n, nI);
+  panel_load<kCBW>(A, n, p, r);
+  panel_store<kCBW>(P, p, r);
+  __syncthreads();
+  for (int b = 0; b < nb; ++b) {
+    const Panel q = panel_of<kCBW>(b + 1, n, nI);
+    if (b + 1 < nb) panel_load<kCBW>(A, n, q, r);
+    const int wb = p.c1 - p.c0;
+    if (wave < R) {
+      // diagonal block of column `wave`: lane l owns row c0 + l
+      double* wc = w + wave * kSweepRows;
+      const int l = tid & 63;
+      double wl = l < wb ? wc[p.c0 + l] : 0.0;
+      const double inv = l < wb ? 1.0 / P[l + l * p.rows] : 0.0;
+      for (int j = 0; j < wb; ++j) {
+        const double xj = lane_value(wl * inv, j);
+        if (l == j) wl = xj;
+        else if (l > j && l < wb) wl -= P[l + j * p.rows] * xj;
+      }
+      if (l < wb) wc[p.c0 + l] = wl;
+    }
+    __syncthreads();
+    // rows below the block, every column
+    const int below = n - p.c0 - wb;
+    for (int t = tid; t < below * R; t += kSweepNT) {
+      const int c = t / below, i = p.c0 + wb + (t - c * below);
+      double* wc = w + c * kSweepRows;
+      double acc = 0.0;
+      const double* Pi = P + (i - p.c0);
+#pragma unroll 8
+      for (int k = 0; k < wb; ++k) acc += Pi[k * p.rows] * wc[p.c0 + k];
+      wc[i] -= acc;
+    }
+    __syncthreads();
+    if (b + 1 < nb) {
+      panel_store<kCBW>(P, q, r);
+      __syncthreads();
+    }
+    p = q;
+  }
+}
+
+__device__ __forceinline__ void sweep_bwd_cols(const double* __restrict__ A, int n, int nI, double* w, int R,
+                                               double* P) {
+  const int tid = threadIdx.x, wave = tid >> 6;
+  const int nb = (nI + kCBW - 1) / kCBW;
+  double r[kRegs<kCBW>];
+  Panel p = panel_of<kCBW>(nb - 1, n, nI);
+  panel_load<kCBW>(A, n, p, r);
+  panel_store<kCBW>(P, p, r);
+  __syncthreads();
+  for (int b = nb - 1; b >= 0; --b) {
+    const Panel q = panel_of<kCBW>(b - 1, n, nI);
+    if (b > 0) panel_load<kCBW>(A, n, q, r);
+    const int wb = p.c1 - p.c0;
+    // w_j -= sum over rows below the block of L[i][j] w_i, eight lanes per
+    // (column, j); the rows read lie below the block, the rows written in it
+    for (int base = 0; base < wb * R; base += kSweepNT / 8) {
+      const int pr = base + (tid >> 3), part = tid & 7;
+      const int c = pr / wb, j = pr - c * wb;
+      double acc = 0.0;
+      if (pr < wb * R) {
+        const double* wc = w + c * kSweepRows;
+        for (int i = p.c0 + wb + part; i < n; i += 8) acc += P[(i - p.c0) + j * p.rows] * wc[i];
+      }
+      acc += __shfl_xor(acc, 1);
+      acc += __shfl_xor(acc, 2);
+      acc += __shfl_xor(acc, 4);
+      if (pr < wb * R && part == 0) w[c * kSweepRows + p.c0 + j] -= acc;
+    }
+    __syncthreads();
+    if (wave < R) {
+      // diagonal block of L^T, from its last row up: lane l owns row c0 + l
+      double* wc = w + wave * kSweepRows;
+      const int l = tid & 63;
+      double wl = l < wb ? wc[p.c0 + l] : 0.0;
+      const double inv = l < wb ? 1.0 / P[l + l * p.rows] : 0.0;
+      for (int j = wb - 1; j >= 0; --j) {
+        const double xj = lane_value(wl * inv, j);
+        if (l == j) wl = xj;
+        else if (l < j) wl -= P[j + l * p.rows] * xj;
+      }
+      if (l < wb) wc[p.c0 + l] = wl;
+    }
+    __syncthreads();
+    if (b > 0) {
+      panel_store<kCBW>(P, q, r);
+      __syncthreads();
+    }
+    p = q;
+  }
+}
+
 }  // namespace
+
+// The condensation and the interior recovery of the interface-reduced solve
+// for R right-hand sides at once (column c of r, y, t, x, u at c times its
+// stride): y = L_II^{-1} r_I, t = L_GI y ...
+__global__ void __launch_bounds__(kSweepNT, kSweepBlocks<32>) k_sweep_pre_cols(LevelDev L, const double* __restrict__ r,
+                                                                               int64_t ldr, double* __restrict__ y, int ldy,
+                                                                               double* __restrict__ t, int ldt, int R) {
+  extern __shared__ double sh[];
+  const int s = blockIdx.x;
+  const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
+  const int nI = L.nint[s];
+  double* w = sh;
+  double* P = sh + (size_t)R * kSweepRows;
+  const int tid = threadIdx.x;
+  for (int q = tid; q < n * R; q += kSweepNT) {
+    const int c = q / n, i = q - c * n;
+    w[c * kSweepRows + i] = i < nI ? r[(size_t)c * ldr + L.int_gid[L.ioff[s] + i]] : 0.0;
+  }
+  __syncthreads();
+  if (nI > 0) sweep_fwd_cols(L.K + L.koff[s], n, nI, w, R, P);
+  for (int q = tid; q < n * R; q += kSweepNT) {
+    const int c = q / n, i = q - c * n;
+    if (i < nI) y[(size_t)c * ldy + L.ioff[s] + i] = w[c * kSweepRows + i];
+    else t[(size_t)c * ldt + L.goff[s] + i - nI] = -w[c * kSweepRows + i];
+  }
+}
+
+// ... and u_G = x, u_I = L_II^{-T}(y - L_GI^T x_s)
+__global__ void __launch_bounds__(kSweepNT, kSweepBlocks<32>) k_sweep_recover_cols(
+    LevelDev L, const double* __restrict__ x, int ldx, const double* __restrict__ y, int ldy, double* __restrict__ u,
+    int64_t ldu, int R) {
+  extern __shared__ double sh[];
+  const int s = blockIdx.x;
+  const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
+  const int nI = L.nint[s];
+  const int ng = n - nI;
+  const int g0 = L.goff[s];
+  double* w = sh;
+  double* P = sh + (size_t)R * kSweepRows;
+  const int tid = threadIdx.x;
+  for (int q = tid; q < ng * R; q += kSweepNT) {
+    const int c = q / ng, a = q - c * ng;
+    const int f = g0 + a;
+    const int gi = L.gam_iid[f];
+    const double v = x[(size_t)c * ldx + gi];
+    w[c * kSweepRows + nI + a] = v;
+    if (L.sh_flat[L.sh_ptr[gi]] == f) u[(size_t)c * ldu + L.gam_gid[f]] = v;
+  }
+  for (int q = tid; q < nI * R; q += kSweepNT) {
+    const int c = q / nI, i = q - c * nI;
+    w[c * kSweepRows + i] = y[(size_t)c * ldy + L.ioff[s] + i];
+  }
+  __syncthreads();
+  if (nI == 0) return;
+  sweep_bwd_cols(L.K + L.koff[s], n, nI, w, R, P);
+  for (int q = tid; q < nI * R; q += kSweepNT) {
+    const int c = q / nI, i = q - c * nI;
+    u[(size_t)c * ldu + L.int_gid[L.ioff[s] + i]] = w[c * kSweepRows + i];
+  }
+}
 
 // y = L_II^{-1} r_I (kept for the post-correction), t = L_GI y
 template <int BW>
@@ -252,6 +416,22 @@ static_assert(sweep_lds_bytes<64>() <= 160 * 1024, "sweep LDS");
 static_assert(2 * sweep_lds_bytes<32>() <= 160 * 1024, "two 32-wide sweep workgroups per CU");
 
 bool sweep_fits(int nmax) { return nmax <= kSweepRows; }
+
+static size_t sweep_cols_lds(int R) { return sizeof(double) * ((size_t)R * kSweepRows + (size_t)kSweepRows * kCBW); }
+static_assert(sizeof(double) * ((size_t)kMaxRhs * kSweepRows + (size_t)kSweepRows * kCBW) <= 160 * 1024,
+              "column sweeps of kMaxRhs columns");
+
+void launch_sweep_pre_cols(hipStream_t st, const LevelDev& L, const double* r, int64_t ldr, double* y, int ldy, double* t,
+                           int ldt, int R) {
+  if (L.nsub == 0 || R == 0) return;
+  launch_kernel(k_sweep_pre_cols, dim3(L.nsub), dim3(kSweepNT), sweep_cols_lds(R), st, L, r, ldr, y, ldy, t, ldt, R);
+}
+void launch_sweep_recover_cols(hipStream_t st, const LevelDev& L, const double* x, int ldx, const double* y, int ldy,
+                               double* u, int64_t ldu, int R) {
+  if (L.nsub == 0 || R == 0) return;
+  launch_kernel(k_sweep_recover_cols, dim3(L.nsub), dim3(kSweepNT), sweep_cols_lds(R), st, L, x, ldx, y, ldy, u, ldu,
+                R);
+}
 
 // 32-wide panels once the grid takes more than one round of one workgroup per
 // CU (BDDC_SWEEP_BW=32/64 forces either width)

@@ -17,19 +17,23 @@
 
 namespace bddc {
 
-// r_2 at level-2 dof k: the sum of the level-1 coarse contributions
-__device__ inline double wide_r2(const WideDev& W, int k) {
+// r_2 at level-2 dof k: the sum of the level-1 coarse contributions b1
+__device__ inline double wide_r2(const WideDev& W, const double* b1, int k) {
   double acc = 0.0;
-  for (int q = W.csh_ptr1[k]; q < W.csh_ptr1[k + 1]; ++q) acc += W.b1[W.csh_flat1[q]];
+  for (int q = W.csh_ptr1[k]; q < W.csh_ptr1[k + 1]; ++q) acc += b1[W.csh_flat1[q]];
   return acc;
 }
 
-// grid (chunks, substructures): rows [chunk*rows1, ...) of [K_II^-1 ; M]
+// grid (chunks, substructures, columns): rows [chunk*rows1, ...) of [K_II^-1 ; M]
 __global__ void __launch_bounds__(kNT) k_wide_pre(WideDev W) {
   extern __shared__ double sh[];
   if (W.stop && *W.stop) return;
   const LevelDev& L = W.L;
-  const int s = blockIdx.y, chunk = blockIdx.x;
+  const int s = blockIdx.y, chunk = blockIdx.x, col = blockIdx.z;
+  const double* b1 = W.b1 + (size_t)col * W.ld_b1;
+  double* r2 = W.r2 + (size_t)col * W.ld_r2;
+  double* Ly = L.y + (size_t)col * W.ld_i;
+  double* Lt = L.t + (size_t)col * W.ld_g;
   const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
   const int nI = L.nint[s];
   const int ng = n - nI;
@@ -40,14 +44,14 @@ __global__ void __launch_bounds__(kNT) k_wide_pre(WideDev W) {
   double* rI = sh;
   for (int i = tid; i < nI; i += kNT) {
     const int k = L.int_gid[L.ioff[s] + i];
-    const double v = wide_r2(W, k);
+    const double v = wide_r2(W, b1, k);
     rI[i] = v;
-    if (chunk == 0) W.r2[k] = v;
+    if (chunk == 0) r2[k] = v;
   }
   if (chunk == 0)
     for (int a = tid; a < ng; a += kNT) {
       const int k = L.gam_gid[L.goff[s] + a];
-      W.r2[k] = wide_r2(W, k);   // every sharer stores the same value
+      r2[k] = wide_r2(W, b1, k);   // every sharer stores the same value
     }
   __syncthreads();
   const double* Ki = W.Kinv + W.kioff[s];
@@ -70,22 +74,27 @@ __global__ void __launch_bounds__(kNT) k_wide_pre(WideDev W) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     if (lane == 0) {
-      if (rho < nI) L.y[L.ioff[s] + rho] = v;
-      else L.t[L.goff[s] + rho - nI] = v;
+      if (rho < nI) Ly[L.ioff[s] + rho] = v;
+      else Lt[L.goff[s] + rho - nI] = v;
     }
   }
 }
 
 // the coarsest problem (solved by every workgroup, it is small) and the
 // prolongation of its solution to the workgroup's slice of interface entries
+// grid (blocks, columns)
 __global__ void __launch_bounds__(kNT) k_wide_coarse(WideDev W) {
   extern __shared__ double sh[];
   if (W.stop && *W.stop) return;
   const LevelDev& L = W.L;
+  const int col = blockIdx.y;
+  const double* Lb = L.b + (size_t)col * W.ld_c;
+  const double* La = L.a + (size_t)col * W.ld_g;
+  double* Lv = L.v + (size_t)col * W.ld_g;
   double* u3 = sh;
   for (int k = threadIdx.x; k < W.ncL; k += kNT) {
     double acc = 0.0;
-    for (int q = L.csh_ptr[k]; q < L.csh_ptr[k + 1]; ++q) acc += L.b[L.csh_flat[q]];
+    for (int q = L.csh_ptr[k]; q < L.csh_ptr[k + 1]; ++q) acc += Lb[L.csh_flat[q]];
     u3[k] = acc;
   }
   __syncthreads();
@@ -97,19 +106,22 @@ __global__ void __launch_bounds__(kNT) k_wide_coarse(WideDev W) {
     const int ng = (L.loc_ptr[s + 1] - L.loc_ptr[s]) - L.nint[s];
     const int c0 = L.coff[s], ncs = L.coff[s + 1] - c0;
     const double* P = L.Psi + L.psioff[s];
-    double w = L.a[f];
+    double w = La[f];
     for (int k = 0; k < ncs; ++k) w += P[a + (size_t)k * ng] * u3[L.cid[c0 + k]];
-    L.v[f] = L.delta[f] * w;
+    Lv[f] = L.delta[f] * w;
   }
 }
 
-// grid (chunks of 64 interior rows, substructures): u_B, then
+// grid (chunks of 64 interior rows, substructures, columns): u_B, then
 // u_I = z_I - M^T u_B with four threads per row (fixed-order reduction)
 __global__ void __launch_bounds__(kNT) k_wide_post(WideDev W) {
   extern __shared__ double sh[];
   if (W.stop && *W.stop) return;
   const LevelDev& L = W.L;
-  const int s = blockIdx.y, chunk = blockIdx.x;
+  const int s = blockIdx.y, chunk = blockIdx.x, col = blockIdx.z;
+  const double* Lv = L.v + (size_t)col * W.ld_g;
+  const double* Ly = L.y + (size_t)col * W.ld_i;
+  double* u2 = W.u2 + (size_t)col * W.ld_u2;
   const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
   const int nI = L.nint[s];
   const int ng = n - nI;
@@ -122,9 +134,9 @@ __global__ void __launch_bounds__(kNT) k_wide_post(WideDev W) {
     const int f = g0 + a;
     const int gi = L.gam_iid[f];
     double acc = 0.0;
-    for (int k = L.sh_ptr[gi]; k < L.sh_ptr[gi + 1]; ++k) acc += L.v[L.sh_flat[k]];
+    for (int k = L.sh_ptr[gi]; k < L.sh_ptr[gi + 1]; ++k) acc += Lv[L.sh_flat[k]];
     uB[a] = acc;
-    if (chunk == 0 && L.sh_flat[L.sh_ptr[gi]] == f) W.u2[L.gam_gid[f]] = acc;
+    if (chunk == 0 && L.sh_flat[L.sh_ptr[gi]] == f) u2[L.gam_gid[f]] = acc;
   }
   __syncthreads();
   const int il = tid & 63, ag = tid >> 6;
@@ -137,7 +149,7 @@ __global__ void __launch_bounds__(kNT) k_wide_post(WideDev W) {
   __syncthreads();
   if (ag == 0 && i < nI) {
     const double m = (part[il] + part[il + 64]) + (part[il + 128] + part[il + 192]);
-    W.u2[L.int_gid[L.ioff[s] + i]] = L.y[L.ioff[s] + i] - m;
+    u2[L.int_gid[L.ioff[s] + i]] = Ly[L.ioff[s] + i] - m;
   }
 }
 
@@ -189,17 +201,18 @@ void launch_wide_ops(hipStream_t st, const LevelDev& L, int nmax_ops, double* Ki
 }
 
 void launch_wide_pre(hipStream_t st, const WideDev& W) {
-  launch_kernel(k_wide_pre, dim3(W.nchunk1, W.L.nsub), dim3(kNT), sizeof(double) * (size_t)max(W.nImax, 1), st, W);
+  launch_kernel(k_wide_pre, dim3(W.nchunk1, W.L.nsub, W.nrhs), dim3(kNT), sizeof(double) * (size_t)max(W.nImax, 1), st,
+                W);
 }
 
 void launch_wide_coarse(hipStream_t st, const WideDev& W) {
   const int nb = max(1, min(64, (W.nflat + kNT - 1) / kNT));
-  launch_kernel(k_wide_coarse, dim3(nb), dim3(kNT), sizeof(double) * (size_t)max(W.ncL, 1), st, W);
+  launch_kernel(k_wide_coarse, dim3(nb, W.nrhs), dim3(kNT), sizeof(double) * (size_t)max(W.ncL, 1), st, W);
 }
 
 void launch_wide_post(hipStream_t st, const WideDev& W) {
-  launch_kernel(k_wide_post, dim3(W.nchunk4, W.L.nsub), dim3(kNT), sizeof(double) * ((size_t)W.ngmax + kNT), st,
-                W);
+  launch_kernel(k_wide_post, dim3(W.nchunk4, W.L.nsub, W.nrhs), dim3(kNT), sizeof(double) * ((size_t)W.ngmax + kNT),
+                st, W);
 }
 
 }  // namespace bddc

@@ -161,10 +161,17 @@ struct WideDev {
   const int32_t* sub_of_flat = nullptr;   // level-2 interface flat entry -> substructure
   int nflat = 0;
   const int32_t* stop = nullptr;
+  // columns: one grid slice per column c; b1, r2, u2 and the level-2 scratch
+  // (L.y interior flat, L.t / L.a / L.v interface flat, L.b coarse flat)
+  // hold nrhs columns at these strides
+  int nrhs = 1;
+  int ld_b1 = 0, ld_r2 = 0, ld_u2 = 0, ld_i = 0, ld_g = 0, ld_c = 0;
 };
 void launch_wide_ops(hipStream_t st, const LevelDev& L, int nmax_ops, double* Kinv, const int64_t* kioff, double* Mt,
                      const int64_t* moff);
 void launch_wide_pre(hipStream_t st, const WideDev& W);
+// k_apply_restrict<true> for W.nrhs columns of W.r2 on W.L (the wide path's level-2 restriction)
+void launch_wide_restrict(hipStream_t st, const WideDev& W, const int32_t* gam_map);
 void launch_wide_coarse(hipStream_t st, const WideDev& W);
 void launch_wide_post(hipStream_t st, const WideDev& W);
 
@@ -261,6 +268,12 @@ bool sweep_fits(int nmax);
 void launch_sweep_pre(hipStream_t st, const LevelDev& L, const double* r);
 void launch_sweep_post(hipStream_t st, const LevelDev& L, double* u, const int32_t* gam_map);
 void launch_sweep_recover(hipStream_t st, const LevelDev& L, const double* x, double* u);
+// condensation (y = L_II^-1 r_I, t = L_GI y) and interior recovery for R <= kMaxRhs
+// columns at once (column c of each vector at c times its stride)
+void launch_sweep_pre_cols(hipStream_t st, const LevelDev& L, const double* r, int64_t ldr, double* y, int ldy, double* t,
+                           int ldt, int R);
+void launch_sweep_recover_cols(hipStream_t st, const LevelDev& L, const double* x, int ldx, const double* y, int ldy,
+                               double* u, int64_t ldu, int R);
 size_t constrained_factor_lds(int ng, int n_r, int n_cr, int ncs);
 void launch_constrained_factor_lds(hipStream_t st, int nsub, size_t lds, const int64_t* koff, const int32_t* loc_ptr,
                                    const int32_t* nint, const int32_t* nr, const int32_t* ncr, const int64_t* croff,
