@@ -279,6 +279,44 @@ __device__ inline double block_sum_of(const double* __restrict__ v, int n, doubl
   return wg_sum(acc, red);
 }
 
+// Live columns of a blocked PCG launch: the indices of the columns not yet
+// finished, in order (lc[0..nl-1]); read once by thread 0 into LDS.
+__device__ inline int live_columns(const PcgDev& P, int* lc) {
+  __shared__ int nl_s;
+  if (threadIdx.x == 0) {
+    int m = 0;
+    for (int c = 0; c < P.nrhs; ++c)
+      if (!P.sc[c].done) lc[m++] = c;
+    nl_s = m;
+  }
+  __syncthreads();
+  return nl_s;
+}
+
+// Column slots: a phase over entries a < m of every live column gives each
+// column a slot of W = m rounded up to whole waves (when W <= kNT), kNT / W
+// columns side by side; thread t works on entry t mod W of column
+// k0 + t / W.  Entry a of a column sits on the same lane of a wave as in the
+// one-column launch, so sums over a slot keep the order of wg_sum.
+__device__ inline int slot_width(int m) { return ((max(m, 1) + 63) / 64) * 64; }
+
+// wg_sum over the threads of each slot of width W (one value per thread), for
+// the kNT / W slots of one pass: out[j] = sum of slot j, to every thread
+__device__ inline void slot_sums(double v, int W, double* red, double* out) {
+  const int nw = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  const int wpw = W >> 6;   // waves per slot
+  if ((int)threadIdx.x < nw / wpw) {
+    double r = 0.0;
+    for (int w = threadIdx.x * wpw; w < (int)(threadIdx.x + 1) * wpw; ++w) r += red[w];
+    out[threadIdx.x] = r;
+  }
+  __syncthreads();
+}
+
 // One block: the sum of n partials in the order of block_sum_of (bitwise the
 // same value) into the scalar `which` (0 p^T S p, 1 r.r, 2 r.z of iteration
 // it).  With many blocks on both sides this replaces every consuming block's
@@ -418,7 +456,9 @@ __device__ inline double sym_row_part(const double* A, int m, int i, int c, int 
 
 __global__ void __launch_bounds__(kNT) k_pcg_matvec(LevelDev L, PcgDev P, int u) {
   extern __shared__ double sh[];
-  __shared__ double red[kNT];
+  __shared__ double red[kMaxRhs * 16];
+  __shared__ double bet[kMaxRhs];
+  __shared__ int lc[kMaxRhs];
   if (P.sc[0].all_done) return;
   const int it = P.sc[0].it_base + u;
   const int s = blockIdx.x;
@@ -427,11 +467,10 @@ __global__ void __launch_bounds__(kNT) k_pcg_matvec(LevelDev L, PcgDev P, int u)
   const int ng = n - nI;
   const int g0 = L.goff[s];
   const int tid = threadIdx.x;
-  double* pl = sh;
-  double* part = sh + ng;
-  // thread (mi, mc) forms the partial row sum of row mi over the columns mc,
-  // mc + nch, ...; its entries of S_s (packed symmetric) are loaded before the
-  // scalars and p are formed, so HBM latency overlaps that work
+  // thread (mi, mc) forms the partial row sums of row mi over the columns mc,
+  // mc + nch, ... for every right-hand side; its entries of S_s (packed
+  // symmetric) are loaded before the scalars and p are formed, so HBM latency
+  // overlaps that work
   const double* Sg = P.Sp + P.spoff[s];
   const int nch = max(1, kNT / max(1, ng));
   const bool narrow = ng <= kNT;
@@ -440,52 +479,79 @@ __global__ void __launch_bounds__(kNT) k_pcg_matvec(LevelDev L, PcgDev P, int u)
   const bool act = narrow && mc < nch;
   SymRowRegs<16, double> sv;
   if (narrow) sv.load(Sg, ng, mi, mc, nch);
-  for (int col = 0; col < P.nrhs; ++col) {
-    PcgScalars* S = P.sc + col;
-    if (S->done) continue;
-    double beta = 0.0;
-    if (it >= 2) {
-      double rz, rz0;
-      if (P.fin) {
-        rz = S->rzs[(it - 1) & 1];
-        rz0 = S->rzs[(it - 2) & 1];
-      } else {
-        rz = block_sum_of(P.rz_part[(it - 1) & 1] + (size_t)col * P.ld_blk, P.nblk, red);
-        rz0 = block_sum_of(P.rz_part[(it - 2) & 1] + (size_t)col * P.ld_blk, P.nblk, red);
+  const int nl = live_columns(P, lc);
+  if (nl == 0) return;
+  const int psz = ng + kNT;                 // part stride per column
+  double* pl = sh;                          // nl x ng
+  double* part = sh + (size_t)nl * ng;      // nl x psz
+  // beta per live column
+  if (it >= 2) {
+    if (P.fin) {
+      if (tid < nl) {
+        const PcgScalars& S = P.sc[lc[tid]];
+        bet[tid] = S.rzs[(it - 1) & 1] / S.rzs[(it - 2) & 1];
       }
-      beta = rz / rz0;
-      if (blockIdx.x == 0 && threadIdx.x == 0) S->betas[min(it - 2, kMaxHist - 1)] = beta;
-    }
-    const size_t ci = (size_t)col * P.ld_if;
-    const double* pold = P.p[(it - 1) & 1] + ci;
-    double* pnew = P.p[it & 1] + ci;
-    const double* z = P.z + ci;
-    for (int a = tid; a < ng; a += kNT) {
-      const int f = g0 + a;
-      const int gi = L.gam_iid[f];
-      const bool own = P.shf4 ? P.shf4[f].x == f : L.sh_flat[L.sh_ptr[gi]] == f;
-      const double pv = (it >= 2) ? z[gi] + beta * pold[gi] : z[gi];
-      pl[a] = pv;
-      if (own) pnew[gi] = pv;
-    }
-    __syncthreads();
-    if (narrow) {
-      if (act) part[mi + mc * ng] = sv.dot(Sg, ng, mi, mc, nch, pl);
     } else {
-      for (int i = tid; i < ng; i += kNT) part[i] = sym_row_part(Sg, ng, i, 0, 1, pl);
+      for (int k = 0; k < nl; ++k) {
+        const size_t o = (size_t)lc[k] * P.ld_blk;
+        const double rz = block_sum_of(P.rz_part[(it - 1) & 1] + o, P.nblk, red);
+        const double rz0 = block_sum_of(P.rz_part[(it - 2) & 1] + o, P.nblk, red);
+        if (tid == 0) bet[k] = rz / rz0;
+      }
     }
     __syncthreads();
-    double e = 0.0;
-    const int nc = narrow ? nch : 1;
-    double* q = P.qloc + (size_t)col * P.ld_flat;
-    for (int i = tid; i < ng; i += kNT) {
-      double acc = 0.0;
-      for (int c = 0; c < nc; ++c) acc += part[i + c * ng];
-      q[g0 + i] = acc;
-      e += pl[i] * acc;
+    if (blockIdx.x == 0 && tid < nl) P.sc[lc[tid]].betas[min(it - 2, kMaxHist - 1)] = bet[tid];
+  }
+  // p_k = z + beta p_{k-1} on the substructure's interface, every live column
+  for (int t = tid; t < ng * nl; t += kNT) {
+    const int k = t / ng, a = t - k * ng;
+    const int f = g0 + a;
+    const int gi = L.gam_iid[f];
+    const bool own = P.shf4 ? P.shf4[f].x == f : L.sh_flat[L.sh_ptr[gi]] == f;
+    const size_t ci = (size_t)lc[k] * P.ld_if;
+    const double pv = (it >= 2) ? P.z[ci + gi] + bet[k] * P.p[(it - 1) & 1][ci + gi] : P.z[ci + gi];
+    pl[k * ng + a] = pv;
+    if (own) P.p[it & 1][ci + gi] = pv;
+  }
+  __syncthreads();
+  if (narrow) {
+    if (act)
+      for (int k = 0; k < nl; ++k) part[k * psz + mi + mc * ng] = sv.dot(Sg, ng, mi, mc, nch, pl + k * ng);
+  } else {
+    for (int k = 0; k < nl; ++k)
+      for (int i = tid; i < ng; i += kNT) part[k * psz + i] = sym_row_part(Sg, ng, i, 0, 1, pl + k * ng);
+  }
+  __syncthreads();
+  // the local products and energies p_s^T S_s p_s, in column slots
+  const int nc = narrow ? nch : 1;
+  const int W = slot_width(ng);
+  if (W <= kNT) {
+    const int per = kNT / W;
+    for (int k0 = 0; k0 < nl; k0 += per) {
+      const int k = k0 + tid / W, i = tid % W;
+      double e = 0.0;
+      if (k < nl && i < ng) {
+        double acc = 0.0;
+        for (int c = 0; c < nc; ++c) acc += part[k * psz + i + c * ng];
+        P.qloc[(size_t)lc[k] * P.ld_flat + g0 + i] = acc;
+        e = pl[k * ng + i] * acc;
+      }
+      slot_sums(e, W, red, bet);
+      if (tid < per && k0 + tid < nl) P.pq_part[(size_t)lc[k0 + tid] * P.ld_sub + s] = bet[tid];
     }
-    e = wg_sum(e, red);   // (ends with a barrier: pl and part are free again)
-    if (tid == 0) P.pq_part[(size_t)col * P.ld_sub + s] = e;
+  } else {
+    for (int k = 0; k < nl; ++k) {
+      double* q = P.qloc + (size_t)lc[k] * P.ld_flat;
+      double e = 0.0;
+      for (int i = tid; i < ng; i += kNT) {
+        double acc = 0.0;
+        for (int c = 0; c < nc; ++c) acc += part[k * psz + i + c * ng];
+        q[g0 + i] = acc;
+        e += pl[k * ng + i] * acc;
+      }
+      e = wg_sum(e, red);
+      if (tid == 0) P.pq_part[(size_t)lc[k] * P.ld_sub + s] = e;
+    }
   }
 }
 
@@ -515,7 +581,9 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
   using TS = typename PrecForm<kPrec>::TS;
   using PS = typename PrecForm<kPrec>::PS;
   extern __shared__ double sh[];
-  __shared__ double red[kNT];
+  __shared__ double red[kMaxRhs * 16];   // (slot sums: waves, then the per-slot results at 16)
+  __shared__ double alph[kMaxRhs];
+  __shared__ int lc[kMaxRhs];
   if (P.sc[0].all_done) return;
   const int it = u < 0 ? 0 : P.sc[0].it_base + u;
   const int s = blockIdx.x;
@@ -526,9 +594,11 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
   const int wave = tid >> 6, lane = tid & 63;
   const int n_r = L.nr[s];
   const int ncs = L.coff[s + 1] - L.coff[s];
-  double* g = sh;                        // ngmax
-  double* part = sh + ngmax;             // kNT + ngmax
-  double* xv = part + kNT + ngmax;       // factored form: x, then v (nrmax)
+  const int R = P.nrhs;
+  const int psz = kNT + ngmax;                          // part stride per column
+  double* g = sh;                                       // R x ngmax
+  double* part = sh + (size_t)R * ngmax;                // R x psz
+  double* xv = part + (size_t)R * psz;                  // factored form: x, then v (nrmax)
   float* Tl = reinterpret_cast<float*>(xv + nrmax);                       // factored form: packed W
   float* Ql = reinterpret_cast<float*>(xv + nrmax + ((size_t)nrmax * (nrmax + 1) / 2));   // Q
   float* dinv = Ql + (size_t)nrmax * ncsmax;                              // D^-1
@@ -571,27 +641,39 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
     const float* Qg = P.Q32 + P.croff[s];
     for (int a = tid; a < nq; a += kNT) Ql[a] = Qg[a];
   }
-  bool staged = false;
-  for (int col = 0; col < P.nrhs; ++col) {
-  PcgScalars* S = P.sc + col;
-  if (S->done) continue;
-  const size_t ci = (size_t)col * P.ld_if, cf = (size_t)col * P.ld_flat;
+  const int nl = live_columns(P, lc);
+  if (nl == 0) return;
+  // every phase below serves all live columns (column k of g / part in LDS)
   if (it == 0) {
-    for (int a = tid; a < ng; a += kNT) g[a] = L.delta[g0 + a] * P.r[0][ci + L.gam_iid[g0 + a]];
+    for (int t = tid; t < ng * nl; t += kNT) {
+      const int k = t / ng, a = t - k * ng;
+      g[k * ngmax + a] = L.delta[g0 + a] * P.r[0][(size_t)lc[k] * P.ld_if + L.gam_iid[g0 + a]];
+    }
   } else {
-    const double rz = P.fin ? S->rzs[(it - 1) & 1]
-                            : block_sum_of(P.rz_part[(it - 1) & 1] + (size_t)col * P.ld_blk, P.nblk, red);
-    const double pq = P.fin ? S->pqs : block_sum_of(P.pq_part + (size_t)col * P.ld_sub, P.nsub1, red);
-    const double alpha = rz / pq;
-    const double* rold = P.r[(it - 1) & 1] + ci;
-    double* rnew = P.r[it & 1] + ci;
-    const double* p = P.p[it & 1] + ci;
-    double* x = P.x + ci;
-    const double* ql = P.qloc + cf;
-    double rr = 0.0;
-    for (int a = tid; a < ng; a += kNT) {
+    // alpha = r.z / p^T S p per live column
+    if (P.fin) {
+      if (tid < nl) {
+        const PcgScalars& S = P.sc[lc[tid]];
+        alph[tid] = S.rzs[(it - 1) & 1] / S.pqs;
+      }
+    } else {
+      for (int k = 0; k < nl; ++k) {
+        const double rz = block_sum_of(P.rz_part[(it - 1) & 1] + (size_t)lc[k] * P.ld_blk, P.nblk, red);
+        const double pq = block_sum_of(P.pq_part + (size_t)lc[k] * P.ld_sub, P.nsub1, red);
+        if (tid == 0) alph[k] = rz / pq;
+      }
+    }
+    __syncthreads();
+    const double* rold = P.r[(it - 1) & 1];
+    double* rnew = P.r[it & 1];
+    const double* p = P.p[it & 1];
+    // r_k = r_{k-1} - alpha sum of the sharers' q; g = delta r; owners store
+    // r_k and update x; partial r.r -- entry a of column k in its slot
+    auto update = [&](int k, int a) {
       const int f = g0 + a;
       const int gi = L.gam_iid[f];
+      const size_t ci = (size_t)lc[k] * P.ld_if;
+      const double* ql = P.qloc + (size_t)lc[k] * P.ld_flat;
       double q = 0.0;
       bool own;
       if (P.shf4) {
@@ -603,109 +685,142 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
         if (sf.w >= 0) q += ql[sf.w];
         own = sf.x == f;
       } else {
-        for (int k = L.sh_ptr[gi]; k < L.sh_ptr[gi + 1]; ++k) q += ql[L.sh_flat[k]];
+        for (int m = L.sh_ptr[gi]; m < L.sh_ptr[gi + 1]; ++m) q += ql[L.sh_flat[m]];
         own = L.sh_flat[L.sh_ptr[gi]] == f;
       }
-      const double ri = rold[gi] - alpha * q;
-      g[a] = L.delta[f] * ri;
+      const double ri = rold[ci + gi] - alph[k] * q;
+      g[k * ngmax + a] = L.delta[f] * ri;
+      double rr = 0.0;
       if (own) {
-        rnew[gi] = ri;
-        x[gi] += alpha * p[gi];
-        rr += ri * ri;
+        rnew[ci + gi] = ri;
+        P.x[ci + gi] += alph[k] * p[ci + gi];
+        rr = ri * ri;
       }
-    }
-    rr = wg_sum(rr, red);
-    if (tid == 0) P.rr_part[(size_t)col * P.ld_sub + s] = rr;
-    if (s == 0 && tid == 0) {
-      S->iters = it;
-      S->alphas[min(it - 1, kMaxHist - 1)] = alpha;
-    }
-  }
-  if constexpr (kPrec == 2) {
-    if (!staged) pt.finish();
-  }
-  staged = true;
-  __syncthreads();
-  // b = Psi^T g, one wave per coarse dof
-  for (int k = wave, m = 0; k < ncs; k += kNT / 64, ++m) {
-    double acc = 0.0;
-    if (m < kPV) {
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const int a = lane + 64 * q;
-        if (a < ng) acc += static_cast<double>(pv[m][q]) * g[a];
+      return rr;
+    };
+    auto publish = [&](int k, double rr) {
+      P.rr_part[(size_t)lc[k] * P.ld_sub + s] = rr;
+      if (s == 0) {
+        PcgScalars& S = P.sc[lc[k]];
+        S.iters = it;
+        S.alphas[min(it - 1, kMaxHist - 1)] = alph[k];
       }
-      for (int a = lane + 128; a < ng; a += 64) acc += static_cast<double>(Pg[a + (size_t)k * ng]) * g[a];
+    };
+    const int W = slot_width(ng);
+    if (W <= kNT) {
+      const int per = kNT / W;
+      double* out = red + 16;
+      for (int k0 = 0; k0 < nl; k0 += per) {
+        const int k = k0 + tid / W, a = tid % W;
+        const double rr = (k < nl && a < ng) ? update(k, a) : 0.0;
+        slot_sums(rr, W, red, out);
+        if (tid < per && k0 + tid < nl) publish(k0 + tid, out[tid]);
+      }
     } else {
-      for (int a = lane; a < ng; a += 64) acc += static_cast<double>(Pg[a + (size_t)k * ng]) * g[a];
+      for (int k = 0; k < nl; ++k) {
+        double rr = 0.0;
+        for (int a = tid; a < ng; a += kNT) rr += update(k, a);
+        rr = wg_sum(rr, red);
+        if (tid == 0) publish(k, rr);
+      }
     }
+  }
+  if constexpr (kPrec == 2) pt.finish();
+  __syncthreads();
+  // b = Psi^T g, one wave per coarse dof, every live column
+  for (int kd = wave, m = 0; kd < ncs; kd += kNT / 64, ++m) {
+    for (int k = 0; k < nl; ++k) {
+      const double* gk = g + k * ngmax;
+      double acc = 0.0;
+      if (m < kPV) {
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
-    if (lane == 0) P.b[(size_t)col * P.ld_cflat + L.coff[s] + k] = acc;
+        for (int q = 0; q < 2; ++q) {
+          const int a = lane + 64 * q;
+          if (a < ng) acc += static_cast<double>(pv[m][q]) * gk[a];
+        }
+        for (int a = lane + 128; a < ng; a += 64) acc += static_cast<double>(Pg[a + (size_t)kd * ng]) * gk[a];
+      } else {
+        for (int a = lane; a < ng; a += 64) acc += static_cast<double>(Pg[a + (size_t)kd * ng]) * gk[a];
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+      if (lane == 0) P.b[(size_t)lc[k] * P.ld_cflat + L.coff[s] + kd] = acc;
+    }
   }
   if constexpr (kPrec == 2) {
+    // factored form: two dependent passes over W per column
     const int n_cr = P.ncr[s];
-    for (ColWalk w_(tid, kNT, n_r); w_.j < nch; w_.next()) {
-      const int i = w_.i, c = w_.j;
-      [[maybe_unused]] const int idx = i + c * n_r;
-      double acc = 0.0;
-      for (int j = c; j <= i; j += nch)
-        acc += static_cast<double>(Tl[packed_col(j, n_r) + (i - j)]) * (g[j] * static_cast<double>(dinv[j]));
-      part[idx] = acc;
-    }
-    __syncthreads();
-    for (int i = tid; i < n_r; i += kNT) {
-      double acc = 0.0;
-      for (int c = 0; c < nch; ++c) acc += part[i + c * n_r];
-      xv[i] = acc;
-    }
-    __syncthreads();
-    if (n_cr > 0 && wave == 0) {
-      for (int rep = 0; rep < 2; ++rep)
-        for (int m = 0; m < n_cr; ++m) {
-          const float* q = Ql + (size_t)m * n_r;
-          double d = 0.0;
-          for (int a = lane; a < n_r; a += 64) d += static_cast<double>(q[a]) * xv[a];
+    for (int k = 0; k < nl; ++k) {
+      const double* gk = g + k * ngmax;
+      double* pk = part;
+      double* da = P.da + (size_t)lc[k] * P.ld_flat;
+      for (ColWalk w_(tid, kNT, n_r); w_.j < nch; w_.next()) {
+        const int i = w_.i, c = w_.j;
+        [[maybe_unused]] const int idx = i + c * n_r;
+        double acc = 0.0;
+        for (int j = c; j <= i; j += nch)
+          acc += static_cast<double>(Tl[packed_col(j, n_r) + (i - j)]) * (gk[j] * static_cast<double>(dinv[j]));
+        pk[idx] = acc;
+      }
+      __syncthreads();
+      for (int i = tid; i < n_r; i += kNT) {
+        double acc = 0.0;
+        for (int c = 0; c < nch; ++c) acc += pk[i + c * n_r];
+        xv[i] = acc;
+      }
+      __syncthreads();
+      if (n_cr > 0 && wave == 0) {
+        for (int rep = 0; rep < 2; ++rep)
+          for (int m = 0; m < n_cr; ++m) {
+            const float* q = Ql + (size_t)m * n_r;
+            double d = 0.0;
+            for (int a = lane; a < n_r; a += 64) d += static_cast<double>(q[a]) * xv[a];
 #pragma unroll
-          for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
-          for (int a = lane; a < n_r; a += 64) xv[a] -= d * static_cast<double>(q[a]);
-        }
-    }
-    __syncthreads();
-    for (ColWalk w_(tid, kNT, n_r); w_.j < nch; w_.next()) {
-      const int j = w_.i, c = w_.j;
-      [[maybe_unused]] const int idx = j + c * n_r;
-      const int cj = packed_col(j, n_r) - j;
-      double acc = 0.0;
-      for (int i = j + c; i < n_r; i += nch) acc += static_cast<double>(Tl[cj + i]) * xv[i];
-      part[idx] = acc;
-    }
-    __syncthreads();
-    for (int i = tid; i < n_r; i += kNT) {
-      double acc = 0.0;
-      for (int c = 0; c < nch; ++c) acc += part[i + c * n_r];
-      P.da[cf + g0 + i] = L.delta[g0 + i] * (acc * static_cast<double>(dinv[i]));
+            for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
+            for (int a = lane; a < n_r; a += 64) xv[a] -= d * static_cast<double>(q[a]);
+          }
+      }
+      __syncthreads();
+      for (ColWalk w_(tid, kNT, n_r); w_.j < nch; w_.next()) {
+        const int j = w_.i, c = w_.j;
+        [[maybe_unused]] const int idx = j + c * n_r;
+        const int cj = packed_col(j, n_r) - j;
+        double acc = 0.0;
+        for (int i = j + c; i < n_r; i += nch) acc += static_cast<double>(Tl[cj + i]) * xv[i];
+        pk[idx] = acc;
+      }
+      __syncthreads();
+      for (int i = tid; i < n_r; i += kNT) {
+        double acc = 0.0;
+        for (int c = 0; c < nch; ++c) acc += pk[i + c * n_r];
+        da[g0 + i] = L.delta[g0 + i] * (acc * static_cast<double>(dinv[i]));
+      }
+      __syncthreads();   // part and x/v are taken by the next column
     }
   } else {
     if (narrow) {
-      if (act) part[ti + tc * n_r] = tv.dot(Tg, n_r, ti, tc, nch, g);
+      if (act)
+        for (int k = 0; k < nl; ++k) part[k * psz + ti + tc * n_r] = tv.dot(Tg, n_r, ti, tc, nch, g + k * ngmax);
     } else {
-      for (int i = tid; i < n_r; i += kNT) {
-        double acc = 0.0;
-        for (int j = 0; j < n_r; ++j) acc += static_cast<double>(Tg[sym_index(i, j, n_r)]) * g[j];
-        part[i] = acc;
-      }
+      for (int k = 0; k < nl; ++k)
+        for (int i = tid; i < n_r; i += kNT) {
+          double acc = 0.0;
+          for (int j = 0; j < n_r; ++j) acc += static_cast<double>(Tg[sym_index(i, j, n_r)]) * g[k * ngmax + j];
+          part[k * psz + i] = acc;
+        }
     }
     __syncthreads();
     const int nc = narrow ? nch : 1;
-    for (int i = tid; i < n_r; i += kNT) {
+    for (int t = tid; t < n_r * nl; t += kNT) {
+      const int k = t / n_r, i = t - k * n_r;
       double acc = 0.0;
-      for (int c = 0; c < nc; ++c) acc += part[i + c * n_r];
-      P.da[cf + g0 + i] = L.delta[g0 + i] * acc;
+      for (int c = 0; c < nc; ++c) acc += part[k * psz + i + c * n_r];
+      P.da[(size_t)lc[k] * P.ld_flat + g0 + i] = L.delta[g0 + i] * acc;
     }
   }
-  for (int a = n_r + tid; a < ng; a += kNT) P.da[cf + g0 + a] = 0.0;
-  __syncthreads();   // g, part and x/v are taken by the next column
+  for (int t = tid; t < (ng - n_r) * nl; t += kNT) {
+    const int k = t / (ng - n_r), a = n_r + t - k * (ng - n_r);
+    P.da[(size_t)lc[k] * P.ld_flat + g0 + a] = 0.0;
   }
 }
 
@@ -828,41 +943,67 @@ __global__ void __launch_bounds__(kNT) k_pack_pcg(LevelDev L, PcgDev P) {
 // the dof's row of the delta-weighted coarse basis times u_c  (ML-uBi-1), and
 // the per-block partial of r_k . z.
 __global__ void __launch_bounds__(kNT) k_pcg_prolong_post(LevelDev L, PcgDev P, int u) {
-  __shared__ double red[kNT];
-  __shared__ int live[kMaxRhs];
+  __shared__ double red[kMaxRhs * 16];
+  __shared__ int lc[kMaxRhs];
+  __shared__ int gc[kMaxRhs];
+  __shared__ int ngo_s;
   if (P.sc[0].all_done) return;
   const int it = u < 0 ? 0 : P.sc[0].it_base + u;
   const bool check = it > 0;
   const int parity = it & 1;
   // the columns' states on entry (block 0 updates them below)
-  if (threadIdx.x < P.nrhs) live[threadIdx.x] = P.sc[threadIdx.x].done == 0;
-  __syncthreads();
-  int going = 0;
-  for (int col = 0; col < P.nrhs; ++col) {
-    if (!live[col]) continue;
-    PcgScalars* S = P.sc + col;
-    if (check) {
-      const double rr = P.fin ? S->rrs : block_sum_of(P.rr_part + (size_t)col * P.ld_sub, P.nsub1, red);
-      const bool conv = rr <= S->thr2;
-      const bool maxed = S->iters >= S->maxit;
-      if (blockIdx.x == 0 && threadIdx.x == 0) {
-        S->rr = rr;
-        if (conv || maxed) S->done = conv ? 1 : 2;
+  const int nl = live_columns(P, lc);
+  // convergence test on r.r per live column; gc = the columns still going
+  __shared__ double rrv[kMaxRhs];
+  if (check) {
+    if (P.fin) {
+      if (threadIdx.x < nl) rrv[threadIdx.x] = P.sc[lc[threadIdx.x]].rrs;
+    } else {
+      for (int k = 0; k < nl; ++k) {
+        const double rr = block_sum_of(P.rr_part + (size_t)lc[k] * P.ld_sub, P.nsub1, red);
+        if (threadIdx.x == 0) rrv[k] = rr;
       }
-      if (conv || maxed) continue;
     }
-    ++going;
-    // eight lanes per interface dof, fixed-order reduction over the eight
-    const size_t ci = (size_t)col * P.ld_if;
-    const double* r = P.r[parity] + ci;
-    const double* da = P.da + (size_t)col * P.ld_flat;
-    const double* uc = P.uc + (size_t)col * P.ld_coarse;
-    const int gi = (blockIdx.x * kNT + threadIdx.x) >> 3;
-    const int sub = threadIdx.x & 7;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int m = 0;
+      for (int k = 0; k < nl; ++k) {
+        PcgScalars* S = P.sc + lc[k];
+        const bool conv = rrv[k] <= S->thr2;
+        const bool maxed = S->iters >= S->maxit;
+        if (blockIdx.x == 0) {
+          S->rr = rrv[k];
+          if (conv || maxed) S->done = conv ? 1 : 2;
+        }
+        if (!(conv || maxed)) gc[m++] = lc[k];
+      }
+      ngo_s = m;
+    }
+  } else if (threadIdx.x == 0) {
+    for (int k = 0; k < nl; ++k) gc[k] = lc[k];
+    ngo_s = nl;
+  }
+  __syncthreads();
+  const int ngo = ngo_s;
+  if (ngo == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) P.sc[0].all_done = 1;
+    return;
+  }
+  // z = sum over the sharers of delta T_rr g plus the averaged coarse basis
+  // row times u_c: eight lanes per interface dof, fixed-order reduction over
+  // the eight; the partial r.z of each going column is reduced as wg_sum does
+  // (per wave here, over the waves below)
+  const int gi = (blockIdx.x * kNT + threadIdx.x) >> 3;
+  const int sub = threadIdx.x & 7;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = kNT / 64;
+  for (int k = 0; k < ngo; ++k) {
+    const size_t ci = (size_t)gc[k] * P.ld_if;
+    const double* da = P.da + (size_t)gc[k] * P.ld_flat;
+    const double* uc = P.uc + (size_t)gc[k] * P.ld_coarse;
     double acc = 0.0;
     if (gi < P.nif) {
       const int k0 = L.sh_ptr[gi], k1 = L.sh_ptr[gi + 1];
-      for (int k = k0 + sub; k < k1; k += 8) acc += da[L.sh_flat[k]];
+      for (int m = k0 + sub; m < k1; m += 8) acc += da[L.sh_flat[m]];
       for (int j = P.phi_ptr[gi] + sub; j < P.phi_ptr[gi + 1]; j += 8) acc += P.phi_w[j] * uc[P.phi_ids[j]];
     }
     acc += __shfl_xor(acc, 1);
@@ -871,12 +1012,18 @@ __global__ void __launch_bounds__(kNT) k_pcg_prolong_post(LevelDev L, PcgDev P, 
     double rz = 0.0;
     if (gi < P.nif && sub == 0) {
       P.z[ci + gi] = acc;
-      rz = acc * r[gi];
+      rz = acc * P.r[parity][ci + gi];
     }
-    rz = wg_sum(rz, red);
-    if (threadIdx.x == 0) P.rz_part[parity][(size_t)col * P.ld_blk + blockIdx.x] = rz;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) rz += __shfl_xor(rz, o, 64);
+    if (lane == 0) red[k * 16 + wave] = rz;
   }
-  if (going == 0 && blockIdx.x == 0 && threadIdx.x == 0) P.sc[0].all_done = 1;
+  __syncthreads();
+  if ((int)threadIdx.x < ngo) {
+    double r = 0.0;
+    for (int w = 0; w < nw; ++w) r += red[threadIdx.x * 16 + w];
+    P.rz_part[parity][(size_t)gc[threadIdx.x] * P.ld_blk + blockIdx.x] = r;
+  }
 }
 
 // Rows of the averaged coarse basis: for interface dof gi, in sharer order,
@@ -906,7 +1053,7 @@ __global__ void __launch_bounds__(kNT) k_build_phi(LevelDev L, int nif, const in
 }
 
 void launch_pcg_matvec(hipStream_t st, const LevelDev& L, int ngmax, const PcgDev& P, int u) {
-  const size_t lds = sizeof(double) * ((size_t)ngmax + kNT + ngmax);
+  const size_t lds = sizeof(double) * (size_t)P.nrhs * ((size_t)ngmax + kNT + ngmax);
   launch_kernel(k_pcg_matvec, dim3(L.nsub), dim3(kNT), lds, st, L, P, u);
 }
 void launch_pcg_sum(hipStream_t st, const PcgDev& P, int which, int u) {
@@ -917,8 +1064,8 @@ void launch_pcg_advance(hipStream_t st, const PcgDev& P, int n) {
 }
 void launch_pcg_update_restrict(hipStream_t st, const LevelDev& L, int ngmax, int nrmax, int ncsmax, const PcgDev& P,
                                 int u) {
-  // doubles: g | part ; factored form also: x/v (doubles) | W | Q | D^-1 (floats)
-  size_t lds = sizeof(double) * ((size_t)ngmax + kNT + ngmax);
+  // doubles: g | part per column; factored form also: x/v (doubles) | W | Q | D^-1 (floats)
+  size_t lds = sizeof(double) * (size_t)P.nrhs * ((size_t)ngmax + kNT + ngmax);
   if (P.prec == 2)
     lds += sizeof(double) * (nrmax + (size_t)nrmax * (nrmax + 1) / 2) +
            sizeof(float) * ((size_t)nrmax * ncsmax + nrmax);
