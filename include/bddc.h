@@ -131,6 +131,49 @@ bddc_status bddc_solve(bddc_handle h, const double* f, double* u, int32_t nrhs, 
 /* Sizes and diagnostics.  Errors: BDDC_EINVAL. */
 bddc_status bddc_query(bddc_handle h, bddc_info* info);
 
+/* Launch configuration of bddc_solve (no effect on the method: Algorithm
+ * "Multilevel BDDC" inside PCG, Section 5).  deep_path: how levels >= 2 and
+ * the coarsest solve run -- BDDC_DEEP_COOP (one cooperative launch, one
+ * workgroup per level-2 substructure), BDDC_DEEP_WIDE (row blocks of dense
+ * level-2 operators over many workgroups), BDDC_DEEP_FUSED (all deep levels in
+ * one workgroup), BDDC_DEEP_LEVELS (one launch per phase and level); only the
+ * paths planned at set-up are available (bit p of `available`, read-only).
+ * finalize: 1 sums the PCG partials once per producing launch in a one-block
+ * launch, 0 lets every consuming block sum them.  graph: 1 replays a captured
+ * chunk of PCG launches, 0 launches directly.  check: PCG iterations between
+ * host convergence checks (4, 8 or 16).  solve_ms: the median time of one
+ * bddc_solve with this configuration when bddc_autotune chose it, else 0.
+ * finalize, graph and check leave the iterates bitwise unchanged; the deep
+ * paths agree to rounding. */
+typedef enum { BDDC_DEEP_COOP = 0, BDDC_DEEP_WIDE = 1, BDDC_DEEP_FUSED = 2, BDDC_DEEP_LEVELS = 3 } bddc_deep_path;
+typedef struct {
+  int32_t deep_path;
+  int32_t finalize;
+  int32_t graph;
+  int32_t check;
+  int32_t available;
+  double solve_ms;
+} bddc_tuning;
+
+/* Current launch configuration (bddc_get_tuning) or a new one
+ * (bddc_set_tuning; `available` and `solve_ms` are ignored).
+ * Errors: BDDC_EINVAL (NULL, a deep path not available, check not 4/8/16,
+ * finalize or graph not 0/1). */
+bddc_status bddc_get_tuning(bddc_handle h, bddc_tuning* t);
+bddc_status bddc_set_tuning(bddc_handle h, const bddc_tuning* t);
+
+/* Autotuner: times bddc_solve of the nrhs device columns f (leading dimension
+ * ld; u receives the solutions, as for bddc_solve) under the available launch
+ * configurations -- one knob at a time (deep path, finalize, check, graph),
+ * keeping the fastest value of each -- with the median of `reps` (>= 1) solves
+ * per candidate, installs the fastest configuration on the handle and returns
+ * it in *t (may be NULL).  The choice is also remembered for the problem's
+ * shape (mesh, partition sizes, levels, constraints, precision, coarse sizes):
+ * a later bddc_setup of the same shape starts from it.  Synchronises the
+ * stream.  Errors: BDDC_EINVAL, BDDC_ENOCONV, BDDC_EDEVICE. */
+bddc_status bddc_autotune(bddc_handle h, const double* f, double* u, int32_t nrhs, int64_t ld, double rtol,
+                          int32_t reps, bddc_tuning* t, void* hip_stream);
+
 /* Eigenvalues of the pair eigenproblem of Theorem "local-est" for edge
  * `edge` (0-based, pairs (s,t), s < t, in increasing order) of level `level`
  * (1-based) of an ADAPTIVE set-up.  Writes up to cap eigenvalues in

@@ -47,9 +47,16 @@ class BddcInfoC(ctypes.Structure):
                 ("matvec_bytes", ctypes.c_int64)]
 
 
+class BddcTuningC(ctypes.Structure):
+    _fields_ = [("deep_path", ctypes.c_int32), ("finalize", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("check", ctypes.c_int32), ("available", ctypes.c_int32), ("solve_ms", ctypes.c_double)]
+
+
+DEEP_PATHS = ("coop", "wide", "fused", "levels")
+
 SYMBOLS = ["bddc_plan", "bddc_setup", "bddc_apply", "bddc_solve", "bddc_query", "bddc_edge_eigs",
-           "bddc_edge_constraints", "bddc_timing_start", "bddc_timing_stop", "bddc_last_error",
-           "bddc_status_string", "bddc_destroy"]
+           "bddc_edge_constraints", "bddc_timing_start", "bddc_timing_stop", "bddc_get_tuning",
+           "bddc_set_tuning", "bddc_autotune", "bddc_last_error", "bddc_status_string", "bddc_destroy"]
 
 _lib = None
 
@@ -78,6 +85,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.bddc_edge_constraints.argtypes = [vp, i32, i32, P(i32), i32, P(dbl), i32, P(i32), P(i32)]
     lib.bddc_timing_start.argtypes = [ctypes.c_char_p, i32]
     lib.bddc_timing_stop.argtypes = [P(dbl), P(i64), P(dbl), P(dbl)]
+    lib.bddc_get_tuning.argtypes = [vp, P(BddcTuningC)]
+    lib.bddc_set_tuning.argtypes = [vp, P(BddcTuningC)]
+    lib.bddc_autotune.argtypes = [vp, vp, vp, i32, i64, dbl, i32, P(BddcTuningC), vp]
     lib.bddc_status_string.argtypes = [i32]
     lib.bddc_status_string.restype = ctypes.c_char_p
     lib.bddc_destroy.argtypes = [vp]
@@ -244,6 +254,34 @@ class Solver:
             _check(st, "bddc_solve")
         return u, list(iters), list(relres)
 
+    def tuning(self) -> dict:
+        """The handle's launch configuration (bddc_get_tuning)."""
+        t = BddcTuningC()
+        _check(self.lib.bddc_get_tuning(self.h, ctypes.byref(t)), "bddc_get_tuning")
+        return _tuning_dict(t)
+
+    def set_tuning(self, **kw):
+        """Change knobs of the launch configuration: deep_path ("coop", "wide",
+        "fused", "levels"), finalize, graph (0/1), check (4, 8, 16)."""
+        t = BddcTuningC()
+        _check(self.lib.bddc_get_tuning(self.h, ctypes.byref(t)), "bddc_get_tuning")
+        for k, v in kw.items():
+            setattr(t, k, DEEP_PATHS.index(v) if k == "deep_path" else int(v))
+        _check(self.lib.bddc_set_tuning(self.h, ctypes.byref(t)), "bddc_set_tuning")
+
+    def autotune(self, f, u=None, rtol=1e-8, reps=3, stream=None) -> dict:
+        """Time bddc_solve of f under the available launch configurations and
+        keep the fastest (bddc_autotune); returns the chosen configuration."""
+        import torch
+        nrhs, ld = _vec_args(f, self.n_free)
+        if u is None:
+            u = torch.empty_like(f)
+        t = BddcTuningC()
+        _check(self.lib.bddc_autotune(self.h, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(u.data_ptr()), nrhs,
+                                      ld, float(rtol), int(reps), ctypes.byref(t),
+                                      ctypes.c_void_p(_stream_ptr(stream))), "bddc_autotune")
+        return _tuning_dict(t)
+
     def edge_eigs(self, level: int, edge: int):
         n_lam, n_sel, ned = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         pair = (ctypes.c_int32 * 2)()
@@ -264,6 +302,11 @@ class Solver:
                                               None), "bddc_edge_constraints")
         Q = np.array(q[:ne.value * m.value]).reshape(m.value, ne.value).T
         return np.array(dofs[:ne.value]), Q
+
+
+def _tuning_dict(t: BddcTuningC) -> dict:
+    return {"deep_path": DEEP_PATHS[t.deep_path], "finalize": t.finalize, "graph": t.graph, "check": t.check,
+            "available": [p for i, p in enumerate(DEEP_PATHS) if t.available >> i & 1], "solve_ms": t.solve_ms}
 
 
 def timing_start(kernel: str, every: int = 1):

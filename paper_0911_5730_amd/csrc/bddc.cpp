@@ -418,6 +418,12 @@ struct bddc_ctx {
   bddc::PcgDev pcg;
   // deep levels (2 .. L-1) and the coarsest solve in one workgroup when small
   bool fused_deep = false;
+  // launch configuration (bddc_tuning): the deep path in use, PCG iterations
+  // per chunk, and what the autotuner measured
+  int deep_sel = BDDC_DEEP_LEVELS;
+  int pcg_check = 8;
+  double tuned_ms = 0.0;
+  std::string shape_key;
   bddc::DeepArgs deep;
   // one deep level and the coarsest solve in one cooperative launch
   std::vector<void*> staged;   // pinned upload buffers of the setup, released after it synchronises
@@ -1293,7 +1299,7 @@ static void run_deep_at(bddc_ctx* h, hipStream_t st, const double* b1, double* u
     launch_coarsest_solve(st, l1.nc, h->AL, l1.d.rc, uc, l1.dev.stop);
     return;
   }
-  if (h->coop_deep) {
+  if (h->deep_sel == BDDC_DEEP_COOP) {
     CoopDev C = h->coop;
     C.stop = l1.dev.stop;
     C.b1 = b1;
@@ -1302,7 +1308,7 @@ static void run_deep_at(bddc_ctx* h, hipStream_t st, const double* b1, double* u
     launch_deep_coop(st, C, h->coop_launch);
     return;
   }
-  if (h->wide_deep) {
+  if (h->deep_sel == BDDC_DEEP_WIDE) {
     Level& l2 = *h->levels[1];
     WideDev W = h->wide;
     W.b1 = b1;
@@ -1316,7 +1322,7 @@ static void run_deep_at(bddc_ctx* h, hipStream_t st, const double* b1, double* u
     launch_wide_post(st, W);
     return;
   }
-  if (h->fused_deep) {
+  if (h->deep_sel == BDDC_DEEP_FUSED) {
     DeepArgs A = h->deep;
     A.stop = l1.dev.stop;
     A.b1 = b1;
@@ -1342,7 +1348,7 @@ static void run_deep_cols(bddc_ctx* h, hipStream_t st, const double* b1, int ldb
     launch_coarse_direct_cols(st, l1.nc, l1.d.csh_ptr, l1.d.csh_flat, b1, ldb, h->AL, uc, ldu, R, l1.dev.stop);
     return;
   }
-  if (h->wide_deep && R <= kMaxRhs) {
+  if (h->deep_sel == BDDC_DEEP_WIDE && R <= kMaxRhs) {
     Level& l2 = *h->levels[1];
     WideDev W = h->wide;
     W.nrhs = R;
@@ -1358,7 +1364,7 @@ static void run_deep_cols(bddc_ctx* h, hipStream_t st, const double* b1, int ldb
     launch_wide_post(st, W);
     return;
   }
-  if (h->coop_deep && h->levels.size() > 1 && R <= h->coop_rmax) {
+  if (h->deep_sel == BDDC_DEEP_COOP && R <= h->coop_rmax) {
     CoopDev C = h->coop;
     C.stop = h->levels[0]->dev.stop;
     C.nrhs = R;
@@ -1651,9 +1657,16 @@ static bool plan_wide(bddc_ctx* h) {
 static void plan_deep(bddc_ctx* h) {
   h->fused_deep = false;
   const int L = (int)h->levels.size();
+  h->deep_sel = BDDC_DEEP_LEVELS;
   if (L < 2 || L - 1 > kMaxDeep) return;
-  if (plan_coop(h)) return;
-  if (plan_wide(h)) return;
+  // one deep level: both the cooperative and the row-block path where they
+  // apply (the tuning chooses; the cooperative one first)
+  const bool coop = plan_coop(h);
+  const bool wide = plan_wide(h);
+  if (coop || wide) {
+    h->deep_sel = coop ? BDDC_DEEP_COOP : BDDC_DEEP_WIDE;
+    return;
+  }
   const char* env = getenv("BDDC_DEEP_PATH");
   if (env && (std::string(env) == "levels" || std::string(env) == "coop" || std::string(env) == "wide")) return;
   double bytes = 0;
@@ -1694,6 +1707,7 @@ static void plan_deep(bddc_ctx* h) {
   A.b1 = l1.d.b;
   A.wstride = wstride;
   h->fused_deep = true;
+  h->deep_sel = BDDC_DEEP_FUSED;
 }
 
 // symmetric tridiagonal extreme eigenvalues by Sturm bisection
@@ -1909,7 +1923,7 @@ static int pcg_block(bddc_ctx* h, const double* f, double* u, int64_t ld, int R,
     }
     if (P.fin) launch_pcg_sum(q, P, 2, uu);
   };
-  const int check = 8;   // iterations between host convergence checks
+  const int check = h->pcg_check;   // iterations between host convergence checks
   auto chunk = [&](hipStream_t q, int it0) {
     for (int uu = 0; uu < check; ++uu) {
       const int it = it0 + uu;
@@ -2109,6 +2123,64 @@ bddc_status bddc_plan(const bddc_problem* p, bddc_info* info) {
   });
 }
 
+namespace bddc {
+namespace {
+
+// launch configurations chosen by the autotuner, by problem shape
+std::mutex g_tune_mu;
+std::map<std::string, bddc_tuning> g_tune_cache;
+
+int deep_available(const bddc_ctx* h) {
+  int m = 1 << BDDC_DEEP_LEVELS;
+  if (h->coop_deep) m |= 1 << BDDC_DEEP_COOP;
+  if (h->wide_deep) m |= 1 << BDDC_DEEP_WIDE;
+  if (h->fused_deep) m |= 1 << BDDC_DEEP_FUSED;
+  return m;
+}
+
+bddc_tuning current_tuning(const bddc_ctx* h) {
+  bddc_tuning t{};
+  t.deep_path = h->deep_sel;
+  t.finalize = h->pcg.fin;
+  t.graph = h->graph_off ? 0 : 1;
+  t.check = h->pcg_check;
+  t.available = deep_available(h);
+  t.solve_ms = h->tuned_ms;
+  return t;
+}
+
+void check_tuning(const bddc_ctx* h, const bddc_tuning& t) {
+  if (t.deep_path < 0 || t.deep_path > BDDC_DEEP_LEVELS || !(deep_available(h) >> t.deep_path & 1))
+    fail(BDDC_EINVAL, "deep path not available for this set-up");
+  if (t.finalize != 0 && t.finalize != 1) fail(BDDC_EINVAL, "finalize must be 0 or 1");
+  if (t.graph != 0 && t.graph != 1) fail(BDDC_EINVAL, "graph must be 0 or 1");
+  if (t.check != 4 && t.check != 8 && t.check != 16) fail(BDDC_EINVAL, "check must be 4, 8 or 16");
+}
+
+// install a configuration; a captured chunk of launches no longer matches it
+void apply_tuning(bddc_ctx* h, const bddc_tuning& t) {
+  if (h->graph_exec) {
+    BDDC_HIP(hipStreamSynchronize(h->stream));
+    (void)hipGraphExecDestroy(h->graph_exec);
+    h->graph_exec = nullptr;
+    h->graph_nrhs = 0;
+  }
+  h->deep_sel = t.deep_path;
+  h->pcg.fin = t.finalize;
+  h->graph_off = t.graph == 0;
+  h->pcg_check = t.check;
+}
+
+std::string shape_key(const bddc_ctx* h) {
+  std::string k = std::to_string(h->nx) + "x" + std::to_string(h->ny) + " e" + std::to_string(h->element) + " c" +
+                  std::to_string(h->constraints) + " p" + std::to_string(h->precision);
+  for (const auto& lv : h->levels) k += " " + std::to_string(lv->nsub) + ":" + std::to_string(lv->nc);
+  return k;
+}
+
+}  // namespace
+}  // namespace bddc
+
 bddc_status bddc_setup(const bddc_problem* p, void* hip_stream, bddc_handle* out) {
   if (out) *out = nullptr;
   bddc_ctx* h = nullptr;
@@ -2268,12 +2340,105 @@ bddc_status bddc_setup(const bddc_problem* p, void* hip_stream, bddc_handle* out
     h->info.device_bytes = (int64_t)(dev + h->top.size() + h->coop_arena.size() + h->wide_arena.size());
     h->info.apply_bytes = model_bytes(h, true);
     h->info.matvec_bytes = model_bytes(h, false);
+    // a launch configuration the autotuner chose for this shape before
+    h->shape_key = shape_key(h);
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      const auto it = g_tune_cache.find(h->shape_key);
+      if (it != g_tune_cache.end() && (deep_available(h) >> it->second.deep_path & 1)) {
+        apply_tuning(h, it->second);
+        h->tuned_ms = it->second.solve_ms;
+      }
+    }
     *out = h;
   });
   if (st != BDDC_OK && h) {
     release(h);
     if (out) *out = nullptr;
   }
+  return st;
+}
+
+
+bddc_status bddc_get_tuning(bddc_handle h, bddc_tuning* t) {
+  return guard([&] {
+    if (!h || !t) fail(BDDC_EINVAL, "handle or tuning is NULL");
+    *t = current_tuning(h);
+  });
+}
+
+bddc_status bddc_set_tuning(bddc_handle h, const bddc_tuning* t) {
+  return guard([&] {
+    if (!h || !t) fail(BDDC_EINVAL, "handle or tuning is NULL");
+    check_tuning(h, *t);
+    apply_tuning(h, *t);
+    h->tuned_ms = 0.0;
+  });
+}
+
+bddc_status bddc_autotune(bddc_handle h, const double* f, double* u, int32_t nrhs, int64_t ld, double rtol,
+                          int32_t reps, bddc_tuning* t, void* hip_stream) {
+  bool noconv = false;
+  bddc_status st = guard([&] {
+    if (!h || !f || !u || nrhs < 1 || ld < h->n_free || !(rtol >= 0) || reps < 1)
+      fail(BDDC_EINVAL, "bad autotune arguments");
+    hipStream_t saved = h->stream;
+    h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    struct Restore {
+      bddc_ctx* h;
+      hipStream_t s;
+      ~Restore() { h->stream = s; }
+    } restore{h, saved};
+    const int R = std::min<int>(nrhs, kMaxRhs);
+    std::vector<int32_t> its(R);
+    std::vector<double> rel(R);
+    const int maxit = 1000;
+    auto solve_once = [&] {
+      if (pcg_block(h, f, u, ld, R, rtol, maxit, its.data(), rel.data()) > 0) noconv = true;
+    };
+    auto time_solves = [&] {
+      solve_once();   // first use of a configuration (graph capture) is not timed
+      std::vector<double> ms(reps);
+      for (int r = 0; r < reps; ++r) {
+        const auto t0 = std::chrono::steady_clock::now();
+        solve_once();   // synchronises the stream before it returns
+        ms[r] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+      }
+      std::nth_element(ms.begin(), ms.begin() + reps / 2, ms.end());
+      return ms[reps / 2];
+    };
+    bddc_tuning best = current_tuning(h);
+    double best_ms = time_solves();
+    // one knob at a time; a candidate must win by 2% (timing noise)
+    auto try_knob = [&](int bddc_tuning::*knob, std::initializer_list<int> values) {
+      for (int v : values) {
+        if (v == best.*knob) continue;
+        bddc_tuning c = best;
+        c.*knob = v;
+        if (knob == &bddc_tuning::deep_path && !(deep_available(h) >> v & 1)) continue;
+        apply_tuning(h, c);
+        const double ms = time_solves();
+        if (ms < 0.98 * best_ms) {
+          best = c;
+          best_ms = ms;
+        }
+      }
+      apply_tuning(h, best);
+    };
+    try_knob(&bddc_tuning::deep_path, {BDDC_DEEP_COOP, BDDC_DEEP_WIDE, BDDC_DEEP_FUSED, BDDC_DEEP_LEVELS});
+    try_knob(&bddc_tuning::finalize, {0, 1});
+    try_knob(&bddc_tuning::check, {4, 8, 16});
+    try_knob(&bddc_tuning::graph, {1, 0});
+    h->tuned_ms = best_ms;
+    best.solve_ms = best_ms;
+    best.available = deep_available(h);
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      g_tune_cache[h->shape_key] = best;
+    }
+    if (t) *t = best;
+  });
+  if (st == BDDC_OK && noconv) return BDDC_ENOCONV;
   return st;
 }
 

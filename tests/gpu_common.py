@@ -22,11 +22,14 @@ TIGHT = 1e-10     # PCG tolerance at which the 1e-10 energy-norm bar is applied
 LAM_RTOL = 1e-6
 
 
-def run_pair(prob, rtol=1e-8, maxit=1000, oracle=None):
-    """Solve the same problem with the GPU library and the oracle."""
+def run_pair(prob, rtol=1e-8, maxit=1000, oracle=None, tuning=None):
+    """Solve the same problem with the GPU library (launch configuration
+    `tuning`, if given) and the oracle."""
     import paper_0911_5730_amd as P
     B = oracle or BDDC(prob)
     S = P.Solver(prob)
+    if tuning:
+        S.set_tuning(**tuning)
     f = cuda_vec(prob.f[0])
     u, it, rr = S.solve(f, rtol=rtol, maxit=maxit)
     o = pcg.solve(B, prob.f[0], rtol=rtol, maxit=maxit)

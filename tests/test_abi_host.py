@@ -33,6 +33,15 @@ def test_library_exports_every_declared_symbol():
     assert isinstance(ctypes.CDLL(P.bddc.LIB_PATH).bddc_status_string, object)
 
 
+def test_tuning_entry_points_validate_without_a_device():
+    import ctypes
+    lib = P.load_library()
+    t = P.bddc.BddcTuningC()
+    assert lib.bddc_get_tuning(None, ctypes.byref(t)) == -1
+    assert lib.bddc_set_tuning(None, ctypes.byref(t)) == -1
+    assert lib.bddc_autotune(None, None, None, 1, 1, 1e-8, 1, None, None) == -1
+
+
 def test_status_strings():
     for code in (0, -1, -2, -3, -4, -5, -6, -7, -8):
         assert P.status_string(code) != "unknown status"
