@@ -183,6 +183,40 @@ def blocked_rhs(P, synth, torch, cid: int, stream, nrhs: int = 8, precs=("fp64",
     return out
 
 
+def autotuned(P, synth, torch, cid: int, stream, nrhs: int) -> dict:
+    """bddc_autotune on one workload (the preconditioner set up once): the
+    configuration it chose and right-hand sides per second with the default
+    launch configuration and with the tuned one (a fresh handle of the same
+    shape starts from the remembered choice)."""
+    prob = synth.config(cid, nrhs=nrhs)
+    coeff = torch.tensor(prob.coeff, dtype=torch.float64, device="cuda")
+    F = torch.tensor(prob.f, dtype=torch.float64, device="cuda")
+    U = torch.empty_like(F)
+
+    def rate(S):
+        S.solve(F, u=U, rtol=prob.rtol, stream=stream)
+        torch.cuda.synchronize()
+        reps = 5
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            S.solve(F, u=U, rtol=prob.rtol, stream=stream)
+        torch.cuda.synchronize()
+        return nrhs * reps / (time.perf_counter() - t0)
+
+    S = P.Solver(prob, coeff=coeff, stream=stream)
+    default = S.tuning()
+    r0 = rate(S)
+    t = S.autotune(F, u=U, rtol=prob.rtol, reps=3, stream=stream)
+    S.close()
+    S = P.Solver(prob, coeff=coeff, stream=stream)
+    r1 = rate(S)
+    assert S.tuning()["deep_path"] == t["deep_path"]
+    S.close()
+    log(f"bench: config {cid}, {nrhs} rhs: default {r0:.1f}/s, tuned {r1:.1f}/s ({t})")
+    return {"default": {k: default[k] for k in ("deep_path", "finalize", "graph", "check")}, "default_rhs_per_s": r0,
+            "tuned": {k: t[k] for k in ("deep_path", "finalize", "graph", "check")}, "tuned_rhs_per_s": r1}
+
+
 def concurrent_steps(P, prob, coeff, f, torch, nsteps: int, nstreams: int = 2) -> float:
     """Whole steps (set-up, solve, destroy) of independent problems issued from
     `nstreams` host threads, each with a stream and handles of its own, so one
@@ -256,6 +290,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="skip the request-stream measurement")
     ap.add_argument("--no-blocked", action="store_true", help="skip the blocked right-hand-side measurement")
+    ap.add_argument("--no-autotune", action="store_true", help="skip the autotuner measurement")
     ap.add_argument("--no-precision-forms", action="store_true",
                     help="skip the FP64 / FP32 / BF16 comparison on configs 2 and 3")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -422,6 +457,13 @@ def main():
                     "operator block to every column still iterating) against the same loads one at a time",
             "config2": blocked_rhs(P, synth, torch, 2, stream),
             "config3": blocked_rhs(P, synth, torch, 3, stream),
+        }
+    if not args.no_autotune:
+        out["autotune"] = {
+            "note": "launch configuration chosen by bddc_autotune (deep-level path, partial-sum mode, graph, "
+                    "iterations per chunk) and right-hand sides per second before and after",
+            "config2_1rhs": autotuned(P, synth, torch, 2, stream, 1),
+            "config3_8rhs": autotuned(P, synth, torch, 3, stream, 8),
         }
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle on a bounded sample")

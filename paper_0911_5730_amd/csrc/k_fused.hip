@@ -280,7 +280,8 @@ __device__ inline double block_sum_of(const double* __restrict__ v, int n, doubl
 }
 
 // Live columns of a blocked PCG launch: the indices of the columns not yet
-// finished, in order (lc[0..nl-1]); read once by thread 0 into LDS.
+// finished, in order (lc[0..nl-1]).  Snapshot form: read once by thread 0
+// into LDS (for a launch that changes the flags itself).
 __device__ inline int live_columns(const PcgDev& P, int* lc) {
   __shared__ int nl_s;
   if (threadIdx.x == 0) {
@@ -454,6 +455,9 @@ __device__ inline double sym_row_part(const double* A, int m, int i, int c, int 
   return acc;
 }
 
+// kMulti: several columns; otherwise the one column 0 (compile-time column
+// offsets, uniform pointers), with the same arithmetic per column.
+template <bool kMulti>
 __global__ void __launch_bounds__(kNT) k_pcg_matvec(LevelDev L, PcgDev P, int u) {
   extern __shared__ double sh[];
   __shared__ double red[kMaxRhs * 16];
@@ -469,8 +473,8 @@ __global__ void __launch_bounds__(kNT) k_pcg_matvec(LevelDev L, PcgDev P, int u)
   const int tid = threadIdx.x;
   // thread (mi, mc) forms the partial row sums of row mi over the columns mc,
   // mc + nch, ... for every right-hand side; its entries of S_s (packed
-  // symmetric) are loaded before the scalars and p are formed, so HBM latency
-  // overlaps that work
+  // symmetric) are loaded into registers before the scalars and p are
+  // formed, so HBM latency overlaps that work
   const double* Sg = P.Sp + P.spoff[s];
   const int nch = max(1, kNT / max(1, ng));
   const bool narrow = ng <= kNT;
@@ -479,28 +483,36 @@ __global__ void __launch_bounds__(kNT) k_pcg_matvec(LevelDev L, PcgDev P, int u)
   const bool act = narrow && mc < nch;
   SymRowRegs<16, double> sv;
   if (narrow) sv.load(Sg, ng, mi, mc, nch);
-  const int nl = live_columns(P, lc);
+  // the live columns and their beta: every thread reads the flags and scalars
+  // (uniform loads, before this launch stores anything, so they take the
+  // scalar path and do not wait for the operator loads above) and writes the
+  // same values to LDS, so no barrier is needed before reading them back
+  int nl = 0;
+  for (int c = 0; c < P.nrhs; ++c) {
+    if (P.sc[c].done) continue;
+    if (it >= 2 && P.fin) bet[nl] = P.sc[c].rzs[(it - 1) & 1] / P.sc[c].rzs[(it - 2) & 1];
+    lc[nl++] = c;
+  }
   if (nl == 0) return;
-  const int psz = ng + kNT;                 // part stride per column
-  double* pl = sh;                          // nl x ng
-  double* part = sh + (size_t)nl * ng;      // nl x psz
-  // beta per live column
+  if constexpr (!kMulti) nl = 1;   // (the one column is live here)
+  auto col = [&](int k) -> int {
+    if constexpr (kMulti) return lc[k];
+    else return 0;
+  };
+  const int psz = ng + kNT;                              // part stride per column
+  double* pl = sh;                                       // nl x ng
+  double* part = pl + (size_t)nl * ng;                   // nl x psz
+  // beta per live column from the partials (when they are not summed once)
   if (it >= 2) {
-    if (P.fin) {
-      if (tid < nl) {
-        const PcgScalars& S = P.sc[lc[tid]];
-        bet[tid] = S.rzs[(it - 1) & 1] / S.rzs[(it - 2) & 1];
-      }
-    } else {
+    if (!P.fin) {
       for (int k = 0; k < nl; ++k) {
-        const size_t o = (size_t)lc[k] * P.ld_blk;
+        const size_t o = (size_t)col(k) * P.ld_blk;
         const double rz = block_sum_of(P.rz_part[(it - 1) & 1] + o, P.nblk, red);
         const double rz0 = block_sum_of(P.rz_part[(it - 2) & 1] + o, P.nblk, red);
-        if (tid == 0) bet[k] = rz / rz0;
+        bet[k] = rz / rz0;   // every thread, the same value
       }
     }
-    __syncthreads();
-    if (blockIdx.x == 0 && tid < nl) P.sc[lc[tid]].betas[min(it - 2, kMaxHist - 1)] = bet[tid];
+    if (blockIdx.x == 0 && tid < nl) P.sc[col(tid)].betas[min(it - 2, kMaxHist - 1)] = bet[tid];
   }
   // p_k = z + beta p_{k-1} on the substructure's interface, every live column
   for (int t = tid; t < ng * nl; t += kNT) {
@@ -508,7 +520,7 @@ __global__ void __launch_bounds__(kNT) k_pcg_matvec(LevelDev L, PcgDev P, int u)
     const int f = g0 + a;
     const int gi = L.gam_iid[f];
     const bool own = P.shf4 ? P.shf4[f].x == f : L.sh_flat[L.sh_ptr[gi]] == f;
-    const size_t ci = (size_t)lc[k] * P.ld_if;
+    const size_t ci = (size_t)col(k) * P.ld_if;
     const double pv = (it >= 2) ? P.z[ci + gi] + bet[k] * P.p[(it - 1) & 1][ci + gi] : P.z[ci + gi];
     pl[k * ng + a] = pv;
     if (own) P.p[it & 1][ci + gi] = pv;
@@ -533,15 +545,15 @@ __global__ void __launch_bounds__(kNT) k_pcg_matvec(LevelDev L, PcgDev P, int u)
       if (k < nl && i < ng) {
         double acc = 0.0;
         for (int c = 0; c < nc; ++c) acc += part[k * psz + i + c * ng];
-        P.qloc[(size_t)lc[k] * P.ld_flat + g0 + i] = acc;
+        P.qloc[(size_t)col(k) * P.ld_flat + g0 + i] = acc;
         e = pl[k * ng + i] * acc;
       }
       slot_sums(e, W, red, bet);
-      if (tid < per && k0 + tid < nl) P.pq_part[(size_t)lc[k0 + tid] * P.ld_sub + s] = bet[tid];
+      if (tid < per && k0 + tid < nl) P.pq_part[(size_t)col(k0 + tid) * P.ld_sub + s] = bet[tid];
     }
   } else {
     for (int k = 0; k < nl; ++k) {
-      double* q = P.qloc + (size_t)lc[k] * P.ld_flat;
+      double* q = P.qloc + (size_t)col(k) * P.ld_flat;
       double e = 0.0;
       for (int i = tid; i < ng; i += kNT) {
         double acc = 0.0;
@@ -550,7 +562,7 @@ __global__ void __launch_bounds__(kNT) k_pcg_matvec(LevelDev L, PcgDev P, int u)
         e += pl[k * ng + i] * acc;
       }
       e = wg_sum(e, red);
-      if (tid == 0) P.pq_part[(size_t)lc[k] * P.ld_sub + s] = e;
+      if (tid == 0) P.pq_part[(size_t)col(k) * P.ld_sub + s] = e;
     }
   }
 }
@@ -575,7 +587,7 @@ template <> struct PrecForm<2> { using TS = uint16_t; using PS = float; };
 //   FP64 / FP32 forms: thread (ti, tc) forms row ti of T_rr g_r over the
 //   columns tc, tc + nch, ...  Factored BF16 form: x = D^-1 g_r, v = W x,
 //   v = (I - Q Q^T)^2 v, y = W^T v, T_rr g_r = D^-1 y (two passes over W).
-template <int kPrec>
+template <int kPrec, bool kMulti>
 __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev P, int u, int nrmax, int ngmax,
                                                              int ncsmax) {
   using TS = typename PrecForm<kPrec>::TS;
@@ -641,29 +653,44 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
     const float* Qg = P.Q32 + P.croff[s];
     for (int a = tid; a < nq; a += kNT) Ql[a] = Qg[a];
   }
-  const int nl = live_columns(P, lc);
+  // the live columns and their alpha (as in the product: uniform reads, the
+  // same values written by every thread, no barrier)
+  int nl = 0;
+  for (int c = 0; c < P.nrhs; ++c) {
+    if (P.sc[c].done) continue;
+    if (it > 0 && P.fin) alph[nl] = P.sc[c].rzs[(it - 1) & 1] / P.sc[c].pqs;
+    lc[nl++] = c;
+  }
   if (nl == 0) return;
+  if constexpr (!kMulti) nl = 1;   // (the one column is live here)
+  auto col = [&](int k) -> int {
+    if constexpr (kMulti) return lc[k];
+    else return 0;
+  };
   // every phase below serves all live columns (column k of g / part in LDS)
   if (it == 0) {
-    for (int t = tid; t < ng * nl; t += kNT) {
-      const int k = t / ng, a = t - k * ng;
-      g[k * ngmax + a] = L.delta[g0 + a] * P.r[0][(size_t)lc[k] * P.ld_if + L.gam_iid[g0 + a]];
+    if constexpr (!kMulti) {
+      for (int a = tid; a < ng; a += kNT) g[a] = L.delta[g0 + a] * P.r[0][L.gam_iid[g0 + a]];
+    } else {
+      for (int t = tid; t < ng * nl; t += kNT) {
+        const int k = t / ng, a = t - k * ng;
+        g[k * ngmax + a] = L.delta[g0 + a] * P.r[0][(size_t)col(k) * P.ld_if + L.gam_iid[g0 + a]];
+      }
     }
   } else {
-    // alpha = r.z / p^T S p per live column
-    if (P.fin) {
-      if (tid < nl) {
-        const PcgScalars& S = P.sc[lc[tid]];
-        alph[tid] = S.rzs[(it - 1) & 1] / S.pqs;
-      }
-    } else {
+    // alpha = r.z / p^T S p per live column, from the partials when they are
+    // not summed once (one column: kept in a register)
+    double alpha0 = 0.0;
+    if (!P.fin) {
       for (int k = 0; k < nl; ++k) {
-        const double rz = block_sum_of(P.rz_part[(it - 1) & 1] + (size_t)lc[k] * P.ld_blk, P.nblk, red);
-        const double pq = block_sum_of(P.pq_part + (size_t)lc[k] * P.ld_sub, P.nsub1, red);
-        if (tid == 0) alph[k] = rz / pq;
+        const double rz = block_sum_of(P.rz_part[(it - 1) & 1] + (size_t)col(k) * P.ld_blk, P.nblk, red);
+        const double pq = block_sum_of(P.pq_part + (size_t)col(k) * P.ld_sub, P.nsub1, red);
+        alph[k] = rz / pq;   // every thread, the same value
+        alpha0 = rz / pq;
       }
+    } else if (!kMulti) {
+      alpha0 = P.sc[0].rzs[(it - 1) & 1] / P.sc[0].pqs;
     }
-    __syncthreads();
     const double* rold = P.r[(it - 1) & 1];
     double* rnew = P.r[it & 1];
     const double* p = P.p[it & 1];
@@ -672,8 +699,8 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
     auto update = [&](int k, int a) {
       const int f = g0 + a;
       const int gi = L.gam_iid[f];
-      const size_t ci = (size_t)lc[k] * P.ld_if;
-      const double* ql = P.qloc + (size_t)lc[k] * P.ld_flat;
+      const size_t ci = (size_t)col(k) * P.ld_if;
+      const double* ql = P.qloc + (size_t)col(k) * P.ld_flat;
       double q = 0.0;
       bool own;
       if (P.shf4) {
@@ -688,26 +715,33 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
         for (int m = L.sh_ptr[gi]; m < L.sh_ptr[gi + 1]; ++m) q += ql[L.sh_flat[m]];
         own = L.sh_flat[L.sh_ptr[gi]] == f;
       }
-      const double ri = rold[ci + gi] - alph[k] * q;
+      const double al = kMulti ? alph[k] : alpha0;
+      const double ri = rold[ci + gi] - al * q;
       g[k * ngmax + a] = L.delta[f] * ri;
       double rr = 0.0;
       if (own) {
         rnew[ci + gi] = ri;
-        P.x[ci + gi] += alph[k] * p[ci + gi];
+        P.x[ci + gi] += al * p[ci + gi];
         rr = ri * ri;
       }
       return rr;
     };
     auto publish = [&](int k, double rr) {
-      P.rr_part[(size_t)lc[k] * P.ld_sub + s] = rr;
+      P.rr_part[(size_t)col(k) * P.ld_sub + s] = rr;
       if (s == 0) {
-        PcgScalars& S = P.sc[lc[k]];
+        PcgScalars& S = P.sc[col(k)];
         S.iters = it;
-        S.alphas[min(it - 1, kMaxHist - 1)] = alph[k];
+        S.alphas[min(it - 1, kMaxHist - 1)] = kMulti ? alph[k] : alpha0;
       }
     };
     const int W = slot_width(ng);
-    if (W <= kNT) {
+    if (!kMulti) {
+      // one column: entry a on thread a, as in its slot
+      double rr = 0.0;
+      for (int a = tid; a < ng; a += kNT) rr += update(0, a);
+      rr = wg_sum(rr, red);
+      if (tid == 0) publish(0, rr);
+    } else if (W <= kNT) {
       const int per = kNT / W;
       double* out = red + 16;
       for (int k0 = 0; k0 < nl; k0 += per) {
@@ -744,7 +778,7 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
       }
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
-      if (lane == 0) P.b[(size_t)lc[k] * P.ld_cflat + L.coff[s] + kd] = acc;
+      if (lane == 0) P.b[(size_t)col(k) * P.ld_cflat + L.coff[s] + kd] = acc;
     }
   }
   if constexpr (kPrec == 2) {
@@ -753,7 +787,7 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
     for (int k = 0; k < nl; ++k) {
       const double* gk = g + k * ngmax;
       double* pk = part;
-      double* da = P.da + (size_t)lc[k] * P.ld_flat;
+      double* da = P.da + (size_t)col(k) * P.ld_flat;
       for (ColWalk w_(tid, kNT, n_r); w_.j < nch; w_.next()) {
         const int i = w_.i, c = w_.j;
         [[maybe_unused]] const int idx = i + c * n_r;
@@ -811,16 +845,28 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
     }
     __syncthreads();
     const int nc = narrow ? nch : 1;
-    for (int t = tid; t < n_r * nl; t += kNT) {
-      const int k = t / n_r, i = t - k * n_r;
-      double acc = 0.0;
-      for (int c = 0; c < nc; ++c) acc += part[k * psz + i + c * n_r];
-      P.da[(size_t)lc[k] * P.ld_flat + g0 + i] = L.delta[g0 + i] * acc;
+    if constexpr (!kMulti) {
+      for (int i = tid; i < n_r; i += kNT) {
+        double acc = 0.0;
+        for (int c = 0; c < nc; ++c) acc += part[i + c * n_r];
+        P.da[g0 + i] = L.delta[g0 + i] * acc;
+      }
+    } else {
+      for (int t = tid; t < n_r * nl; t += kNT) {
+        const int k = t / n_r, i = t - k * n_r;
+        double acc = 0.0;
+        for (int c = 0; c < nc; ++c) acc += part[k * psz + i + c * n_r];
+        P.da[(size_t)col(k) * P.ld_flat + g0 + i] = L.delta[g0 + i] * acc;
+      }
     }
   }
-  for (int t = tid; t < (ng - n_r) * nl; t += kNT) {
-    const int k = t / (ng - n_r), a = n_r + t - k * (ng - n_r);
-    P.da[(size_t)lc[k] * P.ld_flat + g0 + a] = 0.0;
+  if constexpr (!kMulti) {
+    for (int a = n_r + tid; a < ng; a += kNT) P.da[g0 + a] = 0.0;
+  } else {
+    for (int t = tid; t < (ng - n_r) * nl; t += kNT) {
+      const int k = t / (ng - n_r), a = n_r + t - k * (ng - n_r);
+      P.da[(size_t)col(k) * P.ld_flat + g0 + a] = 0.0;
+    }
   }
 }
 
@@ -942,6 +988,7 @@ __global__ void __launch_bounds__(kNT) k_pack_pcg(LevelDev L, PcgDev P) {
 // records it), then per interface dof z = sum over sharers of delta T_rr g plus
 // the dof's row of the delta-weighted coarse basis times u_c  (ML-uBi-1), and
 // the per-block partial of r_k . z.
+template <bool kMulti>
 __global__ void __launch_bounds__(kNT) k_pcg_prolong_post(LevelDev L, PcgDev P, int u) {
   __shared__ double red[kMaxRhs * 16];
   __shared__ int lc[kMaxRhs];
@@ -951,44 +998,71 @@ __global__ void __launch_bounds__(kNT) k_pcg_prolong_post(LevelDev L, PcgDev P, 
   const int it = u < 0 ? 0 : P.sc[0].it_base + u;
   const bool check = it > 0;
   const int parity = it & 1;
-  // the columns' states on entry (block 0 updates them below)
-  const int nl = live_columns(P, lc);
-  // convergence test on r.r per live column; gc = the columns still going
-  __shared__ double rrv[kMaxRhs];
-  if (check) {
-    if (P.fin) {
-      if (threadIdx.x < nl) rrv[threadIdx.x] = P.sc[lc[threadIdx.x]].rrs;
-    } else {
-      for (int k = 0; k < nl; ++k) {
-        const double rr = block_sum_of(P.rr_part + (size_t)lc[k] * P.ld_sub, P.nsub1, red);
-        if (threadIdx.x == 0) rrv[k] = rr;
+  int ngo;
+  if constexpr (kMulti) {
+    // the columns' states on entry (block 0 updates them below)
+    const int nl = live_columns(P, lc);
+    // convergence test on r.r per live column; gc = the columns still going
+    __shared__ double rrv[kMaxRhs];
+    if (check) {
+      if (P.fin) {
+        if (threadIdx.x < nl) rrv[threadIdx.x] = P.sc[lc[threadIdx.x]].rrs;
+      } else {
+        for (int k = 0; k < nl; ++k) {
+          const double rr = block_sum_of(P.rr_part + (size_t)lc[k] * P.ld_sub, P.nsub1, red);
+          if (threadIdx.x == 0) rrv[k] = rr;
+        }
       }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        int m = 0;
+        for (int k = 0; k < nl; ++k) {
+          PcgScalars* S = P.sc + lc[k];
+          const bool conv = rrv[k] <= S->thr2;
+          const bool maxed = S->iters >= S->maxit;
+          if (blockIdx.x == 0) {
+            S->rr = rrv[k];
+            if (conv || maxed) S->done = conv ? 1 : 2;
+          }
+          if (!(conv || maxed)) gc[m++] = lc[k];
+        }
+        ngo_s = m;
+      }
+    } else if (threadIdx.x == 0) {
+      for (int k = 0; k < nl; ++k) gc[k] = lc[k];
+      ngo_s = nl;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-      int m = 0;
-      for (int k = 0; k < nl; ++k) {
-        PcgScalars* S = P.sc + lc[k];
-        const bool conv = rrv[k] <= S->thr2;
-        const bool maxed = S->iters >= S->maxit;
-        if (blockIdx.x == 0) {
-          S->rr = rrv[k];
-          if (conv || maxed) S->done = conv ? 1 : 2;
-        }
-        if (!(conv || maxed)) gc[m++] = lc[k];
-      }
-      ngo_s = m;
+    ngo = ngo_s;
+    if (ngo == 0) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) P.sc[0].all_done = 1;
+      return;
     }
-  } else if (threadIdx.x == 0) {
-    for (int k = 0; k < nl; ++k) gc[k] = lc[k];
-    ngo_s = nl;
+  } else {
+    // one column: every thread takes the same decision from the same values
+    // (a wave that sees the flag raised by block 0 in this launch returns, as
+    // block 0 itself does)
+    PcgScalars* S = P.sc;
+    if (S->done) return;
+    if (check) {
+      const double rr = P.fin ? S->rrs : block_sum_of(P.rr_part, P.nsub1, red);
+      const bool conv = rr <= S->thr2;
+      const bool maxed = S->iters >= S->maxit;
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        S->rr = rr;
+        if (conv || maxed) {
+          S->done = conv ? 1 : 2;
+          S->all_done = 1;
+        }
+      }
+      if (conv || maxed) return;
+    }
+    ngo = 1;
   }
-  __syncthreads();
-  const int ngo = ngo_s;
-  if (ngo == 0) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) P.sc[0].all_done = 1;
-    return;
-  }
+  auto gcol = [&](int k) -> int {
+    if constexpr (kMulti) return gc[k];
+    else return 0;
+  };
   // z = sum over the sharers of delta T_rr g plus the averaged coarse basis
   // row times u_c: eight lanes per interface dof, fixed-order reduction over
   // the eight; the partial r.z of each going column is reduced as wg_sum does
@@ -997,9 +1071,9 @@ __global__ void __launch_bounds__(kNT) k_pcg_prolong_post(LevelDev L, PcgDev P, 
   const int sub = threadIdx.x & 7;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = kNT / 64;
   for (int k = 0; k < ngo; ++k) {
-    const size_t ci = (size_t)gc[k] * P.ld_if;
-    const double* da = P.da + (size_t)gc[k] * P.ld_flat;
-    const double* uc = P.uc + (size_t)gc[k] * P.ld_coarse;
+    const size_t ci = (size_t)gcol(k) * P.ld_if;
+    const double* da = P.da + (size_t)gcol(k) * P.ld_flat;
+    const double* uc = P.uc + (size_t)gcol(k) * P.ld_coarse;
     double acc = 0.0;
     if (gi < P.nif) {
       const int k0 = L.sh_ptr[gi], k1 = L.sh_ptr[gi + 1];
@@ -1022,7 +1096,7 @@ __global__ void __launch_bounds__(kNT) k_pcg_prolong_post(LevelDev L, PcgDev P, 
   if ((int)threadIdx.x < ngo) {
     double r = 0.0;
     for (int w = 0; w < nw; ++w) r += red[threadIdx.x * 16 + w];
-    P.rz_part[parity][(size_t)gc[threadIdx.x] * P.ld_blk + blockIdx.x] = r;
+    P.rz_part[parity][(size_t)gcol(threadIdx.x) * P.ld_blk + blockIdx.x] = r;
   }
 }
 
@@ -1054,7 +1128,10 @@ __global__ void __launch_bounds__(kNT) k_build_phi(LevelDev L, int nif, const in
 
 void launch_pcg_matvec(hipStream_t st, const LevelDev& L, int ngmax, const PcgDev& P, int u) {
   const size_t lds = sizeof(double) * (size_t)P.nrhs * ((size_t)ngmax + kNT + ngmax);
-  launch_kernel(k_pcg_matvec, dim3(L.nsub), dim3(kNT), lds, st, L, P, u);
+  if (P.nrhs > 1)
+    launch_kernel(k_pcg_matvec<true>, dim3(L.nsub), dim3(kNT), lds, st, L, P, u);
+  else
+    launch_kernel(k_pcg_matvec<false>, dim3(L.nsub), dim3(kNT), lds, st, L, P, u);
 }
 void launch_pcg_sum(hipStream_t st, const PcgDev& P, int which, int u) {
   launch_kernel(k_pcg_sum, dim3(P.nrhs), dim3(kNT), 0, st, P, which, u);
@@ -1069,12 +1146,14 @@ void launch_pcg_update_restrict(hipStream_t st, const LevelDev& L, int ngmax, in
   if (P.prec == 2)
     lds += sizeof(double) * (nrmax + (size_t)nrmax * (nrmax + 1) / 2) +
            sizeof(float) * ((size_t)nrmax * ncsmax + nrmax);
+  auto go = [&](auto kern) { launch_kernel(kern, dim3(L.nsub), dim3(kNT), lds, st, L, P, u, nrmax, ngmax, ncsmax); };
+  const bool multi = P.nrhs > 1;
   if (P.prec == 0)
-    launch_kernel(k_pcg_update_restrict<0>, dim3(L.nsub), dim3(kNT), lds, st, L, P, u, nrmax, ngmax, ncsmax);
+    multi ? go(k_pcg_update_restrict<0, true>) : go(k_pcg_update_restrict<0, false>);
   else if (P.prec == 1)
-    launch_kernel(k_pcg_update_restrict<1>, dim3(L.nsub), dim3(kNT), lds, st, L, P, u, nrmax, ngmax, ncsmax);
+    multi ? go(k_pcg_update_restrict<1, true>) : go(k_pcg_update_restrict<1, false>);
   else
-    launch_kernel(k_pcg_update_restrict<2>, dim3(L.nsub), dim3(kNT), lds, st, L, P, u, nrmax, ngmax, ncsmax);
+    multi ? go(k_pcg_update_restrict<2, true>) : go(k_pcg_update_restrict<2, false>);
 }
 void launch_pack_pcg(hipStream_t st, const LevelDev& L, const PcgDev& P) {
   if (L.nsub == 0) return;
@@ -1087,7 +1166,10 @@ void launch_round_factors(hipStream_t st, const LevelDev& L, const PcgDev& P, in
   launch_kernel(k_round_factors, dim3(L.nsub), dim3(kNT), lds, st, L, P, nrmax, ncrmax, Cr, status);
 }
 void launch_pcg_prolong_post(hipStream_t st, const LevelDev& L, const PcgDev& P, int u) {
-  launch_kernel(k_pcg_prolong_post, dim3(P.nblk), dim3(kNT), 0, st, L, P, u);
+  if (P.nrhs > 1)
+    launch_kernel(k_pcg_prolong_post<true>, dim3(P.nblk), dim3(kNT), 0, st, L, P, u);
+  else
+    launch_kernel(k_pcg_prolong_post<false>, dim3(P.nblk), dim3(kNT), 0, st, L, P, u);
 }
 void launch_build_phi(hipStream_t st, const LevelDev& L, int nif, const int32_t* sub_of_flat, const int32_t* phi_ptr,
                       int32_t* phi_ids, double* phi_w, const float* psi32) {
