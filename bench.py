@@ -249,20 +249,25 @@ def concurrent_steps(P, prob, coeff, f, torch, nsteps: int, nstreams: int = 2) -
     return nsteps / (t1 - t0)
 
 
-def serving(synth, count: int = 40, rate: float = 200.0, slots: int = 2, precision: str = "fp32") -> dict:
-    """A seeded Poisson stream of independent requests (grid side 128 or 256,
-    H/h 8 or 16, 2-3 levels, k = 10^U(0,m), m in 0..6, 1-4 right-hand sides,
-    adaptive tau = 10) submitted at their arrival times to the serving loop."""
+def serving(synth, count: int = 40, rate: float = 200.0, slots: int = 2, precision: str = "fp32",
+            problems=None, resident: bool = False) -> dict:
+    """A seeded Poisson stream of requests (grid side 128 or 256, H/h 8 or 16,
+    2-3 levels, k = 10^U(0,m), m in 0..6, 1-4 right-hand sides, adaptive
+    tau = 10) submitted at their arrival times to the serving loop; with
+    `problems`, the requests share that many problems (loads of their own),
+    and with `resident` the server keeps set-up problems and merges the
+    pending loads of one problem into one blocked solve."""
     from paper_0911_5730_amd.serve import Request, Server
-    stream = synth.request_stream(count, rate=rate)
-    srv = Server(slots=slots)
+    stream = synth.request_stream(count, rate=rate, problems=problems)
+    srv = Server(slots=slots, resident=resident)
     try:
         t0 = srv.now()
         for t, prob in stream:
             wait = t - (srv.now() - t0)
             if wait > 0:
                 time.sleep(wait)
-            srv.submit(Request(prob=prob, rhs=prob.f, precision=precision, arrival=srv.now()))
+            key = prob.meta.get("problem") if problems else None
+            srv.submit(Request(prob=prob, rhs=prob.f, precision=precision, arrival=srv.now(), key=key))
         srv.drain()
     finally:
         srv.close()
@@ -270,7 +275,7 @@ def serving(synth, count: int = 40, rate: float = 200.0, slots: int = 2, precisi
     if bad:
         raise bad[0].error
     st = srv.stats()
-    st.update({"rate_per_s": rate, "precision": precision,
+    st.update({"rate_per_s": rate, "precision": precision, "problems": problems,
                "rhs": int(sum(p.f.shape[0] for _, p in stream))})
     return st
 
@@ -441,9 +446,19 @@ def main():
     }
     if not args.no_serving:
         out["serving"] = {"two_slots": serving(synth, slots=2), "one_slot": serving(synth, slots=1),
+                          "shared_problems": serving(synth, count=120, rate=2000.0, slots=2, problems=4),
+                          "shared_problems_resident": serving(synth, count=120, rate=2000.0, slots=2, problems=4,
+                                                              resident=True),
                           "note": "requests/s over the stream and arrival-to-completion latency; each request is "
-                                  "set up, solved to 1e-8 and released on a slot with its own stream"}
-        log(f"bench: serving {out['serving']['two_slots']['solves_per_s']:.1f} req/s (two slots)")
+                                  "set up, solved to 1e-8 and released on a slot with its own stream; "
+                                  "shared_problems: 120 requests at 2000/s over 4 problems (loads of their own), "
+                                  "_resident: set-up problems kept and pending loads of one problem merged into "
+                                  "one blocked solve"}
+        sv = out["serving"]
+        log(f"bench: serving {sv['two_slots']['solves_per_s']:.1f} req/s (two slots); shared problems "
+            f"{sv['shared_problems']['solves_per_s']:.1f} req/s, resident {sv['shared_problems_resident']['solves_per_s']:.1f}"
+            f" req/s (p99 {sv['shared_problems']['latency_ms']['p99']:.1f} -> "
+            f"{sv['shared_problems_resident']['latency_ms']['p99']:.1f} ms)")
     if not args.no_precision_forms:
         out["precision_forms"] = {
             "note": "solves/s with the preconditioner set up once; FP32 / BF16 = reduced storage of the level-1 "

@@ -221,14 +221,35 @@ def config(cid: int, nrhs: int = 1) -> Problem:
 
 
 def request_stream(count: int, *, rate: float = 200.0, sides=(128, 256), hh=(8, 16), seed: int = 5000,
-                   max_rhs: int = 4):
+                   max_rhs: int = 4, problems: Optional[int] = None):
     """A seeded stream of independent solve requests shaped like the serving
     workload: Poisson arrivals (mean `rate` per second), grid side and H/h
     drawn uniformly from `sides` and `hh`, 3 levels (level-2 substructures of
     4 x 4 level-1 substructures) from 16 x 16 substructures on, else 2, k = 10^U(0, m) with m uniform in 0..6,
     adaptive tau = 10, 1 to
-    `max_rhs` right-hand sides U[-1, 1].  Returns [(arrival_seconds, Problem)]."""
+    `max_rhs` right-hand sides U[-1, 1].  Returns [(arrival_seconds, Problem)].
+
+    With `problems`, that many distinct problems are drawn first and every
+    request takes one of them uniformly with loads of its own (seeded):
+    requests of one problem share its mesh, coefficient field and partition
+    (`meta["problem"]` is the problem's index), as repeated solves against
+    one discretization do."""
     rng = np.random.Generator(np.random.PCG64(seed))
+    if problems:
+        base = request_stream(problems, rate=rate, sides=sides, hh=hh, seed=seed + 1, max_rhs=max_rhs)
+        t = 0.0
+        out = []
+        for r in range(count):
+            t += rng.exponential(1.0 / rate)
+            j = int(rng.integers(0, problems))
+            src = base[j][1]
+            nrhs = int(rng.integers(1, max_rhs + 1))
+            f = rng.uniform(-1.0, 1.0, size=(nrhs, src.n_free))
+            prob = Problem(nx=src.nx, ny=src.ny, coeff=src.coeff, part=src.part, nsub=src.nsub, levels=src.levels,
+                           agglom=src.agglom, constraints=src.constraints, tau=src.tau, f=f, element=src.element,
+                           rtol=src.rtol, name=f"request{r}", meta=dict(src.meta, problem=j))
+            out.append((t, prob))
+        return out
     t = 0.0
     out = []
     for r in range(count):

@@ -191,3 +191,38 @@ def test_serving_loop_results_alone_equal_in_the_mix():
             assert np.array_equal(r.solution, u)
         st = srv.stats()
         assert st["requests"] == len(stream) and st["latency_ms"]["p99"] >= st["latency_ms"]["p50"]
+
+
+def test_serving_resident_problems_merge_loads_and_match_alone():
+    """Requests against a few shared problems: a resident problem is reused
+    without a new set-up and the pending loads of one problem are merged into
+    one blocked solve; every request's solution equals (bitwise) the request
+    solved alone on a fresh set-up."""
+    import synth
+    from paper_0911_5730_amd.serve import Request, Server
+
+    import paper_0911_5730_amd as P
+
+    stream = synth.request_stream(12, seed=78, problems=3, sides=(64, 128), hh=(8, 16))
+    alone = []
+    for _, prob in stream:
+        S = P.Solver(prob, precision="fp32")
+        try:
+            u, it, _ = S.solve(cuda_vec(prob.f).reshape(prob.f.shape))
+            alone.append((u.cpu().numpy(), it))
+        finally:
+            S.close()
+    srv = Server(slots=2, resident=True)
+    try:
+        # all submitted at once, so loads of one problem can merge
+        reqs = [srv.submit(Request(prob=p, rhs=p.f, precision="fp32", key=p.meta["problem"])) for _, p in stream]
+        srv.drain()
+        st = srv.stats()
+    finally:
+        srv.close()
+    for r, (u, it) in zip(reqs, alone):
+        assert r.error is None, r.error
+        assert r.iterations == it
+        assert np.array_equal(r.solution, u)
+    print(f"serving resident: {st}", flush=True)
+    assert st["reused"] > 0 and st["mean_batch"] > 1.0
