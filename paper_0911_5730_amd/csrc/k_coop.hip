@@ -60,12 +60,14 @@ __device__ void grid_barrier(unsigned* bar, unsigned nblocks, int* status) {
 // then store(c, i, value) on lane 0 of the eight: row t of the combined loop
 // is row i = t mod rows of column c = t / rows.  With xi, x_c is read at
 // xi[j] (a gathered product).
-template <class J0, class J1, class Store>
+// (kMulti false: the one column 0, no index division)
+template <bool kMulti, class J0, class J1, class Store>
 __device__ inline void mv8c(int rows, int R, const double* A, int rs, int cs, const double* x, int xs, J0 j0f,
                             J1 j1f, Store store, const int32_t* xi = nullptr) {
   const int sub = threadIdx.x & 7;
-  for (int t = threadIdx.x >> 3; t < rows * R; t += kCoopNT / 8) {
-    const int c = t / rows, i = t - c * rows;
+  const int tot = kMulti ? rows * R : rows;
+  for (int t = threadIdx.x >> 3; t < tot; t += kCoopNT / 8) {
+    const int c = kMulti ? t / rows : 0, i = kMulti ? t - c * rows : t;
     const double* xc = x + (size_t)c * xs;
     double acc = 0.0;
     const int j1 = j1f(i);
@@ -91,6 +93,7 @@ __device__ inline void copy_batched(T* dst, const T* __restrict__ src, int n) {
 
 }  // namespace
 
+template <bool kMulti>
 __global__ void __launch_bounds__(kCoopNT) k_deep_coop(CoopDev C) {
   if (C.stop && *C.stop) return;
   extern __shared__ double sh[];
@@ -99,7 +102,7 @@ __global__ void __launch_bounds__(kCoopNT) k_deep_coop(CoopDev C) {
   const int nI = me[0], ng = me[1], nr = me[2], ncs = me[3], nsh = me[4], ng1 = me[5], goff = me[6], coff = me[7];
   const int n = nI + ng;
   const int ncL = C.ncL;
-  const int R = C.nrhs;                  // columns: vectors below hold R columns each
+  const int R = kMulti ? C.nrhs : 1;     // columns: vectors below hold R columns each
   const int mI = C.nImax, mG = C.ngmax;  // their column strides
   (void)me[8];
   // LDS: operator block | vectors | coarsest inverse factor | ints
@@ -184,7 +187,7 @@ __global__ void __launch_bounds__(kCoopNT) k_deep_coop(CoopDev C) {
   // barriers of one.
   // r_2 on the local dofs: sums of the level-1 coarse contributions
   for (int t = tid; t < n * R; t += kCoopNT) {
-    const int c = t / n, p = t - c * n;
+    const int c = kMulti ? t / n : 0, p = kMulti ? t - c * n : t;
     const double* b1 = C.b1 + (size_t)c * C.ld_b1;
     double acc = 0.0;
     for (int q = gp[p]; q < gp[p + 1]; ++q) acc += b1[gf[q]];
@@ -194,7 +197,7 @@ __global__ void __launch_bounds__(kCoopNT) k_deep_coop(CoopDev C) {
   __syncthreads();
   // interior correction (ML-uIi, ML-rBi): y = K_II^-1 r_I and t = K_GI K_II^-1 r_I
   // in one pass: row rho of [K_II^-1 ; M] is column rho of [K_II^-1  M^T]
-  mv8c(nI + ng, R, Li, nI, 1, rI, mI, [](int) { return 0; }, [&](int) { return nI; },
+  mv8c<kMulti>(nI + ng, R, Li, nI, 1, rI, mI, [](int) { return 0; }, [&](int) { return nI; },
        [&](int c, int i, double v) {
          if (i < nI) y[c * mI + i] = v;
          else C.t[(size_t)c * C.ld_t + goff + i - nI] = v;
@@ -202,47 +205,47 @@ __global__ void __launch_bounds__(kCoopNT) k_deep_coop(CoopDev C) {
   grid_barrier(C.bar, gridDim.x, C.status);
   // g = delta (r_G - sum t);  a = T_rr g_r (ML-wDi);  b = Psi^T g (ML-coarse)
   for (int t = tid; t < ng * R; t += kCoopNT) {
-    const int c = t / ng, a = t - c * ng;
+    const int c = kMulti ? t / ng : 0, a = kMulti ? t - c * ng : t;
     const double* tc = C.t + (size_t)c * C.ld_t;
     double v = rG[c * mG + a];
     for (int q = shp[a]; q < shp[a + 1]; ++q) v -= tc[shf[q]];
     g[c * mG + a] = dl[a] * v;
   }
   __syncthreads();
-  mv8c(nr, R, Tm, 1, nr, g, mG, [](int) { return 0; }, [&](int) { return nr; },
+  mv8c<kMulti>(nr, R, Tm, 1, nr, g, mG, [](int) { return 0; }, [&](int) { return nr; },
        [&](int c, int a, double v) { C.da[(size_t)c * C.ld_t + goff + a] = dl[a] * v; });
   for (int t = tid; t < (ng - nr) * R; t += kCoopNT) {
-    const int c = t / (ng - nr), a = nr + t - c * (ng - nr);
+    const int c = kMulti ? t / (ng - nr) : 0, a = nr + (kMulti ? t - c * (ng - nr) : t);
     C.da[(size_t)c * C.ld_t + goff + a] = 0.0;
   }
-  mv8c(ncs, R, Ps, ng, 1, g, mG, [](int) { return 0; }, [&](int) { return ng; },
+  mv8c<kMulti>(ncs, R, Ps, ng, 1, g, mG, [](int) { return 0; }, [&](int) { return ng; },
        [&](int c, int k, double v) { C.b[(size_t)c * C.ld_b + coff + k] = v; });
   grid_barrier(C.bar, gridDim.x, C.status);
   // coarsest right-hand side r_c = sum of the coarse contributions, and the
   // sharers' sum of delta T_rr g on the interface, in one round of loads
   for (int t = tid; t < ncL * R; t += kCoopNT) {
-    const int c = t / ncL, k = t - c * ncL;
+    const int c = kMulti ? t / ncL : 0, k = kMulti ? t - c * ncL : t;
     const double* bc = C.b + (size_t)c * C.ld_b;
     double acc = 0.0;
     for (int q = cg[k]; q < cg[k + 1]; ++q) acc += bc[cg[ncL + 1 + q]];
     rc[c * ncL + k] = acc;
   }
   for (int t = tid; t < ng * R; t += kCoopNT) {
-    const int c = t / ng, a = t - c * ng;
+    const int c = kMulti ? t / ng : 0, a = kMulti ? t - c * ng : t;
     const double* dc = C.da + (size_t)c * C.ld_t;
     double acc = 0.0;
     for (int q = shp[a]; q < shp[a + 1]; ++q) acc += dc[shf[q]];
     av[c * mG + a] = acc;
   }
   __syncthreads();
-  mv8c(ncL, R, LL, 1, ncL, rc, ncL, [](int) { return 0; }, [](int i) { return i + 1; },
+  mv8c<kMulti>(ncL, R, LL, 1, ncL, rc, ncL, [](int) { return 0; }, [](int i) { return i + 1; },
        [&](int c, int i, double v) { wc[c * ncL + i] = v; });
   __syncthreads();
-  mv8c(ncL, R, LL, ncL, 1, wc, ncL, [](int i) { return i; }, [&](int) { return ncL; },
+  mv8c<kMulti>(ncL, R, LL, ncL, 1, wc, ncL, [](int i) { return i; }, [&](int) { return ncL; },
        [&](int c, int i, double v) { uc[c * ncL + i] = v; });
   __syncthreads();
   // u_B = sum over sharers of delta (T_rr g + Psi u_c)   (ML-uBi-1), owner writes
-  mv8c(ng, R, phw, 0, 1, uc, ncL, [&](int a) { return phi_ptr[a]; }, [&](int a) { return phi_ptr[a + 1]; },
+  mv8c<kMulti>(ng, R, phw, 0, 1, uc, ncL, [&](int a) { return phi_ptr[a]; }, [&](int a) { return phi_ptr[a + 1]; },
        [&](int c, int a, double v) {
          const double u = av[c * mG + a] + v;
          uB[c * mG + a] = u;
@@ -251,7 +254,7 @@ __global__ void __launch_bounds__(kCoopNT) k_deep_coop(CoopDev C) {
        phi_ids);
   __syncthreads();
   // u_I = K_II^-1 (r_I - K_IG u_B) = y - M^T u_B   (ML-vIi, ML-ui)
-  mv8c(nI, R, G, 1, nI, uB, mG, [](int) { return 0; }, [&](int) { return ng; },
+  mv8c<kMulti>(nI, R, G, 1, nI, uB, mG, [](int) { return 0; }, [&](int) { return ng; },
        [&](int c, int i, double v) { C.u2[(size_t)c * C.ld_u2 + int_gid[i]] = y[c * mI + i] - v; });
 }
 
@@ -267,7 +270,7 @@ int coop_max_blocks(size_t lds) {
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_deep_coop, kCoopNT, lds) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_deep_coop<true>, kCoopNT, lds) != hipSuccess) return 0;
   return per * ncu;
 }
 
@@ -280,7 +283,10 @@ int coop_max_blocks(size_t lds) {
 // kernel and the status flag reports it.
 void launch_deep_coop(hipStream_t st, const CoopDev& C, bool cooperative) {
   if (!cooperative) {
-    launch_kernel(k_deep_coop, dim3(C.nsub), dim3(kCoopNT), coop_lds(C), st, C);
+    if (C.nrhs > 1)
+      launch_kernel(k_deep_coop<true>, dim3(C.nsub), dim3(kCoopNT), coop_lds(C), st, C);
+    else
+      launch_kernel(k_deep_coop<false>, dim3(C.nsub), dim3(kCoopNT), coop_lds(C), st, C);
     return;
   }
   // a cooperative launch takes no dispatch events: record them around it instead
@@ -289,7 +295,9 @@ void launch_deep_coop(hipStream_t st, const CoopDev& C, bool cooperative) {
   if (ev.start) (void)hipEventRecord(ev.start, st);
   CoopDev arg = C;
   void* args[] = {&arg};
-  const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_deep_coop), dim3(C.nsub),
+  const void* kern = C.nrhs > 1 ? reinterpret_cast<const void*>(k_deep_coop<true>)
+                                 : reinterpret_cast<const void*>(k_deep_coop<false>);
+  const hipError_t e = hipLaunchCooperativeKernel(kern, dim3(C.nsub),
                                                   dim3(kCoopNT), args, coop_lds(C), st);
   if (e != hipSuccess) fail(BDDC_EDEVICE, std::string("cooperative launch: ") + hipGetErrorString(e));
   if (ev.stop) (void)hipEventRecord(ev.stop, st);
