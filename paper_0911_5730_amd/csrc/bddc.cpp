@@ -753,7 +753,7 @@ class Builder {
       }
       eptr[prev.nsub] = (int32_t)edof.size();
       const int nsub_next = *std::max_element(esub.begin(), esub.end()) + 1;
-      nl->topo = classify(prev.nc, nsub_next, eptr, edof, esub, etouch);
+      nl->topo = classify(prev.nc, nsub_next, eptr, edof, esub, etouch, true);
       layout_level(*nl);
       check_limits(*nl);
       clk.lap("classify+layout");

@@ -542,7 +542,7 @@ __global__ void __launch_bounds__(kNT) k_pcg_matvec(LevelDev L, PcgDev P, int u)
     for (int k0 = 0; k0 < nl; k0 += per) {
       const int k = k0 + tid / W, i = tid % W;
       double e = 0.0;
-      if (k < nl && i < ng) {
+      if (tid < per * W && k < nl && i < ng) {   // (threads past the last slot idle)
         double acc = 0.0;
         for (int c = 0; c < nc; ++c) acc += part[k * psz + i + c * ng];
         P.qloc[(size_t)col(k) * P.ld_flat + g0 + i] = acc;
@@ -746,7 +746,7 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
       double* out = red + 16;
       for (int k0 = 0; k0 < nl; k0 += per) {
         const int k = k0 + tid / W, a = tid % W;
-        const double rr = (k < nl && a < ng) ? update(k, a) : 0.0;
+        const double rr = (tid < per * W && k < nl && a < ng) ? update(k, a) : 0.0;   // (past the last slot: idle)
         slot_sums(rr, W, red, out);
         if (tid < per && k0 + tid < nl) publish(k0 + tid, out[tid]);
       }

@@ -20,7 +20,7 @@ inline uint64_t pair_key(int s, int t) {
 
 Topology classify(int n, int nsub, const std::vector<int32_t>& elem_ptr,
                   const std::vector<int32_t>& elem_dof, const std::vector<int32_t>& elem_sub,
-                  const std::vector<uint8_t>& elem_touch) {
+                  const std::vector<uint8_t>& elem_touch, bool require_connected) {
   const bool timing = getenv("BDDC_HOST_TIMING") != nullptr;
   auto t0 = std::chrono::steady_clock::now();
   auto lap = [&](const char* what) {
@@ -72,6 +72,42 @@ Topology classify(int n, int nsub, const std::vector<int32_t>& elem_ptr,
     raw_ptr[s + 1] = static_cast<int32_t>(raw.size());
   }
   lap("sharers");
+  if (require_connected) {
+    // every substructure connected through its dofs (elements without dofs
+    // left out): a disconnected one would have a null space per piece, which
+    // the corners of the rules below do not remove
+    std::vector<int32_t> up(ne), first(n, -1);
+    for (int e = 0; e < ne; ++e) up[e] = e;
+    auto root = [&](int x) {
+      while (up[x] != x) x = up[x] = up[up[x]];
+      return x;
+    };
+    for (int s = 0; s < nsub; ++s) {
+      for (int k = sptr[s]; k < sptr[s + 1]; ++k) {
+        const int e = order[k];
+        for (int q = elem_ptr[e]; q < elem_ptr[e + 1]; ++q) {
+          const int d = elem_dof[q];
+          if (first[d] < 0 || elem_sub[first[d]] != s) {
+            first[d] = e;
+          } else {
+            const int a = root(e), b = root(first[d]);
+            if (a != b) up[a] = b;
+          }
+        }
+      }
+      int pieces = 0, r0 = -1;
+      for (int k = sptr[s]; k < sptr[s + 1]; ++k) {
+        const int e = order[k];
+        if (elem_ptr[e + 1] == elem_ptr[e]) continue;
+        const int r = root(e);
+        if (r0 < 0) r0 = r, pieces = 1;
+        else if (r != r0) pieces = 2;
+      }
+      if (pieces > 1)
+        fail(BDDC_EPARTITION, "substructure " + std::to_string(s) + " of a coarse level is not connected through its dofs");
+    }
+    lap("connected");
+  }
   classify_rules(T, raw_ptr, raw);
   lap("rules");
   return T;

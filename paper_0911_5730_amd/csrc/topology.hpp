@@ -46,10 +46,12 @@ struct Topology {
 
 // elements given as CSR (elem_ptr, elem_dof); elem_sub[e] in [0, nsub);
 // elem_touch[e] != 0 if the element carries Dirichlet data (its substructure does not float).
-// Throws Error{BDDC_EPARTITION} on an empty substructure or too many sharers.
+// Throws Error{BDDC_EPARTITION} on an empty substructure, too many sharers,
+// or (require_connected) a substructure whose elements with dofs do not form
+// one piece connected through shared dofs.
 Topology classify(int n, int nsub, const std::vector<int32_t>& elem_ptr,
                   const std::vector<int32_t>& elem_dof, const std::vector<int32_t>& elem_sub,
-                  const std::vector<uint8_t>& elem_touch);
+                  const std::vector<uint8_t>& elem_touch, bool require_connected = false);
 
 // The rules above applied to given sharer lists (T.nshare, T.share_), floating
 // flags and each substructure's dof list (raw_ptr, raw): corners, edges and the

@@ -131,14 +131,22 @@ def square_problem(nx: int, nsx: int, *, ny: Optional[int] = None, nsy: Optional
                    name=name, meta={"channels": ch, "nsx": nsx, "nsy": nsy, "groups": groups})
 
 
-def voronoi_partition(rng: np.random.Generator, nx: int, ny: int, nsub: int):
+def voronoi_partition(rng: np.random.Generator, nx: int, ny: int, nsub: int, jitter: bool = False):
     """Element -> region of the nearest of `nsub` seed points drawn uniformly in
     the unit square (nearest to the element centre, ties to the lower seed).
-    Seeds whose region holds no element are dropped and the ids renumbered in
-    seed order.  Returns (part, seed points of the kept regions)."""
+    With `jitter` (nsub a square q^2), one seed is drawn uniformly in each cell
+    of a q x q grid of the unit square instead, which bounds the spread of the
+    region sizes.  Seeds whose region holds no element are dropped and the ids
+    renumbered in seed order.  Returns (part, seed points of the kept regions)."""
     from scipy.spatial import cKDTree
 
-    pts = rng.uniform(0.0, 1.0, size=(nsub, 2))
+    if jitter:
+        q = int(round(np.sqrt(nsub)))
+        assert q * q == nsub, "jittered seeds need a square count"
+        cell = np.stack(np.meshgrid(np.arange(q), np.arange(q)), axis=-1).reshape(-1, 2)
+        pts = (cell + rng.uniform(0.0, 1.0, size=(nsub, 2))) / q
+    else:
+        pts = rng.uniform(0.0, 1.0, size=(nsub, 2))
     cx = (np.arange(nx) + 0.5) / nx
     cy = (np.arange(ny) + 0.5) / ny
     X, Y = np.meshgrid(cx, cy)
@@ -150,26 +158,76 @@ def voronoi_partition(rng: np.random.Generator, nx: int, ny: int, nsub: int):
 
 
 def voronoi_agglomeration(rng: np.random.Generator, nx: int, ny: int, part: np.ndarray, nsub: int,
-                          ngroups: int) -> np.ndarray:
-    """Level-1 region -> group of the nearest of `ngroups` uniform seed points
-    to the region's centroid (mean element centre); empty groups dropped."""
+                          ngroups: int, jitter: bool = False) -> np.ndarray:
+    """Level-1 region -> group of the nearest of `ngroups` seed points (uniform,
+    or jittered as in voronoi_partition) to the region's centroid (mean element
+    centre); empty groups dropped."""
     from scipy.spatial import cKDTree
 
-    pts = rng.uniform(0.0, 1.0, size=(ngroups, 2))
+    if jitter:
+        q = int(round(np.sqrt(ngroups)))
+        assert q * q == ngroups, "jittered seeds need a square count"
+        cell = np.stack(np.meshgrid(np.arange(q), np.arange(q)), axis=-1).reshape(-1, 2)
+        pts = (cell + rng.uniform(0.0, 1.0, size=(ngroups, 2))) / q
+    else:
+        pts = rng.uniform(0.0, 1.0, size=(ngroups, 2))
     cx = np.tile((np.arange(nx) + 0.5) / nx, ny)
     cy = np.repeat((np.arange(ny) + 0.5) / ny, nx)
     cnt = np.bincount(part, minlength=nsub).astype(np.float64)
     cen = np.column_stack([np.bincount(part, cx, nsub) / cnt, np.bincount(part, cy, nsub) / cnt])
     _, near = cKDTree(pts).query(cen)
+    near = _connected_groups(part.reshape(ny, nx), nsub, near)
     used = np.unique(near)
-    remap = np.full(ngroups, -1, dtype=np.int64)
+    remap = np.full(int(near.max()) + 1, -1, dtype=np.int64)
     remap[used] = np.arange(used.size)
     return remap[near].astype(np.int32)
 
 
+def _connected_groups(part2d: np.ndarray, nsub: int, group: np.ndarray) -> np.ndarray:
+    """Make every group of regions connected (regions adjacent when they share
+    a mesh node): a piece of a group cut off from its largest piece joins the
+    adjacent group it touches most, until no group is cut."""
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+
+    q = np.stack([part2d[:-1, :-1], part2d[:-1, 1:], part2d[1:, :-1], part2d[1:, 1:]], 0).reshape(4, -1)
+    a, b = [], []
+    for i in range(4):
+        for j in range(i + 1, 4):
+            m = q[i] != q[j]
+            a.append(q[i][m])
+            b.append(q[j][m])
+    a, b = np.concatenate(a), np.concatenate(b)
+    adj = coo_matrix((np.ones(a.size), (a, b)), shape=(nsub, nsub)).tocsr()
+    adj = ((adj + adj.T) > 0).astype(np.int8).tocsr()
+    group = group.copy()
+    for _ in range(50):
+        r, c = adj.nonzero()
+        keep = group[r] == group[c]
+        inner = coo_matrix((np.ones(keep.sum()), (r[keep], c[keep])), shape=(nsub, nsub))
+        ncomp, lab = connected_components(inner, directed=False)
+        size = np.bincount(lab, minlength=ncomp)
+        # the largest piece of each group stays
+        best = {}
+        for comp in np.argsort(-size, kind="stable"):
+            g = int(group[np.argmax(lab == comp)])
+            best.setdefault(g, comp)
+        stray = [comp for comp in range(ncomp) if best[int(group[np.argmax(lab == comp)])] != comp]
+        if not stray:
+            return group
+        for comp in stray:
+            members = np.where(lab == comp)[0]
+            nb = adj[members].nonzero()[1]
+            nb = nb[group[nb] != group[members[0]]]
+            if nb.size:
+                group[members] = np.bincount(group[nb]).argmax()
+    return group
+
+
 def voronoi_problem(nx: int, nsub: int, *, levels: int = 2, ngroups: int = 1, constraints: str = "corners",
                     tau: float = float("inf"), kmode: str = "one", kmax_exp: float = 0.0, channels: int = 0,
-                    nrhs: int = 1, seed: int = 0, element: str = "Q1", name: str = "") -> Problem:
+                    nrhs: int = 1, seed: int = 0, element: str = "Q1", name: str = "",
+                    jitter: bool = False) -> Problem:
     """A seeded problem on an irregular partition of uneven substructures:
     Voronoi regions of `nsub` uniform seed points (level 1) and, for three
     levels, Voronoi groups of their centroids around `ngroups` further seeds.
@@ -184,9 +242,9 @@ def voronoi_problem(nx: int, nsub: int, *, levels: int = 2, ngroups: int = 1, co
     else:
         raise ValueError(kmode)
     ch = add_channels(rng, nx, ny, coeff, count=channels) if channels else []
-    part, _ = voronoi_partition(rng, nx, ny, nsub)
+    part, _ = voronoi_partition(rng, nx, ny, nsub, jitter=jitter)
     nkept = int(part.max()) + 1
-    agg = [voronoi_agglomeration(rng, nx, ny, part, nkept, ngroups)] if levels == 3 else []
+    agg = [voronoi_agglomeration(rng, nx, ny, part, nkept, ngroups, jitter=jitter)] if levels == 3 else []
     nfree = (nx - 1) * (ny - 1)
     f = rng.uniform(-1.0, 1.0, size=(nrhs, nfree))
     sizes = np.bincount(part, minlength=nkept)
@@ -201,6 +259,8 @@ CONFIG_NAMES = {
     2: "adaptive three-level, 256x256 Q1, 16x16 subs (H/h=16), 4x4 groups, "
        "k=10^U(0,6) + 8 channels k=1e6, tau=10",
     3: "adaptive three-level, 1024x1024 Q1, 64x64 subs (H/h=16), 16x16 groups, k=1, tau=10",
+    4: "adaptive three-level, 2048x2048 Q1, 9216 jittered Voronoi regions (152-927 dofs), 576 Voronoi groups, "
+       "k=10^U(0,4), tau=10",
 }
 
 
@@ -217,6 +277,11 @@ def config(cid: int, nrhs: int = 1) -> Problem:
     if cid == 3:
         return square_problem(1024, 64, levels=3, groups=(4, 4), constraints="adaptive",
                               tau=10.0, kmode="one", nrhs=nrhs, seed=seed, name="config3")
+    if cid == 4:
+        # the batching form's uneven substructures, with regions small enough
+        # for dense local factors (one seed uniform in each of 96 x 96 cells)
+        return voronoi_problem(2048, 96 * 96, levels=3, ngroups=24 * 24, constraints="adaptive", tau=10.0,
+                               kmode="loguniform", kmax_exp=4.0, nrhs=nrhs, seed=seed, jitter=True, name="config4")
     raise ValueError(f"unknown config {cid}")
 
 

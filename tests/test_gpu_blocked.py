@@ -4,7 +4,8 @@ each launch applying its operator block to every column still iterating.
 Every column keeps its own recurrences, scalars and convergence test, and
 its arithmetic is the single-column arithmetic, so a blocked solve must give
 bitwise the iterates of solving each column alone (BDDC_SOLVE_BLOCK=1), for
-every deep-level path, precision form and partial-sum mode, with columns
+every deep-level path, precision form and partial-sum mode (and interfaces
+whose column slots do not fill a workgroup: 129-192 dofs), with columns
 that converge at different iterations (one at once: a zero load), a ragged
 last block (11 columns = 8 + 3), and a changing block width between solves
 on one handle (the captured chunk of launches is rebuilt).  The blocked
@@ -50,12 +51,13 @@ def _alone(S, F, monkeypatch, **kw):
 
 
 @pytest.mark.parametrize("case,path", [("adaptive3", "coop"), ("adaptive3", "wide"), ("adaptive3", "fused"),
-                                       ("adaptive3", "levels"), ("corners_kjump", "two-level")])
+                                       ("adaptive3", "levels"), ("corners_kjump", "two-level"),
+                                       ("voronoi_jitter3", "default")])
 def test_blocked_columns_equal_single_columns_bitwise(case, path, monkeypatch):
     import torch
 
     import paper_0911_5730_amd as P
-    if path != "two-level":
+    if path not in ("two-level", "default"):
         monkeypatch.setenv("BDDC_DEEP_PATH", path)
     prob = _case(case)
     F = _loads(prob, 11, 3)

@@ -226,3 +226,17 @@ def test_serving_resident_problems_merge_loads_and_match_alone():
         assert np.array_equal(r.solution, u)
     print(f"serving resident: {st}", flush=True)
     assert st["reused"] > 0 and st["mean_batch"] > 1.0
+
+
+def test_disconnected_coarse_substructure_is_rejected():
+    """A level-2 substructure made of two level-1 substructures that share
+    no coarse dof would carry a null space per piece: set-up refuses it with
+    BDDC_EPARTITION instead of meeting a singular pivot."""
+    import paper_0911_5730_amd as P
+    prob = synth.square_problem(16, 4, levels=3, groups=(2, 2), kmode="loguniform", kmax_exp=1, seed=37)
+    agg = np.ones(16, dtype=np.int32)
+    agg[0] = agg[15] = 0                     # opposite corners of the 4 x 4 partition
+    prob.agglom = [agg]
+    with pytest.raises(P.BDDCError) as ei:
+        P.Solver(prob)
+    assert ei.value.name == "BDDC_EPARTITION"

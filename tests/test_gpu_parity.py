@@ -50,12 +50,15 @@ def _case(name):
                                         kmode="loguniform", kmax_exp=3, channels=2, seed=33),
         "voronoi_adaptive3_large": lambda: vo(128, 48, levels=3, ngroups=8, constraints="adaptive", tau=10.0,
                                               kmode="loguniform", kmax_exp=4, channels=2, seed=34),
+        # jittered seeds, up to 1114 local dofs and interfaces of 160 dofs
+        "voronoi_jitter3": lambda: vo(160, 36, levels=3, ngroups=4, constraints="adaptive", tau=10.0,
+                                      kmode="loguniform", kmax_exp=3, seed=91, jitter=True),
     }[name]()
 
 
 CASES = ["config1", "corners_kjump", "ce_ragged", "rect", "p1", "adaptive2", "adaptive3", "adaptive3_h16",
          "corners3", "single_sub", "adaptive2_h32", "voronoi2", "voronoi_adaptive2", "voronoi_adaptive3",
-         "voronoi_adaptive3_large"]
+         "voronoi_adaptive3_large", "voronoi_jitter3"]
 
 
 @pytest.mark.parametrize("name", CASES)
