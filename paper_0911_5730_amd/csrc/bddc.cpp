@@ -404,6 +404,13 @@ struct bddc_ctx {
   bddc::Arena top;        // coarsest factor, PCG state, status flag
   double* AL = nullptr;
   int ncL = 0;
+  // coarse spaces of kCoarseInvMin dofs and more: AL holds A_L^-1 (block
+  // Gauss-Jordan at set-up) and every coarsest solve is a product with it;
+  // P / T are the sweep's scratch, coarse_r / coarse_u kMaxRhs columns of
+  // coarsest right-hand sides and solutions at stride ld_cr
+  bool coarse_inv = false;
+  double *coarse_P = nullptr, *coarse_T = nullptr, *coarse_r = nullptr, *coarse_u = nullptr;
+  int ld_cr = 0;
   int* status = nullptr;
   // PCG on the level-1 interface; the per-column state (vectors, partials,
   // scalars) sits in its own arena, sized for cols_cap columns
@@ -1188,7 +1195,18 @@ class Builder {
       d.b = A.take<double>(lv.nflat_c);
       d.rc = A.take<double>(lv.nc);
       d.uc = A.take<double>(lv.nc);
-      if (last) h_->AL = A.take<double>((size_t)lv.nc * lv.nc);
+      if (last) {
+        const char* cenv = getenv("BDDC_COARSE");
+        h_->coarse_inv = lv.nc >= kCoarseInvMin || (cenv && std::string(cenv) == "inverse");
+        h_->AL = A.take<double>((size_t)lv.nc * lv.nc);
+        if (h_->coarse_inv) {
+          h_->ld_cr = (int)(((std::max(lv.nc, 1) * 8 + 255) / 256) * 32);
+          h_->coarse_P = A.take<double>(64 * 64);
+          h_->coarse_T = A.take<double>((size_t)std::max(lv.nc, 1) * 64);
+          h_->coarse_r = A.take<double>((size_t)kMaxRhs * h_->ld_cr);
+          h_->coarse_u = A.take<double>((size_t)kMaxRhs * h_->ld_cr);
+        }
+      }
     };
     A.reset_sizing();
     layout();
@@ -1252,8 +1270,12 @@ class Builder {
   void coarsest() {
     Level& lv = *h_->levels.back();
     h_->ncL = lv.nc;
-    if (lv.nc > 0)
+    if (lv.nc > 0 && h_->coarse_inv) {
+      launch_coarsest_assemble(st_, lv.nsub, lv.nc, lv.d.coff, lv.d.cid, lv.d.Ac, lv.d.acoff, h_->AL);
+      launch_coarsest_inverse(st_, lv.nc, h_->AL, h_->coarse_P, h_->coarse_T, h_->status);
+    } else if (lv.nc > 0) {
       launch_coarsest_factor(st_, lv.nsub, lv.nc, lv.d.coff, lv.d.cid, lv.d.Ac, lv.d.acoff, h_->AL, h_->status);
+    }
   }
 };
 
@@ -1263,6 +1285,15 @@ class Builder {
 // Levels >= 2 run in full space with the explicit inverse of their interior
 // factors; level 1 runs in full space for bddc_apply and on the interface
 // inside bddc_solve.
+// u_L = A_L^-1 r_L: two triangular solves with the Cholesky factor in one
+// workgroup, or the product with A_L^-1 for a large coarse space
+static void coarsest_solve(bddc_ctx* h, hipStream_t st, int nc, const double* rc, double* uc, const int32_t* stop) {
+  if (h->coarse_inv)
+    launch_coarse_inv_apply(st, nc, h->AL, rc, nc, uc, nc, 1, stop);
+  else
+    launch_coarsest_solve(st, nc, h->AL, rc, uc, stop);
+}
+
 static void apply_deep_level(bddc_ctx* h, int li, const double* r, double* u, hipStream_t st) {
   Level& lv = *h->levels[li];
   const std::string sfx = "_l" + std::to_string(li + 1);
@@ -1276,7 +1307,7 @@ static void apply_deep_level(bddc_ctx* h, int li, const double* r, double* u, hi
   }
   launch_coarse_gather(st, lv.nc, lv.d.csh_ptr, lv.d.csh_flat, lv.d.b, lv.d.rc, lv.dev.stop);
   if (li + 1 == (int)h->levels.size())
-    launch_coarsest_solve(st, lv.nc, h->AL, lv.d.rc, lv.d.uc, lv.dev.stop);
+    coarsest_solve(h, st, lv.nc, lv.d.rc, lv.d.uc, lv.dev.stop);
   else
     apply_deep_level(h, li + 1, lv.d.rc, lv.d.uc, st);
   {
@@ -1296,7 +1327,7 @@ static void run_deep_at(bddc_ctx* h, hipStream_t st, const double* b1, double* u
   Level& l1 = *h->levels[0];
   if (h->levels.size() == 1) {
     launch_coarse_gather(st, l1.nc, l1.d.csh_ptr, l1.d.csh_flat, b1, l1.d.rc, l1.dev.stop);
-    launch_coarsest_solve(st, l1.nc, h->AL, l1.d.rc, uc, l1.dev.stop);
+    coarsest_solve(h, st, l1.nc, l1.d.rc, uc, l1.dev.stop);
     return;
   }
   if (h->deep_sel == BDDC_DEEP_COOP) {
@@ -1345,7 +1376,13 @@ static void run_deep(bddc_ctx* h, hipStream_t st) {
 static void run_deep_cols(bddc_ctx* h, hipStream_t st, const double* b1, int ldb, double* uc, int ldu, int R) {
   Level& l1 = *h->levels[0];
   if (h->levels.size() == 1) {
-    launch_coarse_direct_cols(st, l1.nc, l1.d.csh_ptr, l1.d.csh_flat, b1, ldb, h->AL, uc, ldu, R, l1.dev.stop);
+    if (h->coarse_inv) {
+      launch_coarse_gather_cols(st, l1.nc, l1.d.csh_ptr, l1.d.csh_flat, b1, ldb, h->coarse_r, h->ld_cr, R,
+                                l1.dev.stop);
+      launch_coarse_inv_apply(st, l1.nc, h->AL, h->coarse_r, h->ld_cr, uc, ldu, R, l1.dev.stop);
+    } else {
+      launch_coarse_direct_cols(st, l1.nc, l1.d.csh_ptr, l1.d.csh_flat, b1, ldb, h->AL, uc, ldu, R, l1.dev.stop);
+    }
     return;
   }
   if (h->deep_sel == BDDC_DEEP_WIDE && R <= kMaxRhs) {
@@ -1401,7 +1438,7 @@ static void apply_full(bddc_ctx* h, const double* r, double* u) {
 // index lists per substructure and use the cooperative kernel if it fits.
 static bool plan_coop(bddc_ctx* h) {
   h->coop_deep = false;
-  if (h->levels.size() != 2) return false;
+  if (h->levels.size() != 2 || h->coarse_inv) return false;
   const char* env = getenv("BDDC_DEEP_PATH");
   if (env && std::string(env) != "coop") return false;
   Level& l1 = *h->levels[0];
@@ -1580,7 +1617,8 @@ static bool plan_wide(bddc_ctx* h) {
     nmax_ops = std::max<int>(nmax_ops, (int)(nI * nI + nI * ng));
   }
   // the coarsest solve and the level-2 interface live in one workgroup's LDS
-  if (sizeof(double) * (size_t)lv.nc > kLdsLimit || sizeof(double) * ((size_t)lv.ngmax + kNT) > kLdsLimit ||
+  if ((!h->coarse_inv && sizeof(double) * (size_t)lv.nc > kLdsLimit) ||
+      sizeof(double) * ((size_t)lv.ngmax + kNT) > kLdsLimit ||
       sizeof(double) * (size_t)lv.nImax > kLdsLimit)
     return false;
   std::vector<int32_t> sub_of_flat(lv.nflat_g);
@@ -1640,6 +1678,10 @@ static bool plan_wide(bddc_ctx* h) {
   W.u2 = l1.d.uc;
   W.ncL = lv.nc;
   W.AL = h->AL;
+  W.coarse_inv = h->coarse_inv ? 1 : 0;
+  W.r3 = h->coarse_r;
+  W.u3 = h->coarse_u;
+  W.ld_3 = h->ld_cr;
   W.nflat = lv.nflat_g;
   h->wide = W;
   h->wide_deep = true;
@@ -1681,6 +1723,7 @@ static void plan_deep(bddc_ctx* h) {
     wstride = std::max({wstride, 2 * lv.nImax, lv.ngmax + lv.nImax, lv.ncsmax, lv.ngmax});
   }
   const int ncL = h->levels.back()->nc;
+  if (h->coarse_inv) return;   // the fused kernel solves the coarsest problem with its Cholesky factor
   const bool forced = env && std::string(env) == "fused";
   if (!forced && bytes > 4.0e6) return;
   if (deep_lds(wstride, ncL) > kLdsLimit) return;
@@ -1876,15 +1919,20 @@ static int pcg_block(bddc_ctx* h, const double* f, double* u, int64_t ld, int R,
   }
   // the condensation: with the streamed sweeps all columns in one pass over
   // L (y = L^{-1} f_I, t = L_GI y per column), else column by column
+  // interior pre-correction of every column: column sweeps for small
+  // substructures, else the blocked triangular solves when kMaxRhs columns fit
+  // the LDS, else column by column
   const bool sweep = use_sweep(l1.nmax);
+  const bool blocked = !sweep && apply_cols_lds(kMaxRhs, l1.nImax, l1.ngmax) <= kLdsMax;
   if (sweep) launch_sweep_pre_cols(st, l1.dev, f, ld, h->cy, h->ld_cy, h->ct, P.ld_flat, R);
+  if (blocked) launch_apply_pre_cols(st, l1.dev, l1.nImax, l1.ngmax, f, ld, h->cy, h->ld_cy, h->ct, P.ld_flat, R);
   for (int c = 0; c < R; ++c) {
     const double* fc = f + (size_t)c * ld;
     double* rc = P.r[0] + (size_t)c * P.ld_if;
     launch_dot_partial(st, nbf, (int)h->n_free, fc, fc, h->partial);
     launch_scalar(st, 4, nbf, h->partial, P.sc + c);                 // bb, thr2 = rtol^2 bb
-    if (!sweep) launch_apply_pre(st, l1.dev, l1.nImax, l1.ngmax, fc);
-    const double* tc = sweep ? h->ct + (size_t)c * P.ld_flat : l1.d.t;
+    if (!sweep && !blocked) launch_apply_pre(st, l1.dev, l1.nImax, l1.ngmax, fc);
+    const double* tc = sweep || blocked ? h->ct + (size_t)c * P.ld_flat : l1.d.t;
     launch_condense(st, nif, l1.d.sh_ptr, l1.d.sh_flat, l1.d.iface_dof, fc, tc, rc, P.x + (size_t)c * P.ld_if);
     launch_dot_partial(st, nb, nif, rc, rc, h->partial);
     launch_scalar(st, 5, nb, h->partial, P.sc + c);                  // rr0, done if already small
@@ -1958,13 +2006,15 @@ static int pcg_block(bddc_ctx* h, const double* f, double* u, int64_t ld, int R,
   }
   timing::current_tag = -1;
   // interior recovery u_I = L^-T (y - L_GI^T x) with each column's own y:
-  // the column sweeps kept every column's y; column by column, the set-up
-  // pass above left the last column's y (the level's stop flag is raised by
-  // now, so these launches go without it)
+  // the column sweeps and the blocked solves kept every column's y; column by
+  // column, the set-up pass above left the last column's y (the level's stop
+  // flag is raised by now, so these launches go without it)
   LevelDev L1 = l1.dev;
   L1.stop = nullptr;
   if (sweep) {
     launch_sweep_recover_cols(st, L1, P.x, P.ld_if, h->cy, h->ld_cy, u, ld, R);
+  } else if (blocked) {
+    launch_recover_cols(st, L1, l1.nImax, l1.ngmax, P.x, P.ld_if, h->cy, h->ld_cy, u, ld, R);
   } else {
     for (int c = R - 1; c >= 0; --c) {
       if (c < R - 1) launch_apply_pre(st, L1, l1.nImax, l1.ngmax, f + (size_t)c * ld);
@@ -2123,6 +2173,8 @@ bddc_status bddc_plan(const bddc_problem* p, bddc_info* info) {
   });
 }
 
+}  // extern "C"
+
 namespace bddc {
 namespace {
 
@@ -2180,6 +2232,7 @@ std::string shape_key(const bddc_ctx* h) {
 
 }  // namespace
 }  // namespace bddc
+extern "C" {
 
 bddc_status bddc_setup(const bddc_problem* p, void* hip_stream, bddc_handle* out) {
   if (out) *out = nullptr;

@@ -391,6 +391,193 @@ __global__ void __launch_bounds__(kNT) k_recover(LevelDev L, const double* __res
   for (int j = tid; j < nI; j += kNT) u[L.int_gid[L.ioff[s] + j]] = yv[j];
 }
 
+// ---------------------------------------------------------------------------
+// R right-hand sides at once (R <= kMaxRhs), for substructures too large for
+// the column sweeps: every factor entry is read once for all columns, and
+// each column's arithmetic is that of the single-column kernels above
+// (wg_trsv_lower / wg_trsv_lower_trans and the same sums in the same order).
+// Y holds column c at Y + c ldy (LDS).
+
+// L Y = Y: the 16 x 16 diagonal block by a group of 16 lanes per column
+// (four columns per wave), the rows below by one thread per row
+__device__ inline void wg_trsm_lower_cols(const double* Lm, int ldl, int n, double* Y, int ldy, int R) {
+  const int tid = threadIdx.x, lane = tid & 63, q = lane & 15;
+  const int c = (tid >> 6) * 4 + (lane >> 4);
+  for (int j0 = 0; j0 < n; j0 += 16) {
+    const int jb = min(16, n - j0);
+    if (c < R) {
+      double yi = q < jb ? Y[c * ldy + j0 + q] : 0.0;
+      double row[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k)
+        row[k] = (q < jb && k <= q && k < jb) ? Lm[(j0 + q) + (size_t)(j0 + k) * ldl] : 0.0;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        if (k < jb) {
+          if (q == k) yi = yi / row[k];
+          const double yk = __shfl(yi, (lane & ~15) + k, 64);
+          if (q > k) yi -= row[k] * yk;
+        }
+      }
+      if (q < jb) Y[c * ldy + j0 + q] = yi;
+    }
+    __syncthreads();
+    for (int i = j0 + jb + tid; i < n; i += kNT) {
+      double l[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) l[k] = k < jb ? Lm[i + (size_t)(j0 + k) * ldl] : 0.0;
+      for (int cc = 0; cc < R; ++cc) {
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+          if (k < jb) acc += l[k] * Y[cc * ldy + j0 + k];
+        Y[cc * ldy + i] -= acc;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// L^T X = Y in place, blocked by 16 from the bottom
+__device__ inline void wg_trsm_lower_trans_cols(const double* Lm, int ldl, int n, double* Y, int ldy, int R) {
+  const int tid = threadIdx.x, lane = tid & 63, q = lane & 15;
+  const int c = (tid >> 6) * 4 + (lane >> 4);
+  for (int b = (n + 15) / 16 - 1; b >= 0; --b) {
+    const int j0 = b * 16;
+    const int jb = min(16, n - j0);
+    if (c < R) {
+      double xi = q < jb ? Y[c * ldy + j0 + q] : 0.0;
+      double col[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k)
+        col[k] = (q < jb && k >= q && k < jb) ? Lm[(j0 + k) + (size_t)(j0 + q) * ldl] : 0.0;
+#pragma unroll
+      for (int kk = 15; kk >= 0; --kk) {
+        if (kk < jb) {
+          if (q == kk) xi = xi / col[kk];
+          const double xk = __shfl(xi, (lane & ~15) + kk, 64);
+          if (q < kk) xi -= col[kk] * xk;
+        }
+      }
+      if (q < jb) Y[c * ldy + j0 + q] = xi;
+    }
+    __syncthreads();
+    for (int i = tid; i < j0; i += kNT) {
+      double l[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) l[k] = k < jb ? Lm[(j0 + k) + (size_t)i * ldl] : 0.0;
+      for (int cc = 0; cc < R; ++cc) {
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+          if (k < jb) acc += l[k] * Y[cc * ldy + j0 + k];
+        Y[cc * ldy + i] -= acc;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// k_apply_pre for R columns: y[:, c] = L_II^-1 r_I[:, c], t[:, c] = L_GI y[:, c]
+// (r at stride ldr, y interior flat at ldy, t interface flat at ldt)
+__global__ void __launch_bounds__(kNT) k_apply_pre_cols(LevelDev L, const double* __restrict__ r, int64_t ldr,
+                                                        double* __restrict__ yout, int ldy, double* __restrict__ tout,
+                                                        int ldt, int R) {
+  extern __shared__ double sh[];
+  if (L.stop && *L.stop) return;
+  const int s = blockIdx.x;
+  const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
+  const int nI = L.nint[s];
+  const int ng = n - nI;
+  const double* A = L.K + L.koff[s];
+  const int tid = threadIdx.x;
+  double* Y = sh;
+  double* part = sh + (size_t)R * nI;
+  const int i0 = L.ioff[s], g0 = L.goff[s];
+  for (int idx = tid; idx < R * nI; idx += kNT) {
+    const int c = idx / nI, i = idx - c * nI;
+    Y[idx] = r[(size_t)c * ldr + L.int_gid[i0 + i]];
+  }
+  __syncthreads();
+  wg_trsm_lower_cols(A, n, nI, Y, nI, R);
+  for (int idx = tid; idx < R * nI; idx += kNT) {
+    const int c = idx / nI, i = idx - c * nI;
+    yout[(size_t)c * ldy + i0 + i] = Y[idx];
+  }
+  if (ng == 0) return;
+  const int nch = max(1, kNT / ng);
+  const int pw = ng * nch;
+  for (ColWalk w_(tid, kNT, ng); w_.j < nch; w_.next()) {
+    const int a = w_.i, ch = w_.j;
+    double acc[kMaxRhs];
+#pragma unroll
+    for (int c = 0; c < kMaxRhs; ++c) acc[c] = 0.0;
+    for (int j = ch; j < nI; j += nch) {
+      const double l = A[(nI + a) + (size_t)j * n];
+#pragma unroll
+      for (int c = 0; c < kMaxRhs; ++c)
+        if (c < R) acc[c] += l * Y[c * nI + j];
+    }
+#pragma unroll
+    for (int c = 0; c < kMaxRhs; ++c)
+      if (c < R) part[c * pw + a + ch * ng] = acc[c];
+  }
+  __syncthreads();
+  for (int idx = tid; idx < R * ng; idx += kNT) {
+    const int c = idx / ng, a = idx - c * ng;
+    double acc = 0.0;
+    for (int ch = 0; ch < nch; ++ch) acc += part[c * pw + a + ch * ng];
+    tout[(size_t)c * ldt + g0 + a] = acc;
+  }
+}
+
+// k_recover for R columns: u_B[:, c] = x[:, c] (at ldx), u_I[:, c] =
+// L_II^-T (y[:, c] - L_GI^T u_B[:, c]) (y at ldy, u at ldu)
+__global__ void __launch_bounds__(kNT) k_recover_cols(LevelDev L, const double* __restrict__ x, int ldx,
+                                                      const double* __restrict__ y, int ldy, double* __restrict__ u,
+                                                      int64_t ldu, int R) {
+  extern __shared__ double sh[];
+  const int s = blockIdx.x;
+  const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
+  const int nI = L.nint[s];
+  const int ng = n - nI;
+  const int g0 = L.goff[s], i0 = L.ioff[s];
+  const int tid = threadIdx.x;
+  double* UB = sh;
+  double* YV = sh + (size_t)R * ng;
+  for (int idx = tid; idx < R * ng; idx += kNT) {
+    const int c = idx / ng, a = idx - c * ng;
+    const int f = g0 + a;
+    const int gi = L.gam_iid[f];
+    const double v = x[(size_t)c * ldx + gi];
+    UB[idx] = v;
+    if (L.sh_flat[L.sh_ptr[gi]] == f) u[(size_t)c * ldu + L.gam_gid[f]] = v;
+  }
+  if (nI == 0) return;
+  __syncthreads();
+  const double* A = L.K + L.koff[s];
+  for (int j = tid; j < nI; j += kNT) {
+    double acc[kMaxRhs];
+#pragma unroll
+    for (int c = 0; c < kMaxRhs; ++c) acc[c] = 0.0;
+    for (int a = 0; a < ng; ++a) {
+      const double l = A[(nI + a) + (size_t)j * n];
+#pragma unroll
+      for (int c = 0; c < kMaxRhs; ++c)
+        if (c < R) acc[c] += l * UB[c * ng + a];
+    }
+#pragma unroll
+    for (int c = 0; c < kMaxRhs; ++c)
+      if (c < R) YV[c * nI + j] = y[(size_t)c * ldy + i0 + j] - acc[c];
+  }
+  __syncthreads();
+  wg_trsm_lower_trans_cols(A, n, nI, YV, nI, R);
+  for (int idx = tid; idx < R * nI; idx += kNT) {
+    const int c = idx / nI, j = idx - c * nI;
+    u[(size_t)c * ldu + L.int_gid[i0 + j]] = YV[idx];
+  }
+}
+
 __global__ void k_copy(int n, const double* __restrict__ a, double* __restrict__ b) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) b[i] = a[i];
@@ -478,6 +665,23 @@ void launch_condense(hipStream_t st, int nif, const int32_t* sh_ptr, const int32
 void launch_recover(hipStream_t st, const LevelDev& L, int nImax, int ngmax, const double* x, double* u) {
   const size_t lds = sizeof(double) * ((size_t)ngmax + nImax + 1);
   launch_kernel(k_recover, dim3(L.nsub), dim3(kNT), lds, st, L, x, u);
+}
+size_t apply_cols_lds(int R, int nImax, int ngmax) {
+  return sizeof(double) * (size_t)R * ((size_t)nImax + (size_t)max(kNT, ngmax));
+}
+void launch_apply_pre_cols(hipStream_t st, const LevelDev& L, int nImax, int ngmax, const double* r, int64_t ldr,
+                           double* y, int ldy, double* t, int ldt, int R) {
+  if (L.nsub == 0 || R == 0) return;
+  if (R > kMaxRhs) throw std::invalid_argument("launch_apply_pre_cols: too many columns");
+  launch_kernel(k_apply_pre_cols, dim3(L.nsub), dim3(kNT), apply_cols_lds(R, nImax, ngmax), st, L, r, ldr, y, ldy, t,
+                ldt, R);
+}
+void launch_recover_cols(hipStream_t st, const LevelDev& L, int nImax, int ngmax, const double* x, int ldx,
+                         const double* y, int ldy, double* u, int64_t ldu, int R) {
+  if (L.nsub == 0 || R == 0) return;
+  if (R > kMaxRhs) throw std::invalid_argument("launch_recover_cols: too many columns");
+  launch_kernel(k_recover_cols, dim3(L.nsub), dim3(kNT), apply_cols_lds(R, nImax, ngmax), st, L, x, ldx, y, ldy, u,
+                ldu, R);
 }
 void launch_copy(hipStream_t st, int n, const double* a, double* b) {
   if (n == 0) return;

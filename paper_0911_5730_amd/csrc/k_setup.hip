@@ -9,6 +9,7 @@
 #include <algorithm>
 
 #include "dense.hpp"
+#include "common.hpp"
 #include "kernels.hpp"
 
 namespace bddc {
@@ -343,13 +344,9 @@ __global__ void __launch_bounds__(kNT) k_constrained_factor(
 
 // Coarsest level (Algorithm "Multilevel BDDC", direct solve at level L):
 // A_L = sum_s R_cs^T A_cs R_cs assembled in substructure order, then factored.
-__global__ void __launch_bounds__(kNT) k_coarsest_factor(int nsub, int nc, const int32_t* __restrict__ cptr,
-                                                         const int32_t* __restrict__ cid,
-                                                         const double* __restrict__ Ac,
-                                                         const int64_t* __restrict__ acoff,
-                                                         double* __restrict__ AL, int* status) {
-  for (int idx = threadIdx.x; idx < nc * nc; idx += kNT) AL[idx] = 0.0;
-  __syncthreads();
+__device__ inline void coarsest_assemble(int nsub, int nc, const int32_t* __restrict__ cptr,
+                                         const int32_t* __restrict__ cid, const double* __restrict__ Ac,
+                                         const int64_t* __restrict__ acoff, double* __restrict__ AL) {
   for (int s = 0; s < nsub; ++s) {
     const int m = cptr[s + 1] - cptr[s];
     const int32_t* map = cid + cptr[s];
@@ -361,7 +358,26 @@ __global__ void __launch_bounds__(kNT) k_coarsest_factor(int nsub, int nc, const
     }
     __syncthreads();
   }
+}
+
+__global__ void __launch_bounds__(kNT) k_coarsest_factor(int nsub, int nc, const int32_t* __restrict__ cptr,
+                                                         const int32_t* __restrict__ cid,
+                                                         const double* __restrict__ Ac,
+                                                         const int64_t* __restrict__ acoff,
+                                                         double* __restrict__ AL, int* status) {
+  for (int idx = threadIdx.x; idx < nc * nc; idx += kNT) AL[idx] = 0.0;
+  __syncthreads();
+  coarsest_assemble(nsub, nc, cptr, cid, Ac, acoff, AL);
   wg_potrf(AL, nc, nc, status);
+}
+
+// the same assembly into a zeroed AL, left unfactored
+__global__ void __launch_bounds__(kNT) k_coarsest_assemble(int nsub, int nc, const int32_t* __restrict__ cptr,
+                                                           const int32_t* __restrict__ cid,
+                                                           const double* __restrict__ Ac,
+                                                           const int64_t* __restrict__ acoff,
+                                                           double* __restrict__ AL) {
+  coarsest_assemble(nsub, nc, cptr, cid, Ac, acoff, AL);
 }
 
 // ---------------------------------------------------------------------------
@@ -428,6 +444,11 @@ void launch_coarsest_factor(hipStream_t st, int nsub, int nc, const int32_t* cpt
                             const double* Ac, const int64_t* acoff, double* AL, int* status) {
   launch_kernel(k_coarsest_factor, dim3(1), dim3(kNT), 0, st, nsub, nc, cptr, cid, Ac, acoff, AL,
                      status);
+}
+void launch_coarsest_assemble(hipStream_t st, int nsub, int nc, const int32_t* cptr, const int32_t* cid,
+                              const double* Ac, const int64_t* acoff, double* AL) {
+  BDDC_HIP(hipMemsetAsync(AL, 0, sizeof(double) * (size_t)nc * nc, st));
+  launch_kernel(k_coarsest_assemble, dim3(1), dim3(kNT), 0, st, nsub, nc, cptr, cid, Ac, acoff, AL);
 }
 
 }  // namespace bddc

@@ -80,26 +80,34 @@ __global__ void __launch_bounds__(kNT) k_wide_pre(WideDev W) {
   }
 }
 
-// the coarsest problem (solved by every workgroup, it is small) and the
-// prolongation of its solution to the workgroup's slice of interface entries
+// the coarsest problem (solved by every workgroup when it is small; kInv: its
+// solution u_3 already formed in W.u3 by the product with A_L^-1) and the
+// prolongation of u_3 to the workgroup's slice of interface entries
 // grid (blocks, columns)
+template <bool kInv>
 __global__ void __launch_bounds__(kNT) k_wide_coarse(WideDev W) {
   extern __shared__ double sh[];
   if (W.stop && *W.stop) return;
   const LevelDev& L = W.L;
   const int col = blockIdx.y;
-  const double* Lb = L.b + (size_t)col * W.ld_c;
   const double* La = L.a + (size_t)col * W.ld_g;
   double* Lv = L.v + (size_t)col * W.ld_g;
-  double* u3 = sh;
-  for (int k = threadIdx.x; k < W.ncL; k += kNT) {
-    double acc = 0.0;
-    for (int q = L.csh_ptr[k]; q < L.csh_ptr[k + 1]; ++q) acc += Lb[L.csh_flat[q]];
-    u3[k] = acc;
+  const double* u3;
+  if constexpr (kInv) {
+    u3 = W.u3 + (size_t)col * W.ld_3;
+  } else {
+    const double* Lb = L.b + (size_t)col * W.ld_c;
+    double* y = sh;
+    for (int k = threadIdx.x; k < W.ncL; k += kNT) {
+      double acc = 0.0;
+      for (int q = L.csh_ptr[k]; q < L.csh_ptr[k + 1]; ++q) acc += Lb[L.csh_flat[q]];
+      y[k] = acc;
+    }
+    __syncthreads();
+    wg_trsv_lower(W.AL, W.ncL, W.ncL, y);
+    wg_trsv_lower_trans(W.AL, W.ncL, W.ncL, y);
+    u3 = y;
   }
-  __syncthreads();
-  wg_trsv_lower(W.AL, W.ncL, W.ncL, u3);
-  wg_trsv_lower_trans(W.AL, W.ncL, W.ncL, u3);
   for (int f = blockIdx.x * kNT + threadIdx.x; f < W.nflat; f += gridDim.x * kNT) {
     const int s = W.sub_of_flat[f];
     const int a = f - L.goff[s];
@@ -206,8 +214,15 @@ void launch_wide_pre(hipStream_t st, const WideDev& W) {
 }
 
 void launch_wide_coarse(hipStream_t st, const WideDev& W) {
+  if (W.coarse_inv) {
+    launch_coarse_gather_cols(st, W.ncL, W.L.csh_ptr, W.L.csh_flat, W.L.b, W.ld_c, W.r3, W.ld_3, W.nrhs, W.stop);
+    launch_coarse_inv_apply(st, W.ncL, W.AL, W.r3, W.ld_3, W.u3, W.ld_3, W.nrhs, W.stop);
+    const int nb = max(1, (W.nflat + kNT - 1) / kNT);
+    launch_kernel(k_wide_coarse<true>, dim3(nb, W.nrhs), dim3(kNT), 0, st, W);
+    return;
+  }
   const int nb = max(1, min(64, (W.nflat + kNT - 1) / kNT));
-  launch_kernel(k_wide_coarse, dim3(nb, W.nrhs), dim3(kNT), sizeof(double) * (size_t)max(W.ncL, 1), st, W);
+  launch_kernel(k_wide_coarse<false>, dim3(nb, W.nrhs), dim3(kNT), sizeof(double) * (size_t)max(W.ncL, 1), st, W);
 }
 
 void launch_wide_post(hipStream_t st, const WideDev& W) {

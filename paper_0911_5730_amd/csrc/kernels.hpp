@@ -157,7 +157,11 @@ struct WideDev {
   double* r2 = nullptr;               // level-2 right-hand side
   double* u2 = nullptr;               // level-2 solution
   int ncL = 0;
-  const double* AL = nullptr;         // coarsest Cholesky factor
+  const double* AL = nullptr;         // coarsest Cholesky factor, or A_L^-1 with coarse_inv
+  int coarse_inv = 0;                 // the coarsest solve is a product with A_L^-1
+  double* r3 = nullptr;               // with coarse_inv: coarsest right-hand sides and solutions,
+  double* u3 = nullptr;               // nrhs columns at stride ld_3
+  int ld_3 = 0;
   const int32_t* sub_of_flat = nullptr;   // level-2 interface flat entry -> substructure
   int nflat = 0;
   const int32_t* stop = nullptr;
@@ -234,6 +238,7 @@ struct PcgDev {
   const double* uc = nullptr;  // level-1 coarse correction, per column
 };
 constexpr int kMaxRhs = 8;   // columns of one blocked solve
+constexpr int kCoarseInvMin = 512;   // coarse spaces at least this large are solved with A_L^-1
 
 constexpr int kMaxHist = 4096;
 
@@ -300,6 +305,9 @@ void launch_constrained_factor(hipStream_t st, int nsub, const int64_t* koff, co
                                const int64_t* acoff, double* work, const int64_t* woff, int* status);
 void launch_coarsest_factor(hipStream_t st, int nsub, int nc, const int32_t* cptr, const int32_t* cid,
                             const double* Ac, const int64_t* acoff, double* AL, int* status);
+// the assembly of launch_coarsest_factor without the factorization (AL zeroed first)
+void launch_coarsest_assemble(hipStream_t st, int nsub, int nc, const int32_t* cptr, const int32_t* cid,
+                              const double* Ac, const int64_t* acoff, double* AL);
 
 // adaptive
 void launch_pair_schur(hipStream_t st, int ninc, int ngmax, const int32_t* inc_sub, const int32_t* inc_fptr,
@@ -325,6 +333,19 @@ void launch_apply_restrict(hipStream_t st, const LevelDev& L, int ngmax, const d
                            const int32_t* gam_map, int use_t);
 void launch_coarse_gather(hipStream_t st, int nc, const int32_t* csh_ptr, const int32_t* csh_flat,
                           const double* b, double* rc, const int32_t* stop);
+// large coarsest problems: A_L^-1 in place of A_L (block Gauss-Jordan; P is
+// 64 x 64 and T n x 64 scratch), and the solve as a product with it
+void launch_coarsest_inverse(hipStream_t st, int n, double* A, double* P, double* T, int* status);
+void launch_coarse_gather_cols(hipStream_t st, int nc, const int32_t* csh_ptr, const int32_t* csh_flat,
+                               const double* b, int64_t ldb, double* r, int64_t ldr, int ncols, const int32_t* stop);
+void launch_coarse_inv_apply(hipStream_t st, int n, const double* Ainv, const double* r, int64_t ldr, double* u,
+                             int64_t ldu, int ncols, const int32_t* stop);
+// k_apply_pre / k_recover for R <= kMaxRhs columns (LDS apply_cols_lds(R, nImax, ngmax))
+size_t apply_cols_lds(int R, int nImax, int ngmax);
+void launch_apply_pre_cols(hipStream_t st, const LevelDev& L, int nImax, int ngmax, const double* r, int64_t ldr,
+                           double* y, int ldy, double* t, int ldt, int R);
+void launch_recover_cols(hipStream_t st, const LevelDev& L, int nImax, int ngmax, const double* x, int ldx,
+                         const double* y, int ldy, double* u, int64_t ldu, int R);
 void launch_coarsest_solve(hipStream_t st, int nc, const double* Lc, const double* rc, double* uc,
                            const int32_t* stop);
 void launch_coarse_direct_cols(hipStream_t st, int nc, const int32_t* csh_ptr, const int32_t* csh_flat,

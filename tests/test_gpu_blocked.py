@@ -4,7 +4,9 @@ each launch applying its operator block to every column still iterating.
 Every column keeps its own recurrences, scalars and convergence test, and
 its arithmetic is the single-column arithmetic, so a blocked solve must give
 bitwise the iterates of solving each column alone (BDDC_SOLVE_BLOCK=1), for
-every deep-level path, precision form and partial-sum mode (and interfaces
+every deep-level path (with the coarsest problem solved by its Cholesky
+factor or by the product with its inverse), precision form and partial-sum
+mode (and interfaces
 whose column slots do not fill a workgroup: 129-192 dofs), with columns
 that converge at different iterations (one at once: a zero load), a ragged
 last block (11 columns = 8 + 3), and a changing block width between solves
@@ -52,13 +54,17 @@ def _alone(S, F, monkeypatch, **kw):
 
 @pytest.mark.parametrize("case,path", [("adaptive3", "coop"), ("adaptive3", "wide"), ("adaptive3", "fused"),
                                        ("adaptive3", "levels"), ("corners_kjump", "two-level"),
-                                       ("voronoi_jitter3", "default")])
+                                       ("voronoi_jitter3", "default"), ("adaptive3", "wide+inverse"),
+                                       ("adaptive3", "levels+inverse"), ("corners_kjump", "two-level+inverse")])
 def test_blocked_columns_equal_single_columns_bitwise(case, path, monkeypatch):
     import torch
 
     import paper_0911_5730_amd as P
-    if path not in ("two-level", "default"):
-        monkeypatch.setenv("BDDC_DEEP_PATH", path)
+    deep, _, coarse = path.partition("+")
+    if deep not in ("two-level", "default"):
+        monkeypatch.setenv("BDDC_DEEP_PATH", deep)
+    if coarse:
+        monkeypatch.setenv("BDDC_COARSE", coarse)
     prob = _case(case)
     F = _loads(prob, 11, 3)
     print(f"blocked rhs, case {case}, deep path {path}", flush=True)

@@ -114,6 +114,36 @@ def test_deep_level_paths(path, case, monkeypatch):
         S.close()
 
 
+@pytest.mark.parametrize("case,path", [("corners_kjump", "default"), ("adaptive2", "default"),
+                                       ("adaptive3", "wide"), ("adaptive3", "levels"),
+                                       ("voronoi_adaptive3", "wide")])
+def test_coarsest_inverse_path(case, path, monkeypatch):
+    """Large coarse spaces are solved with A_L^-1 formed at set-up by a block
+    Gauss-Jordan sweep over 64-wide pivot blocks (forced here on small ones).
+    The inverse carries an error of order cond(A_L) eps where the Cholesky
+    solve has one of order eps times a modest growth factor, so the
+    preconditioner apply is compared to 1e-10 instead of 1e-11 (the coarse
+    part of z is a fraction of it) and the solution and iteration counts to
+    the usual bars."""
+    monkeypatch.setenv("BDDC_COARSE", "inverse")
+    if path != "default":
+        monkeypatch.setenv("BDDC_DEEP_PATH", path)
+    prob = _case(case)
+    print(f"coarsest inverse, case {case}, deep path {path}", flush=True)
+    S, B, ug, it, rr, o = run_pair(prob)
+    try:
+        assert abs(it - o["iters"]) <= 1
+        rng = np.random.default_rng(8)
+        r = rng.standard_normal(prob.n_free)
+        zg = S.apply(cuda_vec(r)).cpu().numpy()
+        zo = B.apply(r)
+        assert np.linalg.norm(zg - zo) <= 1e-10 * np.linalg.norm(zo)
+        check_solution(S, B, ug, o)
+    finally:
+        S.close()
+
+
+
 def test_pcg_scalar_finalize(monkeypatch):
     """The PCG scalars (r.z, p^T S p, r.r) are summed either by every consuming
     block or once, by a one-block launch after the producing launch, in the
