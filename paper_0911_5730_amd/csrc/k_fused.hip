@@ -442,6 +442,31 @@ struct SymRowRegs {
     for (int j = c + K * nch; j < m; j += nch) acc += static_cast<double>(A[sym_index(i, j, m)]) * x[j];
     return acc;
   }
+  // dot for nl columns of x (stride ldx) at once: each entry of the row is
+  // loaded once for all of them; column k's sum is dot's, term by term
+  __device__ void dot_cols(const T* A, int m, int i, int c, int nch, const double* x, int ldx, int nl,
+                           double (&acc)[kMaxRhs]) const {
+#pragma unroll
+    for (int k = 0; k < kMaxRhs; ++k) acc[k] = 0.0;
+#pragma unroll
+    for (int kk = 0; kk < K; ++kk) {
+      const int j = c + kk * nch;
+      T r = v[kk];
+      __asm__ volatile("" : "+v"(r));
+      if (j < m) {
+        const double rd = static_cast<double>(r);
+#pragma unroll
+        for (int k = 0; k < kMaxRhs; ++k)
+          if (k < nl) acc[k] += rd * x[k * ldx + j];
+      }
+    }
+    for (int j = c + K * nch; j < m; j += nch) {
+      const double a = static_cast<double>(A[sym_index(i, j, m)]);
+#pragma unroll
+      for (int k = 0; k < kMaxRhs; ++k)
+        if (k < nl) acc[k] += a * x[k * ldx + j];
+    }
+  }
 };
 
 // Partial row sum over the columns c, c + nch, ... of row i of the symmetric
@@ -527,8 +552,17 @@ __global__ void __launch_bounds__(kNT) k_pcg_matvec(LevelDev L, PcgDev P, int u)
   }
   __syncthreads();
   if (narrow) {
-    if (act)
-      for (int k = 0; k < nl; ++k) part[k * psz + mi + mc * ng] = sv.dot(Sg, ng, mi, mc, nch, pl + k * ng);
+    if (act) {
+      if constexpr (kMulti) {
+        double acc[kMaxRhs];
+        sv.dot_cols(Sg, ng, mi, mc, nch, pl, ng, nl, acc);
+#pragma unroll
+        for (int k = 0; k < kMaxRhs; ++k)
+          if (k < nl) part[k * psz + mi + mc * ng] = acc[k];
+      } else {
+        part[mi + mc * ng] = sv.dot(Sg, ng, mi, mc, nch, pl);
+      }
+    }
   } else {
     for (int k = 0; k < nl; ++k)
       for (int i = tid; i < ng; i += kNT) part[k * psz + i] = sym_row_part(Sg, ng, i, 0, 1, pl + k * ng);
@@ -761,7 +795,38 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
   }
   if constexpr (kPrec == 2) pt.finish();
   __syncthreads();
-  // b = Psi^T g, one wave per coarse dof, every live column
+  // b = Psi^T g, one wave per coarse dof, every live column (several columns:
+  // each entry of Psi loaded once for all of them, the same sums per column)
+  if constexpr (kMulti) {
+    for (int kd = wave, m = 0; kd < ncs; kd += kNT / 64, ++m) {
+      double acc[kMaxRhs];
+#pragma unroll
+      for (int k = 0; k < kMaxRhs; ++k) acc[k] = 0.0;
+      auto term = [&](double pd, int a) {
+#pragma unroll
+        for (int k = 0; k < kMaxRhs; ++k)
+          if (k < nl) acc[k] += pd * g[k * ngmax + a];
+      };
+      if (m < kPV) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int a = lane + 64 * q;
+          if (a < ng) term(static_cast<double>(pv[m][q]), a);
+        }
+        for (int a = lane + 128; a < ng; a += 64) term(static_cast<double>(Pg[a + (size_t)kd * ng]), a);
+      } else {
+        for (int a = lane; a < ng; a += 64) term(static_cast<double>(Pg[a + (size_t)kd * ng]), a);
+      }
+#pragma unroll
+      for (int k = 0; k < kMaxRhs; ++k) {
+        if (k >= nl) break;
+        double v = acc[k];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+        if (lane == 0) P.b[(size_t)col(k) * P.ld_cflat + L.coff[s] + kd] = v;
+      }
+    }
+  } else
   for (int kd = wave, m = 0; kd < ncs; kd += kNT / 64, ++m) {
     for (int k = 0; k < nl; ++k) {
       const double* gk = g + k * ngmax;
@@ -833,8 +898,17 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
     }
   } else {
     if (narrow) {
-      if (act)
-        for (int k = 0; k < nl; ++k) part[k * psz + ti + tc * n_r] = tv.dot(Tg, n_r, ti, tc, nch, g + k * ngmax);
+      if (act) {
+        if constexpr (kMulti) {
+          double acc[kMaxRhs];
+          tv.dot_cols(Tg, n_r, ti, tc, nch, g, ngmax, nl, acc);
+#pragma unroll
+          for (int k = 0; k < kMaxRhs; ++k)
+            if (k < nl) part[k * psz + ti + tc * n_r] = acc[k];
+        } else {
+          part[ti + tc * n_r] = tv.dot(Tg, n_r, ti, tc, nch, g);
+        }
+      }
     } else {
       for (int k = 0; k < nl; ++k)
         for (int i = tid; i < n_r; i += kNT) {
@@ -1070,12 +1144,39 @@ __global__ void __launch_bounds__(kNT) k_pcg_prolong_post(LevelDev L, PcgDev P, 
   const int gi = (blockIdx.x * kNT + threadIdx.x) >> 3;
   const int sub = threadIdx.x & 7;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = kNT / 64;
-  for (int k = 0; k < ngo; ++k) {
-    const size_t ci = (size_t)gcol(k) * P.ld_if;
-    const double* da = P.da + (size_t)gcol(k) * P.ld_flat;
-    const double* uc = P.uc + (size_t)gcol(k) * P.ld_coarse;
-    double acc = 0.0;
+  // (several columns: the sharer and coarse-row entries are loaded once for
+  // all of them, each column's terms in the same order)
+  double accs[kMulti ? kMaxRhs : 1];
+  if constexpr (kMulti) {
+#pragma unroll
+    for (int k = 0; k < kMaxRhs; ++k) accs[k] = 0.0;
     if (gi < P.nif) {
+      const int k0 = L.sh_ptr[gi], k1 = L.sh_ptr[gi + 1];
+      for (int m = k0 + sub; m < k1; m += 8) {
+        const int fl = L.sh_flat[m];
+#pragma unroll
+        for (int k = 0; k < kMaxRhs; ++k)
+          if (k < ngo) accs[k] += P.da[(size_t)gcol(k) * P.ld_flat + fl];
+      }
+      for (int j = P.phi_ptr[gi] + sub; j < P.phi_ptr[gi + 1]; j += 8) {
+        const double w = P.phi_w[j];
+        const int id = P.phi_ids[j];
+#pragma unroll
+        for (int k = 0; k < kMaxRhs; ++k)
+          if (k < ngo) accs[k] += w * P.uc[(size_t)gcol(k) * P.ld_coarse + id];
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < (kMulti ? kMaxRhs : 1); ++k) {
+    if (k >= ngo) break;
+    const size_t ci = (size_t)gcol(k) * P.ld_if;
+    double acc = 0.0;
+    if constexpr (kMulti) {
+      acc = accs[k];
+    } else if (gi < P.nif) {
+      const double* da = P.da + (size_t)gcol(k) * P.ld_flat;
+      const double* uc = P.uc + (size_t)gcol(k) * P.ld_coarse;
       const int k0 = L.sh_ptr[gi], k1 = L.sh_ptr[gi + 1];
       for (int m = k0 + sub; m < k1; m += 8) acc += da[L.sh_flat[m]];
       for (int j = P.phi_ptr[gi] + sub; j < P.phi_ptr[gi + 1]; j += 8) acc += P.phi_w[j] * uc[P.phi_ids[j]];
