@@ -2274,11 +2274,16 @@ bddc_status bddc_setup(const bddc_problem* p, void* hip_stream, bddc_handle* out
     }
     const size_t nphi = (size_t)phi_ptr[nif];
     // packed lower triangles of S_s and T_rr
+    // (interfaces wider than 64 dofs: full matrices, so that the rows a
+    // workgroup reads are adjacent in memory for every column; their partial
+    // row sums no longer fit the registers of the packed form)
+    const char* oenv = getenv("BDDC_PCG_OPS");
+    P.full = oenv ? std::string(oenv) == "full" : l1.ngmax > 64;
     std::vector<int64_t> spoff(l1.nsub + 1, 0), tpoff(l1.nsub + 1, 0);
     for (int s = 0; s < l1.nsub; ++s) {
       const int64_t ng = l1.topo.ngam(s), nr = l1.topo.n_r[s];
-      spoff[s + 1] = spoff[s] + ng * (ng + 1) / 2;
-      tpoff[s + 1] = tpoff[s] + nr * (nr + 1) / 2;
+      spoff[s + 1] = spoff[s] + (P.full ? ng * ng : ng * (ng + 1) / 2);
+      tpoff[s + 1] = tpoff[s] + (P.full ? nr * nr : nr * (nr + 1) / 2);
     }
     // every sharer's flat entry of each flat entry's dof, padded to four
     bool fits4 = true;

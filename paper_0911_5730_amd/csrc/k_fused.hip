@@ -416,6 +416,11 @@ __device__ inline int sym_index(int i, int j, int m) {
   return i >= j ? packed_col(j, m) + (i - j) : packed_col(i, m) + (j - i);
 }
 
+// Entry (i, j) of a level-1 PCG operator: packed lower triangle, or (full)
+// the whole column-major matrix, where the entries (i, j) of consecutive rows
+// i are adjacent for every j
+__device__ inline int op_index(int i, int j, int m, bool full) { return full ? i + j * m : sym_index(i, j, m); }
+
 // Thread (i, c) of a row-partial product loads the entries (i, c + k nch),
 // k < K, of a packed symmetric operator into registers (unconditional loads at
 // clamped in-block addresses, so they issue back to back), and later forms its
@@ -423,12 +428,12 @@ __device__ inline int sym_index(int i, int j, int m) {
 template <int K, class T>
 struct SymRowRegs {
   T v[K];
-  __device__ void load(const T* A, int m, int i, int c, int nch) {
+  __device__ void load(const T* A, int m, int i, int c, int nch, bool full) {
     if (m <= 0) return;
 #pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = A[sym_index(i, min(c + k * nch, m - 1), m)];
+    for (int k = 0; k < K; ++k) v[k] = A[op_index(i, min(c + k * nch, m - 1), m, full)];
   }
-  __device__ double dot(const T* A, int m, int i, int c, int nch, const double* x) const {
+  __device__ double dot(const T* A, int m, int i, int c, int nch, const double* x, bool full) const {
     double acc = 0.0;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -439,12 +444,20 @@ struct SymRowRegs {
       __asm__ volatile("" : "+v"(r));
       if (j < m) acc += static_cast<double>(r) * x[j];
     }
-    for (int j = c + K * nch; j < m; j += nch) acc += static_cast<double>(A[sym_index(i, j, m)]) * x[j];
+    // the entries past the registers in batches of 8 loads in flight
+    for (int j0 = c + K * nch; j0 < m; j0 += 8 * nch) {
+      T t[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) t[q] = A[op_index(i, min(j0 + q * nch, m - 1), m, full)];
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (j0 + q * nch < m) acc += static_cast<double>(t[q]) * x[j0 + q * nch];
+    }
     return acc;
   }
   // dot for nl columns of x (stride ldx) at once: each entry of the row is
   // loaded once for all of them; column k's sum is dot's, term by term
-  __device__ void dot_cols(const T* A, int m, int i, int c, int nch, const double* x, int ldx, int nl,
+  __device__ void dot_cols(const T* A, int m, int i, int c, int nch, const double* x, int ldx, int nl, bool full,
                            double (&acc)[kMaxRhs]) const {
 #pragma unroll
     for (int k = 0; k < kMaxRhs; ++k) acc[k] = 0.0;
@@ -460,20 +473,33 @@ struct SymRowRegs {
           if (k < nl) acc[k] += rd * x[k * ldx + j];
       }
     }
-    for (int j = c + K * nch; j < m; j += nch) {
-      const double a = static_cast<double>(A[sym_index(i, j, m)]);
+    for (int j0 = c + K * nch; j0 < m; j0 += 8 * nch) {
+      T t[8];
 #pragma unroll
-      for (int k = 0; k < kMaxRhs; ++k)
-        if (k < nl) acc[k] += a * x[k * ldx + j];
+      for (int q = 0; q < 8; ++q) t[q] = A[op_index(i, min(j0 + q * nch, m - 1), m, full)];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int j = j0 + q * nch;
+        if (j < m) {
+          const double a = static_cast<double>(t[q]);
+#pragma unroll
+          for (int k = 0; k < kMaxRhs; ++k)
+            if (k < nl) acc[k] += a * x[k * ldx + j];
+        }
+      }
     }
   }
 };
 
 // Partial row sum over the columns c, c + nch, ... of row i of the symmetric
 // m x m matrix held as its packed lower triangle A (column-major), times x.
-__device__ inline double sym_row_part(const double* A, int m, int i, int c, int nch, const double* x) {
+__device__ inline double sym_row_part(const double* A, int m, int i, int c, int nch, const double* x, bool full) {
   double acc = 0.0;
   int j = c;
+  if (full) {
+    for (; j < m; j += nch) acc += A[i + (size_t)j * m] * x[j];
+    return acc;
+  }
   for (; j <= i; j += nch) acc += A[packed_col(j, m) + (i - j)] * x[j];
   const double* Ai = A + packed_col(i, m) - i;   // row i, columns j > i
   for (; j < m; j += nch) acc += Ai[j] * x[j];
@@ -507,7 +533,7 @@ __global__ void __launch_bounds__(kNT) k_pcg_matvec(LevelDev L, PcgDev P, int u)
   const int mc = narrow && ng > 0 ? tid / ng : nch;
   const bool act = narrow && mc < nch;
   SymRowRegs<16, double> sv;
-  if (narrow) sv.load(Sg, ng, mi, mc, nch);
+  if (narrow) sv.load(Sg, ng, mi, mc, nch, P.full);
   // the live columns and their beta: every thread reads the flags and scalars
   // (uniform loads, before this launch stores anything, so they take the
   // scalar path and do not wait for the operator loads above) and writes the
@@ -555,17 +581,17 @@ __global__ void __launch_bounds__(kNT) k_pcg_matvec(LevelDev L, PcgDev P, int u)
     if (act) {
       if constexpr (kMulti) {
         double acc[kMaxRhs];
-        sv.dot_cols(Sg, ng, mi, mc, nch, pl, ng, nl, acc);
+        sv.dot_cols(Sg, ng, mi, mc, nch, pl, ng, nl, P.full, acc);
 #pragma unroll
         for (int k = 0; k < kMaxRhs; ++k)
           if (k < nl) part[k * psz + mi + mc * ng] = acc[k];
       } else {
-        part[mi + mc * ng] = sv.dot(Sg, ng, mi, mc, nch, pl);
+        part[mi + mc * ng] = sv.dot(Sg, ng, mi, mc, nch, pl, P.full);
       }
     }
   } else {
     for (int k = 0; k < nl; ++k)
-      for (int i = tid; i < ng; i += kNT) part[k * psz + i] = sym_row_part(Sg, ng, i, 0, 1, pl + k * ng);
+      for (int i = tid; i < ng; i += kNT) part[k * psz + i] = sym_row_part(Sg, ng, i, 0, 1, pl + k * ng, P.full);
   }
   __syncthreads();
   // the local products and energies p_s^T S_s p_s, in column slots
@@ -666,7 +692,7 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
   const bool act = narrow && tc < nch;
   SymRowRegs<16, TS> tv;
   if constexpr (kPrec != 2)
-    if (narrow) tv.load(Tg, n_r, ti, tc, nch);   // every thread: no divergent region to merge
+    if (narrow) tv.load(Tg, n_r, ti, tc, nch, P.full);   // every thread: no divergent region to merge
   Prefetch<8, uint16_t, float> pt;
   if constexpr (kPrec == 2) pt.fetch(P.W16 + L.toff[s], reinterpret_cast<float*>(Tl), ntri);
   // (the loads are unconditional, at clamped in-block addresses, so that
@@ -901,19 +927,19 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
       if (act) {
         if constexpr (kMulti) {
           double acc[kMaxRhs];
-          tv.dot_cols(Tg, n_r, ti, tc, nch, g, ngmax, nl, acc);
+          tv.dot_cols(Tg, n_r, ti, tc, nch, g, ngmax, nl, P.full, acc);
 #pragma unroll
           for (int k = 0; k < kMaxRhs; ++k)
             if (k < nl) part[k * psz + ti + tc * n_r] = acc[k];
         } else {
-          part[ti + tc * n_r] = tv.dot(Tg, n_r, ti, tc, nch, g);
+          part[ti + tc * n_r] = tv.dot(Tg, n_r, ti, tc, nch, g, P.full);
         }
       }
     } else {
       for (int k = 0; k < nl; ++k)
         for (int i = tid; i < n_r; i += kNT) {
           double acc = 0.0;
-          for (int j = 0; j < n_r; ++j) acc += static_cast<double>(Tg[sym_index(i, j, n_r)]) * g[k * ngmax + j];
+          for (int j = 0; j < n_r; ++j) acc += static_cast<double>(Tg[op_index(i, j, n_r, P.full)]) * g[k * ngmax + j];
           part[k * psz + i] = acc;
         }
     }
@@ -1046,12 +1072,12 @@ __global__ void __launch_bounds__(kNT) k_pack_pcg(LevelDev L, PcgDev P) {
   const double* S = L.K + L.koff[s] + nI + (size_t)nI * n;
   double* Sp = const_cast<double*>(P.Sp) + P.spoff[s];
   for (ColWalk w_(threadIdx.x, kNT, ng); w_.j < ng; w_.next())
-    if (w_.i >= w_.j) Sp[packed_col(w_.j, ng) + (w_.i - w_.j)] = S[w_.i + (size_t)w_.j * n];
+    if (P.full || w_.i >= w_.j) Sp[op_index(w_.i, w_.j, ng, P.full)] = S[w_.i + (size_t)w_.j * n];
   if (P.prec == 2) return;
   const double* T = L.T + L.toff[s];
   for (ColWalk w_(threadIdx.x, kNT, n_r); w_.j < n_r; w_.next()) {
-    if (w_.i < w_.j) continue;
-    const int k = packed_col(w_.j, n_r) + (w_.i - w_.j);
+    if (!P.full && w_.i < w_.j) continue;
+    const int k = op_index(w_.i, w_.j, n_r, P.full);
     const double v = T[w_.i + (size_t)w_.j * n_r];
     if (P.prec == 0) const_cast<double*>(P.Tp)[P.tpoff[s] + k] = v;
     else const_cast<float*>(P.Tp32)[P.tpoff[s] + k] = static_cast<float>(v);

@@ -212,6 +212,7 @@ struct PcgDev {
   // FP64 (reduced storage, FP64 arithmetic); every vector stays FP64.
   int prec = 0;
   const double* Sp = nullptr;       // S_s, packed lower triangle (column-major), offsets spoff
+  int full = 0;                     // S_s and T_rr held as full column-major matrices instead (wide interfaces)
   const int64_t* spoff = nullptr;
   const double* Tp = nullptr;       // FP64 form: T_rr packed lower triangle, offsets tpoff
   const float* Tp32 = nullptr;      // FP32 form: T_rr packed lower triangle, offsets tpoff

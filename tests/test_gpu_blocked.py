@@ -81,6 +81,26 @@ def test_blocked_columns_equal_single_columns_bitwise(case, path, monkeypatch):
         assert its8 == its[3:] and torch.equal(U8, U[3:])
 
 
+@pytest.mark.parametrize("case,ops,prec", [("adaptive3_h16", "full", "fp64"), ("adaptive3_h16", "full", "fp32"),
+                                           ("voronoi_jitter3", "packed", "fp32")])
+def test_blocked_pcg_operator_storage(case, ops, prec, monkeypatch):
+    """S_s and T_rr as packed lower triangles or as full matrices (wide
+    interfaces use the full form): blocked columns bitwise equal to single
+    ones in either form."""
+    import torch
+
+    import paper_0911_5730_amd as P
+    monkeypatch.setenv("BDDC_PCG_OPS", ops)
+    prob = _case(case)
+    F = _loads(prob, 5, 4)
+    print(f"operator storage {ops}, case {case}, {prec}", flush=True)
+    with P.Solver(prob, precision=prec) as S:
+        U, its, _ = S.solve(cuda_vec(F), rtol=1e-10)
+        Ua, itsa = _alone(S, F, monkeypatch, rtol=1e-10)
+        assert its == itsa
+        assert torch.equal(U, Ua)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
 @pytest.mark.parametrize("fin", ["0", "1"])
 def test_blocked_precision_forms_and_partial_sums(prec, fin, monkeypatch):

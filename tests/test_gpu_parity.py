@@ -203,7 +203,8 @@ def test_pcg_graph_replays_match_direct_launches(deep, monkeypatch):
         S.close()
 
 
-@pytest.mark.parametrize("path", ["default", "lds16_global", "sweep32", "eig_workgroup", "pair_global"])
+@pytest.mark.parametrize("path", ["default", "lds16_global", "sweep32", "eig_workgroup", "pair_global",
+                                  "pcg_ops_full"])
 def test_setup_kernel_paths(path, monkeypatch):
     """The setup runs with 64-wide Cholesky panels and a matrix-core trailing
     update plus LDS-resident Gauss-Jordan factorizations, and the level-1
@@ -213,8 +214,10 @@ def test_setup_kernel_paths(path, monkeypatch):
     The pair eigenproblems run one wave per edge (default) or one
     256-thread workgroup per edge; the pair Schur complements and
     eigenproblems work in LDS (default) or in a global workspace (used for
-    interfaces and edges too large for LDS).  Both must give the oracle's preconditioner and solution (H/h = 16,
-    ragged 64-column panels)."""
+    interfaces and edges too large for LDS).  The PCG operators S_s and T_rr
+    are packed lower triangles (default here) or full matrices (the form of
+    interfaces wider than 64 dofs).  All must give the oracle's
+    preconditioner and solution (H/h = 16, ragged 64-column panels)."""
     if path == "lds16_global":
         monkeypatch.setenv("BDDC_CHOL_PATH", "lds16")
         monkeypatch.setenv("BDDC_SETUP_PATH", "global")
@@ -225,6 +228,8 @@ def test_setup_kernel_paths(path, monkeypatch):
         monkeypatch.setenv("BDDC_EIG_PATH", "wg")
     if path == "pair_global":
         monkeypatch.setenv("BDDC_PAIR_WS", "global")
+    if path == "pcg_ops_full":
+        monkeypatch.setenv("BDDC_PCG_OPS", "full")
     prob = _case("adaptive3_h16")
     print(f"setup kernel path {path}", flush=True)
     S, B, ug, it, rr, o = run_pair(prob)
