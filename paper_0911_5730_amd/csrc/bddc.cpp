@@ -1619,7 +1619,7 @@ static bool plan_wide(bddc_ctx* h) {
   // the coarsest solve and the level-2 interface live in one workgroup's LDS
   if ((!h->coarse_inv && sizeof(double) * (size_t)lv.nc > kLdsLimit) ||
       sizeof(double) * ((size_t)lv.ngmax + kNT) > kLdsLimit ||
-      sizeof(double) * (size_t)lv.nImax > kLdsLimit)
+      sizeof(double) * (size_t)lv.nImax * kMaxRhs > kLdsMax)
     return false;
   std::vector<int32_t> sub_of_flat(lv.nflat_g);
   for (int s = 0; s < nsub; ++s)

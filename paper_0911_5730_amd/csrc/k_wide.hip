@@ -24,16 +24,20 @@ __device__ inline double wide_r2(const WideDev& W, const double* b1, int k) {
   return acc;
 }
 
-// grid (chunks, substructures, columns): rows [chunk*rows1, ...) of [K_II^-1 ; M]
+// grid (chunks, substructures, column groups): rows [chunk*rows1, ...) of
+// [K_II^-1 ; M] applied to the cols1 columns of the group (each operator row
+// read once for all of them; a column's sums are those of a one-column launch)
 __global__ void __launch_bounds__(kNT) k_wide_pre(WideDev W) {
   extern __shared__ double sh[];
   if (W.stop && *W.stop) return;
   const LevelDev& L = W.L;
-  const int s = blockIdx.y, chunk = blockIdx.x, col = blockIdx.z;
-  const double* b1 = W.b1 + (size_t)col * W.ld_b1;
-  double* r2 = W.r2 + (size_t)col * W.ld_r2;
-  double* Ly = L.y + (size_t)col * W.ld_i;
-  double* Lt = L.t + (size_t)col * W.ld_g;
+  const int s = blockIdx.y, chunk = blockIdx.x;
+  const int cb = blockIdx.z * W.cols1;            // first column of the group
+  const int R = min(W.cols1, W.nrhs - cb);
+  const double* b1 = W.b1 + (size_t)cb * W.ld_b1;
+  double* r2 = W.r2 + (size_t)cb * W.ld_r2;
+  double* Ly = L.y + (size_t)cb * W.ld_i;
+  double* Lt = L.t + (size_t)cb * W.ld_g;
   const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
   const int nI = L.nint[s];
   const int ng = n - nI;
@@ -41,17 +45,19 @@ __global__ void __launch_bounds__(kNT) k_wide_pre(WideDev W) {
   if (r0 >= n) return;
   const int r1 = min(n, r0 + W.rows1);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  double* rI = sh;
-  for (int i = tid; i < nI; i += kNT) {
+  double* rI = sh;   // column c at rI + c nI
+  for (int idx = tid; idx < R * nI; idx += kNT) {
+    const int c = idx / nI, i = idx - c * nI;
     const int k = L.int_gid[L.ioff[s] + i];
-    const double v = wide_r2(W, b1, k);
-    rI[i] = v;
-    if (chunk == 0) r2[k] = v;
+    const double v = wide_r2(W, b1 + (size_t)c * W.ld_b1, k);
+    rI[idx] = v;
+    if (chunk == 0) r2[(size_t)c * W.ld_r2 + k] = v;
   }
   if (chunk == 0)
-    for (int a = tid; a < ng; a += kNT) {
+    for (int idx = tid; idx < R * ng; idx += kNT) {
+      const int c = idx / ng, a = idx - c * ng;
       const int k = L.gam_gid[L.goff[s] + a];
-      r2[k] = wide_r2(W, b1, k);   // every sharer stores the same value
+      r2[(size_t)c * W.ld_r2 + k] = wide_r2(W, b1 + (size_t)c * W.ld_b1, k);   // every sharer stores the same value
     }
   __syncthreads();
   const double* Ki = W.Kinv + W.kioff[s];
@@ -60,22 +66,40 @@ __global__ void __launch_bounds__(kNT) k_wide_pre(WideDev W) {
   // column rho - nI of M^T (row of M): both contiguous
   for (int rho = r0 + wave; rho < r1; rho += kNT / 64) {
     const double* col = rho < nI ? Ki + (size_t)rho * nI : Mt + (size_t)(rho - nI) * nI;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    double acc[kMaxRhs][4];
+#pragma unroll
+    for (int c = 0; c < kMaxRhs; ++c) acc[c][0] = acc[c][1] = acc[c][2] = acc[c][3] = 0.0;
     int j = lane;
     for (; j + 192 < nI; j += 256) {
       const double c0 = col[j], c1 = col[j + 64], c2 = col[j + 128], c3 = col[j + 192];
-      acc[0] += c0 * rI[j];
-      acc[1] += c1 * rI[j + 64];
-      acc[2] += c2 * rI[j + 128];
-      acc[3] += c3 * rI[j + 192];
-    }
-    for (; j < nI; j += 64) acc[0] += col[j] * rI[j];
-    double v = (acc[0] + acc[1]) + (acc[2] + acc[3]);
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    if (lane == 0) {
-      if (rho < nI) Ly[L.ioff[s] + rho] = v;
-      else Lt[L.goff[s] + rho - nI] = v;
+      for (int c = 0; c < kMaxRhs; ++c) {
+        if (c >= R) break;
+        const double* x = rI + c * nI;
+        acc[c][0] += c0 * x[j];
+        acc[c][1] += c1 * x[j + 64];
+        acc[c][2] += c2 * x[j + 128];
+        acc[c][3] += c3 * x[j + 192];
+      }
+    }
+    for (; j < nI; j += 64) {
+      const double c0 = col[j];
+#pragma unroll
+      for (int c = 0; c < kMaxRhs; ++c) {
+        if (c >= R) break;
+        acc[c][0] += c0 * rI[c * nI + j];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < kMaxRhs; ++c) {
+      if (c >= R) break;
+      double v = (acc[c][0] + acc[c][1]) + (acc[c][2] + acc[c][3]);
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+      if (lane == 0) {
+        if (rho < nI) Ly[(size_t)c * W.ld_i + L.ioff[s] + rho] = v;
+        else Lt[(size_t)c * W.ld_g + L.goff[s] + rho - nI] = v;
+      }
     }
   }
 }
@@ -209,8 +233,22 @@ void launch_wide_ops(hipStream_t st, const LevelDev& L, int nmax_ops, double* Ki
 }
 
 void launch_wide_pre(hipStream_t st, const WideDev& W) {
-  launch_kernel(k_wide_pre, dim3(W.nchunk1, W.L.nsub, W.nrhs), dim3(kNT), sizeof(double) * (size_t)max(W.nImax, 1), st,
-                W);
+  if (W.nrhs < 1 || W.nrhs > kMaxRhs) throw std::invalid_argument("launch_wide_pre: bad column count");
+  // several columns: a small grid (< 1024 workgroups per column) keeps one
+  // grid slice per column; a large one takes every column in each workgroup,
+  // with up to four times the rows while the grid keeps >= 1024 workgroups,
+  // so fewer workgroups gather the same r_I
+  WideDev V = W;
+  const int wgs = W.nchunk1 * W.L.nsub;
+  V.cols1 = wgs < 1024 ? 1 : W.nrhs;
+  if (V.cols1 > 1) {
+    const int f = std::min(4, std::max(1, wgs / 1024));
+    V.rows1 = W.rows1 * f;
+    V.nchunk1 = (W.nchunk1 + f - 1) / f;
+  }
+  const int groups = (W.nrhs + V.cols1 - 1) / V.cols1;
+  launch_kernel(k_wide_pre, dim3(V.nchunk1, V.L.nsub, groups), dim3(kNT),
+                sizeof(double) * (size_t)V.cols1 * max(V.nImax, 1), st, V);
 }
 
 void launch_wide_coarse(hipStream_t st, const WideDev& W) {

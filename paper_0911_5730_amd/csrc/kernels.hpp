@@ -169,6 +169,7 @@ struct WideDev {
   // (L.y interior flat, L.t / L.a / L.v interface flat, L.b coarse flat)
   // hold nrhs columns at these strides
   int nrhs = 1;
+  int cols1 = 1;                      // columns per workgroup of the pre kernel (set at its launch)
   int ld_b1 = 0, ld_r2 = 0, ld_u2 = 0, ld_i = 0, ld_g = 0, ld_c = 0;
 };
 void launch_wide_ops(hipStream_t st, const LevelDev& L, int nmax_ops, double* Kinv, const int64_t* kioff, double* Mt,
