@@ -385,9 +385,14 @@ def test_adaptive_setup_meets_target():
     B = BDDC(p)
     assert all(w <= tau for w in B.omega_levels)
     assert B.indicator <= tau ** (p.levels - 1)
-    # the coarse dofs actually installed on each edge bring the pair bound down to tau
+    # the coarse dofs actually installed on each edge bring the pair bound down
+    # to tau, and the level's omega is the largest pair bound left once every
+    # edge carries its installed constraints (Theorem "adaptive": the largest
+    # eigenvalue of the augmented pair problem is the first unselected one),
+    # computed here from the augmented pencils, not from the selection's lists
     added = 0
     for li, lv in enumerate(B.levels):
+        om_aug = 0.0
         for (s, t), E in lv.topo.edges.items():
             rows = [w for d, w in lv.func if len(d) == len(E) and np.array_equal(d, E)]
             lam0 = adaptive.pair_eig_full(lv, s, t)[0][:len(E)]
@@ -395,7 +400,10 @@ def test_adaptive_setup_meets_target():
             added += len(rows)
             lam1 = adaptive.pair_eig_full(lv, s, t, extra_rows=rows)[0]
             assert lam1[0] <= tau * (1 + 1e-9)
+            om_aug = max(om_aug, float(lam1[0]))
+        assert abs(B.omega_levels[li] - om_aug) <= 1e-8 * max(1.0, om_aug), (li, B.omega_levels[li], om_aug)
     assert added > 0
+    assert abs(B.indicator - np.prod(B.omega_levels)) <= 1e-14 * B.indicator
     ev = _dense_MA_eigs(B)
     om = [_brute_omega(lv) for lv in B.levels]
     assert ev[-1] <= np.prod(om) * (1 + 1e-10)
