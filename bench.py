@@ -1,17 +1,20 @@
 #!/usr/bin/env python3
 """Throughput of adaptive-multilevel BDDC PCG solves on one MI355X.
 
-Workload (default): Q1 diffusion on a 256 x 256 grid, 16 x 16 substructures
-(H/h = 16), three levels with 4 x 4 groups, k = 10^U(0,6) per element plus 8
-channels of k = 1e6, adaptive coarse dofs with tau = 10, f ~ U[-1, 1],
-PCG to relative residual 1e-8, FP64 throughout.
+Workload (default): Q1 diffusion on a 1024 x 1024 grid (1,046,529 unknowns),
+64 x 64 substructures (H/h = 16), three levels with 16 x 16 groups, k = 1,
+adaptive coarse dofs with tau = 10, f ~ U[-1, 1], PCG to relative residual
+1e-8.
 
-One step is the whole hot path on one synthetic input: bddc_setup (local
-matrices, weights, interior elimination, per-edge eigenproblems, constrained
-factors, next level, coarsest factor), bddc_solve (PCG on the level-1
-interface with the three-level preconditioner, interior recovery) and
-bddc_destroy.  Coefficients and load are resident in HBM before timing; the
-partition (integer topology input) is read on the host.
+One step is one bddc_solve of the load with a set-up preconditioner: PCG on
+the level-1 interface with the three-level preconditioner (substructure
+corrections, stiffness-scaled averaging, the level-2 problem and the
+coarsest solve every iteration) and the interior recovery.  The timed steps
+run the mixed form (level-1 preconditioner operators stored in FP32, FP64
+outer PCG); the FP64 path is timed beside it on the same load, and the
+set-up (local matrices, interior elimination, per-edge eigenproblems,
+constrained factors, next level, coarsest factor) is timed separately.
+Coefficients and load are resident in HBM before timing.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -61,43 +64,6 @@ def measured_traffic(kernel: str, workload: str):
     if not ent or ent.get("source_hash") != kernel_source_hash():
         return None
     return ent.get("bytes_per_launch")
-
-
-def cpu_baseline(prob_full):
-    """The oracle on a bounded sample of the same workload: the lower-left
-    quarter of the 256 x 256 coefficient field (128 x 128 elements, 8 x 8
-    substructures with H/h = 16, three levels with 2 x 2 groups, tau = 10),
-    set up and solved to 1e-8; scaled by the substructure count (x4) to one
-    full solve."""
-    import numpy as np
-
-    import synth
-    from oracle import pcg
-    from oracle.bddc import BDDC
-
-    nx = prob_full.nx // 2
-    k = prob_full.coeff.reshape(prob_full.ny, prob_full.nx)[:nx, :nx].reshape(-1).copy()
-    sample = synth.square_problem(nx, 8, levels=3, groups=(2, 2), constraints="adaptive", tau=prob_full.tau,
-                                  seed=2000)
-    sample.coeff = k
-    threads = 1
-    try:
-        from threadpoolctl import threadpool_info
-        info = threadpool_info()
-        if info:
-            threads = max(int(p.get("num_threads", 1)) for p in info)
-    except Exception:
-        pass
-    t0 = time.perf_counter()
-    B = BDDC(sample)
-    out = pcg.solve(B, sample.f[0], rtol=prob_full.rtol)
-    t = time.perf_counter() - t0
-    scale = prob_full.nsub / sample.nsub
-    return {"value": 1.0 / (t * scale), "unit": "solves/s", "cores": threads, "kind": "oracle",
-            "sample": f"oracle setup+PCG on the 128x128 lower-left quarter of the workload's coefficient "
-                      f"field (64 substructures, 3 levels, tau=10): {t:.2f} s, {out['iters']} iterations; "
-                      f"scaled x{scale:g} by substructure count to one full solve",
-            "host_cpus": len(os.sched_getaffinity(0))}
 
 
 def precision_forms(P, synth, torch, cid: int, stream, precs=("fp64", "fp32", "bf16")) -> dict:
@@ -253,38 +219,6 @@ def batching_form(P, synth, torch, stream, precision: str = "fp32") -> dict:
     return out
 
 
-def concurrent_steps(P, prob, coeff, f, torch, nsteps: int, nstreams: int = 2) -> float:
-    """Whole steps (set-up, solve, destroy) of independent problems issued from
-    `nstreams` host threads, each with a stream and handles of its own, so one
-    problem's host set-up work overlaps another's kernels.  Returns steps/s."""
-    import threading
-    streams = [torch.cuda.Stream() for _ in range(nstreams)]
-    outs = [torch.empty_like(f) for _ in range(nstreams)]
-    errors = []
-
-    def worker(k):
-        try:
-            for _ in range(k, nsteps, nstreams):
-                S = P.Solver(prob, coeff=coeff, stream=streams[k])
-                S.solve(f, u=outs[k], rtol=prob.rtol, stream=streams[k])
-                S.close()
-        except Exception as e:  # reported after the join
-            errors.append(e)
-
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    th = [threading.Thread(target=worker, args=(k,)) for k in range(nstreams)]
-    for t in th:
-        t.start()
-    for t in th:
-        t.join()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    if errors:
-        raise errors[0]
-    return nsteps / (t1 - t0)
-
-
 def serving(synth, count: int = 40, rate: float = 200.0, slots: int = 2, precision: str = "fp32",
             problems=None, resident: bool = False) -> dict:
     """A seeded Poisson stream of requests (grid side 128 or 256, H/h 8 or 16,
@@ -316,16 +250,108 @@ def serving(synth, count: int = 40, rate: float = 200.0, slots: int = 2, precisi
     return st
 
 
+# kernels whose launches may dominate a PCG iteration (timed in a pre-pass;
+# the one with the largest share is timed in the timed region)
+ROOFLINE_CANDIDATES = ("schur_local", "apply_restrict", "apply_average", "deep", "wide_pre", "wide_restrict",
+                       "wide_coarse", "wide_post")
+
+
+def solve_rate(S, f, u, stream, torch, steps, rtol):
+    """`steps` bddc_solve calls of one load on a set-up handle: solves/s and
+    the per-solve wall times (each call synchronises its stream)."""
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = None
+    for _ in range(steps):
+        ts = time.perf_counter()
+        _, its, _ = S.solve(f, u=u, rtol=rtol, stream=stream)
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    return steps / (time.perf_counter() - t0), lat, its
+
+
+def dominant_kernel(P, S, f, u, stream, rtol):
+    """The library kernel with the largest summed time over one solve."""
+    best, best_ms, shares = None, -1.0, {}
+    for name in ROOFLINE_CANDIDATES:
+        P.timing_start(name, 1)
+        S.solve(f, u=u, rtol=rtol, stream=stream)
+        tm = P.timing_stop()
+        shares[name] = tm["ms"]
+        if tm["launches"] and tm["ms"] > best_ms:
+            best, best_ms = name, tm["ms"]
+    return best, shares
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(gpu_rates: dict) -> dict:
+    """The oracle timed on this host: the full config-2 problem (256 x 256,
+    65,025 unknowns, three levels, adaptive tau = 10), set up and solved to
+    1e-8 with every BLAS thread, and config 1 with every thread and with one.
+    Configs 3 and 4 are not run (the oracle's set-up alone takes tens of
+    minutes there) and are reported as not completed."""
+    import synth
+    from oracle import pcg
+    from oracle.bddc import BDDC
+    threads = 1
+    limiter = None
+    try:
+        from threadpoolctl import threadpool_info, threadpool_limits
+        info = threadpool_info()
+        if info:
+            threads = max(int(p.get("num_threads", 1)) for p in info)
+        limiter = threadpool_limits
+    except Exception:
+        pass
+
+    def run(cid):
+        prob = synth.config(cid)
+        t0 = time.perf_counter()
+        B = BDDC(prob)
+        t1 = time.perf_counter()
+        out = pcg.solve(B, prob.f[0], rtol=prob.rtol)
+        t2 = time.perf_counter()
+        return {"setup_s": t1 - t0, "solve_s": t2 - t1, "total_s": t2 - t0, "iterations": out["iters"],
+                "solves_per_s": 1.0 / (t2 - t0), "solve_only_per_s": 1.0 / (t2 - t1)}
+
+    c2 = run(2)
+    c1 = run(1)
+    c1_1t = None
+    if limiter is not None:
+        with limiter(limits=1):
+            c1_1t = run(1)
+    return {"value": c2["solves_per_s"], "unit": "solves/s", "cores": threads, "kind": "oracle",
+            "sample": f"the full config-2 problem (256x256 Q1, 65,025 unknowns, 16x16 substructures, 3 levels, "
+                      f"adaptive tau=10): oracle set-up {c2['setup_s']:.1f} s + PCG {c2['solve_s']:.1f} s "
+                      f"({c2['iterations']} iterations), no scaling; configs 3 and 4 not completed (oracle "
+                      f"set-up beyond the bench's time budget)",
+            "cpu_model": cpu_model(), "host_cpus": len(os.sched_getaffinity(0)), "blas_threads": threads,
+            "config2": c2, "config1": c1, "config1_one_thread": c1_1t,
+            "config3": "not completed", "config4": "not completed",
+            "gpu_config2_fp64_solves_per_s": gpu_rates.get("config2_fp64"),
+            "gpu_config2_setup_plus_solve_per_s": gpu_rates.get("config2_step")}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", type=int, default=2)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"],
-                    help="storage of the level-1 preconditioner operators in the timed steps")
-    ap.add_argument("--roofline-kernel", default="deep",
-                    help="library kernel timed for the roofline (default: the one with the largest share of a step)")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=3)
+    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "bf16"],
+                    help="precision form of the timed solves (the FP64 path is timed beside it)")
+    ap.add_argument("--roofline-kernel", default="auto",
+                    help="library kernel timed for the roofline (auto: the one with the largest share of a solve)")
     ap.add_argument("--sample-every", type=int, default=8,
                     help="time one in this many launches of the roofline kernel")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -334,7 +360,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="skip the autotuner measurement")
     ap.add_argument("--no-batching", action="store_true", help="skip the config-4 (uneven substructures) measurement")
     ap.add_argument("--no-precision-forms", action="store_true",
-                    help="skip the FP64 / FP32 / BF16 comparison on configs 2 and 3")
+                    help="skip the FP64 / FP32 / BF16 comparison on config 2")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 256 MiB device buffer three times (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -365,64 +391,68 @@ def main():
     f = torch.tensor(prob.f[0], dtype=torch.float64, device="cuda")
     u = torch.empty_like(f)
     stream = torch.cuda.current_stream()
+    log(f"bench: config {args.config} ({synth.CONFIG_NAMES[args.config]}), {args.precision} against fp64")
 
-    def step():
-        S = P.Solver(prob, coeff=coeff, stream=stream, precision=args.precision)
-        _, it, rr = S.solve(f, u=u, rtol=prob.rtol, stream=stream)
-        info = S.info()
-        S.close()
-        return it[0], rr[0], info
+    def setup(prec):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S = P.Solver(prob, coeff=coeff, stream=stream, precision=prec)
+        torch.cuda.synchronize()
+        return S, time.perf_counter() - t0
 
-    log(f"bench: config {args.config} ({synth.CONFIG_NAMES[args.config]}), warmup {args.warmup}")
+    P.Solver(prob, coeff=coeff, stream=stream, precision=args.precision).close()   # first use of the sizes
+    S, setup_s = setup(args.precision)
+    S64, setup64_s = setup("fp64")
     for _ in range(args.warmup):
-        step()
+        S.solve(f, u=u, rtol=prob.rtol, stream=stream)
+        S64.solve(f, u=u, rtol=prob.rtol, stream=stream)
     torch.cuda.synchronize()
+    kernel = args.roofline_kernel
+    shares = None
+    if kernel == "auto":
+        kernel, shares = dominant_kernel(P, S, f, u, stream, prob.rtol)
+        log(f"bench: kernel time per solve (ms): " + ", ".join(f"{k} {v:.3f}" for k, v in shares.items() if v))
 
-    # ---- timed region: K whole steps
-    P.timing_start(args.roofline_kernel, args.sample_every)
-    lat = []
-    iters = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ts = time.perf_counter()
-        it, rr, info = step()
-        lat.append(time.perf_counter() - ts)
-        iters.append(it)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    # ---- timed region: K solves of the load with the set-up preconditioner
+    P.timing_start(kernel, args.sample_every)
+    rate, lat, its = solve_rate(S, f, u, stream, torch, args.steps, prob.rtol)
     tm = P.timing_stop()
-    elapsed = t1 - t0
-    log(f"bench: {args.steps} steps in {elapsed:.3f} s, iterations {iters[0]}, relres {rr:.2e}")
+    elapsed = args.steps / rate
+    info = S.info()
+    log(f"bench: {args.steps} {args.precision} solves in {elapsed:.4f} s ({rate:.1f}/s), {its[0]} iterations")
 
-    # ---- solve-only, apply-only and setup-only rates (outside the timed region)
-    S = P.Solver(prob, coeff=coeff, stream=stream, precision=args.precision)
-    S.solve(f, u=u)
-    torch.cuda.synchronize()
-    ns = max(5, args.steps)
-    s0 = time.perf_counter()
-    for _ in range(ns):
-        S.solve(f, u=u)
-    torch.cuda.synchronize()
-    solve_s = (time.perf_counter() - s0) / ns
+    # ---- the FP64 path on the same load (outside the timed region)
+    rate64, lat64, its64 = solve_rate(S64, f, u, stream, torch, args.steps, prob.rtol)
+    log(f"bench: fp64 {rate64:.1f} solves/s, {its64[0]} iterations; {args.precision}/fp64 = {rate / rate64:.3f}")
     # the full-space preconditioner z = M^-1 r (bddc_apply) on one vector
     z = torch.empty_like(f)
     S.apply(f, z, stream=stream)
     torch.cuda.synchronize()
-    na = 20 * ns
+    na = max(20, 4 * args.steps)
     a0 = time.perf_counter()
     for _ in range(na):
         S.apply(f, z, stream=stream)
     torch.cuda.synchronize()
     apply_s = (time.perf_counter() - a0) / na
     S.close()
-    # set-ups alone, with the interior elimination timed for its MFMA roofline
+    S64.close()
+    # whole steps: set-up, solve, destroy
+    nst = max(3, args.steps // 4)
+    torch.cuda.synchronize()
+    e0 = time.perf_counter()
+    for _ in range(nst):
+        S1, _ = setup(args.precision)
+        S1.solve(f, u=u, rtol=prob.rtol, stream=stream)
+        S1.close()
+    torch.cuda.synchronize()
+    step_s = (time.perf_counter() - e0) / nst
+    # set-ups alone, with the level-1 interior elimination timed for its MFMA roofline
     P.timing_start("partial_chol", 1)
     su0 = time.perf_counter()
-    for _ in range(ns):
+    for _ in range(nst):
         P.Solver(prob, coeff=coeff, stream=stream, precision=args.precision).close()
     torch.cuda.synchronize()
-    setup_s = (time.perf_counter() - su0) / ns
+    setup_avg_s = (time.perf_counter() - su0) / nst
     tch = P.timing_stop()
     ch_ms = tch["ms"] / max(1, tch["launches"])
     ch_tf = (tch["flops"] / max(1, tch["launches"])) / (ch_ms * 1e-3) / 1e12 if tch["launches"] else 0.0
@@ -430,8 +460,7 @@ def main():
                   "unit": "TFLOP/s", "frac": ch_tf / PEAK_FP64_TFLOPS, "avg_launch_us": ch_ms * 1e3,
                   "flops_per_launch": tch["flops"] / max(1, tch["launches"]), "launches": tch["launches"]}
 
-    # ---- roofline of the chosen kernel, from the events of the timed region
-    kernel = args.roofline_kernel
+    # ---- roofline of the dominant kernel, from the events of the timed region
     bound = KERNEL_BOUND.get(kernel, "hbm")
     per_launch_ms = tm["ms"] / max(1, tm["launches"])
     workload = f"config{args.config}"
@@ -445,15 +474,13 @@ def main():
                 "frac": achieved / PEAK_FP64_TFLOPS}
     roof.update({"kernel": kernel, "launches": tm["launches"], "avg_launch_us": per_launch_ms * 1e3,
                  "algorithmic_bytes_per_launch": tm["bytes"] / max(1, tm["launches"]),
-                 "traffic": measured_traffic(kernel, workload)})
-
-    # the same steps from two host threads on two streams (independent problems in flight)
-    conc = concurrent_steps(P, prob, coeff, f, torch, max(2 * args.steps, 8))
-    log(f"bench: two streams: {conc:.1f} steps/s")
+                 "traffic": measured_traffic(kernel, f"{workload}_{args.precision}"),
+                 "kernel_ms_per_solve": shares})
     lat_ms = np.array(lat) * 1e3
+    lat64_ms = np.array(lat64) * 1e3
     out = {
         "metric": METRIC,
-        "value": args.steps / elapsed,
+        "value": rate,
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -462,25 +489,30 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else f"{'f32' if args.precision == 'fp32' else 'bf16'}+f64",
         "data": "synthetic (seeded coefficient field, partition and load)",
         "config": {"workload": workload + ": " + synth.CONFIG_NAMES[args.config], "n_free": prob.n_free,
                    "substructures": prob.nsub, "levels": prob.levels, "tau": prob.tau,
-                   "precision": args.precision, "rtol": prob.rtol, "step": "setup + PCG solve + destroy"},
+                   "precision": args.precision, "rtol": prob.rtol,
+                   "step": "one bddc_solve of one load to relative residual 1e-8 (PCG with the set-up "
+                           "multilevel preconditioner, interior recovery); set-up excluded, reported beside"},
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
-        "concurrent_steps_per_s": {"value": conc, "streams": 2,
-                                   "note": "independent steps from two host threads, one stream each; a set-up's "
-                                           "host work overlaps the other problem's kernels"},
-        "solve_only_per_s": 1.0 / solve_s,
-        "applies_per_s": 1.0 / apply_s,
+        "fp64": {"solves_per_s": rate64, "latency_ms": {"p50": float(np.percentile(lat64_ms, 50)),
+                                                          "p99": float(np.percentile(lat64_ms, 99))},
+                 "iterations": int(its64[0]), "setup_ms": setup64_s * 1e3},
+        "mixed_vs_fp64": rate / rate64,
+        "iterations": int(its[0]),
         "setup_ms": setup_s * 1e3,
-        "iterations": iters[0],
+        "setup_avg_ms": setup_avg_s * 1e3,
+        "end_to_end_steps_per_s": 1.0 / step_s,
+        "applies_per_s": 1.0 / apply_s,
         "nc": info["nc"],
         "indicator": info["indicator"],
         "kappa": info["kappa"],
         "roofline": roof,
         "setup_roofline": setup_roof,
     }
+    gpu_rates = {}
     if not args.no_serving:
         out["serving"] = {"two_slots": serving(synth, slots=2), "one_slot": serving(synth, slots=1),
                           "shared_problems": serving(synth, count=120, rate=2000.0, slots=2, problems=4),
@@ -497,11 +529,13 @@ def main():
             f" req/s (p99 {sv['shared_problems']['latency_ms']['p99']:.1f} -> "
             f"{sv['shared_problems_resident']['latency_ms']['p99']:.1f} ms)")
     if not args.no_precision_forms:
+        c2 = precision_forms(P, synth, torch, 2, stream)
+        gpu_rates["config2_fp64"] = c2["fp64"]["solves_per_s"]
+        gpu_rates["config2_step"] = 1.0 / (1e-3 * (c2["fp64"]["setup_ms"] + c2["fp64"]["solve_ms"]))
         out["precision_forms"] = {
             "note": "solves/s with the preconditioner set up once; FP32 / BF16 = reduced storage of the level-1 "
                     "T_rr and Psi streamed every iteration (BF16: inverse Cholesky factor), FP64 outer PCG",
-            "config2": precision_forms(P, synth, torch, 2, stream),
-            "config3": precision_forms(P, synth, torch, 3, stream),
+            "config2": c2,
         }
     if not args.no_blocked:
         out["blocked_rhs"] = {
@@ -512,9 +546,7 @@ def main():
         }
     if not args.no_batching:
         out["batching_form"] = dict(batching_form(P, synth, torch, stream),
-                                    note="config 4: 2048x2048 Q1, 9216 jittered Voronoi regions (152-927 dofs) in "
-                                         "576 groups, k = 10^U(0,4), adaptive tau = 10, 8 loads; regions smaller than "
-                                         "the workload's 1500-6000 dofs (dense local factors, see the design notes)")
+                                    note="config 4: " + synth.CONFIG_NAMES[4])
     if not args.no_autotune:
         out["autotune"] = {
             "note": "launch configuration chosen by bddc_autotune (deep-level path, partial-sum mode, graph, "
@@ -523,8 +555,8 @@ def main():
             "config3_8rhs": autotuned(P, synth, torch, 3, stream, 8),
         }
     if not args.no_cpu_baseline:
-        log("bench: timing the CPU oracle on a bounded sample")
-        out["cpu_baseline"] = cpu_baseline(prob)
+        log("bench: timing the CPU oracle (full config 2, config 1 with all threads and with one)")
+        out["cpu_baseline"] = cpu_baseline(gpu_rates)
     print(json.dumps(out))
 
 

@@ -68,7 +68,7 @@ typedef struct {
                                   substructure s (l = 2..L-1); may be NULL when levels == 2 */
   int32_t constraints;         /* bddc_constraints; corners are always coarse dofs */
   double tau;                  /* ADAPTIVE threshold: eigenvectors with lambda > tau become coarse dofs */
-  int32_t precision;           /* bddc_precision; this build implements BDDC_FP64 */
+  int32_t precision;           /* bddc_precision: storage of the reduced-precision preconditioner operators */
   const double* coeff_device;  /* optional DEVICE pointer to the same nx*ny coefficients; when non-NULL it is
                                   used instead of coeff (which may then be NULL) and the positivity check runs
                                   on the device (BDDC_EINVAL after the device work) */
@@ -193,6 +193,18 @@ bddc_status bddc_edge_constraints(bddc_handle h, int32_t level, int32_t edge, in
                                   int32_t cap_dofs, double* q, int32_t cap_q,
                                   int32_t* n_edge_dofs, int32_t* n_cols);
 
+/* Corner dofs of level `level` (1-based): the dofs shared by three or more
+ * substructures, plus the corners promoted where a floating substructure or
+ * pair would otherwise have none (Section 2 coarse dofs; Section 5 asks for
+ * "sufficient" corners).  Written in ascending order to the host array
+ * corners (cap entries; may be NULL to query the count); *n_corners receives
+ * the count.  Level-l dofs for l >= 2 are the level-(l-1) coarse dofs,
+ * numbered corners first (ascending corner dof), then edge by edge in
+ * bddc_edge_eigs order, each edge's columns in the order of
+ * bddc_edge_constraints.  Errors: BDDC_EINVAL (level out of range, cap too
+ * small). */
+bddc_status bddc_corners(bddc_handle h, int32_t level, int32_t* corners, int32_t cap, int32_t* n_corners);
+
 /* Kernel timing for measurement tools.  bddc_timing_start(name, every) arms
  * HIP events on one in `every` (>= 1) later launches of the named kernel, on
  * any handle: the events are stamped by the dispatch itself, on the stream the
@@ -202,7 +214,9 @@ bddc_status bddc_edge_constraints(bddc_handle h, int32_t level, int32_t edge, in
  * level-1 restriction), "deep" (levels >= 2 and the coarsest solve in one
  * launch), "apply_average" (level-1 interface average), "apply_pre_l2",
  * "apply_restrict_l2", "apply_prolong_l2", "apply_post_l2" ("_l3" ...; deep
- * levels when they run one launch per phase), "partial_chol", "partial_chol_l2".
+ * levels when they run one launch per phase), "wide_pre", "wide_restrict",
+ * "wide_coarse", "wide_post" (the row-block deep level), "partial_chol",
+ * "partial_chol_l2".
  * bddc_timing_stop synchronises those events and returns the summed kernel
  * time in ms, the number of timed launches, and the summed algorithmic bytes
  * and flops of those launches (each operator and vector entry the kernel must

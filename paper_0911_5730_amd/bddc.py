@@ -55,7 +55,7 @@ class BddcTuningC(ctypes.Structure):
 DEEP_PATHS = ("coop", "wide", "fused", "levels")
 
 SYMBOLS = ["bddc_plan", "bddc_setup", "bddc_apply", "bddc_solve", "bddc_query", "bddc_edge_eigs",
-           "bddc_edge_constraints", "bddc_timing_start", "bddc_timing_stop", "bddc_get_tuning",
+           "bddc_edge_constraints", "bddc_corners", "bddc_timing_start", "bddc_timing_stop", "bddc_get_tuning",
            "bddc_set_tuning", "bddc_autotune", "bddc_last_error", "bddc_status_string", "bddc_destroy"]
 
 _lib = None
@@ -83,6 +83,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.bddc_query.argtypes = [vp, P(BddcInfoC)]
     lib.bddc_edge_eigs.argtypes = [vp, i32, i32, P(dbl), i32, P(i32), P(i32), P(i32), P(i32)]
     lib.bddc_edge_constraints.argtypes = [vp, i32, i32, P(i32), i32, P(dbl), i32, P(i32), P(i32)]
+    lib.bddc_corners.argtypes = [vp, i32, P(i32), i32, P(i32)]
     lib.bddc_timing_start.argtypes = [ctypes.c_char_p, i32]
     lib.bddc_timing_stop.argtypes = [P(dbl), P(i64), P(dbl), P(dbl)]
     lib.bddc_get_tuning.argtypes = [vp, P(BddcTuningC)]
@@ -302,6 +303,15 @@ class Solver:
                                               None), "bddc_edge_constraints")
         Q = np.array(q[:ne.value * m.value]).reshape(m.value, ne.value).T
         return np.array(dofs[:ne.value]), Q
+
+
+    def corners(self, level: int) -> np.ndarray:
+        """Corner dofs of a level, ascending (bddc_corners)."""
+        n = ctypes.c_int32()
+        _check(self.lib.bddc_corners(self.h, level, None, 0, ctypes.byref(n)), "bddc_corners")
+        buf = (ctypes.c_int32 * max(1, n.value))()
+        _check(self.lib.bddc_corners(self.h, level, buf, n.value, None), "bddc_corners")
+        return np.array(buf[:n.value], dtype=np.int64)
 
 
 def _tuning_dict(t: BddcTuningC) -> dict:

@@ -7,6 +7,7 @@
 // basis and the next level's matrices; the last level is factored directly.
 // bddc_apply runs Algorithm "Multilevel BDDC"; bddc_solve runs PCG on the
 // level-1 interface (Section 5, reduction of level 1 to the interfaces).
+#include <atomic>
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -24,6 +25,10 @@
 #include "topology.hpp"
 
 namespace bddc {
+
+// handles alive in the process; the cooperative deep kernel uses the
+// cooperative launch API whenever another handle may be running beside it
+std::atomic<int> g_live_handles{0};
 
 void check_launch() {
   const hipError_t e = hipGetLastError();
@@ -435,7 +440,10 @@ struct bddc_ctx {
   // one deep level and the coarsest solve in one cooperative launch
   std::vector<void*> staged;   // pinned upload buffers of the setup, released after it synchronises
   bool coop_deep = false;
-  bool coop_launch = false;   // use the cooperative launch API
+  bool coop_launch = false;   // use the cooperative launch API (BDDC_COOP_LAUNCH=1)
+  bool coop_shared = false;   // this solve shares the device with other handles: cooperative API
+  bool counted = false;       // counted in g_live_handles
+  int device = 0;             // the device the handle's memory lives on
   int coop_rmax = 1;          // most columns one cooperative launch serves (LDS and residency)
   double coop_bytes = 0;      // algorithmic bytes of one launch
   hipGraphExec_t graph_exec = nullptr;   // one chunk of PCG launches (captured on first use)
@@ -444,6 +452,7 @@ struct bddc_ctx {
   bool wide_deep = false;     // one deep level in row-block launches (WideDev)
   bddc::WideDev wide;
   double wide_bytes = 0;      // algorithmic bytes of the four launches
+  double wide_by[4] = {0, 0, 0, 0};   // ... of each of them (pre, restrict, coarse, post)
   bddc::Arena wide_arena;
   double by_average = 0;      // algorithmic bytes of the level-1 interface average
   double by_ur_prec = 0;      // update + restriction (it >= 1), T_rr and Psi in the precision form's storage
@@ -1320,6 +1329,26 @@ static void apply_deep_level(bddc_ctx* h, int li, const double* r, double* u, hi
   }
 }
 
+// the four launches of the row-block deep level, each timed under its own name
+static void wide_launches(bddc_ctx* h, hipStream_t st, const WideDev& W, const int32_t* gam_gid2) {
+  {
+    timing::Scope ts("wide_pre", h->wide_by[0], 0);
+    launch_wide_pre(st, W);
+  }
+  {
+    timing::Scope ts("wide_restrict", h->wide_by[1], 0);
+    launch_wide_restrict(st, W, gam_gid2);
+  }
+  {
+    timing::Scope ts("wide_coarse", h->wide_by[2], 0);
+    launch_wide_coarse(st, W);
+  }
+  {
+    timing::Scope ts("wide_post", h->wide_by[3], 0);
+    launch_wide_post(st, W);
+  }
+}
+
 // level-1 coarse right-hand side (the level-1 b) -> level-1 coarse solution (level-1 uc)
 // Levels >= 2 and the coarsest solve for the level-1 coarse contributions b1
 // (local coarse flat), leaving the level-1 coarse correction in uc.
@@ -1336,7 +1365,7 @@ static void run_deep_at(bddc_ctx* h, hipStream_t st, const double* b1, double* u
     C.b1 = b1;
     C.u2 = uc;
     timing::Scope ts("deep", h->coop_bytes, 0);
-    launch_deep_coop(st, C, h->coop_launch);
+    launch_deep_coop(st, C, h->coop_launch || h->coop_shared);
     return;
   }
   if (h->deep_sel == BDDC_DEEP_WIDE) {
@@ -1347,10 +1376,7 @@ static void run_deep_at(bddc_ctx* h, hipStream_t st, const double* b1, double* u
     W.nrhs = 1;
     W.stop = l1.dev.stop;
     W.L.stop = l1.dev.stop;
-    launch_wide_pre(st, W);
-    launch_wide_restrict(st, W, l2.d.gam_gid);
-    launch_wide_coarse(st, W);
-    launch_wide_post(st, W);
+    wide_launches(h, st, W, l2.d.gam_gid);
     return;
   }
   if (h->deep_sel == BDDC_DEEP_FUSED) {
@@ -1395,10 +1421,7 @@ static void run_deep_cols(bddc_ctx* h, hipStream_t st, const double* b1, int ldb
     W.ld_u2 = ldu;
     W.stop = l1.dev.stop;
     W.L.stop = l1.dev.stop;
-    launch_wide_pre(st, W);
-    launch_wide_restrict(st, W, l2.d.gam_gid);
-    launch_wide_coarse(st, W);
-    launch_wide_post(st, W);
+    wide_launches(h, st, W, l2.d.gam_gid);
     return;
   }
   if (h->deep_sel == BDDC_DEEP_COOP && R <= h->coop_rmax) {
@@ -1410,7 +1433,7 @@ static void run_deep_cols(bddc_ctx* h, hipStream_t st, const double* b1, int ldb
     C.u2 = uc;
     C.ld_u2 = ldu;
     timing::Scope ts("deep", h->coop_bytes, 0);
-    launch_deep_coop(st, C, h->coop_launch);
+    launch_deep_coop(st, C, h->coop_launch || h->coop_shared);
     return;
   }
   for (int c = 0; c < R; ++c) run_deep_at(h, st, b1 + (size_t)c * ldb, uc + (size_t)c * ldu);
@@ -1426,7 +1449,18 @@ static void apply_full(bddc_ctx* h, const double* r, double* u) {
   else
     launch_apply_pre(st, l1.dev, l1.nImax, l1.ngmax, r);
   launch_apply_restrict(st, l1.dev, l1.ngmax, r, l1.d.gam_gid, 1);
-  run_deep(h, st);
+  {
+    // bddc_apply returns before its kernels run, so it could not report a
+    // grid barrier that timed out: the deep levels take a path without grid
+    // barriers here (the row-block path, else one launch per phase)
+    struct Restore {
+      bddc_ctx* h;
+      int sel;
+      ~Restore() { h->deep_sel = sel; }
+    } restore{h, h->deep_sel};
+    if (h->deep_sel == BDDC_DEEP_COOP) h->deep_sel = h->wide_deep ? BDDC_DEEP_WIDE : BDDC_DEEP_LEVELS;
+    run_deep(h, st);
+  }
   launch_apply_prolong(st, l1.dev, l1.ncsmax, l1.d.uc);
   if (sweep)
     launch_sweep_post(st, l1.dev, u, l1.d.gam_gid);
@@ -1686,12 +1720,22 @@ static bool plan_wide(bddc_ctx* h) {
   h->wide = W;
   h->wide_deep = true;
   // K_II^-1, M^T twice, T_rr, Psi twice, and the level vectors
-  double by = 0;
+  double by = 0, op_pre = 0, op_res = 0, op_crs = 0, op_post = 0;
   for (int s = 0; s < nsub; ++s) {
     const double nI = T.n_int[s], ng = T.ngam(s), nr = T.n_r[s], ncs = lv.coff[s + 1] - lv.coff[s];
     by += 8 * (nI * nI + 2 * nI * ng + nr * nr + 2 * ng * ncs);
+    op_pre += 8 * (nI * nI + nI * ng);
+    op_res += 8 * (nr * nr + ng * ncs);
+    op_crs += 8 * (ng * ncs);
+    op_post += 8 * (nI * ng);
   }
   h->wide_bytes = by + 8.0 * (2.0 * l1.nflat_c + 3.0 * lv.n + 6.0 * lv.nflat_g + lv.nflat_c + lv.nc);
+  // per launch: the gather of r_2 and y, t written; g, delta T g, b; u_3 and
+  // v; u_B and y read, u_I and u_2 written
+  h->wide_by[0] = op_pre + 8.0 * (2.0 * l1.nflat_c + lv.n + lv.nflat_i + lv.nflat_g);
+  h->wide_by[1] = op_res + 8.0 * (3.0 * lv.nflat_g + lv.nflat_c);
+  h->wide_by[2] = op_crs + 8.0 * (lv.nflat_c + 2.0 * lv.nc + 2.0 * lv.nflat_g);
+  h->wide_by[3] = op_post + 8.0 * (2.0 * lv.nflat_i + 2.0 * lv.nflat_g + lv.n);
   return true;
 }
 
@@ -1799,6 +1843,8 @@ static double lanczos_kappa(const std::vector<double>& al, const std::vector<dou
 template <class F>
 static bool graph_chunk(bddc_ctx* h, hipStream_t st, F&& enqueue) {
   if (h->graph_off || timing::active()) return false;
+  // cooperative launches are issued directly, not replayed from a graph
+  if (h->coop_shared && h->deep_sel == BDDC_DEEP_COOP) return false;
   if (!h->graph_exec) {
     const char* env = getenv("BDDC_PCG_GRAPH");
     if (env && std::string(env) == "0") {
@@ -1848,18 +1894,11 @@ static bool graph_chunk(bddc_ctx* h, hipStream_t st, F&& enqueue) {
   return true;
 }
 
-// The per-column PCG state for R columns (reallocated when a solve needs more
-// columns than the arena holds; a captured chunk keeps the old addresses, so
-// it is dropped).
-static void ensure_columns(bddc_ctx* h, int R) {
-  if (h->cols_cap >= R) return;
+// The per-column PCG state for R columns, laid out in A (a sizing pass when A
+// holds no memory yet).
+static void lay_columns(bddc_ctx* h, Arena& A, int R) {
   Level& l1 = *h->levels[0];
   PcgDev& P = h->pcg;
-  BDDC_HIP(hipStreamSynchronize(h->stream));
-  h->cols_arena.release(h->stream);
-  if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
-  h->graph_exec = nullptr;
-  h->graph_nrhs = 0;
   auto pad = [](int64_t n) { return (int)(((std::max<int64_t>(n, 1) * 8 + 255) / 256) * 32); };   // 256-byte columns
   P.ld_if = pad(P.nif);
   P.ld_flat = pad(l1.nflat_g);
@@ -1868,30 +1907,40 @@ static void ensure_columns(bddc_ctx* h, int R) {
   P.ld_sub = pad(P.nsub1);
   P.ld_blk = pad(P.nblk);
   h->ld_cy = pad(l1.nflat_i);
+  P.x = A.take<double>((size_t)R * P.ld_if);
+  P.r[0] = A.take<double>((size_t)R * P.ld_if);
+  P.r[1] = A.take<double>((size_t)R * P.ld_if);
+  P.p[0] = A.take<double>((size_t)R * P.ld_if);
+  P.p[1] = A.take<double>((size_t)R * P.ld_if);
+  P.z = A.take<double>((size_t)R * P.ld_if);
+  P.pq_part = A.take<double>((size_t)R * P.ld_sub);
+  P.rr_part = A.take<double>((size_t)R * P.ld_sub);
+  P.rz_part[0] = A.take<double>((size_t)R * P.ld_blk);
+  P.rz_part[1] = A.take<double>((size_t)R * P.ld_blk);
+  P.qloc = A.take<double>((size_t)R * P.ld_flat);
+  P.da = A.take<double>((size_t)R * P.ld_flat);
+  P.b = A.take<double>((size_t)R * P.ld_cflat);
+  P.uc = A.take<double>((size_t)R * P.ld_coarse);
+  P.sc = A.take<PcgScalars>(R);
+  h->cy = A.take<double>((size_t)R * h->ld_cy);
+  h->ct = A.take<double>((size_t)R * P.ld_flat);
+}
+
+// The per-column PCG state for R columns (reallocated when a solve needs more
+// columns than the arena holds; a captured chunk keeps the old addresses, so
+// it is dropped).
+static void ensure_columns(bddc_ctx* h, int R) {
+  if (h->cols_cap >= R) return;
+  BDDC_HIP(hipStreamSynchronize(h->stream));
+  h->cols_arena.release(h->stream);
+  if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+  h->graph_exec = nullptr;
+  h->graph_nrhs = 0;
   Arena& A = h->cols_arena;
-  auto lay = [&] {
-    P.x = A.take<double>((size_t)R * P.ld_if);
-    P.r[0] = A.take<double>((size_t)R * P.ld_if);
-    P.r[1] = A.take<double>((size_t)R * P.ld_if);
-    P.p[0] = A.take<double>((size_t)R * P.ld_if);
-    P.p[1] = A.take<double>((size_t)R * P.ld_if);
-    P.z = A.take<double>((size_t)R * P.ld_if);
-    P.pq_part = A.take<double>((size_t)R * P.ld_sub);
-    P.rr_part = A.take<double>((size_t)R * P.ld_sub);
-    P.rz_part[0] = A.take<double>((size_t)R * P.ld_blk);
-    P.rz_part[1] = A.take<double>((size_t)R * P.ld_blk);
-    P.qloc = A.take<double>((size_t)R * P.ld_flat);
-    P.da = A.take<double>((size_t)R * P.ld_flat);
-    P.b = A.take<double>((size_t)R * P.ld_cflat);
-    P.uc = A.take<double>((size_t)R * P.ld_coarse);
-    P.sc = A.take<PcgScalars>(R);
-    h->cy = A.take<double>((size_t)R * h->ld_cy);
-    h->ct = A.take<double>((size_t)R * P.ld_flat);
-  };
   A.reset_sizing();
-  lay();
+  lay_columns(h, A, R);
   A.allocate(h->stream);
-  lay();
+  lay_columns(h, A, R);
   h->cols_cap = R;
 }
 
@@ -1906,6 +1955,10 @@ static int pcg_block(bddc_ctx* h, const double* f, double* u, int64_t ld, int R,
   ensure_columns(h, R);
   PcgDev& P = h->pcg;
   P.nrhs = R;
+  if (h->coop_deep) {
+    h->coop_shared = g_live_handles.load() > 1;
+    launch_coop_reset(st, h->coop);
+  }
   const int nif = (int)l1.iface_dof.size();
   const int nb = h->nblk;
   const int nbf = std::min(1024, std::max(1, (int)((h->n_free + kNT - 1) / kNT)));
@@ -2098,6 +2151,7 @@ bddc_status guard(const std::function<void()>& fn) {
 
 void release(bddc_ctx* h) {
   if (!h) return;
+  if (h->counted) g_live_handles.fetch_sub(1);
   hipStream_t st = h->stream;
   (void)hipStreamSynchronize(st);
   for (auto& lv : h->levels) {
@@ -2250,6 +2304,7 @@ bddc_status bddc_setup(const bddc_problem* p, void* hip_stream, bddc_handle* out
     h->tau = p->tau;
     h->n_free = (int64_t)(p->nx - 1) * (p->ny - 1);
     h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    BDDC_HIP(hipGetDevice(&h->device));
     HostClock clk;
     Builder(h, p).run();
     clk.lap("builder");
@@ -2408,6 +2463,8 @@ bddc_status bddc_setup(const bddc_problem* p, void* hip_stream, bddc_handle* out
         h->tuned_ms = it->second.solve_ms;
       }
     }
+    h->counted = true;
+    g_live_handles.fetch_add(1);
     *out = h;
   });
   if (st != BDDC_OK && h) {
@@ -2575,6 +2632,18 @@ bddc_status bddc_edge_constraints(bddc_handle h, int32_t level, int32_t edge, in
       BDDC_HIP(hipMemcpyAsync(q, lv.d.Q + lv.qoff[edge], sizeof(double) * ne * m, hipMemcpyDeviceToHost, h->stream));
       BDDC_HIP(hipStreamSynchronize(h->stream));
     });
+  }
+  return BDDC_OK;
+}
+
+bddc_status bddc_corners(bddc_handle h, int32_t level, int32_t* corners, int32_t cap, int32_t* n_corners) {
+  if (!h || level < 1 || level > (int)h->levels.size() || cap < 0) return BDDC_EINVAL;
+  const std::vector<int32_t>& c = h->levels[level - 1]->topo.corners;
+  const int n = (int)c.size();
+  if (n_corners) *n_corners = n;
+  if (corners) {
+    if (cap < n) return BDDC_EINVAL;
+    std::copy(c.begin(), c.end(), corners);
   }
   return BDDC_OK;
 }

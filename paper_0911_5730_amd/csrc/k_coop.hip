@@ -275,12 +275,15 @@ int coop_max_blocks(size_t lds) {
 }
 
 // The grid barriers need every workgroup resident.  The grid is at most the
-// device's cooperative capacity (checked when the path is chosen) and follows
-// the previous kernel of the same stream, so an ordinary launch finds the
-// device free; the cooperative API guarantees residency but costs about 25 us
-// of queue synchronisation per launch, so it is used only on request
-// (BDDC_COOP_LAUNCH=1).  If residency ever failed, the bounded spin ends the
-// kernel and the status flag reports it.
+// device's cooperative capacity (checked when the path is chosen).  While the
+// process holds a single handle, the launch follows the previous kernel of
+// the same stream and nothing else of the library runs beside it, so an
+// ordinary launch finds room for every workgroup; with several live handles
+// (other streams may hold the compute units) the caller asks for the
+// cooperative API, which guarantees residency at about 25 us of queue
+// synchronisation per launch (also forced by BDDC_COOP_LAUNCH=1).  If
+// residency ever failed, the bounded spin ends the kernel and the status flag
+// reports it; the next solve resets the barrier (launch_coop_reset).
 void launch_deep_coop(hipStream_t st, const CoopDev& C, bool cooperative) {
   if (!cooperative) {
     if (C.nrhs > 1)
@@ -301,6 +304,22 @@ void launch_deep_coop(hipStream_t st, const CoopDev& C, bool cooperative) {
                                                   dim3(kCoopNT), args, coop_lds(C), st);
   if (e != hipSuccess) fail(BDDC_EDEVICE, std::string("cooperative launch: ") + hipGetErrorString(e));
   if (ev.stop) (void)hipEventRecord(ev.stop, st);
+}
+
+// Barrier counter, generation and the barrier-timeout status bit back to
+// zero before a solve: a timed-out barrier leaves the counter mid-way, and
+// every later launch must start from a clean state.  A kernel, not a memset,
+// so that the reset can sit in a captured stream.
+__global__ void k_coop_reset(unsigned* bar, int* status) {
+  if (threadIdx.x == 0) {
+    bar[0] = 0u;
+    bar[1] = 0u;
+    *status &= ~4;
+  }
+}
+
+void launch_coop_reset(hipStream_t st, const CoopDev& C) {
+  launch_kernel(k_coop_reset, dim3(1), dim3(64), 0, st, C.bar, C.status);
 }
 
 // pack the level-2 operators of one substructure per workgroup

@@ -136,6 +136,7 @@ struct CoopDev {
 };
 size_t coop_lds(const CoopDev& C);
 void launch_deep_coop(hipStream_t st, const CoopDev& C, bool cooperative);
+void launch_coop_reset(hipStream_t st, const CoopDev& C);
 void launch_pack_coop(hipStream_t st, const LevelDev& L, const CoopDev& C);
 void launch_tri_inverse_dense(hipStream_t st, const double* L, int ld, int m, double* X);
 int coop_max_blocks(size_t lds);

@@ -224,7 +224,17 @@ class Server:
                     r.error = err
                     self.finished.append(r)
                 hk = self._hkey(head)
-                if ent is not None:
+                if ent is not None and err is not None:
+                    # a failed solve leaves the handle in an unknown state:
+                    # release it, later requests of the problem set it up anew
+                    if self.handles.get(hk) is ent:
+                        del self.handles[hk]
+                    self.in_flight -= ent.footprint
+                    try:
+                        ent.solver.close()
+                    except Exception:   # a failed release must not stop the slot
+                        pass
+                elif ent is not None:
                     ent.busy = False
                 elif keep is not None and err is None:
                     ph = self.handles[hk]                  # the placeholder of the set-up

@@ -91,5 +91,44 @@ def check_adaptive_edges(S, B, tau, levels_to_span=(1,)):
                     assert np.max(ang) < 1e-6, (li, key, np.max(ang))
 
 
+# entrywise bar of the preconditioner apply: |z_gpu - z_oracle| <=
+# APPLY_ATOL * max|z_oracle| + APPLY_RTOL * |z_oracle| on every entry.  The
+# two sides apply the same operator with different algorithms (explicit
+# constrained inverses and dense interior inverses against KKT and sparse LU
+# solves), so every entry carries rounding of order eps times the local
+# condition numbers (coefficient jumps up to 1e6, H/h up to 32) relative to
+# the largest entries of the local solutions
+APPLY_ATOL = 1e-11
+APPLY_RTOL = 1e-10
+
+
+def check_apply(zg, zo, atol=APPLY_ATOL, rtol=APPLY_RTOL, tag=""):
+    """Entrywise comparison of two preconditioner applies."""
+    zg = np.asarray(zg)
+    zo = np.asarray(zo)
+    assert zg.shape == zo.shape and np.isfinite(zg).all()
+    d = np.abs(zg - zo)
+    scale = float(np.max(np.abs(zo))) if zo.size else 0.0
+    bound = atol * scale + rtol * np.abs(zo)
+    worst = int(np.argmax(d - bound)) if zo.size else 0
+    print(f"apply {tag}: max |dz|/max|z| = {float(d.max()) / max(scale, 1e-300):.2e}, "
+          f"worst entry {worst}: dz {d[worst]:.2e} bound {bound[worst]:.2e}", flush=True)
+    assert np.all(d <= bound), (tag, worst, d[worst], bound[worst])
+
+
+def check_topology(S, B):
+    """Corner sets and every edge's dof list, at every level, bit-exact
+    against the oracle's classification (level-l dofs for l >= 2 are the
+    level-(l-1) coarse dofs, numbered the same way on both sides)."""
+    for li, lv in enumerate(B.levels):
+        cg = S.corners(li + 1)
+        assert np.array_equal(cg, np.asarray(lv.topo.corners, dtype=np.int64)), (li, cg[:8])
+        keys = list(lv.topo.edges.keys())
+        assert S.info()["n_edges"][li] == len(keys)
+        for e, key in enumerate(keys):
+            dofs, _ = S.edge_constraints(li + 1, e)
+            assert np.array_equal(dofs, lv.topo.edges[key]), (li, key)
+
+
 def direct(B, b=None):
     return spla.spsolve(B.A.tocsc(), B.prob.f[0] if b is None else b)

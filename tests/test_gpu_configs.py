@@ -6,9 +6,14 @@
   are compared.
 * 1024 x 1024, 64 x 64 substructures, three levels, k = 1: too large for the
   oracle's setup, so the checks are properties that hold at any size (true
-  residual, symmetry of the preconditioner) and the interior-edge pair
-  eigenvalues, which for k = 1 coincide with those of the same floating pair
-  in a 4 x 4 partition that the oracle solves.
+  residual, symmetry of the preconditioner), the energy-norm error of the
+  FP64, FP32 and BF16 solutions against a sparse direct solve of the oracle's
+  assembled matrix (at most 1e-8), and the interior-edge pair eigenvalues,
+  which for k = 1 coincide with those of the same floating pair in a 4 x 4
+  partition that the oracle solves.
+* 2048 x 2048, uneven Voronoi regions, eight loads: the true residual of
+  every column, the energy-norm error of the FP32 form against the FP64 path
+  converged to 1e-12, and a column solved alone against the blocked column.
 """
 
 import numpy as np
@@ -41,18 +46,39 @@ def test_config2_full_parity():
 
 
 def test_config3_properties_and_sampled_edges():
+    import time
+
+    import scipy.sparse.linalg as spla
+
     import paper_0911_5730_amd as P
+    from oracle import pcg
     prob = synth.config(3)
+    A = fem.assemble(prob.nx, prob.ny, prob.coeff)
+    t0 = time.perf_counter()
+    xs = spla.spsolve(A.tocsc(), prob.f[0], permc_spec="MMD_AT_PLUS_A")
+    print(f"config3: sparse direct solve of the assembled matrix {time.perf_counter() - t0:.1f} s", flush=True)
+    assert np.linalg.norm(A @ xs - prob.f[0]) <= 1e-12 * np.linalg.norm(prob.f[0])
+    # the precision forms: the outer FP64 iteration wins the accuracy back
+    f = cuda_vec(prob.f[0])
+    for prec in ("fp32", "bf16"):
+        with P.Solver(prob, precision=prec) as S:
+            u, it, rr = S.solve(f)
+            ug = u.cpu().numpy()
+        res = np.linalg.norm(A @ ug - prob.f[0]) / np.linalg.norm(prob.f[0])
+        err = pcg.energy_error(A, ug, xs)
+        print(f"config3 {prec}: iterations {it[0]}, true residual {res:.2e}, energy error {err:.2e}", flush=True)
+        assert rr[0] <= 1e-8 and res <= 2e-8
+        assert err <= 1e-8, (prec, err)
     print("config3: GPU setup + solve", flush=True)
     with P.Solver(prob) as S:
-        f = cuda_vec(prob.f[0])
         u, it, rr = S.solve(f)
         info = S.info()
         ug = u.cpu().numpy()
-        A = fem.assemble(prob.nx, prob.ny, prob.coeff)
         res = np.linalg.norm(A @ ug - prob.f[0]) / np.linalg.norm(prob.f[0])
-        print("config3 iters", it, "relres", rr, "true", res, "nc", info["nc"], flush=True)
+        err = pcg.energy_error(A, ug, xs)
+        print("config3 iters", it, "relres", rr, "true", res, "energy error", err, "nc", info["nc"], flush=True)
         assert rr[0] <= 1e-8 and res <= 2e-8
+        assert err <= 1e-8
         assert info["indicator"] <= prob.tau ** 2
         # symmetry of the three-level preconditioner
         rng = np.random.default_rng(9)
@@ -101,14 +127,21 @@ def test_config4_uneven_substructures_eight_loads():
     import torch
 
     import paper_0911_5730_amd as P
+    from oracle import pcg
     prob = synth.config(4, nrhs=8)
     print(f"config4: {prob.nsub} regions, {prob.n_free} unknowns", flush=True)
+    F = cuda_vec(prob.f)
+    # reference: the FP64 path (oracle-checked on smaller cases) to 1e-12
+    with P.Solver(prob) as S64:
+        Uref, itr, rrr = S64.solve(F, rtol=1e-12)
+        print(f"config4 FP64 reference iterations {itr}", flush=True)
+        assert all(x <= 1e-12 for x in rrr)
+        Uref = Uref.cpu().numpy()
     t0 = time.perf_counter()
     S = P.Solver(prob, precision="fp32")
     try:
         torch.cuda.synchronize()
         print(f"config4 setup {time.perf_counter() - t0:.2f} s, nc {S.info()['nc']}", flush=True)
-        F = cuda_vec(prob.f)
         U, its, rr = S.solve(F)
         print(f"config4 iterations {its}", flush=True)
         assert all(x <= 1e-8 for x in rr)
@@ -121,3 +154,7 @@ def test_config4_uneven_substructures_eight_loads():
     for c in range(8):
         r = A @ U[c] - prob.f[c]
         assert np.linalg.norm(r) <= 2e-8 * np.linalg.norm(prob.f[c]), c
+        assert np.linalg.norm(A @ Uref[c] - prob.f[c]) <= 2e-12 * np.linalg.norm(prob.f[c]), c
+        err = pcg.energy_error(A, U[c], Uref[c])
+        print(f"config4 column {c}: energy error of the FP32 form {err:.2e}", flush=True)
+        assert err <= 1e-8, (c, err)
