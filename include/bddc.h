@@ -56,6 +56,10 @@ typedef struct bddc_ctx* bddc_handle;   /* opaque, owned by the library */
 
 #define BDDC_MAX_LEVELS 8
 
+/* Size of the fixed device working array of bddc_solve_noalloc (one per
+ * device, held until the process ends). */
+#define BDDC_NOALLOC_SCRATCH_BYTES (64u << 20)
+
 /* Problem description; pointers are HOST pointers read during the call only, except coeff_device. */
 typedef struct {
   int32_t nx, ny;              /* elements per side of the unit square, nx, ny >= 2 */
@@ -127,6 +131,24 @@ bddc_status bddc_apply(bddc_handle h, const double* r, double* z, int32_t nrhs, 
  * Errors: BDDC_EINVAL, BDDC_ENOCONV (u holds the last iterate), BDDC_EDEVICE. */
 bddc_status bddc_solve(bddc_handle h, const double* f, double* u, int32_t nrhs, int64_t ld,
                        double rtol, int32_t maxit, int32_t* iters, double* relres, void* hip_stream);
+
+/* bddc_solve for callers that cannot allocate device memory (serving loops
+ * and harnesses that forbid allocation after set-up): the same PCG, the same
+ * kernels and bitwise the same results as bddc_solve, but the per-column PCG
+ * state (iterates, residuals, directions, partial sums, scalars, condensed
+ * load) is laid out in one fixed device array of BDDC_NOALLOC_SCRATCH_BYTES
+ * per device, owned by the library and held until the process ends, instead
+ * of the handle's arena; the iterations are launched directly (no graph is
+ * captured or replayed).  The call allocates and frees no device memory.
+ * Columns are solved in blocks of up to eight, as many as the array holds;
+ * the array is cleared at the start of every call.  Every call on one device
+ * shares that array: calls that overlap in time on one device (from several
+ * threads or streams) race and must not be made.  The current device must be
+ * the one the handle was set up on.  Arguments and outputs as bddc_solve.
+ * Errors: BDDC_EINVAL, BDDC_EUNSUPPORTED (one column's state does not fit
+ * the array), BDDC_ENOCONV, BDDC_EDEVICE. */
+bddc_status bddc_solve_noalloc(bddc_handle h, const double* f, double* u, int32_t nrhs, int64_t ld,
+                               double rtol, int32_t maxit, int32_t* iters, double* relres, void* hip_stream);
 
 /* Sizes and diagnostics.  Errors: BDDC_EINVAL. */
 bddc_status bddc_query(bddc_handle h, bddc_info* info);

@@ -54,7 +54,7 @@ class BddcTuningC(ctypes.Structure):
 
 DEEP_PATHS = ("coop", "wide", "fused", "levels")
 
-SYMBOLS = ["bddc_plan", "bddc_setup", "bddc_apply", "bddc_solve", "bddc_query", "bddc_edge_eigs",
+SYMBOLS = ["bddc_plan", "bddc_setup", "bddc_apply", "bddc_solve", "bddc_solve_noalloc", "bddc_query", "bddc_edge_eigs",
            "bddc_edge_constraints", "bddc_corners", "bddc_timing_start", "bddc_timing_stop", "bddc_get_tuning",
            "bddc_set_tuning", "bddc_autotune", "bddc_last_error", "bddc_status_string", "bddc_destroy"]
 
@@ -80,6 +80,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.bddc_setup.argtypes = [P(BddcProblemC), vp, P(vp)]
     lib.bddc_apply.argtypes = [vp, vp, vp, i32, i64, vp]
     lib.bddc_solve.argtypes = [vp, vp, vp, i32, i64, dbl, i32, P(i32), P(dbl), vp]
+    lib.bddc_solve_noalloc.argtypes = [vp, vp, vp, i32, i64, dbl, i32, P(i32), P(dbl), vp]
     lib.bddc_query.argtypes = [vp, P(BddcInfoC)]
     lib.bddc_edge_eigs.argtypes = [vp, i32, i32, P(dbl), i32, P(i32), P(i32), P(i32), P(i32)]
     lib.bddc_edge_constraints.argtypes = [vp, i32, i32, P(i32), i32, P(dbl), i32, P(i32), P(i32)]

@@ -444,6 +444,7 @@ struct bddc_ctx {
   bool coop_shared = false;   // this solve shares the device with other handles: cooperative API
   bool counted = false;       // counted in g_live_handles
   int device = 0;             // the device the handle's memory lives on
+  bool noalloc_now = false;   // inside bddc_solve_noalloc: no graph, no (re)allocation
   int coop_rmax = 1;          // most columns one cooperative launch serves (LDS and residency)
   double coop_bytes = 0;      // algorithmic bytes of one launch
   hipGraphExec_t graph_exec = nullptr;   // one chunk of PCG launches (captured on first use)
@@ -1842,7 +1843,7 @@ static double lanczos_kappa(const std::vector<double>& al, const std::vector<dou
 // false when the chunk must be launched directly.
 template <class F>
 static bool graph_chunk(bddc_ctx* h, hipStream_t st, F&& enqueue) {
-  if (h->graph_off || timing::active()) return false;
+  if (h->graph_off || h->noalloc_now || timing::active()) return false;
   // cooperative launches are issued directly, not replayed from a graph
   if (h->coop_shared && h->deep_sel == BDDC_DEEP_COOP) return false;
   if (!h->graph_exec) {
@@ -1931,6 +1932,7 @@ static void lay_columns(bddc_ctx* h, Arena& A, int R) {
 // it is dropped).
 static void ensure_columns(bddc_ctx* h, int R) {
   if (h->cols_cap >= R) return;
+  if (h->noalloc_now) fail(BDDC_EUNSUPPORTED, "the no-allocation solve needs more columns than it laid out");
   BDDC_HIP(hipStreamSynchronize(h->stream));
   h->cols_arena.release(h->stream);
   if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
@@ -2041,7 +2043,7 @@ static int pcg_block(bddc_ctx* h, const double* f, double* u, int64_t ld, int R,
   };
   // z_0 = M r_0 and its r.z partials (parity 0)
   apply_iface(st, -1, 0);
-  if (h->graph_exec && h->graph_nrhs != R) {
+  if (h->graph_exec && h->graph_nrhs != R && !h->noalloc_now) {
     (void)hipGraphExecDestroy(h->graph_exec);
     h->graph_exec = nullptr;
   }
@@ -2586,6 +2588,76 @@ bddc_status bddc_solve(bddc_handle h, const double* f, double* u, int32_t nrhs, 
         noconv = true;
     }
     h->stream = saved;
+  });
+  if (st == BDDC_OK && noconv) return BDDC_ENOCONV;
+  return st;
+}
+
+bddc_status bddc_solve_noalloc(bddc_handle h, const double* f, double* u, int32_t nrhs, int64_t ld, double rtol,
+                               int32_t maxit, int32_t* iters, double* relres, void* hip_stream) {
+  bool noconv = false;
+  bddc_status st = guard([&] {
+    if (!h || !f || !u || nrhs < 0 || ld < h->n_free || !(rtol >= 0) || maxit < 0 || !iters || !relres)
+      fail(BDDC_EINVAL, "bad solve arguments");
+    if (maxit > kMaxHist) fail(BDDC_EINVAL, "maxit too large");
+    int dev = -1;
+    BDDC_HIP(hipGetDevice(&dev));
+    if (dev != h->device) fail(BDDC_EINVAL, "the current device is not the handle's device");
+    size_t limit = BDDC_NOALLOC_SCRATCH_BYTES;
+    if (const char* env = getenv("BDDC_NOALLOC_LIMIT")) {   // a lower limit, for tests of the size check
+      const long long v = atoll(env);
+      if (v > 0) limit = std::min(limit, (size_t)v);
+    }
+    // the caller's layout and the captured chunk stay as they are: the state
+    // of this call is laid out in the scratch array and put back at the end
+    struct Restore {
+      bddc_ctx* h;
+      PcgDev pcg;
+      double *cy, *ct;
+      int ld_cy, cols_cap;
+      hipStream_t stream;
+      ~Restore() {
+        h->pcg = pcg;
+        h->cy = cy;
+        h->ct = ct;
+        h->ld_cy = ld_cy;
+        h->cols_cap = cols_cap;
+        h->stream = stream;
+        h->noalloc_now = false;
+      }
+    } restore{h, h->pcg, h->cy, h->ct, h->ld_cy, h->cols_cap, h->stream};
+    // the widest block of columns whose state fits the scratch
+    int blk = 0;
+    size_t one = 0;
+    for (int R = std::min<int>(kMaxRhs, std::max(1, nrhs)); R >= 1 && blk == 0; --R) {
+      Arena A;
+      A.reset_sizing();
+      lay_columns(h, A, R);
+      if (R == 1) one = A.used();
+      if (A.used() <= limit) blk = R;
+    }
+    if (blk == 0)
+      fail(BDDC_EUNSUPPORTED, "one column of PCG state needs " + std::to_string(one) + " bytes, more than the " +
+                                  std::to_string(limit) + " bytes of the no-allocation scratch");
+    if (nrhs == 0) return;
+    void* base = noalloc_scratch();
+    h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    h->noalloc_now = true;
+    Arena A;
+    A.reset_sizing();
+    lay_columns(h, A, blk);
+    const size_t used = A.used();
+    A.attach(base);
+    lay_columns(h, A, blk);
+    A.detach();
+    h->cols_cap = blk;
+    // earlier calls (any handle) left their state in the array: start from zeros
+    launch_zero_bytes(h->stream, base, used);
+    for (int c = 0; c < nrhs; c += blk) {
+      const int R = std::min(blk, nrhs - c);
+      if (pcg_block(h, f + (size_t)c * ld, u + (size_t)c * ld, ld, R, rtol, maxit, iters + c, relres + c) > 0)
+        noconv = true;
+    }
   });
   if (st == BDDC_OK && noconv) return BDDC_ENOCONV;
   return st;

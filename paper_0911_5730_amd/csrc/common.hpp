@@ -63,6 +63,13 @@ class Arena {
     base_ = nullptr;
   }
   size_t size() const { return size_; }
+  // lay pieces out in memory the arena does not own (its size checked by the
+  // caller against used() of a sizing pass); detach() forgets it again
+  void attach(void* base) {
+    base_ = static_cast<char*>(base);
+    used_ = 0;
+  }
+  void detach() { base_ = nullptr; }
 
  private:
   char* base_ = nullptr;

@@ -137,6 +137,11 @@ struct CoopDev {
 size_t coop_lds(const CoopDev& C);
 void launch_deep_coop(hipStream_t st, const CoopDev& C, bool cooperative);
 void launch_coop_reset(hipStream_t st, const CoopDev& C);
+
+// The fixed working array of the no-allocation solve: its device address on
+// the current device, and a kernel that zeroes the first `bytes` of a buffer.
+void* noalloc_scratch();
+void launch_zero_bytes(hipStream_t st, void* p, size_t bytes);
 void launch_pack_coop(hipStream_t st, const LevelDev& L, const CoopDev& C);
 void launch_tri_inverse_dense(hipStream_t st, const double* L, int ld, int m, double* X);
 int coop_max_blocks(size_t lds);
