@@ -8,6 +8,7 @@
 // bddc_apply runs Algorithm "Multilevel BDDC"; bddc_solve runs PCG on the
 // level-1 interface (Section 5, reduction of level 1 to the interfaces).
 #include <atomic>
+#include <climits>
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -278,11 +279,21 @@ constexpr size_t kLdsLimit = 64 * 1024 - 1024;   // dynamic LDS of the kernels s
 constexpr size_t kLdsMax = 160 * 1024;          // LDS of one CU, all of it usable by one block on gfx950
 
 // Interior elimination: 64-wide LDS panels with an MFMA trailing update, unless
-// the substructure is too large for a 16-wide panel in LDS or BDDC_CHOL_PATH=lds16.
+// the substructure is too large for a 16-wide panel in LDS or BDDC_CHOL_PATH=lds16
+// (16-wide panels on the vector units) or =big.
 bool use_mfma_chol(int nmax) {
   const char* env = getenv("BDDC_CHOL_PATH");
-  if (env && std::string(env) == "lds16") return false;
+  if (env && (std::string(env) == "lds16" || std::string(env) == "big")) return false;
   return partial_chol_mfma_nb(nmax) >= 16 && partial_chol_mfma_lds(nmax) <= kLdsMax;
+}
+
+// Local matrices too large for the panel kernels (or BDDC_CHOL_PATH=big): the
+// left-looking tiled elimination, whose LDS does not depend on the size.
+bool use_big_chol(int nmax) {
+  const char* env = getenv("BDDC_CHOL_PATH");
+  if (env && std::string(env) == "big") return true;
+  if (env && std::string(env) == "lds16") return false;
+  return !use_mfma_chol(nmax);
 }
 
 // Level-1 interior sweeps streamed through LDS panels unless the substructures
@@ -393,8 +404,13 @@ struct Level {
     double *y, *t, *a, *v, *b, *rc, *uc, *qloc;
     double* Linv;
     int64_t* linvoff;
+    // tiled elimination (large local matrices): envelope per row tile, inverses of the diagonal tiles
+    int32_t *tprof, *tproff;
+    double* Wd;
+    int64_t* woff;
   } d{};
   std::vector<int64_t> linvoff;
+  bool big = false;   // interior elimination by the tiled kernel
   LevelDev dev;
 };
 
@@ -803,7 +819,7 @@ class Builder {
   hipStream_t st_;
 
   void check_limits(const Level& lv) {
-    if (partial_chol_lds(lv.nmax) > kLdsMax && !use_mfma_chol(lv.nmax))
+    if (partial_chol_lds(lv.nmax) > kLdsMax && !use_mfma_chol(lv.nmax) && !use_big_chol(lv.nmax))
       fail(BDDC_EUNSUPPORTED, "substructure too large for this build");
   }
 
@@ -866,6 +882,50 @@ class Builder {
     lv.linvoff.assign(nsub + 1, 0);
     if (prev)
       for (int s = 0; s < nsub; ++s) lv.linvoff[s + 1] = lv.linvoff[s] + (int64_t)T.n_int[s] * T.n_int[s];
+    // tiled elimination: per row tile of 64 local dofs (interior tiles, then
+    // interface tiles) the first interior column tile of the envelope of the
+    // local matrix, i.e. of its factor (fill stays right of each row's first
+    // nonzero); found from the elements at level 1, every tile at other levels
+    std::vector<int32_t> tproff, tprof;
+    std::vector<int64_t> woff;
+    lv.big = use_big_chol(lv.nmax);
+    if (lv.big) {
+      constexpr int kT = 64;
+      tproff.assign(nsub + 1, 0);
+      woff.assign(nsub + 1, 0);
+      for (int s = 0; s < nsub; ++s) {
+        const int nbI = (T.n_int[s] + kT - 1) / kT, nbG = (T.ngam(s) + kT - 1) / kT;
+        tproff[s + 1] = tproff[s] + nbI + nbG;
+        woff[s + 1] = woff[s] + (int64_t)nbI * kT * kT;
+      }
+      tprof.assign(tproff[nsub], 0);
+      if (G)
+        parallel_for(nsub, 4, [&](int s0, int s1) {
+          std::vector<int> f;
+          for (int s = s0; s < s1; ++s) {
+            const int n = T.nloc(s), nI = T.n_int[s];
+            f.assign(n, INT32_MAX);
+            for (int k = sub_el_ptr[s]; k < sub_el_ptr[s + 1]; ++k) {
+              const int32_t* loc = &el_loc[(size_t)k * 4];
+              int mn = INT32_MAX;
+              for (int q = 0; q < 4; ++q)
+                if (loc[q] >= 0 && loc[q] < nI) mn = std::min(mn, (int)loc[q]);
+              if (mn == INT32_MAX) continue;
+              for (int q = 0; q < 4; ++q)
+                if (loc[q] >= 0) f[loc[q]] = std::min(f[loc[q]], mn);
+            }
+            const int nbI = (nI + kT - 1) / kT;
+            int32_t* pr = &tprof[tproff[s]];
+            for (int t = 0; t < tproff[s + 1] - tproff[s]; ++t) {
+              const int r0 = t < nbI ? t * kT : nI + (t - nbI) * kT;
+              const int r1 = t < nbI ? std::min(nI, r0 + kT) : std::min(n, r0 + kT);
+              int mn = INT32_MAX;
+              for (int r = r0; r < r1; ++r) mn = std::min(mn, f[r]);
+              pr[t] = mn == INT32_MAX ? nbI : mn / kT;
+            }
+          }
+        });
+    }
 
     clk.lap("  maps");
     Arena& A = lv.arena_a;
@@ -933,6 +993,10 @@ class Builder {
       d.qloc = A.take<double>(lv.nflat_g);
       d.Linv = A.take<double>((size_t)lv.linvoff[nsub]);
       d.linvoff = A.take<int64_t>(nsub + 1);
+      d.tprof = A.take<int32_t>(tprof.size());
+      d.tproff = A.take<int32_t>(tproff.size());
+      d.Wd = A.take<double>(woff.empty() ? 0 : (size_t)woff.back());
+      d.woff = A.take<int64_t>(woff.size());
     };
     A.reset_sizing();
     layout(false);
@@ -984,6 +1048,11 @@ class Builder {
     stg.add(d.edge_dof, edge_dof);
     stg.add(d.floating, floating);
     stg.add(d.inc_off, lv.inc_off);
+    if (lv.big) {
+      stg.add(d.tprof, tprof);
+      stg.add(d.tproff, tproff);
+      stg.add(d.woff, woff);
+    }
     if (adaptive) {
       stg.add(d.schws_off, lv.schws_off);
       stg.add(d.eigws_off, lv.eigws_off);
@@ -1031,7 +1100,18 @@ class Builder {
       double by = 0;
       for (int s = 0; s < lv.nsub; ++s) by += 16.0 * T.nloc(s) * T.nloc(s);
       timing::Scope ts(lv.ell == 1 ? "partial_chol" : "partial_chol_l2", by, fl);
-      if (use_mfma_chol(lv.nmax))
+      if (lv.big) {
+        LevelDev D{};
+        D.nsub = lv.nsub;
+        D.koff = d.koff;
+        D.loc_ptr = d.loc_ptr;
+        D.nint = d.nint;
+        D.tprof = d.tprof;
+        D.tproff = d.tproff;
+        D.woff = d.woff;
+        launch_partial_chol_big(st_, D, d.K, d.Wd, h_->status);
+      }
+      else if (use_mfma_chol(lv.nmax))
         launch_partial_chol_mfma(st_, lv.nsub, lv.nmax, d.koff, d.loc_ptr, d.nint, d.K, h_->status);
       else
         launch_partial_chol(st_, lv.nsub, lv.nmax, d.koff, d.loc_ptr, d.nint, d.K, h_->status);
@@ -1268,6 +1348,10 @@ class Builder {
     D.psioff = d.psioff;
     D.Linv = d.Linv;
     D.linvoff = d.linvoff;
+    D.tprof = lv.big ? d.tprof : nullptr;
+    D.tproff = lv.big ? d.tproff : nullptr;
+    D.Wd = lv.big ? d.Wd : nullptr;
+    D.woff = lv.big ? d.woff : nullptr;
     D.csh_ptr = d.csh_ptr;
     D.csh_flat = d.csh_flat;
     D.y = d.y;
@@ -1978,16 +2062,18 @@ static int pcg_block(bddc_ctx* h, const double* f, double* u, int64_t ld, int R,
   // substructures, else the blocked triangular solves when kMaxRhs columns fit
   // the LDS, else column by column
   const bool sweep = use_sweep(l1.nmax);
-  const bool blocked = !sweep && apply_cols_lds(kMaxRhs, l1.nImax, l1.ngmax) <= kLdsMax;
+  const bool tiles = !sweep && l1.big;   // the tiled factor of large substructures: block substitution
+  const bool blocked = !sweep && !tiles && apply_cols_lds(kMaxRhs, l1.nImax, l1.ngmax) <= kLdsMax;
   if (sweep) launch_sweep_pre_cols(st, l1.dev, f, ld, h->cy, h->ld_cy, h->ct, P.ld_flat, R);
+  if (tiles) launch_tile_pre_cols(st, l1.dev, f, ld, h->cy, h->ld_cy, h->ct, P.ld_flat, R);
   if (blocked) launch_apply_pre_cols(st, l1.dev, l1.nImax, l1.ngmax, f, ld, h->cy, h->ld_cy, h->ct, P.ld_flat, R);
   for (int c = 0; c < R; ++c) {
     const double* fc = f + (size_t)c * ld;
     double* rc = P.r[0] + (size_t)c * P.ld_if;
     launch_dot_partial(st, nbf, (int)h->n_free, fc, fc, h->partial);
     launch_scalar(st, 4, nbf, h->partial, P.sc + c);                 // bb, thr2 = rtol^2 bb
-    if (!sweep && !blocked) launch_apply_pre(st, l1.dev, l1.nImax, l1.ngmax, fc);
-    const double* tc = sweep || blocked ? h->ct + (size_t)c * P.ld_flat : l1.d.t;
+    if (!sweep && !tiles && !blocked) launch_apply_pre(st, l1.dev, l1.nImax, l1.ngmax, fc);
+    const double* tc = sweep || tiles || blocked ? h->ct + (size_t)c * P.ld_flat : l1.d.t;
     launch_condense(st, nif, l1.d.sh_ptr, l1.d.sh_flat, l1.d.iface_dof, fc, tc, rc, P.x + (size_t)c * P.ld_if);
     launch_dot_partial(st, nb, nif, rc, rc, h->partial);
     launch_scalar(st, 5, nb, h->partial, P.sc + c);                  // rr0, done if already small
@@ -2068,6 +2154,8 @@ static int pcg_block(bddc_ctx* h, const double* f, double* u, int64_t ld, int R,
   L1.stop = nullptr;
   if (sweep) {
     launch_sweep_recover_cols(st, L1, P.x, P.ld_if, h->cy, h->ld_cy, u, ld, R);
+  } else if (tiles) {
+    launch_tile_recover_cols(st, L1, P.x, P.ld_if, h->cy, h->ld_cy, u, ld, R, l1.ngmax);
   } else if (blocked) {
     launch_recover_cols(st, L1, l1.nImax, l1.ngmax, P.x, P.ld_if, h->cy, h->ld_cy, u, ld, R);
   } else {

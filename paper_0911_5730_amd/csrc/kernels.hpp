@@ -72,6 +72,15 @@ struct LevelDev {
   const int64_t* linvoff = nullptr;
   const int32_t* csh_ptr = nullptr;   // coarse dof -> local coarse flat entries (sharers)
   const int32_t* csh_flat = nullptr;
+  // tiled elimination of large local matrices (64 x 64 tiles): per row tile
+  // (interior tiles, then interface tiles) the first interior column tile that
+  // holds a nonzero of the factor (the envelope; null = every tile), offsets
+  // tproff; and the inverses of the interior diagonal tiles of L_II (64 x 64
+  // column-major each), offsets woff
+  const int32_t* tprof = nullptr;
+  const int32_t* tproff = nullptr;
+  const double* Wd = nullptr;
+  const int64_t* woff = nullptr;
 };
 
 // All levels >= 2 and the coarsest solve in one workgroup (used when they are small).
@@ -273,6 +282,17 @@ void launch_assemble_coarse(hipStream_t st, int nsub, const int64_t* koff, const
                             const int32_t* goff);
 void launch_weights(hipStream_t st, int nflat, const int32_t* flat_iid, const int32_t* sh_ptr,
                     const int32_t* sh_flat, const double* diagK, double* delta);
+// local matrices of any size: left-looking blocked elimination with 64 x 64
+// tiles staged in LDS and FP64 MFMA products (k_bigchol.hip)
+void launch_partial_chol_big(hipStream_t st, const LevelDev& L, double* K, double* Wd, int* status);
+// interior solves of many columns with the tiled factor (k_tile.hip):
+//   pre:     y = L_II^-1 r_I, t = L_GI y  (condensation / interior pre-correction)
+//   recover: u_G = x, u_I = L_II^-T (y - L_GI^T x)
+void launch_tile_pre_cols(hipStream_t st, const LevelDev& L, const double* r, int64_t ldr, double* y, int ldy,
+                          double* t, int ldt, int R);
+void launch_tile_recover_cols(hipStream_t st, const LevelDev& L, const double* x, int ldx, const double* y, int ldy,
+                              double* u, int64_t ldu, int R, int ngmax);
+size_t partial_chol_big_lds();
 void launch_partial_chol(hipStream_t st, int nsub, int nmax, const int64_t* koff, const int32_t* loc_ptr,
                          const int32_t* nint, double* K, int* status);
 size_t partial_chol_lds(int nmax);

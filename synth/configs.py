@@ -131,13 +131,16 @@ def square_problem(nx: int, nsx: int, *, ny: Optional[int] = None, nsy: Optional
                    name=name, meta={"channels": ch, "nsx": nsx, "nsy": nsy, "groups": groups})
 
 
-def voronoi_partition(rng: np.random.Generator, nx: int, ny: int, nsub: int, jitter: bool = False):
+def voronoi_partition(rng: np.random.Generator, nx: int, ny: int, nsub: int, jitter: bool = False,
+                      lloyd: int = 0):
     """Element -> region of the nearest of `nsub` seed points drawn uniformly in
     the unit square (nearest to the element centre, ties to the lower seed).
     With `jitter` (nsub a square q^2), one seed is drawn uniformly in each cell
     of a q x q grid of the unit square instead, which bounds the spread of the
-    region sizes.  Seeds whose region holds no element are dropped and the ids
-    renumbered in seed order.  Returns (part, seed points of the kept regions)."""
+    region sizes.  `lloyd` relaxation steps then move every seed to the mean
+    element centre of its region and reassign (no random draws).  Seeds whose
+    region holds no element are dropped and the ids renumbered in seed order.
+    Returns (part, seed points of the kept regions)."""
     from scipy.spatial import cKDTree
 
     if jitter:
@@ -150,7 +153,16 @@ def voronoi_partition(rng: np.random.Generator, nx: int, ny: int, nsub: int, jit
     cx = (np.arange(nx) + 0.5) / nx
     cy = (np.arange(ny) + 0.5) / ny
     X, Y = np.meshgrid(cx, cy)
-    _, near = cKDTree(pts).query(np.column_stack([X.reshape(-1), Y.reshape(-1)]))
+    centres = np.column_stack([X.reshape(-1), Y.reshape(-1)])
+    _, near = cKDTree(pts).query(centres)
+    for _ in range(lloyd):
+        cnt = np.bincount(near, minlength=len(pts)).astype(np.float64)
+        keep = cnt > 0
+        moved = pts.copy()
+        moved[keep] = np.column_stack([np.bincount(near, centres[:, 0], len(pts))[keep] / cnt[keep],
+                                       np.bincount(near, centres[:, 1], len(pts))[keep] / cnt[keep]])
+        pts = moved
+        _, near = cKDTree(pts).query(centres)
     used = np.unique(near)
     remap = np.full(nsub, -1, dtype=np.int64)
     remap[used] = np.arange(used.size)
@@ -227,7 +239,7 @@ def _connected_groups(part2d: np.ndarray, nsub: int, group: np.ndarray) -> np.nd
 def voronoi_problem(nx: int, nsub: int, *, levels: int = 2, ngroups: int = 1, constraints: str = "corners",
                     tau: float = float("inf"), kmode: str = "one", kmax_exp: float = 0.0, channels: int = 0,
                     nrhs: int = 1, seed: int = 0, element: str = "Q1", name: str = "",
-                    jitter: bool = False) -> Problem:
+                    jitter: bool = False, lloyd: int = 0) -> Problem:
     """A seeded problem on an irregular partition of uneven substructures:
     Voronoi regions of `nsub` uniform seed points (level 1) and, for three
     levels, Voronoi groups of their centroids around `ngroups` further seeds.
@@ -242,7 +254,7 @@ def voronoi_problem(nx: int, nsub: int, *, levels: int = 2, ngroups: int = 1, co
     else:
         raise ValueError(kmode)
     ch = add_channels(rng, nx, ny, coeff, count=channels) if channels else []
-    part, _ = voronoi_partition(rng, nx, ny, nsub, jitter=jitter)
+    part, _ = voronoi_partition(rng, nx, ny, nsub, jitter=jitter, lloyd=lloyd)
     nkept = int(part.max()) + 1
     agg = [voronoi_agglomeration(rng, nx, ny, part, nkept, ngroups, jitter=jitter)] if levels == 3 else []
     nfree = (nx - 1) * (ny - 1)
@@ -259,8 +271,8 @@ CONFIG_NAMES = {
     2: "adaptive three-level, 256x256 Q1, 16x16 subs (H/h=16), 4x4 groups, "
        "k=10^U(0,6) + 8 channels k=1e6, tau=10",
     3: "adaptive three-level, 1024x1024 Q1, 64x64 subs (H/h=16), 16x16 groups, k=1, tau=10",
-    4: "adaptive three-level, 2048x2048 Q1, 9216 jittered Voronoi regions (152-927 dofs), 576 Voronoi groups, "
-       "k=10^U(0,4), tau=10",
+    4: "adaptive three-level, 2048x2048 Q1, 1024 Voronoi regions (jittered seeds, 3 Lloyd steps; about "
+       "3000-5700 local dofs), 16 Voronoi groups, k=10^U(0,4), tau=10",
 }
 
 
@@ -278,10 +290,12 @@ def config(cid: int, nrhs: int = 1) -> Problem:
         return square_problem(1024, 64, levels=3, groups=(4, 4), constraints="adaptive",
                               tau=10.0, kmode="one", nrhs=nrhs, seed=seed, name="config3")
     if cid == 4:
-        # the batching form's uneven substructures, with regions small enough
-        # for dense local factors (one seed uniform in each of 96 x 96 cells)
-        return voronoi_problem(2048, 96 * 96, levels=3, ngroups=24 * 24, constraints="adaptive", tau=10.0,
-                               kmode="loguniform", kmax_exp=4.0, nrhs=nrhs, seed=seed, jitter=True, name="config4")
+        # the batching form: about 1024 uneven substructures of 1500-6000
+        # local dofs (one seed uniform in each of 32 x 32 cells, then three
+        # Lloyd steps), 16 level-2 groups
+        return voronoi_problem(2048, 32 * 32, levels=3, ngroups=4 * 4, constraints="adaptive", tau=10.0,
+                               kmode="loguniform", kmax_exp=4.0, nrhs=nrhs, seed=seed, jitter=True, lloyd=3,
+                               name="config4")
     raise ValueError(f"unknown config {cid}")
 
 

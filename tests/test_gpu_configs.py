@@ -11,9 +11,10 @@
   assembled matrix (at most 1e-8), and the interior-edge pair eigenvalues,
   which for k = 1 coincide with those of the same floating pair in a 4 x 4
   partition that the oracle solves.
-* 2048 x 2048, uneven Voronoi regions, eight loads: the true residual of
-  every column, the energy-norm error of the FP32 form against the FP64 path
-  converged to 1e-12, and a column solved alone against the blocked column.
+* 2048 x 2048, 1024 uneven Voronoi regions of 3000-5700 dofs, eight loads:
+  the true residual of every column, the energy-norm error of the FP32 form
+  against the FP64 path converged to 1e-12, and a column solved alone
+  against the blocked column.
 """
 
 import numpy as np
@@ -117,11 +118,16 @@ def _edge_index(S, key):
 
 
 def test_config4_uneven_substructures_eight_loads():
-    """2048 x 2048 (4.2M unknowns), 9216 jittered Voronoi regions of 152-927
-    dofs, 576 Voronoi groups, adaptive tau = 10, k = 10^U(0,4), eight loads in
-    one blocked solve in the FP32 form: every column converges with a true
-    residual of the solve's tolerance (checked with the oracle's assembled
-    matrix), and one column solved alone gives bitwise the blocked column."""
+    """2048 x 2048 (4.2M unknowns), 1024 Voronoi regions of about 3000-5700
+    local dofs (interior elimination by the tiled MFMA kernel, interior
+    solves by tiled block substitution), 16 Voronoi groups, adaptive
+    tau = 10, k = 10^U(0,4), eight loads in one blocked solve in the FP32
+    form: every column converges with a true residual of the solve's
+    tolerance (checked with the oracle's assembled matrix) and lies within
+    1e-8 in the energy norm of the FP64 path converged to 1e-12, and one
+    column solved alone gives bitwise the blocked column.  The two forms are
+    set up one after the other (each holds about 160 GB of dense local
+    matrices)."""
     import time
 
     import torch

@@ -219,7 +219,7 @@ def test_pcg_graph_replays_match_direct_launches(deep, monkeypatch):
 
 
 @pytest.mark.parametrize("path", ["default", "lds16_global", "sweep32", "eig_workgroup", "pair_global",
-                                  "pcg_ops_full"])
+                                  "pcg_ops_full", "chol_big"])
 def test_setup_kernel_paths(path, monkeypatch):
     """The setup runs with 64-wide Cholesky panels and a matrix-core trailing
     update plus LDS-resident Gauss-Jordan factorizations, and the level-1
@@ -231,7 +231,10 @@ def test_setup_kernel_paths(path, monkeypatch):
     eigenproblems work in LDS (default) or in a global workspace (used for
     interfaces and edges too large for LDS).  The PCG operators S_s and T_rr
     are packed lower triangles (default here) or full matrices (the form of
-    interfaces wider than 64 dofs).  All must give the oracle's
+    interfaces wider than 64 dofs).  The interior elimination of local
+    matrices too large for LDS panels (64 x 64 tiles, left-looking, MFMA, the
+    envelope's zero tiles skipped) and the block substitutions of the
+    condensation and recovery with its tiles are forced here on every level.  All must give the oracle's
     preconditioner and solution (H/h = 16, ragged 64-column panels)."""
     if path == "lds16_global":
         monkeypatch.setenv("BDDC_CHOL_PATH", "lds16")
@@ -245,6 +248,9 @@ def test_setup_kernel_paths(path, monkeypatch):
         monkeypatch.setenv("BDDC_PAIR_WS", "global")
     if path == "pcg_ops_full":
         monkeypatch.setenv("BDDC_PCG_OPS", "full")
+    if path == "chol_big":
+        monkeypatch.setenv("BDDC_CHOL_PATH", "big")
+        monkeypatch.setenv("BDDC_SWEEP", "off")   # the tiled interior solves of the condensation and recovery
     prob = _case("adaptive3_h16")
     print(f"setup kernel path {path}", flush=True)
     S, B, ug, it, rr, o = run_pair(prob)
