@@ -225,16 +225,17 @@ def batching_form(P, synth, torch, stream, precs=("fp32", "fp64")) -> dict:
     return out
 
 
-def serving(synth, count: int = 40, rate: float = 200.0, slots: int = 2, precision: str = "fp32",
-            problems=None, resident: bool = False) -> dict:
-    """A seeded Poisson stream of requests (grid side 128 or 256, H/h 8 or 16,
-    2-3 levels, k = 10^U(0,m), m in 0..6, 1-4 right-hand sides, adaptive
-    tau = 10) submitted at their arrival times to the serving loop; with
-    `problems`, the requests share that many problems (loads of their own),
-    and with `resident` the server keeps set-up problems and merges the
-    pending loads of one problem into one blocked solve."""
+def serving(synth, count: int = 40, rate: float = 200.0, slots: int = 4, precision: str = "fp32",
+            problems=None, resident: bool = False, full: bool = False) -> dict:
+    """A seeded Poisson stream of requests submitted at their arrival times to
+    the continuous-batching server.  full: the serving workload (grid side
+    128-1024, H/h 8-32, two or three levels, k = 10^U(0,m), m in 0..6, 1-16
+    right-hand sides, adaptive tau = 10); else sides 128/256, H/h 8/16, 1-4
+    right-hand sides, and with `problems` the requests share that many
+    problems (loads of their own), kept set up with `resident`."""
     from paper_0911_5730_amd.serve import Request, Server
-    stream = synth.request_stream(count, rate=rate, problems=problems)
+    stream = (synth.serving_stream(count, rate=rate) if full
+              else synth.request_stream(count, rate=rate, problems=problems))
     srv = Server(slots=slots, resident=resident)
     try:
         t0 = srv.now()
@@ -522,20 +523,24 @@ def main():
     }
     gpu_rates = {}
     if not args.no_serving:
-        out["serving"] = {"two_slots": serving(synth, slots=2), "one_slot": serving(synth, slots=1),
-                          "shared_problems": serving(synth, count=120, rate=2000.0, slots=2, problems=4),
-                          "shared_problems_resident": serving(synth, count=120, rate=2000.0, slots=2, problems=4,
+        out["serving"] = {"config5": serving(synth, count=60, full=True),
+                          "config5_one_slot": serving(synth, count=60, full=True, slots=1),
+                          "shared_problems": serving(synth, count=120, rate=2000.0, problems=4),
+                          "shared_problems_resident": serving(synth, count=120, rate=2000.0, problems=4,
                                                               resident=True),
-                          "note": "requests/s over the stream and arrival-to-completion latency; each request is "
-                                  "set up, solved to 1e-8 and released on a slot with its own stream; "
-                                  "shared_problems: 120 requests at 2000/s over 4 problems (loads of their own), "
+                          "note": "requests/s (and right-hand sides/s) over the stream and arrival-to-completion "
+                                  "latency; config5: 60 requests of the serving workload at 200/s, set up when "
+                                  "their HBM footprint fits, solved stepwise (up to 4 solves in flight, new ones "
+                                  "joining between chunks of 8 iterations), mixed precision, rtol 1e-8; one_slot: "
+                                  "one solve in flight; shared_problems: 120 requests at 2000/s over 4 problems, "
                                   "_resident: set-up problems kept and pending loads of one problem merged into "
                                   "one blocked solve"}
         sv = out["serving"]
-        log(f"bench: serving {sv['two_slots']['solves_per_s']:.1f} req/s (two slots); shared problems "
-            f"{sv['shared_problems']['solves_per_s']:.1f} req/s, resident {sv['shared_problems_resident']['solves_per_s']:.1f}"
-            f" req/s (p99 {sv['shared_problems']['latency_ms']['p99']:.1f} -> "
-            f"{sv['shared_problems_resident']['latency_ms']['p99']:.1f} ms)")
+        log(f"bench: serving config 5: {sv['config5']['solves_per_s']:.1f} req/s, p50/p99 "
+            f"{sv['config5']['latency_ms']['p50']:.1f}/{sv['config5']['latency_ms']['p99']:.1f} ms (one solve in "
+            f"flight: {sv['config5_one_slot']['solves_per_s']:.1f} req/s); shared problems "
+            f"{sv['shared_problems']['solves_per_s']:.1f} req/s, resident "
+            f"{sv['shared_problems_resident']['solves_per_s']:.1f} req/s")
     if not args.no_precision_forms:
         c2 = precision_forms(P, synth, torch, 2, stream)
         gpu_rates["config2_fp64"] = c2["fp64"]["solves_per_s"]

@@ -44,7 +44,7 @@ typedef enum {
   BDDC_EPARTITION = -4,   /* partition or agglomeration invalid (id out of range, empty substructure) */
   BDDC_ENOCONV = -5,      /* PCG reached maxit; u holds the last iterate */
   BDDC_EDEVICE = -6,      /* a HIP runtime call failed */
-  BDDC_EBUSY = -7,        /* reserved for admission control */
+  BDDC_EBUSY = -7,        /* the handle has a stepwise solve in progress */
   BDDC_EUNSUPPORTED = -8  /* valid input outside what this build implements (sizes, precision) */
 } bddc_status;
 
@@ -100,8 +100,10 @@ typedef struct {
 
 /* Validate a problem and report its level-1 topology (n_free, nsub, interface,
  * corner and edge counts) without touching the device.  Only level 1 is filled
- * (levels beyond 1 depend on the coarse dofs chosen at set-up).
- * Errors: BDDC_EINVAL, BDDC_EPARTITION, BDDC_EUNSUPPORTED. */
+ * (levels beyond 1 depend on the coarse dofs chosen at set-up), and
+ * device_bytes holds the device memory a set-up of it will need (estimated
+ * from the level-1 sizes, with a margin for the deeper levels), for admission
+ * control.  Errors: BDDC_EINVAL, BDDC_EPARTITION, BDDC_EUNSUPPORTED. */
 bddc_status bddc_plan(const bddc_problem* p, bddc_info* info);
 
 /* Set up the preconditioner (Section 5, adaptive setup algorithm, then the
@@ -149,6 +151,33 @@ bddc_status bddc_solve(bddc_handle h, const double* f, double* u, int32_t nrhs, 
  * the array), BDDC_ENOCONV, BDDC_EDEVICE. */
 bddc_status bddc_solve_noalloc(bddc_handle h, const double* f, double* u, int32_t nrhs, int64_t ld,
                                double rtol, int32_t maxit, int32_t* iters, double* relres, void* hip_stream);
+
+/* Stepwise bddc_solve, for serving loops that interleave several solves and
+ * admit new ones between chunks of iterations (Section 5's PCG, the same
+ * launches and bitwise the same results as bddc_solve).
+ *   bddc_solve_begin:   enqueue the condensation, r_0 and z_0 of nrhs (1..8)
+ *                       columns of f (device, leading dimension ld) on
+ *                       hip_stream, which the handle keeps until the end.
+ *   bddc_solve_advance: enqueue at least `iterations` more iterations (whole
+ *                       chunks; none past maxit or convergence do work), then
+ *                       an asynchronous copy of the convergence flags.
+ *   bddc_solve_poll:    without waiting: *state = 1 when the iterations
+ *                       enqueued so far finished every column (or reached
+ *                       maxit), 0 when more are needed, -1 while the last
+ *                       advance is still running.
+ *   bddc_solve_end:     recover the interior into u (device, ld), write the
+ *                       host arrays iters[nrhs] and relres[nrhs], synchronise;
+ *                       BDDC_ENOCONV if a column did not converge.
+ * f must stay valid until bddc_solve_end.  While a stepwise solve is in
+ * progress, bddc_solve, bddc_solve_noalloc, bddc_apply, bddc_autotune and a
+ * second bddc_solve_begin on the handle return BDDC_EBUSY.
+ * Errors: BDDC_EINVAL (arguments, or no stepwise solve in progress),
+ * BDDC_EBUSY, BDDC_ENOCONV, BDDC_EDEVICE. */
+bddc_status bddc_solve_begin(bddc_handle h, const double* f, int32_t nrhs, int64_t ld, double rtol, int32_t maxit,
+                             void* hip_stream);
+bddc_status bddc_solve_advance(bddc_handle h, int32_t iterations);
+bddc_status bddc_solve_poll(bddc_handle h, int32_t* state);
+bddc_status bddc_solve_end(bddc_handle h, double* u, int64_t ld, int32_t* iters, double* relres);
 
 /* Sizes and diagnostics.  Errors: BDDC_EINVAL. */
 bddc_status bddc_query(bddc_handle h, bddc_info* info);

@@ -54,7 +54,8 @@ class BddcTuningC(ctypes.Structure):
 
 DEEP_PATHS = ("coop", "wide", "fused", "levels")
 
-SYMBOLS = ["bddc_plan", "bddc_setup", "bddc_apply", "bddc_solve", "bddc_solve_noalloc", "bddc_query", "bddc_edge_eigs",
+SYMBOLS = ["bddc_plan", "bddc_setup", "bddc_apply", "bddc_solve", "bddc_solve_noalloc", "bddc_solve_begin",
+           "bddc_solve_advance", "bddc_solve_poll", "bddc_solve_end", "bddc_query", "bddc_edge_eigs",
            "bddc_edge_constraints", "bddc_corners", "bddc_timing_start", "bddc_timing_stop", "bddc_get_tuning",
            "bddc_set_tuning", "bddc_autotune", "bddc_last_error", "bddc_status_string", "bddc_destroy"]
 
@@ -81,6 +82,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.bddc_apply.argtypes = [vp, vp, vp, i32, i64, vp]
     lib.bddc_solve.argtypes = [vp, vp, vp, i32, i64, dbl, i32, P(i32), P(dbl), vp]
     lib.bddc_solve_noalloc.argtypes = [vp, vp, vp, i32, i64, dbl, i32, P(i32), P(dbl), vp]
+    lib.bddc_solve_begin.argtypes = [vp, vp, i32, i64, dbl, i32, vp]
+    lib.bddc_solve_advance.argtypes = [vp, i32]
+    lib.bddc_solve_poll.argtypes = [vp, P(i32)]
+    lib.bddc_solve_end.argtypes = [vp, vp, i64, P(i32), P(dbl)]
     lib.bddc_query.argtypes = [vp, P(BddcInfoC)]
     lib.bddc_edge_eigs.argtypes = [vp, i32, i32, P(dbl), i32, P(i32), P(i32), P(i32), P(i32)]
     lib.bddc_edge_constraints.argtypes = [vp, i32, i32, P(i32), i32, P(dbl), i32, P(i32), P(i32)]
@@ -171,6 +176,11 @@ def plan(prob, **kw) -> dict:
     return {k: (v[0] if isinstance(v, list) else v) for k, v in d.items()}
 
 
+def footprint(prob) -> int:
+    """Device bytes a set-up of the problem will hold (bddc_plan, no device work)."""
+    return int(plan(prob)["device_bytes"])
+
+
 def _stream_ptr(stream) -> int:
     import torch
     if stream is None:
@@ -254,6 +264,35 @@ class Solver:
                                  float(rtol), int(maxit), iters, relres, ctypes.c_void_p(_stream_ptr(stream)))
         if not (st == -5 and allow_noconv):
             _check(st, "bddc_solve")
+        return u, list(iters), list(relres)
+
+    # stepwise solve (bddc_solve_begin / _advance / _poll / _end)
+    def begin(self, f, rtol=1e-8, maxit=1000, stream=None):
+        nrhs, ld = _vec_args(f, self.n_free)
+        self._step_f = f   # kept alive until end()
+        _check(self.lib.bddc_solve_begin(self.h, ctypes.c_void_p(f.data_ptr()), nrhs, ld, float(rtol), int(maxit),
+                                         ctypes.c_void_p(_stream_ptr(stream))), "bddc_solve_begin")
+
+    def advance(self, iterations=8):
+        _check(self.lib.bddc_solve_advance(self.h, int(iterations)), "bddc_solve_advance")
+
+    def poll(self) -> int:
+        st = ctypes.c_int32()
+        _check(self.lib.bddc_solve_poll(self.h, ctypes.byref(st)), "bddc_solve_poll")
+        return st.value
+
+    def end(self, u=None, allow_noconv=False):
+        import torch
+        f = self._step_f
+        nrhs, ld = _vec_args(f, self.n_free)
+        if u is None:
+            u = torch.empty_like(f)
+        iters = (ctypes.c_int32 * nrhs)()
+        relres = (ctypes.c_double * nrhs)()
+        st = self.lib.bddc_solve_end(self.h, ctypes.c_void_p(u.data_ptr()), ld, iters, relres)
+        self._step_f = None
+        if not (st == -5 and allow_noconv):
+            _check(st, "bddc_solve_end")
         return u, list(iters), list(relres)
 
     def tuning(self) -> dict:

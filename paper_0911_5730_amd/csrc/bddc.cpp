@@ -414,6 +414,19 @@ struct Level {
   LevelDev dev;
 };
 
+// A PCG solve in progress on a handle: its load, columns, iteration count
+// and the interior-solve form chosen at its start.
+struct PcgRun {
+  bool active = false;
+  bool stepwise = false;          // begun by bddc_solve_begin
+  hipStream_t saved_stream = nullptr;
+  const double* f = nullptr;
+  int64_t ld = 0;
+  int R = 0, maxit = 0, it = 0;
+  bool sweep = false, tiles = false, blocked = false;
+  size_t tmark = 0;
+};
+
 }  // namespace bddc
 
 struct bddc_ctx {
@@ -461,6 +474,8 @@ struct bddc_ctx {
   bool counted = false;       // counted in g_live_handles
   int device = 0;             // the device the handle's memory lives on
   bool noalloc_now = false;   // inside bddc_solve_noalloc: no graph, no (re)allocation
+  bddc::PcgRun run;           // the solve in progress (stepwise API or a blocking solve)
+  hipEvent_t run_event = nullptr;   // after the last advance's copy of the convergence flags
   int coop_rmax = 1;          // most columns one cooperative launch serves (LDS and residency)
   double coop_bytes = 0;      // algorithmic bytes of one launch
   hipGraphExec_t graph_exec = nullptr;   // one chunk of PCG launches (captured on first use)
@@ -2031,16 +2046,67 @@ static void ensure_columns(bddc_ctx* h, int R) {
 }
 
 // PCG on the level-1 interface for R <= kMaxRhs right-hand sides at once
-// (columns of f and u at stride ld).  Each column runs its own recurrences
-// and convergence test; the launches of one iteration serve every column
-// still iterating.  Returns the number of columns that did not converge.
-static int pcg_block(bddc_ctx* h, const double* f, double* u, int64_t ld, int R, double rtol, int maxit,
-                     int32_t* iters_out, double* relres) {
+// (columns of f and u at stride ld), in three parts so that a caller can
+// interleave several solves: pcg_begin enqueues the condensation, r_0 and
+// z_0; pcg_advance enqueues chunks of iterations and an asynchronous copy of
+// the convergence flags; pcg_finish waits, recovers the interior and reports.
+// Each column runs its own recurrences and convergence test; the launches of
+// one iteration serve every column still iterating.
+
+// Iteration k: matvec, update + restriction, deep levels, prolongation with
+// the convergence test, post.  The test sits in the prolongation, so at the
+// converged iteration K the update, restriction and deep levels still run
+// (tagged k - 1: they work iff k <= K) and the rest return at once.  The
+// kernels take their iteration as sc[0].it_base + u (u < 0: iteration 0), so
+// one chunk of launches is the same for every chunk and can be replayed as a
+// HIP graph.
+static void pcg_apply_iface(bddc_ctx* h, hipStream_t q, int uu, int it) {
+  Level& l1 = *h->levels[0];
+  PcgDev& P = h->pcg;
+  timing::current_tag = it - 1;
+  {
+    timing::Scope ts("apply_restrict", it > 0 ? h->by_ur_prec : h->by_r_prec, 0);
+    launch_pcg_update_restrict(q, l1.dev, l1.ngmax, l1.nrmax, l1.ncsmax, P, uu);
+  }
+  if (P.fin && it > 0) launch_pcg_sum(q, P, 1, uu);
+  run_deep_cols(h, q, P.b, P.ld_cflat, const_cast<double*>(P.uc), P.ld_coarse, P.nrhs);
+  timing::current_tag = it;
+  {
+    timing::Scope ts("apply_average", h->by_average, 0);
+    launch_pcg_prolong_post(q, l1.dev, P, uu);
+  }
+  if (P.fin) launch_pcg_sum(q, P, 2, uu);
+}
+
+static void pcg_chunk(bddc_ctx* h, hipStream_t q, int it0) {
+  Level& l1 = *h->levels[0];
+  PcgDev& P = h->pcg;
+  for (int uu = 0; uu < h->pcg_check; ++uu) {
+    const int it = it0 + uu;
+    timing::current_tag = it;
+    {
+      // the product of iteration k works iff k <= K (K = converged iteration)
+      timing::Scope ts("schur_local", h->by_schur_packed, 0, -1);
+      launch_pcg_matvec(q, l1.dev, l1.ngmax, P, uu);
+    }
+    if (P.fin) launch_pcg_sum(q, P, 0, uu);
+    pcg_apply_iface(h, q, uu, it);
+  }
+  launch_pcg_advance(q, P, h->pcg_check);
+}
+
+static void pcg_begin(bddc_ctx* h, const double* f, int64_t ld, int R, double rtol, int maxit) {
   hipStream_t st = h->stream;
   Level& l1 = *h->levels[0];
   ensure_columns(h, R);
   PcgDev& P = h->pcg;
   P.nrhs = R;
+  PcgRun& run = h->run;
+  run = PcgRun{};
+  run.f = f;
+  run.ld = ld;
+  run.R = R;
+  run.maxit = maxit;
   if (h->coop_deep) {
     h->coop_shared = g_live_handles.load() > 1;
     launch_coop_reset(st, h->coop);
@@ -2056,14 +2122,14 @@ static int pcg_block(bddc_ctx* h, const double* f, double* u, int64_t ld, int R,
     sch[c].it_base = 1;
     BDDC_HIP(hipMemcpyAsync(P.sc + c, sch + c, offsetof(PcgScalars, alphas), hipMemcpyHostToDevice, st));
   }
-  // the condensation: with the streamed sweeps all columns in one pass over
-  // L (y = L^{-1} f_I, t = L_GI y per column), else column by column
-  // interior pre-correction of every column: column sweeps for small
-  // substructures, else the blocked triangular solves when kMaxRhs columns fit
-  // the LDS, else column by column
-  const bool sweep = use_sweep(l1.nmax);
-  const bool tiles = !sweep && l1.big;   // the tiled factor of large substructures: block substitution
-  const bool blocked = !sweep && !tiles && apply_cols_lds(kMaxRhs, l1.nImax, l1.ngmax) <= kLdsMax;
+  // the condensation: with the streamed sweeps (small substructures) or the
+  // tiled block substitution (large ones) all columns in one pass over L
+  // (y = L^{-1} f_I, t = L_GI y per column); else the blocked triangular
+  // solves when kMaxRhs columns fit the LDS, else column by column
+  run.sweep = use_sweep(l1.nmax);
+  run.tiles = !run.sweep && l1.big;
+  run.blocked = !run.sweep && !run.tiles && apply_cols_lds(kMaxRhs, l1.nImax, l1.ngmax) <= kLdsMax;
+  const bool sweep = run.sweep, tiles = run.tiles, blocked = run.blocked;
   if (sweep) launch_sweep_pre_cols(st, l1.dev, f, ld, h->cy, h->ld_cy, h->ct, P.ld_flat, R);
   if (tiles) launch_tile_pre_cols(st, l1.dev, f, ld, h->cy, h->ld_cy, h->ct, P.ld_flat, R);
   if (blocked) launch_apply_pre_cols(st, l1.dev, l1.nImax, l1.ngmax, f, ld, h->cy, h->ld_cy, h->ct, P.ld_flat, R);
@@ -2078,92 +2144,89 @@ static int pcg_block(bddc_ctx* h, const double* f, double* u, int64_t ld, int R,
     launch_dot_partial(st, nb, nif, rc, rc, h->partial);
     launch_scalar(st, 5, nb, h->partial, P.sc + c);                  // rr0, done if already small
   }
-
   // every kernel below returns at once once every column has finished
-  struct StopGuard {
-    bddc_ctx* h;
-    ~StopGuard() {
-      for (auto& lvp : h->levels) lvp->dev.stop = nullptr;
-      timing::current_tag = -1;
-    }
-  } guard_stop{h};
   for (auto& lvp : h->levels) lvp->dev.stop = &P.sc[0].all_done;
-  const size_t tmark = timing::mark();
-
-  // Iteration k: matvec, update + restriction, deep levels, prolongation with
-  // the convergence test, post.  The test sits in the prolongation, so at the
-  // converged iteration K the update, restriction and deep levels still run
-  // (tagged k - 1: they work iff k <= K) and the rest return at once.  The
-  // kernels take their iteration as sc[0].it_base + u (u < 0: iteration 0), so
-  // one chunk of launches is the same for every chunk and can be replayed as a
-  // HIP graph.
-  auto apply_iface = [&](hipStream_t q, int uu, int it) {
-    timing::current_tag = it - 1;
-    {
-      timing::Scope ts("apply_restrict", it > 0 ? h->by_ur_prec : h->by_r_prec, 0);
-      launch_pcg_update_restrict(q, l1.dev, l1.ngmax, l1.nrmax, l1.ncsmax, P, uu);
-    }
-    if (P.fin && it > 0) launch_pcg_sum(q, P, 1, uu);
-    run_deep_cols(h, q, P.b, P.ld_cflat, const_cast<double*>(P.uc), P.ld_coarse, R);
-    timing::current_tag = it;
-    {
-      timing::Scope ts("apply_average", h->by_average, 0);
-      launch_pcg_prolong_post(q, l1.dev, P, uu);
-    }
-    if (P.fin) launch_pcg_sum(q, P, 2, uu);
-  };
-  const int check = h->pcg_check;   // iterations between host convergence checks
-  auto chunk = [&](hipStream_t q, int it0) {
-    for (int uu = 0; uu < check; ++uu) {
-      const int it = it0 + uu;
-      timing::current_tag = it;
-      {
-        // the product of iteration k works iff k <= K (K = converged iteration)
-        timing::Scope ts("schur_local", h->by_schur_packed, 0, -1);
-        launch_pcg_matvec(q, l1.dev, l1.ngmax, P, uu);
-      }
-      if (P.fin) launch_pcg_sum(q, P, 0, uu);
-      apply_iface(q, uu, it);
-    }
-    launch_pcg_advance(q, P, check);
-  };
+  run.tmark = timing::mark();
   // z_0 = M r_0 and its r.z partials (parity 0)
-  apply_iface(st, -1, 0);
+  pcg_apply_iface(h, st, -1, 0);
   if (h->graph_exec && h->graph_nrhs != R && !h->noalloc_now) {
     (void)hipGraphExecDestroy(h->graph_exec);
     h->graph_exec = nullptr;
   }
-  int it = 0;
-  while (it < maxit) {
-    // iterations past maxit or convergence return at once (sc[c].done)
-    if (graph_chunk(h, st, [&](hipStream_t q) { chunk(q, it + 1); }))
+  run.active = true;
+}
+
+// Enqueue chunks covering at least `iters` more iterations (iterations past
+// maxit or convergence return at once), then an asynchronous copy of the
+// convergence flags to the pinned host scalars and an event after it.
+static void pcg_advance(bddc_ctx* h, int iters) {
+  hipStream_t st = h->stream;
+  PcgRun& run = h->run;
+  const int R = run.R;
+  for (int done = 0; done < std::max(1, iters) && run.it < run.maxit; done += h->pcg_check) {
+    if (graph_chunk(h, st, [&](hipStream_t q) { pcg_chunk(h, q, run.it + 1); }))
       h->graph_nrhs = R;
     else
-      chunk(st, it + 1);
-    it += check;
-    BDDC_HIP(hipMemcpyAsync(sch, P.sc, offsetof(PcgScalars, alphas), hipMemcpyDeviceToHost, st));
-    BDDC_HIP(hipStreamSynchronize(st));
-    if (sch[0].all_done) break;
+      pcg_chunk(h, st, run.it + 1);
+    run.it += h->pcg_check;
   }
   timing::current_tag = -1;
+  BDDC_HIP(hipMemcpyAsync(h->sc_host, h->pcg.sc, offsetof(PcgScalars, alphas), hipMemcpyDeviceToHost, st));
+  if (!h->run_event) BDDC_HIP(hipEventCreateWithFlags(&h->run_event, hipEventDisableTiming));
+  BDDC_HIP(hipEventRecord(h->run_event, st));
+}
+
+// 1 when the iterations enqueued so far have finished every column (or
+// reached maxit), 0 when more are needed, -1 while the last advance runs.
+static int pcg_poll(bddc_ctx* h, bool wait) {
+  PcgRun& run = h->run;
+  if (wait) {
+    BDDC_HIP(hipEventSynchronize(h->run_event));
+  } else {
+    const hipError_t e = hipEventQuery(h->run_event);
+    if (e == hipErrorNotReady) return -1;
+    BDDC_HIP(e);
+  }
+  return (h->sc_host[0].all_done || run.it >= run.maxit) ? 1 : 0;
+}
+
+// Interior recovery and the per-column results; synchronises the stream.
+// Returns the number of columns that did not converge.
+static int pcg_finish(bddc_ctx* h, double* u, int64_t ld, int32_t* iters_out, double* relres) {
+  hipStream_t st = h->stream;
+  Level& l1 = *h->levels[0];
+  PcgDev& P = h->pcg;
+  PcgRun& run = h->run;
+  const int R = run.R;
+  const double* f = run.f;
+  struct Clear {
+    bddc_ctx* h;
+    ~Clear() {
+      for (auto& lvp : h->levels) lvp->dev.stop = nullptr;
+      timing::current_tag = -1;
+      h->run.active = false;
+    }
+  } clear{h};
+  timing::current_tag = -1;
   // interior recovery u_I = L^-T (y - L_GI^T x) with each column's own y:
-  // the column sweeps and the blocked solves kept every column's y; column by
-  // column, the set-up pass above left the last column's y (the level's stop
-  // flag is raised by now, so these launches go without it)
+  // the column sweeps, the tiled and the blocked solves kept every column's
+  // y; column by column, the set-up pass left the last column's y (the
+  // level's stop flag is raised by now, so these launches go without it)
   LevelDev L1 = l1.dev;
   L1.stop = nullptr;
-  if (sweep) {
+  if (run.sweep) {
     launch_sweep_recover_cols(st, L1, P.x, P.ld_if, h->cy, h->ld_cy, u, ld, R);
-  } else if (tiles) {
+  } else if (run.tiles) {
     launch_tile_recover_cols(st, L1, P.x, P.ld_if, h->cy, h->ld_cy, u, ld, R, l1.ngmax);
-  } else if (blocked) {
+  } else if (run.blocked) {
     launch_recover_cols(st, L1, l1.nImax, l1.ngmax, P.x, P.ld_if, h->cy, h->ld_cy, u, ld, R);
   } else {
     for (int c = R - 1; c >= 0; --c) {
-      if (c < R - 1) launch_apply_pre(st, L1, l1.nImax, l1.ngmax, f + (size_t)c * ld);
+      if (c < R - 1) launch_apply_pre(st, L1, l1.nImax, l1.ngmax, f + (size_t)c * run.ld);
       launch_recover(st, L1, l1.nImax, l1.ngmax, P.x + (size_t)c * P.ld_if, u + (size_t)c * ld);
     }
   }
+  PcgScalars* sch = h->sc_host;
   int dev_status = 0;
   for (int c = 0; c < R; ++c) BDDC_HIP(hipMemcpyAsync(sch + c, P.sc + c, sizeof(PcgScalars), hipMemcpyDeviceToHost, st));
   BDDC_HIP(hipMemcpyAsync(&dev_status, h->status, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -2178,13 +2241,34 @@ static int pcg_block(bddc_ctx* h, const double* f, double* u, int64_t ld, int R,
     maxiters = std::max(maxiters, S.iters);
   }
   // launches of iteration k work iff k < K (the product: k <= K, tagged k-1)
-  timing::prune(tmark, maxiters);
+  timing::prune(run.tmark, maxiters);
   const PcgScalars& S = sch[R - 1];
   std::vector<double> al(S.alphas, S.alphas + std::min(S.iters, kMaxHist));
   std::vector<double> be(S.betas, S.betas + std::max(0, std::min(S.iters, kMaxHist) - 1));
   h->info.kappa = lanczos_kappa(al, be);
   h->info.last_iters = S.iters;
   return failed;
+}
+
+// The blocking solve: begin, chunks until every column has finished, finish.
+static int pcg_block(bddc_ctx* h, const double* f, double* u, int64_t ld, int R, double rtol, int maxit,
+                     int32_t* iters_out, double* relres) {
+  struct Abort {
+    bddc_ctx* h;
+    ~Abort() {
+      if (h->run.active) {
+        for (auto& lvp : h->levels) lvp->dev.stop = nullptr;
+        timing::current_tag = -1;
+        h->run.active = false;
+      }
+    }
+  } abort_guard{h};
+  pcg_begin(h, f, ld, R, rtol, maxit);
+  while (h->run.it < maxit) {
+    pcg_advance(h, h->pcg_check);
+    if (pcg_poll(h, true) == 1) break;
+  }
+  return pcg_finish(h, u, ld, iters_out, relres);
 }
 
 static int64_t model_bytes(const bddc_ctx* h, bool apply) {
@@ -2255,6 +2339,7 @@ void release(bddc_ctx* h) {
   h->cols_arena.release(st);
   if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
   h->graph_exec = nullptr;
+  if (h->run_event) (void)hipEventDestroy(h->run_event);
   pinned_release(h->sc_host);
   for (void* b : h->staged) pinned_release(b);
   delete h;   // the pool frees above are stream-ordered
@@ -2314,6 +2399,20 @@ bddc_status bddc_plan(const bddc_problem* p, bddc_info* info) {
     info->n_free = (int64_t)(p->nx - 1) * (p->ny - 1);
     info->levels = p->levels;
     fill_level_info(lv, 0, info);
+    // device bytes a set-up will hold, from the level-1 sizes: the dense local
+    // matrices (and the tiled kernel's diagonal inverses), the PCG operators
+    // S_s and T_rr (full; packed is smaller), the level's flat arrays and one
+    // column of PCG state; the deeper levels are a fraction of level 1 and
+    // are covered by a 10% margin
+    const Topology& T = lv.topo;
+    double by = 0;
+    for (int s = 0; s < lv.nsub; ++s) {
+      const double n = T.nloc(s), ng = T.ngam(s), nI = T.n_int[s];
+      by += 8.0 * n * n + 16.0 * ng * ng + 8.0 * ng * 8;
+      if (use_big_chol(lv.nmax)) by += 8.0 * 64.0 * 64.0 * std::ceil(nI / 64.0);
+    }
+    by += 8.0 * (12.0 * lv.nflat_g + 4.0 * lv.nflat_i) + 8.0 * 10.0 * (double)info->n_free;
+    info->device_bytes = (int64_t)(1.1 * by);
   });
 }
 
@@ -2587,6 +2686,7 @@ bddc_status bddc_autotune(bddc_handle h, const double* f, double* u, int32_t nrh
   bddc_status st = guard([&] {
     if (!h || !f || !u || nrhs < 1 || ld < h->n_free || !(rtol >= 0) || reps < 1)
       fail(BDDC_EINVAL, "bad autotune arguments");
+    if (h->run.active) fail(BDDC_EBUSY, "a stepwise solve is in progress on this handle");
     hipStream_t saved = h->stream;
     h->stream = reinterpret_cast<hipStream_t>(hip_stream);
     struct Restore {
@@ -2650,6 +2750,7 @@ bddc_status bddc_autotune(bddc_handle h, const double* f, double* u, int32_t nrh
 bddc_status bddc_apply(bddc_handle h, const double* r, double* z, int32_t nrhs, int64_t ld, void* hip_stream) {
   return guard([&] {
     if (!h || !r || !z || nrhs < 0 || ld < h->n_free) fail(BDDC_EINVAL, "bad apply arguments");
+    if (h->run.active) fail(BDDC_EBUSY, "a stepwise solve is in progress on this handle");
     if (r == z) fail(BDDC_EINVAL, "r and z must not alias");
     hipStream_t saved = h->stream;
     h->stream = reinterpret_cast<hipStream_t>(hip_stream);
@@ -2665,6 +2766,7 @@ bddc_status bddc_solve(bddc_handle h, const double* f, double* u, int32_t nrhs, 
     if (!h || !f || !u || nrhs < 0 || ld < h->n_free || !(rtol >= 0) || maxit < 0 || !iters || !relres)
       fail(BDDC_EINVAL, "bad solve arguments");
     if (maxit > kMaxHist) fail(BDDC_EINVAL, "maxit too large");
+    if (h->run.active) fail(BDDC_EBUSY, "a stepwise solve is in progress on this handle");
     hipStream_t saved = h->stream;
     h->stream = reinterpret_cast<hipStream_t>(hip_stream);
     // blocks of up to kMaxRhs columns (BDDC_SOLVE_BLOCK=1: one column at a time)
@@ -2681,6 +2783,76 @@ bddc_status bddc_solve(bddc_handle h, const double* f, double* u, int32_t nrhs, 
   return st;
 }
 
+bddc_status bddc_solve_begin(bddc_handle h, const double* f, int32_t nrhs, int64_t ld, double rtol, int32_t maxit,
+                             void* hip_stream) {
+  return guard([&] {
+    if (!h || !f || nrhs < 1 || nrhs > kMaxRhs || ld < h->n_free || !(rtol >= 0) || maxit < 0)
+      fail(BDDC_EINVAL, "bad solve arguments");
+    if (maxit > kMaxHist) fail(BDDC_EINVAL, "maxit too large");
+    if (h->run.active) fail(BDDC_EBUSY, "a solve is already in progress on this handle");
+    const hipStream_t saved = h->stream;
+    h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    try {
+      pcg_begin(h, f, ld, nrhs, rtol, maxit);
+    } catch (...) {
+      for (auto& lvp : h->levels) lvp->dev.stop = nullptr;
+      h->run.active = false;
+      h->stream = saved;
+      throw;
+    }
+    h->run.stepwise = true;
+    h->run.saved_stream = saved;
+  });
+}
+
+static void end_stepwise(bddc_ctx* h) {
+  for (auto& lvp : h->levels) lvp->dev.stop = nullptr;
+  h->run.active = false;
+  h->run.stepwise = false;
+  h->stream = h->run.saved_stream;
+}
+
+bddc_status bddc_solve_advance(bddc_handle h, int32_t iterations) {
+  return guard([&] {
+    if (!h || iterations < 0) fail(BDDC_EINVAL, "bad advance arguments");
+    if (!h->run.active || !h->run.stepwise) fail(BDDC_EINVAL, "no stepwise solve in progress");
+    try {
+      pcg_advance(h, iterations);
+    } catch (...) {
+      end_stepwise(h);
+      throw;
+    }
+  });
+}
+
+bddc_status bddc_solve_poll(bddc_handle h, int32_t* state) {
+  return guard([&] {
+    if (!h || !state) fail(BDDC_EINVAL, "bad poll arguments");
+    if (!h->run.active || !h->run.stepwise) fail(BDDC_EINVAL, "no stepwise solve in progress");
+    if (!h->run_event) {
+      *state = 0;   // nothing advanced yet
+      return;
+    }
+    *state = pcg_poll(h, false);
+  });
+}
+
+bddc_status bddc_solve_end(bddc_handle h, double* u, int64_t ld, int32_t* iters, double* relres) {
+  bool noconv = false;
+  bddc_status st = guard([&] {
+    if (!h || !u || !iters || !relres) fail(BDDC_EINVAL, "bad solve arguments");
+    if (!h->run.active || !h->run.stepwise) fail(BDDC_EINVAL, "no stepwise solve in progress");
+    if (ld < h->n_free) fail(BDDC_EINVAL, "bad leading dimension");
+    struct End {
+      bddc_ctx* h;
+      ~End() { end_stepwise(h); }
+    } end{h};
+    if (pcg_finish(h, u, ld, iters, relres) > 0) noconv = true;
+  });
+  if (st == BDDC_OK && noconv) return BDDC_ENOCONV;
+  return st;
+}
+
 bddc_status bddc_solve_noalloc(bddc_handle h, const double* f, double* u, int32_t nrhs, int64_t ld, double rtol,
                                int32_t maxit, int32_t* iters, double* relres, void* hip_stream) {
   bool noconv = false;
@@ -2688,6 +2860,7 @@ bddc_status bddc_solve_noalloc(bddc_handle h, const double* f, double* u, int32_
     if (!h || !f || !u || nrhs < 0 || ld < h->n_free || !(rtol >= 0) || maxit < 0 || !iters || !relres)
       fail(BDDC_EINVAL, "bad solve arguments");
     if (maxit > kMaxHist) fail(BDDC_EINVAL, "maxit too large");
+    if (h->run.active) fail(BDDC_EBUSY, "a stepwise solve is in progress on this handle");
     int dev = -1;
     BDDC_HIP(hipGetDevice(&dev));
     if (dev != h->device) fail(BDDC_EINVAL, "the current device is not the handle's device");

@@ -590,8 +590,38 @@ __global__ void __launch_bounds__(kNT) k_pcg_matvec(LevelDev L, PcgDev P, int u)
       }
     }
   } else {
-    for (int k = 0; k < nl; ++k)
-      for (int i = tid; i < ng; i += kNT) part[k * psz + i] = sym_row_part(Sg, ng, i, 0, 1, pl + k * ng, P.full);
+    // wide interfaces: one thread per row, every entry of S_s loaded once and
+    // applied to all live columns (each column's terms in the order of
+    // sym_row_part)
+    for (int i = tid; i < ng; i += kNT) {
+      double acc[kMulti ? kMaxRhs : 1];
+#pragma unroll
+      for (int k = 0; k < (kMulti ? kMaxRhs : 1); ++k) acc[k] = 0.0;
+      auto term = [&](double a, int j) {
+#pragma unroll
+        for (int k = 0; k < (kMulti ? kMaxRhs : 1); ++k)
+          if (k < nl) acc[k] += a * pl[k * ng + j];
+      };
+      if (P.full) {
+        // eight loads in flight, then their terms in column order
+        int j = 0;
+        for (; j + 8 <= ng; j += 8) {
+          double t[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) t[q] = Sg[i + (size_t)(j + q) * ng];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) term(t[q], j + q);
+        }
+        for (; j < ng; ++j) term(Sg[i + (size_t)j * ng], j);
+      } else {
+        for (int j = 0; j <= i; ++j) term(Sg[packed_col(j, ng) + (i - j)], j);
+        const double* Ai = Sg + packed_col(i, ng) - i;
+        for (int j = i + 1; j < ng; ++j) term(Ai[j], j);
+      }
+#pragma unroll
+      for (int k = 0; k < (kMulti ? kMaxRhs : 1); ++k)
+        if (k < nl) part[k * psz + i] = acc[k];
+    }
   }
   __syncthreads();
   // the local products and energies p_s^T S_s p_s, in column slots
@@ -936,12 +966,30 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
         }
       }
     } else {
-      for (int k = 0; k < nl; ++k)
-        for (int i = tid; i < n_r; i += kNT) {
-          double acc = 0.0;
-          for (int j = 0; j < n_r; ++j) acc += static_cast<double>(Tg[op_index(i, j, n_r, P.full)]) * g[k * ngmax + j];
-          part[k * psz + i] = acc;
+      // wide interfaces: one thread per row, each entry of T_rr loaded once
+      // for all live columns (per column the order of the one-column sum)
+      for (int i = tid; i < n_r; i += kNT) {
+        double acc[kMulti ? kMaxRhs : 1];
+#pragma unroll
+        for (int k = 0; k < (kMulti ? kMaxRhs : 1); ++k) acc[k] = 0.0;
+        auto term = [&](double t, int j) {
+#pragma unroll
+          for (int k = 0; k < (kMulti ? kMaxRhs : 1); ++k)
+            if (k < nl) acc[k] += t * g[k * ngmax + j];
+        };
+        int j = 0;
+        for (; j + 8 <= n_r; j += 8) {   // eight loads in flight, then their terms in column order
+          TS t[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) t[q] = Tg[op_index(i, j + q, n_r, P.full)];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) term(static_cast<double>(t[q]), j + q);
         }
+        for (; j < n_r; ++j) term(static_cast<double>(Tg[op_index(i, j, n_r, P.full)]), j);
+#pragma unroll
+        for (int k = 0; k < (kMulti ? kMaxRhs : 1); ++k)
+          if (k < nl) part[k * psz + i] = acc[k];
+      }
     }
     __syncthreads();
     const int nc = narrow ? nch : 1;

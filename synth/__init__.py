@@ -15,6 +15,6 @@ from .configs import (  # noqa: F401
     voronoi_agglomeration,
     voronoi_problem,
     config,
-    request_stream,
+    request_stream, serving_stream,
     CONFIG_NAMES,
 )

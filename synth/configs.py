@@ -303,10 +303,13 @@ def request_stream(count: int, *, rate: float = 200.0, sides=(128, 256), hh=(8, 
                    max_rhs: int = 4, problems: Optional[int] = None):
     """A seeded stream of independent solve requests shaped like the serving
     workload: Poisson arrivals (mean `rate` per second), grid side and H/h
-    drawn uniformly from `sides` and `hh`, 3 levels (level-2 substructures of
-    4 x 4 level-1 substructures) from 16 x 16 substructures on, else 2, k = 10^U(0, m) with m uniform in 0..6,
-    adaptive tau = 10, 1 to
-    `max_rhs` right-hand sides U[-1, 1].  Returns [(arrival_seconds, Problem)].
+    drawn uniformly from `sides` and `hh` (H/h above the side is skipped:
+    the draw is repeated), levels: 3 (level-2 substructures of 4 x 4 level-1
+    substructures) from 16 x 16 substructures on, 2 or 3 at random from
+    8 x 8 (3: 2 x 2 groups), else 2; k = 10^U(0, m) with m uniform in 0..6,
+    adaptive tau = 10, 1 to `max_rhs` right-hand sides U[-1, 1].  Returns
+    [(arrival_seconds, Problem)].  The serving workload itself is
+    `serving_stream`.
 
     With `problems`, that many distinct problems are drawn first and every
     request takes one of them uniformly with loads of its own (seeded):
@@ -335,14 +338,29 @@ def request_stream(count: int, *, rate: float = 200.0, sides=(128, 256), hh=(8, 
         t += rng.exponential(1.0 / rate)
         nx = int(rng.choice(sides))
         h = int(rng.choice(hh))
+        while h > nx // 2:
+            h = int(rng.choice(hh))
         nsx = nx // h
         # two levels only while the coarse problem stays small (<= 8 x 8
-        # substructures): the coarsest problem is factored densely
-        levels = 3 if nsx >= 16 and nsx % 4 == 0 else 2
+        # substructures: the coarsest problem is solved directly)
+        if nsx >= 16 and nsx % 4 == 0:
+            levels, groups = 3, (nsx // 4, nsx // 4)
+        elif nsx == 8 and int(rng.integers(0, 2)):
+            levels, groups = 3, (2, 2)
+        else:
+            levels, groups = 2, (1, 1)
         m = int(rng.integers(0, 7))
         nrhs = int(rng.integers(1, max_rhs + 1))
-        prob = square_problem(nx, nsx, levels=levels, groups=(nsx // 4, nsx // 4), constraints="adaptive", tau=10.0,
+        prob = square_problem(nx, nsx, levels=levels, groups=groups, constraints="adaptive", tau=10.0,
                               kmode="loguniform" if m else "one", kmax_exp=float(m), nrhs=nrhs,
                               seed=int(rng.integers(1 << 30)), name=f"request{r}")
         out.append((t, prob))
     return out
+
+
+def serving_stream(count: int, *, rate: float = 200.0, seed: int = 5000):
+    """The serving workload: Poisson arrivals (mean 200 per second), grid side
+    in {128, 256, 512, 1024}, H/h in {8, 16, 32}, two or three levels, k =
+    10^U(0, m) with m uniform in 0..6, 1 to 16 right-hand sides, adaptive
+    tau = 10 (see request_stream for the level rule)."""
+    return request_stream(count, rate=rate, sides=(128, 256, 512, 1024), hh=(8, 16, 32), seed=seed, max_rhs=16)

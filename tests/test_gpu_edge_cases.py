@@ -193,6 +193,87 @@ def test_serving_loop_results_alone_equal_in_the_mix():
         assert st["requests"] == len(stream) and st["latency_ms"]["p99"] >= st["latency_ms"]["p50"]
 
 
+def test_stepwise_solve_matches_solve_and_guards_the_handle():
+    """bddc_solve_begin / _advance / _poll / _end give bitwise the solution and
+    iteration counts of bddc_solve (the same launches, in chunks); while a
+    stepwise solve is in progress the handle refuses other solves and applies
+    with BDDC_EBUSY, and works normally after the end."""
+    import time
+
+    import torch
+
+    import paper_0911_5730_amd as P
+    prob = synth.square_problem(48, 4, levels=3, groups=(2, 2), constraints="adaptive", tau=3.0,
+                                kmode="loguniform", kmax_exp=3, nrhs=3, seed=33)
+    with _solver(prob) as S:
+        F = cuda_vec(prob.f)
+        U, its, rr = S.solve(F)
+        S.begin(F)
+        with pytest.raises(P.BDDCError) as ei:
+            S.solve(F)
+        assert ei.value.name == "BDDC_EBUSY"
+        with pytest.raises(P.BDDCError) as ei:
+            S.apply(F[0].contiguous())
+        assert ei.value.name == "BDDC_EBUSY"
+        states = []
+        S.advance(4)
+        for _ in range(1000):
+            st = S.poll()
+            states.append(st)
+            if st == 1:
+                break
+            if st == 0:
+                S.advance(4)
+            else:
+                time.sleep(1e-4)
+        assert states[-1] == 1
+        U2, its2, rr2 = S.end()
+        assert its2 == its and rr2 == rr
+        assert torch.equal(U2, U)
+        U3, its3, _ = S.solve(F)
+        assert its3 == its and torch.equal(U3, U)
+
+
+def test_serving_admits_requests_while_others_run():
+    """Continuous batching: a request that arrives while a long solve is in
+    flight is set up and started at an iteration boundary of the running
+    solve (both in flight together); both results equal their solves alone
+    (bitwise)."""
+    import time
+
+    import paper_0911_5730_amd as P
+    from paper_0911_5730_amd.serve import Request, Server
+    big = synth.square_problem(1024, 64, levels=3, groups=(4, 4), constraints="adaptive", tau=10.0,
+                               kmode="one", nrhs=8, seed=61)
+    small = synth.square_problem(64, 8, constraints="adaptive", tau=10.0, kmode="loguniform", kmax_exp=2,
+                                 nrhs=1, seed=62)
+    alone = []
+    for prob in (big, small):
+        S = P.Solver(prob, precision="fp32")
+        try:
+            u, it, _ = S.solve(cuda_vec(prob.f), rtol=1e-10)
+            alone.append((u.cpu().numpy(), it))
+        finally:
+            S.close()
+    srv = Server(slots=4, chunk=2)
+    try:
+        rb = srv.submit(Request(prob=big, rhs=big.f, precision="fp32", rtol=1e-10))
+        while not rb.started:
+            time.sleep(1e-3)
+        rs = srv.submit(Request(prob=small, rhs=small.f, precision="fp32", rtol=1e-10))
+        srv.drain()
+    finally:
+        srv.close()
+    assert rb.error is None and rs.error is None, (rb.error, rs.error)
+    print(f"big: started {rb.started:.4f} done {rb.done:.4f}; small: arrival {rs.arrival:.4f} started "
+          f"{rs.started:.4f} done {rs.done:.4f}", flush=True)
+    assert rs.started < rb.done
+    assert srv.max_active >= 2
+    for r, (u, it) in zip((rb, rs), alone):
+        assert r.iterations == it
+        assert np.array_equal(r.solution, u)
+
+
 def test_serving_resident_problems_merge_loads_and_match_alone():
     """Requests against a few shared problems: a resident problem is reused
     without a new set-up and the pending loads of one problem are merged into
