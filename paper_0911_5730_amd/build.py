@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 OUT = os.path.join(HERE, "libbddc.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["bddc.cpp", "topology.cpp", "host_pool.cpp", "k_setup.hip", "k_eig.hip", "k_apply.hip", "k_fused.hip", "k_coop.hip", "k_sweep.hip", "k_wide.hip", "k_coarse.hip", "noalloc.hip", "k_bigchol.hip", "k_tile.hip"]
+SOURCES = ["bddc.cpp", "topology.cpp", "host_pool.cpp", "k_setup.hip", "k_eig.hip", "k_apply.hip", "k_fused.hip", "k_coop.hip", "k_sweep.hip", "k_wide.hip", "k_coarse.hip", "noalloc.hip", "k_bigchol.hip", "k_tile.hip", "k_pcg_rows.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("BDDC_OFFLOAD_ARCH", "gfx950")

@@ -2004,7 +2004,7 @@ static void lay_columns(bddc_ctx* h, Arena& A, int R) {
   P.ld_flat = pad(l1.nflat_g);
   P.ld_cflat = pad(l1.nflat_c);
   P.ld_coarse = pad(l1.nc);
-  P.ld_sub = pad(P.nsub1);
+  P.ld_sub = pad(std::max(P.nsub1, P.npq));
   P.ld_blk = pad(P.nblk);
   h->ld_cy = pad(l1.nflat_i);
   P.x = A.take<double>((size_t)R * P.ld_if);
@@ -2066,7 +2066,10 @@ static void pcg_apply_iface(bddc_ctx* h, hipStream_t q, int uu, int it) {
   timing::current_tag = it - 1;
   {
     timing::Scope ts("apply_restrict", it > 0 ? h->by_ur_prec : h->by_r_prec, 0);
-    launch_pcg_update_restrict(q, l1.dev, l1.ngmax, l1.nrmax, l1.ncsmax, P, uu);
+    if (P.nrb)
+      launch_pcg_update_restrict_rows(q, l1.dev, l1.ngmax, P, uu);
+    else
+      launch_pcg_update_restrict(q, l1.dev, l1.ngmax, l1.nrmax, l1.ncsmax, P, uu);
   }
   if (P.fin && it > 0) launch_pcg_sum(q, P, 1, uu);
   run_deep_cols(h, q, P.b, P.ld_cflat, const_cast<double*>(P.uc), P.ld_coarse, P.nrhs);
@@ -2087,7 +2090,10 @@ static void pcg_chunk(bddc_ctx* h, hipStream_t q, int it0) {
     {
       // the product of iteration k works iff k <= K (K = converged iteration)
       timing::Scope ts("schur_local", h->by_schur_packed, 0, -1);
-      launch_pcg_matvec(q, l1.dev, l1.ngmax, P, uu);
+      if (P.nrb)
+        launch_pcg_matvec_rows(q, l1.dev, l1.ngmax, P, uu);
+      else
+        launch_pcg_matvec(q, l1.dev, l1.ngmax, P, uu);
     }
     if (P.fin) launch_pcg_sum(q, P, 0, uu);
     pcg_apply_iface(h, q, uu, it);
@@ -2523,6 +2529,24 @@ bddc_status bddc_setup(const bddc_problem* p, void* hip_stream, bddc_handle* out
     // row sums no longer fit the registers of the packed form)
     const char* oenv = getenv("BDDC_PCG_OPS");
     P.full = oenv ? std::string(oenv) == "full" : l1.ngmax > 64;
+    {
+      // interfaces wider than a workgroup: the product and the
+      // update/restriction by 64-row blocks (full storage, one-block sums);
+      // BDDC_PCG_ROWS=1/0 forces either (not the factored BF16 form)
+      const char* renv = getenv("BDDC_PCG_ROWS");
+      const bool rows = h->precision != BDDC_BF16 && (renv ? std::string(renv) == "1" : l1.ngmax > kNT);
+      P.nrb = rows ? pcg_rows_blocks(l1.ngmax) : 0;
+      if (rows) P.full = 1;
+      if (h->precision == BDDC_BF16) {
+        // the factored form stages W of a whole substructure in LDS
+        const size_t nr = (size_t)l1.nrmax;
+        const size_t lds = sizeof(double) * (2 * (size_t)l1.ngmax + kNT + nr + nr * (nr + 1) / 2) +
+                           sizeof(float) * (nr * (size_t)l1.ncsmax + nr);
+        if (lds > kLdsMax)
+          fail(BDDC_EUNSUPPORTED, "the BF16 form needs the factored T_rr of each substructure in LDS; the widest "
+                                  "interface is too large for it");
+      }
+    }
     std::vector<int64_t> spoff(l1.nsub + 1, 0), tpoff(l1.nsub + 1, 0);
     for (int s = 0; s < l1.nsub; ++s) {
       const int64_t ng = l1.topo.ngam(s), nr = l1.topo.n_r[s];
@@ -2571,6 +2595,7 @@ bddc_status bddc_setup(const bddc_problem* p, void* hip_stream, bddc_handle* out
     P.nblk = nblk_avg;
     P.nif = nif;
     P.nsub1 = l1.nsub;
+    P.npq = l1.nsub * std::max(1, P.nrb);
     ensure_columns(h, 1);
     {
       // sum the PCG partials once, in a one-block launch, when the consuming
@@ -2578,6 +2603,7 @@ bddc_status bddc_setup(const bddc_problem* p, void* hip_stream, bddc_handle* out
       // (BDDC_PCG_FINALIZE=0/1 forces either form)
       const char* env = getenv("BDDC_PCG_FINALIZE");
       P.fin = env ? (std::string(env) == "1" ? 1 : 0) : (std::max(nblk_avg, l1.nsub) > 1024 ? 1 : 0);
+      if (P.nrb) P.fin = 1;   // (the row-block launches read the summed scalars)
     }
     {
       Staging stg(h->stream, &h->staged);

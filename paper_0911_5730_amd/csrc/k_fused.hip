@@ -8,10 +8,11 @@
 //   product; phases that read other substructures' data are separated by
 //   workgroup barriers.  The coarsest Cholesky factor is staged in LDS and
 //   solved by one wave.  Used when the deep levels are small.
-// * k_pcg_*: one PCG iteration on the level-1 interface in five launches plus
-//   the apply.  Scalars (alpha, beta, convergence) are recomputed by every
-//   block from the per-block partial sums of the previous launch, in a fixed
-//   order, so no scalar-only launches are needed and results stay bitwise
+// * k_pcg_*: one PCG iteration on the level-1 interface in four launches
+//   (product, update/restriction, deep levels, prolongation).  Scalars
+//   (alpha, beta, convergence) are recomputed by every block from the
+//   per-block partial sums of the previous launch, in a fixed order, or
+//   summed once by a one-block launch on large grids; results stay bitwise
 //   reproducible.
 #include "dense.hpp"
 #include "kernels.hpp"
@@ -332,7 +333,7 @@ __global__ void __launch_bounds__(kNT) k_pcg_sum(PcgDev P, int which, int u) {
   const double* part = which == 0 ? P.pq_part + (size_t)c * P.ld_sub
                                   : (which == 1 ? P.rr_part + (size_t)c * P.ld_sub
                                                 : P.rz_part[it & 1] + (size_t)c * P.ld_blk);
-  const int n = which == 2 ? P.nblk : P.nsub1;
+  const int n = which == 2 ? P.nblk : (which == 0 ? P.npq : P.nsub1);
   const double v = block_sum_of(part, n, red);
   if (threadIdx.x == 0) {
     if (which == 0) S->pqs = v;
@@ -774,7 +775,7 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
     if (!P.fin) {
       for (int k = 0; k < nl; ++k) {
         const double rz = block_sum_of(P.rz_part[(it - 1) & 1] + (size_t)col(k) * P.ld_blk, P.nblk, red);
-        const double pq = block_sum_of(P.pq_part + (size_t)col(k) * P.ld_sub, P.nsub1, red);
+        const double pq = block_sum_of(P.pq_part + (size_t)col(k) * P.ld_sub, P.npq, red);
         alph[k] = rz / pq;   // every thread, the same value
         alpha0 = rz / pq;
       }

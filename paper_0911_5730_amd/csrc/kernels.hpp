@@ -214,6 +214,12 @@ struct PcgDev {
   const int4* shf4 = nullptr;
   int nif = 0;
   int nsub1 = 0;
+  // wide interfaces: the product and the update/restriction take a workgroup
+  // per 64-row block of each substructure (nrb blocks per substructure, 0:
+  // one workgroup per substructure); the energies p_s^T S_s p_s are then left
+  // per block, npq = nsub1 * max(1, nrb) partials per column
+  int nrb = 0;
+  int npq = 0;
   int nblk = 1;                              // blocks of the interface average (rz partials)
   // 1: a one-block launch after each producing launch sums its partials once
   // into PcgScalars (rzs, pqs, rrs) and the consumers read that scalar; 0:
@@ -282,6 +288,11 @@ void launch_assemble_coarse(hipStream_t st, int nsub, const int64_t* koff, const
                             const int32_t* goff);
 void launch_weights(hipStream_t st, int nflat, const int32_t* flat_iid, const int32_t* sh_ptr,
                     const int32_t* sh_flat, const double* diagK, double* delta);
+// PCG product and update/restriction by 64-row blocks (k_pcg_rows.hip)
+size_t pcg_rows_lds(int ngmax, int nrhs);
+int pcg_rows_blocks(int ngmax);
+void launch_pcg_matvec_rows(hipStream_t st, const LevelDev& L, int ngmax, const PcgDev& P, int u);
+void launch_pcg_update_restrict_rows(hipStream_t st, const LevelDev& L, int ngmax, const PcgDev& P, int u);
 // local matrices of any size: left-looking blocked elimination with 64 x 64
 // tiles staged in LDS and FP64 MFMA products (k_bigchol.hip)
 void launch_partial_chol_big(hipStream_t st, const LevelDev& L, double* K, double* Wd, int* status);

@@ -82,15 +82,21 @@ def test_blocked_columns_equal_single_columns_bitwise(case, path, monkeypatch):
 
 
 @pytest.mark.parametrize("case,ops,prec", [("adaptive3_h16", "full", "fp64"), ("adaptive3_h16", "full", "fp32"),
-                                           ("voronoi_jitter3", "packed", "fp32")])
+                                           ("voronoi_jitter3", "packed", "fp32"), ("voronoi_jitter3", "rows", "fp64"),
+                                           ("voronoi_jitter3", "rows", "fp32"), ("adaptive3_h16", "rows", "fp32")])
 def test_blocked_pcg_operator_storage(case, ops, prec, monkeypatch):
     """S_s and T_rr as packed lower triangles or as full matrices (wide
-    interfaces use the full form): blocked columns bitwise equal to single
-    ones in either form."""
+    interfaces use the full form), and the product and update/restriction by
+    64-row blocks with a workgroup per block (the launches of interfaces
+    wider than a workgroup; here interfaces of one to three blocks): blocked
+    columns bitwise equal to single ones in every form."""
     import torch
 
     import paper_0911_5730_amd as P
-    monkeypatch.setenv("BDDC_PCG_OPS", ops)
+    if ops == "rows":
+        monkeypatch.setenv("BDDC_PCG_ROWS", "1")
+    else:
+        monkeypatch.setenv("BDDC_PCG_OPS", ops)
     prob = _case(case)
     F = _loads(prob, 5, 4)
     print(f"operator storage {ops}, case {case}, {prec}", flush=True)

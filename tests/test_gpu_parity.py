@@ -218,6 +218,27 @@ def test_pcg_graph_replays_match_direct_launches(deep, monkeypatch):
         S.close()
 
 
+@pytest.mark.parametrize("case", ["voronoi_jitter3", "adaptive3_h16", "voronoi_adaptive3_large"])
+def test_pcg_row_blocks_match_oracle(case, monkeypatch):
+    """The PCG product and update/restriction with a workgroup per 64-row
+    block of each substructure (the launches of interfaces wider than a
+    workgroup, hundreds of dofs), forced on oracle cases whose interfaces
+    take one to three blocks with ragged last blocks: iterations and
+    solution against the oracle, and a second solve on the same handle
+    bitwise equal to the first."""
+    monkeypatch.setenv("BDDC_PCG_ROWS", "1")
+    prob = _case(case)
+    print(f"pcg row blocks, case {case}", flush=True)
+    S, B, ug, it, rr, o = run_pair(prob)
+    try:
+        assert abs(it - o["iters"]) <= 1
+        check_solution(S, B, ug, o)
+        u2, it2, _ = S.solve(cuda_vec(prob.f[0]))
+        assert it2[0] == it and np.array_equal(u2.cpu().numpy(), ug)
+    finally:
+        S.close()
+
+
 @pytest.mark.parametrize("path", ["default", "lds16_global", "sweep32", "eig_workgroup", "pair_global",
                                   "pcg_ops_full", "chol_big"])
 def test_setup_kernel_paths(path, monkeypatch):
