@@ -44,12 +44,14 @@ __device__ inline void row_task(int nrb, int& s, int& rb) {
 
 // acc[k] += sum over columns j in [j0, j1) of A[row, j] v[j][k]: A column-major
 // (leading dimension ld, already offset to the row), v in LDS as [j][k] with
-// stride nls; kNL accumulators of which the first nl are live
+// stride kNL.  All kNL accumulators run (entries of columns past the live
+// ones are zero in v): no branch in the loop, and each column's sum is the
+// same whatever the other columns hold
 // (the last batch loads at clamped column indices and adds zero terms past
 // j1, so a ragged end costs one batch, not a chain of single loads)
 template <int kNL, class T>
 __device__ inline void row_product(double (&acc)[kNL], const T* __restrict__ A, int ld, int j0, int j1,
-                                   const double* v, int nls, int nl) {
+                                   const double* v) {
   for (int j = j0; j < j1; j += kBatch) {
     T t[kBatch];
 #pragma unroll
@@ -59,17 +61,15 @@ __device__ inline void row_product(double (&acc)[kNL], const T* __restrict__ A, 
       // past j1: a zero term on the last column (a select, so that the
       // loads above stay unconditional)
       const double a = j + q < j1 ? static_cast<double>(t[q]) : 0.0;
-      const double* vj = v + (size_t)min(j + q, j1 - 1) * nls;
+      const double* vj = v + (size_t)min(j + q, j1 - 1) * kNL;
       if constexpr (kNL == 1) {
         acc[0] += a * vj[0];
       } else {
 #pragma unroll
         for (int k = 0; k < kNL; k += 2) {
-          if (k < nl) {
-            const double2 pv = *reinterpret_cast<const double2*>(vj + k);
-            acc[k] += a * pv.x;
-            acc[k + 1] += a * pv.y;
-          }
+          const double2 pv = *reinterpret_cast<const double2*>(vj + k);
+          acc[k] += a * pv.x;
+          acc[k + 1] += a * pv.y;
         }
       }
     }
@@ -124,9 +124,9 @@ __global__ void __launch_bounds__(kRT) k_pcg_matvec_rows(LevelDev L, PcgDev P, i
     if (it >= 2) bet[k] = P.sc[c].rzs[(it - 1) & 1] / P.sc[c].rzs[(it - 2) & 1];
   }
   if (it >= 2 && blockIdx.x == 0 && tid < nl) P.sc[col(tid)].betas[min(it - 2, kMaxHist - 1)] = bet[tid];
-  const int nls = kMulti ? ((nl + 1) & ~1) : 1;
-  double* pl = sh;                                  // ng x nls
-  double* part = sh + (((size_t)ng * nls + 1) & ~(size_t)1);   // kNW x kNL x 64
+  constexpr int nls = kNL;
+  double* pl = sh;                       // ng x kNL
+  double* part = sh + (size_t)ng * nls;  // kNW x kNL x 64
   // entry a of every live column on thread a: all of its loads are issued
   // before any store (the stores of p_k could alias them)
   for (int a = tid; a < ng; a += kRT) {
@@ -151,13 +151,13 @@ __global__ void __launch_bounds__(kRT) k_pcg_matvec_rows(LevelDev L, PcgDev P, i
       }
     }
   }
-  if (kMulti && (nl & 1))
-    for (int a = tid; a < ng; a += kRT) pl[(size_t)a * nls + nl] = 0.0;
+  if (kMulti && nl < kNL)
+    for (int t = tid; t < ng * (kNL - nl); t += kRT) pl[(size_t)(t / (kNL - nl)) * nls + nl + t % (kNL - nl)] = 0.0;
   __syncthreads();
   double acc[kNL];
 #pragma unroll
   for (int k = 0; k < kNL; ++k) acc[k] = 0.0;
-  row_product<kNL>(acc, Sg, ng, j0, j1, pl, nls, nl);
+  row_product<kNL>(acc, Sg, ng, j0, j1, pl);
 #pragma unroll
   for (int k = 0; k < kNL; ++k)
     if (k < nl) part[(wave * kNL + k) * kRows + lane] = acc[k];
@@ -222,9 +222,9 @@ __global__ void __launch_bounds__(kRT) k_pcg_update_restrict_rows(LevelDev L, Pc
                 r0 + min(lane, max(rows_r, 1) - 1);
   const int cq = (n_r + kNW - 1) / kNW;
   const int j0 = min(n_r, wave * cq), j1 = min(n_r, j0 + cq);
-  const int nls = kMulti ? ((nl + 1) & ~1) : 1;
-  double* g = sh;                                              // ng x nls
-  double* part = sh + (((size_t)ng * nls + 1) & ~(size_t)1);   // kNW x kNL x 64
+  constexpr int nls = kNL;
+  double* g = sh;                        // ng x kNL
+  double* part = sh + (size_t)ng * nls;  // kNW x kNL x 64
   if (it == 0) {
     for (int t = tid; t < ng * nl; t += kRT) {
       const int k = t / ng, a = t - k * ng;
@@ -325,8 +325,8 @@ __global__ void __launch_bounds__(kRT) k_pcg_update_restrict_rows(LevelDev L, Pc
       }
     }
   }
-  if (kMulti && (nl & 1))
-    for (int a = tid; a < ng; a += kRT) g[(size_t)a * nls + nl] = 0.0;
+  if (kMulti && nl < kNL)
+    for (int t = tid; t < ng * (kNL - nl); t += kRT) g[(size_t)(t / (kNL - nl)) * nls + nl + t % (kNL - nl)] = 0.0;
   __syncthreads();
   // b = Psi^T g: one wave per coarse dof of this block, lanes over the
   // interface entries, each entry of Psi applied to every live column
@@ -352,7 +352,7 @@ __global__ void __launch_bounds__(kRT) k_pcg_update_restrict_rows(LevelDev L, Pc
             const double* ga = g + (size_t)a * nls;
 #pragma unroll
             for (int k = 0; k < kNL; ++k)
-              if (k < nl) acc[k] += wv * ga[k];
+              acc[k] += wv * ga[k];
           }
         }
       }
@@ -371,7 +371,7 @@ __global__ void __launch_bounds__(kRT) k_pcg_update_restrict_rows(LevelDev L, Pc
     double acc[kNL];
 #pragma unroll
     for (int k = 0; k < kNL; ++k) acc[k] = 0.0;
-    row_product<kNL>(acc, Tg, n_r, j0, j1, g, nls, nl);
+    row_product<kNL>(acc, Tg, n_r, j0, j1, g);
 #pragma unroll
     for (int k = 0; k < kNL; ++k)
       if (k < nl) part[(wave * kNL + k) * kRows + lane] = acc[k];
@@ -395,9 +395,8 @@ __global__ void __launch_bounds__(kRT) k_pcg_update_restrict_rows(LevelDev L, Pc
 // dynamic LDS of both launches: the gathered vector (ng x columns, even) and
 // the wave partials
 size_t pcg_rows_lds(int ngmax, int nrhs) {
-  const int kNL = nrhs > 1 ? kMaxRhs : 1;
-  const size_t nls = nrhs > 1 ? (size_t)((nrhs + 1) & ~1) : 1;
-  return sizeof(double) * ((((size_t)ngmax * nls + 1) & ~(size_t)1) + (size_t)kNW * kNL * kRows);
+  const size_t kNL = nrhs > 1 ? kMaxRhs : 1;
+  return sizeof(double) * ((size_t)ngmax * kNL + (size_t)kNW * kNL * kRows);
 }
 
 int pcg_rows_blocks(int ngmax) { return (ngmax + kRows - 1) / kRows; }
