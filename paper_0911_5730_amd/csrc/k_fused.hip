@@ -515,8 +515,6 @@ __global__ void __launch_bounds__(kNT) k_pcg_matvec(LevelDev L, PcgDev P, int u)
   __shared__ double red[kMaxRhs * 16];
   __shared__ double bet[kMaxRhs];
   __shared__ int lc[kMaxRhs];
-  if (P.sc[0].all_done) return;
-  const int it = P.sc[0].it_base + u;
   const int s = blockIdx.x;
   const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
   const int nI = L.nint[s];
@@ -535,6 +533,10 @@ __global__ void __launch_bounds__(kNT) k_pcg_matvec(LevelDev L, PcgDev P, int u)
   const bool act = narrow && mc < nch;
   SymRowRegs<16, double> sv;
   if (narrow) sv.load(Sg, ng, mi, mc, nch, P.full);
+  // (the flag is tested after the operator loads are issued: they are in
+  // bounds either way, and the test does not delay them)
+  if (P.sc[0].all_done) return;
+  const int it = P.sc[0].it_base + u;
   // the live columns and their beta: every thread reads the flags and scalars
   // (uniform loads, before this launch stores anything, so they take the
   // scalar path and do not wait for the operator loads above) and writes the
@@ -687,8 +689,6 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
   __shared__ double red[kMaxRhs * 16];   // (slot sums: waves, then the per-slot results at 16)
   __shared__ double alph[kMaxRhs];
   __shared__ int lc[kMaxRhs];
-  if (P.sc[0].all_done) return;
-  const int it = u < 0 ? 0 : P.sc[0].it_base + u;
   const int s = blockIdx.x;
   const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
   const int ng = n - L.nint[s];
@@ -738,6 +738,9 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
         pv[m][q] = Pg[a + (size_t)k * ng];
       }
   }
+  // (the flag is tested after the operator loads are issued)
+  if (P.sc[0].all_done) return;
+  const int it = u < 0 ? 0 : P.sc[0].it_base + u;
   if constexpr (kPrec == 2) {
     for (int a = tid; a < n_r; a += kNT) dinv[a] = P.Dinv[g0 + a];
     const int nq = n_r * P.ncr[s];
@@ -807,12 +810,17 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
         own = L.sh_flat[L.sh_ptr[gi]] == f;
       }
       const double al = kMulti ? alph[k] : alpha0;
-      const double ri = rold[ci + gi] - al * q;
+      // the owner's x and p are loaded with r_{k-1}, before any store (the
+      // compiler may not move loads across the store of r_k)
+      const double ro = rold[ci + gi];
+      const double xo = own ? P.x[ci + gi] : 0.0;
+      const double po = own ? p[ci + gi] : 0.0;
+      const double ri = ro - al * q;
       g[k * ngmax + a] = L.delta[f] * ri;
       double rr = 0.0;
       if (own) {
         rnew[ci + gi] = ri;
-        P.x[ci + gi] += al * p[ci + gi];
+        P.x[ci + gi] = xo + al * po;
         rr = ri * ri;
       }
       return rr;
