@@ -2536,6 +2536,7 @@ bddc_status bddc_setup(const bddc_problem* p, void* hip_stream, bddc_handle* out
       const char* renv = getenv("BDDC_PCG_ROWS");
       const bool rows = h->precision != BDDC_BF16 && (renv ? std::string(renv) == "1" : l1.ngmax > kNT);
       P.nrb = rows ? pcg_rows_blocks(l1.ngmax) : 0;
+      P.fullpad = rows ? 1 : 0;
       if (rows) P.full = 1;
       if (h->precision == BDDC_BF16) {
         // the factored form stages W of a whole substructure in LDS
@@ -2550,8 +2551,10 @@ bddc_status bddc_setup(const bddc_problem* p, void* hip_stream, bddc_handle* out
     std::vector<int64_t> spoff(l1.nsub + 1, 0), tpoff(l1.nsub + 1, 0);
     for (int s = 0; s < l1.nsub; ++s) {
       const int64_t ng = l1.topo.ngam(s), nr = l1.topo.n_r[s];
-      spoff[s + 1] = spoff[s] + (P.full ? ng * ng : ng * (ng + 1) / 2);
-      tpoff[s + 1] = tpoff[s] + (P.full ? nr * nr : nr * (nr + 1) / 2);
+      const int64_t lds_ = P.fullpad ? pad_ld((int)ng, 8) : ng;
+      const int64_t ldt = P.fullpad ? pad_ld((int)nr, h->precision == BDDC_FP32 ? 4 : 8) : nr;
+      spoff[s + 1] = spoff[s] + (P.full ? lds_ * ng : ng * (ng + 1) / 2);
+      tpoff[s + 1] = tpoff[s] + (P.full ? ldt * nr : nr * (nr + 1) / 2);
     }
     // every sharer's flat entry of each flat entry's dof, padded to four
     bool fits4 = true;

@@ -1128,13 +1128,15 @@ __global__ void __launch_bounds__(kNT) k_pack_pcg(LevelDev L, PcgDev P) {
   const int n_r = L.nr[s];
   const double* S = L.K + L.koff[s] + nI + (size_t)nI * n;
   double* Sp = const_cast<double*>(P.Sp) + P.spoff[s];
+  const int lds_ = P.fullpad ? pad_ld(ng, 8) : ng;
   for (ColWalk w_(threadIdx.x, kNT, ng); w_.j < ng; w_.next())
-    if (P.full || w_.i >= w_.j) Sp[op_index(w_.i, w_.j, ng, P.full)] = S[w_.i + (size_t)w_.j * n];
+    if (P.full || w_.i >= w_.j) Sp[op_index(w_.i, w_.j, lds_, P.full)] = S[w_.i + (size_t)w_.j * n];
   if (P.prec == 2) return;
   const double* T = L.T + L.toff[s];
+  const int ldt = P.fullpad ? pad_ld(n_r, P.prec == 0 ? 8 : 4) : n_r;
   for (ColWalk w_(threadIdx.x, kNT, n_r); w_.j < n_r; w_.next()) {
     if (!P.full && w_.i < w_.j) continue;
-    const int k = op_index(w_.i, w_.j, n_r, P.full);
+    const int k = P.full ? op_index(w_.i, w_.j, ldt, true) : op_index(w_.i, w_.j, n_r, false);
     const double v = T[w_.i + (size_t)w_.j * n_r];
     if (P.prec == 0) const_cast<double*>(P.Tp)[P.tpoff[s] + k] = v;
     else const_cast<float*>(P.Tp32)[P.tpoff[s] + k] = static_cast<float>(v);

@@ -9,8 +9,8 @@
 // chain of dependent batches.  Here the rows of S_s (and of T_rr) are cut
 // into blocks of 64 and every block gets a workgroup of four waves; wave w
 // reads the columns of its quarter, lane l row 64 rb + l, so every load is
-// 64 consecutive entries of one column (full column-major storage), sixteen
-// loads in flight per lane, and each entry is applied to every live
+// 64 consecutive entries of one column (full column-major storage, columns
+// starting on 128-byte boundaries), sixteen loads in flight per lane, and each entry is applied to every live
 // right-hand side.  The wave partials are summed in wave order, so a column
 // solved alone and the same column in a blocked solve give bitwise the same
 // result.  The vectors a block needs (p_s, or g = delta r_s) are gathered by
@@ -116,6 +116,7 @@ __global__ void __launch_bounds__(kRT) k_pcg_matvec_rows(LevelDev L, PcgDev P, i
     if (tid < nl) P.pq_part[(size_t)col(tid) * P.ld_sub + slot] = 0.0;
     return;
   }
+  const int ld = pad_ld(ng, 8);   // (columns on 128-byte boundaries: a 64-row block is four whole lines)
   const double* Sg = P.Sp + P.spoff[s] + r0 + min(lane, rows - 1);
   const int cq = (ng + kNW - 1) / kNW;
   const int j0 = min(ng, wave * cq), j1 = min(ng, j0 + cq);
@@ -157,7 +158,7 @@ __global__ void __launch_bounds__(kRT) k_pcg_matvec_rows(LevelDev L, PcgDev P, i
   double acc[kNL];
 #pragma unroll
   for (int k = 0; k < kNL; ++k) acc[k] = 0.0;
-  row_product<kNL>(acc, Sg, ng, j0, j1, pl);
+  row_product<kNL>(acc, Sg, ld, j0, j1, pl);
 #pragma unroll
   for (int k = 0; k < kNL; ++k)
     if (k < nl) part[(wave * kNL + k) * kRows + lane] = acc[k];
@@ -371,7 +372,7 @@ __global__ void __launch_bounds__(kRT) k_pcg_update_restrict_rows(LevelDev L, Pc
     double acc[kNL];
 #pragma unroll
     for (int k = 0; k < kNL; ++k) acc[k] = 0.0;
-    row_product<kNL>(acc, Tg, n_r, j0, j1, g);
+    row_product<kNL>(acc, Tg, pad_ld(n_r, sizeof(T)), j0, j1, g);
 #pragma unroll
     for (int k = 0; k < kNL; ++k)
       if (k < nl) part[(wave * kNL + k) * kRows + lane] = acc[k];

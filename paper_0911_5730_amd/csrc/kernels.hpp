@@ -220,6 +220,9 @@ struct PcgDev {
   // per block, npq = nsub1 * max(1, nrb) partials per column
   int nrb = 0;
   int npq = 0;
+  // full storage with each column starting on a 128-byte boundary (leading
+  // dimension pad_ld(m, element bytes)), used with the row-block launches
+  int fullpad = 0;
   int nblk = 1;                              // blocks of the interface average (rz partials)
   // 1: a one-block launch after each producing launch sums its partials once
   // into PcgScalars (rzs, pqs, rrs) and the consumers read that scalar; 0:
@@ -261,6 +264,12 @@ struct PcgDev {
   const double* uc = nullptr;  // level-1 coarse correction, per column
 };
 constexpr int kMaxRhs = 8;   // columns of one blocked solve
+// leading dimension of an m-row column-major matrix whose columns start on
+// 128-byte boundaries
+__host__ __device__ inline int pad_ld(int m, int elem_bytes) {
+  const int e = 128 / elem_bytes;
+  return (m + e - 1) / e * e;
+}
 constexpr int kCoarseInvMin = 512;   // coarse spaces at least this large are solved with A_L^-1
 
 constexpr int kMaxHist = 4096;
