@@ -368,6 +368,8 @@ def main():
     ap.add_argument("--no-batching", action="store_true", help="skip the config-4 (uneven substructures) measurement")
     ap.add_argument("--no-precision-forms", action="store_true",
                     help="skip the FP64 / FP32 / BF16 comparison on config 2")
+    ap.add_argument("--batching-only", action="store_true",
+                    help="only the config-4 (uneven substructures, eight loads) measurement, as one JSON line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 256 MiB device buffer three times (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -392,6 +394,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration": {"bytes_read": COPY_BYTES, "bytes_written": COPY_BYTES, "copies": 3}}))
+        return
+    if args.batching_only:
+        print(json.dumps({"batching_form": batching_form(P, synth, torch, torch.cuda.current_stream())}))
         return
     prob = synth.config(args.config)
     coeff = torch.tensor(prob.coeff, dtype=torch.float64, device="cuda")
