@@ -321,3 +321,19 @@ def test_disconnected_coarse_substructure_is_rejected():
     with pytest.raises(P.BDDCError) as ei:
         P.Solver(prob)
     assert ei.value.name == "BDDC_EPARTITION"
+
+
+def test_bf16_form_refused_where_its_factor_does_not_fit_lds():
+    """The factored BF16 form stages each substructure's W in LDS: with a
+    centre substructure of 256 interface dofs (3 x 3 substructures of 64 x 64
+    elements) the set-up refuses it with BDDC_EUNSUPPORTED, while the FP32
+    form of the same problem sets up and solves."""
+    import paper_0911_5730_amd as P
+    prob = synth.square_problem(192, 3, kmode="one", seed=41)
+    print("bf16 refusal: 192 x 192, 3 x 3 substructures", flush=True)
+    with pytest.raises(P.BDDCError) as ei:
+        P.Solver(prob, precision="bf16")
+    assert ei.value.name == "BDDC_EUNSUPPORTED"
+    with P.Solver(prob, precision="fp32") as S:
+        _, it, rr = S.solve(cuda_vec(prob.f[0]))
+        assert rr[0] <= 1e-8 and it[0] > 0
