@@ -408,7 +408,10 @@ struct Level {
     int32_t *tprof, *tproff;
     double* Wd;
     int64_t* woff;
+    // level-1 sweeps: the envelope's interior row ends per panel
+    int32_t *srend, *srendoff;
   } d{};
+  bool sweep_env = false;
   std::vector<int64_t> linvoff;
   bool big = false;   // interior elimination by the tiled kernel
   LevelDev dev;
@@ -942,6 +945,51 @@ class Builder {
         });
     }
 
+    // level-1 sweeps (local matrices small enough for LDS panels): per
+    // substructure and panel (64-wide panels, then 32-wide) the end of the
+    // interior rows that can be nonzero in the panel's columns -- one past
+    // the last interior row whose first nonzero lies left of the panel's end
+    // (BDDC_SWEEP_ENV=0: every row)
+    std::vector<int32_t> srendoff, srend;
+    {
+      const char* eenv = getenv("BDDC_SWEEP_ENV");
+      const bool env_on = !(eenv && std::string(eenv) == "0");
+      if (G && !lv.big && env_on && sweep_fits(lv.nmax)) {
+        srendoff.assign(nsub + 1, 0);
+        for (int s = 0; s < nsub; ++s) {
+          const int nI = T.n_int[s];
+          srendoff[s + 1] = srendoff[s] + (nI + 63) / 64 + (nI + 31) / 32;
+        }
+        srend.assign(std::max<int32_t>(1, srendoff[nsub]), 0);
+        parallel_for(nsub, 8, [&](int s0, int s1) {
+          std::vector<int> f;
+          for (int s = s0; s < s1; ++s) {
+            const int n = T.nloc(s), nI = T.n_int[s];
+            f.assign(n, INT32_MAX);
+            for (int k = sub_el_ptr[s]; k < sub_el_ptr[s + 1]; ++k) {
+              const int32_t* loc = &el_loc[(size_t)k * 4];
+              int mn = INT32_MAX;
+              for (int q = 0; q < 4; ++q)
+                if (loc[q] >= 0 && loc[q] < nI) mn = std::min(mn, (int)loc[q]);
+              if (mn == INT32_MAX) continue;
+              for (int q = 0; q < 4; ++q)
+                if (loc[q] >= 0) f[loc[q]] = std::min(f[loc[q]], mn);
+            }
+            int32_t* e = &srend[srendoff[s]];
+            for (const int bw : {64, 32}) {
+              for (int b = 0; b * bw < nI; ++b) {
+                const int c1 = std::min(nI, (b + 1) * bw);
+                int r = c1;
+                for (int i = c1; i < nI; ++i)
+                  if (f[i] < c1) r = i + 1;
+                *e++ = r;
+              }
+            }
+          }
+        });
+      }
+    }
+
     clk.lap("  maps");
     Arena& A = lv.arena_a;
     auto& d = lv.d;
@@ -1012,6 +1060,8 @@ class Builder {
       d.tproff = A.take<int32_t>(tproff.size());
       d.Wd = A.take<double>(woff.empty() ? 0 : (size_t)woff.back());
       d.woff = A.take<int64_t>(woff.size());
+      d.srend = A.take<int32_t>(srend.size());
+      d.srendoff = A.take<int32_t>(srendoff.size());
     };
     A.reset_sizing();
     layout(false);
@@ -1068,6 +1118,11 @@ class Builder {
       stg.add(d.tproff, tproff);
       stg.add(d.woff, woff);
     }
+    if (!srend.empty()) {
+      stg.add(d.srend, srend);
+      stg.add(d.srendoff, srendoff);
+    }
+    lv.sweep_env = !srend.empty();
     if (adaptive) {
       stg.add(d.schws_off, lv.schws_off);
       stg.add(d.eigws_off, lv.eigws_off);
@@ -1365,6 +1420,8 @@ class Builder {
     D.linvoff = d.linvoff;
     D.tprof = lv.big ? d.tprof : nullptr;
     D.tproff = lv.big ? d.tproff : nullptr;
+    D.srend = lv.sweep_env ? d.srend : nullptr;
+    D.srendoff = lv.sweep_env ? d.srendoff : nullptr;
     D.Wd = lv.big ? d.Wd : nullptr;
     D.woff = lv.big ? d.woff : nullptr;
     D.csh_ptr = d.csh_ptr;

@@ -42,29 +42,58 @@ __device__ inline double lane_value(double v, int lane) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// A panel holds columns [c0, c1) of the rows that can be nonzero there: the
+// interior rows [c0, ri) and the interface rows [nI, n).  ri comes from the
+// envelope of the local matrix (the factor keeps it: L[i][j] = 0 left of row
+// i's first nonzero), so the interior rows past the band are neither loaded
+// nor swept; without an envelope ri = nI (every row below c0).
 struct Panel {
-  int c0, c1, rows;                        // columns [c0, c1), rows [c0, n)
+  int c0, c1, rows;                        // columns [c0, c1), `rows` panel rows
+  int ri, nI;
+  __device__ int row(int r) const { return r < ri - c0 ? c0 + r : nI + (r - (ri - c0)); }
+  __device__ int local(int i) const { return i < ri ? i - c0 : (ri - c0) + (i - nI); }
 };
 
+// panel b of BW columns; rend: the envelope's interior row ends of the
+// substructure's panels (null: every row)
 template <int BW>
-__device__ inline Panel panel_of(int b, int n, int nI) {
+__device__ inline Panel panel_of(int b, int n, int nI, const int32_t* rend) {
   Panel p;
   p.c0 = b * BW;
   p.c1 = min(p.c0 + BW, nI);
-  p.rows = n - p.c0;
+  const int nb = (nI + BW - 1) / BW;
+  p.ri = (rend && b >= 0 && b < nb) ? max(p.c1, min(nI, (int)rend[b])) : nI;
+  p.nI = nI;
+  p.rows = (p.ri - p.c0) + (n - nI);
   return p;
 }
 
-// issue the loads of panel p (rows [c0, n) x cols [c0, c1) of A) into registers
+// the interior row ends of substructure s for BW-wide panels (64-wide panels
+// first, then 32-wide), or null
+template <int BW>
+__device__ inline const int32_t* panel_ends(const LevelDev& L, int s) {
+  if (!L.srend) return nullptr;
+  const int32_t* e = L.srend + L.srendoff[s];
+  return BW == 64 ? e : e + (L.nint[s] + 63) / 64;
+}
+
+// issue the loads of panel p (its rows x cols [c0, c1) of A) into registers
 template <int BW>
 __device__ inline void panel_load(const double* __restrict__ A, int n, const Panel& p, double (&r)[kRegs<BW>]) {
   const int w = p.c1 - p.c0;
   ColWalk cw(threadIdx.x, kSweepNT, p.rows);
 #pragma unroll
   for (int u = 0; u < kRegs<BW>; ++u) {
-    r[u] = cw.j < w ? A[(p.c0 + cw.i) + (size_t)(p.c0 + cw.j) * n] : 0.0;
+    r[u] = cw.j < w ? A[p.row(cw.i) + (size_t)(p.c0 + cw.j) * n] : 0.0;
     cw.next();
   }
+}
+
+// the first global row >= i0 with i0's residue mod 8 that lies in the panel
+// (rows between ri and nI are skipped; the stride-8 pattern over global rows
+// is the dense sweep's, so every partial sum keeps its terms and order)
+__device__ inline int next_row8(const Panel& p, int i) {
+  return (i >= p.ri && i < p.nI) ? i + ((p.nI - i + 7) / 8) * 8 : i;
 }
 
 // store panel registers into LDS: P[(i - c0) + k * rows]
@@ -79,16 +108,17 @@ __device__ inline void panel_store(double* P, const Panel& p, const double (&r)[
 }
 
 template <int BW>
-__device__ __forceinline__ void sweep_fwd(const double* __restrict__ A, int n, int nI, double* w, double* P) {
+__device__ __forceinline__ void sweep_fwd(const double* __restrict__ A, int n, int nI, double* w, double* P,
+                                          const int32_t* rend) {
   const int tid = threadIdx.x;
   const int nb = (nI + BW - 1) / BW;
   double r[kRegs<BW>];
-  Panel p = panel_of<BW>(0, n, nI);
+  Panel p = panel_of<BW>(0, n, nI, rend);
   panel_load<BW>(A, n, p, r);
   panel_store<BW>(P, p, r);
   __syncthreads();
   for (int b = 0; b < nb; ++b) {
-    const Panel q = panel_of<BW>(b + 1, n, nI);
+    const Panel q = panel_of<BW>(b + 1, n, nI, rend);
     if (b + 1 < nb) panel_load<BW>(A, n, q, r);
     const int wb = p.c1 - p.c0;
     if (tid < 64) {
@@ -105,12 +135,12 @@ __device__ __forceinline__ void sweep_fwd(const double* __restrict__ A, int n, i
     }
     __syncthreads();
     // rows below the block
-    for (int i = p.c0 + wb + tid; i < n; i += kSweepNT) {
+    for (int rr = wb + tid; rr < p.rows; rr += kSweepNT) {
       double acc = 0.0;
-      const double* Pi = P + (i - p.c0);
+      const double* Pi = P + rr;
 #pragma unroll 8
       for (int k = 0; k < wb; ++k) acc += Pi[k * p.rows] * w[p.c0 + k];
-      w[i] -= acc;
+      w[p.row(rr)] -= acc;
     }
     __syncthreads();
     if (b + 1 < nb) {
@@ -122,16 +152,17 @@ __device__ __forceinline__ void sweep_fwd(const double* __restrict__ A, int n, i
 }
 
 template <int BW>
-__device__ __forceinline__ void sweep_bwd(const double* __restrict__ A, int n, int nI, double* w, double* P) {
+__device__ __forceinline__ void sweep_bwd(const double* __restrict__ A, int n, int nI, double* w, double* P,
+                                          const int32_t* rend) {
   const int tid = threadIdx.x;
   const int nb = (nI + BW - 1) / BW;
   double r[kRegs<BW>];
-  Panel p = panel_of<BW>(nb - 1, n, nI);
+  Panel p = panel_of<BW>(nb - 1, n, nI, rend);
   panel_load<BW>(A, n, p, r);
   panel_store<BW>(P, p, r);
   __syncthreads();
   for (int b = nb - 1; b >= 0; --b) {
-    const Panel q = panel_of<BW>(b - 1, n, nI);
+    const Panel q = panel_of<BW>(b - 1, n, nI, rend);
     if (b > 0) panel_load<BW>(A, n, q, r);
     const int wb = p.c1 - p.c0;
     // w_j -= sum over rows below the block of L[i][j] w_i, eight lanes per column
@@ -139,7 +170,8 @@ __device__ __forceinline__ void sweep_bwd(const double* __restrict__ A, int n, i
       const int j = tid >> 3, part = tid & 7;
       double acc = 0.0;
       if (j < wb)
-        for (int i = p.c0 + wb + part; i < n; i += 8) acc += P[(i - p.c0) + j * p.rows] * w[i];
+        for (int i = next_row8(p, p.c0 + wb + part); i < n; i = next_row8(p, i + 8))
+          acc += P[p.local(i) + j * p.rows] * w[i];
       acc += __shfl_xor(acc, 1);
       acc += __shfl_xor(acc, 2);
       acc += __shfl_xor(acc, 4);
@@ -175,16 +207,16 @@ __device__ __forceinline__ void sweep_bwd(const double* __restrict__ A, int n, i
 constexpr int kCBW = 32;
 
 __device__ __forceinline__ void sweep_fwd_cols(const double* __restrict__ A, int n, int nI, double* w, int R,
-                                               double* P) {
+                                               double* P, const int32_t* rend) {
   const int tid = threadIdx.x, wave = tid >> 6;
   const int nb = (nI + kCBW - 1) / kCBW;
   double r[kRegs<kCBW>];
-  Panel p = panel_of<kCBW>(0, n, nI);
+  Panel p = panel_of<kCBW>(0, n, nI, rend);
   panel_load<kCBW>(A, n, p, r);
   panel_store<kCBW>(P, p, r);
   __syncthreads();
   for (int b = 0; b < nb; ++b) {
-    const Panel q = panel_of<kCBW>(b + 1, n, nI);
+    const Panel q = panel_of<kCBW>(b + 1, n, nI, rend);
     if (b + 1 < nb) panel_load<kCBW>(A, n, q, r);
     const int wb = p.c1 - p.c0;
     if (wave < R) {
@@ -202,15 +234,15 @@ __device__ __forceinline__ void sweep_fwd_cols(const double* __restrict__ A, int
     }
     __syncthreads();
     // rows below the block, every column
-    const int below = n - p.c0 - wb;
+    const int below = p.rows - wb;
     for (int t = tid; t < below * R; t += kSweepNT) {
-      const int c = t / below, i = p.c0 + wb + (t - c * below);
+      const int c = t / below, rr = wb + (t - c * below);
       double* wc = w + c * kSweepRows;
       double acc = 0.0;
-      const double* Pi = P + (i - p.c0);
+      const double* Pi = P + rr;
 #pragma unroll 8
       for (int k = 0; k < wb; ++k) acc += Pi[k * p.rows] * wc[p.c0 + k];
-      wc[i] -= acc;
+      wc[p.row(rr)] -= acc;
     }
     __syncthreads();
     if (b + 1 < nb) {
@@ -222,16 +254,16 @@ __device__ __forceinline__ void sweep_fwd_cols(const double* __restrict__ A, int
 }
 
 __device__ __forceinline__ void sweep_bwd_cols(const double* __restrict__ A, int n, int nI, double* w, int R,
-                                               double* P) {
+                                               double* P, const int32_t* rend) {
   const int tid = threadIdx.x, wave = tid >> 6;
   const int nb = (nI + kCBW - 1) / kCBW;
   double r[kRegs<kCBW>];
-  Panel p = panel_of<kCBW>(nb - 1, n, nI);
+  Panel p = panel_of<kCBW>(nb - 1, n, nI, rend);
   panel_load<kCBW>(A, n, p, r);
   panel_store<kCBW>(P, p, r);
   __syncthreads();
   for (int b = nb - 1; b >= 0; --b) {
-    const Panel q = panel_of<kCBW>(b - 1, n, nI);
+    const Panel q = panel_of<kCBW>(b - 1, n, nI, rend);
     if (b > 0) panel_load<kCBW>(A, n, q, r);
     const int wb = p.c1 - p.c0;
     // w_j -= sum over rows below the block of L[i][j] w_i, eight lanes per
@@ -242,7 +274,8 @@ __device__ __forceinline__ void sweep_bwd_cols(const double* __restrict__ A, int
       double acc = 0.0;
       if (pr < wb * R) {
         const double* wc = w + c * kSweepRows;
-        for (int i = p.c0 + wb + part; i < n; i += 8) acc += P[(i - p.c0) + j * p.rows] * wc[i];
+        for (int i = next_row8(p, p.c0 + wb + part); i < n; i = next_row8(p, i + 8))
+          acc += P[p.local(i) + j * p.rows] * wc[i];
       }
       acc += __shfl_xor(acc, 1);
       acc += __shfl_xor(acc, 2);
@@ -292,7 +325,7 @@ __global__ void __launch_bounds__(kSweepNT, kSweepBlocks<32>) k_sweep_pre_cols(L
     w[c * kSweepRows + i] = i < nI ? r[(size_t)c * ldr + L.int_gid[L.ioff[s] + i]] : 0.0;
   }
   __syncthreads();
-  if (nI > 0) sweep_fwd_cols(L.K + L.koff[s], n, nI, w, R, P);
+  if (nI > 0) sweep_fwd_cols(L.K + L.koff[s], n, nI, w, R, P, panel_ends<kCBW>(L, s));
   for (int q = tid; q < n * R; q += kSweepNT) {
     const int c = q / n, i = q - c * n;
     if (i < nI) y[(size_t)c * ldy + L.ioff[s] + i] = w[c * kSweepRows + i];
@@ -327,7 +360,7 @@ __global__ void __launch_bounds__(kSweepNT, kSweepBlocks<32>) k_sweep_recover_co
   }
   __syncthreads();
   if (nI == 0) return;
-  sweep_bwd_cols(L.K + L.koff[s], n, nI, w, R, P);
+  sweep_bwd_cols(L.K + L.koff[s], n, nI, w, R, P, panel_ends<kCBW>(L, s));
   for (int q = tid; q < nI * R; q += kSweepNT) {
     const int c = q / nI, i = q - c * nI;
     u[(size_t)c * ldu + L.int_gid[L.ioff[s] + i]] = w[c * kSweepRows + i];
@@ -349,7 +382,7 @@ __global__ void __launch_bounds__(kSweepNT, kSweepBlocks<BW>) k_sweep_pre(LevelD
   const int tid = threadIdx.x;
   for (int i = tid; i < n; i += kSweepNT) w[i] = i < nI ? r[L.int_gid[L.ioff[s] + i]] : 0.0;
   __syncthreads();
-  if (nI > 0) sweep_fwd<BW>(A, n, nI, w, P);
+  if (nI > 0) sweep_fwd<BW>(A, n, nI, w, P, panel_ends<BW>(L, s));
   for (int i = tid; i < nI; i += kSweepNT) L.y[L.ioff[s] + i] = w[i];
   for (int a = tid; a < ng; a += kSweepNT) L.t[L.goff[s] + a] = -w[nI + a];
 }
@@ -379,7 +412,7 @@ __global__ void __launch_bounds__(kSweepNT, kSweepBlocks<BW>) k_sweep_post(Level
   for (int i = tid; i < nI; i += kSweepNT) w[i] = L.y[L.ioff[s] + i];
   __syncthreads();
   if (nI == 0) return;
-  sweep_bwd<BW>(L.K + L.koff[s], n, nI, w, P);
+  sweep_bwd<BW>(L.K + L.koff[s], n, nI, w, P, panel_ends<BW>(L, s));
   for (int i = tid; i < nI; i += kSweepNT) u[L.int_gid[L.ioff[s] + i]] = w[i];
 }
 
@@ -406,7 +439,7 @@ __global__ void __launch_bounds__(kSweepNT, kSweepBlocks<BW>) k_sweep_recover(Le
   for (int i = tid; i < nI; i += kSweepNT) w[i] = L.y[L.ioff[s] + i];
   __syncthreads();
   if (nI == 0) return;
-  sweep_bwd<BW>(L.K + L.koff[s], n, nI, w, P);
+  sweep_bwd<BW>(L.K + L.koff[s], n, nI, w, P, panel_ends<BW>(L, s));
   for (int i = tid; i < nI; i += kSweepNT) u[L.int_gid[L.ioff[s] + i]] = w[i];
 }
 

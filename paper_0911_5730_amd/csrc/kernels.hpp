@@ -79,6 +79,11 @@ struct LevelDev {
   // column-major each), offsets woff
   const int32_t* tprof = nullptr;
   const int32_t* tproff = nullptr;
+  // level-1 sweeps: per substructure the end of the interior rows of each
+  // panel's envelope (64-wide panels, then 32-wide), offsets srendoff; null =
+  // every interior row below the panel
+  const int32_t* srend = nullptr;
+  const int32_t* srendoff = nullptr;
   const double* Wd = nullptr;
   const int64_t* woff = nullptr;
 };
