@@ -2598,7 +2598,7 @@ bddc_status bddc_setup(const bddc_problem* p, void* hip_stream, bddc_handle* out
       if (h->precision == BDDC_BF16) {
         // the factored form stages W of a whole substructure in LDS
         const size_t nr = (size_t)l1.nrmax;
-        const size_t lds = sizeof(double) * (2 * (size_t)l1.ngmax + kNT + nr + nr * (nr + 1) / 2) +
+        const size_t lds = sizeof(double) * (3 * (size_t)l1.ngmax + kNT + nr + nr * (nr + 1) / 2) +
                            sizeof(float) * (nr * (size_t)l1.ncsmax + nr);
         if (lds > kLdsMax)
           fail(BDDC_EUNSUPPORTED, "the BF16 form needs the factored T_rr of each substructure in LDS; the widest "

@@ -701,7 +701,8 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
   const int psz = kNT + ngmax;                          // part stride per column
   double* g = sh;                                       // R x ngmax
   double* part = sh + (size_t)R * ngmax;                // R x psz
-  double* xv = part + (size_t)R * psz;                  // factored form: x, then v (nrmax)
+  double* dl = part + (size_t)R * psz;                  // delta on the substructure's interface (ngmax)
+  double* xv = dl + ngmax;                              // factored form: x, then v (nrmax)
   float* Tl = reinterpret_cast<float*>(xv + nrmax);                       // factored form: packed W
   float* Ql = reinterpret_cast<float*>(xv + nrmax + ((size_t)nrmax * (nrmax + 1) / 2));   // Q
   float* dinv = Ql + (size_t)nrmax * ncsmax;                              // D^-1
@@ -738,6 +739,9 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
         pv[m][q] = Pg[a + (size_t)k * ng];
       }
   }
+  // the weights of the rows' final scaling, loaded with the operators (kept
+  // in LDS below, so the last phase does not wait on another load)
+  const double dlv = tid < ng ? L.delta[g0 + tid] : 0.0;
   // (the flag is tested after the operator loads are issued)
   if (P.sc[0].all_done) return;
   const int it = u < 0 ? 0 : P.sc[0].it_base + u;
@@ -859,6 +863,8 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
     }
   }
   if constexpr (kPrec == 2) pt.finish();
+  if (tid < ng) dl[tid] = dlv;
+  for (int a = kNT + tid; a < ng; a += kNT) dl[a] = L.delta[g0 + a];   // (wider than the workgroup)
   __syncthreads();
   // b = Psi^T g, one wave per coarse dof, every live column (several columns:
   // each entry of Psi loaded once for all of them, the same sums per column)
@@ -957,7 +963,7 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
       for (int i = tid; i < n_r; i += kNT) {
         double acc = 0.0;
         for (int c = 0; c < nch; ++c) acc += pk[i + c * n_r];
-        da[g0 + i] = L.delta[g0 + i] * (acc * static_cast<double>(dinv[i]));
+        da[g0 + i] = dl[i] * (acc * static_cast<double>(dinv[i]));
       }
       __syncthreads();   // part and x/v are taken by the next column
     }
@@ -1006,14 +1012,14 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
       for (int i = tid; i < n_r; i += kNT) {
         double acc = 0.0;
         for (int c = 0; c < nc; ++c) acc += part[i + c * n_r];
-        P.da[g0 + i] = L.delta[g0 + i] * acc;
+        P.da[g0 + i] = dl[i] * acc;
       }
     } else {
       for (int t = tid; t < n_r * nl; t += kNT) {
         const int k = t / n_r, i = t - k * n_r;
         double acc = 0.0;
         for (int c = 0; c < nc; ++c) acc += part[k * psz + i + c * n_r];
-        P.da[(size_t)col(k) * P.ld_flat + g0 + i] = L.delta[g0 + i] * acc;
+        P.da[(size_t)col(k) * P.ld_flat + g0 + i] = dl[i] * acc;
       }
     }
   }
@@ -1327,8 +1333,8 @@ void launch_pcg_advance(hipStream_t st, const PcgDev& P, int n) {
 }
 void launch_pcg_update_restrict(hipStream_t st, const LevelDev& L, int ngmax, int nrmax, int ncsmax, const PcgDev& P,
                                 int u) {
-  // doubles: g | part per column; factored form also: x/v (doubles) | W | Q | D^-1 (floats)
-  size_t lds = sizeof(double) * (size_t)P.nrhs * ((size_t)ngmax + kNT + ngmax);
+  // doubles: g | part per column | delta; factored form also: x/v (doubles) | W | Q | D^-1 (floats)
+  size_t lds = sizeof(double) * ((size_t)P.nrhs * ((size_t)ngmax + kNT + ngmax) + ngmax);
   if (P.prec == 2)
     lds += sizeof(double) * (nrmax + (size_t)nrmax * (nrmax + 1) / 2) +
            sizeof(float) * ((size_t)nrmax * ncsmax + nrmax);
