@@ -27,22 +27,31 @@ namespace {
 
 constexpr int kSpinLimit = 1 << 22;   // about 0.1 s of polling; past it the status flags a failure
 
-// Grid barrier (sense reversal).  The launch is cooperative, so every
-// workgroup is resident; the bounded spin only guards against a broken launch.
-__device__ void grid_barrier(unsigned* bar, unsigned nblocks, int* status) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+// Grid barrier (sense reversal) without cache maintenance.  Every value one
+// workgroup hands to another across a barrier (t, then da and b) is written
+// and read with agent-scope atomic accesses, which are coherent across the
+// XCDs' L2 caches; so the barrier only has to order them: each thread's
+// stores have completed (s_waitcnt) before the workgroup arrives, and the
+// reads after it are issued once the generation has moved.  A release /
+// acquire pair at agent scope would instead write back and invalidate the
+// L2 of every XCD at every barrier (measured: 4.0 and 4.7 us per barrier
+// against 3.0 and 3.4 us here, 16 workgroups).  `g` is the generation this
+// workgroup last saw (read at the start of the launch, thread 0 only).  The
+// spin is bounded; past the bound the status flags a failure.
+__device__ void grid_barrier(unsigned* bar, unsigned nblocks, int* status, unsigned& g) {
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
     unsigned* count = bar;
     unsigned* gen = bar + 1;
-    const unsigned g = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned arrived = __hip_atomic_fetch_add(count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned arrived = __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (arrived == nblocks - 1) {
       __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(gen, g + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_s_waitcnt(0);   // (the reset lands before the next generation is published)
+      __hip_atomic_store(gen, g + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
       int spins = 0;
-      while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+      while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
         if (++spins > kSpinLimit) {
           atomicOr(status, 4);
           break;
@@ -50,9 +59,15 @@ __device__ void grid_barrier(unsigned* bar, unsigned nblocks, int* status) {
         __builtin_amdgcn_s_sleep(1);
       }
     }
+    ++g;
   }
   __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// values handed between workgroups across a grid barrier
+__device__ inline void xstore(double* p, double v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+__device__ inline double xload(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // out(c, i) = sum_{j in [j0(i), j1(i))} A[i*rs + j*cs] x_c[j] for i < rows and
@@ -98,6 +113,9 @@ __global__ void __launch_bounds__(kCoopNT) k_deep_coop(CoopDev C) {
   if (C.stop && *C.stop) return;
   extern __shared__ double sh[];
   const int s = blockIdx.x, tid = threadIdx.x;
+  // the barrier generation on entry (no workgroup can move it before every
+  // workgroup has arrived at the first barrier, i.e. has read it)
+  unsigned gen = tid == 0 ? __hip_atomic_load(C.bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
   const int32_t* me = C.meta + (size_t)kCoopMeta * s;
   const int nI = me[0], ng = me[1], nr = me[2], ncs = me[3], nsh = me[4], ng1 = me[5], goff = me[6], coff = me[7];
   const int n = nI + ng;
@@ -200,41 +218,41 @@ __global__ void __launch_bounds__(kCoopNT) k_deep_coop(CoopDev C) {
   mv8c<kMulti>(nI + ng, R, Li, nI, 1, rI, mI, [](int) { return 0; }, [&](int) { return nI; },
        [&](int c, int i, double v) {
          if (i < nI) y[c * mI + i] = v;
-         else C.t[(size_t)c * C.ld_t + goff + i - nI] = v;
+         else xstore(&C.t[(size_t)c * C.ld_t + goff + i - nI], v);
        });
-  grid_barrier(C.bar, gridDim.x, C.status);
+  grid_barrier(C.bar, gridDim.x, C.status, gen);
   // g = delta (r_G - sum t);  a = T_rr g_r (ML-wDi);  b = Psi^T g (ML-coarse)
   for (int t = tid; t < ng * R; t += kCoopNT) {
     const int c = kMulti ? t / ng : 0, a = kMulti ? t - c * ng : t;
     const double* tc = C.t + (size_t)c * C.ld_t;
     double v = rG[c * mG + a];
-    for (int q = shp[a]; q < shp[a + 1]; ++q) v -= tc[shf[q]];
+    for (int q = shp[a]; q < shp[a + 1]; ++q) v -= xload(&tc[shf[q]]);
     g[c * mG + a] = dl[a] * v;
   }
   __syncthreads();
   mv8c<kMulti>(nr, R, Tm, 1, nr, g, mG, [](int) { return 0; }, [&](int) { return nr; },
-       [&](int c, int a, double v) { C.da[(size_t)c * C.ld_t + goff + a] = dl[a] * v; });
+       [&](int c, int a, double v) { xstore(&C.da[(size_t)c * C.ld_t + goff + a], dl[a] * v); });
   for (int t = tid; t < (ng - nr) * R; t += kCoopNT) {
     const int c = kMulti ? t / (ng - nr) : 0, a = nr + (kMulti ? t - c * (ng - nr) : t);
-    C.da[(size_t)c * C.ld_t + goff + a] = 0.0;
+    xstore(&C.da[(size_t)c * C.ld_t + goff + a], 0.0);
   }
   mv8c<kMulti>(ncs, R, Ps, ng, 1, g, mG, [](int) { return 0; }, [&](int) { return ng; },
-       [&](int c, int k, double v) { C.b[(size_t)c * C.ld_b + coff + k] = v; });
-  grid_barrier(C.bar, gridDim.x, C.status);
+       [&](int c, int k, double v) { xstore(&C.b[(size_t)c * C.ld_b + coff + k], v); });
+  grid_barrier(C.bar, gridDim.x, C.status, gen);
   // coarsest right-hand side r_c = sum of the coarse contributions, and the
   // sharers' sum of delta T_rr g on the interface, in one round of loads
   for (int t = tid; t < ncL * R; t += kCoopNT) {
     const int c = kMulti ? t / ncL : 0, k = kMulti ? t - c * ncL : t;
     const double* bc = C.b + (size_t)c * C.ld_b;
     double acc = 0.0;
-    for (int q = cg[k]; q < cg[k + 1]; ++q) acc += bc[cg[ncL + 1 + q]];
+    for (int q = cg[k]; q < cg[k + 1]; ++q) acc += xload(&bc[cg[ncL + 1 + q]]);
     rc[c * ncL + k] = acc;
   }
   for (int t = tid; t < ng * R; t += kCoopNT) {
     const int c = kMulti ? t / ng : 0, a = kMulti ? t - c * ng : t;
     const double* dc = C.da + (size_t)c * C.ld_t;
     double acc = 0.0;
-    for (int q = shp[a]; q < shp[a + 1]; ++q) acc += dc[shf[q]];
+    for (int q = shp[a]; q < shp[a + 1]; ++q) acc += xload(&dc[shf[q]]);
     av[c * mG + a] = acc;
   }
   __syncthreads();
