@@ -27,31 +27,28 @@ namespace {
 
 constexpr int kSpinLimit = 1 << 22;   // about 0.1 s of polling; past it the status flags a failure
 
-// Grid barrier (sense reversal) without cache maintenance.  Every value one
-// workgroup hands to another across a barrier (t, then da and b) is written
-// and read with agent-scope atomic accesses, which are coherent across the
-// XCDs' L2 caches; so the barrier only has to order them: each thread's
-// stores have completed (s_waitcnt) before the workgroup arrives, and the
-// reads after it are issued once the generation has moved.  A release /
-// acquire pair at agent scope would instead write back and invalidate the
-// L2 of every XCD at every barrier (measured: 4.0 and 4.7 us per barrier
-// against 3.0 and 3.4 us here, 16 workgroups).  `g` is the generation this
-// workgroup last saw (read at the start of the launch, thread 0 only).  The
-// spin is bounded; past the bound the status flags a failure.
-__device__ void grid_barrier(unsigned* bar, unsigned nblocks, int* status, unsigned& g) {
+// Grid barrier without cache maintenance.  Every value one workgroup hands
+// to another across a barrier (t, then da and b) is written and read with
+// agent-scope atomic accesses, which are coherent across the XCDs' L2
+// caches; so the barrier only has to order them: each thread's stores have
+// completed (s_waitcnt) before the workgroup arrives, and the reads after it
+// are issued once every workgroup has arrived.  A release / acquire pair at
+// agent scope would instead write back and invalidate the L2 of every XCD
+// at every barrier (measured: 4.0 and 4.7 us per barrier, 16 workgroups).
+// The arrival counter only grows (reset before each solve): barrier k of the
+// launch completes when it reaches (done + k + 1) x nblocks, where `done`
+// (thread 0's `passed`) counts the barriers completed before; no workgroup
+// can complete one before all have arrived, so the count read at the start
+// of the launch, divided by nblocks, gives it.  The spin is bounded; past
+// the bound the status flags a failure.
+__device__ void grid_barrier(unsigned* count, unsigned nblocks, int* status, unsigned& passed) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
-    unsigned* count = bar;
-    unsigned* gen = bar + 1;
-    const unsigned arrived = __hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (arrived == nblocks - 1) {
-      __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __builtin_amdgcn_s_waitcnt(0);   // (the reset lands before the next generation is published)
-      __hip_atomic_store(gen, g + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
+    const unsigned target = (passed + 1) * nblocks;
+    if (__hip_atomic_fetch_add(count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1 != target) {
       int spins = 0;
-      while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+      while (__hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
         if (++spins > kSpinLimit) {
           atomicOr(status, 4);
           break;
@@ -59,7 +56,7 @@ __device__ void grid_barrier(unsigned* bar, unsigned nblocks, int* status, unsig
         __builtin_amdgcn_s_sleep(1);
       }
     }
-    ++g;
+    ++passed;
   }
   __syncthreads();
 }
@@ -113,9 +110,8 @@ __global__ void __launch_bounds__(kCoopNT) k_deep_coop(CoopDev C) {
   if (C.stop && *C.stop) return;
   extern __shared__ double sh[];
   const int s = blockIdx.x, tid = threadIdx.x;
-  // the barrier generation on entry (no workgroup can move it before every
-  // workgroup has arrived at the first barrier, i.e. has read it)
-  unsigned gen = tid == 0 ? __hip_atomic_load(C.bar + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+  // grid barriers completed before this launch
+  unsigned passed = tid == 0 ? __hip_atomic_load(C.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) / gridDim.x : 0u;
   const int32_t* me = C.meta + (size_t)kCoopMeta * s;
   const int nI = me[0], ng = me[1], nr = me[2], ncs = me[3], nsh = me[4], ng1 = me[5], goff = me[6], coff = me[7];
   const int n = nI + ng;
@@ -220,7 +216,7 @@ __global__ void __launch_bounds__(kCoopNT) k_deep_coop(CoopDev C) {
          if (i < nI) y[c * mI + i] = v;
          else xstore(&C.t[(size_t)c * C.ld_t + goff + i - nI], v);
        });
-  grid_barrier(C.bar, gridDim.x, C.status, gen);
+  grid_barrier(C.bar, gridDim.x, C.status, passed);
   // g = delta (r_G - sum t);  a = T_rr g_r (ML-wDi);  b = Psi^T g (ML-coarse)
   for (int t = tid; t < ng * R; t += kCoopNT) {
     const int c = kMulti ? t / ng : 0, a = kMulti ? t - c * ng : t;
@@ -238,7 +234,7 @@ __global__ void __launch_bounds__(kCoopNT) k_deep_coop(CoopDev C) {
   }
   mv8c<kMulti>(ncs, R, Ps, ng, 1, g, mG, [](int) { return 0; }, [&](int) { return ng; },
        [&](int c, int k, double v) { xstore(&C.b[(size_t)c * C.ld_b + coff + k], v); });
-  grid_barrier(C.bar, gridDim.x, C.status, gen);
+  grid_barrier(C.bar, gridDim.x, C.status, passed);
   // coarsest right-hand side r_c = sum of the coarse contributions, and the
   // sharers' sum of delta T_rr g on the interface, in one round of loads
   for (int t = tid; t < ncL * R; t += kCoopNT) {
