@@ -410,8 +410,11 @@ struct Level {
     int64_t* woff;
     // level-1 sweeps: the envelope's interior row ends per panel
     int32_t *srend, *srendoff;
+    // large local matrices: workgroup -> substructure, largest first
+    int32_t* order;
   } d{};
   bool sweep_env = false;
+  bool has_order = false;
   std::vector<int64_t> linvoff;
   bool big = false;   // interior elimination by the tiled kernel
   LevelDev dev;
@@ -904,7 +907,7 @@ class Builder {
     // interface tiles) the first interior column tile of the envelope of the
     // local matrix, i.e. of its factor (fill stays right of each row's first
     // nonzero); found from the elements at level 1, every tile at other levels
-    std::vector<int32_t> tproff, tprof;
+    std::vector<int32_t> tproff, tprof, big_order;
     std::vector<int64_t> woff;
     lv.big = use_big_chol(lv.nmax);
     if (lv.big) {
@@ -943,6 +946,20 @@ class Builder {
             }
           }
         });
+      // the substructures by decreasing envelope (tiles of the factor), the
+      // order their workgroups start in (BDDC_BIG_ORDER=0: index order)
+      const char* oenv = getenv("BDDC_BIG_ORDER");
+      if (!(oenv && std::string(oenv) == "0")) {
+        std::vector<int64_t> wgt(nsub, 0);
+        for (int s = 0; s < nsub; ++s) {
+          const int nbI = (T.n_int[s] + kT - 1) / kT;
+          const int nt = tproff[s + 1] - tproff[s];
+          for (int t = 0; t < nt; ++t) wgt[s] += std::max(0, std::min(t, nbI - 1) - tprof[tproff[s] + t] + 1);
+        }
+        big_order.resize(nsub);
+        for (int s = 0; s < nsub; ++s) big_order[s] = s;
+        std::stable_sort(big_order.begin(), big_order.end(), [&](int a, int b) { return wgt[a] > wgt[b]; });
+      }
     }
 
     // level-1 sweeps (local matrices small enough for LDS panels): per
@@ -1062,6 +1079,7 @@ class Builder {
       d.woff = A.take<int64_t>(woff.size());
       d.srend = A.take<int32_t>(srend.size());
       d.srendoff = A.take<int32_t>(srendoff.size());
+      d.order = A.take<int32_t>(big_order.size());
     };
     A.reset_sizing();
     layout(false);
@@ -1122,6 +1140,8 @@ class Builder {
       stg.add(d.srend, srend);
       stg.add(d.srendoff, srendoff);
     }
+    if (!big_order.empty()) stg.add(d.order, big_order);
+    lv.has_order = !big_order.empty();
     lv.sweep_env = !srend.empty();
     if (adaptive) {
       stg.add(d.schws_off, lv.schws_off);
@@ -1179,6 +1199,7 @@ class Builder {
         D.tprof = d.tprof;
         D.tproff = d.tproff;
         D.woff = d.woff;
+        D.order = lv.has_order ? d.order : nullptr;
         launch_partial_chol_big(st_, D, d.K, d.Wd, h_->status);
       }
       else if (use_mfma_chol(lv.nmax))
@@ -1422,6 +1443,7 @@ class Builder {
     D.tproff = lv.big ? d.tproff : nullptr;
     D.srend = lv.sweep_env ? d.srend : nullptr;
     D.srendoff = lv.sweep_env ? d.srendoff : nullptr;
+    D.order = lv.has_order ? d.order : nullptr;
     D.Wd = lv.big ? d.Wd : nullptr;
     D.woff = lv.big ? d.woff : nullptr;
     D.csh_ptr = d.csh_ptr;

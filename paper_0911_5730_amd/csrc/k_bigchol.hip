@@ -111,7 +111,7 @@ __global__ void __launch_bounds__(kBigNT) k_partial_chol_big(LevelDev L, double*
   double* W = Y + kBT * kBLd;      // L_KK, then its inverse
   __shared__ double piv[kBT];
   __shared__ double colk[kBT];
-  const int s = blockIdx.x;
+  const int s = L.order ? L.order[blockIdx.x] : blockIdx.x;
   const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
   const int nI = L.nint[s];
   double* A = K + L.koff[s];

@@ -96,7 +96,7 @@ __global__ void __launch_bounds__(kNT) k_tile_pre_cols(LevelDev L, const double*
   extern __shared__ double sh[];
   if (L.stop && *L.stop) return;
   const TileLds S(sh);
-  const int s = blockIdx.x;
+  const int s = L.order ? L.order[blockIdx.x] : blockIdx.x;
   const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
   const int nI = L.nint[s];
   const int ng = n - nI;
@@ -158,7 +158,7 @@ __global__ void __launch_bounds__(kNT) k_tile_recover_cols(LevelDev L, const dou
                                                            double* __restrict__ u, int64_t ldu, int R, int ngmax) {
   extern __shared__ double sh[];
   const TileLds S(sh);
-  const int s = blockIdx.x;
+  const int s = L.order ? L.order[blockIdx.x] : blockIdx.x;
   const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
   const int nI = L.nint[s];
   const int ng = n - nI;

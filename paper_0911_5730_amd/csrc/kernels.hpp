@@ -79,6 +79,10 @@ struct LevelDev {
   // column-major each), offsets woff
   const int32_t* tprof = nullptr;
   const int32_t* tproff = nullptr;
+  // large local matrices: the substructures in decreasing order of their
+  // elimination work (workgroup b takes substructure order[b], so the largest
+  // start first and the uneven sizes pack the CUs; null = in index order)
+  const int32_t* order = nullptr;
   // level-1 sweeps: per substructure the end of the interior rows of each
   // panel's envelope (64-wide panels, then 32-wide), offsets srendoff; null =
   // every interior row below the panel

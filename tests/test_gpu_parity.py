@@ -129,6 +129,28 @@ def test_deep_level_paths(path, case, monkeypatch):
         S.close()
 
 
+def test_large_substructures_size_order_bitwise(monkeypatch):
+    """The workgroups of the tiled elimination and tiled substitutions take
+    the substructures largest first; the results are bitwise those of index
+    order (uneven Voronoi regions, the tiled path forced)."""
+    import torch
+
+    import paper_0911_5730_amd as P
+    monkeypatch.setenv("BDDC_CHOL_PATH", "big")
+    monkeypatch.setenv("BDDC_SWEEP", "off")
+    prob = _case("voronoi_jitter3")
+    F = cuda_vec(np.random.default_rng(14).uniform(-1, 1, (3, prob.n_free)))
+    r = cuda_vec(np.random.default_rng(15).standard_normal(prob.n_free))
+    out = {}
+    for order in ("1", "0"):
+        monkeypatch.setenv("BDDC_BIG_ORDER", order)
+        with P.Solver(prob) as S:
+            U, its, _ = S.solve(F, rtol=1e-10)
+            out[order] = (U, its, S.apply(r))
+    assert out["1"][1] == out["0"][1]
+    assert torch.equal(out["1"][0], out["0"][0]) and torch.equal(out["1"][2], out["0"][2])
+
+
 @pytest.mark.parametrize("case", ["adaptive3_h16", "voronoi_jitter3", "adaptive2_h32"])
 def test_sweep_envelope_bitwise(case, monkeypatch):
     """The level-1 interior sweeps skip the interior rows outside the local
