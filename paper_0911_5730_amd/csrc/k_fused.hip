@@ -694,7 +694,7 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
   const int ng = n - L.nint[s];
   const int g0 = L.goff[s];
   const int tid = threadIdx.x;
-  const int wave = tid >> 6, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;   // (wave-uniform in scalar registers)
   const int n_r = L.nr[s];
   const int ncs = L.coff[s + 1] - L.coff[s];
   const int R = P.nrhs;

@@ -49,13 +49,16 @@ __device__ inline void row_task(int nrb, int& s, int& rb) {
 // same whatever the other columns hold
 // (the last batch loads at clamped column indices and adds zero terms past
 // j1, so a ragged end costs one batch, not a chain of single loads)
+// A is the block's first row (the same for the whole wave) and `row` the
+// lane's row in it, so every load takes a wave-uniform column address plus
+// a 32-bit lane offset (one register for the lane part of all the loads).
 template <int kNL, class T>
-__device__ inline void row_product(double (&acc)[kNL], const T* __restrict__ A, int ld, int j0, int j1,
+__device__ inline void row_product(double (&acc)[kNL], const T* __restrict__ A, int row, int ld, int j0, int j1,
                                    const double* v) {
   for (int j = j0; j < j1; j += kBatch) {
     T t[kBatch];
 #pragma unroll
-    for (int q = 0; q < kBatch; ++q) t[q] = A[(size_t)min(j + q, j1 - 1) * ld];
+    for (int q = 0; q < kBatch; ++q) t[q] = (A + (size_t)min(j + q, j1 - 1) * ld)[row];
 #pragma unroll
     for (int q = 0; q < kBatch; ++q) {
       // past j1: a zero term on the last column (a select, so that the
@@ -103,7 +106,8 @@ __global__ void __launch_bounds__(kRT) k_pcg_matvec_rows(LevelDev L, PcgDev P, i
   const int ng = L.loc_ptr[s + 1] - L.loc_ptr[s] - L.nint[s];
   const int g0 = L.goff[s];
   const int r0 = rb * kRows, rows = max(0, min(kRows, ng - r0));
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // (uniform: the columns of a wave in scalar registers)
   int nl = live_columns(P, lc);
   if (nl == 0) return;
   if constexpr (!kMulti) nl = 1;
@@ -117,7 +121,8 @@ __global__ void __launch_bounds__(kRT) k_pcg_matvec_rows(LevelDev L, PcgDev P, i
     return;
   }
   const int ld = pad_ld(ng, 8);   // (columns on 128-byte boundaries: a 64-row block is four whole lines)
-  const double* Sg = P.Sp + P.spoff[s] + r0 + min(lane, rows - 1);
+  const double* Sg = P.Sp + P.spoff[s] + r0;
+  const int lrow = min(lane, rows - 1);
   const int cq = (ng + kNW - 1) / kNW;
   const int j0 = min(ng, wave * cq), j1 = min(ng, j0 + cq);
   for (int k = 0; k < nl; ++k) {
@@ -158,7 +163,7 @@ __global__ void __launch_bounds__(kRT) k_pcg_matvec_rows(LevelDev L, PcgDev P, i
   double acc[kNL];
 #pragma unroll
   for (int k = 0; k < kNL; ++k) acc[k] = 0.0;
-  row_product<kNL>(acc, Sg, ld, j0, j1, pl);
+  row_product<kNL>(acc, Sg, lrow, ld, j0, j1, pl);
 #pragma unroll
   for (int k = 0; k < kNL; ++k)
     if (k < nl) part[(wave * kNL + k) * kRows + lane] = acc[k];
@@ -211,7 +216,12 @@ __global__ void __launch_bounds__(kRT) k_pcg_update_restrict_rows(LevelDev L, Pc
   const int ncs = L.coff[s + 1] - L.coff[s];
   const int r0 = rb * kRows;
   const int rows_r = max(0, min(kRows, n_r - r0));
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tid = threadIdx.x, lane = tid & 63;
+  // the FP32 form takes the wave's columns in scalar registers (104 against
+  // 133 registers, 262 against 336 us per launch at config 4); the FP64 form
+  // keeps them per lane (106 against 140 registers with scalar columns, 297
+  // against 334 us)
+  const int wave = kPrec == 1 ? __builtin_amdgcn_readfirstlane(tid >> 6) : (tid >> 6);
   int nl = live_columns(P, lc);
   if (nl == 0) return;
   if constexpr (!kMulti) nl = 1;
@@ -219,8 +229,8 @@ __global__ void __launch_bounds__(kRT) k_pcg_update_restrict_rows(LevelDev L, Pc
     if constexpr (kMulti) return lc[k];
     else return 0;
   };
-  const T* Tg = (kPrec == 0 ? reinterpret_cast<const T*>(P.Tp) : reinterpret_cast<const T*>(P.Tp32)) + P.tpoff[s] +
-                r0 + min(lane, max(rows_r, 1) - 1);
+  const T* Tg = (kPrec == 0 ? reinterpret_cast<const T*>(P.Tp) : reinterpret_cast<const T*>(P.Tp32)) + P.tpoff[s] + r0;
+  const int lrow = min(lane, max(rows_r, 1) - 1);
   const int cq = (n_r + kNW - 1) / kNW;
   const int j0 = min(n_r, wave * cq), j1 = min(n_r, j0 + cq);
   constexpr int nls = kNL;
@@ -372,7 +382,7 @@ __global__ void __launch_bounds__(kRT) k_pcg_update_restrict_rows(LevelDev L, Pc
     double acc[kNL];
 #pragma unroll
     for (int k = 0; k < kNL; ++k) acc[k] = 0.0;
-    row_product<kNL>(acc, Tg, pad_ld(n_r, sizeof(T)), j0, j1, g);
+    row_product<kNL>(acc, Tg, lrow, pad_ld(n_r, sizeof(T)), j0, j1, g);
 #pragma unroll
     for (int k = 0; k < kNL; ++k)
       if (k < nl) part[(wave * kNL + k) * kRows + lane] = acc[k];
