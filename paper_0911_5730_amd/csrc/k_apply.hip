@@ -62,12 +62,15 @@ __global__ void __launch_bounds__(kNT) k_apply_pre(LevelDev L, const double* __r
 // input is an interface vector with zero interior residual.  Grid
 // (substructures, columns): column c reads r + c ldr and L.t + c ldg, writes
 // L.a + c ldg and L.b + c ldc.
-template <bool kFS>
+// kRK > 0: each thread's first kRK entries of T_rr are held in registers,
+// loaded before g is gathered (for grids of few workgroups, where the
+// launch is one dependent chain; with many workgroups the 48 registers
+// would halve the resident waves).  The sums are the same either way.
+template <bool kFS, int kRK>
 __global__ void __launch_bounds__(kNT) k_apply_restrict(LevelDev L, const double* __restrict__ r,
                                                         const int32_t* __restrict__ gam_map, int ldr, int ldg,
                                                         int ldc) {
   extern __shared__ double sh[];
-  if (L.stop && *L.stop) return;
   const int s = blockIdx.x;
   {
     const size_t col = blockIdx.y;
@@ -85,6 +88,29 @@ __global__ void __launch_bounds__(kNT) k_apply_restrict(LevelDev L, const double
   double* g = sh;
   double* part = sh + ng;
   const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  // The operators' loads go out first (in-bounds clamped addresses; entries
+  // past the block unused) and land while g is gathered: thread (ti, tc) of
+  // the row-partial products T_rr g_r (rows n_r <= the workgroup: one item
+  // per thread) its first kRK entries of row ti (columns tc, tc + nch, ...),
+  // and wave w the first two 64-entry chunks of its first column of Psi.
+  const double* T = L.T + L.toff[s];
+  const int nch = n_r > 0 ? max(1, kNT / n_r) : 1;
+  const bool one = n_r > 0 && n_r <= kNT;
+  const int ti = one ? tid % n_r : 0, tc = one ? tid / n_r : nch;
+  double tv[kRK > 0 ? kRK : 1];
+  if (kRK > 0 && one) {
+#pragma unroll
+    for (int k = 0; k < kRK; ++k) tv[k] = T[ti + (size_t)min(tc + k * nch, n_r - 1) * n_r];
+  }
+  const double* P = L.Psi + L.psioff[s];
+  double pv[2] = {0.0, 0.0};
+  if (ng > 0 && ncs > 0) {
+    const int k = min(wave, ncs - 1);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) pv[q] = P[min(lane + 64 * q, ng - 1) + (size_t)k * ng];
+  }
+  if (L.stop && *L.stop) return;
   for (int a = tid; a < ng; a += kNT) {
     const int f = g0 + a;
     double v = r[gam_map[f]];
@@ -95,30 +121,67 @@ __global__ void __launch_bounds__(kNT) k_apply_restrict(LevelDev L, const double
     g[a] = L.delta[f] * v;
   }
   __syncthreads();
-  const double* T = L.T + L.toff[s];
-  if (n_r > 0) {
-    const int nch = max(1, kNT / n_r);
+  if (kRK == 0 && one) {
     for (ColWalk w_(tid, kNT, n_r); w_.j < nch; w_.next()) {
       const int i = w_.i, c = w_.j;
       [[maybe_unused]] const int idx = i + c * n_r;
       part[idx] = dot_strided(T + i, n_r, g, c, n_r, nch);
     }
+  } else if (one) {
+    if (tc < nch) {
+      // the sum of dot_strided over the columns tc, tc + nch, ...: eight
+      // interleaved partial sums over the full batches of eight, then the
+      // rest in order
+      const int cnt = (n_r - tc + nch - 1) / nch;
+      const int nfull = cnt & ~7;
+      double a8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      double rest = 0.0;
+#pragma unroll
+      for (int e = 0; e < kRK; ++e) {
+        if (e < cnt) {
+          const double x = g[tc + e * nch];
+          if (e < nfull) a8[e & 7] += tv[e] * x;
+          else rest += tv[e] * x;
+        }
+      }
+      for (int e0 = kRK; e0 < cnt; e0 += 8) {   // the rest: eight loads in flight
+        double t8[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) t8[u] = T[ti + (size_t)min(tc + (e0 + u) * nch, n_r - 1) * n_r];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int e = e0 + u;
+          if (e < cnt) {
+            const double x = g[tc + e * nch];
+            if (e < nfull) a8[e & 7] += t8[u] * x;
+            else rest += t8[u] * x;
+          }
+        }
+      }
+      part[ti + tc * n_r] = (((a8[0] + a8[1]) + (a8[2] + a8[3])) + ((a8[4] + a8[5]) + (a8[6] + a8[7]))) + rest;
+    }
+  } else if (n_r > 0) {
+    for (int i = tid; i < n_r; i += kNT) part[i] = dot_strided(T + i, n_r, g, 0, n_r, 1);
   }
   // b = Psi^T g, one wave per coarse dof
-  const double* P = L.Psi + L.psioff[s];
-  const int wave = tid >> 6, lane = tid & 63;
-  for (int k = wave; k < ncs; k += kNT / 64) {
+  for (int k = wave, m = 0; k < ncs; k += kNT / 64, ++m) {
     double acc = 0.0;
-    for (int a = lane; a < ng; a += 64) acc += P[a + (size_t)k * ng] * g[a];
+    int a = lane;
+    if (m == 0) {
+#pragma unroll
+      for (int q = 0; q < 2; ++q, a += 64)
+        if (a < ng) acc += pv[q] * g[a];
+    }
+    for (; a < ng; a += 64) acc += P[a + (size_t)k * ng] * g[a];
     acc = wave_sum(acc);
     if (lane == 0) L.b[L.coff[s] + k] = acc;
   }
   __syncthreads();
   if (n_r > 0) {
-    const int nch = max(1, kNT / n_r);
+    const int nc = one ? nch : 1;
     for (int i = tid; i < n_r; i += kNT) {
       double acc = 0.0;
-      for (int c = 0; c < nch; ++c) acc += part[i + c * n_r];
+      for (int c = 0; c < nc; ++c) acc += part[i + c * n_r];
       L.a[g0 + i] = acc;
     }
   }
@@ -594,16 +657,16 @@ void launch_apply_restrict(hipStream_t st, const LevelDev& L, int ngmax, const d
                            const int32_t* gam_map, int use_t) {
   const size_t lds = sizeof(double) * ((size_t)ngmax + kNT + ngmax);
   if (use_t)
-    launch_kernel(k_apply_restrict<true>, dim3(L.nsub), dim3(kNT), lds, st, L, r, gam_map, 0, 0, 0);
+    launch_kernel(k_apply_restrict<true, 0>, dim3(L.nsub), dim3(kNT), lds, st, L, r, gam_map, 0, 0, 0);
   else
-    launch_kernel(k_apply_restrict<false>, dim3(L.nsub), dim3(kNT), lds, st, L, r, gam_map, 0, 0, 0);
+    launch_kernel(k_apply_restrict<false, 0>, dim3(L.nsub), dim3(kNT), lds, st, L, r, gam_map, 0, 0, 0);
 }
 void launch_wide_restrict(hipStream_t st, const WideDev& W, const int32_t* gam_map) {
   LevelDev L = W.L;
   L.stop = W.stop;
   const size_t lds = sizeof(double) * ((size_t)W.ngmax + kNT + W.ngmax);
-  launch_kernel(k_apply_restrict<true>, dim3(L.nsub, W.nrhs), dim3(kNT), lds, st, L, W.r2, gam_map, W.ld_r2, W.ld_g,
-                W.ld_c);
+  launch_kernel(k_apply_restrict<true, 24>, dim3(L.nsub, W.nrhs), dim3(kNT), lds, st, L, W.r2, gam_map, W.ld_r2,
+                W.ld_g, W.ld_c);
 }
 void launch_coarse_gather(hipStream_t st, int nc, const int32_t* csh_ptr, const int32_t* csh_flat,
                           const double* b, double* rc, const int32_t* stop) {

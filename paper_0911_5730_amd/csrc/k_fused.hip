@@ -509,8 +509,12 @@ __device__ inline double sym_row_part(const double* A, int m, int i, int c, int 
 
 // kMulti: several columns; otherwise the one column 0 (compile-time column
 // offsets, uniform pointers), with the same arithmetic per column.
+// The one-column instance is held to 72 registers (seven waves per SIMD, no
+// spills; 84 and five waves otherwise): with one workgroup per substructure
+// the launch runs in rounds of resident workgroups.
 template <bool kMulti>
-__global__ void __launch_bounds__(kNT) k_pcg_matvec(LevelDev L, PcgDev P, int u) {
+__global__ void __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(kMulti ? 1 : 7)))
+k_pcg_matvec(LevelDev L, PcgDev P, int u) {
   extern __shared__ double sh[];
   __shared__ double red[kMaxRhs * 16];
   __shared__ double bet[kMaxRhs];

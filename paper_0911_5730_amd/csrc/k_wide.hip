@@ -29,22 +29,40 @@ __device__ inline double wide_r2(const WideDev& W, const double* b1, int k) {
 // read once for all of them; a column's sums are those of a one-column launch)
 __global__ void __launch_bounds__(kNT) k_wide_pre(WideDev W) {
   extern __shared__ double sh[];
-  if (W.stop && *W.stop) return;
   const LevelDev& L = W.L;
   const int s = blockIdx.y, chunk = blockIdx.x;
-  const int cb = blockIdx.z * W.cols1;            // first column of the group
-  const int R = min(W.cols1, W.nrhs - cb);
-  const double* b1 = W.b1 + (size_t)cb * W.ld_b1;
-  double* r2 = W.r2 + (size_t)cb * W.ld_r2;
-  double* Ly = L.y + (size_t)cb * W.ld_i;
-  double* Lt = L.t + (size_t)cb * W.ld_g;
   const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
   const int nI = L.nint[s];
   const int ng = n - nI;
   const int r0 = chunk * W.rows1;
   if (r0 >= n) return;
   const int r1 = min(n, r0 + W.rows1);
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const double* Ki = W.Kinv + W.kioff[s];
+  const double* Mt = W.Mt + W.moff[s];
+  // one wave per row; rows < nI: column rho of the symmetric K_II^-1, else
+  // column rho - nI of M^T (row of M): both contiguous.  Lane l takes the
+  // entries l + 64 u (u < 4) of every 256; the first 256 of the wave's first
+  // kAhead rows are loaded before r_2 is gathered (in-bounds clamped
+  // addresses, entries past nI unused), so that gather hides their latency.
+  auto column = [&](int rho) { return rho < nI ? Ki + (size_t)rho * nI : Mt + (size_t)(rho - nI) * nI; };
+  auto load4 = [&](double (&cv)[4], const double* col, int jb) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) cv[u] = col[min(jb + lane + 64 * u, nI - 1)];
+  };
+  constexpr int kAhead = 2;
+  double ahead[kAhead][4];
+  if (nI > 0) {
+#pragma unroll
+    for (int q = 0; q < kAhead; ++q) load4(ahead[q], column(min(r0 + wave + 4 * q, r1 - 1)), 0);
+  }
+  if (W.stop && *W.stop) return;
+  const int cb = blockIdx.z * W.cols1;            // first column of the group
+  const int R = min(W.cols1, W.nrhs - cb);
+  const double* b1 = W.b1 + (size_t)cb * W.ld_b1;
+  double* r2 = W.r2 + (size_t)cb * W.ld_r2;
+  double* Ly = L.y + (size_t)cb * W.ld_i;
+  double* Lt = L.t + (size_t)cb * W.ld_g;
   double* rI = sh;   // column c at rI + c nI
   for (int idx = tid; idx < R * nI; idx += kNT) {
     const int c = idx / nI, i = idx - c * nI;
@@ -60,34 +78,39 @@ __global__ void __launch_bounds__(kNT) k_wide_pre(WideDev W) {
       r2[(size_t)c * W.ld_r2 + k] = wide_r2(W, b1 + (size_t)c * W.ld_b1, k);   // every sharer stores the same value
     }
   __syncthreads();
-  const double* Ki = W.Kinv + W.kioff[s];
-  const double* Mt = W.Mt + W.moff[s];
-  // one wave per row; rows < nI: column rho of the symmetric K_II^-1, else
-  // column rho - nI of M^T (row of M): both contiguous
-  for (int rho = r0 + wave; rho < r1; rho += kNT / 64) {
-    const double* col = rho < nI ? Ki + (size_t)rho * nI : Mt + (size_t)(rho - nI) * nI;
+  for (int rho = r0 + wave, q = 0; rho < r1; rho += kNT / 64, ++q) {
+    const double* col = column(rho);
     double acc[kMaxRhs][4];
 #pragma unroll
     for (int c = 0; c < kMaxRhs; ++c) acc[c][0] = acc[c][1] = acc[c][2] = acc[c][3] = 0.0;
-    int j = lane;
-    for (; j + 192 < nI; j += 256) {
-      const double c0 = col[j], c1 = col[j + 64], c2 = col[j + 128], c3 = col[j + 192];
+    auto terms = [&](const double (&cv)[4], int jb) {
 #pragma unroll
-      for (int c = 0; c < kMaxRhs; ++c) {
-        if (c >= R) break;
-        const double* x = rI + c * nI;
-        acc[c][0] += c0 * x[j];
-        acc[c][1] += c1 * x[j + 64];
-        acc[c][2] += c2 * x[j + 128];
-        acc[c][3] += c3 * x[j + 192];
+      for (int u = 0; u < 4; ++u) {
+        const int j = jb + lane + 64 * u;
+        if (j < nI) {
+#pragma unroll
+          for (int c = 0; c < kMaxRhs; ++c) {
+            if (c >= R) break;
+            acc[c][u] += cv[u] * rI[c * nI + j];
+          }
+        }
       }
-    }
-    for (; j < nI; j += 64) {
-      const double c0 = col[j];
+    };
+    if (nI > 0) {
+      double cv[4];
+      if (q < kAhead) {
 #pragma unroll
-      for (int c = 0; c < kMaxRhs; ++c) {
-        if (c >= R) break;
-        acc[c][0] += c0 * rI[c * nI + j];
+        for (int t = 0; t < kAhead; ++t)
+          if (q == t)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) cv[u] = ahead[t][u];
+      } else {
+        load4(cv, col, 0);
+      }
+      terms(cv, 0);
+      for (int jb = 256; jb < nI; jb += 256) {
+        load4(cv, col, jb);
+        terms(cv, jb);
       }
     }
 #pragma unroll
@@ -110,12 +133,38 @@ __global__ void __launch_bounds__(kNT) k_wide_pre(WideDev W) {
 // grid (blocks, columns)
 template <bool kInv>
 __global__ void __launch_bounds__(kNT) k_wide_coarse(WideDev W) {
+  constexpr int kCK = 8;   // coarse dofs per substructure held in registers
   extern __shared__ double sh[];
-  if (W.stop && *W.stop) return;
   const LevelDev& L = W.L;
   const int col = blockIdx.y;
   const double* La = L.a + (size_t)col * W.ld_g;
   double* Lv = L.v + (size_t)col * W.ld_g;
+  // the operands of the thread's first interface entry (its row of Psi, the
+  // coarse ids, a and delta), loaded before the coarsest problem is solved
+  const int f0 = blockIdx.x * kNT + threadIdx.x;
+  int a0 = 0, ng0 = 0, c00 = 0, ncs0 = 0;
+  const double* P0 = nullptr;
+  double pv[kCK], la0 = 0.0, dl0 = 0.0;
+  int cv[kCK];
+  if (f0 < W.nflat) {
+    const int s = W.sub_of_flat[f0];
+    a0 = f0 - L.goff[s];
+    ng0 = (L.loc_ptr[s + 1] - L.loc_ptr[s]) - L.nint[s];
+    c00 = L.coff[s];
+    ncs0 = L.coff[s + 1] - c00;
+    P0 = L.Psi + L.psioff[s];
+    if (ncs0 > 0) {
+#pragma unroll
+      for (int k = 0; k < kCK; ++k) {
+        const int kk = min(k, ncs0 - 1);
+        pv[k] = P0[a0 + (size_t)kk * ng0];
+        cv[k] = L.cid[c00 + kk];
+      }
+    }
+    la0 = La[f0];
+    dl0 = L.delta[f0];
+  }
+  if (W.stop && *W.stop) return;
   const double* u3;
   if constexpr (kInv) {
     u3 = W.u3 + (size_t)col * W.ld_3;
@@ -132,7 +181,25 @@ __global__ void __launch_bounds__(kNT) k_wide_coarse(WideDev W) {
     wg_trsv_lower_trans(W.AL, W.ncL, W.ncL, y);
     u3 = y;
   }
-  for (int f = blockIdx.x * kNT + threadIdx.x; f < W.nflat; f += gridDim.x * kNT) {
+  if (f0 < W.nflat) {
+    double w = la0;
+#pragma unroll
+    for (int k = 0; k < kCK; ++k)
+      if (k < ncs0) w += pv[k] * u3[cv[k]];
+    for (int k0 = kCK; k0 < ncs0; k0 += kCK) {   // the rest: kCK loads in flight
+#pragma unroll
+      for (int k = 0; k < kCK; ++k) {
+        const int kk = min(k0 + k, ncs0 - 1);
+        pv[k] = P0[a0 + (size_t)kk * ng0];
+        cv[k] = L.cid[c00 + kk];
+      }
+#pragma unroll
+      for (int k = 0; k < kCK; ++k)
+        if (k0 + k < ncs0) w += pv[k] * u3[cv[k]];
+    }
+    Lv[f0] = dl0 * w;
+  }
+  for (int f = f0 + gridDim.x * kNT; f < W.nflat; f += gridDim.x * kNT) {
     const int s = W.sub_of_flat[f];
     const int a = f - L.goff[s];
     const int ng = (L.loc_ptr[s + 1] - L.loc_ptr[s]) - L.nint[s];
@@ -145,23 +212,39 @@ __global__ void __launch_bounds__(kNT) k_wide_coarse(WideDev W) {
 }
 
 // grid (chunks of 64 interior rows, substructures, columns): u_B, then
-// u_I = z_I - M^T u_B with four threads per row (fixed-order reduction)
+// u_I = z_I - M^T u_B with four threads per row (fixed-order reduction).
+// Thread (row, a0) holds its first kPostK entries of M^T (columns a0,
+// a0 + 4, ...) and z_I, loaded before u_B is gathered.
 __global__ void __launch_bounds__(kNT) k_wide_post(WideDev W) {
+  constexpr int kPostK = 24;
   extern __shared__ double sh[];
-  if (W.stop && *W.stop) return;
   const LevelDev& L = W.L;
   const int s = blockIdx.y, chunk = blockIdx.x, col = blockIdx.z;
-  const double* Lv = L.v + (size_t)col * W.ld_g;
-  const double* Ly = L.y + (size_t)col * W.ld_i;
-  double* u2 = W.u2 + (size_t)col * W.ld_u2;
   const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
   const int nI = L.nint[s];
   const int ng = n - nI;
   const int g0 = L.goff[s];
   const int tid = threadIdx.x;
+  if (chunk * 64 >= max(nI, 1)) return;
+  const int il = tid & 63, ag = tid >> 6;
+  const int i = chunk * 64 + il;
+  const double* Mt = W.Mt + W.moff[s];
+  const double* Ly = L.y + (size_t)col * W.ld_i;
+  double mv[kPostK];
+  double zi = 0.0;
+  if (nI > 0) {
+    const int ic = min(i, nI - 1);
+    if (ng > 0) {
+#pragma unroll
+      for (int k = 0; k < kPostK; ++k) mv[k] = Mt[ic + (size_t)min(ag + 4 * k, ng - 1) * nI];
+    }
+    zi = Ly[L.ioff[s] + ic];
+  }
+  if (W.stop && *W.stop) return;
+  const double* Lv = L.v + (size_t)col * W.ld_g;
+  double* u2 = W.u2 + (size_t)col * W.ld_u2;
   double* uB = sh;
   double* part = sh + ng;
-  if (chunk * 64 >= max(nI, 1)) return;
   for (int a = tid; a < ng; a += kNT) {
     const int f = g0 + a;
     const int gi = L.gam_iid[f];
@@ -171,17 +254,25 @@ __global__ void __launch_bounds__(kNT) k_wide_post(WideDev W) {
     if (chunk == 0 && L.sh_flat[L.sh_ptr[gi]] == f) u2[L.gam_gid[f]] = acc;
   }
   __syncthreads();
-  const int il = tid & 63, ag = tid >> 6;
-  const int i = chunk * 64 + il;
-  const double* Mt = W.Mt + W.moff[s];
   double acc = 0.0;
-  if (i < nI)
-    for (int a = ag; a < ng; a += 4) acc += Mt[i + (size_t)a * nI] * uB[a];
+  if (i < nI) {
+#pragma unroll
+    for (int k = 0; k < kPostK; ++k)
+      if (ag + 4 * k < ng) acc += mv[k] * uB[ag + 4 * k];
+    for (int a0 = ag + 4 * kPostK; a0 < ng; a0 += 32) {   // the rest: eight loads in flight
+      double m8[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) m8[u] = Mt[i + (size_t)min(a0 + 4 * u, ng - 1) * nI];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (a0 + 4 * u < ng) acc += m8[u] * uB[a0 + 4 * u];
+    }
+  }
   part[tid] = acc;
   __syncthreads();
   if (ag == 0 && i < nI) {
     const double m = (part[il] + part[il + 64]) + (part[il + 128] + part[il + 192]);
-    u2[L.int_gid[L.ioff[s] + i]] = Ly[L.ioff[s] + i] - m;
+    u2[L.int_gid[L.ioff[s] + i]] = zi - m;
   }
 }
 
