@@ -10,8 +10,17 @@
 // triangular solve:
 //   forward  y_I = W_I (f_I - sum_{J in envelope, J < I} L_IJ y_J)
 //   backward u_I = W_I^T (y_I - L_GI^T u_G - sum_{J > I} L_JI^T u_J)
-// One workgroup per substructure; every operand tile is staged in LDS with
-// coalesced loads and applied to all columns from there.
+// One workgroup of four waves per substructure.  Every tile product runs on
+// the matrix cores (v_mfma_f64_16x16x4f64): wave w owns rows 16 w .. 16 w + 15
+// of the 64-row output block and all (up to eight) columns, and loads its
+// operands straight into registers in the instruction's layout -- no LDS
+// staging of the operator tiles and no barrier inside a row tile's sum.  Lane
+// l = 16 q + i' takes output row i' and, at step s of the 16 steps of a
+// 64-wide product, the reduction index k = 4 s + q: for a tile read as stored
+// (L_IJ, W) sixteen consecutive rows of four adjacent columns per load, for a
+// tile read transposed (L_GI^T, L_JI^T, W^T) four consecutive rows of sixteen
+// columns.  The accumulator lands with lane l holding output row i', columns
+// q and 4 + q.
 #include "dense.hpp"
 #include "kernels.hpp"
 
@@ -19,70 +28,28 @@ namespace bddc {
 
 namespace {
 
-constexpr int kTT = 64;    // tile size
-constexpr int kTL = 65;    // LDS leading dimension of a staged tile
+constexpr int kTT = 64;   // tile size
+constexpr int kXS = 9;    // LDS row stride of an operand block: entry (k, c) at k kXS + c (c < 8)
 
-// rows [r0, r0 + rows) x columns [c0, c0 + w) of A (column-major, ld lda) into
-// Tl, zero-padded to 64 x 64; sixteen loads per thread, all issued first
-__device__ inline void stage_tile(double* Tl, const double* __restrict__ A, int64_t lda, int r0, int rows, int c0,
-                                  int w) {
-  double v[kTT * kTT / kNT];
+typedef double tile_d4 __attribute__((ext_vector_type(4)));
+
+static_assert(kMaxRhs == 8, "the tile products hold eight columns");
+
+// acc(c, i') += sum over the 64 reduction indices of x(k, c) t(i', k), with
+// lane l = 16 q + i' holding t[s] = op(T)(i', 4 s + q) and x[s] = X(4 s + q, i')
+// (zero for columns i' >= 8)
+__device__ inline void mma_tile(tile_d4& acc, const double (&x)[16], const double (&t)[16]) {
 #pragma unroll
-  for (int u = 0; u < kTT * kTT / kNT; ++u) {
-    const int idx = threadIdx.x + u * kNT;
-    const int i = idx & (kTT - 1), j = idx >> 6;
-    v[u] = (i < rows && j < w) ? A[(r0 + i) + (size_t)(c0 + j) * lda] : 0.0;
-  }
-#pragma unroll
-  for (int u = 0; u < kTT * kTT / kNT; ++u) {
-    const int idx = threadIdx.x + u * kNT;
-    Tl[(idx & (kTT - 1)) + (idx >> 6) * kTL] = v[u];
-  }
+  for (int s = 0; s < 16; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x[s], t[s], acc, 0, 0, 0);
 }
 
-// out(i, c) = sum_k op(T)(i, k) x(k, c) for the 64 rows of a staged tile and
-// R columns of x (LDS, ld 64): thread (i, q) sums k in [16 q, 16 q + 16), the
-// four quarter sums are added in a fixed order.  acc(i, c) (LDS, ld 64) is
-// then updated: acc = sign * out + (add ? acc : 0).  Ends with a barrier.
-template <bool kTrans>
-__device__ inline void tile_product(const double* Tl, const double* x, int R, double* part, double* acc, double sign,
-                                    bool add) {
-  const int i = threadIdx.x & (kTT - 1), q = threadIdx.x >> 6;
-  double s[kMaxRhs];
-#pragma unroll
-  for (int c = 0; c < kMaxRhs; ++c) s[c] = 0.0;
-#pragma unroll 4
-  for (int k = 16 * q; k < 16 * q + 16; ++k) {
-    const double t = kTrans ? Tl[k + i * kTL] : Tl[i + k * kTL];
-#pragma unroll
-    for (int c = 0; c < kMaxRhs; ++c)
-      if (c < R) s[c] += t * x[k + c * kTT];
-  }
-#pragma unroll
-  for (int c = 0; c < kMaxRhs; ++c)
-    if (c < R) part[(q * kMaxRhs + c) * kTT + i] = s[c];
-  __syncthreads();
-  for (int idx = threadIdx.x; idx < kTT * R; idx += kNT) {
-    const int ii = idx & (kTT - 1), c = idx >> 6;
-    const double v = (part[c * kTT + ii] + part[(kMaxRhs + c) * kTT + ii]) +
-                     (part[(2 * kMaxRhs + c) * kTT + ii] + part[(3 * kMaxRhs + c) * kTT + ii]);
-    acc[ii + c * kTT] = (add ? acc[ii + c * kTT] : 0.0) + sign * v;
-  }
-  __syncthreads();
-}
-
-struct TileLds {
-  double* Tl;     // 64 x 65 operator tile
-  double* xb;     // 64 x 8 input tile
-  double* bb;     // 64 x 8 accumulator
-  double* part;   // 4 x 8 x 64 quarter sums
-  double* xg;     // interface values, ngmax x 8 (recovery)
-  __device__ TileLds(double* sh) {
-    Tl = sh;
-    xb = Tl + kTT * kTL;
-    bb = xb + kTT * kMaxRhs;
-    part = bb + kTT * kMaxRhs;
-    xg = part + 4 * kMaxRhs * kTT;
+struct TileLane {
+  int li, lq, ib;
+  __device__ TileLane() {
+    const int lane = threadIdx.x & 63;
+    li = lane & 15;
+    lq = lane >> 4;
+    ib = 16 * __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   }
 };
 
@@ -90,12 +57,14 @@ struct TileLds {
 
 // y = L_II^-1 r_I (columns at ldy, interior flat) and t = L_GI y (at ldt,
 // interface flat) for R columns of r (at ldr, level dofs)
-__global__ void __launch_bounds__(kNT) k_tile_pre_cols(LevelDev L, const double* __restrict__ r, int64_t ldr,
-                                                       double* __restrict__ yout, int ldy, double* __restrict__ tout,
-                                                       int ldt, int R) {
+// (held to 128 registers: four workgroups per compute unit, every
+// substructure's workgroup resident at once for 1024 substructures)
+__global__ void __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(4)))
+k_tile_pre_cols(LevelDev L, const double* __restrict__ r, int64_t ldr, double* __restrict__ yout, int ldy,
+                double* __restrict__ tout, int ldt, int R) {
   extern __shared__ double sh[];
   if (L.stop && *L.stop) return;
-  const TileLds S(sh);
+  double* xs = sh;   // the right-hand side of the diagonal product, 64 x kXS
   const int s = L.order ? L.order[blockIdx.x] : blockIdx.x;
   const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
   const int nI = L.nint[s];
@@ -105,59 +74,89 @@ __global__ void __launch_bounds__(kNT) k_tile_pre_cols(LevelDev L, const double*
   const double* Ws = L.Wd + L.woff[s];
   const int i0 = L.ioff[s], g0 = L.goff[s];
   const int nbI = (nI + kTT - 1) / kTT, nbG = (ng + kTT - 1) / kTT;
-  const int tid = threadIdx.x;
+  const TileLane T;
+  double* yI = yout + i0;   // column c at yI + c ldy
   for (int I = 0; I < nbI; ++I) {
     const int r0 = I * kTT, rows = min(kTT, nI - r0);
-    for (int idx = tid; idx < kTT * R; idx += kNT) {
-      const int i = idx & (kTT - 1), c = idx >> 6;
-      S.bb[idx] = i < rows ? r[(size_t)c * ldr + L.int_gid[i0 + r0 + i]] : 0.0;
-    }
-    for (int J = prof[I]; J < I; ++J) {
-      stage_tile(S.Tl, A, n, r0, rows, J * kTT, kTT);
-      for (int idx = tid; idx < kTT * R; idx += kNT) {
-        const int k = idx & (kTT - 1), c = idx >> 6;
-        S.xb[idx] = yout[(size_t)c * ldy + i0 + J * kTT + k];
+    const int row = r0 + T.ib + T.li;
+    const bool row_ok = T.ib + T.li < rows;
+    // this lane's entries of f_I (row, columns q and 4 + q), loaded first
+    double f[2];
+    {
+      const int gid = row_ok ? L.int_gid[i0 + row] : 0;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int c = 4 * h + T.lq;
+        f[h] = (row_ok && c < R) ? r[(size_t)c * ldr + gid] : 0.0;
       }
-      __syncthreads();
-      tile_product<false>(S.Tl, S.xb, R, S.part, S.bb, -1.0, true);
     }
-    stage_tile(S.Tl, Ws + (size_t)I * kTT * kTT, kTT, 0, kTT, 0, kTT);
-    __syncthreads();
-    tile_product<false>(S.Tl, S.bb, R, S.part, S.xb, 1.0, false);
-    for (int idx = tid; idx < kTT * R; idx += kNT) {
-      const int i = idx & (kTT - 1), c = idx >> 6;
-      if (i < rows) yout[(size_t)c * ldy + i0 + r0 + i] = S.xb[idx];
+    tile_d4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int J = prof[I]; J < I; ++J) {
+      double t[16], x[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int k = J * kTT + 4 * q + T.lq;
+        t[q] = row_ok ? A[row + (size_t)k * n] : 0.0;
+        x[q] = T.li < R ? yI[(size_t)T.li * ldy + k] : 0.0;
+      }
+      mma_tile(acc, x, t);
     }
+    // b = f_I - sum L_IJ y_J (rows past the tile and columns past R are zero)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) xs[(T.ib + T.li) * kXS + 4 * h + T.lq] = f[h] - acc[h];
     __syncthreads();
+    tile_d4 y4 = {0.0, 0.0, 0.0, 0.0};
+    {
+      const double* WI = Ws + (size_t)I * kTT * kTT;
+      double t[16], x[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int k = 4 * q + T.lq;
+        t[q] = WI[(T.ib + T.li) + k * kTT];
+        x[q] = T.li < kMaxRhs ? xs[k * kXS + T.li] : 0.0;
+      }
+      mma_tile(y4, x, t);
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int c = 4 * h + T.lq;
+      if (row_ok && c < R) yI[(size_t)c * ldy + row] = y4[h];
+    }
+    __syncthreads();   // xs is rewritten, and y_I is read by the later row tiles
   }
   for (int G = 0; G < nbG; ++G) {
     const int r0 = nI + G * kTT, rows = min(kTT, n - r0);
-    for (int idx = tid; idx < kTT * R; idx += kNT) S.bb[idx] = 0.0;
+    const int row = r0 + T.ib + T.li;
+    const bool row_ok = T.ib + T.li < rows;
+    tile_d4 acc = {0.0, 0.0, 0.0, 0.0};
     for (int J = prof[nbI + G]; J < nbI; ++J) {
-      const int w = min(kTT, nI - J * kTT);
-      stage_tile(S.Tl, A, n, r0, rows, J * kTT, w);
-      for (int idx = tid; idx < kTT * R; idx += kNT) {
-        const int k = idx & (kTT - 1), c = idx >> 6;
-        S.xb[idx] = k < w ? yout[(size_t)c * ldy + i0 + J * kTT + k] : 0.0;
+      double t[16], x[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int k = J * kTT + 4 * q + T.lq;
+        t[q] = (row_ok && k < nI) ? A[row + (size_t)k * n] : 0.0;
+        x[q] = (T.li < R && k < nI) ? yI[(size_t)T.li * ldy + k] : 0.0;
       }
-      __syncthreads();
-      tile_product<false>(S.Tl, S.xb, R, S.part, S.bb, 1.0, true);
+      mma_tile(acc, x, t);
     }
-    for (int idx = tid; idx < kTT * R; idx += kNT) {
-      const int i = idx & (kTT - 1), c = idx >> 6;
-      if (i < rows) tout[(size_t)c * ldt + g0 + G * kTT + i] = S.bb[idx];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int c = 4 * h + T.lq;
+      if (row_ok && c < R) tout[(size_t)c * ldt + g0 + G * kTT + T.ib + T.li] = acc[h];
     }
-    __syncthreads();
   }
 }
 
 // u_G = x (interface values at ldx, interface index; the owner writes u),
-// u_I = L_II^-T (y - L_GI^T u_G) for R columns (y at ldy, u at ldu, level dofs)
-__global__ void __launch_bounds__(kNT) k_tile_recover_cols(LevelDev L, const double* __restrict__ x, int ldx,
-                                                           const double* __restrict__ y, int ldy,
-                                                           double* __restrict__ u, int64_t ldu, int R, int ngmax) {
+// u_I = L_II^-T (y - L_GI^T u_G) for R columns (y at ldy, interior flat; u at
+// ldu, level dofs).  y is overwritten: each row tile's entries by u_I once
+// that tile is solved (the earlier tiles read u_J there, contiguous).
+__global__ void __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(4)))
+k_tile_recover_cols(LevelDev L, const double* __restrict__ x, int ldx, double* __restrict__ y, int ldy,
+                    double* __restrict__ u, int64_t ldu, int R, int ngmax) {
   extern __shared__ double sh[];
-  const TileLds S(sh);
+  double* xs = sh;              // the right-hand side of the diagonal product, 64 x kXS
+  double* xg = sh + kTT * kXS;  // u_G, ngp x kXS
   const int s = L.order ? L.order[blockIdx.x] : blockIdx.x;
   const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
   const int nI = L.nint[s];
@@ -169,63 +168,89 @@ __global__ void __launch_bounds__(kNT) k_tile_recover_cols(LevelDev L, const dou
   const int nbI = (nI + kTT - 1) / kTT, nbG = (ng + kTT - 1) / kTT;
   const int tid = threadIdx.x;
   const int ngp = nbG * kTT;   // (<= ngmax rounded up to the tile)
-  for (int idx = tid; idx < ngp * R; idx += kNT) {
-    const int c = idx / ngp, a = idx - c * ngp;
+  (void)ngmax;
+  for (int idx = tid; idx < ngp * kMaxRhs; idx += kNT) {
+    const int a = idx >> 3, c = idx & 7;
     double v = 0.0;
-    if (a < ng) {
+    if (a < ng && c < R) {
       const int f = g0 + a;
       const int gi = L.gam_iid[f];
       v = x[(size_t)c * ldx + gi];
       if (L.sh_flat[L.sh_ptr[gi]] == f) u[(size_t)c * ldu + L.gam_gid[f]] = v;
     }
-    S.xg[idx] = v;
+    xg[a * kXS + c] = v;
   }
-  (void)ngmax;
   __syncthreads();
+  const TileLane T;
+  double* yI = y + i0;   // y_I in, u_I out
   for (int I = nbI - 1; I >= 0; --I) {
     const int r0 = I * kTT, rows = min(kTT, nI - r0);
-    for (int idx = tid; idx < kTT * R; idx += kNT) {
-      const int i = idx & (kTT - 1), c = idx >> 6;
-      S.bb[idx] = i < rows ? y[(size_t)c * ldy + i0 + r0 + i] : 0.0;
+    const int col = r0 + T.ib + T.li;   // output row of u_I: the column of the tiles read transposed
+    const bool col_ok = T.ib + T.li < rows;
+    const int gid = col_ok ? L.int_gid[i0 + col] : 0;
+    double f[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int c = 4 * h + T.lq;
+      f[h] = (col_ok && c < R) ? yI[(size_t)c * ldy + col] : 0.0;
     }
-    // - L_GI^T u_G over the interface tiles whose envelope reaches tile I
+    tile_d4 acc = {0.0, 0.0, 0.0, 0.0};
+    // L_GI^T u_G over the interface tiles whose envelope reaches tile I
     for (int G = 0; G < nbG; ++G) {
       if (prof[nbI + G] > I) continue;
       const int g_0 = nI + G * kTT, grows = min(kTT, n - g_0);
-      stage_tile(S.Tl, A, n, g_0, grows, r0, rows);
-      for (int idx = tid; idx < kTT * R; idx += kNT) {
-        const int k = idx & (kTT - 1), c = idx >> 6;
-        S.xb[idx] = S.xg[c * ngp + G * kTT + k];
+      double t[16], xv[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int k = 4 * q + T.lq;
+        t[q] = (col_ok && k < grows) ? A[(g_0 + k) + (size_t)col * n] : 0.0;
+        xv[q] = T.li < kMaxRhs ? xg[(G * kTT + k) * kXS + T.li] : 0.0;
       }
-      __syncthreads();
-      tile_product<true>(S.Tl, S.xb, R, S.part, S.bb, -1.0, true);
+      mma_tile(acc, xv, t);
     }
-    // - L_JI^T u_J over the later interior tiles whose envelope reaches tile I
+    // L_JI^T u_J over the later interior tiles whose envelope reaches tile I
     for (int J = I + 1; J < nbI; ++J) {
       if (prof[J] > I) continue;
       const int j0 = J * kTT, jrows = min(kTT, nI - j0);
-      stage_tile(S.Tl, A, n, j0, jrows, r0, rows);
-      for (int idx = tid; idx < kTT * R; idx += kNT) {
-        const int k = idx & (kTT - 1), c = idx >> 6;
-        S.xb[idx] = k < jrows ? u[(size_t)c * ldu + L.int_gid[i0 + j0 + k]] : 0.0;
+      double t[16], xv[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int k = 4 * q + T.lq;
+        t[q] = (col_ok && k < jrows) ? A[(j0 + k) + (size_t)col * n] : 0.0;
+        xv[q] = (T.li < R && k < jrows) ? yI[(size_t)T.li * ldy + j0 + k] : 0.0;
       }
-      __syncthreads();
-      tile_product<true>(S.Tl, S.xb, R, S.part, S.bb, -1.0, true);
+      mma_tile(acc, xv, t);
     }
-    stage_tile(S.Tl, Ws + (size_t)I * kTT * kTT, kTT, 0, kTT, 0, kTT);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) xs[(T.ib + T.li) * kXS + 4 * h + T.lq] = f[h] - acc[h];
     __syncthreads();
-    tile_product<true>(S.Tl, S.bb, R, S.part, S.xb, 1.0, false);
-    for (int idx = tid; idx < kTT * R; idx += kNT) {
-      const int i = idx & (kTT - 1), c = idx >> 6;
-      if (i < rows) u[(size_t)c * ldu + L.int_gid[i0 + r0 + i]] = S.xb[idx];
+    tile_d4 u4 = {0.0, 0.0, 0.0, 0.0};
+    {
+      const double* WI = Ws + (size_t)I * kTT * kTT;
+      double t[16], xv[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int k = 4 * q + T.lq;
+        t[q] = WI[k + (T.ib + T.li) * kTT];
+        xv[q] = T.li < kMaxRhs ? xs[k * kXS + T.li] : 0.0;
+      }
+      mma_tile(u4, xv, t);
     }
-    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int c = 4 * h + T.lq;
+      if (col_ok && c < R) {
+        yI[(size_t)c * ldy + col] = u4[h];
+        u[(size_t)c * ldu + gid] = u4[h];
+      }
+    }
+    __syncthreads();   // xs is rewritten, and u_I is read by the earlier row tiles
   }
 }
 
 static size_t tile_lds(int ngmax) {
   const size_t ngp = (size_t)((ngmax + kTT - 1) / kTT) * kTT;
-  return sizeof(double) * ((size_t)kTT * kTL + 2 * (size_t)kTT * kMaxRhs + 4 * (size_t)kMaxRhs * kTT + ngp * kMaxRhs);
+  return sizeof(double) * (size_t)kXS * (kTT + ngp);
 }
 
 void launch_tile_pre_cols(hipStream_t st, const LevelDev& L, const double* r, int64_t ldr, double* y, int ldy,
@@ -234,7 +259,7 @@ void launch_tile_pre_cols(hipStream_t st, const LevelDev& L, const double* r, in
   launch_kernel(k_tile_pre_cols, dim3(L.nsub), dim3(kNT), tile_lds(0), st, L, r, ldr, y, ldy, t, ldt, R);
 }
 
-void launch_tile_recover_cols(hipStream_t st, const LevelDev& L, const double* x, int ldx, const double* y, int ldy,
+void launch_tile_recover_cols(hipStream_t st, const LevelDev& L, const double* x, int ldx, double* y, int ldy,
                               double* u, int64_t ldu, int R, int ngmax) {
   if (R < 1 || R > kMaxRhs) throw std::invalid_argument("launch_tile_recover_cols: bad column count");
   launch_kernel(k_tile_recover_cols, dim3(L.nsub), dim3(kNT), tile_lds(ngmax), st, L, x, ldx, y, ldy, u, ldu, R,

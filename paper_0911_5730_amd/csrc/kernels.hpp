@@ -316,10 +316,10 @@ void launch_pcg_update_restrict_rows(hipStream_t st, const LevelDev& L, int ngma
 void launch_partial_chol_big(hipStream_t st, const LevelDev& L, double* K, double* Wd, int* status);
 // interior solves of many columns with the tiled factor (k_tile.hip):
 //   pre:     y = L_II^-1 r_I, t = L_GI y  (condensation / interior pre-correction)
-//   recover: u_G = x, u_I = L_II^-T (y - L_GI^T x)
+//   recover: u_G = x, u_I = L_II^-T (y - L_GI^T x)  (y is overwritten by u_I)
 void launch_tile_pre_cols(hipStream_t st, const LevelDev& L, const double* r, int64_t ldr, double* y, int ldy,
                           double* t, int ldt, int R);
-void launch_tile_recover_cols(hipStream_t st, const LevelDev& L, const double* x, int ldx, const double* y, int ldy,
+void launch_tile_recover_cols(hipStream_t st, const LevelDev& L, const double* x, int ldx, double* y, int ldy,
                               double* u, int64_t ldu, int R, int ngmax);
 size_t partial_chol_big_lds();
 void launch_partial_chol(hipStream_t st, int nsub, int nmax, const int64_t* koff, const int32_t* loc_ptr,
