@@ -296,6 +296,20 @@ bool use_big_chol(int nmax) {
   return !use_mfma_chol(nmax);
 }
 
+// Level 1: the interior elimination by the tiled kernel at any size, for the
+// tiled block substitutions of the interface-reduced solve (its condensation
+// and recovery; the set-up also leaves the tiles' envelope and diagonal
+// inverses), unless BDDC_IR_PATH=sweep or another elimination path is forced.
+// Deeper levels: the tiled kernel only where the panels do not fit.
+bool level_big_chol(int ell, int nmax) {
+  if (use_big_chol(nmax)) return true;
+  if (ell != 1) return false;
+  const char* env = getenv("BDDC_CHOL_PATH");
+  if (env && *env) return false;
+  const char* ir = getenv("BDDC_IR_PATH");
+  return !(ir && std::string(ir) == "sweep");
+}
+
 // Level-1 interior sweeps streamed through LDS panels unless the substructures
 // are too large for them or BDDC_SWEEP=off.
 bool use_sweep(int nmax) {
@@ -405,7 +419,7 @@ struct Level {
     double* Linv;
     int64_t* linvoff;
     // tiled elimination (large local matrices): envelope per row tile, inverses of the diagonal tiles
-    int32_t *tprof, *tproff;
+    int32_t *tprof, *tproff, *rgf, *rgfoff;
     double* Wd;
     int64_t* woff;
     // level-1 sweeps: the envelope's interior row ends per panel
@@ -415,6 +429,7 @@ struct Level {
   } d{};
   bool sweep_env = false;
   bool has_order = false;
+  bool has_rgf = false;
   std::vector<int64_t> linvoff;
   bool big = false;   // interior elimination by the tiled kernel
   LevelDev dev;
@@ -907,9 +922,9 @@ class Builder {
     // interface tiles) the first interior column tile of the envelope of the
     // local matrix, i.e. of its factor (fill stays right of each row's first
     // nonzero); found from the elements at level 1, every tile at other levels
-    std::vector<int32_t> tproff, tprof, big_order;
+    std::vector<int32_t> tproff, tprof, big_order, rgfoff, rgf;
     std::vector<int64_t> woff;
-    lv.big = use_big_chol(lv.nmax);
+    lv.big = level_big_chol(lv.ell, lv.nmax);
     if (lv.big) {
       constexpr int kT = 64;
       tproff.assign(nsub + 1, 0);
@@ -920,6 +935,12 @@ class Builder {
         woff[s + 1] = woff[s] + (int64_t)nbI * kT * kT;
       }
       tprof.assign(tproff[nsub], 0);
+      if (G) {
+        rgfoff.assign(nsub + 1, 0);
+        for (int s = 0; s < nsub; ++s)
+          rgfoff[s + 1] = rgfoff[s] + (T.n_int[s] + 3) / 4 + (T.ngam(s) + 3) / 4;
+        rgf.assign(rgfoff[nsub], 0);
+      }
       if (G)
         parallel_for(nsub, 4, [&](int s0, int s1) {
           std::vector<int> f;
@@ -943,6 +964,17 @@ class Builder {
               int mn = INT32_MAX;
               for (int r = r0; r < r1; ++r) mn = std::min(mn, f[r]);
               pr[t] = mn == INT32_MAX ? nbI : mn / kT;
+            }
+            // per four rows (interior, then interface): the first interior
+            // column of the envelope (nI when the rows hold none)
+            int32_t* gf = &rgf[rgfoff[s]];
+            const int ng4 = (n - nI + 3) / 4, nI4 = (nI + 3) / 4;
+            for (int g = 0; g < nI4 + ng4; ++g) {
+              const int r0 = g < nI4 ? 4 * g : nI + 4 * (g - nI4);
+              const int r1 = g < nI4 ? std::min(nI, r0 + 4) : std::min(n, r0 + 4);
+              int mn = INT32_MAX;
+              for (int r = r0; r < r1; ++r) mn = std::min(mn, f[r]);
+              gf[g] = mn == INT32_MAX ? nI : mn;
             }
           }
         });
@@ -971,7 +1003,7 @@ class Builder {
     {
       const char* eenv = getenv("BDDC_SWEEP_ENV");
       const bool env_on = !(eenv && std::string(eenv) == "0");
-      if (G && !lv.big && env_on && sweep_fits(lv.nmax)) {
+      if (G && env_on && sweep_fits(lv.nmax)) {
         srendoff.assign(nsub + 1, 0);
         for (int s = 0; s < nsub; ++s) {
           const int nI = T.n_int[s];
@@ -1075,6 +1107,8 @@ class Builder {
       d.linvoff = A.take<int64_t>(nsub + 1);
       d.tprof = A.take<int32_t>(tprof.size());
       d.tproff = A.take<int32_t>(tproff.size());
+      d.rgf = A.take<int32_t>(rgf.size());
+      d.rgfoff = A.take<int32_t>(rgfoff.size());
       d.Wd = A.take<double>(woff.empty() ? 0 : (size_t)woff.back());
       d.woff = A.take<int64_t>(woff.size());
       d.srend = A.take<int32_t>(srend.size());
@@ -1135,6 +1169,10 @@ class Builder {
       stg.add(d.tprof, tprof);
       stg.add(d.tproff, tproff);
       stg.add(d.woff, woff);
+      if (!rgf.empty()) {
+        stg.add(d.rgf, rgf);
+        stg.add(d.rgfoff, rgfoff);
+      }
     }
     if (!srend.empty()) {
       stg.add(d.srend, srend);
@@ -1142,6 +1180,7 @@ class Builder {
     }
     if (!big_order.empty()) stg.add(d.order, big_order);
     lv.has_order = !big_order.empty();
+    lv.has_rgf = !rgf.empty() && !(getenv("BDDC_TILE_ENV") && std::string(getenv("BDDC_TILE_ENV")) == "0");
     lv.sweep_env = !srend.empty();
     if (adaptive) {
       stg.add(d.schws_off, lv.schws_off);
@@ -1441,6 +1480,8 @@ class Builder {
     D.linvoff = d.linvoff;
     D.tprof = lv.big ? d.tprof : nullptr;
     D.tproff = lv.big ? d.tproff : nullptr;
+    D.rgf = lv.big && lv.has_rgf ? d.rgf : nullptr;
+    D.rgfoff = lv.big && lv.has_rgf ? d.rgfoff : nullptr;
     D.srend = lv.sweep_env ? d.srend : nullptr;
     D.srendoff = lv.sweep_env ? d.srendoff : nullptr;
     D.order = lv.has_order ? d.order : nullptr;
@@ -2207,12 +2248,16 @@ static void pcg_begin(bddc_ctx* h, const double* f, int64_t ld, int R, double rt
     sch[c].it_base = 1;
     BDDC_HIP(hipMemcpyAsync(P.sc + c, sch + c, offsetof(PcgScalars, alphas), hipMemcpyHostToDevice, st));
   }
-  // the condensation: with the streamed sweeps (small substructures) or the
-  // tiled block substitution (large ones) all columns in one pass over L
-  // (y = L^{-1} f_I, t = L_GI y per column); else the blocked triangular
-  // solves when kMaxRhs columns fit the LDS, else column by column
-  run.sweep = use_sweep(l1.nmax);
-  run.tiles = !run.sweep && l1.big;
+  // the condensation: with the tiled block substitution (the level-1 factor
+  // of the tiled elimination; BDDC_IR_PATH=sweep: not taken) or the streamed
+  // sweeps all columns in one pass over L (y = L^{-1} f_I, t = L_GI y per
+  // column); else the blocked triangular solves when kMaxRhs columns fit the
+  // LDS, else column by column
+  {
+    const char* ir = getenv("BDDC_IR_PATH");
+    run.tiles = l1.big && !(ir && std::string(ir) == "sweep");
+  }
+  run.sweep = !run.tiles && use_sweep(l1.nmax);
   run.blocked = !run.sweep && !run.tiles && apply_cols_lds(kMaxRhs, l1.nImax, l1.ngmax) <= kLdsMax;
   const bool sweep = run.sweep, tiles = run.tiles, blocked = run.blocked;
   if (sweep) launch_sweep_pre_cols(st, l1.dev, f, ld, h->cy, h->ld_cy, h->ct, P.ld_flat, R);
@@ -2494,7 +2539,7 @@ bddc_status bddc_plan(const bddc_problem* p, bddc_info* info) {
     for (int s = 0; s < lv.nsub; ++s) {
       const double n = T.nloc(s), ng = T.ngam(s), nI = T.n_int[s];
       by += 8.0 * n * n + 16.0 * ng * ng + 8.0 * ng * 8;
-      if (use_big_chol(lv.nmax)) by += 8.0 * 64.0 * 64.0 * std::ceil(nI / 64.0);
+      if (level_big_chol(1, lv.nmax)) by += 8.0 * 64.0 * 64.0 * std::ceil(nI / 64.0);
     }
     by += 8.0 * (12.0 * lv.nflat_g + 4.0 * lv.nflat_i) + 8.0 * 10.0 * (double)info->n_free;
     info->device_bytes = (int64_t)(1.1 * by);

@@ -20,7 +20,9 @@
 // (L_IJ, W) sixteen consecutive rows of four adjacent columns per load, for a
 // tile read transposed (L_GI^T, L_JI^T, W^T) four consecutive rows of sixteen
 // columns.  The accumulator lands with lane l holding output row i', columns
-// q and 4 + q.
+// q and 4 + q.  Entries known to be zero are not loaded: those left of the
+// envelope (per four rows, the first column of the factor's nonzeros) and
+// the upper triangle of W.  They are exact zeros, so the sums are the same.
 #include "dense.hpp"
 #include "kernels.hpp"
 
@@ -75,11 +77,14 @@ k_tile_pre_cols(LevelDev L, const double* __restrict__ r, int64_t ldr, double* _
   const int i0 = L.ioff[s], g0 = L.goff[s];
   const int nbI = (nI + kTT - 1) / kTT, nbG = (ng + kTT - 1) / kTT;
   const TileLane T;
+  const int32_t* gf = L.rgf ? L.rgf + L.rgfoff[s] : nullptr;   // envelope per four rows
+  const int nI4 = (nI + 3) / 4;
   double* yI = yout + i0;   // column c at yI + c ldy
   for (int I = 0; I < nbI; ++I) {
     const int r0 = I * kTT, rows = min(kTT, nI - r0);
     const int row = r0 + T.ib + T.li;
     const bool row_ok = T.ib + T.li < rows;
+    const int fr = !row_ok ? INT32_MAX : gf ? gf[row >> 2] : 0;   // the row's first column to load
     // this lane's entries of f_I (row, columns q and 4 + q), loaded first
     double f[2];
     {
@@ -96,7 +101,7 @@ k_tile_pre_cols(LevelDev L, const double* __restrict__ r, int64_t ldr, double* _
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         const int k = J * kTT + 4 * q + T.lq;
-        t[q] = row_ok ? A[row + (size_t)k * n] : 0.0;
+        t[q] = k >= fr ? A[row + (size_t)k * n] : 0.0;
         x[q] = T.li < R ? yI[(size_t)T.li * ldy + k] : 0.0;
       }
       mma_tile(acc, x, t);
@@ -112,7 +117,7 @@ k_tile_pre_cols(LevelDev L, const double* __restrict__ r, int64_t ldr, double* _
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         const int k = 4 * q + T.lq;
-        t[q] = WI[(T.ib + T.li) + k * kTT];
+        t[q] = (row_ok && k <= T.ib + T.li) ? WI[(T.ib + T.li) + k * kTT] : 0.0;   // (W lower triangular)
         x[q] = T.li < kMaxRhs ? xs[k * kXS + T.li] : 0.0;
       }
       mma_tile(y4, x, t);
@@ -128,13 +133,14 @@ k_tile_pre_cols(LevelDev L, const double* __restrict__ r, int64_t ldr, double* _
     const int r0 = nI + G * kTT, rows = min(kTT, n - r0);
     const int row = r0 + T.ib + T.li;
     const bool row_ok = T.ib + T.li < rows;
+    const int fr = !row_ok ? INT32_MAX : gf ? gf[nI4 + ((G * kTT + T.ib + T.li) >> 2)] : 0;
     tile_d4 acc = {0.0, 0.0, 0.0, 0.0};
     for (int J = prof[nbI + G]; J < nbI; ++J) {
       double t[16], x[16];
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         const int k = J * kTT + 4 * q + T.lq;
-        t[q] = (row_ok && k < nI) ? A[row + (size_t)k * n] : 0.0;
+        t[q] = (k >= fr && k < nI) ? A[row + (size_t)k * n] : 0.0;
         x[q] = (T.li < R && k < nI) ? yI[(size_t)T.li * ldy + k] : 0.0;
       }
       mma_tile(acc, x, t);
@@ -182,6 +188,11 @@ k_tile_recover_cols(LevelDev L, const double* __restrict__ x, int ldx, double* _
   }
   __syncthreads();
   const TileLane T;
+  // envelope per four rows: at step q of a tile read transposed the four
+  // rows of lane group q share one entry (wave-uniform, clamped to the last
+  // group; the rows past it are not loaded anyway)
+  const int32_t* gf = L.rgf ? L.rgf + L.rgfoff[s] : nullptr;
+  const int nI4 = (nI + 3) / 4, ng4 = (ng + 3) / 4;
   double* yI = y + i0;   // y_I in, u_I out
   for (int I = nbI - 1; I >= 0; --I) {
     const int r0 = I * kTT, rows = min(kTT, nI - r0);
@@ -203,7 +214,8 @@ k_tile_recover_cols(LevelDev L, const double* __restrict__ x, int ldx, double* _
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         const int k = 4 * q + T.lq;
-        t[q] = (col_ok && k < grows) ? A[(g_0 + k) + (size_t)col * n] : 0.0;
+        const int fq = gf ? gf[nI4 + min(16 * G + q, ng4 - 1)] : 0;
+        t[q] = (col_ok && k < grows && col >= fq) ? A[(g_0 + k) + (size_t)col * n] : 0.0;
         xv[q] = T.li < kMaxRhs ? xg[(G * kTT + k) * kXS + T.li] : 0.0;
       }
       mma_tile(acc, xv, t);
@@ -216,7 +228,8 @@ k_tile_recover_cols(LevelDev L, const double* __restrict__ x, int ldx, double* _
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         const int k = 4 * q + T.lq;
-        t[q] = (col_ok && k < jrows) ? A[(j0 + k) + (size_t)col * n] : 0.0;
+        const int fq = gf ? gf[min(16 * J + q, nI4 - 1)] : 0;
+        t[q] = (col_ok && k < jrows && col >= fq) ? A[(j0 + k) + (size_t)col * n] : 0.0;
         xv[q] = (T.li < R && k < jrows) ? yI[(size_t)T.li * ldy + j0 + k] : 0.0;
       }
       mma_tile(acc, xv, t);
@@ -231,7 +244,7 @@ k_tile_recover_cols(LevelDev L, const double* __restrict__ x, int ldx, double* _
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         const int k = 4 * q + T.lq;
-        t[q] = WI[k + (T.ib + T.li) * kTT];
+        t[q] = (col_ok && k >= T.ib + T.li && k < rows) ? WI[k + (T.ib + T.li) * kTT] : 0.0;   // (W^T upper)
         xv[q] = T.li < kMaxRhs ? xs[k * kXS + T.li] : 0.0;
       }
       mma_tile(u4, xv, t);

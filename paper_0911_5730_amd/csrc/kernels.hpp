@@ -79,6 +79,12 @@ struct LevelDev {
   // column-major each), offsets woff
   const int32_t* tprof = nullptr;
   const int32_t* tproff = nullptr;
+  // the same envelope per group of four rows (interior rows, then interface
+  // rows, each from a group boundary): the first interior column any of the
+  // four rows holds a nonzero in (entries left of it are zeros of the factor
+  // and are not loaded), offsets rgfoff; null = column 0
+  const int32_t* rgf = nullptr;
+  const int32_t* rgfoff = nullptr;
   // large local matrices: the substructures in decreasing order of their
   // elimination work (workgroup b takes substructure order[b], so the largest
   // start first and the uneven sizes pack the CUs; null = in index order)

@@ -129,10 +129,13 @@ def test_deep_level_paths(path, case, monkeypatch):
         S.close()
 
 
-def test_large_substructures_size_order_bitwise(monkeypatch):
+@pytest.mark.parametrize("switch", ["BDDC_BIG_ORDER", "BDDC_TILE_ENV"])
+def test_large_substructures_order_and_envelope_bitwise(switch, monkeypatch):
     """The workgroups of the tiled elimination and tiled substitutions take
-    the substructures largest first; the results are bitwise those of index
-    order (uneven Voronoi regions, the tiled path forced)."""
+    the substructures largest first, and the tiled substitutions leave the
+    entries left of the envelope and W's upper triangle unread (exact zeros);
+    the results are bitwise those of index order and of reading every entry
+    (uneven Voronoi regions, the tiled path forced, three loads)."""
     import torch
 
     import paper_0911_5730_amd as P
@@ -142,13 +145,15 @@ def test_large_substructures_size_order_bitwise(monkeypatch):
     F = cuda_vec(np.random.default_rng(14).uniform(-1, 1, (3, prob.n_free)))
     r = cuda_vec(np.random.default_rng(15).standard_normal(prob.n_free))
     out = {}
-    for order in ("1", "0"):
-        monkeypatch.setenv("BDDC_BIG_ORDER", order)
+    for on in ("1", "0"):
+        monkeypatch.setenv(switch, on)
         with P.Solver(prob) as S:
             U, its, _ = S.solve(F, rtol=1e-10)
-            out[order] = (U, its, S.apply(r))
+            u1, it1, _ = S.solve(F[1].contiguous(), rtol=1e-10)
+            out[on] = (U, its, S.apply(r), u1)
     assert out["1"][1] == out["0"][1]
-    assert torch.equal(out["1"][0], out["0"][0]) and torch.equal(out["1"][2], out["0"][2])
+    for k in (0, 2, 3):
+        assert torch.equal(out["1"][k], out["0"][k]), k
 
 
 @pytest.mark.parametrize("case", ["adaptive3_h16", "voronoi_jitter3", "adaptive2_h32"])
@@ -165,6 +170,7 @@ def test_sweep_envelope_bitwise(case, monkeypatch):
     f = cuda_vec(prob.f[0])
     F = cuda_vec(np.random.default_rng(12).uniform(-1, 1, (3, prob.n_free)))
     r = cuda_vec(np.random.default_rng(13).standard_normal(prob.n_free))
+    monkeypatch.setenv("BDDC_IR_PATH", "sweep")   # the sweeps in the condensation and recovery too
     out = {}
     for env in ("1", "0"):
         monkeypatch.setenv("BDDC_SWEEP_ENV", env)
@@ -287,14 +293,18 @@ def test_pcg_row_blocks_match_oracle(case, monkeypatch):
         S.close()
 
 
-@pytest.mark.parametrize("path", ["default", "lds16_global", "sweep32", "eig_workgroup", "pair_global",
+@pytest.mark.parametrize("path", ["default", "ir_sweep", "lds16_global", "sweep32", "eig_workgroup", "pair_global",
                                   "pcg_ops_full", "chol_big"])
 def test_setup_kernel_paths(path, monkeypatch):
-    """The setup runs with 64-wide Cholesky panels and a matrix-core trailing
-    update plus LDS-resident Gauss-Jordan factorizations, and the level-1
-    interior sweeps stream 64-column panels (default; 32-column panels,
-    two workgroups per CU, on large grids); or with 16-wide panels on the
-    vector units, global-memory factorizations and 16-row blocked sweeps.
+    """The level-1 interior elimination runs the tiled left-looking kernel
+    (64 x 64 tiles, MFMA) and the condensation and recovery of the solve the
+    tiled block substitutions (default), the deeper levels 64-wide Cholesky
+    panels with a matrix-core trailing update plus LDS-resident Gauss-Jordan
+    factorizations; the FS apply's level-1 interior sweeps stream 64-column
+    panels (32-column panels, two workgroups per CU, on large grids).  Or:
+    the panels at level 1 too and the sweeps in the solve (ir_sweep); or
+    16-wide panels on the vector units, global-memory factorizations and
+    16-row blocked sweeps.
     The pair eigenproblems run one wave per edge (default) or one
     256-thread workgroup per edge; the pair Schur complements and
     eigenproblems work in LDS (default) or in a global workspace (used for
@@ -309,6 +319,8 @@ def test_setup_kernel_paths(path, monkeypatch):
         monkeypatch.setenv("BDDC_CHOL_PATH", "lds16")
         monkeypatch.setenv("BDDC_SETUP_PATH", "global")
         monkeypatch.setenv("BDDC_SWEEP", "off")
+    if path == "ir_sweep":
+        monkeypatch.setenv("BDDC_IR_PATH", "sweep")
     if path == "sweep32":
         monkeypatch.setenv("BDDC_SWEEP_BW", "32")
     if path == "eig_workgroup":
