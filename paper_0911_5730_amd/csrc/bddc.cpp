@@ -2139,6 +2139,7 @@ static void lay_columns(bddc_ctx* h, Arena& A, int R) {
   P.rz_part[1] = A.take<double>((size_t)R * P.ld_blk);
   P.qloc = A.take<double>((size_t)R * P.ld_flat);
   P.da = A.take<double>((size_t)R * P.ld_flat);
+  P.gflat = A.take<double>(P.nrb ? (size_t)R * P.ld_flat : 0);
   P.b = A.take<double>((size_t)R * P.ld_cflat);
   P.uc = A.take<double>((size_t)R * P.ld_coarse);
   P.sc = A.take<PcgScalars>(R);
@@ -2184,12 +2185,15 @@ static void pcg_apply_iface(bddc_ctx* h, hipStream_t q, int uu, int it) {
   Level& l1 = *h->levels[0];
   PcgDev& P = h->pcg;
   timing::current_tag = it - 1;
-  {
+  if (P.nrb) {
+    // wide interfaces: the update once per substructure, then the
+    // restriction by row blocks
+    if (it > 0) launch_pcg_update_rows(q, l1.dev, P, uu);
+    timing::Scope ts("apply_restrict", h->by_r_prec, 0);
+    launch_pcg_restrict_rows(q, l1.dev, l1.ngmax, P, uu);
+  } else {
     timing::Scope ts("apply_restrict", it > 0 ? h->by_ur_prec : h->by_r_prec, 0);
-    if (P.nrb)
-      launch_pcg_update_restrict_rows(q, l1.dev, l1.ngmax, P, uu);
-    else
-      launch_pcg_update_restrict(q, l1.dev, l1.ngmax, l1.nrmax, l1.ncsmax, P, uu);
+    launch_pcg_update_restrict(q, l1.dev, l1.ngmax, l1.nrmax, l1.ncsmax, P, uu);
   }
   if (P.fin && it > 0) launch_pcg_sum(q, P, 1, uu);
   run_deep_cols(h, q, P.b, P.ld_cflat, const_cast<double*>(P.uc), P.ld_coarse, P.nrhs);

@@ -189,20 +189,132 @@ template <int kPrec> struct RowsForm;
 template <> struct RowsForm<0> { using T = double; };
 template <> struct RowsForm<1> { using T = float; };
 
-// alpha; r_k = r_{k-1} - alpha sum of the sharers' q and g = delta r_k on the
-// whole interface (block 0 also stores r_k and x and the partial r.r), then
-// b = Psi^T g for the coarse dofs rb, rb + nrb_s, ... and delta T_rr g on the
-// block's rows (zero on the corner rows).
-template <int kPrec, bool kMulti>
-__global__ void __launch_bounds__(kRT) k_pcg_update_restrict_rows(LevelDev L, PcgDev P, int u) {
-  using T = typename RowsForm<kPrec>::T;
+// alpha; r_k = r_{k-1} - alpha sum of the sharers' q (the owner stores r_k
+// and x += alpha p) and g = delta r_k for every interface entry of the
+// substructure, to P.gflat; the substructure's partial r.r.  One workgroup
+// per substructure, so the gathers of the sharers' products are done once
+// (not by each row block of the restriction).
+template <bool kMulti>
+__global__ void __launch_bounds__(kRT) k_pcg_update_rows(LevelDev L, PcgDev P, int u) {
   constexpr int kNL = kMulti ? kMaxRhs : 1;
   constexpr int kGrp = kNL < 4 ? kNL : 4;
-  extern __shared__ double2 sh2[];
-  double* sh = reinterpret_cast<double*>(sh2);
   __shared__ int lc[kMaxRhs];
   __shared__ double red[kNW];
   __shared__ double alph[kMaxRhs];
+  if (P.sc[0].all_done) return;
+  const int it = P.sc[0].it_base + u;   // (an iteration: u >= 0)
+  const int s = blockIdx.x;
+  const int ng = L.loc_ptr[s + 1] - L.loc_ptr[s] - L.nint[s];
+  const int g0 = L.goff[s];
+  const int tid = threadIdx.x;
+  int nl = live_columns(P, lc);
+  if (nl == 0) return;
+  if constexpr (!kMulti) nl = 1;
+  auto col = [&](int k) -> int {
+    if constexpr (kMulti) return lc[k];
+    else return 0;
+  };
+  const double* rold = P.r[(it - 1) & 1];
+  double* rnew = P.r[it & 1];
+  const double* p = P.p[it & 1];
+  double rr[kNL];
+#pragma unroll
+  for (int k = 0; k < kNL; ++k) rr[k] = 0.0;
+  // alpha per live column (every thread writes the same values: no barrier)
+  for (int k = 0; k < nl; ++k) alph[k] = P.sc[col(k)].rzs[(it - 1) & 1] / P.sc[col(k)].pqs;
+  // entry a of every live column on thread a: its loads (the sharers'
+  // products, r_{k-1}) are issued before the stores of r_k
+  for (int a = tid; a < ng; a += kRT) {
+    const int f = g0 + a;
+    const int gi = L.gam_iid[f];
+    const double d = L.delta[f];
+    const int4 sf = P.shf4 ? P.shf4[f] : make_int4(-1, -1, -1, -1);
+    const bool own = P.shf4 ? sf.x == f : L.sh_flat[L.sh_ptr[gi]] == f;
+    // four columns at a time (the loads of a group go out together; the
+    // next group's follow this group's stores)
+#pragma unroll
+    for (int h = 0; h < kNL; h += kGrp) {
+      double q[kGrp], ro[kGrp];
+#pragma unroll
+      for (int e = 0; e < kGrp; ++e) {
+        const int k = h + e;
+        if (k < nl) {
+          const double* ql = P.qloc + (size_t)col(k) * P.ld_flat;
+          double v;
+          if (P.shf4) {
+            v = ql[sf.x];
+            if (sf.y >= 0) v += ql[sf.y];
+            if (sf.z >= 0) v += ql[sf.z];
+            if (sf.w >= 0) v += ql[sf.w];
+          } else {
+            v = 0.0;
+            for (int m = L.sh_ptr[gi]; m < L.sh_ptr[gi + 1]; ++m) v += ql[L.sh_flat[m]];
+          }
+          q[e] = v;
+          ro[e] = rold[(size_t)col(k) * P.ld_if + gi];
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < kGrp; ++e) {
+        const int k = h + e;
+        if (k < nl) {
+          const double ri = ro[e] - alph[k] * q[e];
+          P.gflat[(size_t)col(k) * P.ld_flat + f] = d * ri;
+          if (own) {
+            rnew[(size_t)col(k) * P.ld_if + gi] = ri;
+            rr[k] += ri * ri;
+          }
+        }
+      }
+    }
+  }
+  // x += alpha p by the owners, in a pass of its own so that the loads of
+  // every column go out together (after the stores of r_k, which the
+  // compiler may not move them across)
+  for (int a = tid; a < ng; a += kRT) {
+    const int f = g0 + a;
+    const int gi = L.gam_iid[f];
+    if (!(P.shf4 ? P.shf4[f].x == f : L.sh_flat[L.sh_ptr[gi]] == f)) continue;
+    double pv[kNL], xv[kNL];
+#pragma unroll
+    for (int k = 0; k < kNL; ++k) {
+      if (k < nl) {
+        const size_t ci = (size_t)col(k) * P.ld_if + gi;
+        pv[k] = p[ci];
+        xv[k] = P.x[ci];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kNL; ++k)
+      if (k < nl) P.x[(size_t)col(k) * P.ld_if + gi] = xv[k] + alph[k] * pv[k];
+  }
+  for (int k = 0; k < nl; ++k) {
+    double v = 0.0;
+#pragma unroll
+    for (int m = 0; m < kNL; ++m)
+      if (m == k) v = rr[m];   // (constant register index)
+    v = wg_sum(v, red);
+    if (tid == 0) {
+      const int c = col(k);
+      P.rr_part[(size_t)c * P.ld_sub + s] = v;
+      if (s == 0) {
+        P.sc[c].iters = it;
+        P.sc[c].alphas[min(it - 1, kMaxHist - 1)] = alph[k];
+      }
+    }
+  }
+}
+
+// g = delta r on the whole interface (iteration 0: from r_0; later: g of
+// k_pcg_update_rows), then b = Psi^T g for the coarse dofs rb, rb + nrb_s,
+// ... and delta T_rr g on the block's rows (zero on the corner rows).
+template <int kPrec, bool kMulti>
+__global__ void __launch_bounds__(kRT) k_pcg_restrict_rows(LevelDev L, PcgDev P, int u) {
+  using T = typename RowsForm<kPrec>::T;
+  constexpr int kNL = kMulti ? kMaxRhs : 1;
+  extern __shared__ double2 sh2[];
+  double* sh = reinterpret_cast<double*>(sh2);
+  __shared__ int lc[kMaxRhs];
   if (P.sc[0].all_done) return;
   const int it = u < 0 ? 0 : P.sc[0].it_base + u;
   int s, rb;
@@ -210,18 +322,14 @@ __global__ void __launch_bounds__(kRT) k_pcg_update_restrict_rows(LevelDev L, Pc
   if (s >= L.nsub) return;
   const int ng = L.loc_ptr[s + 1] - L.loc_ptr[s] - L.nint[s];
   const int nrb_s = (ng + kRows - 1) / kRows;
-  if (rb >= max(1, nrb_s)) return;   // (no rows, no coarse dofs, no update)
+  if (rb >= max(1, nrb_s)) return;   // (no rows, no coarse dofs)
   const int g0 = L.goff[s];
   const int n_r = L.nr[s];
   const int ncs = L.coff[s + 1] - L.coff[s];
   const int r0 = rb * kRows;
   const int rows_r = max(0, min(kRows, n_r - r0));
   const int tid = threadIdx.x, lane = tid & 63;
-  // the FP32 form takes the wave's columns in scalar registers (104 against
-  // 133 registers, 262 against 336 us per launch at config 4); the FP64 form
-  // keeps them per lane (106 against 140 registers with scalar columns, 297
-  // against 334 us)
-  const int wave = kPrec == 1 ? __builtin_amdgcn_readfirstlane(tid >> 6) : (tid >> 6);
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // (uniform: the columns of a wave in scalar registers)
   int nl = live_columns(P, lc);
   if (nl == 0) return;
   if constexpr (!kMulti) nl = 1;
@@ -242,98 +350,9 @@ __global__ void __launch_bounds__(kRT) k_pcg_update_restrict_rows(LevelDev L, Pc
       g[(size_t)a * nls + k] = L.delta[g0 + a] * P.r[0][(size_t)col(k) * P.ld_if + L.gam_iid[g0 + a]];
     }
   } else {
-    const double* rold = P.r[(it - 1) & 1];
-    double* rnew = P.r[it & 1];
-    const double* p = P.p[it & 1];
-    double rr[kNL];
-#pragma unroll
-    for (int k = 0; k < kNL; ++k) rr[k] = 0.0;
-    // alpha per live column (every thread writes the same values: no barrier)
-    for (int k = 0; k < nl; ++k) alph[k] = P.sc[col(k)].rzs[(it - 1) & 1] / P.sc[col(k)].pqs;
-    // entry a of every live column on thread a: its loads (the sharers'
-    // products, r_{k-1}, p) are issued before the stores of r_k and x
-    for (int a = tid; a < ng; a += kRT) {
-      const int f = g0 + a;
-      const int gi = L.gam_iid[f];
-      const double d = L.delta[f];
-      const int4 sf = P.shf4 ? P.shf4[f] : make_int4(-1, -1, -1, -1);
-      const bool own = rb == 0 && (P.shf4 ? sf.x == f : L.sh_flat[L.sh_ptr[gi]] == f);
-      // four columns at a time (the loads of a group go out together; the
-      // next group's follow this group's stores)
-#pragma unroll
-      for (int h = 0; h < kNL; h += kGrp) {
-        double q[kGrp], ro[kGrp];
-#pragma unroll
-        for (int e = 0; e < kGrp; ++e) {
-          const int k = h + e;
-          if (k < nl) {
-            const double* ql = P.qloc + (size_t)col(k) * P.ld_flat;
-            double v;
-            if (P.shf4) {
-              v = ql[sf.x];
-              if (sf.y >= 0) v += ql[sf.y];
-              if (sf.z >= 0) v += ql[sf.z];
-              if (sf.w >= 0) v += ql[sf.w];
-            } else {
-              v = 0.0;
-              for (int m = L.sh_ptr[gi]; m < L.sh_ptr[gi + 1]; ++m) v += ql[L.sh_flat[m]];
-            }
-            q[e] = v;
-            ro[e] = rold[(size_t)col(k) * P.ld_if + gi];
-          }
-        }
-#pragma unroll
-        for (int e = 0; e < kGrp; ++e) {
-          const int k = h + e;
-          if (k < nl) {
-            const double ri = ro[e] - alph[k] * q[e];
-            g[(size_t)a * nls + k] = d * ri;
-            if (own) {
-              rnew[(size_t)col(k) * P.ld_if + gi] = ri;
-              rr[k] += ri * ri;
-            }
-          }
-        }
-      }
-    }
-    // x += alpha p by the owners, in a pass of its own so that the loads of
-    // every column go out together (after the stores of r_k, which the
-    // compiler may not move them across)
-    if (rb == 0) {
-      for (int a = tid; a < ng; a += kRT) {
-        const int f = g0 + a;
-        const int gi = L.gam_iid[f];
-        if (!(P.shf4 ? P.shf4[f].x == f : L.sh_flat[L.sh_ptr[gi]] == f)) continue;
-        double pv[kNL], xv[kNL];
-#pragma unroll
-        for (int k = 0; k < kNL; ++k) {
-          if (k < nl) {
-            const size_t ci = (size_t)col(k) * P.ld_if + gi;
-            pv[k] = p[ci];
-            xv[k] = P.x[ci];
-          }
-        }
-#pragma unroll
-        for (int k = 0; k < kNL; ++k)
-          if (k < nl) P.x[(size_t)col(k) * P.ld_if + gi] = xv[k] + alph[k] * pv[k];
-      }
-    }
-    if (rb == 0) {
-      for (int k = 0; k < nl; ++k) {
-        double v = 0.0;
-#pragma unroll
-        for (int m = 0; m < kNL; ++m)
-          if (m == k) v = rr[m];   // (constant register index)
-        v = wg_sum(v, red);
-        if (tid == 0) {
-          const int c = col(k);
-          P.rr_part[(size_t)c * P.ld_sub + s] = v;
-          if (s == 0) {
-            P.sc[c].iters = it;
-            P.sc[c].alphas[min(it - 1, kMaxHist - 1)] = alph[k];
-          }
-        }
-      }
+    for (int t = tid; t < ng * nl; t += kRT) {
+      const int k = t / ng, a = t - k * ng;
+      g[(size_t)a * nls + k] = P.gflat[(size_t)col(k) * P.ld_flat + g0 + a];
     }
   }
   if (kMulti && nl < kNL)
@@ -424,14 +443,22 @@ void launch_pcg_matvec_rows(hipStream_t st, const LevelDev& L, int ngmax, const 
     launch_kernel(k_pcg_matvec_rows<false>, rows_grid(L, P), dim3(kRT), lds, st, L, P, u);
 }
 
-void launch_pcg_update_restrict_rows(hipStream_t st, const LevelDev& L, int ngmax, const PcgDev& P, int u) {
+void launch_pcg_update_rows(hipStream_t st, const LevelDev& L, const PcgDev& P, int u) {
+  if (u < 0) throw std::invalid_argument("launch_pcg_update_rows: iterations only");
+  if (P.nrhs > 1)
+    launch_kernel(k_pcg_update_rows<true>, dim3(L.nsub), dim3(kRT), 0, st, L, P, u);
+  else
+    launch_kernel(k_pcg_update_rows<false>, dim3(L.nsub), dim3(kRT), 0, st, L, P, u);
+}
+
+void launch_pcg_restrict_rows(hipStream_t st, const LevelDev& L, int ngmax, const PcgDev& P, int u) {
   const size_t lds = pcg_rows_lds(ngmax, P.nrhs);
   auto go = [&](auto kern) { launch_kernel(kern, rows_grid(L, P), dim3(kRT), lds, st, L, P, u); };
   const bool multi = P.nrhs > 1;
   if (P.prec == 0)
-    multi ? go(k_pcg_update_restrict_rows<0, true>) : go(k_pcg_update_restrict_rows<0, false>);
+    multi ? go(k_pcg_restrict_rows<0, true>) : go(k_pcg_restrict_rows<0, false>);
   else
-    multi ? go(k_pcg_update_restrict_rows<1, true>) : go(k_pcg_update_restrict_rows<1, false>);
+    multi ? go(k_pcg_restrict_rows<1, true>) : go(k_pcg_restrict_rows<1, false>);
 }
 
 }  // namespace bddc

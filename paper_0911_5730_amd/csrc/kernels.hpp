@@ -221,6 +221,7 @@ struct PcgDev {
   double* rz_part[2] = {nullptr, nullptr};   // per level-1 substructure, by iteration parity
   double* qloc = nullptr;                    // local Schur products, level-1 interface flat
   double* da = nullptr;                      // delta T_rr g, level-1 interface flat
+  double* gflat = nullptr;                   // row-block path: g = delta r_k, level-1 interface flat
   const int32_t* phi_ptr = nullptr;          // per interface dof: its row of the delta-weighted
   const int32_t* phi_ids = nullptr;          //   coarse basis of all sharers (coarse ids, weights)
   const double* phi_w = nullptr;
@@ -316,7 +317,8 @@ void launch_weights(hipStream_t st, int nflat, const int32_t* flat_iid, const in
 size_t pcg_rows_lds(int ngmax, int nrhs);
 int pcg_rows_blocks(int ngmax);
 void launch_pcg_matvec_rows(hipStream_t st, const LevelDev& L, int ngmax, const PcgDev& P, int u);
-void launch_pcg_update_restrict_rows(hipStream_t st, const LevelDev& L, int ngmax, const PcgDev& P, int u);
+void launch_pcg_update_rows(hipStream_t st, const LevelDev& L, const PcgDev& P, int u);
+void launch_pcg_restrict_rows(hipStream_t st, const LevelDev& L, int ngmax, const PcgDev& P, int u);
 // local matrices of any size: left-looking blocked elimination with 64 x 64
 // tiles staged in LDS and FP64 MFMA products (k_bigchol.hip)
 void launch_partial_chol_big(hipStream_t st, const LevelDev& L, double* K, double* Wd, int* status);
