@@ -1882,7 +1882,7 @@ static bool plan_wide(bddc_ctx* h) {
   Arena& A = h->wide_arena;
   auto colpad = [](int64_t n) { return (int)(((std::max<int64_t>(n, 1) * 8 + 255) / 256) * 32); };
   const int ldi = colpad(lv.nflat_i), ldg = colpad(lv.nflat_g), ldc = colpad(lv.nflat_c), ldr = colpad(lv.n);
-  double *cy = nullptr, *ct = nullptr, *ca = nullptr, *cv = nullptr, *cb = nullptr, *cr = nullptr;
+  double *cy = nullptr, *ct = nullptr, *ca = nullptr, *cv = nullptr, *cb = nullptr, *cr = nullptr, *ci = nullptr;
   auto lay = [&] {
     W.Kinv = A.take<double>(std::max<int64_t>(1, kioff[nsub]));
     W.kioff = A.take<int64_t>(nsub + 1);
@@ -1896,6 +1896,7 @@ static bool plan_wide(bddc_ctx* h) {
     cv = A.take<double>((size_t)kMaxRhs * ldg);
     cb = A.take<double>((size_t)kMaxRhs * ldc);
     cr = A.take<double>((size_t)kMaxRhs * ldr);
+    ci = A.take<double>((size_t)kMaxRhs * ldi);
   };
   A.reset_sizing();
   lay();
@@ -1920,6 +1921,9 @@ static bool plan_wide(bddc_ctx* h) {
   W.ld_g = ldg;
   W.ld_c = ldc;
   W.ld_r2 = ldr;
+  W.rIf = ci;
+  W.n2 = lv.n;
+  W.nflat_i = lv.nflat_i;
   W.nImax = lv.nImax;
   W.ngmax = lv.ngmax;
   W.rows1 = 8;

@@ -24,6 +24,19 @@ __device__ inline double wide_r2(const WideDev& W, const double* b1, int k) {
   return acc;
 }
 
+// r_2 = the sums of the level-1 coarse contributions, once for every column:
+// at every level-2 dof (r2) and in the interior-flat order of the
+// substructures (rIf); grid (blocks, columns)
+__global__ void __launch_bounds__(kNT) k_wide_gather(WideDev W) {
+  if (W.stop && *W.stop) return;
+  const int c = blockIdx.y;
+  const double* b1 = W.b1 + (size_t)c * W.ld_b1;
+  for (int e = blockIdx.x * kNT + threadIdx.x; e < max(W.n2, W.nflat_i); e += gridDim.x * kNT) {
+    if (e < W.n2) W.r2[(size_t)c * W.ld_r2 + e] = wide_r2(W, b1, e);
+    if (e < W.nflat_i) W.rIf[(size_t)c * W.ld_i + e] = wide_r2(W, b1, W.L.int_gid[e]);
+  }
+}
+
 // grid (chunks, substructures, column groups): rows [chunk*rows1, ...) of
 // [K_II^-1 ; M] applied to the cols1 columns of the group (each operator row
 // read once for all of them; a column's sums are those of a one-column launch)
@@ -64,14 +77,23 @@ __global__ void __launch_bounds__(kNT) k_wide_pre(WideDev W) {
   double* Ly = L.y + (size_t)cb * W.ld_i;
   double* Lt = L.t + (size_t)cb * W.ld_g;
   double* rI = sh;   // column c at rI + c nI
-  for (int idx = tid; idx < R * nI; idx += kNT) {
-    const int c = idx / nI, i = idx - c * nI;
-    const int k = L.int_gid[L.ioff[s] + i];
-    const double v = wide_r2(W, b1 + (size_t)c * W.ld_b1, k);
-    rI[idx] = v;
-    if (chunk == 0) r2[(size_t)c * W.ld_r2 + k] = v;
+  if (W.gathered) {
+    // r_2 gathered by k_wide_gather: the substructure's interior entries
+    const double* rIf = W.rIf + (size_t)cb * W.ld_i + L.ioff[s];
+    for (int idx = tid; idx < R * nI; idx += kNT) {
+      const int c = idx / nI, i = idx - c * nI;
+      rI[idx] = rIf[(size_t)c * W.ld_i + i];
+    }
+  } else {
+    for (int idx = tid; idx < R * nI; idx += kNT) {
+      const int c = idx / nI, i = idx - c * nI;
+      const int k = L.int_gid[L.ioff[s] + i];
+      const double v = wide_r2(W, b1 + (size_t)c * W.ld_b1, k);
+      rI[idx] = v;
+      if (chunk == 0) r2[(size_t)c * W.ld_r2 + k] = v;
+    }
   }
-  if (chunk == 0)
+  if (chunk == 0 && !W.gathered)
     for (int idx = tid; idx < R * ng; idx += kNT) {
       const int c = idx / ng, a = idx - c * ng;
       const int k = L.gam_gid[L.goff[s] + a];
@@ -336,6 +358,12 @@ void launch_wide_pre(hipStream_t st, const WideDev& W) {
     const int f = std::min(4, std::max(1, wgs / 1024));
     V.rows1 = W.rows1 * f;
     V.nchunk1 = (W.nchunk1 + f - 1) / f;
+  }
+  // several columns: r_2 gathered once, not by every workgroup
+  V.gathered = W.nrhs > 1 ? 1 : 0;
+  if (V.gathered) {
+    const int nb = std::max(1, std::min(1024, (std::max(W.n2, W.nflat_i) + kNT - 1) / kNT));
+    launch_kernel(k_wide_gather, dim3(nb, W.nrhs), dim3(kNT), 0, st, V);
   }
   const int groups = (W.nrhs + V.cols1 - 1) / V.cols1;
   launch_kernel(k_wide_pre, dim3(V.nchunk1, V.L.nsub, groups), dim3(kNT),

@@ -201,6 +201,11 @@ struct WideDev {
   int nrhs = 1;
   int cols1 = 1;                      // columns per workgroup of the pre kernel (set at its launch)
   int ld_b1 = 0, ld_r2 = 0, ld_u2 = 0, ld_i = 0, ld_g = 0, ld_c = 0;
+  // several columns: r_2 is gathered once by a launch of its own, into r2
+  // and (interior flat, stride ld_i) rIf, which the pre kernel reads
+  double* rIf = nullptr;
+  int gathered = 0;                   // (set at the pre kernel's launch)
+  int n2 = 0, nflat_i = 0;            // level-2 dofs, interior flat entries
 };
 void launch_wide_ops(hipStream_t st, const LevelDev& L, int nmax_ops, double* Kinv, const int64_t* kioff, double* Mt,
                      const int64_t* moff);
