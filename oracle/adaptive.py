@@ -108,15 +108,19 @@ def pair_eig_full(level, s, t, extra_rows=None):
             r[[pt[int(d)] for d in E]] = -c
             rows.append(r)
     G = np.array(rows).reshape(len(rows), n)
+    # the kernels of the floating substructures' operators (one column per
+    # mode: the constants, or the rigid-body modes of elasticity)
     zcols = []
     if top.sub_floating[s]:
-        zc = np.zeros(n)
-        zc[:len(gs)] = level.z[ds_glob]
-        zcols.append(zc)
+        for m in range(level.z.shape[1]):
+            zc = np.zeros(n)
+            zc[:len(gs)] = level.z[ds_glob, m]
+            zcols.append(zc)
     if top.sub_floating[t]:
-        zc = np.zeros(n)
-        zc[len(gs):] = level.z[dt_glob]
-        zcols.append(zc)
+        for m in range(level.z.shape[1]):
+            zc = np.zeros(n)
+            zc[len(gs):] = level.z[dt_glob, m]
+            zcols.append(zc)
     Z = np.array(zcols).T.reshape(n, len(zcols))
     Pi, Pib = _projections(n, G, Z)
     X = Pi @ IE.T @ S @ IE @ Pi
@@ -166,13 +170,15 @@ def pair_eig_reduced(level, s, t):
     G = np.array(rows).reshape(len(rows), n)
     zcols = []
     if top.sub_floating[s]:
-        zc = np.zeros(n)
-        zc[:nf] = level.z[F]
-        zcols.append(zc)
+        for m in range(level.z.shape[1]):
+            zc = np.zeros(n)
+            zc[:nf] = level.z[F, m]
+            zcols.append(zc)
     if top.sub_floating[t]:
-        zc = np.zeros(n)
-        zc[nf:] = level.z[F]
-        zcols.append(zc)
+        for m in range(level.z.shape[1]):
+            zc = np.zeros(n)
+            zc[nf:] = level.z[F, m]
+            zcols.append(zc)
     Z = np.array(zcols).T.reshape(n, len(zcols))
     Pi, Pib = _projections(n, G, Z)
     X = Pi @ IE.T @ Snum @ IE @ Pi

@@ -67,7 +67,7 @@ class Level:
         self.elems = elems
         self.elem_sub = np.asarray(elem_sub)
         self.nsub = nsub
-        self.z = z
+        self.z = np.asarray(z).reshape(n, -1)   # the kernel's modes (columns) on the level's dofs
         self.A = assemble_elements(n, elems)
         self.topo = classify(n, elems, self.elem_sub, nsub, np.asarray(elem_floating))
         self._local_matrices()
@@ -160,7 +160,7 @@ class Level:
             self.kkt.append(lu)
             self.Psi.append(Psi)
             self.Ac.append(Psi.T @ self.K[s] @ Psi)
-        self.z_next = np.array([w @ self.z[d] for d, w in func])
+        self.z_next = np.array([w @ self.z[d] for d, w in func]).reshape(len(func), self.z.shape[1])
 
     def local_solve(self, s: int, g: np.ndarray) -> np.ndarray:
         """w in W_Delta,s: min 1/2 w^T K_s w - g^T w subject to C_s w = 0 (eq. ML-wDi)."""
@@ -200,12 +200,12 @@ class BDDC:
         nx, ny = prob.nx, prob.ny
         self.A = fem.assemble(nx, ny, prob.coeff, prob.element)
         elems, touches = fem.level1_elements(nx, ny, prob.coeff, prob.element)
-        n = (nx - 1) * (ny - 1)
+        n = fem.n_free(nx, ny, prob.element)
         self.levels: List[Level] = []
         self.eigs = []                       # per level: {(s,t): lambdas}
         self.edge_Q = []                     # per level: {(s,t): orthonormal constraint columns}
         self.omega_levels = []               # per level: max_st lambda_{n+1}
-        cur = Level(1, n, elems, prob.part, prob.nsub, ~touches, np.ones(n))
+        cur = Level(1, n, elems, prob.part, prob.nsub, ~touches, fem.null_modes(nx, ny, prob.element))
         from . import adaptive
         for ell in range(1, self.L):
             if all_interface_corners and ell == 1:

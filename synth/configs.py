@@ -45,7 +45,7 @@ class Problem:
 
     @property
     def n_free(self) -> int:
-        return (self.nx - 1) * (self.ny - 1)
+        return (2 if self.element == "Q1E" else 1) * (self.nx - 1) * (self.ny - 1)
 
 
 def square_partition(nx: int, ny: int, nsx: int, nsy: int) -> np.ndarray:
@@ -124,7 +124,7 @@ def square_problem(nx: int, nsx: int, *, ny: Optional[int] = None, nsy: Optional
     ch = add_channels(rng, nx, ny, coeff, count=channels) if channels else []
     part = square_partition(nx, ny, nsx, nsy)
     agg = _levels_agglom(nsx, nsy, levels, groups)
-    nfree = (nx - 1) * (ny - 1)
+    nfree = (2 if element == "Q1E" else 1) * (nx - 1) * (ny - 1)
     f = rng.uniform(-1.0, 1.0, size=(nrhs, nfree))
     return Problem(nx=nx, ny=ny, coeff=coeff, part=part, nsub=nsx * nsy, levels=levels,
                    agglom=agg, constraints=constraints, tau=tau, f=f, element=element,

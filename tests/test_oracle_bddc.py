@@ -441,3 +441,53 @@ def test_voronoi_partition_spectrum_and_adaptive_target(seed):
     assert eva[0] >= 1.0 - 1e-10
     assert eva[-1] <= _brute_omega(Ba.levels[0]) * (1 + 1e-8)
     assert eva[-1] <= ev[-1] + 1e-9
+
+
+# ---------------------------------------------------------------- elasticity (NEXT-4)
+def test_elasticity_two_level_spectrum_bounds_and_direct_solution():
+    """Plane-strain elasticity (two dofs per node, the paper's experiment): the
+    same Lemma holds -- lambda_min(M^-1 A) >= 1 and lambda_max = omega for two
+    levels -- corners carry both components, so a floating substructure's
+    three rigid modes are constrained; PCG reaches the direct solution."""
+    p = tiny("corners", element="Q1E")
+    B = BDDC(p)
+    assert B.A.shape[0] == 2 * (p.nx - 1) * (p.ny - 1) == p.n_free
+    ev = _dense_MA_eigs(B)
+    assert ev[0] >= 1.0 - 1e-10
+    om = _brute_omega(B.levels[0])
+    assert abs(ev[-1] - om) <= 1e-8 * om
+    out = pcg.solve(B, p.f[0], rtol=1e-12)
+    xs = spla.spsolve(B.A.tocsc(), p.f[0])
+    assert pcg.energy_error(B.A, out["x"], xs) < 1e-10
+
+
+def test_elasticity_exact_cases():
+    p = tiny("corners", element="Q1E")
+    B = BDDC(p, all_interface_corners=True)
+    Minv = B.dense_preconditioner()
+    Ainv = np.linalg.inv(B.A.toarray())
+    assert np.abs(Minv - Ainv).max() <= 1e-11 * np.abs(Ainv).max()
+    p = tiny("adaptive", tau=1e-6, element="Q1E")
+    out = pcg.solve(BDDC(p), p.f[0], rtol=1e-10)
+    assert out["iters"] <= 1
+    p = tiny("corners", nx=16, ns=4, levels=3, groups=(1, 1), element="Q1E")
+    M3 = BDDC(p).dense_preconditioner()
+    M2 = BDDC(p, levels=2).dense_preconditioner()
+    assert np.abs(M3 - M2).max() <= 1e-11 * np.abs(M2).max()
+
+
+def test_elasticity_adaptive_setup_meets_target():
+    """Theorem "adaptive" on elasticity, three levels: every level's omega <= tau,
+    the indicator <= tau^(L-1), and the spectrum within the product of the
+    levels' omegas (computed by brute force)."""
+    tau = 3.0
+    p = tiny("adaptive", nx=16, ns=4, levels=3, groups=(2, 2), tau=tau, seed=3, element="Q1E")
+    B = BDDC(p)
+    assert all(w <= tau for w in B.omega_levels)
+    assert B.indicator <= tau ** (p.levels - 1)
+    ev = _dense_MA_eigs(B)
+    assert ev[0] >= 1.0 - 1e-10
+    om = [_brute_omega(lv) for lv in B.levels]
+    assert ev[-1] <= np.prod(om) * (1 + 1e-10)
+    Bc = BDDC(p, constraints="corners")
+    assert _dense_MA_eigs(Bc)[-1] > ev[-1]

@@ -71,3 +71,96 @@ def test_element_dofs_layout():
     assert list(d[1 * nx + 1]) == [0, 1, 4, 3]
     # the corner element touches three Dirichlet nodes
     assert list(d[0]) == [-1, -1, 0, -1]
+
+
+# ---------------------------------------------------------------- elasticity (the paper's experiments)
+def _rigid_modes(hx, hy):
+    x = np.array([0.0, hx, hx, 0.0])
+    y = np.array([0.0, 0.0, hy, hy])
+    tx = np.zeros(8)
+    tx[0::2] = 1.0
+    ty = np.zeros(8)
+    ty[1::2] = 1.0
+    rot = np.zeros(8)                    # u = (-y, x): an infinitesimal rotation
+    rot[0::2] = -y
+    rot[1::2] = x
+    return x, y, [tx, ty, rot]
+
+
+@pytest.mark.parametrize("hx,hy", [(0.25, 0.25), (0.5, 0.2)])
+def test_elastic_element_null_space_is_the_rigid_modes(hx, hy):
+    K = fem.q1_elastic_element_matrix(hx, hy)
+    assert np.allclose(K, K.T, atol=1e-14)
+    _, _, Z = _rigid_modes(hx, hy)
+    for z in Z:
+        assert np.abs(K @ z).max() <= 1e-13 * np.abs(K).max()
+    ev = np.linalg.eigvalsh(K)
+    assert np.sum(ev > 1e-10 * ev[-1]) == 5      # 8 dofs - 3 rigid modes
+    assert ev[0] >= -1e-13 * ev[-1]
+
+
+@pytest.mark.parametrize("hx,hy", [(0.25, 0.25), (0.5, 0.2)])
+def test_elastic_element_energy_of_linear_and_bilinear_fields(hx, hy):
+    """Bilinear elements hold every linear field exactly, so u^T K u is the
+    exact strain energy int eps : C eps: for a constant strain (e_xx, e_yy,
+    gamma) it is (e^T D e) hx hy with plane-strain D (lambda = 1, mu = 2);
+    u = (x y, 0) is bilinear too: eps_xx = y, gamma = x."""
+    lam, mu = fem.LAME_LAMBDA, fem.LAME_MU
+    K = fem.q1_elastic_element_matrix(hx, hy)
+    x, y, _ = _rigid_modes(hx, hy)
+    D = np.array([[lam + 2 * mu, lam, 0.0], [lam, lam + 2 * mu, 0.0], [0.0, 0.0, mu]])
+    rng = np.random.default_rng(3)
+    for _ in range(4):
+        a, b, c, d = rng.standard_normal(4)     # u = (a x + b y, c x + d y)
+        u = np.zeros(8)
+        u[0::2] = a * x + b * y
+        u[1::2] = c * x + d * y
+        e = np.array([a, d, b + c])
+        assert np.isclose(u @ K @ u, e @ D @ e * hx * hy, rtol=1e-13)
+    u = np.zeros(8)
+    u[0::2] = x * y
+    ref = (lam + 2 * mu) * hx * hy**3 / 3.0 + mu * hy * hx**3 / 3.0
+    assert np.isclose(u @ K @ u, ref, rtol=1e-13)
+
+
+def test_elastic_patch_test_reproduces_a_linear_field():
+    """Clamp the boundary nodes of a 7 x 5 grid of one material to a linear
+    displacement field and solve for the interior (no body force): the FE
+    solution is that field at every interior node.  Also checks the assembly
+    of the free dofs (two per node, 2 f + c), with element-wise coefficients,
+    against the all-node matrix built here."""
+    nx, ny = 7, 5
+    hx, hy = 1.0 / nx, 1.0 / ny
+    Ke = fem.q1_elastic_element_matrix(hx, hy)
+    nn = (nx + 1) * (ny + 1)
+
+    def full_matrix(kcoef):
+        full = np.zeros((2 * nn, 2 * nn))
+        for j in range(ny):
+            for i in range(nx):
+                nodes = [j * (nx + 1) + i, j * (nx + 1) + i + 1, (j + 1) * (nx + 1) + i + 1,
+                         (j + 1) * (nx + 1) + i]
+                dof = np.ravel([[2 * a, 2 * a + 1] for a in nodes])
+                full[np.ix_(dof, dof)] += kcoef[j * nx + i] * Ke
+        return full
+    X, Y = np.meshgrid(np.arange(nx + 1) * hx, np.arange(ny + 1) * hy)
+    X, Y = X.ravel(), Y.ravel()
+    ulin = np.zeros(2 * nn)
+    ulin[0::2] = 0.3 + 1.5 * X - 0.7 * Y
+    ulin[1::2] = -0.2 + 0.4 * X + 2.0 * Y
+    interior = np.zeros(nn, dtype=bool)
+    for j in range(1, ny):
+        for i in range(1, nx):
+            interior[j * (nx + 1) + i] = True
+    I = np.ravel([[2 * a, 2 * a + 1] for a in np.nonzero(interior)[0]])
+    B = np.setdiff1d(np.arange(2 * nn), I)
+    # the oracle's free-dof matrix is the interior block, in the same order
+    kvar = 10.0 ** np.random.default_rng(5).uniform(0, 2, nx * ny)
+    A = fem.assemble(nx, ny, kvar, "Q1E").toarray()
+    assert A.shape == (len(I), len(I))
+    assert np.abs(A - full_matrix(kvar)[np.ix_(I, I)]).max() <= 1e-12 * np.abs(A).max()
+    kone = np.full(nx * ny, 3.0)
+    full = full_matrix(kone)
+    A = fem.assemble(nx, ny, kone, "Q1E").toarray()
+    uI = np.linalg.solve(A, -full[np.ix_(I, B)] @ ulin[B])
+    assert np.abs(uI - ulin[I]).max() <= 1e-12
