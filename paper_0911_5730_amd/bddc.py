@@ -22,7 +22,7 @@ MAX_LEVELS = 8
 STATUS = {0: "BDDC_OK", -1: "BDDC_EINVAL", -2: "BDDC_ENOMEM", -3: "BDDC_ESINGULAR",
           -4: "BDDC_EPARTITION", -5: "BDDC_ENOCONV", -6: "BDDC_EDEVICE", -7: "BDDC_EBUSY",
           -8: "BDDC_EUNSUPPORTED"}
-ELEMENT = {"Q1": 0, "P1": 1}
+ELEMENT = {"Q1": 0, "P1": 1, "Q1E": 2}   # Q1E: plane elasticity, two dofs per node
 CONSTRAINTS = {"corners": 0, "corners_edges": 1, "adaptive": 2}
 PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2}
 
@@ -219,7 +219,7 @@ class Solver:
         _check(self.lib.bddc_setup(ctypes.byref(m.c), ctypes.c_void_p(_stream_ptr(stream)), ctypes.byref(h)),
                "bddc_setup")
         self.h = h
-        self.n_free = (prob.nx - 1) * (prob.ny - 1)
+        self.n_free = (2 if prob.element == "Q1E" else 1) * (prob.nx - 1) * (prob.ny - 1)
         self.levels = prob.levels
 
     def close(self):

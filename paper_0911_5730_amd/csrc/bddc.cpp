@@ -336,6 +336,45 @@ std::vector<T> prefix(const std::vector<T>& cnt) {
   return p;
 }
 
+int dofs_per_node(int element) { return element == BDDC_Q1_ELASTIC ? 2 : 1; }
+
+// Plane-strain elasticity (Section 6: lambda = 1, mu = 2) on an hx x hy
+// rectangle, bilinear displacements: K = int B^T D B with strains (e_xx,
+// e_yy, g_xy) and D the plane-strain stiffness, by the tensor 2-point Gauss
+// rule (exact for these integrands).  Dof 2 q + c is component c of local
+// node q (CCW from (i,j)); row-major 8 x 8.
+Khat64 elastic_element_matrix(int nx, int ny) {
+  const double lam = 1.0, mu = 2.0;
+  const double hx = 1.0 / nx, hy = 1.0 / ny;
+  const double Dm[3][3] = {{lam + 2 * mu, lam, 0.0}, {lam, lam + 2 * mu, 0.0}, {0.0, 0.0, mu}};
+  const double gp[2] = {0.5 - 0.5 / std::sqrt(3.0), 0.5 + 0.5 / std::sqrt(3.0)};
+  const double xq[4] = {0, 1, 1, 0}, yq[4] = {0, 0, 1, 1};   // local node positions on the unit square
+  Khat64 k{};
+  for (double xi : gp)
+    for (double eta : gp) {
+      double B[3][8] = {};
+      for (int q = 0; q < 4; ++q) {
+        // bilinear shape function of node q: (xq ? xi : 1 - xi) (yq ? eta : 1 - eta)
+        const double fx = xq[q] ? xi : 1.0 - xi, fy = yq[q] ? eta : 1.0 - eta;
+        const double dx = (xq[q] ? 1.0 : -1.0) * fy / hx;   // d/dx
+        const double dy = (yq[q] ? 1.0 : -1.0) * fx / hy;   // d/dy
+        B[0][2 * q] = dx;
+        B[1][2 * q + 1] = dy;
+        B[2][2 * q] = dy;
+        B[2][2 * q + 1] = dx;
+      }
+      const double w = 0.25 * hx * hy;
+      for (int a = 0; a < 8; ++a)
+        for (int b = 0; b < 8; ++b) {
+          double acc = 0.0;
+          for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) acc += B[i][a] * Dm[i][j] * B[j][b];
+          k.v[a * 8 + b] += w * acc;
+        }
+    }
+  return k;
+}
+
 // reference element matrices (k = 1) of an hx x hy rectangle, local nodes
 // (i,j), (i+1,j), (i+1,j+1), (i,j+1)
 Khat16 element_matrix(int element, int nx, int ny) {
@@ -524,11 +563,14 @@ static void validate(const bddc_problem* p) {
   if (!p) fail(BDDC_EINVAL, "problem is NULL");
   if (p->nx < 2 || p->ny < 2) fail(BDDC_EINVAL, "nx and ny must be >= 2");
   if ((int64_t)p->nx * p->ny > (int64_t)1 << 30) fail(BDDC_EUNSUPPORTED, "mesh too large");
-  if (p->element != BDDC_Q1 && p->element != BDDC_P1) fail(BDDC_EINVAL, "unknown element");
+  if (p->element != BDDC_Q1 && p->element != BDDC_P1 && p->element != BDDC_Q1_ELASTIC)
+    fail(BDDC_EINVAL, "unknown element");
   if ((!p->coeff && !p->coeff_device) || !p->part) fail(BDDC_EINVAL, "coeff and part are required");
   if (p->nsub < 1) fail(BDDC_EINVAL, "nsub must be >= 1");
   if (p->levels < 2 || p->levels > BDDC_MAX_LEVELS) fail(BDDC_EINVAL, "levels must be in [2, 8]");
   if (p->constraints < 0 || p->constraints > 2) fail(BDDC_EINVAL, "unknown constraint kind");
+  if (p->element == BDDC_Q1_ELASTIC && p->constraints == BDDC_ADAPTIVE)
+    fail(BDDC_EUNSUPPORTED, "the adaptive constraints are not built for elasticity");
   if (std::isnan(p->tau) || p->tau < 0) fail(BDDC_EINVAL, "tau must be >= 0");
   if (p->precision != BDDC_FP64 && p->precision != BDDC_FP32 && p->precision != BDDC_BF16)
     fail(BDDC_EINVAL, "unknown precision");
@@ -798,6 +840,7 @@ class Builder {
     auto lv = std::make_unique<Level>();
     lv->ell = 1;
     lv->topo = classify_grid(p_->nx, p_->ny, p_->part, p_->nsub, &G);
+    expand_node_topology(lv->topo, &G, dofs_per_node(p_->element));
     clk.lap("classify l1");
     layout_level(*lv);
     check_limits(*lv);
@@ -877,6 +920,7 @@ class Builder {
     // level-1 assembly maps (from the grid classification)
     std::vector<int32_t> node_el, sub_el_ptr, el_gid, el_loc;
     std::vector<int32_t> child_ptr, child_id, child_map_off, child_map;
+    const int pe = G ? G->per_el : 4;   // element dofs in el_loc
     if (G) {
       node_el.swap(G->node_el);
       sub_el_ptr.swap(G->sub_el_ptr);
@@ -948,12 +992,12 @@ class Builder {
             const int n = T.nloc(s), nI = T.n_int[s];
             f.assign(n, INT32_MAX);
             for (int k = sub_el_ptr[s]; k < sub_el_ptr[s + 1]; ++k) {
-              const int32_t* loc = &el_loc[(size_t)k * 4];
+              const int32_t* loc = &el_loc[(size_t)k * pe];
               int mn = INT32_MAX;
-              for (int q = 0; q < 4; ++q)
+              for (int q = 0; q < pe; ++q)
                 if (loc[q] >= 0 && loc[q] < nI) mn = std::min(mn, (int)loc[q]);
               if (mn == INT32_MAX) continue;
-              for (int q = 0; q < 4; ++q)
+              for (int q = 0; q < pe; ++q)
                 if (loc[q] >= 0) f[loc[q]] = std::min(f[loc[q]], mn);
             }
             const int nbI = (nI + kT - 1) / kT;
@@ -1016,12 +1060,12 @@ class Builder {
             const int n = T.nloc(s), nI = T.n_int[s];
             f.assign(n, INT32_MAX);
             for (int k = sub_el_ptr[s]; k < sub_el_ptr[s + 1]; ++k) {
-              const int32_t* loc = &el_loc[(size_t)k * 4];
+              const int32_t* loc = &el_loc[(size_t)k * pe];
               int mn = INT32_MAX;
-              for (int q = 0; q < 4; ++q)
+              for (int q = 0; q < pe; ++q)
                 if (loc[q] >= 0 && loc[q] < nI) mn = std::min(mn, (int)loc[q]);
               if (mn == INT32_MAX) continue;
-              for (int q = 0; q < 4; ++q)
+              for (int q = 0; q < pe; ++q)
                 if (loc[q] >= 0) f[loc[q]] = std::min(f[loc[q]], mn);
             }
             int32_t* e = &srend[srendoff[s]];
@@ -1202,6 +1246,13 @@ class Builder {
   }
 
   void assemble_l1(Level& lv) {
+    if (p_->element == BDDC_Q1_ELASTIC) {
+      const Khat64 kh = elastic_element_matrix(h_->nx, h_->ny);
+      launch_assemble_l1_elastic(st_, lv.nsub, lv.d.koff, lv.d.loc_ptr, lv.d.nint, lv.d.node_el, lv.d.sub_el_ptr,
+                                 lv.d.el_gid, lv.d.el_loc, lv.d.coeff, kh, lv.d.K, lv.d.diagK, lv.d.goff,
+                                 h_->status);
+      return;
+    }
     const Khat16 kh = element_matrix(p_->element, h_->nx, h_->ny);
     launch_assemble_l1(st_, lv.nsub, lv.d.koff, lv.d.loc_ptr, lv.d.nint, lv.d.node_el, lv.d.sub_el_ptr,
                        lv.d.el_gid, lv.d.el_loc, lv.d.coeff, kh, lv.d.K, lv.d.diagK, lv.d.goff, h_->status);
@@ -2530,11 +2581,12 @@ bddc_status bddc_plan(const bddc_problem* p, bddc_info* info) {
     } else {
       lv.topo = classify_grid(p->nx, p->ny, p->part, p->nsub, nullptr);
     }
+    expand_node_topology(lv.topo, nullptr, dofs_per_node(p->element));
     clk.lap("classify");
     layout_level(lv);
     clk.lap("layout");
     std::memset(info, 0, sizeof(*info));
-    info->n_free = (int64_t)(p->nx - 1) * (p->ny - 1);
+    info->n_free = (int64_t)dofs_per_node(p->element) * (p->nx - 1) * (p->ny - 1);
     info->levels = p->levels;
     fill_level_info(lv, 0, info);
     // device bytes a set-up will hold, from the level-1 sizes: the dense local
@@ -2629,7 +2681,7 @@ bddc_status bddc_setup(const bddc_problem* p, void* hip_stream, bddc_handle* out
     h->constraints = p->constraints;
     h->precision = p->precision;
     h->tau = p->tau;
-    h->n_free = (int64_t)(p->nx - 1) * (p->ny - 1);
+    h->n_free = (int64_t)dofs_per_node(p->element) * (p->nx - 1) * (p->ny - 1);
     h->stream = reinterpret_cast<hipStream_t>(hip_stream);
     BDDC_HIP(hipGetDevice(&h->device));
     HostClock clk;

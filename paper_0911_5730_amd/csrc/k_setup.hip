@@ -19,11 +19,14 @@ namespace bddc {
 // K_s = sum over the elements of s of k_e * Khat.  Thread a owns row a, so the
 // accumulation order is fixed and no atomics are needed.  The interface part
 // of the diagonal is kept for the stiffness-scaling weights.
+// kM element dofs (4 nodes, or 8: two components per node), kBits bits of
+// element position in the node_el codes
+template <int kM, int kBits, class KH>
 __global__ void __launch_bounds__(kNT) k_assemble_l1(
     const int64_t* __restrict__ koff, const int32_t* __restrict__ loc_ptr,
     const int32_t* __restrict__ nint, const int32_t* __restrict__ node_el,
     const int32_t* __restrict__ sub_el_ptr, const int32_t* __restrict__ el_gid,
-    const int32_t* __restrict__ el_loc, const double* __restrict__ coeff, Khat16 khat,
+    const int32_t* __restrict__ el_loc, const double* __restrict__ coeff, KH khat,
     double* __restrict__ K, double* __restrict__ diagK, const int32_t* __restrict__ goff, int* status) {
   const int s = blockIdx.x;
   const int base = loc_ptr[s];
@@ -36,13 +39,13 @@ __global__ void __launch_bounds__(kNT) k_assemble_l1(
     for (int k = 0; k < 4; ++k) {
       const int code = node_el[(size_t)(base + a) * 4 + k];
       if (code < 0) continue;
-      const int le = code >> 2, pos = code & 3;
+      const int le = code >> kBits, pos = code & ((1 << kBits) - 1);
       const double kk = coeff[el_gid[e0 + le]];
       if (!(kk > 0.0 && kk < 1e308)) atomicOr(status, 2);   // check of device-resident input
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int b = el_loc[(size_t)(e0 + le) * 4 + q];
-        if (b >= 0) A[a + (size_t)b * n] += kk * khat.v[pos * 4 + q];
+      for (int q = 0; q < kM; ++q) {
+        const int b = el_loc[(size_t)(e0 + le) * kM + q];
+        if (b >= 0) A[a + (size_t)b * n] += kk * khat.v[pos * kM + q];
       }
     }
     if (a >= nint[s]) diagK[goff[s] + a - nint[s]] = A[a + (size_t)a * n];
@@ -386,8 +389,15 @@ void launch_assemble_l1(hipStream_t st, int nsub, const int64_t* koff, const int
                         const int32_t* nint, const int32_t* node_el, const int32_t* sub_el_ptr,
                         const int32_t* el_gid, const int32_t* el_loc, const double* coeff,
                         const Khat16& khat, double* K, double* diagK, const int32_t* goff, int* status) {
-  launch_kernel(k_assemble_l1, dim3(nsub), dim3(kNT), 0, st, koff, loc_ptr, nint, node_el,
-                     sub_el_ptr, el_gid, el_loc, coeff, khat, K, diagK, goff, status);
+  launch_kernel(k_assemble_l1<4, 2, Khat16>, dim3(nsub), dim3(kNT), 0, st, koff, loc_ptr, nint, node_el,
+                sub_el_ptr, el_gid, el_loc, coeff, khat, K, diagK, goff, status);
+}
+void launch_assemble_l1_elastic(hipStream_t st, int nsub, const int64_t* koff, const int32_t* loc_ptr,
+                                const int32_t* nint, const int32_t* node_el, const int32_t* sub_el_ptr,
+                                const int32_t* el_gid, const int32_t* el_loc, const double* coeff,
+                                const Khat64& khat, double* K, double* diagK, const int32_t* goff, int* status) {
+  launch_kernel(k_assemble_l1<8, 3, Khat64>, dim3(nsub), dim3(kNT), 0, st, koff, loc_ptr, nint, node_el,
+                sub_el_ptr, el_gid, el_loc, coeff, khat, K, diagK, goff, status);
 }
 
 void launch_assemble_coarse(hipStream_t st, int nsub, const int64_t* koff, const int32_t* loc_ptr,

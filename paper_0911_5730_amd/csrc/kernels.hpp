@@ -38,6 +38,9 @@ inline void launch_kernel(void (*k)(P...), dim3 grid, dim3 block, size_t shm, hi
 struct Khat16 {
   double v[16];   // 4x4 reference element matrix (k = 1), row-major, local node order CCW from (i,j)
 };
+struct Khat64 {
+  double v[64];   // 8x8 elasticity element matrix (k = 1), row-major, dof 2 q + c of local node q
+};
 
 // Everything an apply kernel needs about one level, by value.
 struct LevelDev {
@@ -311,6 +314,11 @@ void launch_assemble_l1(hipStream_t st, int nsub, const int64_t* koff, const int
                         const int32_t* nint, const int32_t* node_el, const int32_t* sub_el_ptr,
                         const int32_t* el_gid, const int32_t* el_loc, const double* coeff,
                         const Khat16& khat, double* K, double* diagK, const int32_t* goff, int* status);
+// the same for plane elasticity: eight element dofs (node_el codes with three position bits)
+void launch_assemble_l1_elastic(hipStream_t st, int nsub, const int64_t* koff, const int32_t* loc_ptr,
+                                const int32_t* nint, const int32_t* node_el, const int32_t* sub_el_ptr,
+                                const int32_t* el_gid, const int32_t* el_loc, const double* coeff,
+                                const Khat64& khat, double* K, double* diagK, const int32_t* goff, int* status);
 void launch_assemble_coarse(hipStream_t st, int nsub, const int64_t* koff, const int32_t* loc_ptr,
                             const int32_t* nint, const int32_t* child_ptr, const int32_t* child_id,
                             const int32_t* child_map_off, const int32_t* child_map, const double* Ac,

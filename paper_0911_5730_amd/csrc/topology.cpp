@@ -374,4 +374,73 @@ Topology classify_grid(int nx, int ny, const int32_t* part, int nsub, GridMaps* 
   return T;
 }
 
+void expand_node_topology(Topology& T, GridMaps* maps, int dpn) {
+  if (dpn == 1) return;
+  const int nn = T.n;
+  Topology D;
+  D.n = dpn * nn;
+  D.nsub = T.nsub;
+  D.nshare.resize(D.n);
+  D.share_.reset(new int32_t[(size_t)std::max(D.n, 1) * kMaxShare]);
+  D.is_corner.resize(D.n);
+  for (int d = 0; d < nn; ++d)
+    for (int c = 0; c < dpn; ++c) {
+      const int e = dpn * d + c;
+      D.nshare[e] = T.nshare[d];
+      for (int k = 0; k < kMaxShare; ++k) D.share_[(size_t)e * kMaxShare + k] = T.share(d)[k];
+      D.is_corner[e] = T.is_corner[d];
+    }
+  D.floating = T.floating;
+  auto scale = [&](const std::vector<int32_t>& v) {
+    std::vector<int32_t> o(v.size());
+    for (size_t i = 0; i < v.size(); ++i) o[i] = dpn * v[i];
+    return o;
+  };
+  auto spread = [&](const std::vector<int32_t>& v) {   // node list -> dof list, components in order
+    std::vector<int32_t> o;
+    o.reserve(v.size() * dpn);
+    for (int32_t d : v)
+      for (int c = 0; c < dpn; ++c) o.push_back(dpn * d + c);
+    return o;
+  };
+  D.loc_ptr = scale(T.loc_ptr);
+  D.loc_dof = spread(T.loc_dof);
+  D.n_int = scale(T.n_int);
+  D.n_r = scale(T.n_r);
+  D.n_c = scale(T.n_c);
+  D.corners = spread(T.corners);
+  D.edge_s = T.edge_s;
+  D.edge_t = T.edge_t;
+  D.edge_ptr = scale(T.edge_ptr);
+  D.edge_dof = spread(T.edge_dof);
+  D.n_interface = dpn * T.n_interface;
+  T = std::move(D);
+  if (!maps) return;
+  GridMaps& M = *maps;
+  const int q0 = M.per_el;
+  const size_t ne = M.el_gid.size();
+  std::vector<int32_t> el_loc(ne * q0 * dpn, -1);
+  for (size_t e = 0; e < ne; ++e)
+    for (int q = 0; q < q0; ++q) {
+      const int a = M.el_loc[e * q0 + q];
+      for (int c = 0; c < dpn; ++c) el_loc[(e * q0 + q) * dpn + c] = a >= 0 ? dpn * a + c : -1;
+    }
+  int bits = 0;
+  while ((1 << bits) < q0 * dpn) ++bits;
+  const size_t nloc = M.node_el.size() / 4;
+  std::vector<int32_t> node_el(nloc * dpn * 4, -1);
+  for (size_t a = 0; a < nloc; ++a)
+    for (int c = 0; c < dpn; ++c)
+      for (int k = 0; k < 4; ++k) {
+        const int code = M.node_el[a * 4 + k];
+        if (code < 0) continue;
+        const int le = code >> M.pos_bits, q = code & ((1 << M.pos_bits) - 1);
+        node_el[((a * dpn + c) * 4) + k] = (le << bits) | (q * dpn + c);
+      }
+  M.el_loc.swap(el_loc);
+  M.node_el.swap(node_el);
+  M.per_el = q0 * dpn;
+  M.pos_bits = bits;
+}
+
 }  // namespace bddc

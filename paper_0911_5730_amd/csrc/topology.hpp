@@ -65,6 +65,8 @@ void classify_rules(Topology& T, const std::vector<int32_t>& raw_ptr, const std:
 // -1 padded, elements in ascending id).
 struct GridMaps {
   std::vector<int32_t> sub_el_ptr, el_gid, el_loc, node_el;
+  int per_el = 4;      // entries of el_loc per element (element dofs)
+  int pos_bits = 2;    // node_el entries: (local element << pos_bits) | position in the element
 };
 
 // Level 1 on the nx x ny element grid of the unit square with zero Dirichlet
@@ -74,5 +76,13 @@ struct GridMaps {
 // elements, so everything is computed node by node; each substructure's dofs
 // are taken in ascending id.  Same rules and errors as classify; maps may be null.
 Topology classify_grid(int nx, int ny, const int32_t* part, int nsub, GridMaps* maps);
+
+// Vector problems with dpn dofs per node (plane elasticity: dpn = 2): the
+// node topology of classify_grid turned into the dof topology in place --
+// node d becomes dofs dpn d .. dpn d + dpn - 1 with its sharers, its class
+// (interior, edge, corner) and its place in each local ordering; the maps
+// list the element dofs node by node (position dpn q + c for component c of
+// the element's node q).
+void expand_node_topology(Topology& T, GridMaps* maps, int dpn);
 
 }  // namespace bddc

@@ -49,7 +49,7 @@ def test_status_strings():
 
 
 def _oracle_counts(prob):
-    dofs = fem.element_dofs(prob.nx, prob.ny)
+    dofs = fem.element_dofs(prob.nx, prob.ny, prob.element)
     elems = [(d[d >= 0], None) for d in dofs]
     touches = (dofs < 0).any(axis=1)
     top = classify(prob.n_free, elems, prob.part, prob.nsub, ~touches)
@@ -71,6 +71,26 @@ def test_plan_topology_matches_oracle(case):
     assert got["n_free"] == prob.n_free
     for k, v in want.items():
         assert got[k] == v, (k, got[k], v)
+
+
+@pytest.mark.parametrize("case", [dict(nx=24, nsx=3), dict(nx=26, nsx=4), dict(nx=20, ny=12, nsx=5, nsy=3)])
+def test_plan_topology_matches_oracle_elasticity(case):
+    """Plane elasticity: two dofs per free node (2 f + c); the host's dof
+    topology (node classes expanded to both components) against the oracle's
+    classification of the elasticity element dofs."""
+    prob = synth.square_problem(case["nx"], case["nsx"], ny=case.get("ny"), nsy=case.get("nsy"), element="Q1E")
+    got = P.plan(prob)
+    want = _oracle_counts(prob)
+    assert got["n_free"] == prob.n_free == 2 * (prob.nx - 1) * (prob.ny - 1)
+    for k, v in want.items():
+        assert got[k] == v, (k, got[k], v)
+
+
+def test_elasticity_refuses_adaptive_constraints():
+    prob = synth.square_problem(24, 3, element="Q1E", constraints="adaptive", tau=2.0)
+    with pytest.raises(P.BDDCError) as e:
+        P.plan(prob)
+    assert e.value.name == "BDDC_EUNSUPPORTED"
 
 
 def test_plan_promotes_corner_for_island():

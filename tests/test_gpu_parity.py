@@ -61,12 +61,22 @@ def _case(name):
                                 kmode="loguniform", kmax_exp=3, channels=1, seed=36),
         "ce4": lambda: sq(64, 16, levels=4, groups=(8, 8), constraints="corners_edges", kmode="loguniform",
                           kmax_exp=2, seed=36),
+        # plane elasticity (two dofs per node; lambda = 1, mu = 2 scaled by k):
+        # the paper's 48 x 48 mesh on a 3 x 3 partition (H/h = 16), a
+        # coefficient-jump case, edge averages, and three levels
+        "elastic_paper": lambda: sq(48, 3, element="Q1E", seed=41),
+        "elastic_kjump": lambda: sq(24, 3, element="Q1E", kmode="loguniform", kmax_exp=2, seed=42),
+        "elastic_ce": lambda: sq(26, 4, constraints="corners_edges", element="Q1E", kmode="loguniform",
+                                 kmax_exp=1, seed=43),
+        "elastic3": lambda: sq(48, 6, levels=3, groups=(3, 3), element="Q1E", kmode="loguniform", kmax_exp=2,
+                               seed=44),
     }[name]()
 
 
 CASES = ["config1", "corners_kjump", "ce_ragged", "rect", "p1", "adaptive2", "adaptive3", "adaptive3_h16",
          "corners3", "single_sub", "adaptive2_h32", "voronoi2", "voronoi_adaptive2", "voronoi_adaptive3",
-         "voronoi_adaptive3_large", "voronoi_jitter3", "adaptive4", "ce4"]
+         "voronoi_adaptive3_large", "voronoi_jitter3", "adaptive4", "ce4",
+         "elastic_paper", "elastic_kjump", "elastic_ce", "elastic3"]
 
 
 @pytest.mark.parametrize("name", CASES)
