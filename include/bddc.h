@@ -53,8 +53,10 @@ typedef enum {
  * parameters lambda = 1, mu = 2, here scaled by coeff per element), Q1 for both
  * displacement components, two dofs per free node: dof 2 f + c is component c
  * (0: x, 1: y) of free node f, so n_free = 2 (nx-1)(ny-1); corners carry both
- * components.  With Q1_ELASTIC the constraint kinds CORNERS and CORNERS_EDGES
- * are supported; ADAPTIVE is refused with BDDC_EUNSUPPORTED. */
+ * components; the kernel of a floating substructure is its three rigid-body
+ * modes.  With ADAPTIVE, every edge of a floating substructure must end at two
+ * corner nodes (square partitions do), else bddc_setup returns
+ * BDDC_EUNSUPPORTED. */
 typedef enum { BDDC_Q1 = 0, BDDC_P1 = 1, BDDC_Q1_ELASTIC = 2 } bddc_element;
 typedef enum { BDDC_CORNERS = 0, BDDC_CORNERS_EDGES = 1, BDDC_ADAPTIVE = 2 } bddc_constraints;
 typedef enum { BDDC_FP64 = 0, BDDC_FP32 = 1, BDDC_BF16 = 2 } bddc_precision;

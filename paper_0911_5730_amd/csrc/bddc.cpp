@@ -491,6 +491,7 @@ struct PcgRun {
 
 struct bddc_ctx {
   int nx = 0, ny = 0, L = 2, element = 0, constraints = 0, precision = 0;
+  int nz = 1;   // kernel modes of the operators without Dirichlet data (elasticity: 3 rigid-body modes)
   double tau = 0;
   int64_t n_free = 0;
   hipStream_t stream = nullptr;
@@ -569,8 +570,7 @@ static void validate(const bddc_problem* p) {
   if (p->nsub < 1) fail(BDDC_EINVAL, "nsub must be >= 1");
   if (p->levels < 2 || p->levels > BDDC_MAX_LEVELS) fail(BDDC_EINVAL, "levels must be in [2, 8]");
   if (p->constraints < 0 || p->constraints > 2) fail(BDDC_EINVAL, "unknown constraint kind");
-  if (p->element == BDDC_Q1_ELASTIC && p->constraints == BDDC_ADAPTIVE)
-    fail(BDDC_EUNSUPPORTED, "the adaptive constraints are not built for elasticity");
+
   if (std::isnan(p->tau) || p->tau < 0) fail(BDDC_EINVAL, "tau must be >= 0");
   if (p->precision != BDDC_FP64 && p->precision != BDDC_FP32 && p->precision != BDDC_BF16)
     fail(BDDC_EINVAL, "unknown precision");
@@ -1141,7 +1141,7 @@ class Builder {
       d.Q = A.take<double>((size_t)lv.qoff.back());
       d.nsel = A.take<int32_t>(lv.nedge);
       d.nkept = A.take<int32_t>(lv.nedge);
-      d.z = A.take<double>(lv.n);
+      d.z = A.take<double>((size_t)lv.n * h_->nz);
       d.y = A.take<double>(lv.nflat_i);
       d.t = A.take<double>(lv.nflat_g);
       d.a = A.take<double>(lv.nflat_g);
@@ -1234,10 +1234,26 @@ class Builder {
     stg.add(d.qoff, lv.qoff);
     stg.add(d.linvoff, lv.linvoff);
     if (prev) {
-      // the constant's coarse values, computed on the previous level
-      BDDC_HIP(hipMemcpyAsync(d.z, prev->d.znext, sizeof(double) * lv.n, hipMemcpyDeviceToDevice, st_));
+      // the kernel modes' coarse values, computed on the previous level
+      BDDC_HIP(hipMemcpyAsync(d.z, prev->d.znext, sizeof(double) * lv.n * h_->nz, hipMemcpyDeviceToDevice, st_));
     } else if (adaptive) {
-      ones.assign(lv.n, 1.0);
+      // level 1: the constants, or for elasticity the rigid-body modes at the
+      // free nodes (x then y component of each node): translations x and y,
+      // and the rotation u = (-y, x)
+      if (h_->nz == 1) {
+        ones.assign(lv.n, 1.0);
+      } else {
+        const int mx = h_->nx - 1;
+        const int nn = lv.n / 2;
+        ones.assign((size_t)lv.n * 3, 0.0);
+        for (int f = 0; f < nn; ++f) {
+          const double x = (double)(f % mx + 1) / h_->nx, y = (double)(f / mx + 1) / h_->ny;
+          ones[2 * f] = 1.0;
+          ones[(size_t)lv.n + 2 * f + 1] = 1.0;
+          ones[2 * (size_t)lv.n + 2 * f] = -y;
+          ones[2 * (size_t)lv.n + 2 * f + 1] = x;
+        }
+      }
       stg.add(d.z, ones);
     }
     stg.flush();
@@ -1307,12 +1323,23 @@ class Builder {
     lv.edge_m.assign(ne_tot, 0);
     lv.edge_nsel.assign(ne_tot, 0);
     std::vector<double> qh;
+    if (h_->constraints == BDDC_ADAPTIVE && ne_tot > 0 && h_->nz > 1) {
+      // elasticity: the pair problems regularise only the rigid-body modes
+      // common to both substructures, so an edge of a floating substructure
+      // must end at two corner nodes (which fix the relative rigid motion),
+      // as on square partitions
+      for (int e = 0; e < ne_tot; ++e)
+        if ((T.floating[T.edge_s[e]] || T.floating[T.edge_t[e]]) && lv.edge_nsc[e] < 4)
+          fail(BDDC_EUNSUPPORTED, "elasticity with adaptive constraints: an edge of a floating substructure "
+                                  "shares fewer than two corner nodes");
+    }
     if (h_->constraints == BDDC_ADAPTIVE && ne_tot > 0) {
       launch_pair_schur(st_, 2 * ne_tot, lv.ngmax, d.inc_sub, d.inc_fptr, d.inc_fpos, d.koff, d.loc_ptr, d.nint,
                         d.K, d.inc_off, d.Shat, d.Sff, h_->status, lv.schws_off.empty() ? nullptr : d.schws,
                         d.schws_off);
       launch_pair_eig(st_, ne_tot, lv.nemax, lv.nvmax, d.edge_s, d.edge_t, d.edge_nsc, d.edge_ne, d.edge_fdof,
-                      d.edge_fptr, d.inc_fptr, d.inc_fpos, d.goff, d.diagK, d.floating, d.z, d.Shat, d.Sff,
+                      d.edge_fptr, d.inc_fptr, d.inc_fpos, d.goff, d.diagK, d.floating, d.z, h_->nz, lv.n, d.Shat,
+                      d.Sff,
                       d.inc_off, h_->tau, d.lam, d.lamoff, d.Q, d.qoff, d.nsel, d.nkept, h_->status,
                       lv.eigws_off.empty() ? nullptr : d.eigws, d.eigws_off);
       std::vector<int32_t> nkept(ne_tot);
@@ -1370,7 +1397,8 @@ class Builder {
       launch_constrained_factor(st_, lv.nsub, d.koff, d.loc_ptr, d.nint, d.nr, d.ncr, d.croff, d.Cr, d.K, d.T,
                                 d.toff, d.Psi, d.psioff, d.Ac, d.acoff, d.cwork, d.cwoff, h_->status);
     if (h_->constraints == BDDC_ADAPTIVE && lv.ell < h_->L - 1)
-      launch_coarse_z(st_, lv.nc, d.cd_dof, d.cd_col, d.edge_ptr, d.edge_dof, d.qoff, d.Q, d.z, d.znext);
+      launch_coarse_z(st_, lv.nc, d.cd_dof, d.cd_col, d.edge_ptr, d.edge_dof, d.qoff, d.Q, d.z, h_->nz, lv.n,
+                      d.znext);
     (void)T;
     // agglomeration towards the next level
     if (lv.ell < h_->L - 1) {
@@ -1462,7 +1490,7 @@ class Builder {
       d.Psi = A.take<double>(lv.psioff[nsub]);
       d.Ac = A.take<double>(lv.acoff[nsub]);
       d.cwork = A.take<double>(lv.cwoff[nsub]);
-      d.znext = A.take<double>(lv.nc);
+      d.znext = A.take<double>((size_t)lv.nc * h_->nz);
       d.b = A.take<double>(lv.nflat_c);
       d.rc = A.take<double>(lv.nc);
       d.uc = A.take<double>(lv.nc);
@@ -2682,6 +2710,7 @@ bddc_status bddc_setup(const bddc_problem* p, void* hip_stream, bddc_handle* out
     h->precision = p->precision;
     h->tau = p->tau;
     h->n_free = (int64_t)dofs_per_node(p->element) * (p->nx - 1) * (p->ny - 1);
+    h->nz = p->element == BDDC_Q1_ELASTIC ? 3 : 1;
     h->stream = reinterpret_cast<hipStream_t>(hip_stream);
     BDDC_HIP(hipGetDevice(&h->device));
     HostClock clk;

@@ -108,7 +108,7 @@ __global__ void __launch_bounds__(kNT) k_pair_eig(
     const int32_t* __restrict__ edge_fdof, const int32_t* __restrict__ edge_fptr,
     const int32_t* __restrict__ inc_fptr, const int32_t* __restrict__ inc_fpos,
     const int32_t* __restrict__ goff, const double* __restrict__ diagK,
-    const uint8_t* __restrict__ floating, const double* __restrict__ z,
+    const uint8_t* __restrict__ floating, const double* __restrict__ z, int nz, int zld,
     const double* __restrict__ Shat, const double* __restrict__ Sff, const int64_t* __restrict__ inc_off,
     double tau, double* __restrict__ lam_out, const int64_t* __restrict__ lamoff, double* __restrict__ Q,
     const int64_t* __restrict__ qoff, int32_t* __restrict__ nsel_out, int32_t* __restrict__ nkept_out,
@@ -140,8 +140,8 @@ __global__ void __launch_bounds__(kNT) k_pair_eig(
   double* cs = dt + ne;                  // rotation cosines (ne/2+1)
   double* sn = cs + (ne / 2 + 1);        // rotation sines (ne/2+1)
   double* lam = sn + (ne / 2 + 1);       // ne
-  double* q = lam + ne;                  // nv: z on F in v coordinates
-  int* perm = reinterpret_cast<int*>(q + nv);
+  double* q = lam + ne;                  // kMaxModes x nv: the kernel modes on F in v coordinates
+  int* perm = reinterpret_cast<int*>(q + (size_t)kMaxModes * nv);
 
   // pair weights on the edge dofs: delta_s^{st} = d_s / (d_s + d_t)
   for (int p = tid; p < ne; p += kNT) {
@@ -154,7 +154,7 @@ __global__ void __launch_bounds__(kNT) k_pair_eig(
   if (both_float) {
     for (int i = tid; i < nv; i += kNT) {
       const int f = i < nsc ? i : (i < nsc + ne ? i : i - ne);
-      q[i] = z[edge_fdof[edge_fptr[e] + f]];
+      for (int m = 0; m < nz; ++m) q[i + m * nv] = z[(size_t)m * zld + edge_fdof[edge_fptr[e] + f]];
     }
   }
   // M in the coordinates v = [shared corners | s-edge | t-edge]: s side at F
@@ -170,7 +170,7 @@ __global__ void __launch_bounds__(kNT) k_pair_eig(
     Y[idx] = y;
   }
   __syncthreads();
-  if (both_float) {
+  if (both_float && nz == 1) {
     // Y = M + a q q^T with a = max diag(M) / |q|^2
     double nq = 0.0, amax = 0.0;
     for (int i = tid; i < nv; i += kNT) {
@@ -191,6 +191,45 @@ __global__ void __launch_bounds__(kNT) k_pair_eig(
       const int i = w_.i, j = w_.j;
       [[maybe_unused]] const int idx = i + j * nv;
       Y[idx] += scale * q[i] * q[j];
+    }
+    __syncthreads();
+  } else if (both_float) {
+    // several kernel modes (elasticity: the rigid-body modes common to both
+    // substructures): Y = M + a sum_m q_m q_m^T over an orthonormal basis
+    // (modified Gram-Schmidt) of the modes on F, a = max diag(M)
+    double amax = 0.0;
+    for (int i = tid; i < nv; i += kNT) amax = fmax(amax, Y[i + (size_t)i * nv]);
+    red[tid] = amax;
+    __syncthreads();
+    for (int w = kNT / 2; w > 0; w >>= 1) {
+      if (tid < w) red[tid] = fmax(red[tid], red[tid + w]);
+      __syncthreads();
+    }
+    amax = red[0];
+    __syncthreads();
+    for (int m = 0; m < nz; ++m) {
+      double* qm = q + m * nv;
+      for (int p = 0; p < m; ++p) {
+        const double* qp = q + p * nv;
+        double d = 0.0;
+        for (int i = tid; i < nv; i += kNT) d += qp[i] * qm[i];
+        d = wg_sum(d, red);
+        for (int i = tid; i < nv; i += kNT) qm[i] -= d * qp[i];
+        __syncthreads();
+      }
+      double nq = 0.0;
+      for (int i = tid; i < nv; i += kNT) nq += qm[i] * qm[i];
+      nq = wg_sum(nq, red);
+      const double inv = nq > 0.0 ? 1.0 / sqrt(nq) : 0.0;
+      for (int i = tid; i < nv; i += kNT) qm[i] *= inv;
+      __syncthreads();
+    }
+    for (ColWalk w_(tid, kNT, nv); w_.j < nv; w_.next()) {
+      const int i = w_.i, j = w_.j;
+      [[maybe_unused]] const int idx = i + j * nv;
+      double acc = 0.0;
+      for (int m = 0; m < nz; ++m) acc += q[i + m * nv] * q[j + m * nv];
+      Y[idx] += amax * acc;
     }
     __syncthreads();
   }
@@ -440,7 +479,7 @@ __global__ void __launch_bounds__(64) k_pair_eig_wave(
     const int32_t* __restrict__ edge_fdof, const int32_t* __restrict__ edge_fptr,
     const int32_t* __restrict__ inc_fptr, const int32_t* __restrict__ inc_fpos,
     const int32_t* __restrict__ goff, const double* __restrict__ diagK,
-    const uint8_t* __restrict__ floating, const double* __restrict__ z,
+    const uint8_t* __restrict__ floating, const double* __restrict__ z, int nz, int zld,
     const double* __restrict__ Shat, const double* __restrict__ Sff, const int64_t* __restrict__ inc_off,
     double tau, double* __restrict__ lam_out, const int64_t* __restrict__ lamoff, double* __restrict__ Q,
     const int64_t* __restrict__ qoff, int32_t* __restrict__ nsel_out, int32_t* __restrict__ nkept_out,
@@ -474,8 +513,8 @@ __global__ void __launch_bounds__(64) k_pair_eig_wave(
   double* ds = V + (size_t)ne * ne;       // ne
   double* dt = ds + ne;                   // ne
   double* lam = dt + ne;                  // ne
-  double* q = lam + ne;                   // nv
-  int* perm = reinterpret_cast<int*>(q + nv);
+  double* q = lam + ne;                   // kMaxModes x nv
+  int* perm = reinterpret_cast<int*>(q + (size_t)kMaxModes * nv);
 
   for (int p = lane; p < ne; p += 64) {
     const double a = diagK[goff[s] + fps[nsc + p]];
@@ -487,7 +526,7 @@ __global__ void __launch_bounds__(64) k_pair_eig_wave(
   if (both_float)
     for (int i = lane; i < nv; i += 64) {
       const int f = i < nsc ? i : (i < nsc + ne ? i : i - ne);
-      q[i] = z[edge_fdof[edge_fptr[e] + f]];
+      for (int m = 0; m < nz; ++m) q[i + m * nv] = z[(size_t)m * zld + edge_fdof[edge_fptr[e] + f]];
     }
   for (ColWalk w_(lane, 64, nv); w_.j < nv; w_.next()) {
     const int vi = w_.i, vj = w_.j;
@@ -499,7 +538,7 @@ __global__ void __launch_bounds__(64) k_pair_eig_wave(
     Y[vi + vj * nv] = y;
   }
   wsync();
-  if (both_float) {
+  if (both_float && nz == 1) {
     // Y = M + a q q^T with a = max diag(M) / |q|^2
     double nq = 0.0, amax = 0.0;
     for (int i = lane; i < nv; i += 64) {
@@ -510,6 +549,35 @@ __global__ void __launch_bounds__(64) k_pair_eig_wave(
     amax = wv_max(amax);
     const double scale = amax / nq;
     for (ColWalk w_(lane, 64, nv); w_.j < nv; w_.next()) Y[w_.i + w_.j * nv] += scale * q[w_.i] * q[w_.j];
+    wsync();
+  } else if (both_float) {
+    // several kernel modes: Y = M + a sum_m q_m q_m^T, q_m orthonormalised
+    // (modified Gram-Schmidt), a = max diag(M)
+    double amax = 0.0;
+    for (int i = lane; i < nv; i += 64) amax = fmax(amax, Y[i + i * nv]);
+    amax = wv_max(amax);
+    for (int m = 0; m < nz; ++m) {
+      double* qm = q + m * nv;
+      for (int p = 0; p < m; ++p) {
+        const double* qp = q + p * nv;
+        double d = 0.0;
+        for (int i = lane; i < nv; i += 64) d += qp[i] * qm[i];
+        d = wv_sum(d);
+        for (int i = lane; i < nv; i += 64) qm[i] -= d * qp[i];
+        wsync();
+      }
+      double nq = 0.0;
+      for (int i = lane; i < nv; i += 64) nq += qm[i] * qm[i];
+      nq = wv_sum(nq);
+      const double inv = nq > 0.0 ? 1.0 / sqrt(nq) : 0.0;
+      for (int i = lane; i < nv; i += 64) qm[i] *= inv;
+      wsync();
+    }
+    for (ColWalk w_(lane, 64, nv); w_.j < nv; w_.next()) {
+      double acc = 0.0;
+      for (int m = 0; m < nz; ++m) acc += q[w_.i + m * nv] * q[w_.j + m * nv];
+      Y[w_.i + w_.j * nv] += amax * acc;
+    }
     wsync();
   }
   wv_potrf(Y, nv, status);
@@ -711,33 +779,33 @@ size_t pair_schur_lds(int ngmax) {
 
 size_t pair_eig_lds(int nemax, int nvmax) {
   return sizeof(double) * ((size_t)nvmax * nvmax + (size_t)nvmax * nemax + 4 * (size_t)nemax * nemax +
-                           3 * (size_t)nemax + 2 * (nemax / 2 + 1) + (size_t)nvmax) +
+                           3 * (size_t)nemax + 2 * (nemax / 2 + 1) + (size_t)kMaxModes * nvmax) +
          sizeof(int) * (nemax + 2) + 64;
 }
 
 void launch_pair_eig(hipStream_t st, int nedge, int nemax, int nvmax, const int32_t* edge_s, const int32_t* edge_t,
                      const int32_t* edge_nsc, const int32_t* edge_ne, const int32_t* edge_fdof,
                      const int32_t* edge_fptr, const int32_t* inc_fptr, const int32_t* inc_fpos,
-                     const int32_t* goff, const double* diagK, const uint8_t* floating, const double* z,
-                     const double* Shat, const double* Sff, const int64_t* inc_off, double tau, double* lam,
+                     const int32_t* goff, const double* diagK, const uint8_t* floating, const double* z, int nz,
+                     int zld, const double* Shat, const double* Sff, const int64_t* inc_off, double tau, double* lam,
                      const int64_t* lamoff, double* Q, const int64_t* qoff, int32_t* nsel, int32_t* nkept,
                      int* status, double* ws, const int64_t* wsoff) {
   if (nedge == 0) return;
   if (ws) {
     launch_kernel(k_pair_eig_wave<true>, dim3(nedge), dim3(64), 0, st, edge_s, edge_t, edge_nsc, edge_ne, edge_fdof,
-                  edge_fptr, inc_fptr, inc_fpos, goff, diagK, floating, z, Shat, Sff, inc_off, tau, lam, lamoff, Q,
+                  edge_fptr, inc_fptr, inc_fpos, goff, diagK, floating, z, nz, zld, Shat, Sff, inc_off, tau, lam, lamoff, Q,
                   qoff, nsel, nkept, status, ws, wsoff);
     return;
   }
   const char* env = getenv("BDDC_EIG_PATH");
   if (!(env && std::string(env) == "wg")) {
     launch_kernel(k_pair_eig_wave<false>, dim3(nedge), dim3(64), pair_eig_lds(nemax, nvmax), st, edge_s, edge_t,
-                  edge_nsc, edge_ne, edge_fdof, edge_fptr, inc_fptr, inc_fpos, goff, diagK, floating, z, Shat, Sff,
+                  edge_nsc, edge_ne, edge_fdof, edge_fptr, inc_fptr, inc_fpos, goff, diagK, floating, z, nz, zld, Shat, Sff,
                   inc_off, tau, lam, lamoff, Q, qoff, nsel, nkept, status, ws, wsoff);
     return;
   }
   launch_kernel(k_pair_eig, dim3(nedge), dim3(kNT), pair_eig_lds(nemax, nvmax), st, nedge, edge_s, edge_t,
-                edge_nsc, edge_ne, edge_fdof, edge_fptr, inc_fptr, inc_fpos, goff, diagK, floating, z, Shat, Sff,
+                edge_nsc, edge_ne, edge_fdof, edge_fptr, inc_fptr, inc_fpos, goff, diagK, floating, z, nz, zld, Shat, Sff,
                 inc_off, tau, lam, lamoff, Q, qoff, nsel, nkept, status);
 }
 

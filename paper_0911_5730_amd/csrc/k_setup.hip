@@ -221,25 +221,29 @@ __global__ void k_build_cr(const int32_t* __restrict__ sub_inc_ptr, const int32_
   }
 }
 
-// Values of the level's coarse dofs for the level's constant vector z: the
-// next level's null-space representative (corners copy z, edge functionals
-// apply their weights).
+// Values of the level's coarse dofs for each kernel mode of the level (the
+// constants, or the rigid-body modes of elasticity; nz columns of z at stride
+// zld): the next level's kernel modes (corners copy z, edge functionals apply
+// their weights), nz columns of znext at stride nc.
 __global__ void k_coarse_z(int nc, const int32_t* __restrict__ cd_dof, const int32_t* __restrict__ cd_col,
                            const int32_t* __restrict__ edge_ptr, const int32_t* __restrict__ edge_dof,
                            const int64_t* __restrict__ qoff, const double* __restrict__ Q,
-                           const double* __restrict__ z, double* __restrict__ znext) {
+                           const double* __restrict__ z, int nz, int zld, double* __restrict__ znext) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nc) return;
-  if (cd_col[k] < 0) {
-    znext[k] = z[cd_dof[k]];
-    return;
+  for (int m = 0; m < nz; ++m) {
+    const double* zm = z + (size_t)m * zld;
+    if (cd_col[k] < 0) {
+      znext[(size_t)m * nc + k] = zm[cd_dof[k]];
+      continue;
+    }
+    const int e = cd_dof[k], j = cd_col[k];
+    const int ne = edge_ptr[e + 1] - edge_ptr[e];
+    const double* q = Q + qoff[e] + (size_t)j * ne;
+    double acc = 0.0;
+    for (int p = 0; p < ne; ++p) acc += q[p] * zm[edge_dof[edge_ptr[e] + p]];
+    znext[(size_t)m * nc + k] = acc;
   }
-  const int e = cd_dof[k], j = cd_col[k];
-  const int ne = edge_ptr[e + 1] - edge_ptr[e];
-  const double* q = Q + qoff[e] + (size_t)j * ne;
-  double acc = 0.0;
-  for (int p = 0; p < ne; ++p) acc += q[p] * z[edge_dof[edge_ptr[e] + p]];
-  znext[k] = acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -435,10 +439,10 @@ void launch_build_cr(hipStream_t st, int nsub, const int32_t* sub_inc_ptr, const
 
 void launch_coarse_z(hipStream_t st, int nc, const int32_t* cd_dof, const int32_t* cd_col,
                      const int32_t* edge_ptr, const int32_t* edge_dof, const int64_t* qoff,
-                     const double* Q, const double* z, double* znext) {
+                     const double* Q, const double* z, int nz, int zld, double* znext) {
   if (nc == 0) return;
-  launch_kernel(k_coarse_z, dim3((nc + kNT - 1) / kNT), dim3(kNT), 0, st, nc, cd_dof, cd_col,
-                     edge_ptr, edge_dof, qoff, Q, z, znext);
+  launch_kernel(k_coarse_z, dim3((nc + kNT - 1) / kNT), dim3(kNT), 0, st, nc, cd_dof, cd_col, edge_ptr, edge_dof,
+                qoff, Q, z, nz, zld, znext);
 }
 
 void launch_constrained_factor(hipStream_t st, int nsub, const int64_t* koff, const int32_t* loc_ptr,

@@ -38,6 +38,10 @@ inline void launch_kernel(void (*k)(P...), dim3 grid, dim3 block, size_t shm, hi
 struct Khat16 {
   double v[16];   // 4x4 reference element matrix (k = 1), row-major, local node order CCW from (i,j)
 };
+// kernel modes of the operators without Dirichlet data: the constants, or
+// the three rigid-body modes of plane elasticity (columns of the level's z)
+constexpr int kMaxModes = 3;
+
 struct Khat64 {
   double v[64];   // 8x8 elasticity element matrix (k = 1), row-major, dof 2 q + c of local node q
 };
@@ -375,7 +379,7 @@ void launch_build_cr(hipStream_t st, int nsub, const int32_t* sub_inc_ptr, const
                      const int64_t* croff, double* Cr);
 void launch_coarse_z(hipStream_t st, int nc, const int32_t* cd_dof, const int32_t* cd_col,
                      const int32_t* edge_ptr, const int32_t* edge_dof, const int64_t* qoff,
-                     const double* Q, const double* z, double* znext);
+                     const double* Q, const double* z, int nz, int zld, double* znext);
 void launch_constrained_factor(hipStream_t st, int nsub, const int64_t* koff, const int32_t* loc_ptr,
                                const int32_t* nint, const int32_t* nr, const int32_t* ncr,
                                const int64_t* croff, const double* Cr, const double* K, double* T,
@@ -400,7 +404,8 @@ size_t pair_eig_lds(int nemax, int nvmax);
 void launch_pair_eig(hipStream_t st, int nedge, int nemax, int nvmax, const int32_t* edge_s, const int32_t* edge_t,
                      const int32_t* edge_nsc, const int32_t* edge_ne, const int32_t* edge_fdof,
                      const int32_t* edge_fptr, const int32_t* inc_fptr, const int32_t* inc_fpos,
-                     const int32_t* goff, const double* diagK, const uint8_t* floating, const double* z,
+                     const int32_t* goff, const double* diagK, const uint8_t* floating, const double* z, int nz,
+                     int zld,
                      const double* Shat, const double* Sff, const int64_t* inc_off, double tau, double* lam,
                      const int64_t* lamoff, double* Q, const int64_t* qoff, int32_t* nsel, int32_t* nkept,
                      int* status, double* ws = nullptr, const int64_t* wsoff = nullptr);

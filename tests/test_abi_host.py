@@ -86,13 +86,6 @@ def test_plan_topology_matches_oracle_elasticity(case):
         assert got[k] == v, (k, got[k], v)
 
 
-def test_elasticity_refuses_adaptive_constraints():
-    prob = synth.square_problem(24, 3, element="Q1E", constraints="adaptive", tau=2.0)
-    with pytest.raises(P.BDDCError) as e:
-        P.plan(prob)
-    assert e.value.name == "BDDC_EUNSUPPORTED"
-
-
 def test_plan_promotes_corner_for_island():
     nx = 12
     prob = synth.square_problem(nx, 1)

@@ -70,13 +70,18 @@ def _case(name):
                                  kmax_exp=1, seed=43),
         "elastic3": lambda: sq(48, 6, levels=3, groups=(3, 3), element="Q1E", kmode="loguniform", kmax_exp=2,
                                seed=44),
+        # adaptive constraints on elasticity (rigid-body modes in the pair problems)
+        "elastic_adaptive2": lambda: sq(48, 4, constraints="adaptive", tau=3.0, element="Q1E", kmode="loguniform",
+                                        kmax_exp=2, channels=1, seed=46),
+        "elastic_adaptive3": lambda: sq(64, 8, levels=3, groups=(2, 2), constraints="adaptive", tau=3.0,
+                                        element="Q1E", kmode="loguniform", kmax_exp=2, seed=47),
     }[name]()
 
 
 CASES = ["config1", "corners_kjump", "ce_ragged", "rect", "p1", "adaptive2", "adaptive3", "adaptive3_h16",
          "corners3", "single_sub", "adaptive2_h32", "voronoi2", "voronoi_adaptive2", "voronoi_adaptive3",
          "voronoi_adaptive3_large", "voronoi_jitter3", "adaptive4", "ce4",
-         "elastic_paper", "elastic_kjump", "elastic_ce", "elastic3"]
+         "elastic_paper", "elastic_kjump", "elastic_ce", "elastic3", "elastic_adaptive2", "elastic_adaptive3"]
 
 
 @pytest.mark.parametrize("name", CASES)
