@@ -61,9 +61,12 @@ class Level:
     """One decomposition level l: level-l elements grouped into substructures."""
 
     def __init__(self, ell: int, n: int, elems, elem_sub, nsub: int,
-                 elem_floating, z: np.ndarray):
+                 elem_floating, z: np.ndarray, comp: Optional[np.ndarray] = None):
         self.ell = ell
         self.n = n
+        # displacement component of each dof (0 for scalar problems; -1 for a
+        # coarse dof that mixes components, as adaptive constraints do)
+        self.comp = np.zeros(n, dtype=np.int64) if comp is None else np.asarray(comp, dtype=np.int64)
         self.elems = elems
         self.elem_sub = np.asarray(elem_sub)
         self.nsub = nsub
@@ -119,20 +122,30 @@ class Level:
         top = self.topo
         func = []
         owners = []
+        comp_next = []
         for c in top.corners:
             func.append((np.array([c]), np.array([1.0])))
             owners.append(top.N[c])
+            comp_next.append(self.comp[c])
         for key, E in top.edges.items():
             if kind == "corners_edges":
-                func.append((E, np.full(len(E), 1.0 / len(E))))
-                owners.append(key)
+                # the arithmetic average over the edge of each displacement
+                # component (Table 1: c+e adds two coarse dofs per edge in 2D
+                # elasticity), components in increasing order
+                for c in np.unique(self.comp[E]):
+                    Ec = E[self.comp[E] == c]
+                    func.append((Ec, np.full(len(Ec), 1.0 / len(Ec))))
+                    owners.append(key)
+                    comp_next.append(c)
             elif kind == "adaptive":
                 Q = edge_Q.get(key) if edge_Q else None
                 if Q is not None:
                     for m in range(Q.shape[1]):
                         func.append((E, Q[:, m].copy()))
                         owners.append(key)
+                        comp_next.append(-1)
         self.func = func
+        self.comp_next = np.array(comp_next, dtype=np.int64)
         self.Nc = len(func)
         sub_c = [[] for _ in range(self.nsub)]
         for k, ow in enumerate(owners):
@@ -205,7 +218,8 @@ class BDDC:
         self.eigs = []                       # per level: {(s,t): lambdas}
         self.edge_Q = []                     # per level: {(s,t): orthonormal constraint columns}
         self.omega_levels = []               # per level: max_st lambda_{n+1}
-        cur = Level(1, n, elems, prob.part, prob.nsub, ~touches, fem.null_modes(nx, ny, prob.element))
+        cur = Level(1, n, elems, prob.part, prob.nsub, ~touches, fem.null_modes(nx, ny, prob.element),
+                    fem.dof_components(nx, ny, prob.element))
         from . import adaptive
         for ell in range(1, self.L):
             if all_interface_corners and ell == 1:
@@ -225,7 +239,7 @@ class BDDC:
                 agg = np.asarray(prob.agglom[ell - 1])
                 nsub_next = int(agg.max()) + 1
                 cur = Level(ell + 1, cur.Nc, nxt_elems, agg, nsub_next,
-                            cur.topo.sub_floating, cur.z_next)
+                            cur.topo.sub_floating, cur.z_next, cur.comp_next)
         last = self.levels[-1]
         Ac = assemble_elements(last.Nc, [(last.cids[s], last.Ac[s]) for s in range(last.nsub)])
         self.A_coarsest = Ac.toarray()

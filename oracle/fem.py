@@ -151,6 +151,12 @@ def n_free(nx: int, ny: int, element: str = "Q1") -> int:
     return dofs_per_node(element) * (nx - 1) * (ny - 1)
 
 
+def dof_components(nx: int, ny: int, element: str = "Q1") -> np.ndarray:
+    """Displacement component of each free dof: 0 for scalar problems; for
+    elasticity 0 (x) on dofs 2 f and 1 (y) on dofs 2 f + 1."""
+    return np.arange(n_free(nx, ny, element), dtype=np.int64) % dofs_per_node(element)
+
+
 def null_modes(nx: int, ny: int, element: str = "Q1") -> np.ndarray:
     """(n_free, m) the kernel of the operator without Dirichlet data, on the
     free dofs: the constants (scalar problems, m = 1) or the rigid-body modes

@@ -14,6 +14,8 @@ from .configs import (  # noqa: F401
     voronoi_partition,
     voronoi_agglomeration,
     voronoi_problem,
+    jag_edge,
+    paper_elasticity_problem,
     config,
     request_stream, serving_stream,
     CONFIG_NAMES,

@@ -266,6 +266,71 @@ def voronoi_problem(nx: int, nsub: int, *, levels: int = 2, ngroups: int = 1, co
                          "elements_max": int(sizes.max())})
 
 
+def jag_edge(owner2d: np.ndarray, split: int, lo: int, hi: int, s: int, t: int, width: int, depth: int) -> int:
+    """Make the straight horizontal edge between owners s (rows below `split`)
+    and t (rows from `split` on), over columns lo..hi-1, jagged in place: the
+    columns lo+1 .. hi-2 (so both end points keep their neighbours) are cut
+    into teeth `width` columns wide that alternate, starting with a tooth of s
+    reaching `depth` rows into t, then one of t reaching `depth` rows into s.
+    Each tooth stays attached to its owner, so both stay connected, and every
+    node on the new edge is still shared by s and t alone.  Returns the number
+    of cells that changed owner."""
+    moved = 0
+    for c in range(lo + 1, hi - 1):
+        if ((c - lo - 1) // width) % 2 == 0:
+            rows, src, dst = slice(split, split + depth), t, s
+        else:
+            rows, src, dst = slice(split - depth, split), s, t
+        col = owner2d[rows, c]
+        assert (col == src).all(), "the teeth must lie inside the two owners"
+        owner2d[rows, c] = dst
+        moved += col.size
+    return moved
+
+
+def paper_elasticity_problem(nx: int = 768, nsx: int = 48, *, levels: int = 2, groups: int = 3,
+                             constraints: str = "corners", tau: float = float("inf"), jagged: bool = True,
+                             teeth=None, nrhs: int = 1, seed: int = 0, name: str = "") -> Problem:
+    """The shape of the paper's experiment (Section 6): plane elasticity
+    (lambda = 1, mu = 2, k = 1) on the unit square, an nx x nx mesh cut into
+    nsx x nsx square substructures (768 / 48: H/h = 16, 2304 substructures)
+    and, for three levels, groups x groups level-2 substructures (3 x 3:
+    coarsening ratio 16), with one jagged edge on each decomposition level:
+    at level 1 between substructures (1, 0) and (1, 1) (x-block, y-block;
+    numbers 2 and 50 counted from one), at level 2 between groups (1, 0) and
+    (1, 1) (numbers 2 and 5).  The figure that draws the jagged edges is not
+    in the text, so the teeth are a reading: one unit wide and one deep
+    (elements at level 1, level-1 substructures at level 2), a zigzag that
+    starts with a tooth of the lower substructure; at level 1 this shape
+    gives the pair eigenvalues printed for the jagged pair and its
+    neighbours (Table 3) to within a few percent.  `teeth` = (width, depth)
+    overrides it at level 1.  The only random draw is the load."""
+    assert constraints in CONSTRAINT_KINDS and levels in (2, 3) and nx % nsx == 0
+    assert levels == 2 or nsx % groups == 0
+    hh = nx // nsx
+    part2d = square_partition(nx, nx, nsx, nsx).reshape(nx, nx)
+    moved = [0, 0]
+    if jagged:
+        assert nsx >= 2 and hh >= 3
+        w, d = teeth or (1, 1)
+        moved[0] = jag_edge(part2d, hh, hh, 2 * hh, 1, nsx + 1, w, d)
+    agg = []
+    if levels == 3:
+        g2d = square_agglomeration(nsx, nsx, groups, groups).reshape(nsx, nsx)
+        m = nsx // groups
+        if jagged:
+            assert groups >= 2 and m >= 3
+            moved[1] = jag_edge(g2d, m, m, 2 * m, 1, groups + 1, 1, 1)
+        agg.append(g2d.reshape(-1).astype(np.int32))
+    rng = np.random.Generator(np.random.PCG64(seed))
+    f = rng.uniform(-1.0, 1.0, size=(nrhs, 2 * (nx - 1) * (nx - 1)))
+    return Problem(nx=nx, ny=nx, coeff=np.ones(nx * nx), part=part2d.reshape(-1).astype(np.int32),
+                   nsub=nsx * nsx, levels=levels, agglom=agg, constraints=constraints, tau=tau, f=f,
+                   element="Q1E", name=name,
+                   meta={"nsx": nsx, "nsy": nsx, "groups": (groups, groups), "jagged": jagged,
+                         "moved": moved, "jagged_pairs": [(1, nsx + 1), (1, groups + 1)]})
+
+
 CONFIG_NAMES = {
     1: "two-level c+e, 32x32 Q1, 4x4 subs (H/h=8), k=1",
     2: "adaptive three-level, 256x256 Q1, 16x16 subs (H/h=16), 4x4 groups, "
