@@ -183,6 +183,83 @@ def autotuned(P, synth, torch, cid: int, stream, nrhs: int) -> dict:
             "tuned": {k: t[k] for k in ("deep_path", "finalize", "graph", "check")}, "tuned_rhs_per_s": r1}
 
 
+def elasticity_form(P, synth, torch, stream, reps: int = 5) -> dict:
+    """The paper's own experiment (Section 6, Tables 1-7): plane elasticity
+    (lambda = 1, mu = 2), 768 x 768 Q1 mesh (1,176,578 free dofs, whole
+    boundary clamped), 48 x 48 substructures (H/h = 16), 3 x 3 level-2
+    substructures for three levels, one jagged edge on each level.  For two
+    and three levels and constraints c, c+e and adaptive with tau = 10, 3, 2:
+    coarse dofs per level, C (coarse problem size over a substructure's
+    dofs), the indicator omega-tilde, the Lanczos condition estimate,
+    iterations to 1e-8, and solves/s in the mixed form and in FP64; the pair
+    eigenvalues of Table 3 (level 1, tau = 10) and Tables 4 and 5 (level 2,
+    tau = 2 and 10)."""
+    ns, groups, hh = 48, 3, 16
+
+    def edge_eigs(S, level, pairs):
+        want = {tuple(sorted(p)): None for p in pairs}
+        e = 0
+        while any(v is None for v in want.values()):
+            lam, nsel, pr = S.edge_eigs(level, e)
+            key = (int(pr[0]), int(pr[1]))
+            if key in want:
+                want[key] = [round(float(x), 3) for x in lam[:8]]
+            e += 1
+        return want
+
+    rows = []
+    eigs = {}
+    for levels in (2, 3):
+        for kind, tau in (("corners", float("inf")), ("corners_edges", float("inf")), ("adaptive", 10.0),
+                          ("adaptive", 3.0), ("adaptive", 2.0)):
+            prob = synth.paper_elasticity_problem(hh * ns, ns, levels=levels, groups=groups, constraints=kind,
+                                                  tau=tau, seed=50)
+            f = torch.tensor(prob.f[0], dtype=torch.float64, device="cuda")
+            u = torch.empty_like(f)
+            row = {"levels": levels, "constraints": kind, "tau": tau if kind == "adaptive" else None}
+            for prec in ("fp32", "fp64"):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                S = P.Solver(prob, stream=stream, precision=prec)
+                torch.cuda.synchronize()
+                setup = time.perf_counter() - t0
+                _, it, rr = S.solve(f, u=u, rtol=prob.rtol, stream=stream)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    S.solve(f, u=u, rtol=prob.rtol, stream=stream)
+                torch.cuda.synchronize()
+                dt = (time.perf_counter() - t0) / reps
+                info = S.info()
+                nc = list(info["nc"])
+                if prec == "fp64":
+                    nblk = 1 if levels == 2 else groups * groups
+                    row.update(nc=nc, C=round(nc[0] / nblk / (prob.n_free / prob.nsub), 2),
+                               omega=info["indicator"] if kind == "adaptive" else None, kappa=info["kappa"],
+                               iterations=int(it[0]), relres=float(rr[0]))
+                    if kind == "adaptive" and tau == 10.0 and levels == 2:
+                        # substructures numbered from one, row by row
+                        pairs = [(1, 2), (1, 49), (2, 3), (2, 50), (3, 4), (3, 51), (49, 50), (50, 51), (50, 98)]
+                        got = edge_eigs(S, 1, [(a - 1, b - 1) for a, b in pairs])
+                        eigs["table3_level1_tau10"] = {f"{a},{b}": got[(a - 1, b - 1)] for a, b in pairs}
+                    if kind == "adaptive" and tau in (2.0, 10.0) and levels == 3:
+                        pairs = [(1, 2), (1, 4), (2, 3), (2, 5), (3, 6), (4, 7), (5, 6), (5, 8), (8, 9)]
+                        got = edge_eigs(S, 2, [(a - 1, b - 1) for a, b in pairs])
+                        eigs[f"table{4 if tau == 2.0 else 5}_level2_tau{tau:g}"] = {
+                            f"{a},{b}": got[(a - 1, b - 1)] for a, b in pairs}
+                row[prec] = {"solves_per_s": 1.0 / dt, "solve_ms": dt * 1e3, "iterations": int(it[0]),
+                             "setup_ms": setup * 1e3}
+                S.close()
+            row["mixed_vs_fp64"] = row["fp32"]["solves_per_s"] / row["fp64"]["solves_per_s"]
+            log(f"bench: paper elasticity L={levels} {kind} tau={row['tau']}: nc {row['nc']}, C {row['C']}, "
+                f"omega {row['omega']}, kappa {row['kappa']:.2f}, {row['iterations']} it; "
+                f"fp32 {row['fp32']['solves_per_s']:.1f}/s, fp64 {row['fp64']['solves_per_s']:.1f}/s")
+            rows.append(row)
+    return {"workload": "768x768 Q1 plane elasticity (lambda 1, mu 2), 48x48 substructures (H/h = 16), "
+                        "3x3 level-2 substructures, one jagged edge per level, whole boundary clamped, "
+                        "f ~ U[-1, 1]", "n_free": 2 * 767 * 767, "rows": rows, "pair_eigenvalues": eigs}
+
+
 def batching_form(P, synth, torch, stream, precs=("fp32", "fp64")) -> dict:
     """Config 4 (2048 x 2048, about 1024 uneven Voronoi regions, three levels,
     eight loads): for each precision form (set up one after the other), the
@@ -366,6 +443,9 @@ def main():
     ap.add_argument("--no-blocked", action="store_true", help="skip the blocked right-hand-side measurement")
     ap.add_argument("--no-autotune", action="store_true", help="skip the autotuner measurement")
     ap.add_argument("--no-batching", action="store_true", help="skip the config-4 (uneven substructures) measurement")
+    ap.add_argument("--no-elasticity", action="store_true", help="skip the plane-elasticity measurement")
+    ap.add_argument("--elasticity-only", action="store_true",
+                    help="only the plane-elasticity measurement (one JSON line)")
     ap.add_argument("--no-precision-forms", action="store_true",
                     help="skip the FP64 / FP32 / BF16 comparison on config 2")
     ap.add_argument("--batching-only", action="store_true",
@@ -394,6 +474,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration": {"bytes_read": COPY_BYTES, "bytes_written": COPY_BYTES, "copies": 3}}))
+        return
+    if args.elasticity_only:
+        print(json.dumps({"elasticity": elasticity_form(P, synth, torch, torch.cuda.current_stream())}))
         return
     if args.batching_only:
         print(json.dumps({"batching_form": batching_form(P, synth, torch, torch.cuda.current_stream())}))
@@ -570,6 +653,8 @@ def main():
     if not args.no_batching:
         out["batching_form"] = dict(batching_form(P, synth, torch, stream),
                                     note="config 4: " + synth.CONFIG_NAMES[4])
+    if not args.no_elasticity:
+        out["elasticity"] = elasticity_form(P, synth, torch, stream)
     if not args.no_autotune:
         out["autotune"] = {
             "note": "launch configuration chosen by bddc_autotune (deep-level path, partial-sum mode, graph, "

@@ -58,6 +58,11 @@ typedef enum {
  * corner nodes (square partitions do), else bddc_setup returns
  * BDDC_EUNSUPPORTED. */
 typedef enum { BDDC_Q1 = 0, BDDC_P1 = 1, BDDC_Q1_ELASTIC = 2 } bddc_element;
+/* Coarse dofs (Section 2): CORNERS, the values at corner dofs; CORNERS_EDGES,
+ * those and the arithmetic average over each edge of each displacement
+ * component (one per edge for scalar problems, two in elasticity; Table 1);
+ * ADAPTIVE, corners and the eigenvectors of the pair eigenproblems above tau
+ * (Section 5). */
 typedef enum { BDDC_CORNERS = 0, BDDC_CORNERS_EDGES = 1, BDDC_ADAPTIVE = 2 } bddc_constraints;
 typedef enum { BDDC_FP64 = 0, BDDC_FP32 = 1, BDDC_BF16 = 2 } bddc_precision;
 

@@ -397,10 +397,17 @@ Khat16 element_matrix(int element, int nx, int ny) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// slots per edge for the components of its averages: -1 (mixed), 0, 1
+constexpr int kMaxComp = 3;
+
 struct Level {
   int ell = 1;
   Topology topo;
   int nsub = 0, n = 0;
+  // displacement component of each dof (0 for scalar problems, -1 for a coarse
+  // dof that mixes components), of each coarse dof, and of each edge average
+  // (kMaxComp slots per edge)
+  std::vector<int8_t> comp, cd_comp, edge_ccomp;
   // layout
   std::vector<int64_t> koff;
   std::vector<int32_t> goff, ioff, coff;
@@ -841,6 +848,11 @@ class Builder {
     lv->ell = 1;
     lv->topo = classify_grid(p_->nx, p_->ny, p_->part, p_->nsub, &G);
     expand_node_topology(lv->topo, &G, dofs_per_node(p_->element));
+    {
+      const int dpn = dofs_per_node(p_->element);
+      lv->comp.resize(lv->topo.n);
+      for (int d = 0; d < lv->topo.n; ++d) lv->comp[d] = (int8_t)(d % dpn);
+    }
     clk.lap("classify l1");
     layout_level(*lv);
     check_limits(*lv);
@@ -866,6 +878,7 @@ class Builder {
       eptr[prev.nsub] = (int32_t)edof.size();
       const int nsub_next = *std::max_element(esub.begin(), esub.end()) + 1;
       nl->topo = classify(prev.nc, nsub_next, eptr, edof, esub, etouch, true);
+      nl->comp = prev.cd_comp;
       layout_level(*nl);
       check_limits(*nl);
       clk.lap("classify+layout");
@@ -1371,11 +1384,25 @@ class Builder {
         lv.omega = std::max(lv.omega, nxt);
       }
     } else if (h_->constraints == BDDC_CORNERS_EDGES && ne_tot > 0) {
+      // the arithmetic average over the edge of each displacement component
+      // present on it (Table 1: two per edge in 2D elasticity), components in
+      // increasing order; column j of the edge's Q at stride edge_ne
       qh.assign(lv.qoff.back(), 0.0);
+      lv.edge_ccomp.assign((size_t)ne_tot * kMaxComp, 0);
       for (int e = 0; e < ne_tot; ++e) {
         const int nn = lv.edge_ne[e];
-        for (int p = 0; p < nn; ++p) qh[lv.qoff[e] + p] = 1.0 / nn;
-        lv.edge_m[e] = 1;
+        const int32_t* dof = T.edge_dof.data() + T.edge_ptr[e];
+        int cnt[kMaxComp] = {};
+        for (int p = 0; p < nn; ++p) cnt[lv.comp[dof[p]] + 1]++;
+        int m = 0;
+        for (int c = 0; c < kMaxComp; ++c) {
+          if (!cnt[c]) continue;
+          for (int p = 0; p < nn; ++p)
+            if (lv.comp[dof[p]] + 1 == c) qh[lv.qoff[e] + (size_t)m * nn + p] = 1.0 / cnt[c];
+          lv.edge_ccomp[(size_t)e * kMaxComp + m] = (int8_t)(c - 1);
+          ++m;
+        }
+        lv.edge_m[e] = m;
       }
       h2d(d.Q, qh, st_);
     }
@@ -1419,9 +1446,19 @@ class Builder {
     lv.nc = ebase[lv.nedge];
     lv.cd_dof.resize(lv.nc);
     lv.cd_col.resize(lv.nc);
-    for (int k = 0; k < ncorner; ++k) { lv.cd_dof[k] = T.corners[k]; lv.cd_col[k] = -1; }
+    lv.cd_comp.resize(lv.nc);
+    for (int k = 0; k < ncorner; ++k) {
+      lv.cd_dof[k] = T.corners[k];
+      lv.cd_col[k] = -1;
+      lv.cd_comp[k] = lv.comp[T.corners[k]];
+    }
+    const bool averages = !lv.edge_ccomp.empty();
     for (int e = 0; e < lv.nedge; ++e)
-      for (int j = 0; j < lv.edge_m[e]; ++j) { lv.cd_dof[ebase[e] + j] = e; lv.cd_col[ebase[e] + j] = j; }
+      for (int j = 0; j < lv.edge_m[e]; ++j) {
+        lv.cd_dof[ebase[e] + j] = e;
+        lv.cd_col[ebase[e] + j] = j;
+        lv.cd_comp[ebase[e] + j] = averages ? lv.edge_ccomp[(size_t)e * kMaxComp + j] : (int8_t)-1;
+      }
     std::vector<int32_t> cnt(nsub);
     lv.ncr.assign(nsub, 0);
     for (int s = 0; s < nsub; ++s) {

@@ -1,0 +1,70 @@
+"""The paper's experiment at full size on the GPU (Section 6).
+
+Plane elasticity, 768 x 768 Q1 mesh (1,176,578 free dofs with the whole
+boundary clamped), 48 x 48 substructures (H/h = 16), one jagged edge between
+substructures 2 and 50.  A pair eigenproblem depends on its two substructures
+only, so the eigenvalues of the pairs listed in Table 3 equal those of the
+oracle on a 5 x 5 stand-in with the same neighbourhoods (compared to the
+parity tolerance of the pair eigenvalues); the count of coarse dofs the
+adaptive rule adds at tau = 10 is Table 6's (4805 - 4794 = 11).
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_common import LAM_RTOL, cuda_vec
+from oracle.bddc import BDDC
+
+pytestmark = pytest.mark.gpu
+
+NS = 48
+N = 5
+
+
+def _ours(k, n):
+    k -= 1
+    return (k // NS) * n + k % NS
+
+
+def _edge_index(S, level, pairs):
+    """Edge index of each (s, t) pair at `level`."""
+    want = {tuple(sorted(p)): None for p in pairs}
+    e = 0
+    while any(v is None for v in want.values()):
+        _, _, pair = S.edge_eigs(level, e)
+        key = tuple(int(x) for x in pair)
+        if key in want:
+            want[key] = e
+        e += 1
+    return want
+
+
+def test_paper_scale_pair_eigenvalues_and_added_dofs():
+    import json
+    import os
+    import paper_0911_5730_amd as P
+    G = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_tables.json")))
+    pairs = [(a, b) for a, b, _ in G["table3"]["pairs"]]
+    stand_in = synth.paper_elasticity_problem(16 * N, N, levels=2, constraints="adaptive", tau=10.0)
+    B = BDDC(stand_in)
+    print("full size: 768 x 768, 48 x 48 substructures, tau = 10", flush=True)
+    prob = synth.paper_elasticity_problem(16 * NS, NS, levels=2, constraints="adaptive", tau=10.0, seed=50)
+    assert prob.n_free == 1176578
+    with P.Solver(prob) as S:
+        idx = _edge_index(S, 1, [(_ours(a, NS), _ours(b, NS)) for a, b in pairs])
+        for a, b in pairs:
+            lam_g, nsel, _ = S.edge_eigs(1, idx[tuple(sorted((_ours(a, NS), _ours(b, NS))))])
+            lo = np.asarray(B.eigs[0][tuple(sorted((_ours(a, N), _ours(b, N))))])
+            assert lam_g.size == lo.size
+            tol = LAM_RTOL * np.maximum(1.0, np.abs(lo)) + 1e-10 * max(1.0, lo[0])
+            assert np.all(np.abs(lam_g - lo) <= tol), ((a, b), lam_g[:4], lo[:4])
+            assert nsel == int(np.sum(lo > 10.0))
+        nc_a = S.info()["nc"][0]
+        u, it, rr = S.solve(cuda_vec(prob.f[0]), rtol=1e-8)
+        assert rr[0] <= 1e-8
+    with P.Solver(synth.paper_elasticity_problem(16 * NS, NS, levels=2, seed=50)) as S:
+        nc_c = S.info()["nc"][0]
+    assert nc_c == 2 * (NS - 1) ** 2                 # the interior cross points, two components each
+    rows = G["table6"]["rows"]
+    assert nc_a - nc_c == [r["nc"] for r in rows if r["tau"] == 10.0][0] - rows[0]["nc"] == 11

@@ -73,6 +73,13 @@ def _case(name):
         # adaptive constraints on elasticity (rigid-body modes in the pair problems)
         "elastic_adaptive2": lambda: sq(48, 4, constraints="adaptive", tau=3.0, element="Q1E", kmode="loguniform",
                                         kmax_exp=2, channels=1, seed=46),
+        # the paper's experiment at reduced size: H/h = 16, one jagged edge per level
+        "paper_jag2": lambda: synth.paper_elasticity_problem(80, 5, levels=2, constraints="adaptive", tau=3.0,
+                                                             seed=48),
+        "paper_jag3": lambda: synth.paper_elasticity_problem(96, 6, levels=3, groups=2, constraints="adaptive",
+                                                             tau=3.0, seed=49),
+        "paper_ce3": lambda: synth.paper_elasticity_problem(96, 6, levels=3, groups=2, constraints="corners_edges",
+                                                            seed=51),
         "elastic_adaptive3": lambda: sq(64, 8, levels=3, groups=(2, 2), constraints="adaptive", tau=3.0,
                                         element="Q1E", kmode="loguniform", kmax_exp=2, seed=47),
     }[name]()
@@ -81,7 +88,8 @@ def _case(name):
 CASES = ["config1", "corners_kjump", "ce_ragged", "rect", "p1", "adaptive2", "adaptive3", "adaptive3_h16",
          "corners3", "single_sub", "adaptive2_h32", "voronoi2", "voronoi_adaptive2", "voronoi_adaptive3",
          "voronoi_adaptive3_large", "voronoi_jitter3", "adaptive4", "ce4",
-         "elastic_paper", "elastic_kjump", "elastic_ce", "elastic3", "elastic_adaptive2", "elastic_adaptive3"]
+         "elastic_paper", "elastic_kjump", "elastic_ce", "elastic3", "elastic_adaptive2", "elastic_adaptive3",
+         "paper_jag2", "paper_jag3", "paper_ce3"]
 
 
 @pytest.mark.parametrize("name", CASES)
