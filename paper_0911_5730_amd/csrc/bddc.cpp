@@ -2263,6 +2263,7 @@ static void lay_columns(bddc_ctx* h, Arena& A, int R) {
   P.b = A.take<double>((size_t)R * P.ld_cflat);
   P.uc = A.take<double>((size_t)R * P.ld_coarse);
   P.sc = A.take<PcgScalars>(R);
+  P.tail_cnt = A.take<unsigned int>(3 * kTailStride);
   h->cy = A.take<double>((size_t)R * h->ld_cy);
   h->ct = A.take<double>((size_t)R * P.ld_flat);
 }
@@ -2301,6 +2302,9 @@ static void ensure_columns(bddc_ctx* h, int R) {
 // kernels take their iteration as sc[0].it_base + u (u < 0: iteration 0), so
 // one chunk of launches is the same for every chunk and can be replayed as a
 // HIP graph.
+// whether the sums of the PCG partials take launches of their own
+static bool sum_launches(const PcgDev& P) { return P.fin == 1 || (P.fin == 2 && P.nrhs > 1); }
+
 static void pcg_apply_iface(bddc_ctx* h, hipStream_t q, int uu, int it) {
   Level& l1 = *h->levels[0];
   PcgDev& P = h->pcg;
@@ -2315,14 +2319,14 @@ static void pcg_apply_iface(bddc_ctx* h, hipStream_t q, int uu, int it) {
     timing::Scope ts("apply_restrict", it > 0 ? h->by_ur_prec : h->by_r_prec, 0);
     launch_pcg_update_restrict(q, l1.dev, l1.ngmax, l1.nrmax, l1.ncsmax, P, uu);
   }
-  if (P.fin && it > 0) launch_pcg_sum(q, P, 1, uu);
+  if (sum_launches(P) && it > 0) launch_pcg_sum(q, P, 1, uu);
   run_deep_cols(h, q, P.b, P.ld_cflat, const_cast<double*>(P.uc), P.ld_coarse, P.nrhs);
   timing::current_tag = it;
   {
     timing::Scope ts("apply_average", h->by_average, 0);
     launch_pcg_prolong_post(q, l1.dev, P, uu);
   }
-  if (P.fin) launch_pcg_sum(q, P, 2, uu);
+  if (sum_launches(P)) launch_pcg_sum(q, P, 2, uu);
 }
 
 static void pcg_chunk(bddc_ctx* h, hipStream_t q, int it0) {
@@ -2339,7 +2343,7 @@ static void pcg_chunk(bddc_ctx* h, hipStream_t q, int it0) {
       else
         launch_pcg_matvec(q, l1.dev, l1.ngmax, P, uu);
     }
-    if (P.fin) launch_pcg_sum(q, P, 0, uu);
+    if (sum_launches(P)) launch_pcg_sum(q, P, 0, uu);
     pcg_apply_iface(h, q, uu, it);
   }
   launch_pcg_advance(q, P, h->pcg_check);
@@ -2361,6 +2365,7 @@ static void pcg_begin(bddc_ctx* h, const double* f, int64_t ld, int R, double rt
     h->coop_shared = g_live_handles.load() > 1;
     launch_coop_reset(st, h->coop);
   }
+  if (P.fin == 2 && R == 1) launch_tail_reset(st, P);
   const int nif = (int)l1.iface_dof.size();
   const int nb = h->nblk;
   const int nbf = std::min(1024, std::max(1, (int)((h->n_free + kNT - 1) / kNT)));
@@ -2702,7 +2707,9 @@ bddc_tuning current_tuning(const bddc_ctx* h) {
 void check_tuning(const bddc_ctx* h, const bddc_tuning& t) {
   if (t.deep_path < 0 || t.deep_path > BDDC_DEEP_LEVELS || !(deep_available(h) >> t.deep_path & 1))
     fail(BDDC_EINVAL, "deep path not available for this set-up");
-  if (t.finalize != 0 && t.finalize != 1) fail(BDDC_EINVAL, "finalize must be 0 or 1");
+  if (t.finalize < 0 || t.finalize > 2) fail(BDDC_EINVAL, "finalize must be 0, 1 or 2");
+  if (h->pcg.nrb && t.finalize != 1)
+    fail(BDDC_EINVAL, "the row-block launches of wide interfaces take finalize 1 only");
   if (t.graph != 0 && t.graph != 1) fail(BDDC_EINVAL, "graph must be 0 or 1");
   if (t.check != 4 && t.check != 8 && t.check != 16) fail(BDDC_EINVAL, "check must be 4, 8 or 16");
 }
@@ -2853,9 +2860,10 @@ bddc_status bddc_setup(const bddc_problem* p, void* hip_stream, bddc_handle* out
     {
       // sum the PCG partials once, in a one-block launch, when the consuming
       // blocks would each re-read more than a thousand of them
-      // (BDDC_PCG_FINALIZE=0/1 forces either form)
+      // (BDDC_PCG_FINALIZE=0/1/2 forces a form)
       const char* env = getenv("BDDC_PCG_FINALIZE");
-      P.fin = env ? (std::string(env) == "1" ? 1 : 0) : (std::max(nblk_avg, l1.nsub) > 1024 ? 1 : 0);
+      P.fin = env ? std::atoi(env) : (std::max(nblk_avg, l1.nsub) > 1024 ? 1 : 0);
+      if (P.fin < 0 || P.fin > 2) P.fin = 1;
       if (P.nrb) P.fin = 1;   // (the row-block launches read the summed scalars)
     }
     {
@@ -2926,7 +2934,17 @@ bddc_status bddc_setup(const bddc_problem* p, void* hip_stream, bddc_handle* out
     {
       std::lock_guard<std::mutex> lk(g_tune_mu);
       const auto it = g_tune_cache.find(h->shape_key);
-      if (it != g_tune_cache.end() && (deep_available(h) >> it->second.deep_path & 1)) {
+      bool valid = it != g_tune_cache.end();
+      if (valid) {
+        // (a set-up of the same shape may still plan other launches, e.g.
+        // forced row blocks; then the remembered choice is not taken)
+        try {
+          check_tuning(h, it->second);
+        } catch (const Error&) {
+          valid = false;
+        }
+      }
+      if (valid) {
         apply_tuning(h, it->second);
         h->tuned_ms = it->second.solve_ms;
       }
@@ -3010,7 +3028,7 @@ bddc_status bddc_autotune(bddc_handle h, const double* f, double* u, int32_t nrh
       apply_tuning(h, best);
     };
     try_knob(&bddc_tuning::deep_path, {BDDC_DEEP_COOP, BDDC_DEEP_WIDE, BDDC_DEEP_FUSED, BDDC_DEEP_LEVELS});
-    try_knob(&bddc_tuning::finalize, {0, 1});
+    if (!h->pcg.nrb) try_knob(&bddc_tuning::finalize, {0, 1, 2});
     try_knob(&bddc_tuning::check, {4, 8, 16});
     try_knob(&bddc_tuning::graph, {1, 0});
     h->tuned_ms = best_ms;

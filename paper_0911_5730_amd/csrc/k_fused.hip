@@ -342,6 +342,72 @@ __global__ void __launch_bounds__(kNT) k_pcg_sum(PcgDev P, int which, int u) {
   }
 }
 
+// Tail form of the sums (finalize 2, one column): the last block of a
+// producing launch to finish sums the launch's partials in the order of
+// block_sum_of (bitwise the value k_pcg_sum forms) and stores the scalar, so
+// the sum needs no launch of its own.  The partials are stored and read with
+// agent-scope atomic accesses, which are coherent across the XCDs' L2 caches,
+// so no cache maintenance is needed: a block counts itself in on an
+// agent-scope counter once its partial's store has completed, and the block
+// that brings the count to the grid size reads all partials, sums them and
+// resets the counter for the next launch.  A launch that returns early (the
+// column finished) does so in every block, and then none counts.
+__device__ inline void part_store(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline double part_load(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline void tail_sum(const PcgDev& P, int which, int it, double* red) {
+  __shared__ int last_s;
+  __builtin_amdgcn_s_waitcnt(0);   // (the block's partial store has completed)
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    // two levels of counters (one counter per 64 bytes): block b counts in on
+    // slot b mod 64; the block that completes its slot resets it and counts
+    // the slot in on the top counter, so no counter sees more than 64 atomics
+    unsigned* cnt = P.tail_cnt + (size_t)which * kTailStride;
+    const unsigned ns = min(gridDim.x, (unsigned)kTailSlots);
+    const unsigned slot = blockIdx.x % kTailSlots;
+    const unsigned in_slot = (gridDim.x - slot + kTailSlots - 1) / kTailSlots;
+    unsigned* sc = cnt + 16 * (1 + slot);
+    int last = 0;
+    if (__hip_atomic_fetch_add(sc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1 == in_slot) {
+      __hip_atomic_store(sc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      last = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1 == ns;
+    }
+    last_s = last;
+  }
+  __syncthreads();
+  if (!last_s) return;
+  const double* v = which == 0 ? P.pq_part : (which == 1 ? P.rr_part : P.rz_part[it & 1]);
+  const int n = which == 2 ? P.nblk : (which == 0 ? P.npq : P.nsub1);
+  // the loads and additions of block_sum_of
+  double acc = 0.0;
+  int i = threadIdx.x;
+  for (; i + 7 * kNT < n; i += 8 * kNT) {
+    double t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t[u] = part_load(v + i + u * kNT);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += t[u];
+  }
+  for (; i < n; i += kNT) acc += part_load(v + i);
+  const double sum = wg_sum(acc, red);
+  if (threadIdx.x == 0) {
+    PcgScalars* S = P.sc;
+    if (which == 0) S->pqs = sum;
+    else if (which == 1) S->rrs = sum;
+    else S->rzs[it & 1] = sum;
+    __hip_atomic_store(P.tail_cnt + (size_t)which * kTailStride, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+__global__ void k_tail_reset(unsigned int* cnt) {
+  for (int i = threadIdx.x; i < 3 * kTailStride; i += blockDim.x) cnt[i] = 0u;
+}
+
 // the next chunk of PCG launches starts n iterations later
 __global__ void k_pcg_advance(PcgScalars* sc, int n) {
   if (threadIdx.x == 0) sc[0].it_base += n;
@@ -646,7 +712,7 @@ k_pcg_matvec(LevelDev L, PcgDev P, int u) {
         e = pl[k * ng + i] * acc;
       }
       slot_sums(e, W, red, bet);
-      if (tid < per && k0 + tid < nl) P.pq_part[(size_t)col(k0 + tid) * P.ld_sub + s] = bet[tid];
+      if (tid < per && k0 + tid < nl) part_store(P.pq_part + (size_t)col(k0 + tid) * P.ld_sub + s, bet[tid]);
     }
   } else {
     for (int k = 0; k < nl; ++k) {
@@ -659,9 +725,11 @@ k_pcg_matvec(LevelDev L, PcgDev P, int u) {
         e += pl[k * ng + i] * acc;
       }
       e = wg_sum(e, red);
-      if (tid == 0) P.pq_part[(size_t)col(k) * P.ld_sub + s] = e;
+      if (tid == 0) part_store(P.pq_part + (size_t)col(k) * P.ld_sub + s, e);
     }
   }
+  if constexpr (!kMulti)
+    if (P.fin == 2) tail_sum(P, 0, it, red);
 }
 
 // Storage of T_rr and Psi in the precision forms: FP64 (kPrec 0), FP32 (1),
@@ -834,7 +902,7 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
       return rr;
     };
     auto publish = [&](int k, double rr) {
-      P.rr_part[(size_t)col(k) * P.ld_sub + s] = rr;
+      part_store(P.rr_part + (size_t)col(k) * P.ld_sub + s, rr);
       if (s == 0) {
         PcgScalars& S = P.sc[col(k)];
         S.iters = it;
@@ -1029,6 +1097,7 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
   }
   if constexpr (!kMulti) {
     for (int a = n_r + tid; a < ng; a += kNT) P.da[g0 + a] = 0.0;
+    if (P.fin == 2 && it > 0) tail_sum(P, 1, it, red);
   } else {
     for (int t = tid; t < (ng - n_r) * nl; t += kNT) {
       const int k = t / (ng - n_r), a = n_r + t - k * (ng - n_r);
@@ -1292,8 +1361,10 @@ __global__ void __launch_bounds__(kNT) k_pcg_prolong_post(LevelDev L, PcgDev P, 
   if ((int)threadIdx.x < ngo) {
     double r = 0.0;
     for (int w = 0; w < nw; ++w) r += red[threadIdx.x * 16 + w];
-    P.rz_part[parity][(size_t)gcol(threadIdx.x) * P.ld_blk + blockIdx.x] = r;
+    part_store(P.rz_part[parity] + (size_t)gcol(threadIdx.x) * P.ld_blk + blockIdx.x, r);
   }
+  if constexpr (!kMulti)
+    if (P.fin == 2) tail_sum(P, 2, it, red);
 }
 
 // Rows of the averaged coarse basis: for interface dof gi, in sharer order,
@@ -1331,6 +1402,9 @@ void launch_pcg_matvec(hipStream_t st, const LevelDev& L, int ngmax, const PcgDe
 }
 void launch_pcg_sum(hipStream_t st, const PcgDev& P, int which, int u) {
   launch_kernel(k_pcg_sum, dim3(P.nrhs), dim3(kNT), 0, st, P, which, u);
+}
+void launch_tail_reset(hipStream_t st, const PcgDev& P) {
+  launch_kernel(k_tail_reset, dim3(1), dim3(256), 0, st, P.tail_cnt);
 }
 void launch_pcg_advance(hipStream_t st, const PcgDev& P, int n) {
   launch_kernel(k_pcg_advance, dim3(1), dim3(64), 0, st, P.sc, n);

@@ -41,6 +41,10 @@ struct Khat16 {
 // kernel modes of the operators without Dirichlet data: the constants, or
 // the three rigid-body modes of plane elasticity (columns of the level's z)
 constexpr int kMaxModes = 3;
+// counters of the tail sums: per sum a top counter and kTailSlots slot
+// counters, 16 words (64 bytes) apart
+constexpr int kTailSlots = 64;
+constexpr int kTailStride = 16 * (1 + kTailSlots);
 
 struct Khat64 {
   double v[64];   // 8x8 elasticity element matrix (k = 1), row-major, dof 2 q + c of local node q
@@ -253,9 +257,12 @@ struct PcgDev {
   int fullpad = 0;
   int nblk = 1;                              // blocks of the interface average (rz partials)
   // 1: a one-block launch after each producing launch sums its partials once
-  // into PcgScalars (rzs, pqs, rrs) and the consumers read that scalar; 0:
-  // every consuming block sums the partials itself (cheaper when there are few)
+  // into PcgScalars (rzs, pqs, rrs) and the consumers read that scalar; 2 (one
+  // column): the producing launch's last block to finish does that sum
+  // (counters tail_cnt, zeroed when a solve begins; several columns: as 1);
+  // 0: every consuming block sums the partials itself (cheaper when there are few)
   int fin = 0;
+  unsigned int* tail_cnt = nullptr;          // counters of the three tail sums (3 kTailStride words)
   // precision form of the interface preconditioner (bddc_precision): 0 FP64
   // T_rr and Psi; 1 FP32 copies of both; 2 T_rr in factored form
   //   T_rr = D^-1 W^T (I - Q Q^T) W D^-1,
@@ -463,6 +470,7 @@ void launch_pcg_matvec(hipStream_t st, const LevelDev& L, int ngmax, const PcgDe
 // which: 0 p^T S p (-> pqs), 1 r.r (-> rrs), 2 r.z of iteration it (-> rzs[it & 1]);
 // iteration numbers are it = sc->it_base + u, or 0 for u < 0
 void launch_pcg_sum(hipStream_t st, const PcgDev& P, int which, int u);
+void launch_tail_reset(hipStream_t st, const PcgDev& P);
 void launch_pcg_advance(hipStream_t st, const PcgDev& P, int n);
 void launch_round_factors(hipStream_t st, const LevelDev& L, const PcgDev& P, int nrmax, int ncrmax, const double* Cr,
                           int* status);
