@@ -1330,7 +1330,7 @@ class Builder {
       if (use_lds_setup() && tri_inverse_lds(lv.nImax) <= kLdsMax)
         launch_tri_inverse_lds(st_, lv.nsub, lv.nImax, d.koff, d.loc_ptr, d.nint, d.K, d.Linv, d.linvoff);
       else
-        launch_tri_inverse(st_, lv.nsub, d.koff, d.loc_ptr, d.nint, d.K, d.Linv, d.linvoff);
+        launch_tri_inverse(st_, lv.nsub, lv.nImax, d.koff, d.loc_ptr, d.nint, d.K, d.Linv, d.linvoff);
     }
     const int ne_tot = lv.nedge;
     lv.edge_m.assign(ne_tot, 0);

@@ -7,6 +7,8 @@
 // with the substructure's local dofs ordered [interior | interface
 // non-corner | corner].
 #include <algorithm>
+#include <cstdlib>
+#include <string>
 
 #include "dense.hpp"
 #include "common.hpp"
@@ -492,9 +494,96 @@ __global__ void __launch_bounds__(kNT) k_tri_inverse(const int64_t* __restrict__
   }
 }
 
-void launch_tri_inverse(hipStream_t st, int nsub, const int64_t* koff, const int32_t* loc_ptr,
+// The same inverse for large interiors, kTiCols columns per workgroup (grid:
+// column blocks x substructures): right-looking forward substitution down the
+// rows of the block, each thread holding its rows' entries of the block's
+// columns in registers (row c0 + t + kNT m on thread t), the pivot row's
+// finished entries handed over through LDS, the next column of L loaded while
+// the current one is applied.  Every entry is formed as in k_tri_inverse:
+// delta minus the products L(i,k) x(k) in increasing k (the terms above the
+// column's diagonal are exact zeros), then divided by L(i,i), so the two
+// kernels agree bitwise.  Interiors up to kTiRows x kNT dofs.
+constexpr int kTiCols = 8;
+constexpr int kTiRows = 8;
+
+__global__ void __launch_bounds__(kNT) k_tri_inverse_cols(const int64_t* __restrict__ koff,
+                                                          const int32_t* __restrict__ loc_ptr,
+                                                          const int32_t* __restrict__ nint,
+                                                          const double* __restrict__ K, double* __restrict__ Linv,
+                                                          const int64_t* __restrict__ linvoff) {
+  __shared__ double xk[2][kTiCols];
+  const int s = blockIdx.y;
+  const int n = loc_ptr[s + 1] - loc_ptr[s];
+  const int nI = nint[s];
+  const int c0 = blockIdx.x * kTiCols;
+  if (c0 >= nI) return;   // (the whole workgroup)
+  const int nc = min(kTiCols, nI - c0);
+  const int tid = threadIdx.x;
+  const double* L = K + koff[s];
+  double* X = Linv + linvoff[s];
+  double x[kTiRows][kTiCols];
+#pragma unroll
+  for (int m = 0; m < kTiRows; ++m)
+#pragma unroll
+    for (int j = 0; j < kTiCols; ++j) x[m][j] = (tid + kNT * m == j) ? 1.0 : 0.0;
+  double lc[kTiRows], ln[kTiRows];
+  auto load_col = [&](double* l, int k) {
+#pragma unroll
+    for (int m = 0; m < kTiRows; ++m) {
+      const int i = c0 + tid + kNT * m;
+      l[m] = (i > k && i < nI) ? L[i + (size_t)k * n] : 0.0;
+    }
+  };
+  load_col(lc, c0);
+  for (int k = c0; k < nI; ++k) {
+    if (k + 1 < nI) load_col(ln, k + 1);
+    const int r = k - c0, buf = k & 1;
+    if (tid == r % kNT) {
+      const double d = L[k + (size_t)k * n];
+      const int mo = r / kNT;
+#pragma unroll
+      for (int m = 0; m < kTiRows; ++m)
+        if (m == mo) {
+#pragma unroll
+          for (int j = 0; j < kTiCols; ++j) {
+            x[m][j] = x[m][j] / d;
+            xk[buf][j] = x[m][j];
+          }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < kTiRows; ++m) {
+      const int i = c0 + tid + kNT * m;
+      if (i > k && i < nI) {
+#pragma unroll
+        for (int j = 0; j < kTiCols; ++j) x[m][j] -= lc[m] * xk[buf][j];
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < kTiRows; ++m) lc[m] = ln[m];
+  }
+#pragma unroll
+  for (int m = 0; m < kTiRows; ++m) {
+    const int i = c0 + tid + kNT * m;
+    if (i < nI)
+#pragma unroll
+      for (int j = 0; j < kTiCols; ++j)
+        if (j < nc) X[i + (size_t)(c0 + j) * nI] = x[m][j];
+  }
+  for (int j = 0; j < nc; ++j)
+    for (int i = tid; i < c0; i += kNT) X[i + (size_t)(c0 + j) * nI] = 0.0;
+}
+
+void launch_tri_inverse(hipStream_t st, int nsub, int nImax, const int64_t* koff, const int32_t* loc_ptr,
                         const int32_t* nint, const double* K, double* Linv, const int64_t* linvoff) {
-  launch_kernel(k_tri_inverse, dim3(nsub), dim3(kNT), 0, st, koff, loc_ptr, nint, K, Linv, linvoff);
+  const char* env = getenv("BDDC_TRI_INVERSE");
+  const bool cols = nImax <= kTiRows * kNT && nsub <= 65535 && !(env && std::string(env) == "rows");
+  if (cols && nImax > 0)
+    launch_kernel(k_tri_inverse_cols, dim3((nImax + kTiCols - 1) / kTiCols, nsub), dim3(kNT), 0, st, koff, loc_ptr,
+                  nint, K, Linv, linvoff);
+  else
+    launch_kernel(k_tri_inverse, dim3(nsub), dim3(kNT), 0, st, koff, loc_ptr, nint, K, Linv, linvoff);
 }
 
 }  // namespace bddc

@@ -458,7 +458,7 @@ void launch_recover(hipStream_t st, const LevelDev& L, int nImax, int ngmax, con
 void launch_copy(hipStream_t st, int n, const double* a, double* b);
 
 // levels >= 2: explicit inverse of the interior factor; fused deep apply
-void launch_tri_inverse(hipStream_t st, int nsub, const int64_t* koff, const int32_t* loc_ptr,
+void launch_tri_inverse(hipStream_t st, int nsub, int nImax, const int64_t* koff, const int32_t* loc_ptr,
                         const int32_t* nint, const double* K, double* Linv, const int64_t* linvoff);
 size_t deep_lds(int wstride, int ncL);
 void launch_deep(hipStream_t st, const DeepArgs& A);
