@@ -1,7 +1,8 @@
 """Pins of the selection rule and the indicator against the paper's own tables.
 
-The tables are for elasticity on a geometry that is not available, so they
-cannot be reproduced; they do fix the semantics, by internal consistency:
+These checks use only the tables' internal consistency (the oracle run on the
+paper's own experiment is in test_oracle_paper_elasticity.py); they fix the
+semantics:
   * Table 6 at tau = 10 adds 4805 - 4794 = 11 coarse dofs over 4512 edges,
     which rules out taking "up to and including the first eigenvalue <= tau"
     (that adds at least one dof per edge) and fits the strict rule lambda > tau;
