@@ -1735,7 +1735,10 @@ static void run_deep(bddc_ctx* h, hipStream_t st) {
 
 // The deep levels for R columns of b1 / uc (strides ldb, ldu): one
 // cooperative launch for all of them when it fits, else column by column.
-static void run_deep_cols(bddc_ctx* h, hipStream_t st, const double* b1, int ldb, double* uc, int ldu, int R) {
+// With rr, the level-1 r.r sums of the PCG columns may be formed by the deep
+// launches themselves (the wide path's pre kernel); returns whether they were.
+static bool run_deep_cols(bddc_ctx* h, hipStream_t st, const double* b1, int ldb, double* uc, int ldu, int R,
+                          const PcgDev* rr = nullptr) {
   Level& l1 = *h->levels[0];
   if (h->levels.size() == 1) {
     if (h->coarse_inv) {
@@ -1745,7 +1748,7 @@ static void run_deep_cols(bddc_ctx* h, hipStream_t st, const double* b1, int ldb
     } else {
       launch_coarse_direct_cols(st, l1.nc, l1.d.csh_ptr, l1.d.csh_flat, b1, ldb, h->AL, uc, ldu, R, l1.dev.stop);
     }
-    return;
+    return false;
   }
   if (h->deep_sel == BDDC_DEEP_WIDE && R <= kMaxRhs) {
     Level& l2 = *h->levels[1];
@@ -1757,8 +1760,14 @@ static void run_deep_cols(bddc_ctx* h, hipStream_t st, const double* b1, int ldb
     W.ld_u2 = ldu;
     W.stop = l1.dev.stop;
     W.L.stop = l1.dev.stop;
+    if (rr) {
+      W.sc = rr->sc;
+      W.rr_part = rr->rr_part;
+      W.rr_ld = rr->ld_sub;
+      W.rr_n = rr->nsub1;
+    }
     wide_launches(h, st, W, l2.d.gam_gid);
-    return;
+    return rr != nullptr;
   }
   if (h->deep_sel == BDDC_DEEP_COOP && R <= h->coop_rmax) {
     CoopDev C = h->coop;
@@ -1770,9 +1779,10 @@ static void run_deep_cols(bddc_ctx* h, hipStream_t st, const double* b1, int ldb
     C.ld_u2 = ldu;
     timing::Scope ts("deep", h->coop_bytes, 0);
     launch_deep_coop(st, C, h->coop_launch || h->coop_shared);
-    return;
+    return false;
   }
   for (int c = 0; c < R; ++c) run_deep_at(h, st, b1 + (size_t)c * ldb, uc + (size_t)c * ldu);
+  return false;
 }
 
 // full-space preconditioner of the level-1 problem (bddc_apply)
@@ -2305,6 +2315,12 @@ static void ensure_columns(bddc_ctx* h, int R) {
 // whether the sums of the PCG partials take launches of their own
 static bool sum_launches(const PcgDev& P) { return P.fin == 1 || (P.fin == 2 && P.nrhs > 1); }
 
+// BDDC_RR_SUM=launch keeps the r.r sum in a launch of its own on the wide path
+static bool rr_sum_launch() {
+  const char* e = getenv("BDDC_RR_SUM");
+  return e && std::string(e) == "launch";
+}
+
 static void pcg_apply_iface(bddc_ctx* h, hipStream_t q, int uu, int it) {
   Level& l1 = *h->levels[0];
   PcgDev& P = h->pcg;
@@ -2319,8 +2335,12 @@ static void pcg_apply_iface(bddc_ctx* h, hipStream_t q, int uu, int it) {
     timing::Scope ts("apply_restrict", it > 0 ? h->by_ur_prec : h->by_r_prec, 0);
     launch_pcg_update_restrict(q, l1.dev, l1.ngmax, l1.nrmax, l1.ncsmax, P, uu);
   }
-  if (sum_launches(P) && it > 0) launch_pcg_sum(q, P, 1, uu);
-  run_deep_cols(h, q, P.b, P.ld_cflat, const_cast<double*>(P.uc), P.ld_coarse, P.nrhs);
+  // r.r is read by the convergence test of the prolongation: the deep
+  // launches may sum it (the wide path), else a launch of its own does
+  const bool want_rr = sum_launches(P) && it > 0;
+  const bool rr_done = run_deep_cols(h, q, P.b, P.ld_cflat, const_cast<double*>(P.uc), P.ld_coarse, P.nrhs,
+                                     want_rr && !rr_sum_launch() ? &P : nullptr);
+  if (want_rr && !rr_done) launch_pcg_sum(q, P, 1, uu);
   timing::current_tag = it;
   {
     timing::Scope ts("apply_average", h->by_average, 0);

@@ -159,6 +159,22 @@ __device__ inline double wg_sum(double v, double* red) {
   return r;
 }
 
+// Sum of n partials by every block in the same fixed order.
+// Eight loads in flight per thread; the additions keep the plain strided order.
+__device__ inline double block_sum_of(const double* __restrict__ v, int n, double* red) {
+  double acc = 0.0;
+  int i = threadIdx.x;
+  for (; i + 7 * kNT < n; i += 8 * kNT) {
+    double t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t[u] = v[i + u * kNT];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += t[u];
+  }
+  for (; i < n; i += kNT) acc += v[i];
+  return wg_sum(acc, red);
+}
+
 // Lower-triangular solve L y = y in place for a single right-hand side held in
 // LDS (y), with L dense in global memory.  Blocked by 16: wave 0 resolves each
 // 16 x 16 diagonal block with lane shuffles, then the whole workgroup applies

@@ -264,21 +264,6 @@ void launch_apply_post_inv(hipStream_t st, const LevelDev& L, int nImax, int ngm
 }
 
 // ---------------------------------------------------------------- fused PCG iteration
-// Sum of n partials by every block in the same fixed order.
-// Eight loads in flight per thread; the additions keep the plain strided order.
-__device__ inline double block_sum_of(const double* __restrict__ v, int n, double* red) {
-  double acc = 0.0;
-  int i = threadIdx.x;
-  for (; i + 7 * kNT < n; i += 8 * kNT) {
-    double t[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) t[u] = v[i + u * kNT];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) acc += t[u];
-  }
-  for (; i < n; i += kNT) acc += v[i];
-  return wg_sum(acc, red);
-}
 
 // Live columns of a blocked PCG launch: the indices of the columns not yet
 // finished, in order (lc[0..nl-1]).  Snapshot form: read once by thread 0

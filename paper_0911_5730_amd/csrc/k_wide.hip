@@ -44,6 +44,18 @@ __global__ void __launch_bounds__(kNT) k_wide_pre(WideDev W) {
   extern __shared__ double sh[];
   const LevelDev& L = W.L;
   const int s = blockIdx.y, chunk = blockIdx.x;
+  if (s == L.nsub) {
+    // the extra row: the r.r sums of the columns still iterating (the order
+    // of block_sum_of, as the one-block sum launch forms them)
+    __shared__ double red[kNT / 64];
+    if (chunk != 0 || blockIdx.z != 0) return;
+    for (int c = 0; c < W.nrhs; ++c) {
+      if (W.sc[0].all_done || W.sc[c].done) continue;
+      const double v = block_sum_of(W.rr_part + (size_t)c * W.rr_ld, W.rr_n, red);
+      if (threadIdx.x == 0) W.sc[c].rrs = v;
+    }
+    return;
+  }
   const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
   const int nI = L.nint[s];
   const int ng = n - nI;
@@ -366,7 +378,7 @@ void launch_wide_pre(hipStream_t st, const WideDev& W) {
     launch_kernel(k_wide_gather, dim3(nb, W.nrhs), dim3(kNT), 0, st, V);
   }
   const int groups = (W.nrhs + V.cols1 - 1) / V.cols1;
-  launch_kernel(k_wide_pre, dim3(V.nchunk1, V.L.nsub, groups), dim3(kNT),
+  launch_kernel(k_wide_pre, dim3(V.nchunk1, V.L.nsub + (V.sc ? 1 : 0), groups), dim3(kNT),
                 sizeof(double) * (size_t)V.cols1 * max(V.nImax, 1), st, V);
 }
 

@@ -183,6 +183,7 @@ int coop_max_blocks(size_t lds);
 
 // One deep level with substructures too large for the cooperative kernel:
 // row blocks of dense K_II^-1 and M^T = (K_GI K_II^-1)^T over many workgroups.
+struct PcgScalars;
 struct WideDev {
   LevelDev L;                         // level 2
   int nImax = 0, ngmax = 0;
@@ -217,6 +218,12 @@ struct WideDev {
   double* rIf = nullptr;
   int gathered = 0;                   // (set at the pre kernel's launch)
   int n2 = 0, nflat_i = 0;            // level-2 dofs, interior flat entries
+  // with sc: one more row of workgroups in the pre kernel, whose first sums the
+  // level-1 r.r partials of each PCG column still iterating (rr_n partials at
+  // stride rr_ld) into sc[c].rrs, in place of a launch of its own
+  PcgScalars* sc = nullptr;
+  const double* rr_part = nullptr;
+  int rr_ld = 0, rr_n = 0;
 };
 void launch_wide_ops(hipStream_t st, const LevelDev& L, int nmax_ops, double* Kinv, const int64_t* kioff, double* Mt,
                      const int64_t* moff);
