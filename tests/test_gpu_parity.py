@@ -370,3 +370,26 @@ def test_setup_kernel_paths(path, monkeypatch):
         check_solution(S, B, ug, o)
     finally:
         S.close()
+
+
+@pytest.mark.parametrize("nrhs", [1, 3])
+def test_rr_sum_folded_into_wide_pre(nrhs, monkeypatch):
+    """On the wide path the r.r sums of the PCG columns are formed by an extra
+    row of workgroups of the level-2 pre kernel instead of a launch of their
+    own (BDDC_RR_SUM=launch), in the same order: bitwise the same iterates."""
+    import torch
+
+    import paper_0911_5730_amd as P
+    prob = _case("adaptive3")
+    F = cuda_vec(synth.square_problem(64, 8, levels=3, groups=(2, 2), nrhs=nrhs, seed=77).f) if nrhs > 1 else \
+        cuda_vec(prob.f[0])
+    out = {}
+    for mode in ("launch", "fold"):
+        monkeypatch.setenv("BDDC_RR_SUM", mode)
+        print(f"r.r sum by {mode}, {nrhs} columns", flush=True)
+        with P.Solver(prob) as S:
+            S.set_tuning(deep_path="wide", finalize=1)
+            u, it, rr = S.solve(F, rtol=1e-10)
+            out[mode] = (u.clone(), list(it))
+    assert out["launch"][1] == out["fold"][1]
+    assert torch.equal(out["launch"][0], out["fold"][0])
