@@ -93,3 +93,36 @@ def test_level2_interior_inverse_forms_bitwise(case, monkeypatch):
             out[form] = (u.clone(), int(it[0]))
     assert out["rows"][1] == out["cols"][1]
     assert torch.equal(out["rows"][0], out["cols"][0])
+
+
+@pytest.mark.parametrize("tau,table", [(10.0, "table5"), (2.0, "table4")])
+def test_level2_jagged_pair_eigenvalues_reproduce_tables_4_5(tau, table):
+    """A reproduction check of the full-size three-level experiment against the
+    printed level-2 eigenvalues (Tables 4 and 5; not an oracle comparison: the
+    oracle cannot set up 1.18M dofs in a test): the jagged pair (2, 5) and its
+    neighbours (5, 6), (5, 8) -- away from the boundary, whose condition the
+    paper does not state -- within 5% + 0.15 on their three leading values
+    (measured: within 1% at tau = 10 and 3.6% at tau = 2, where the level-2
+    problems carry the 13,000 adaptive level-1 constraints), and
+    the jagged pair's leading value the largest of all level-2 pairs."""
+    import json
+    import os
+    import paper_0911_5730_amd as P
+    G = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_tables.json")))
+    printed = {(a, b): v for a, b, v in G[table]["pairs"]}
+    prob = synth.paper_elasticity_problem(16 * NS, NS, levels=3, groups=3, constraints="adaptive", tau=tau, seed=50)
+    with P.Solver(prob) as S:
+        nedge = 0
+        lead = {}
+        while True:
+            try:
+                lam, _, pair = S.edge_eigs(2, nedge)
+            except P.BDDCError:
+                break
+            lead[(int(pair[0]) + 1, int(pair[1]) + 1)] = lam
+            nedge += 1
+        assert nedge == 12          # the edges of a 3 x 3 partition
+        for key in ((2, 5), (5, 6), (5, 8)):
+            ours, p = np.asarray(lead[key][:3]), np.asarray(printed[key][:3])
+            assert np.all(np.abs(ours - p) <= 0.15 + 0.05 * p), (key, ours, p)
+        assert max(lead, key=lambda k: lead[k][0] if len(lead[k]) else 0.0) == (2, 5)
