@@ -204,9 +204,10 @@ bddc_status bddc_query(bddc_handle h, bddc_info* info);
  * one workgroup), BDDC_DEEP_LEVELS (one launch per phase and level); only the
  * paths planned at set-up are available (bit p of `available`, read-only).
  * finalize: 1 sums the PCG partials once per producing launch in a one-block
- * launch, 2 lets the producing launch's last block to finish sum them (one
- * right-hand side; several: as 1), 0 lets every consuming block sum them;
- * interfaces wider than 256 dofs take 1 only.  graph: 1 replays a captured
+ * launch, 2 lets the producing launch's last block to finish sum them, 3
+ * sums them in 256 slots within the producing launch and lets every consuming
+ * block add the slots (2 and 3: one right-hand side; several: as 1), 0 lets
+ * every consuming block sum them; interfaces wider than 256 dofs take 1 only.  graph: 1 replays a captured
  * chunk of PCG launches, 0 launches directly.  check: PCG iterations between
  * host convergence checks (4, 8 or 16).  solve_ms: the median time of one
  * bddc_solve with this configuration when bddc_autotune chose it, else 0.
@@ -225,7 +226,7 @@ typedef struct {
 /* Current launch configuration (bddc_get_tuning) or a new one
  * (bddc_set_tuning; `available` and `solve_ms` are ignored).
  * Errors: BDDC_EINVAL (NULL, a deep path not available, check not 4/8/16,
- * finalize not 0/1/2 or not available, graph not 0/1). */
+ * finalize not 0..3 or not available, graph not 0/1). */
 bddc_status bddc_get_tuning(bddc_handle h, bddc_tuning* t);
 bddc_status bddc_set_tuning(bddc_handle h, const bddc_tuning* t);
 

@@ -2274,6 +2274,8 @@ static void lay_columns(bddc_ctx* h, Arena& A, int R) {
   P.uc = A.take<double>((size_t)R * P.ld_coarse);
   P.sc = A.take<PcgScalars>(R);
   P.tail_cnt = A.take<unsigned int>(3 * kTailStride);
+  P.slot_cnt = A.take<unsigned int>(2 * kSlots * 16);
+  P.slotv = A.take<double>(3 * kSlots);
   h->cy = A.take<double>((size_t)R * h->ld_cy);
   h->ct = A.take<double>((size_t)R * P.ld_flat);
 }
@@ -2312,8 +2314,10 @@ static void ensure_columns(bddc_ctx* h, int R) {
 // kernels take their iteration as sc[0].it_base + u (u < 0: iteration 0), so
 // one chunk of launches is the same for every chunk and can be replayed as a
 // HIP graph.
-// whether the sums of the PCG partials take launches of their own
-static bool sum_launches(const PcgDev& P) { return P.fin == 1 || (P.fin == 2 && P.nrhs > 1); }
+// whether the sums of the PCG partials take launches of their own (p^T S p
+// and r.z; r.r: rr_sum_needed)
+static bool sum_launches(const PcgDev& P) { return P.fin == 1 || (P.fin >= 2 && P.nrhs > 1); }
+static bool rr_sum_needed(const PcgDev& P) { return sum_launches(P) || P.fin == 3; }
 
 // BDDC_RR_SUM=launch keeps the r.r sum in a launch of its own on the wide path
 static bool rr_sum_launch() {
@@ -2337,7 +2341,7 @@ static void pcg_apply_iface(bddc_ctx* h, hipStream_t q, int uu, int it) {
   }
   // r.r is read by the convergence test of the prolongation: the deep
   // launches may sum it (the wide path), else a launch of its own does
-  const bool want_rr = sum_launches(P) && it > 0;
+  const bool want_rr = rr_sum_needed(P) && it > 0;
   const bool rr_done = run_deep_cols(h, q, P.b, P.ld_cflat, const_cast<double*>(P.uc), P.ld_coarse, P.nrhs,
                                      want_rr && !rr_sum_launch() ? &P : nullptr);
   if (want_rr && !rr_done) launch_pcg_sum(q, P, 1, uu);
@@ -2386,6 +2390,7 @@ static void pcg_begin(bddc_ctx* h, const double* f, int64_t ld, int R, double rt
     launch_coop_reset(st, h->coop);
   }
   if (P.fin == 2 && R == 1) launch_tail_reset(st, P);
+  if (P.fin == 3 && R == 1) launch_slot_reset(st, P);
   const int nif = (int)l1.iface_dof.size();
   const int nb = h->nblk;
   const int nbf = std::min(1024, std::max(1, (int)((h->n_free + kNT - 1) / kNT)));
@@ -2727,7 +2732,7 @@ bddc_tuning current_tuning(const bddc_ctx* h) {
 void check_tuning(const bddc_ctx* h, const bddc_tuning& t) {
   if (t.deep_path < 0 || t.deep_path > BDDC_DEEP_LEVELS || !(deep_available(h) >> t.deep_path & 1))
     fail(BDDC_EINVAL, "deep path not available for this set-up");
-  if (t.finalize < 0 || t.finalize > 2) fail(BDDC_EINVAL, "finalize must be 0, 1 or 2");
+  if (t.finalize < 0 || t.finalize > 3) fail(BDDC_EINVAL, "finalize must be 0, 1, 2 or 3");
   if (h->pcg.nrb && t.finalize != 1)
     fail(BDDC_EINVAL, "the row-block launches of wide interfaces take finalize 1 only");
   if (t.graph != 0 && t.graph != 1) fail(BDDC_EINVAL, "graph must be 0 or 1");
@@ -2883,7 +2888,7 @@ bddc_status bddc_setup(const bddc_problem* p, void* hip_stream, bddc_handle* out
       // (BDDC_PCG_FINALIZE=0/1/2 forces a form)
       const char* env = getenv("BDDC_PCG_FINALIZE");
       P.fin = env ? std::atoi(env) : (std::max(nblk_avg, l1.nsub) > 1024 ? 1 : 0);
-      if (P.fin < 0 || P.fin > 2) P.fin = 1;
+      if (P.fin < 0 || P.fin > 3) P.fin = 1;
       if (P.nrb) P.fin = 1;   // (the row-block launches read the summed scalars)
     }
     {
@@ -3048,7 +3053,7 @@ bddc_status bddc_autotune(bddc_handle h, const double* f, double* u, int32_t nrh
       apply_tuning(h, best);
     };
     try_knob(&bddc_tuning::deep_path, {BDDC_DEEP_COOP, BDDC_DEEP_WIDE, BDDC_DEEP_FUSED, BDDC_DEEP_LEVELS});
-    if (!h->pcg.nrb) try_knob(&bddc_tuning::finalize, {0, 1, 2});
+    if (!h->pcg.nrb) try_knob(&bddc_tuning::finalize, {0, 1, 2, 3});
     try_knob(&bddc_tuning::check, {4, 8, 16});
     try_knob(&bddc_tuning::graph, {1, 0});
     h->tuned_ms = best_ms;

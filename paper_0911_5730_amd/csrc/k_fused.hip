@@ -389,6 +389,56 @@ __device__ inline void tail_sum(const PcgDev& P, int which, int it, double* red)
   }
 }
 
+// Slot form of the sums (finalize 3, one column) for p^T S p and r.z.  The
+// one-block sum (block_sum_of) lets thread t add the partials t, t + 256, ...
+// in that order and then reduces the 256 per-thread values (wg_sum).  Here
+// slot t of the producing launch is those same partials: each block counts
+// itself in on its slot's counter (agent scope, about sixteen blocks per slot)
+// once its partial's store has completed, and the block that completes the
+// slot adds the slot's partials in that order (read with agent-scope loads)
+// and stores the slot value.  Every consuming block then reduces the 256 slot
+// values as wg_sum does: bitwise the one-block sum, with no launch of its own.
+static_assert(kSlots == kNT, "one slot per thread of the consuming workgroup");
+
+__device__ inline void slot_tail(const PcgDev& P, int kind, const double* part, double* slot_out) {
+  __shared__ int last_s;
+  __shared__ double pv[kNT];
+  __builtin_amdgcn_s_waitcnt(0);   // (the block's partial store has completed)
+  __syncthreads();
+  const unsigned nb = gridDim.x, slot = blockIdx.x % kSlots;
+  const unsigned in_slot = (nb - slot + kSlots - 1) / kSlots;
+  if (threadIdx.x == 0) {
+    unsigned* c = P.slot_cnt + ((size_t)kind * kSlots + slot) * 16;
+    const int last = __hip_atomic_fetch_add(c, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1 == in_slot;
+    if (last) __hip_atomic_store(c, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    last_s = last;
+  }
+  __syncthreads();
+  if (!last_s) return;
+  double acc = 0.0;   // (thread 0's)
+  for (unsigned q0 = 0; q0 < in_slot; q0 += kNT) {
+    const unsigned q = q0 + threadIdx.x;
+    if (q < in_slot) pv[threadIdx.x] = part_load(part + slot + (size_t)q * kSlots);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const unsigned m = min((unsigned)kNT, in_slot - q0);
+      for (unsigned u = 0; u < m; ++u) acc += pv[u];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) slot_out[slot] = acc;
+}
+
+// the sum whose 256 slot values are at `slots` (every thread of the workgroup)
+__device__ inline double slot_sum(const double* slots, double* red) { return wg_sum(slots[threadIdx.x], red); }
+__device__ inline const double* slots_pq(const PcgDev& P) { return P.slotv; }
+__device__ inline const double* slots_rz(const PcgDev& P, int it) { return P.slotv + kSlots * (1 + (it & 1)); }
+
+__global__ void k_slot_reset(unsigned int* cnt, double* v) {
+  for (int i = threadIdx.x; i < 2 * kSlots * 16; i += blockDim.x) cnt[i] = 0u;
+  for (int i = threadIdx.x; i < 3 * kSlots; i += blockDim.x) v[i] = 0.0;
+}
+
 __global__ void k_tail_reset(unsigned int* cnt) {
   for (int i = threadIdx.x; i < 3 * kTailStride; i += blockDim.x) cnt[i] = 0u;
 }
@@ -596,10 +646,20 @@ k_pcg_matvec(LevelDev L, PcgDev P, int u) {
   // (uniform loads, before this launch stores anything, so they take the
   // scalar path and do not wait for the operator loads above) and writes the
   // same values to LDS, so no barrier is needed before reading them back
+  // (slot sums: the one column's beta from the r.z slots of the last two
+  // iterations, every thread)
+  double bslot = 0.0;
+  if constexpr (!kMulti) {
+    if (P.fin == 3 && it >= 2 && !P.sc[0].done) {
+      const double rz1 = slot_sum(slots_rz(P, it - 1), red);
+      const double rz2 = slot_sum(slots_rz(P, it - 2), red);
+      bslot = rz1 / rz2;
+    }
+  }
   int nl = 0;
   for (int c = 0; c < P.nrhs; ++c) {
     if (P.sc[c].done) continue;
-    if (it >= 2 && P.fin) bet[nl] = P.sc[c].rzs[(it - 1) & 1] / P.sc[c].rzs[(it - 2) & 1];
+    if (it >= 2 && P.fin) bet[nl] = P.fin == 3 && !kMulti ? bslot : P.sc[c].rzs[(it - 1) & 1] / P.sc[c].rzs[(it - 2) & 1];
     lc[nl++] = c;
   }
   if (nl == 0) return;
@@ -713,8 +773,10 @@ k_pcg_matvec(LevelDev L, PcgDev P, int u) {
       if (tid == 0) part_store(P.pq_part + (size_t)col(k) * P.ld_sub + s, e);
     }
   }
-  if constexpr (!kMulti)
+  if constexpr (!kMulti) {
     if (P.fin == 2) tail_sum(P, 0, it, red);
+    if (P.fin == 3) slot_tail(P, 0, P.pq_part, P.slotv);
+  }
 }
 
 // Storage of T_rr and Psi in the precision forms: FP64 (kPrec 0), FP32 (1),
@@ -813,7 +875,7 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
   int nl = 0;
   for (int c = 0; c < P.nrhs; ++c) {
     if (P.sc[c].done) continue;
-    if (it > 0 && P.fin) alph[nl] = P.sc[c].rzs[(it - 1) & 1] / P.sc[c].pqs;
+    if (it > 0 && P.fin && (kMulti || P.fin != 3)) alph[nl] = P.sc[c].rzs[(it - 1) & 1] / P.sc[c].pqs;
     lc[nl++] = c;
   }
   if (nl == 0) return;
@@ -844,7 +906,12 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
         alpha0 = rz / pq;
       }
     } else if (!kMulti) {
-      alpha0 = P.sc[0].rzs[(it - 1) & 1] / P.sc[0].pqs;
+      if (P.fin == 3) {
+        const double rz = slot_sum(slots_rz(P, it - 1), red);
+        alpha0 = rz / slot_sum(slots_pq(P), red);
+      } else {
+        alpha0 = P.sc[0].rzs[(it - 1) & 1] / P.sc[0].pqs;
+      }
     }
     const double* rold = P.r[(it - 1) & 1];
     double* rnew = P.r[it & 1];
@@ -1348,8 +1415,10 @@ __global__ void __launch_bounds__(kNT) k_pcg_prolong_post(LevelDev L, PcgDev P, 
     for (int w = 0; w < nw; ++w) r += red[threadIdx.x * 16 + w];
     part_store(P.rz_part[parity] + (size_t)gcol(threadIdx.x) * P.ld_blk + blockIdx.x, r);
   }
-  if constexpr (!kMulti)
+  if constexpr (!kMulti) {
     if (P.fin == 2) tail_sum(P, 2, it, red);
+    if (P.fin == 3) slot_tail(P, 1, P.rz_part[parity], P.slotv + kSlots * (1 + parity));
+  }
 }
 
 // Rows of the averaged coarse basis: for interface dof gi, in sharer order,
@@ -1387,6 +1456,9 @@ void launch_pcg_matvec(hipStream_t st, const LevelDev& L, int ngmax, const PcgDe
 }
 void launch_pcg_sum(hipStream_t st, const PcgDev& P, int which, int u) {
   launch_kernel(k_pcg_sum, dim3(P.nrhs), dim3(kNT), 0, st, P, which, u);
+}
+void launch_slot_reset(hipStream_t st, const PcgDev& P) {
+  launch_kernel(k_slot_reset, dim3(1), dim3(256), 0, st, P.slot_cnt, P.slotv);
 }
 void launch_tail_reset(hipStream_t st, const PcgDev& P) {
   launch_kernel(k_tail_reset, dim3(1), dim3(256), 0, st, P.tail_cnt);

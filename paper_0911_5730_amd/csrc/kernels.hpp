@@ -44,6 +44,7 @@ constexpr int kMaxModes = 3;
 // counters of the tail sums: per sum a top counter and kTailSlots slot
 // counters, 16 words (64 bytes) apart
 constexpr int kTailSlots = 64;
+constexpr int kSlots = 256;   // slots of the slot sums: one per thread of a 256-thread workgroup
 constexpr int kTailStride = 16 * (1 + kTailSlots);
 
 struct Khat64 {
@@ -267,9 +268,15 @@ struct PcgDev {
   // into PcgScalars (rzs, pqs, rrs) and the consumers read that scalar; 2 (one
   // column): the producing launch's last block to finish does that sum
   // (counters tail_cnt, zeroed when a solve begins; several columns: as 1);
+  // 3 (one column): slot sums (slotv) that every consuming block finishes;
   // 0: every consuming block sums the partials itself (cheaper when there are few)
   int fin = 0;
   unsigned int* tail_cnt = nullptr;          // counters of the three tail sums (3 kTailStride words)
+  // finalize 3 (one column): slot t of a sum holds the partials of producing
+  // blocks t, t + kSlots, ... summed in that order; values for p^T S p and r.z
+  // by parity (3 kSlots doubles), one counter per slot and sum 64 bytes apart
+  double* slotv = nullptr;
+  unsigned int* slot_cnt = nullptr;          // 2 kSlots x 16 words
   // precision form of the interface preconditioner (bddc_precision): 0 FP64
   // T_rr and Psi; 1 FP32 copies of both; 2 T_rr in factored form
   //   T_rr = D^-1 W^T (I - Q Q^T) W D^-1,
@@ -478,6 +485,7 @@ void launch_pcg_matvec(hipStream_t st, const LevelDev& L, int ngmax, const PcgDe
 // iteration numbers are it = sc->it_base + u, or 0 for u < 0
 void launch_pcg_sum(hipStream_t st, const PcgDev& P, int which, int u);
 void launch_tail_reset(hipStream_t st, const PcgDev& P);
+void launch_slot_reset(hipStream_t st, const PcgDev& P);
 void launch_pcg_advance(hipStream_t st, const PcgDev& P, int n);
 void launch_round_factors(hipStream_t st, const LevelDev& L, const PcgDev& P, int nrmax, int ncrmax, const double* Cr,
                           int* status);

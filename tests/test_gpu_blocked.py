@@ -108,7 +108,7 @@ def test_blocked_pcg_operator_storage(case, ops, prec, monkeypatch):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
-@pytest.mark.parametrize("fin", ["0", "1", "2"])
+@pytest.mark.parametrize("fin", ["0", "1", "2", "3"])
 def test_blocked_precision_forms_and_partial_sums(prec, fin, monkeypatch):
     import torch
 

@@ -239,12 +239,13 @@ def test_coarsest_inverse_path(case, path, monkeypatch):
 def test_pcg_scalar_finalize(monkeypatch):
     """The PCG scalars (r.z, p^T S p, r.r) are summed either by every consuming
     block, or once, by a one-block launch after the producing launch or by the
-    producing launch's last block, in the same fixed order: the iterates must
+    producing launch's last block, or in slots within the producing launch
+    that every consuming block adds, in the same fixed order: the iterates must
     be bitwise identical, and match the oracle."""
     prob = _case("adaptive3")
     out = {}
     B = None
-    for fin in ("0", "1", "2"):
+    for fin in ("0", "1", "2", "3"):
         monkeypatch.setenv("BDDC_PCG_FINALIZE", fin)
         print(f"pcg finalize {fin}", flush=True)
         S, B, ug, it, rr, o = run_pair(prob, oracle=B)
@@ -254,7 +255,7 @@ def test_pcg_scalar_finalize(monkeypatch):
             out[fin] = (ug.copy(), it, rr)
         finally:
             S.close()
-    for fin in ("1", "2"):
+    for fin in ("1", "2", "3"):
         assert out["0"][1] == out[fin][1]
         assert np.array_equal(out["0"][0], out[fin][0])
 

@@ -28,7 +28,7 @@ def test_knobs_leave_iterates_bitwise_and_paths_match_oracle():
         t0 = S.tuning()
         assert set(t0["available"]) >= {"coop", "wide", "levels"}, t0
         u0, it0, _ = S.solve(f, rtol=1e-10)
-        for knob, vals in (("finalize", (0, 1, 2)), ("graph", (0, 1)), ("check", (4, 8, 16))):
+        for knob, vals in (("finalize", (0, 1, 2, 3)), ("graph", (0, 1)), ("check", (4, 8, 16))):
             for v in vals:
                 print(f"tuning {knob}={v}", flush=True)
                 S.set_tuning(**{knob: v})
@@ -55,7 +55,7 @@ def test_autotune_installs_and_remembers_the_fastest():
         t = S.autotune(F, reps=2)
         print(f"autotune: {t}", flush=True)
         assert t["deep_path"] in t["available"]
-        assert t["finalize"] in (0, 1, 2) and t["graph"] in (0, 1) and t["check"] in (4, 8, 16)
+        assert t["finalize"] in (0, 1, 2, 3) and t["graph"] in (0, 1) and t["check"] in (4, 8, 16)
         assert t["solve_ms"] > 0
         assert S.tuning() == t
     # a new set-up of the same shape starts from the remembered choice
@@ -73,7 +73,7 @@ def test_set_tuning_rejects_what_the_setup_cannot_run():
     prob = _case("corners_kjump")          # two levels: the coarse problem is solved directly
     with P.Solver(prob) as S:
         assert S.tuning()["available"] == ["levels"]
-        for bad in ({"deep_path": "coop"}, {"check": 5}, {"finalize": 3}, {"graph": -1}):
+        for bad in ({"deep_path": "coop"}, {"check": 5}, {"finalize": 4}, {"graph": -1}):
             with pytest.raises(P.BDDCError) as ei:
                 S.set_tuning(**bad)
             assert ei.value.name == "BDDC_EINVAL"
@@ -94,7 +94,7 @@ def test_row_block_launches_take_finalize_1_only(monkeypatch):
     monkeypatch.setenv("BDDC_PCG_FINALIZE", "2")   # (taken as 1 with row blocks)
     with P.Solver(prob) as S:
         assert S.tuning()["finalize"] == 1
-        for fin in (0, 2):
+        for fin in (0, 2, 3):
             with pytest.raises(P.BDDCError) as ei:
                 S.set_tuning(finalize=fin)
             assert ei.value.name == "BDDC_EINVAL"
