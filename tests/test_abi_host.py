@@ -165,3 +165,19 @@ def test_grid_and_element_list_classifications_agree(nx, nsub, seed, monkeypatch
     want = _oracle_counts(prob)
     for k, v in want.items():
         assert grid[k] == v, (k, grid[k], v)
+
+
+def test_plan_paper_elasticity_topology():
+    """Host-only plan of the paper's experiment (768 x 768 elasticity, 48 x 48
+    substructures, one jagged edge per level): the edge count is Table 1's
+    (13818 - 4794 = 2 x 4512 edge averages), the corners are the interior cross
+    points with both components, and the jagged edge adds two interface nodes
+    per one-element tooth (fourteen teeth)."""
+    p = synth.paper_elasticity_problem(768, 48, levels=3, groups=3, constraints="adaptive", tau=3.0)
+    info = P.plan(p)
+    assert info["n_free"] == 2 * 767 * 767
+    assert info["nsub"] == 48 * 48 and info["levels"] == 3
+    assert info["n_edges"] == 2 * 48 * 47 == 4512
+    assert info["n_corners"] == 2 * 47 * 47
+    straight_nodes = 2 * 47 * 767 - 47 * 47
+    assert info["n_interface"] == 2 * (straight_nodes + 2 * 14)
