@@ -2890,6 +2890,10 @@ bddc_status bddc_setup(const bddc_problem* p, void* hip_stream, bddc_handle* out
       P.fin = env ? std::atoi(env) : (std::max(nblk_avg, l1.nsub) > 1024 ? 1 : 0);
       if (P.fin < 0 || P.fin > 3) P.fin = 1;
       if (P.nrb) P.fin = 1;   // (the row-block launches read the summed scalars)
+      // XCD-aware substructure order of the product and update launches
+      // (BDDC_XCD_MAP=0/1)
+      const char* xe = getenv("BDDC_XCD_MAP");
+      P.xcd = xe ? (std::string(xe) == "1" ? 1 : 0) : 1;
     }
     {
       Staging stg(h->stream, &h->staged);

@@ -265,6 +265,16 @@ void launch_apply_post_inv(hipStream_t st, const LevelDev& L, int nImax, int ngm
 
 // ---------------------------------------------------------------- fused PCG iteration
 
+// Substructure of workgroup b of a launch with one workgroup per
+// substructure: with xcd, the workgroups of XCD k (b = k mod 8) take the
+// contiguous range k q + min(k, r) + [0, q + (k < r)) of the nsub = 8 q + r
+// substructures (a bijection: XCD k holds exactly that many workgroups).
+__device__ inline int sub_of_block(int b, int nsub, int xcd) {
+  if (!xcd) return b;
+  const int q = nsub >> 3, r = nsub & 7, k = b & 7, i = b >> 3;
+  return k * q + min(k, r) + i;
+}
+
 // Live columns of a blocked PCG launch: the indices of the columns not yet
 // finished, in order (lc[0..nl-1]).  Snapshot form: read once by thread 0
 // into LDS (for a launch that changes the flags itself).
@@ -400,12 +410,12 @@ __device__ inline void tail_sum(const PcgDev& P, int which, int it, double* red)
 // values as wg_sum does: bitwise the one-block sum, with no launch of its own.
 static_assert(kSlots == kNT, "one slot per thread of the consuming workgroup");
 
-__device__ inline void slot_tail(const PcgDev& P, int kind, const double* part, double* slot_out) {
+__device__ inline void slot_tail(const PcgDev& P, int kind, const double* part, double* slot_out, int pidx) {
   __shared__ int last_s;
   __shared__ double pv[kNT];
   __builtin_amdgcn_s_waitcnt(0);   // (the block's partial store has completed)
   __syncthreads();
-  const unsigned nb = gridDim.x, slot = blockIdx.x % kSlots;
+  const unsigned nb = gridDim.x, slot = (unsigned)pidx % kSlots;   // (pidx: the block's partial)
   const unsigned in_slot = (nb - slot + kSlots - 1) / kSlots;
   if (threadIdx.x == 0) {
     unsigned* c = P.slot_cnt + ((size_t)kind * kSlots + slot) * 16;
@@ -620,7 +630,7 @@ k_pcg_matvec(LevelDev L, PcgDev P, int u) {
   __shared__ double red[kMaxRhs * 16];
   __shared__ double bet[kMaxRhs];
   __shared__ int lc[kMaxRhs];
-  const int s = blockIdx.x;
+  const int s = sub_of_block(blockIdx.x, L.nsub, P.xcd);
   const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
   const int nI = L.nint[s];
   const int ng = n - nI;
@@ -775,7 +785,7 @@ k_pcg_matvec(LevelDev L, PcgDev P, int u) {
   }
   if constexpr (!kMulti) {
     if (P.fin == 2) tail_sum(P, 0, it, red);
-    if (P.fin == 3) slot_tail(P, 0, P.pq_part, P.slotv);
+    if (P.fin == 3) slot_tail(P, 0, P.pq_part, P.slotv, s);
   }
 }
 
@@ -808,7 +818,7 @@ __global__ void __launch_bounds__(kNT) k_pcg_update_restrict(LevelDev L, PcgDev 
   __shared__ double red[kMaxRhs * 16];   // (slot sums: waves, then the per-slot results at 16)
   __shared__ double alph[kMaxRhs];
   __shared__ int lc[kMaxRhs];
-  const int s = blockIdx.x;
+  const int s = sub_of_block(blockIdx.x, L.nsub, P.xcd);
   const int n = L.loc_ptr[s + 1] - L.loc_ptr[s];
   const int ng = n - L.nint[s];
   const int g0 = L.goff[s];
@@ -1417,7 +1427,7 @@ __global__ void __launch_bounds__(kNT) k_pcg_prolong_post(LevelDev L, PcgDev P, 
   }
   if constexpr (!kMulti) {
     if (P.fin == 2) tail_sum(P, 2, it, red);
-    if (P.fin == 3) slot_tail(P, 1, P.rz_part[parity], P.slotv + kSlots * (1 + parity));
+    if (P.fin == 3) slot_tail(P, 1, P.rz_part[parity], P.slotv + kSlots * (1 + parity), blockIdx.x);
   }
 }
 

@@ -285,6 +285,10 @@ struct PcgDev {
   // FP32, D^-1 in FP32, Psi FP32.  Products of the reduced forms are formed in
   // FP64 (reduced storage, FP64 arithmetic); every vector stays FP64.
   int prec = 0;
+  // 1: the product and update launches give the workgroups that the hardware
+  // deals to one XCD (consecutive ids go round-robin over the eight) a
+  // contiguous range of substructures, so neighbours share that XCD's L2
+  int xcd = 0;
   const double* Sp = nullptr;       // S_s, packed lower triangle (column-major), offsets spoff
   int full = 0;                     // S_s and T_rr held as full column-major matrices instead (wide interfaces)
   const int64_t* spoff = nullptr;

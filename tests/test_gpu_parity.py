@@ -394,3 +394,25 @@ def test_rr_sum_folded_into_wide_pre(nrhs, monkeypatch):
             out[mode] = (u.clone(), list(it))
     assert out["launch"][1] == out["fold"][1]
     assert torch.equal(out["launch"][0], out["fold"][0])
+
+
+@pytest.mark.parametrize("case", ["adaptive3", "rect"])
+def test_xcd_aware_substructure_order_bitwise(case, monkeypatch):
+    """The product and update launches may hand the workgroups of one XCD a
+    contiguous range of substructures (default) or take substructure b on
+    workgroup b (BDDC_XCD_MAP=0): every workgroup writes the same values, so
+    the iterates are bitwise the same (rect: fifteen substructures, a count
+    that is not a multiple of eight)."""
+    import torch
+
+    import paper_0911_5730_amd as P
+    prob = _case(case)
+    out = {}
+    for mode in ("0", "1"):
+        monkeypatch.setenv("BDDC_XCD_MAP", mode)
+        print(f"{case}: XCD-aware order {mode}, nsub {prob.nsub}", flush=True)
+        with P.Solver(prob) as S:
+            u, it, rr = S.solve(cuda_vec(prob.f[0]), rtol=1e-10)
+            out[mode] = (u.clone(), list(it))
+    assert out["0"][1] == out["1"][1]
+    assert torch.equal(out["0"][0], out["1"][0])
