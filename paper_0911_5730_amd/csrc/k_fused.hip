@@ -329,7 +329,22 @@ __global__ void __launch_bounds__(kNT) k_pcg_sum(PcgDev P, int which, int u) {
                                   : (which == 1 ? P.rr_part + (size_t)c * P.ld_sub
                                                 : P.rz_part[it & 1] + (size_t)c * P.ld_blk);
   const int n = which == 2 ? P.nblk : (which == 0 ? P.npq : P.nsub1);
-  const double v = block_sum_of(part, n, red);
+  // block_sum_of's additions (thread t: entries t, t + 256, ... in order, then
+  // wg_sum), with up to kAll of the thread's loads issued before the first
+  // addition: one memory round trip for up to kAll * 256 partials
+  constexpr int kAll = 32;
+  double t[kAll];
+#pragma unroll
+  for (int u = 0; u < kAll; ++u) {
+    const int i = threadIdx.x + u * kNT;
+    t[u] = i < n ? part[i] : 0.0;
+  }
+  double acc = 0.0;
+#pragma unroll
+  for (int u = 0; u < kAll; ++u)
+    if (threadIdx.x + u * kNT < n) acc += t[u];
+  for (int i = threadIdx.x + kAll * kNT; i < n; i += kNT) acc += part[i];
+  const double v = wg_sum(acc, red);
   if (threadIdx.x == 0) {
     if (which == 0) S->pqs = v;
     else if (which == 1) S->rrs = v;
